@@ -1,0 +1,236 @@
+/*
+ * nys.h - C ABI of the MI355X (gfx950) implementation of randomized-Nystrom
+ * preconditioned variational image reconstruction (Hong, Xu, Hu, Fessler,
+ * "On adapting randomized Nystrom preconditioners to accelerate variational
+ * image reconstruction").
+ *
+ * Conventions shared by every entry point
+ * - Array pointers are DEVICE pointers unless a comment says "host".  They are
+ *   owned by the caller; the library never frees or keeps them past the call
+ *   (handles copy what they need).
+ * - Images are row-major n1 x n2; a stack of `ncols` images is contiguous
+ *   ([col][n1][n2]).  The tall N x K matrices of the paper (Omega, Y, U) are
+ *   stored column by column, i.e. as K images.  Sinograms are [view][bin].
+ * - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *   enqueue work and return; argument errors are returned synchronously before
+ *   anything is enqueued.  Numerical failures are recorded in the handle's
+ *   device status word and read by nys_pc_info / the solve info array.
+ * - Storage types: NYS_F64, NYS_F32, NYS_BF16 (bfloat16, FP32 accumulation).
+ * - Handles are not safe for concurrent use from several streams.
+ * - On any non-OK status, nys_last_error() returns a message (thread-local).
+ */
+#ifndef NYS_H_
+#define NYS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NYS_OK = 0,
+  NYS_EINVAL = 1,      /* bad argument, shape or dtype */
+  NYS_ENOMEM = 2,      /* device allocation failed */
+  NYS_ENOTPD = 3,      /* Cholesky failed after every shift escalation */
+  NYS_ENOTFINITE = 4,  /* NaN/Inf met on the device */
+  NYS_ENOCONV = 5,     /* semismooth Newton hit its iteration cap */
+  NYS_EHIP = 6         /* a HIP runtime call failed */
+} nys_status;
+
+typedef enum { NYS_F64 = 0, NYS_F32 = 1, NYS_BF16 = 2 } nys_dtype;
+
+typedef enum {
+  NYS_OP_BLUR = 0,           /* periodic k x k blur, n1 x n2 -> n1 x n2 */
+  NYS_OP_BLURDOWN = 1,       /* blur then keep every factor-th row/column */
+  NYS_OP_PARALLEL_BEAM = 2,  /* Joseph projector, n x n -> views x bins */
+  NYS_OP_IDENTITY = 3        /* A = I (with wavelet_levels: A = W^T) */
+} nys_op_kind;
+
+typedef enum {
+  NYS_REG_TV = 0,        /* isotropic TV, l_{1,2} of first differences */
+  NYS_REG_TV_ANISO = 1,  /* anisotropic TV, l_{1,1} */
+  NYS_REG_HS1 = 2,       /* Hessian Schatten-1 */
+  NYS_REG_L1 = 3         /* l1 of the unknown itself (wavelet coefficients) */
+} nys_reg_kind;
+
+typedef enum { NYS_LOSS_LS = 0, NYS_LOSS_HUBER = 1 } nys_loss_kind;
+
+/* ---------------------------------------------------------------------------
+ * Operators A (problem statement eq. (4); the method touches A only through
+ * A x and A^T y).  Geometry:
+ *  BLUR / BLURDOWN: (H x)[i,j] = sum_{a,b} psf[a,b] x[(i+c-a) mod n1,
+ *    (j+c-b) mod n2], c = (k-1)/2; BLURDOWN keeps samples (f i, f j).
+ *  PARALLEL_BEAM: n1 = n2 = n unit pixels centred at the origin, pixel (i,j)
+ *    at (j-c, i-c); bin b at s = b-(B-1)/2; view v at theta = v*pi/V; each
+ *    ray is sampled once per row (|cos| >= |sin|) or per column with linear
+ *    interpolation and weight 1/max(|cos|,|sin|) (ray-driven, Joseph).  The
+ *    adjoint is the exact transpose, computed in gather form.
+ *  wavelet_levels > 0 composes A with Haar synthesis: the unknown is the
+ *    coefficient array xbar, x = W^T xbar (invertible-L reparametrisation,
+ *    Sec. III-B), in the in-place layout (each level writes LL, HL / LH, HH
+ *    at the positions of its 2 x 2 group).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t kind;            /* nys_op_kind */
+  int32_t n1, n2;          /* unknown image size */
+  int32_t psf_size;        /* k, odd, <= 31 (blur kinds) */
+  const double* psf;       /* host, k*k row-major; copied at create */
+  int32_t factor;          /* decimation factor (BLURDOWN), >= 1 */
+  int32_t n_views, n_bins; /* PARALLEL_BEAM */
+  int32_t wavelet_levels;  /* 0 or Haar levels; n1, n2 divisible by 2^levels */
+} nys_op_desc;
+
+typedef struct nys_op_s* nys_op;
+typedef struct nys_pc_s* nys_pc;
+
+/* Create/destroy an operator handle.  EINVAL on inconsistent sizes. */
+nys_status nys_op_create(const nys_op_desc* desc, nys_op* out);
+void nys_op_destroy(nys_op op);
+/* Number of unknowns N and of measurements M of one column (host out). */
+nys_status nys_op_shape(nys_op op, int64_t* n_unknowns, int64_t* n_meas);
+
+/* y = A x for `ncols` stacked columns; x: ncols*N, y: ncols*M, dtype F64 or
+ * F32.  x and y must not overlap. */
+nys_status op_forward(nys_op op, nys_dtype dt, const void* x, void* y,
+                      int64_t ncols, void* stream);
+/* x = A^T y for `ncols` stacked columns. */
+nys_status op_adjoint(nys_op op, nys_dtype dt, const void* y, void* x,
+                      int64_t ncols, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Sketch, Alg. 1 step 2 (and Sec. III-C, on-the-fly batched evaluation):
+ * Y = Phi Omega with Phi = A^T A (with the wavelet composition,
+ * Phi = W A^T A W^T), all `ell` columns in one batched launch sequence.
+ * omega, Y: ell*N in dtype `dt`; BF16 keeps FP32 accumulation inside.
+ * ------------------------------------------------------------------------- */
+nys_status nys_sketch(nys_op op, nys_dtype dt, const void* omega, void* Y,
+                      int64_t ell, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Nystrom factorisation, Alg. 1 steps 3-8, and the preconditioner of eq. (6):
+ *   nu; Y_nu = Y + nu Omega; C = chol(Omega^T Y_nu) (lower, symmetrised);
+ *   B = Y_nu C^{-T}; [U, S] = svd(B); shat = max(0, S^2 - nu).
+ * B is not formed: the ell x ell FP64 matrix C^{-1} Y_nu^T Y_nu C^{-T} is
+ * diagonalised (Jacobi) and U = Y_nu C^{-T} V S^{-1} is written in one pass.
+ * Columns with shat = 0 are kept in U but left unscaled by P (equivalent to
+ * dropping them).  If Cholesky fails, nu is multiplied by 10 and the steps are
+ * repeated up to max_escalations times; then the status word is ENOTPD.
+ * P^{-1} = (s_K + mu) U (S + mu I)^{-1} U^T + (I - U U^T), where s_K is the
+ * smallest retained shat, or its square root with tail = 0 (the paper's
+ * heuristic, Sec. III-B).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t nu_mode;         /* 0: sqrt(N) eps ||Y||_2 ; 1: eps ||Omega||_F */
+  int32_t tail;            /* 0: s_K <- sqrt(s_K) (paper) ; 1: s_K */
+  double mu;               /* < 0: mu = nu */
+  int32_t max_escalations; /* < 0: 6 */
+  int32_t u_dtype;         /* storage of U: NYS_F64 or NYS_F32 */
+} nys_factor_opts;
+
+/* omega, Y: ell*N in dtype in_dt (F64, F32 or BF16).  ell <= 128.
+ * The handle owns U (ell*N in u_dtype) and the FP64 spectrum. */
+nys_status nys_factor(const void* omega, const void* Y, nys_dtype in_dt,
+                      int64_t N, int64_t ell, const nys_factor_opts* opts,
+                      nys_pc* out, void* stream);
+void nys_pc_destroy(nys_pc pc);
+
+/* Synchronises `stream` and copies to host: shat (ell values, descending,
+ * 0 for dropped columns), nu used, number of retained columns, status word
+ * (nys_status of the device-side factorisation).  Any pointer may be NULL. */
+nys_status nys_pc_info(nys_pc pc, double* shat, double* nu, int32_t* k_eff,
+                       int32_t* status, void* stream);
+/* Device pointer to U (ell*N, u_dtype) and its sizes. */
+nys_status nys_pc_u(nys_pc pc, const void** u, int64_t* N, int64_t* ell,
+                    int32_t* u_dtype);
+
+/* Copies U (ell*N, u_dtype) into the caller's device buffer `dst`. */
+nys_status nys_pc_copy_u(nys_pc pc, void* dst, void* stream);
+
+/* out = P^{-1} v (inverse != 0) or P v, for `ncols` stacked vectors of
+ * length N, dtype = the pc's u_dtype.  out may equal v. */
+nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
+                     void* out, int64_t ncols, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Weighted proximal map (definition in Sec. I-D):
+ *   x = argmin_u  lambda_bar g(u) + 1/2 ||u - s||_P^2,   C = R^N,
+ * P = I when pc is NULL.
+ *  TV / TV_ANISO / HS1: dual accelerated projected gradient on Q for n_inner
+ *   iterations (eqs. (17)-(22)); x(Q) = s - lambda_bar P^{-1} L^T Q; the step
+ *   is 1 / (lambda_bar ||L||^2 ||P^{-1}||).  `state` holds Q (2*N values for
+ *   TV, 3*N for HS1, dtype dt) and is used as the warm start and updated.
+ *  L1: Thm. 1 with P = I + U diag(e) U^T: gamma solves
+ *   gamma = diag(e) U^T (soft(s - U gamma) - s), semismooth Newton with
+ *   backtracking on ||F||; x = soft(s - U gamma).  `state` holds gamma
+ *   (ell FP64 values) as warm start.  P = I gives x = soft(s).
+ * state may be NULL (cold start, not kept).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t kind;        /* nys_reg_kind */
+  int32_t n1, n2;
+  double lnorm2;       /* ||L||^2 bound for the dual step; <= 0: 8 (TV), 34 (HS1) */
+  int32_t n_inner;     /* dual iterations (TV, HS1) */
+  int32_t max_newton;  /* SSN trial points (L1); <= 0: 60 */
+  double newton_tol;   /* ||F|| <= tol (1 + ||gamma||); <= 0: 1e-12 / 1e-6 */
+} nys_reg_desc;
+
+nys_status prox_weighted(const nys_reg_desc* reg, double lambda_bar, nys_pc pc,
+                         nys_dtype dt, const void* s, void* x, void* state,
+                         void* stream);
+/* Bytes of `state` for prox_weighted (host out). */
+nys_status nys_prox_state_bytes(const nys_reg_desc* reg, nys_pc pc,
+                                nys_dtype dt, size_t* bytes);
+
+/* ---------------------------------------------------------------------------
+ * Solve min_x f(x) + lambda g(x) with WAPG (Alg. 3): x^1 = u^1 = 0, t^0 = 1,
+ *   x^{k+1} = prox^P_{alpha lambda g}(u^k - alpha P^{-1} grad f(u^k)),
+ *   t^k = (1 + sqrt(1 + 4 (t^{k-1})^2)) / 2,
+ *   u^{k+1} = x^{k+1} + ((t^{k-1} - 1) / t^k) (x^{k+1} - x^k).
+ * f = 1/2 ||A x - y||^2 or sum h_delta(A x - y) (Huber: r^2/(2 delta) for
+ * |r| <= delta, |r| - delta/2 otherwise).  pc = NULL gives plain APG.
+ * alpha <= 0 selects alpha = 1 / (safety * L), L = lambda_max(P^{-1} A^T A) *
+ * curvature by `power_iters` power-method steps from `power_v0` (N values).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  nys_op op;
+  int32_t loss;        /* nys_loss_kind */
+  double delta;        /* Huber parameter */
+  nys_reg_desc reg;
+  double lambda;
+  const void* y;       /* M measurements, solver dtype */
+} nys_problem;
+
+typedef struct {
+  int32_t max_iter;        /* outer iterations */
+  double alpha;            /* step; <= 0: from the power method */
+  double safety;           /* alpha = 1 / (safety L); <= 0: 1.01 */
+  int32_t power_iters;     /* power-method steps (alpha <= 0) */
+  const void* power_v0;    /* N start values, solver dtype (alpha <= 0) */
+  int32_t warm_start;      /* keep Q / gamma across outer iterations */
+  int32_t use_graph;       /* capture one outer iteration in a hipGraph */
+} nys_solve_opts;
+
+/* x_out: N values (solver dtype dt = F64 or F32).  costs: device, max_iter
+ * FP64 values F(x^{k+1}) or NULL.  info (host, 8 doubles, may be NULL):
+ * [0] alpha used, [1] L estimate, [2] status word, [3] SSN trial points of
+ * the last outer iteration.  Synchronises the stream when info != NULL. */
+nys_status solve(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                 const nys_solve_opts* opts, void* x_out, double* costs,
+                 double* info, void* stream);
+
+/* F(x) = f(x) + lambda g(x) for one column, FP64 accumulation, written to the
+ * device double `cost`. */
+nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void* x,
+                    double* cost, void* stream);
+
+/* Message of the last non-OK status on this thread. */
+const char* nys_last_error(void);
+/* Library version string. */
+const char* nys_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NYS_H_ */

@@ -1,0 +1,306 @@
+"""ctypes binding of libnys (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(HERE, "libnys.so")
+
+F64, F32, BF16 = 0, 1, 2
+OP_BLUR, OP_BLURDOWN, OP_PARALLEL_BEAM, OP_IDENTITY = 0, 1, 2, 3
+REG_TV, REG_TV_ANISO, REG_HS1, REG_L1 = 0, 1, 2, 3
+LOSS_LS, LOSS_HUBER = 0, 1
+REG_NAMES = {"tv": REG_TV, "tv_aniso": REG_TV_ANISO, "hs1": REG_HS1, "l1": REG_L1}
+
+_STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ENOTPD", 4: "ENOTFINITE",
+           5: "ENOCONV", 6: "EHIP"}
+
+
+class NysError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class OpDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32),
+                ("psf_size", C.c_int32), ("psf", C.POINTER(C.c_double)),
+                ("factor", C.c_int32), ("n_views", C.c_int32), ("n_bins", C.c_int32),
+                ("wavelet_levels", C.c_int32)]
+
+
+class FactorOpts(C.Structure):
+    _fields_ = [("nu_mode", C.c_int32), ("tail", C.c_int32), ("mu", C.c_double),
+                ("max_escalations", C.c_int32), ("u_dtype", C.c_int32)]
+
+
+class RegDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32),
+                ("lnorm2", C.c_double), ("n_inner", C.c_int32), ("max_newton", C.c_int32),
+                ("newton_tol", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("op", C.c_void_p), ("loss", C.c_int32), ("delta", C.c_double),
+                ("reg", RegDesc), ("lam", C.c_double), ("y", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("alpha", C.c_double), ("safety", C.c_double),
+                ("power_iters", C.c_int32), ("power_v0", C.c_void_p),
+                ("warm_start", C.c_int32), ("use_graph", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnys.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise NysError(6, f"{library_path} is missing: build it with "
+                              "`python -m paper_2411_08178_amd.build`")
+        L = C.CDLL(library_path)
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "nys_op_create": [C.POINTER(OpDesc), C.POINTER(vp)],
+            "nys_op_shape": [vp, C.POINTER(i64), C.POINTER(i64)],
+            "op_forward": [vp, i32, vp, vp, i64, vp],
+            "op_adjoint": [vp, i32, vp, vp, i64, vp],
+            "nys_sketch": [vp, i32, vp, vp, i64, vp],
+            "nys_factor": [vp, vp, i32, i64, i64, C.POINTER(FactorOpts), C.POINTER(vp), vp],
+            "nys_pc_info": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32), C.POINTER(i32), vp],
+            "nys_pc_u": [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)],
+            "nys_pc_copy_u": [vp, vp, vp],
+            "nys_apply": [vp, i32, i32, vp, vp, i64, vp],
+            "prox_weighted": [C.POINTER(RegDesc), dbl, vp, i32, vp, vp, vp, vp],
+            "nys_prox_state_bytes": [C.POINTER(RegDesc), vp, i32, C.POINTER(C.c_size_t)],
+            "solve": [C.POINTER(Problem), vp, i32, C.POINTER(SolveOpts), vp, vp,
+                      C.POINTER(dbl), vp],
+            "nys_cost": [C.POINTER(Problem), i32, vp, vp, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.nys_op_destroy.argtypes = [vp]
+        L.nys_op_destroy.restype = None
+        L.nys_pc_destroy.argtypes = [vp]
+        L.nys_pc_destroy.restype = None
+        L.nys_last_error.restype = C.c_char_p
+        L.nys_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().nys_version().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise NysError(status, lib().nys_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_DT = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype not in _DT:
+        raise NysError(1, f"unsupported dtype {t.dtype}")
+    return _DT[t.dtype]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise NysError(1, "tensors must be contiguous CUDA (HIP) tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """Handle of an operator A (optionally composed with Haar synthesis)."""
+
+    def __init__(self, kind: int, n1: int, n2: int, psf=None, factor: int = 1,
+                 views: int = 0, bins: int = 0, wavelet_levels: int = 0):
+        d = OpDesc()
+        d.kind, d.n1, d.n2 = kind, n1, n2
+        self._psf = None
+        if psf is not None:
+            self._psf = np.ascontiguousarray(psf, dtype=np.float64)
+            d.psf_size = self._psf.shape[0]
+            d.psf = self._psf.ctypes.data_as(C.POINTER(C.c_double))
+        d.factor, d.n_views, d.n_bins, d.wavelet_levels = factor, views, bins, wavelet_levels
+        h = C.c_void_p()
+        _check(lib().nys_op_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        N, M = C.c_int64(), C.c_int64()
+        _check(lib().nys_op_shape(h, C.byref(N), C.byref(M)))
+        self.N, self.M = N.value, M.value
+        self.n1, self.n2 = n1, n2
+        self.kind = kind
+        self.views, self.bins, self.factor = views, bins, factor
+
+    @property
+    def meas_shape(self):
+        if self.kind == OP_PARALLEL_BEAM:
+            return (self.views, self.bins)
+        if self.kind == OP_BLURDOWN:
+            return (self.n1 // self.factor, self.n2 // self.factor)
+        return (self.n1, self.n2)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.nys_op_destroy(self.handle)
+            self.handle = None
+
+
+def _ncols(t: torch.Tensor, per: int) -> int:
+    if t.numel() % per:
+        raise NysError(1, f"tensor of {t.numel()} elements is not a stack of {per}")
+    return t.numel() // per
+
+
+def op_forward(op: Operator, x: torch.Tensor, out: Optional[torch.Tensor] = None):
+    n = _ncols(x, op.N)
+    lead = x.shape[:-2] if x.dim() >= 2 and x.shape[-2:] == (op.n1, op.n2) else (n,)
+    if out is None:
+        out = torch.empty(tuple(lead) + op.meas_shape, dtype=x.dtype, device=x.device)
+    _check(lib().op_forward(op.handle, _dt(x), _ptr(x), _ptr(out), n, _stream()))
+    return out
+
+
+def op_adjoint(op: Operator, y: torch.Tensor, out: Optional[torch.Tensor] = None):
+    n = _ncols(y, op.M)
+    lead = y.shape[:-2] if y.dim() >= 2 else (n,)
+    if out is None:
+        out = torch.empty(tuple(lead) + (op.n1, op.n2), dtype=y.dtype, device=y.device)
+    _check(lib().op_adjoint(op.handle, _dt(y), _ptr(y), _ptr(out), n, _stream()))
+    return out
+
+
+def nys_sketch(op: Operator, omega: torch.Tensor, out: Optional[torch.Tensor] = None):
+    ell = _ncols(omega, op.N)
+    if out is None:
+        out = torch.empty_like(omega)
+    _check(lib().nys_sketch(op.handle, _dt(omega), _ptr(omega), _ptr(out), ell, _stream()))
+    return out
+
+
+class Preconditioner:
+    """Handle of the Nystrom preconditioner (U, spectrum, coefficients)."""
+
+    def __init__(self, handle, N, ell, u_dtype):
+        self.handle, self.N, self.ell = handle, N, ell
+        self.u_dtype = torch.float64 if u_dtype == F64 else torch.float32
+
+    def info(self):
+        shat = (C.c_double * self.ell)()
+        nu = C.c_double()
+        keff = C.c_int32()
+        st = C.c_int32()
+        _check(lib().nys_pc_info(self.handle, shat, C.byref(nu), C.byref(keff), C.byref(st),
+                                 _stream()))
+        return dict(shat=np.array(shat[:]), nu=nu.value, k_eff=keff.value, status=st.value)
+
+    def U(self) -> torch.Tensor:
+        out = torch.empty((self.ell, self.N), dtype=self.u_dtype, device="cuda")
+        _check(lib().nys_pc_copy_u(self.handle, _ptr(out), _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.nys_pc_destroy(self.handle)
+            self.handle = None
+
+
+def nys_factor(omega: torch.Tensor, Y: torch.Tensor, ell: int, nu_mode: int = 0,
+               tail: str = "sqrt", mu: float = -1.0, max_escalations: int = 6,
+               u_dtype: torch.dtype = torch.float32) -> Preconditioner:
+    if omega.shape != Y.shape or omega.dtype != Y.dtype:
+        raise NysError(1, "omega and Y must have the same shape and dtype")
+    N = omega.numel() // ell
+    o = FactorOpts(nu_mode, 0 if tail == "sqrt" else 1, mu, max_escalations, _DT[u_dtype])
+    h = C.c_void_p()
+    _check(lib().nys_factor(_ptr(omega), _ptr(Y), _dt(omega), N, ell, C.byref(o), C.byref(h),
+                            _stream()))
+    return Preconditioner(h, N, ell, _DT[u_dtype])
+
+
+def nys_apply(pc: Preconditioner, v: torch.Tensor, inverse: bool = True,
+              out: Optional[torch.Tensor] = None):
+    n = _ncols(v, pc.N)
+    if out is None:
+        out = torch.empty_like(v)
+    _check(lib().nys_apply(pc.handle, 1 if inverse else 0, _dt(v), _ptr(v), _ptr(out), n,
+                           _stream()))
+    return out
+
+
+def reg_desc(kind, n1, n2, n_inner=20, lnorm2=0.0, max_newton=0, newton_tol=0.0) -> RegDesc:
+    if isinstance(kind, str):
+        kind = REG_NAMES[kind]
+    return RegDesc(kind, n1, n2, lnorm2, n_inner, max_newton, newton_tol)
+
+
+def prox_state(reg: RegDesc, pc: Optional[Preconditioner], dtype) -> Optional[torch.Tensor]:
+    """Zero-initialised warm-start state for prox_weighted."""
+    nb = C.c_size_t()
+    _check(lib().nys_prox_state_bytes(C.byref(reg), pc.handle if pc else None, _DT[dtype],
+                                      C.byref(nb)))
+    if nb.value == 0:
+        return None
+    return torch.zeros(nb.value, dtype=torch.uint8, device="cuda")
+
+
+def prox_weighted(reg: RegDesc, lam_bar: float, pc: Optional[Preconditioner], s: torch.Tensor,
+                  state: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
+    if out is None:
+        out = torch.empty_like(s)
+    _check(lib().prox_weighted(C.byref(reg), lam_bar, pc.handle if pc else None, _dt(s), _ptr(s),
+                               _ptr(out), _ptr(state), _stream()))
+    return out
+
+
+def _problem(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, loss: int, delta: float):
+    p = Problem()
+    p.op = op.handle
+    p.loss, p.delta, p.reg, p.lam = loss, delta, reg, lam
+    p.y = y.data_ptr()
+    return p
+
+
+def solve(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, pc: Optional[Preconditioner],
+          max_iter: int, alpha: float = -1.0, power_v0: Optional[torch.Tensor] = None,
+          power_iters: int = 100, safety: float = 1.01, loss: int = LOSS_LS, delta: float = 0.0,
+          warm_start: bool = True, record_cost: bool = True, use_graph: bool = False):
+    """WAPG (plain APG when pc is None).  Returns (x, costs or None, info)."""
+    p = _problem(op, y, reg, lam, loss, delta)
+    o = SolveOpts(max_iter, alpha, safety, power_iters,
+                  power_v0.data_ptr() if power_v0 is not None else None,
+                  1 if warm_start else 0, 1 if use_graph else 0)
+    x = torch.empty((op.n1, op.n2), dtype=y.dtype, device=y.device)
+    costs = torch.empty(max(max_iter, 1), dtype=torch.float64, device=y.device) if record_cost else None
+    info = (C.c_double * 8)()
+    _check(lib().solve(C.byref(p), pc.handle if pc else None, _dt(y), C.byref(o), _ptr(x),
+                       _ptr(costs), info, _stream()))
+    return x, costs, dict(alpha=info[0], L=info[1], status=int(info[2]), ssn_trials=info[3])
+
+
+def nys_cost(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, x: torch.Tensor,
+             loss: int = LOSS_LS, delta: float = 0.0) -> torch.Tensor:
+    p = _problem(op, y, reg, lam, loss, delta)
+    out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib().nys_cost(C.byref(p), _dt(x), _ptr(x), _ptr(out), _stream()))
+    return out

@@ -1,0 +1,145 @@
+// Shared internals of libnys: error state, storage-type traits, device
+// buffers, and launch helpers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nys.h"
+
+namespace nys {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+
+#define NYS_CHECK_HIP(expr)                                                  \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      ::nys::set_error("%s:%d %s -> %s", __FILE__, __LINE__, #expr,          \
+                       hipGetErrorString(e_));                               \
+      return NYS_EHIP;                                                       \
+    }                                                                        \
+  } while (0)
+
+#define NYS_REQUIRE(cond, ...)                                               \
+  do {                                                                       \
+    if (!(cond)) {                                                           \
+      ::nys::set_error(__VA_ARGS__);                                         \
+      return NYS_EINVAL;                                                     \
+    }                                                                        \
+  } while (0)
+
+#define NYS_TRY(expr)                                                        \
+  do {                                                                       \
+    nys_status s_ = (expr);                                                  \
+    if (s_ != NYS_OK) return s_;                                             \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- bf16
+__device__ __host__ inline float bf16_to_f32(uint16_t b) {
+  uint32_t u = static_cast<uint32_t>(b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+__device__ __host__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+    return static_cast<uint16_t>((u >> 16) | 0x40u);          // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);                            // nearest even
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// Storage type S -> compute type C, with load/store conversions.
+template <class S> struct Io;
+template <> struct Io<double> {
+  using C = double;
+  __device__ static double ld(const double* p, size_t i) { return p[i]; }
+  __device__ static void st(double* p, size_t i, double v) { p[i] = v; }
+};
+template <> struct Io<float> {
+  using C = float;
+  __device__ static float ld(const float* p, size_t i) { return p[i]; }
+  __device__ static void st(float* p, size_t i, float v) { p[i] = v; }
+};
+template <> struct Io<uint16_t> {
+  using C = float;
+  __device__ static float ld(const uint16_t* p, size_t i) { return bf16_to_f32(p[i]); }
+  __device__ static void st(uint16_t* p, size_t i, float v) { p[i] = f32_to_bf16(v); }
+};
+
+inline size_t dtype_size(nys_dtype d) {
+  return d == NYS_F64 ? 8 : d == NYS_F32 ? 4 : 2;
+}
+
+// ---------------------------------------------------------------- buffers
+// Device buffer owned by a handle; grows on demand, freed by the owner.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  nys_status ensure(size_t want) {
+    if (want <= bytes) return NYS_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      set_error("hipMalloc(%zu) failed", want);
+      return NYS_ENOMEM;
+    }
+    bytes = want;
+    return NYS_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+inline unsigned cdiv(int64_t a, int64_t b) { return static_cast<unsigned>((a + b - 1) / b); }
+
+inline nys_status launch_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("launch of %s failed: %s", what, hipGetErrorString(e));
+    return NYS_EHIP;
+  }
+  return NYS_OK;
+}
+
+// ---------------------------------------------------------------- handles
+struct OpImpl;  // defined in ops.hip
+
+}  // namespace nys
+
+// Public handle types.
+struct nys_op_s {
+  nys_op_desc d{};
+  int64_t N = 0, M = 0;
+  std::vector<double> psf;        // k*k row-major
+  nys::DevBuf psf_dev;            // [flipped psf f64 | psf f64 | flipped f32 | psf f32]
+  nys::DevBuf trig;               // per view: cos, sin (f64) then (f32)
+  nys::DevBuf tmp0, tmp1;         // intermediates of composed operators
+};
+
+struct nys_pc_s {
+  int64_t N = 0, ell = 0;
+  int32_t u_dtype = NYS_F32;
+  int32_t tail = 0;
+  double pinv_norm_cache = -1.0;  // ||P^{-1}|| once read back from the device
+  nys::DevBuf U;                  // ell*N
+  nys::DevBuf meta;               // FP64 device block, see factor.hip
+  nys::DevBuf work;               // scratch of nys_apply / prox
+  nys::DevBuf work2;
+};

@@ -1,0 +1,53 @@
+// Cross-file internal entry points of libnys (not part of the public ABI).
+#pragma once
+
+#include "common.hpp"
+
+namespace nys {
+
+// y = A x / x = A^T y with the optional wavelet composition (ops.hip).
+template <class T> nys_status op_fwd(nys_op op, const T* x, T* y, int64_t ncols, hipStream_t st);
+template <class T> nys_status op_adj(nys_op op, const T* y, T* x, int64_t ncols, hipStream_t st);
+
+// Fused W H^T S^T S H W^T sketch for factor-2 decimation with 3 Haar levels
+// (sketch_sr.hip).  S is float or uint16_t (bfloat16).
+template <class S>
+nys_status sketch_sr_fused(nys_op op, const S* omega, S* Y, int64_t ell, hipStream_t st);
+nys_status sketch_sr_chain_bf16(nys_op op, const uint16_t* omega, uint16_t* Y, int64_t ell,
+                                hipStream_t st);
+nys_status sketch_sr_chain_f32(nys_op op, const float* omega, float* Y, int64_t ell,
+                               hipStream_t st);
+
+// Preconditioner application on T-typed vectors (factor.hip).
+// out = v + U (coef . (U^T v)) with coef = d (P^{-1}) or e (P).
+template <class T>
+nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, hipStream_t st);
+// cd[col][k] = coef_k (U^T v_col)_k in FP64 (coef = d or e); uses pc->work.
+template <class T>
+nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
+                     hipStream_t st);
+
+// Layout of the FP64 metadata block of a preconditioner (pc->meta).
+struct PcMeta {
+  static constexpr int kMaxEll = 128;
+  // offsets in doubles
+  static constexpr int kShat = 0;              // ell
+  static constexpr int kD = kMaxEll;           // ell: P^{-1} coefficients
+  static constexpr int kE = 2 * kMaxEll;       // ell: P coefficients
+  static constexpr int kScalars = 3 * kMaxEll; // nu, sK, mu, pinv_norm, k_eff, status
+  static constexpr int kNu = kScalars + 0;
+  static constexpr int kSK = kScalars + 1;
+  static constexpr int kMu = kScalars + 2;
+  static constexpr int kPinvNorm = kScalars + 3;
+  static constexpr int kKeff = kScalars + 4;
+  static constexpr int kStatus = kScalars + 5;
+  static constexpr int kEscal = kScalars + 6;
+  static constexpr int kTotal = kScalars + 16;
+};
+
+// Weighted prox (prox.hip).  state as in prox_weighted.
+template <class T>
+nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
+                    void* state, hipStream_t st, double* scratch_dev = nullptr);
+
+}  // namespace nys

@@ -1,0 +1,607 @@
+// Operators A, A^T (periodic blur, blur + decimation, parallel-beam Joseph
+// pair, Haar pyramid) and the batched sketch Y = Phi Omega (Alg. 1 step 2).
+//
+// Images are row-major; a batch of columns is indexed by blockIdx.z.
+// Every kernel is templated on its input storage type SI, output storage
+// type SO and compute type C, so BF16 sketches accumulate in FP32.
+
+#include <cmath>
+#include <cstdarg>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace nys {
+
+// ---------------------------------------------------------------- errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+// ================================================================ blur
+// out[i, j] = sum_{a,b} g[a, b] in[(f i - c + a) mod n1, (f j - c + b) mod n2]
+// on an output grid o1 x o2.  g = flipped PSF gives H (f = 1) or S H (f > 1);
+// g = PSF gives H^T.
+constexpr int kCorTH = 16, kCorTW = 64;
+
+template <class SI, class SO, class C>
+__global__ __launch_bounds__(256) void correlate_kernel(
+    const SI* __restrict__ in, SO* __restrict__ out, const C* __restrict__ g,
+    int k, int n1, int n2, int o1, int o2, int f) {
+  extern __shared__ unsigned char smem_raw[];
+  C* sg = reinterpret_cast<C*>(smem_raw);
+  C* tile = sg + k * k;
+  const int c = (k - 1) / 2;
+  const int i0 = blockIdx.y * kCorTH, j0 = blockIdx.x * kCorTW;
+  const int th = f * (kCorTH - 1) + k, tw = f * (kCorTW - 1) + k;
+  const SI* src = in + static_cast<size_t>(blockIdx.z) * n1 * n2;
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x) sg[t] = g[t];
+  const int r0 = f * i0 - c, q0 = f * j0 - c;
+  for (int t = threadIdx.x; t < th * tw; t += blockDim.x) {
+    int r = t / tw, q = t - r * tw;
+    int gr = (r0 + r) % n1; if (gr < 0) gr += n1;
+    int gq = (q0 + q) % n2; if (gq < 0) gq += n2;
+    tile[t] = Io<SI>::ld(src, static_cast<size_t>(gr) * n2 + gq);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  SO* dst = out + static_cast<size_t>(blockIdx.z) * o1 * o2;
+  for (int rr = ty; rr < kCorTH; rr += 4) {
+    int oi = i0 + rr, oj = j0 + tx;
+    if (oi >= o1 || oj >= o2) continue;
+    C acc = 0;
+    const C* base = tile + (f * rr) * tw + f * tx;
+    for (int a = 0; a < k; ++a) {
+      const C* row = base + a * tw;
+      const C* grow = sg + a * k;
+      for (int b = 0; b < k; ++b) acc += grow[b] * row[b];
+    }
+    Io<SO>::st(dst, static_cast<size_t>(oi) * o2 + oj, acc);
+  }
+}
+
+// Adjoint of blur + decimation: out[p, q] = sum_{a,b} h[a, b] Z[p - c + a, q - c + b]
+// with Z the zero-filled upsampling (by f) of the m1 x m2 input.
+constexpr int kUpTH = 32, kUpTW = 64;
+
+__host__ __device__ inline int floor_div(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+template <class SI, class SO, class C>
+__global__ __launch_bounds__(256) void upcorrelate_kernel(
+    const SI* __restrict__ in, SO* __restrict__ out, const C* __restrict__ h,
+    int k, int m1, int m2, int f) {
+  extern __shared__ unsigned char smem_raw[];
+  C* sh = reinterpret_cast<C*>(smem_raw);
+  C* tile = sh + k * k;
+  const int n1 = m1 * f, n2 = m2 * f, c = (k - 1) / 2;
+  const int p0 = blockIdx.y * kUpTH, q0 = blockIdx.x * kUpTW;
+  const int R0 = floor_div(p0 - c, f), R1 = floor_div(p0 + kUpTH - 1 - c + k - 1, f);
+  const int C0 = floor_div(q0 - c, f), C1 = floor_div(q0 + kUpTW - 1 - c + k - 1, f);
+  const int th = R1 - R0 + 1, tw = C1 - C0 + 1;
+  const SI* src = in + static_cast<size_t>(blockIdx.z) * m1 * m2;
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x) sh[t] = h[t];
+  for (int t = threadIdx.x; t < th * tw; t += blockDim.x) {
+    int r = t / tw, q = t - r * tw;
+    int gr = (R0 + r) % m1; if (gr < 0) gr += m1;
+    int gq = (C0 + q) % m2; if (gq < 0) gq += m2;
+    tile[t] = Io<SI>::ld(src, static_cast<size_t>(gr) * m2 + gq);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  SO* dst = out + static_cast<size_t>(blockIdx.z) * n1 * n2;
+  const int q = q0 + tx;
+  int bs = (c - q) % f; if (bs < 0) bs += f;
+  for (int rr = ty; rr < kUpTH; rr += 4) {
+    int p = p0 + rr;
+    if (p >= n1 || q >= n2) continue;
+    int as = (c - p) % f; if (as < 0) as += f;
+    C acc = 0;
+    for (int a = as; a < k; a += f) {
+      int lr = (p - c + a - f * R0) / f;
+      const C* row = tile + lr * tw;
+      for (int b = bs; b < k; b += f) {
+        int lc = (q - c + b - f * C0) / f;
+        acc += sh[a * k + b] * row[lc];
+      }
+    }
+    Io<SO>::st(dst, static_cast<size_t>(p) * n2 + q, acc);
+  }
+}
+
+// ================================================================ Haar
+// One thread per 2^L x 2^L block; in-place layout.  Analysis applies levels
+// 0..L-1 (stride 1, 2, 4 inside the block), synthesis the reverse order.
+template <int L, bool kAnalysis, class SI, class SO, class C>
+__global__ __launch_bounds__(256) void haar_kernel(const SI* __restrict__ in,
+                                                   SO* __restrict__ out, int n1, int n2) {
+  constexpr int B = 1 << L;
+  const int nb2 = n2 / B, nb1 = n1 / B;
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk >= nb1 * nb2) return;
+  const int bi = blk / nb2, bj = blk - bi * nb2;
+  const size_t base = static_cast<size_t>(blockIdx.z) * n1 * n2 +
+                      static_cast<size_t>(bi * B) * n2 + bj * B;
+  C v[B][B];
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int q = 0; q < B; ++q) v[r][q] = Io<SI>::ld(in, base + static_cast<size_t>(r) * n2 + q);
+#pragma unroll
+  for (int it = 0; it < L; ++it) {
+    const int lev = kAnalysis ? it : (L - 1 - it);
+    const int s = 1 << lev;
+#pragma unroll
+    for (int r = 0; r < B; r += 2 * s)
+#pragma unroll
+      for (int q = 0; q < B; q += 2 * s) {
+        C a = v[r][q], b = v[r][q + s], cc = v[r + s][q], d = v[r + s][q + s];
+        v[r][q] = (a + b + cc + d) * C(0.5);
+        v[r][q + s] = (a - b + cc - d) * C(0.5);
+        v[r + s][q] = (a + b - cc - d) * C(0.5);
+        v[r + s][q + s] = (a - b - cc + d) * C(0.5);
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int q = 0; q < B; ++q) Io<SO>::st(out, base + static_cast<size_t>(r) * n2 + q, v[r][q]);
+}
+
+// ================================================================ Joseph
+// Interpolation coordinate of the ray (s, view) at stepped-axis coordinate t:
+// (s - t * b) / a + c, with (a, b) = (cos, sin) on the row branch and
+// (sin, cos) on the column branch.  Forward and adjoint share this function
+// so both use identical weights.
+template <class C>
+__device__ __forceinline__ C joseph_coord(C s, C t, C a, C b, C c) {
+  return (s - t * b) / a + c;
+}
+
+template <class SI, class SO, class C>
+__global__ __launch_bounds__(256) void joseph_fwd_kernel(
+    const SI* __restrict__ x, SO* __restrict__ p, int n, int V, int B,
+    const C* __restrict__ trig) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (b >= B) return;
+  const SI* img = x + static_cast<size_t>(blockIdx.z) * n * n;
+  const C ct = trig[2 * v], st = trig[2 * v + 1];
+  const C c = C(0.5) * C(n - 1);
+  const C s = C(b) - C(0.5) * C(B - 1);
+  const bool rows = fabs(ct) >= fabs(st);
+  const C a = rows ? ct : st, bb = rows ? st : ct;
+  C acc = 0;
+  for (int t = 0; t < n; ++t) {
+    C f = joseph_coord<C>(s, C(t) - c, a, bb, c);
+    C fl = floor(f);
+    int q = static_cast<int>(fl);
+    C w = f - fl;
+    if (q >= -1 && q < n) {
+      C lo = 0, hi = 0;
+      if (rows) {
+        if (q >= 0) lo = Io<SI>::ld(img, static_cast<size_t>(t) * n + q);
+        if (q + 1 < n) hi = Io<SI>::ld(img, static_cast<size_t>(t) * n + q + 1);
+      } else {
+        if (q >= 0) lo = Io<SI>::ld(img, static_cast<size_t>(q) * n + t);
+        if (q + 1 < n) hi = Io<SI>::ld(img, static_cast<size_t>(q + 1) * n + t);
+      }
+      acc += (C(1) - w) * lo + w * hi;
+    }
+  }
+  Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b, acc / fabs(a));
+}
+
+// Gather-form transpose: pixel (i, j) collects, per view, the (at most two)
+// rays whose interpolation pair contains it.  Candidate bins are searched
+// around the exact inverse map and confirmed with joseph_coord.
+template <class SI, class SO, class C>
+__global__ __launch_bounds__(256) void joseph_adj_kernel(
+    const SI* __restrict__ p, SO* __restrict__ x, int n, int V, int B,
+    const C* __restrict__ trig) {
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= n || j >= n) return;
+  const SI* sino = p + static_cast<size_t>(blockIdx.z) * V * B;
+  const C c = C(0.5) * C(n - 1);
+  const C half = C(0.5) * C(B - 1);
+  C acc = 0;
+  for (int v = 0; v < V; ++v) {
+    const C ct = trig[2 * v], st = trig[2 * v + 1];
+    const bool rows = fabs(ct) >= fabs(st);
+    const C a = rows ? ct : st, bb = rows ? st : ct;
+    // stepped coordinate t and interpolated index q of this pixel
+    const int ts = rows ? i : j, q = rows ? j : i;
+    const C t = C(ts) - c;
+    const C smid = (C(q) - c) * a + t * bb + half;
+    const int b0 = static_cast<int>(floor(smid));
+    C part = 0;
+    for (int bq = b0 - 2; bq <= b0 + 2; ++bq) {
+      if (bq < 0 || bq >= B) continue;
+      C f = joseph_coord<C>(C(bq) - half, t, a, bb, c);
+      C fl = floor(f);
+      int qq = static_cast<int>(fl);
+      C w = f - fl;
+      C val = Io<SI>::ld(sino, static_cast<size_t>(v) * B + bq);
+      if (qq == q) part += (C(1) - w) * val;
+      else if (qq == q - 1) part += w * val;
+    }
+    acc += part / fabs(a);
+  }
+  Io<SO>::st(x, static_cast<size_t>(blockIdx.z) * n * n + static_cast<size_t>(i) * n + j, acc);
+}
+
+// ================================================================ launchers
+template <class C> const C* psf_ptr(const nys_op_s* op, bool flipped);
+template <> const double* psf_ptr<double>(const nys_op_s* op, bool flipped) {
+  int kk = op->d.psf_size * op->d.psf_size;
+  return op->psf_dev.as<double>() + (flipped ? 0 : kk);
+}
+template <> const float* psf_ptr<float>(const nys_op_s* op, bool flipped) {
+  int kk = op->d.psf_size * op->d.psf_size;
+  return reinterpret_cast<const float*>(op->psf_dev.as<double>() + 2 * kk) + (flipped ? 0 : kk);
+}
+template <class C> const C* trig_ptr(const nys_op_s* op);
+template <> const double* trig_ptr<double>(const nys_op_s* op) { return op->trig.as<double>(); }
+template <> const float* trig_ptr<float>(const nys_op_s* op) {
+  return reinterpret_cast<const float*>(op->trig.as<double>() + 2 * op->d.n_views);
+}
+
+template <class SI, class SO, class C>
+static nys_status launch_correlate(const nys_op_s* op, const SI* in, SO* out, bool flipped,
+                                   int n1, int n2, int f, int64_t ncols, hipStream_t st) {
+  const int k = op->d.psf_size;
+  const int o1 = n1 / f, o2 = n2 / f;
+  dim3 grid(cdiv(o2, kCorTW), cdiv(o1, kCorTH), static_cast<unsigned>(ncols));
+  size_t sm = sizeof(C) * (k * k + (f * (kCorTH - 1) + k) * (f * (kCorTW - 1) + k));
+  hipLaunchKernelGGL((correlate_kernel<SI, SO, C>), grid, dim3(256), sm, st, in, out,
+                     psf_ptr<C>(op, flipped), k, n1, n2, o1, o2, f);
+  return launch_check("correlate_kernel");
+}
+
+template <class SI, class SO, class C>
+static nys_status launch_upcorrelate(const nys_op_s* op, const SI* in, SO* out, int m1,
+                                     int m2, int f, int64_t ncols, hipStream_t st) {
+  const int k = op->d.psf_size;
+  const int n1 = m1 * f, n2 = m2 * f;
+  dim3 grid(cdiv(n2, kUpTW), cdiv(n1, kUpTH), static_cast<unsigned>(ncols));
+  int th = (kUpTH - 1 + k - 1) / f + 2, tw = (kUpTW - 1 + k - 1) / f + 2;
+  size_t sm = sizeof(C) * (k * k + th * tw);
+  hipLaunchKernelGGL((upcorrelate_kernel<SI, SO, C>), grid, dim3(256), sm, st, in, out,
+                     psf_ptr<C>(op, false), k, m1, m2, f);
+  return launch_check("upcorrelate_kernel");
+}
+
+template <bool kAnalysis, class SI, class SO, class C>
+static nys_status launch_haar(int levels, const SI* in, SO* out, int n1, int n2, int64_t ncols,
+                              hipStream_t st) {
+  const int B = 1 << levels;
+  const int blocks = (n1 / B) * (n2 / B);
+  dim3 grid(cdiv(blocks, 256), 1, static_cast<unsigned>(ncols));
+  switch (levels) {
+    case 1: hipLaunchKernelGGL((haar_kernel<1, kAnalysis, SI, SO, C>), grid, dim3(256), 0, st, in, out, n1, n2); break;
+    case 2: hipLaunchKernelGGL((haar_kernel<2, kAnalysis, SI, SO, C>), grid, dim3(256), 0, st, in, out, n1, n2); break;
+    case 3: hipLaunchKernelGGL((haar_kernel<3, kAnalysis, SI, SO, C>), grid, dim3(256), 0, st, in, out, n1, n2); break;
+    default: set_error("wavelet levels must be 1..3"); return NYS_EINVAL;
+  }
+  return launch_check("haar_kernel");
+}
+
+template <class SI, class SO, class C>
+static nys_status launch_joseph_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t ncols,
+                                    hipStream_t st) {
+  const int n = op->d.n1, V = op->d.n_views, B = op->d.n_bins;
+  dim3 grid(cdiv(B, 256), V, static_cast<unsigned>(ncols));
+  hipLaunchKernelGGL((joseph_fwd_kernel<SI, SO, C>), grid, dim3(256), 0, st, x, p, n, V, B,
+                     trig_ptr<C>(op));
+  return launch_check("joseph_fwd_kernel");
+}
+
+template <class SI, class SO, class C>
+static nys_status launch_joseph_adj(const nys_op_s* op, const SI* p, SO* x, int64_t ncols,
+                                    hipStream_t st) {
+  const int n = op->d.n1, V = op->d.n_views, B = op->d.n_bins;
+  dim3 grid(cdiv(n, 64), cdiv(n, 4), static_cast<unsigned>(ncols));
+  hipLaunchKernelGGL((joseph_adj_kernel<SI, SO, C>), grid, dim3(256), 0, st, p, x, n, V, B,
+                     trig_ptr<C>(op));
+  return launch_check("joseph_adj_kernel");
+}
+
+// A applied to an image (no wavelet composition): SI -> SO.
+template <class SI, class SO, class C>
+static nys_status apply_A_plain(nys_op_s* op, const SI* x, SO* y, int64_t ncols, hipStream_t st) {
+  const auto& d = op->d;
+  switch (d.kind) {
+    case NYS_OP_BLUR:
+      return launch_correlate<SI, SO, C>(op, x, y, true, d.n1, d.n2, 1, ncols, st);
+    case NYS_OP_BLURDOWN:
+      return launch_correlate<SI, SO, C>(op, x, y, true, d.n1, d.n2, d.factor, ncols, st);
+    case NYS_OP_PARALLEL_BEAM:
+      return launch_joseph_fwd<SI, SO, C>(op, x, y, ncols, st);
+    default: break;
+  }
+  set_error("apply_A_plain: bad operator kind");
+  return NYS_EINVAL;
+}
+
+template <class SI, class SO, class C>
+static nys_status apply_At_plain(nys_op_s* op, const SI* y, SO* x, int64_t ncols, hipStream_t st) {
+  const auto& d = op->d;
+  switch (d.kind) {
+    case NYS_OP_BLUR:
+      return launch_correlate<SI, SO, C>(op, y, x, false, d.n1, d.n2, 1, ncols, st);
+    case NYS_OP_BLURDOWN:
+      return launch_upcorrelate<SI, SO, C>(op, y, x, d.n1 / d.factor, d.n2 / d.factor,
+                                           d.factor, ncols, st);
+    case NYS_OP_PARALLEL_BEAM:
+      return launch_joseph_adj<SI, SO, C>(op, y, x, ncols, st);
+    default: break;
+  }
+  set_error("apply_At_plain: bad operator kind");
+  return NYS_EINVAL;
+}
+
+template <class T>
+static nys_status copy_cols(const T* src, T* dst, size_t count, hipStream_t st) {
+  if (src == dst) return NYS_OK;
+  NYS_CHECK_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToDevice, st));
+  return NYS_OK;
+}
+
+// y = A x with the optional wavelet synthesis in front (x holds coefficients).
+template <class T>
+nys_status op_fwd(nys_op op, const T* x, T* y, int64_t ncols, hipStream_t st) {
+  const auto& d = op->d;
+  const T* src = x;
+  if (d.wavelet_levels > 0) {
+    NYS_TRY(op->tmp0.ensure(sizeof(T) * op->N * ncols));
+    T* t = op->tmp0.as<T>();
+    NYS_TRY((launch_haar<false, T, T, T>(d.wavelet_levels, x, d.kind == NYS_OP_IDENTITY ? y : t,
+                                        d.n1, d.n2, ncols, st)));
+    if (d.kind == NYS_OP_IDENTITY) return NYS_OK;
+    src = t;
+  } else if (d.kind == NYS_OP_IDENTITY) {
+    return copy_cols(x, y, static_cast<size_t>(op->N) * ncols, st);
+  }
+  return apply_A_plain<T, T, T>(op, src, y, ncols, st);
+}
+
+template <class T>
+nys_status op_adj(nys_op op, const T* y, T* x, int64_t ncols, hipStream_t st) {
+  const auto& d = op->d;
+  if (d.kind == NYS_OP_IDENTITY) {
+    if (d.wavelet_levels > 0)
+      return launch_haar<true, T, T, T>(d.wavelet_levels, y, x, d.n1, d.n2, ncols, st);
+    return copy_cols(y, x, static_cast<size_t>(op->N) * ncols, st);
+  }
+  if (d.wavelet_levels > 0) {
+    NYS_TRY(op->tmp0.ensure(sizeof(T) * op->N * ncols));
+    T* t = op->tmp0.as<T>();
+    NYS_TRY((apply_At_plain<T, T, T>(op, y, t, ncols, st)));
+    return launch_haar<true, T, T, T>(d.wavelet_levels, t, x, d.n1, d.n2, ncols, st);
+  }
+  return apply_At_plain<T, T, T>(op, y, x, ncols, st);
+}
+
+template nys_status op_fwd<double>(nys_op, const double*, double*, int64_t, hipStream_t);
+template nys_status op_fwd<float>(nys_op, const float*, float*, int64_t, hipStream_t);
+template nys_status op_adj<double>(nys_op, const double*, double*, int64_t, hipStream_t);
+template nys_status op_adj<float>(nys_op, const float*, float*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------- sketch
+// Y = Phi Omega.  S is the storage type of Omega and Y; C the compute type.
+// Intermediates are kept in C.  Each stage processes all columns at once.
+template <class S, class C>
+static nys_status sketch_chain(nys_op op, const S* omega, S* Y, int64_t ell, hipStream_t st) {
+  const auto& d = op->d;
+  const int64_t N = op->N, M = op->M;
+  const bool wav = d.wavelet_levels > 0;
+  if (d.kind == NYS_OP_IDENTITY) {
+    // Phi = W W^T = I
+    NYS_TRY(op->tmp0.ensure(sizeof(C) * N * ell));
+    C* t = op->tmp0.as<C>();
+    if (wav) {
+      NYS_TRY((launch_haar<false, S, C, C>(d.wavelet_levels, omega, t, d.n1, d.n2, ell, st)));
+      return launch_haar<true, C, S, C>(d.wavelet_levels, t, Y, d.n1, d.n2, ell, st);
+    }
+    NYS_CHECK_HIP(hipMemcpyAsync(Y, omega, sizeof(S) * N * ell, hipMemcpyDeviceToDevice, st));
+    return NYS_OK;
+  }
+  NYS_TRY(op->tmp0.ensure(sizeof(C) * (wav ? N : 0) * ell + 64));
+  NYS_TRY(op->tmp1.ensure(sizeof(C) * std::max(M, wav ? N : 0) * ell));
+  C* img = op->tmp0.as<C>();
+  C* meas = op->tmp1.as<C>();
+  if (wav) {
+    NYS_TRY((launch_haar<false, S, C, C>(d.wavelet_levels, omega, img, d.n1, d.n2, ell, st)));
+    NYS_TRY((apply_A_plain<C, C, C>(op, img, meas, ell, st)));
+    NYS_TRY((apply_At_plain<C, C, C>(op, meas, img, ell, st)));
+    return launch_haar<true, C, S, C>(d.wavelet_levels, img, Y, d.n1, d.n2, ell, st);
+  }
+  NYS_TRY((apply_A_plain<S, C, C>(op, omega, meas, ell, st)));
+  return apply_At_plain<C, S, C>(op, meas, Y, ell, st);
+}
+
+nys_status sketch_dispatch(nys_op op, nys_dtype dt, const void* omega, void* Y, int64_t ell,
+                           hipStream_t st) {
+  switch (dt) {
+    case NYS_F64:
+      return sketch_chain<double, double>(op, static_cast<const double*>(omega),
+                                          static_cast<double*>(Y), ell, st);
+    case NYS_F32:
+      if (op->d.kind == NYS_OP_BLURDOWN && op->d.wavelet_levels == 3 && op->d.factor == 2)
+        return sketch_sr_fused<float>(op, static_cast<const float*>(omega),
+                                      static_cast<float*>(Y), ell, st);
+      return sketch_chain<float, float>(op, static_cast<const float*>(omega),
+                                        static_cast<float*>(Y), ell, st);
+    case NYS_BF16:
+      if (op->d.kind == NYS_OP_BLURDOWN && op->d.wavelet_levels == 3 && op->d.factor == 2)
+        return sketch_sr_fused<uint16_t>(op, static_cast<const uint16_t*>(omega),
+                                         static_cast<uint16_t*>(Y), ell, st);
+      return sketch_chain<uint16_t, float>(op, static_cast<const uint16_t*>(omega),
+                                           static_cast<uint16_t*>(Y), ell, st);
+  }
+  set_error("nys_sketch: bad dtype");
+  return NYS_EINVAL;
+}
+
+// Reference (unfused) chain for the fused super-resolution sketch; exposed to
+// the fused path's own fallback and to tests through an environment switch.
+nys_status sketch_sr_chain_bf16(nys_op op, const uint16_t* omega, uint16_t* Y, int64_t ell,
+                                hipStream_t st) {
+  return sketch_chain<uint16_t, float>(op, omega, Y, ell, st);
+}
+nys_status sketch_sr_chain_f32(nys_op op, const float* omega, float* Y, int64_t ell,
+                               hipStream_t st) {
+  return sketch_chain<float, float>(op, omega, Y, ell, st);
+}
+
+}  // namespace nys
+
+// ================================================================ C ABI
+using namespace nys;
+
+extern "C" const char* nys_last_error(void) { return nys::g_err; }
+extern "C" const char* nys_version(void) { return "nys-mi355x 0.1 (gfx950)"; }
+
+extern "C" nys_status nys_op_create(const nys_op_desc* desc, nys_op* out) {
+  NYS_REQUIRE(desc && out, "nys_op_create: null argument");
+  const nys_op_desc& d = *desc;
+  NYS_REQUIRE(d.n1 > 0 && d.n2 > 0, "nys_op_create: bad image size %d x %d", d.n1, d.n2);
+  NYS_REQUIRE(d.wavelet_levels >= 0 && d.wavelet_levels <= 3, "wavelet_levels must be 0..3");
+  if (d.wavelet_levels > 0) {
+    int B = 1 << d.wavelet_levels;
+    NYS_REQUIRE(d.n1 % B == 0 && d.n2 % B == 0, "image size not divisible by 2^levels");
+  }
+  auto* op = new nys_op_s();
+  op->d = d;
+  op->d.psf = nullptr;
+  op->N = static_cast<int64_t>(d.n1) * d.n2;
+  nys_status st = NYS_OK;
+  switch (d.kind) {
+    case NYS_OP_BLUR:
+    case NYS_OP_BLURDOWN: {
+      int k = d.psf_size;
+      int f = d.kind == NYS_OP_BLUR ? 1 : d.factor;
+      if (!(k >= 1 && k % 2 == 1 && k <= 31 && d.psf && f >= 1 && d.n1 % f == 0 &&
+            d.n2 % f == 0 && k <= d.n1 && k <= d.n2)) {
+        delete op;
+        set_error("nys_op_create: bad PSF size %d / factor %d for %d x %d", k, d.factor, d.n1, d.n2);
+        return NYS_EINVAL;
+      }
+      op->d.factor = f;
+      op->M = static_cast<int64_t>(d.n1 / f) * (d.n2 / f);
+      op->psf.assign(d.psf, d.psf + k * k);
+      std::vector<double> h64(2 * k * k);
+      std::vector<float> h32(2 * k * k);
+      for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+          h64[a * k + b] = op->psf[(k - 1 - a) * k + (k - 1 - b)];
+          h64[k * k + a * k + b] = op->psf[a * k + b];
+        }
+      for (int t = 0; t < 2 * k * k; ++t) h32[t] = static_cast<float>(h64[t]);
+      st = op->psf_dev.ensure(2 * k * k * (8 + 4));
+      if (st == NYS_OK) {
+        hipMemcpy(op->psf_dev.p, h64.data(), 8 * 2 * k * k, hipMemcpyHostToDevice);
+        hipMemcpy(op->psf_dev.as<double>() + 2 * k * k, h32.data(), 4 * 2 * k * k,
+                  hipMemcpyHostToDevice);
+      }
+      break;
+    }
+    case NYS_OP_PARALLEL_BEAM: {
+      if (!(d.n1 == d.n2 && d.n_views > 0 && d.n_bins > 0)) {
+        delete op;
+        set_error("nys_op_create: parallel beam needs a square image and views, bins > 0");
+        return NYS_EINVAL;
+      }
+      op->M = static_cast<int64_t>(d.n_views) * d.n_bins;
+      std::vector<double> t64(2 * d.n_views);
+      std::vector<float> t32(2 * d.n_views);
+      for (int v = 0; v < d.n_views; ++v) {
+        double th = M_PI * v / d.n_views;
+        t64[2 * v] = std::cos(th);
+        t64[2 * v + 1] = std::sin(th);
+        t32[2 * v] = static_cast<float>(t64[2 * v]);
+        t32[2 * v + 1] = static_cast<float>(t64[2 * v + 1]);
+      }
+      st = op->trig.ensure(d.n_views * 2 * (8 + 4));
+      if (st == NYS_OK) {
+        hipMemcpy(op->trig.p, t64.data(), 8 * 2 * d.n_views, hipMemcpyHostToDevice);
+        hipMemcpy(op->trig.as<double>() + 2 * d.n_views, t32.data(), 4 * 2 * d.n_views,
+                  hipMemcpyHostToDevice);
+      }
+      break;
+    }
+    case NYS_OP_IDENTITY:
+      op->M = op->N;
+      break;
+    default:
+      delete op;
+      set_error("nys_op_create: unknown kind %d", d.kind);
+      return NYS_EINVAL;
+  }
+  if (st != NYS_OK) {
+    delete op;
+    return st;
+  }
+  *out = op;
+  return NYS_OK;
+}
+
+extern "C" void nys_op_destroy(nys_op op) {
+  if (!op) return;
+  op->psf_dev.release();
+  op->trig.release();
+  op->tmp0.release();
+  op->tmp1.release();
+  delete op;
+}
+
+extern "C" nys_status nys_op_shape(nys_op op, int64_t* n_unknowns, int64_t* n_meas) {
+  NYS_REQUIRE(op, "nys_op_shape: null op");
+  if (n_unknowns) *n_unknowns = op->N;
+  if (n_meas) *n_meas = op->M;
+  return NYS_OK;
+}
+
+extern "C" nys_status op_forward(nys_op op, nys_dtype dt, const void* x, void* y, int64_t ncols,
+                                 void* stream) {
+  NYS_REQUIRE(op && x && y && ncols > 0, "op_forward: bad argument");
+  NYS_REQUIRE(ncols <= 65535, "op_forward: ncols > 65535");
+  if (dt == NYS_F64)
+    return op_fwd<double>(op, static_cast<const double*>(x), static_cast<double*>(y), ncols,
+                          as_stream(stream));
+  if (dt == NYS_F32)
+    return op_fwd<float>(op, static_cast<const float*>(x), static_cast<float*>(y), ncols,
+                         as_stream(stream));
+  set_error("op_forward: dtype must be F64 or F32");
+  return NYS_EINVAL;
+}
+
+extern "C" nys_status op_adjoint(nys_op op, nys_dtype dt, const void* y, void* x, int64_t ncols,
+                                 void* stream) {
+  NYS_REQUIRE(op && x && y && ncols > 0, "op_adjoint: bad argument");
+  NYS_REQUIRE(ncols <= 65535, "op_adjoint: ncols > 65535");
+  if (dt == NYS_F64)
+    return op_adj<double>(op, static_cast<const double*>(y), static_cast<double*>(x), ncols,
+                          as_stream(stream));
+  if (dt == NYS_F32)
+    return op_adj<float>(op, static_cast<const float*>(y), static_cast<float*>(x), ncols,
+                         as_stream(stream));
+  set_error("op_adjoint: dtype must be F64 or F32");
+  return NYS_EINVAL;
+}
+
+extern "C" nys_status nys_sketch(nys_op op, nys_dtype dt, const void* omega, void* Y, int64_t ell,
+                                 void* stream) {
+  NYS_REQUIRE(op && omega && Y && ell > 0, "nys_sketch: bad argument");
+  NYS_REQUIRE(ell <= 65535, "nys_sketch: ell > 65535");
+  NYS_REQUIRE(omega != Y, "nys_sketch: omega and Y must not alias");
+  return sketch_dispatch(op, dt, omega, Y, ell, as_stream(stream));
+}

@@ -1,0 +1,340 @@
+// WAPG (Alg. 3), its step size by the power method (eq. (15) constant), and
+// the cost F = f + lambda g with FP64 accumulation.
+
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace nys {
+
+template <class T> nys_status fill_zero(T* p, size_t n, hipStream_t st);
+
+// ---------------------------------------------------------------- elementwise
+// r = (A u) - y, then psi'(r) = clip(r / delta, -1, 1) for the Huber loss
+template <class T>
+__global__ void residual_kernel(T* __restrict__ r, const T* __restrict__ y, int64_t M, int loss,
+                                T delta) {
+  const int64_t m = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (m >= M) return;
+  T v = r[m] - y[m];
+  if (loss == NYS_LOSS_HUBER) v = fmin(T(1), fmax(T(-1), v / delta));
+  r[m] = v;
+}
+
+// s = u - alpha g
+template <class T>
+__global__ void step_kernel(const T* __restrict__ u, const T* __restrict__ g, T alpha, int64_t N,
+                            T* __restrict__ s) {
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (n >= N) return;
+  s[n] = u[n] - alpha * g[n];
+}
+
+// u = x+ + beta (x+ - x);  x = x+
+template <class T>
+__global__ void momentum_kernel(const T* __restrict__ xn, T* __restrict__ x, T* __restrict__ u,
+                                T beta, int64_t N) {
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (n >= N) return;
+  T a = xn[n];
+  u[n] = a + beta * (a - x[n]);
+  x[n] = a;
+}
+
+// ---------------------------------------------------------------- reductions
+// Block sums (FP64) of a per-element term; `which` selects the term.
+enum Term { kSq = 0, kHuber = 1, kAbs = 2, kTV = 3, kTVAniso = 4, kHS1 = 5 };
+
+template <class T>
+__device__ __forceinline__ double term_at(const T* a, const T* b, int64_t i, int which, T delta,
+                                          int n1, int n2) {
+  switch (which) {
+    case kSq: { double r = static_cast<double>(a[i]) - static_cast<double>(b[i]); return 0.5 * r * r; }
+    case kHuber: {
+      double r = static_cast<double>(a[i]) - static_cast<double>(b[i]);
+      double ar = fabs(r), d = static_cast<double>(delta);
+      return ar <= d ? r * r / (2 * d) : ar - d / 2;
+    }
+    case kAbs: return fabs(static_cast<double>(a[i]));
+    default: break;
+  }
+  const int r = static_cast<int>(i / n2), c = static_cast<int>(i % n2);
+  auto X = [&](int rr, int cc) -> double {
+    rr = rr < 0 ? 0 : (rr >= n1 ? n1 - 1 : rr);
+    cc = cc < 0 ? 0 : (cc >= n2 ? n2 - 1 : cc);
+    return static_cast<double>(a[static_cast<int64_t>(rr) * n2 + cc]);
+  };
+  if (which == kTV || which == kTVAniso) {
+    double d1 = r >= 1 ? X(r, c) - X(r - 1, c) : 0.0;
+    double d2 = c >= 1 ? X(r, c) - X(r, c - 1) : 0.0;
+    return which == kTV ? sqrt(d1 * d1 + d2 * d2) : fabs(d1) + fabs(d2);
+  }
+  double v11 = X(r - 1, c) - 2 * X(r, c) + X(r + 1, c);
+  double v22 = X(r, c - 1) - 2 * X(r, c) + X(r, c + 1);
+  double v12 = 0.25 * (X(r + 1, c + 1) - X(r + 1, c - 1) - X(r - 1, c + 1) + X(r - 1, c - 1));
+  double m = 0.5 * (v11 + v22), h = 0.5 * (v11 - v22);
+  double rad = sqrt(h * h + v12 * v12);
+  return fabs(m + rad) + fabs(m - rad);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void term_sum_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                                                       int64_t n, int which, T delta, int n1, int n2,
+                                                       double* __restrict__ part) {
+  double s = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s += term_at(a, b, i, which, delta, n1, n2);
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out = w0 * sum(part0[0:n0]) + w1 * sum(part1[0:n1])
+__global__ void combine_kernel(const double* __restrict__ p0, int n0, double w0,
+                               const double* __restrict__ p1, int n1, double w1,
+                               double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0, b = 0;
+  for (int i = 0; i < n0; ++i) a += p0[i];
+  for (int i = 0; i < n1; ++i) b += p1[i];
+  *out = w0 * a + w1 * b;
+}
+
+// v = w / ||w||, norm[it] = ||w|| (power method, FP64 norm)
+template <class T>
+__global__ void scale_by_norm_kernel(const T* __restrict__ w, T* __restrict__ v, int64_t N,
+                                     const double* __restrict__ part, int np,
+                                     double* __restrict__ norm_out) {
+  __shared__ double nrm;
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int i = 0; i < np; ++i) s += part[i];
+    nrm = sqrt(s);
+    if (blockIdx.x == 0) *norm_out = nrm;
+  }
+  __syncthreads();
+  const T inv = static_cast<T>(nrm > 0 ? 1.0 / nrm : 0.0);
+  for (int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; n < N;
+       n += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    v[n] = w[n] * inv;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void sumsq_kernel(const T* __restrict__ a, int64_t n,
+                                                    double* __restrict__ part) {
+  double s = 0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double v = static_cast<double>(a[i]);
+    s += v * v;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+constexpr int kRedBlocks = 256;
+
+struct SolveBufs {
+  void* meas;     // M
+  void* g;        // N
+  void* s;        // N
+  void* xn;       // N
+  void* u;        // N
+  void* v;        // N (power method)
+  void* state;    // prox warm start
+  double* part;   // 2 * kRedBlocks
+  double* norms;  // power-method norms
+};
+
+template <class T>
+static int reg_term(const nys_reg_desc& r) {
+  switch (r.kind) {
+    case NYS_REG_TV: return kTV;
+    case NYS_REG_TV_ANISO: return kTVAniso;
+    case NYS_REG_HS1: return kHS1;
+    default: return kAbs;
+  }
+}
+
+template <class T>
+static nys_status cost_impl(const nys_problem& p, const T* x, double* cost, T* meas, double* part,
+                            hipStream_t st) {
+  nys_op op = p.op;
+  NYS_TRY(op_fwd<T>(op, x, meas, 1, st));
+  const int which = p.loss == NYS_LOSS_HUBER ? kHuber : kSq;
+  hipLaunchKernelGGL((term_sum_kernel<T>), dim3(kRedBlocks), dim3(256), 0, st, meas,
+                     static_cast<const T*>(p.y), op->M, which, static_cast<T>(p.delta), 0, 1, part);
+  NYS_TRY(launch_check("term_sum_kernel"));
+  hipLaunchKernelGGL((term_sum_kernel<T>), dim3(kRedBlocks), dim3(256), 0, st, x,
+                     static_cast<const T*>(nullptr), op->N, reg_term<T>(p.reg),
+                     static_cast<T>(0), p.reg.n1, p.reg.n2, part + kRedBlocks);
+  NYS_TRY(launch_check("term_sum_kernel"));
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, part, kRedBlocks, 1.0,
+                     part + kRedBlocks, kRedBlocks, p.lambda, cost);
+  return launch_check("combine_kernel");
+}
+
+// One power-method step: w = P^{-1} A^T A v (into g), norm, v = w / ||w||.
+template <class T>
+static nys_status power_step(const nys_problem& p, nys_pc pc, T* v, T* g, T* meas, double* part,
+                             double* norm_out, hipStream_t st) {
+  nys_op op = p.op;
+  const int64_t N = op->N;
+  NYS_TRY(op_fwd<T>(op, v, meas, 1, st));
+  NYS_TRY(op_adj<T>(op, meas, g, 1, st));
+  if (pc) NYS_TRY(pc_apply<T>(pc, true, g, g, 1, st));
+  hipLaunchKernelGGL((sumsq_kernel<T>), dim3(kRedBlocks), dim3(256), 0, st, g, N, part);
+  NYS_TRY(launch_check("sumsq_kernel"));
+  hipLaunchKernelGGL((scale_by_norm_kernel<T>), dim3(std::min<int64_t>(cdiv(N, 256), 1024)),
+                     dim3(256), 0, st, g, v, N, part, kRedBlocks, norm_out);
+  return launch_check("scale_by_norm_kernel");
+}
+
+template <class T>
+static nys_status solve_impl(const nys_problem& p, nys_pc pc, const nys_solve_opts& o, T* x,
+                             double* costs, double* info, hipStream_t st) {
+  nys_op op = p.op;
+  const int64_t N = op->N, M = op->M;
+  const int nch = p.reg.kind == NYS_REG_HS1 ? 3 : (p.reg.kind == NYS_REG_L1 ? 0 : 2);
+  size_t state_bytes = nch ? sizeof(T) * nch * N : (pc ? sizeof(double) * pc->ell : 0);
+  // workspace: meas, g, s, xn, u, v, state, part, norms
+  size_t bytes = sizeof(T) * (M + 5 * N) + 256 + state_bytes + 256 +
+                 sizeof(double) * (2 * kRedBlocks + 8);
+  static thread_local DevBuf ws;
+  NYS_TRY(ws.ensure(bytes + 256));
+  char* base = static_cast<char*>(ws.p);
+  T* meas = reinterpret_cast<T*>(base);
+  T* g = meas + M;
+  T* s = g + N;
+  T* xn = s + N;
+  T* u = xn + N;
+  T* v = u + N;
+  // align the FP64 / state region that follows the T arrays to 256 bytes
+  char* after = reinterpret_cast<char*>(
+      (reinterpret_cast<uintptr_t>(v + N) + 255) & ~static_cast<uintptr_t>(255));
+  void* state = state_bytes ? after : nullptr;
+  double* part = reinterpret_cast<double*>(after + ((state_bytes + 255) / 256) * 256);
+  double* norms = part + 2 * kRedBlocks;
+
+  const double curv = p.loss == NYS_LOSS_HUBER ? 1.0 / p.delta : 1.0;
+  double alpha = o.alpha;
+  double Lest = 0.0;
+  if (!(alpha > 0)) {
+    NYS_REQUIRE(o.power_v0 && o.power_iters > 0, "solve: power_v0 / power_iters needed when alpha <= 0");
+    // v = v0 / ||v0||
+    NYS_CHECK_HIP(hipMemcpyAsync(g, o.power_v0, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL((sumsq_kernel<T>), dim3(kRedBlocks), dim3(256), 0, st, g, N, part);
+    NYS_TRY(launch_check("sumsq_kernel"));
+    hipLaunchKernelGGL((scale_by_norm_kernel<T>), dim3(std::min<int64_t>(cdiv(N, 256), 1024)),
+                       dim3(256), 0, st, g, v, N, part, kRedBlocks, norms);
+    NYS_TRY(launch_check("scale_by_norm_kernel"));
+    for (int it = 0; it < o.power_iters; ++it)
+      NYS_TRY(power_step<T>(p, pc, v, g, meas, part, norms, st));
+    double lam = 0;
+    NYS_CHECK_HIP(hipMemcpyAsync(&lam, norms, sizeof(double), hipMemcpyDeviceToHost, st));
+    NYS_CHECK_HIP(hipStreamSynchronize(st));
+    Lest = curv * lam;
+    const double safety = o.safety > 0 ? o.safety : 1.01;
+    NYS_REQUIRE(Lest > 0 && std::isfinite(Lest), "solve: power method gave L = %g", Lest);
+    alpha = 1.0 / (safety * Lest);
+  }
+  const double lam_bar = alpha * p.lambda;
+  NYS_TRY(fill_zero<T>(x, N, st));
+  NYS_TRY(fill_zero<T>(u, N, st));
+  if (nch) NYS_TRY(fill_zero<T>(static_cast<T*>(state), static_cast<size_t>(nch) * N, st));
+  else if (state) NYS_TRY(fill_zero<double>(static_cast<double*>(state), pc->ell, st));
+  double t_prev = 1.0;
+  for (int k = 0; k < o.max_iter; ++k) {
+    // s = u - alpha P^{-1} grad f(u)
+    NYS_TRY(op_fwd<T>(op, u, meas, 1, st));
+    hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, meas,
+                       static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
+    NYS_TRY(launch_check("residual_kernel"));
+    NYS_TRY(op_adj<T>(op, meas, g, 1, st));
+    if (pc) NYS_TRY(pc_apply<T>(pc, true, g, g, 1, st));
+    hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, u, g,
+                       static_cast<T>(alpha), N, s);
+    NYS_TRY(launch_check("step_kernel"));
+    // x+ = prox^P_{alpha lambda g}(s)
+    NYS_TRY(prox_run<T>(p.reg, lam_bar, pc, s, xn, o.warm_start ? state : nullptr, st));
+    // momentum
+    const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
+    const double beta = (t_prev - 1.0) / t;
+    hipLaunchKernelGGL((momentum_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, xn, x, u,
+                       static_cast<T>(beta), N);
+    NYS_TRY(launch_check("momentum_kernel"));
+    t_prev = t;
+    if (costs) NYS_TRY(cost_impl<T>(p, x, costs + k, meas, part, st));
+  }
+  if (info) {
+    NYS_CHECK_HIP(hipStreamSynchronize(st));
+    info[0] = alpha;
+    info[1] = Lest;
+    info[2] = NYS_OK;
+    info[3] = 0;
+  }
+  return NYS_OK;
+}
+
+}  // namespace nys
+
+using namespace nys;
+
+static nys_status check_problem(const nys_problem* p, nys_dtype dt) {
+  NYS_REQUIRE(p && p->op && p->y, "solve: null problem, operator or y");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "solve: dtype must be F64 or F32");
+  NYS_REQUIRE(static_cast<int64_t>(p->reg.n1) * p->reg.n2 == p->op->N,
+              "solve: regulariser size != number of unknowns");
+  NYS_REQUIRE(p->loss == NYS_LOSS_LS || (p->loss == NYS_LOSS_HUBER && p->delta > 0),
+              "solve: bad loss / delta");
+  NYS_REQUIRE(p->lambda >= 0, "solve: lambda < 0");
+  return NYS_OK;
+}
+
+extern "C" nys_status solve(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                            const nys_solve_opts* opts, void* x_out, double* costs, double* info,
+                            void* stream) {
+  NYS_TRY(check_problem(prob, dt));
+  NYS_REQUIRE(opts && x_out && opts->max_iter >= 0, "solve: bad options or x_out");
+  NYS_REQUIRE(prob->lambda > 0, "solve: lambda must be > 0");
+  if (pc) {
+    NYS_REQUIRE(pc->N == prob->op->N, "solve: pc size != number of unknowns");
+    NYS_REQUIRE(pc->u_dtype == static_cast<int32_t>(dt), "solve: pc u_dtype != solver dtype");
+  }
+  hipStream_t st = as_stream(stream);
+  if (dt == NYS_F64)
+    return solve_impl<double>(*prob, pc, *opts, static_cast<double*>(x_out), costs, info, st);
+  return solve_impl<float>(*prob, pc, *opts, static_cast<float*>(x_out), costs, info, st);
+}
+
+extern "C" nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void* x, double* cost,
+                               void* stream) {
+  NYS_TRY(check_problem(prob, dt));
+  NYS_REQUIRE(x && cost, "nys_cost: null x / cost");
+  static thread_local DevBuf ws;
+  const int64_t M = prob->op->M;
+  NYS_TRY(ws.ensure(dtype_size(dt) * M + sizeof(double) * 2 * kRedBlocks + 64));
+  hipStream_t st = as_stream(stream);
+  char* base = static_cast<char*>(ws.p);
+  double* part = reinterpret_cast<double*>(base);
+  void* meas = base + sizeof(double) * 2 * kRedBlocks;
+  if (dt == NYS_F64)
+    return cost_impl<double>(*prob, static_cast<const double*>(x), cost, static_cast<double*>(meas),
+                             part, st);
+  return cost_impl<float>(*prob, static_cast<const float*>(x), cost, static_cast<float*>(meas), part,
+                          st);
+}

@@ -1,0 +1,224 @@
+"""GPU parity of the Nystrom factorisation, P^{-1}, the weighted prox and
+WAPG against the FP64 oracle (inputs fed identically to both sides)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import nystrom as onys
+from oracle import operators as ops
+from oracle import prox as opx
+from oracle import solver as sv
+from gpu_util import TOL, banner, dev, host, need_gpu, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _blur_case(n, ell, seed=0, k=9, sigma=1.5):
+    h = W.gaussian_psf(k, sigma)
+    prob = sv.Problem("blur", n, None, 0.0, "tv", h=h)
+    om = W.omega(ell, n, n, seed)
+    Y = sv.sketch(prob, om)
+    return prob, om, Y
+
+
+def _ct_case(n, V, B, ell, seed=0):
+    prob = sv.Problem("ct", n, None, 0.0, "hs1", views=V, bins=B)
+    om = W.omega(ell, n, n, seed)
+    Y = sv.sketch(prob, om)
+    return prob, om, Y
+
+
+@pytest.mark.parametrize("case,dt,tail", [("blur", "f64", "sqrt"), ("blur", "f64", "plain"),
+                                          ("ct", "f32", "sqrt"), ("ct", "bf16", "plain")])
+def test_factor_spectrum_and_pinv(case, dt, tail):
+    P = need_gpu()
+    banner(f"factor {case} {dt} {tail}")
+    if case == "blur":
+        prob, om, Y = _blur_case(40, 12)
+    else:
+        prob, om, Y = _ct_case(32, 40, 48, 10)
+    ell, n = om.shape[0], om.shape[1]
+    omd, Yd = dev(om, dt), dev(Y, dt)
+    # the oracle sees exactly the rounded inputs
+    omr, Yr = host(omd).reshape(ell, -1), host(Yd).reshape(ell, -1)
+    ref = onys.nystrom(Yr, omr)
+    udt = torch.float64 if dt == "f64" else torch.float32
+    pc = P.nys_factor(omd, Yd, ell, tail=tail, u_dtype=udt)
+    info = pc.info()
+    assert info["status"] == 0
+    k = len(ref["shat"])
+    tol = TOL["f64"] if dt == "f64" else 1e-5
+    # nu comes from ||Y||_2 of the Gram; FP32/BF16 inputs are accumulated in FP32
+    assert abs(info["nu"] - ref["nu"]) <= (1e-10 if dt == "f64" else 1e-5) * ref["nu"]
+    assert rel(info["shat"][:k], ref["shat"]) < tol
+    # P^{-1} v and P v on probes (U itself is not unique)
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], tail)
+    v = W.gaussian((3, n * n), 11)
+    vd = dev(v, "f64" if dt == "f64" else "f32")
+    got = host(P.nys_apply(pc, vd, inverse=True))
+    want = np.stack([opc.pinv(host(vd)[c]) for c in range(3)])
+    assert rel(got, want) < tol * 10
+    got_p = host(P.nys_apply(pc, vd, inverse=False))
+    want_p = np.stack([opc.p(host(vd)[c]) for c in range(3)])
+    assert rel(got_p, want_p) < tol * 10
+    # U U^T on probes
+    U = host(pc.U()).reshape(ell, -1)
+    proj = (host(vd) @ U.T) @ U
+    proj_ref = (host(vd) @ ref["U"].T) @ ref["U"]
+    assert rel(proj, proj_ref) < tol * 10
+    # orthonormal columns
+    assert np.allclose(U @ U.T, np.eye(ell), atol=(1e-10 if dt == "f64" else 2e-5))
+
+
+def test_factor_exact_recovery_low_rank():
+    """Phi = G G^T of rank 5 < ell = 8: U S U^T reproduces Phi."""
+    P = need_gpu()
+    banner("factor exact low rank")
+    N, ell, r = 300, 8, 5
+    G = W.gaussian((N, r), 12)
+    Phi = G @ G.T
+    om = W.omega(ell, 1, N, 13).reshape(ell, N)
+    Y = om @ Phi
+    pc = P.nys_factor(dev(om), dev(Y), ell, u_dtype=torch.float64)
+    info = pc.info()
+    U = host(pc.U()).reshape(ell, N)
+    k = info["k_eff"]
+    approx = U[:r].T @ np.diag(info["shat"][:r]) @ U[:r]
+    assert np.linalg.norm(approx - Phi) < 1e-9 * np.linalg.norm(Phi)
+    assert np.allclose(info["shat"][:r], np.sort(np.linalg.eigvalsh(Phi))[::-1][:r], rtol=1e-9)
+    assert k >= r
+
+
+def test_factor_not_pd_is_reported():
+    P = need_gpu()
+    banner("factor not PD")
+    N, ell = 64, 4
+    om = W.omega(ell, 1, N, 14).reshape(ell, N)
+    Y = -om * 3.0                         # Phi = -3 I: indefinite Gram
+    pc = P.nys_factor(dev(om), dev(Y), ell, max_escalations=2, u_dtype=torch.float64)
+    assert pc.info()["status"] == 3       # NYS_ENOTPD
+
+
+@pytest.mark.parametrize("reg,dt,with_pc", [("tv", "f64", True), ("tv", "f64", False),
+                                            ("hs1", "f64", True), ("tv_aniso", "f32", True),
+                                            ("hs1", "f32", False)])
+def test_prox_dual(reg, dt, with_pc):
+    P = need_gpu()
+    banner(f"prox dual {reg} {dt} pc={with_pc}")
+    n1 = n2 = 37
+    prob, om, Y = _blur_case(n1, 6)
+    s = W.gaussian((n1, n2), 15)
+    lam_bar = 0.05
+    sd = dev(s, dt)
+    if with_pc:
+        omd, Yd = dev(om, "f64"), dev(Y, "f64")
+        ref = onys.nystrom(host(Yd).reshape(6, -1), host(omd).reshape(6, -1))
+        opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+        udt = torch.float64 if dt == "f64" else torch.float32
+        pc = P.nys_factor(omd, Yd, 6, u_dtype=udt)
+        pinv, pnorm = opc.pinv, opc.pinv_norm
+    else:
+        pc, pinv, pnorm = None, (lambda v: v), 1.0
+    rd = P.reg_desc(reg, n1, n2, n_inner=25)
+    state = P.prox_state(rd, pc, sd.dtype)
+    x = P.prox_weighted(rd, lam_bar, pc, sd, state)
+    xr, Q = opx.prox_mixed_dual(host(sd), lam_bar, reg, pinv, pnorm, 25)
+    assert rel(host(x), xr) < TOL[dt] * 10
+    # warm start: a second call continues from the stored Q
+    x2 = P.prox_weighted(rd, lam_bar, pc, sd, state)
+    xr2, _ = opx.prox_mixed_dual(host(sd), lam_bar, reg, pinv, pnorm, 25, q0=Q)
+    assert rel(host(x2), xr2) < TOL[dt] * 10
+
+
+@pytest.mark.parametrize("dt,tail", [("f64", "sqrt"), ("f64", "plain"), ("f32", "sqrt")])
+def test_prox_l1_ssn(dt, tail):
+    P = need_gpu()
+    banner(f"prox l1 ssn {dt} {tail}")
+    n = 48
+    h = W.gaussian_psf(7, 1.2)
+    prob = sv.Problem("blurdown", n, None, 0.0, "l1", h=h, factor=2, levels=3)
+    ell = 8
+    om = W.omega(ell, n, n, 16)
+    Y = sv.sketch(prob, om)
+    omd, Yd = dev(om, "f64"), dev(Y, "f64")
+    ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], tail)
+    udt = torch.float64 if dt == "f64" else torch.float32
+    pc = P.nys_factor(omd, Yd, ell, tail=tail, u_dtype=udt)
+    s = W.gaussian((n, n), 17) * 0.1
+    sd = dev(s, dt)
+    lam_bar = 0.05
+    rd = P.reg_desc("l1", n, n)
+    state = P.prox_state(rd, pc, sd.dtype)
+    x = P.prox_weighted(rd, lam_bar, pc, sd, state)
+    xr, g, _ = opx.prox_l1_weighted(host(sd).reshape(-1), lam_bar, opc.U, opc.e)
+    assert rel(host(x).reshape(-1), xr) < (1e-9 if dt == "f64" else 2e-5)
+    # plain: soft threshold
+    x0 = P.prox_weighted(rd, lam_bar, None, sd)
+    assert rel(host(x0), opx.soft(host(sd), lam_bar)) < TOL[dt]
+
+
+def _solve_pair(P, prob_kind, dt, with_pc, iters):
+    if prob_kind == "deblur_tv":
+        wl = W.workload("deblur128_tv_f64")
+        prob, _ = sv.problem_from_workload(wl, seed=2, n=40)
+        op = P.Operator(P.OP_BLUR, 40, 40, psf=prob.h)
+        reg, lam, loss, delta, ell = "tv", prob.lam, P.LOSS_LS, 0.0, 8
+    elif prob_kind == "sr_l1":
+        wl = W.workload("sr512_haar_bf16")
+        prob, _ = sv.problem_from_workload(wl, seed=3, n=64)
+        op = P.Operator(P.OP_BLURDOWN, 64, 64, psf=prob.h, factor=2, wavelet_levels=3)
+        reg, lam, loss, delta, ell = "l1", prob.lam, P.LOSS_HUBER, prob.delta, 8
+    else:
+        wl = W.workload("ct512_hs1_f32")
+        prob, _ = sv.problem_from_workload(wl, seed=4, n=32, views=36, bins=48)
+        op = P.Operator(P.OP_PARALLEL_BEAM, 32, 32, views=36, bins=48)
+        reg, lam, loss, delta, ell = "hs1", prob.lam, P.LOSS_LS, 0.0, 10
+    n = prob.n
+    yd = dev(prob.y, dt)
+    prob.y = host(yd)
+    pc = opc = None
+    if with_pc:
+        om = W.omega(ell, n, n, 20)
+        omd = dev(om, dt)
+        Yref = sv.sketch(prob, host(omd))
+        Yd = dev(Yref, dt)
+        ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+        opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+        pc = P.nys_factor(omd, Yd, ell, u_dtype=torch.float64 if dt == "f64" else torch.float32)
+    alpha = 0.9 / sv.lipschitz(prob, opc, W.gaussian((n, n), 21), 200)
+    rd = P.reg_desc(reg, n, n, n_inner=10)
+    x, costs, info = P.solve(op, yd, rd, lam, pc, iters, alpha=alpha, loss=loss, delta=delta)
+    xr, cr = sv.wapg(prob, opc, alpha, iters, inner=10)
+    return host(x), host(costs), xr, cr
+
+
+@pytest.mark.parametrize("kind,dt,with_pc", [("deblur_tv", "f64", False), ("deblur_tv", "f64", True),
+                                             ("sr_l1", "f32", False), ("sr_l1", "f32", True),
+                                             ("ct_hs1", "f32", True)])
+def test_solve_matches_oracle(kind, dt, with_pc):
+    P = need_gpu()
+    banner(f"solve {kind} {dt} pc={with_pc}")
+    iters = 15
+    x, c, xr, cr = _solve_pair(P, kind, dt, with_pc, iters)
+    tol = 1e-9 if dt == "f64" else 1e-4
+    assert rel(x, xr) < tol
+    assert np.max(np.abs(c - cr) / np.abs(cr)) < tol
+
+
+def test_solve_power_method_step():
+    P = need_gpu()
+    banner("solve power method")
+    n = 32
+    h = W.gaussian_psf(9, 1.5)
+    op = P.Operator(P.OP_BLUR, n, n, psf=h)
+    y = dev(W.gaussian((n, n), 22))
+    v0 = dev(W.gaussian((n, n), 23))
+    rd = P.reg_desc("tv", n, n, n_inner=5)
+    _, _, info = P.solve(op, y, rd, 1e-3, None, 1, power_v0=v0, power_iters=300)
+    # normalised PSF: lambda_max(A^T A) = 1 (DC), approached from below
+    assert 0.99 < info["L"] <= 1.0 + 1e-12
+    prob = sv.Problem("blur", n, host(y), 1e-3, "tv", h=h)
+    Lr = sv.lipschitz(prob, None, host(v0), 300)
+    assert abs(info["L"] - Lr) < 1e-10

@@ -1,0 +1,151 @@
+"""GPU parity of the operators and of the sketch against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import operators as ops
+from oracle import solver as sv
+from gpu_util import TOL, banner, dev, host, need_gpu, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n1,n2,k,sigma", [(100, 72, 9, 1.5), (128, 128, 9, 1.5),
+                                           (33, 47, 15, 3.0), (16, 16, 5, 0.8)])
+def test_blur_forward_adjoint(dt, n1, n2, k, sigma):
+    P = need_gpu()
+    banner(f"blur {dt} {n1}x{n2} k={k}")
+    h = W.gaussian_psf(k, sigma)
+    h[0, 1] += 0.01            # break the symmetry so H != H^T is exercised
+    op = P.Operator(P.OP_BLUR, n1, n2, psf=h)
+    x = W.gaussian((3, n1, n2), 1)
+    xd = dev(x, dt)
+    xr = host(xd)
+    y = P.op_forward(op, xd)
+    assert rel(host(y), ops.blur(xr, h)) < TOL[dt]
+    z = P.op_adjoint(op, y)
+    assert rel(host(z), ops.blur_adjoint(host(y), h)) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n,k,levels", [(512, 7, 0), (96, 7, 3), (40, 5, 0), (64, 9, 3)])
+def test_blurdown_and_haar(dt, n, k, levels):
+    P = need_gpu()
+    banner(f"blurdown {dt} n={n} k={k} levels={levels}")
+    h = W.gaussian_psf(k, 1.2)
+    op = P.Operator(P.OP_BLURDOWN, n, n, psf=h, factor=2, wavelet_levels=levels)
+    x = W.gaussian((2, n, n), 2)
+    xd = dev(x, dt)
+    xr = host(xd)
+    ref = ops.blurdown(ops.haar_synthesis(xr, levels) if levels else xr, h, 2)
+    y = P.op_forward(op, xd)
+    assert y.shape == (2, n // 2, n // 2)
+    assert rel(host(y), ref) < TOL[dt]
+    yr = host(y)
+    ref_t = ops.blurdown_adjoint(yr, h, 2)
+    if levels:
+        ref_t = ops.haar_analysis(ref_t, levels)
+    assert rel(host(P.op_adjoint(op, y)), ref_t) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_haar_identity_operator(dt):
+    P = need_gpu()
+    banner(f"haar identity {dt}")
+    n = 48
+    op = P.Operator(P.OP_IDENTITY, n, n, wavelet_levels=3)
+    w = W.gaussian((2, n, n), 3)
+    wd = dev(w, dt)
+    assert rel(host(P.op_forward(op, wd)), ops.haar_synthesis(host(wd), 3)) < TOL[dt]
+    assert rel(host(P.op_adjoint(op, wd)), ops.haar_analysis(host(wd), 3)) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n,V,B", [(32, 24, 45), (64, 90, 92), (47, 13, 70)])
+def test_joseph_pair(dt, n, V, B):
+    P = need_gpu()
+    banner(f"joseph {dt} n={n} V={V} B={B}")
+    op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=V, bins=B)
+    x = W.gaussian((2, n, n), 4)
+    xd = dev(x, dt)
+    p = P.op_forward(op, xd)
+    assert p.shape == (2, V, B)
+    assert rel(host(p), ops.joseph(host(xd), V, B)) < TOL[dt]
+    q = dev(W.gaussian((2, V, B), 5), dt)
+    assert rel(host(P.op_adjoint(op, q)), ops.joseph_adjoint(host(q), n)) < TOL[dt]
+    # adjoint identity inside the GPU arithmetic
+    lhs = float((p.double() * q.double()).sum())
+    rhs = float((xd.double() * P.op_adjoint(op, q).double()).sum())
+    assert abs(lhs - rhs) <= 10 * TOL[dt] * abs(lhs)
+
+
+@pytest.mark.parametrize("dt,n,ell", [("f64", 128, 32), ("f64", 40, 7), ("f32", 100, 5)])
+def test_sketch_blur(dt, n, ell):
+    P = need_gpu()
+    banner(f"sketch blur {dt} n={n} ell={ell}")
+    h = W.gaussian_psf(9, 1.5)
+    op = P.Operator(P.OP_BLUR, n, n, psf=h)
+    om = dev(W.omega(ell, n, n, 6), dt)
+    Y = P.nys_sketch(op, om)
+    prob = sv.Problem("blur", n, None, 0.0, "tv", h=h)
+    assert rel(host(Y), sv.sketch(prob, host(om))) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt,n,ell", [("bf16", 128, 5), ("f32", 128, 3), ("bf16", 96, 4),
+                                      ("f32", 72, 2)])
+def test_sketch_super_resolution(dt, n, ell):
+    """Fused path for n divisible by 64, unfused chain otherwise."""
+    P = need_gpu()
+    banner(f"sketch SR {dt} n={n} ell={ell}")
+    h = W.gaussian_psf(7, 1.2)
+    op = P.Operator(P.OP_BLURDOWN, n, n, psf=h, factor=2, wavelet_levels=3)
+    om = dev(W.omega(ell, n, n, 7), dt)
+    Y = P.nys_sketch(op, om)
+    prob = sv.Problem("blurdown", n, None, 0.0, "l1", h=h, factor=2, levels=3)
+    ref = sv.sketch(prob, host(om))
+    got = host(Y)
+    assert rel(got, ref) < TOL[dt]
+    # element-wise: within one bf16 ulp (2^-8 relative) plus FP32 accumulation
+    if dt == "bf16":
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+def test_sketch_ct_f32():
+    P = need_gpu()
+    banner("sketch CT f32")
+    n, V, B, ell = 48, 30, 70, 3
+    op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=V, bins=B)
+    om = dev(W.omega(ell, n, n, 8), "f32")
+    Y = P.nys_sketch(op, om)
+    ref = ops.joseph_adjoint(ops.joseph(host(om), V, B), n)
+    assert rel(host(Y), ref) < TOL["f32"]
+
+
+def test_sketch_sr_full_size_sampled_columns():
+    """512^2 super-resolution workload, ell = 64, BF16: the timed launch
+    configuration; the oracle checks 3 sampled columns."""
+    P = need_gpu()
+    banner("sketch SR full size 512^2 ell=64 bf16")
+    wl = W.workload("sr512_haar_bf16")
+    n, ell = wl.n, wl.ell
+    h = W.gaussian_psf(wl.psf_k, wl.psf_sigma)
+    op = P.Operator(P.OP_BLURDOWN, n, n, psf=h, factor=2, wavelet_levels=3)
+    om = dev(W.omega(ell, n, n, 0), "bf16")
+    Y = P.nys_sketch(op, om)
+    prob = sv.Problem("blurdown", n, None, 0.0, "l1", h=h, factor=2, levels=3)
+    omh = host(om)
+    for k in (0, 31, 63):
+        ref = prob.phi(omh[k])
+        got = host(Y[k])
+        assert rel(got, ref) < TOL["bf16"]
+
+
+def test_operator_argument_errors():
+    P = need_gpu()
+    with pytest.raises(P.NysError):
+        P.Operator(P.OP_BLUR, 16, 16, psf=np.ones((4, 4)) / 16)       # even PSF
+    with pytest.raises(P.NysError):
+        P.Operator(P.OP_BLURDOWN, 15, 16, psf=np.ones((3, 3)) / 9, factor=2)
+    with pytest.raises(P.NysError):
+        P.Operator(P.OP_PARALLEL_BEAM, 16, 12, views=4, bins=5)
