@@ -1,0 +1,303 @@
+"""Time to a 1e-4 relative cost gap: Nystrom-preconditioned WAPG vs plain APG.
+
+One "step" is one whole preconditioned reconstruction on the GPU: the sketch
+Y = A^T A Omega (Alg. 1 step 2), the shifted Nystrom factorisation (Alg. 1
+steps 3-8), the step size by the power method, and WAPG (Alg. 3) run for the
+number of outer iterations that reaches a relative cost gap of 1e-4.  Plain
+APG (P = I, with its own power method) is timed the same way beside it.
+
+Inputs are synthetic and seeded (module `workloads`), already resident in
+HBM when the timed region starts.  F* is the smallest cost seen over long
+untimed runs of both methods; the iteration counts that reach the gap are
+found by untimed runs that record the cost, then the timed runs repeat the
+solve with exactly that many iterations and no cost recording.
+
+Prints one JSON line.  Usage:
+    python bench.py [--steps K] [--warmup W] [--workload sr512|ct512|deblur128]
+                    [--no-cpu-baseline] [--copy-calibration]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+GAP = 1e-4
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD_KEYS = {
+    "sr512": "sr512_haar_bf16",
+    "ct512": "ct512_hs1_f32",
+    "deblur128": "deblur128_tv_f64",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- inputs
+class Setup:
+    """Operator, measurements and Omega of one workload, on the GPU."""
+
+    def __init__(self, P, torch, wl, seed=0):
+        self.wl = wl
+        n = wl.n
+        self.torch = torch
+        tdt = {"f64": torch.float64, "f32": torch.float32}[wl.dtype]
+        sdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[wl.sketch_dtype]
+        self.tdt, self.sdt = tdt, sdt
+        if wl.op == "ct":
+            self.op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=wl.views, bins=wl.bins)
+            xt = W.phantom_ellipses(n, seed)
+            clean = P.op_forward(self.op, torch.from_numpy(xt).to(tdt).cuda())
+            cmax = float(clean.abs().max())
+            noise = W.gaussian(tuple(clean.shape), seed)
+            y = clean + wl.noise_rel_max * cmax * torch.from_numpy(noise).to(tdt).cuda()
+            self.reg, self.loss, self.delta = wl.reg, P.LOSS_LS, 0.0
+        else:
+            h = W.gaussian_psf(wl.psf_k, wl.psf_sigma)
+            xt = W.phantom_blocks(n, seed)
+            kind = P.OP_BLUR if wl.op == "blur" else P.OP_BLURDOWN
+            plain = P.Operator(kind, n, n, psf=h, factor=wl.factor)
+            clean = P.op_forward(plain, torch.from_numpy(xt).to(tdt).cuda())
+            noise = W.gaussian(tuple(clean.shape), seed)
+            y = clean + wl.noise_sigma * torch.from_numpy(noise).to(tdt).cuda()
+            if wl.salt_pepper:
+                salt, pepper = W.salt_pepper_masks(tuple(clean.shape), seed, wl.salt_pepper)
+                y[torch.from_numpy(salt).cuda()] = 1.0
+                y[torch.from_numpy(pepper).cuda()] = 0.0
+            levels = 3 if wl.reg == "l1haar3" else 0
+            self.op = P.Operator(kind, n, n, psf=h, factor=wl.factor, wavelet_levels=levels)
+            self.reg = "l1" if levels else wl.reg
+            huber = wl.loss == "huber"
+            self.loss = P.LOSS_HUBER if huber else P.LOSS_LS
+            self.delta = wl.huber_delta if huber else 0.0
+        self.y = y.contiguous()
+        self.omega = torch.from_numpy(W.round_dtype(W.omega(wl.ell, n, n, seed), wl.sketch_dtype)) \
+            .to(sdt).cuda().contiguous()
+        self.v0 = torch.from_numpy(W.gaussian((n, n), seed, stream=7)).to(tdt).cuda().contiguous()
+        self.rd = P.reg_desc(self.reg, n, n, n_inner=wl.inner)
+        self.Y = torch.empty_like(self.omega)
+
+
+def run_pc(P, S, iters, power_iters, record_cost, ev=None):
+    """Sketch + factor + power method + WAPG for `iters` outer iterations."""
+    if ev is not None:
+        ev[0].record()
+    P.nys_sketch(S.op, S.omega, out=S.Y)
+    if ev is not None:
+        ev[1].record()
+    pc = P.nys_factor(S.omega, S.Y, S.wl.ell, u_dtype=S.tdt)
+    x, costs, info = P.solve(S.op, S.y, S.rd, S.wl.lam, pc, iters, power_v0=S.v0,
+                             power_iters=power_iters, loss=S.loss, delta=S.delta,
+                             record_cost=record_cost)
+    return x, costs, info, pc
+
+
+def run_plain(P, S, iters, power_iters, record_cost):
+    x, costs, info = P.solve(S.op, S.y, S.rd, S.wl.lam, None, iters, power_v0=S.v0,
+                             power_iters=power_iters, loss=S.loss, delta=S.delta,
+                             record_cost=record_cost)
+    return x, costs, info
+
+
+def first_below(costs, fstar, gap):
+    g = (costs - fstar) / abs(fstar)
+    idx = np.nonzero(g <= gap)[0]
+    return int(idx[0]) + 1 if len(idx) else None
+
+
+# ---------------------------------------------------------------- CPU leg
+def cpu_baseline(wl, k_pc, power_iters, alpha, seed=0):
+    """The FP64 oracle timed on a bounded sample of the same workload and
+    extrapolated to one preconditioned time-to-gap (seconds)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import nystrom as onys
+    from oracle import solver as sv
+    prob, _ = sv.problem_from_workload(wl, seed=seed)
+    n, ell = wl.n, wl.ell
+    om = W.round_dtype(W.omega(ell, n, n, seed), wl.sketch_dtype)
+    # sketch: a few columns, scaled to ell
+    ncols = 2 if wl.op == "ct" else 8
+    t0 = time.perf_counter()
+    for k in range(ncols):
+        prob.phi(om[k])
+    t_col = (time.perf_counter() - t0) / ncols
+    # factorisation on all ell columns: its cost does not depend on the
+    # values, so the sketch of a positive diagonal operator of the same shape
+    # stands in for the columns not computed above
+    d = 0.01 + 0.24 * np.abs(W.gaussian((n * n,), seed, stream=8))
+    Yfull = d[None, :] * om.reshape(ell, -1)
+    t0 = time.perf_counter()
+    r = onys.nystrom(Yfull, om.reshape(ell, -1))
+    t_factor = time.perf_counter() - t0
+    pc = sv.Precond(r["U"], r["shat"], r["nu"], "sqrt")
+    # power method: a few steps, scaled
+    v = W.gaussian((n, n), seed, stream=7)
+    pi = 5
+    t0 = time.perf_counter()
+    sv.lipschitz(prob, pc, v, pi)
+    t_pow = (time.perf_counter() - t0) / pi
+    # WAPG: a few outer iterations, scaled
+    it = 6
+    t0 = time.perf_counter()
+    sv.wapg(prob, pc, alpha, it, inner=wl.inner, record_cost=False)
+    t_it = (time.perf_counter() - t0) / it
+    total = t_col * ell + t_factor + t_pow * power_iters + t_it * k_pc
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    sample = (f"oracle on {ncols} sketch columns (x{ell}), full Alg. 1 factor, "
+              f"{pi} power steps (x{power_iters}), {it} WAPG iterations (x{k_pc}); "
+              f"numpy/scipy FP64, BLAS threads {threads}")
+    return dict(value=total, unit="s", cores=threads, kind="oracle", sample=sample,
+                parts=dict(sketch_per_col_s=t_col, factor_s=t_factor, power_step_s=t_pow,
+                           wapg_iter_s=t_it))
+
+
+# ---------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sr512", choices=sorted(WORKLOAD_KEYS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--power-iters", type=int, default=100)
+    ap.add_argument("--ref-iters", type=int, default=0,
+                    help="iterations of the untimed F* runs (0: 20x the workload's outer count)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2411_08178_amd as P
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    P.lib()
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "launches": 3}))
+        return
+
+    wl = W.workload(WORKLOAD_KEYS[args.workload])
+    log(f"workload {wl.name}: n={wl.n} ell={wl.ell} sketch={wl.sketch_dtype} solver={wl.dtype}")
+    S = Setup(P, torch, wl, args.seed)
+    torch.cuda.synchronize()
+
+    # ---- F* and iteration counts (untimed)
+    ref_iters = args.ref_iters or 20 * wl.outer
+    t0 = time.perf_counter()
+    _, c_pc, info_pc, pc_ref = run_pc(P, S, ref_iters, args.power_iters, True)
+    _, c_pl, info_pl = run_plain(P, S, ref_iters, args.power_iters, True)
+    torch.cuda.synchronize()
+    c_pc, c_pl = c_pc.cpu().numpy(), c_pl.cpu().numpy()
+    fstar = float(min(c_pc.min(), c_pl.min()))
+    k_pc = first_below(c_pc, fstar, GAP)
+    k_pl = first_below(c_pl, fstar, GAP)
+    pcinfo = pc_ref.info()
+    log(f"reference runs {ref_iters} its in {time.perf_counter() - t0:.1f}s; F*={fstar:.10g} "
+        f"(pc end {c_pc[-1]:.10g}, plain end {c_pl[-1]:.10g}); k_pc={k_pc} k_plain={k_pl}; "
+        f"L_pc={info_pc['L']:.6g} L_plain={info_pl['L']:.6g}; nu={pcinfo['nu']:.3e} "
+        f"shat[0]={pcinfo['shat'][0]:.6g} shat[-1]={pcinfo['shat'][pcinfo['k_eff'] - 1]:.6g}")
+    del pc_ref
+    fstar_resolved = abs(c_pc.min() - c_pl.min()) <= 1e-6 * abs(fstar)
+    kp = k_pc if k_pc is not None else ref_iters
+    kq = k_pl if k_pl is not None else ref_iters
+
+    # ---- timed: preconditioned
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        run_pc(P, S, kp, args.power_iters, False)
+    torch.cuda.synchronize()
+    sk_ms = []
+    pcs = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for s in range(args.steps):
+        _, _, _, pc = run_pc(P, S, kp, args.power_iters, False, ev=ev[2 * s:2 * s + 2])
+        pcs.append(pc)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_pc = t_start.elapsed_time(t_end) / args.steps
+    sk_ms = [ev[2 * s].elapsed_time(ev[2 * s + 1]) for s in range(args.steps)]
+    del pcs
+
+    # ---- timed: plain APG
+    for _ in range(args.warmup):
+        run_plain(P, S, kq, args.power_iters, False)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for s in range(args.steps):
+        run_plain(P, S, kq, args.power_iters, False)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_pl = t_start.elapsed_time(t_end) / args.steps
+    log(f"preconditioned {ms_pc:.3f} ms ({kp} its), plain {ms_pl:.3f} ms ({kq} its)")
+
+    # ---- roofline of the sketch kernel (algorithmic bytes: Omega in, Y out)
+    esz = S.omega.element_size()
+    sk_bytes = 2 * wl.ell * S.op.N * esz
+    sk_avg_ms = float(np.mean(sk_ms))
+    achieved = sk_bytes / (sk_avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "sketch (A^T A Omega)", "bytes_per_launch": sk_bytes,
+            "avg_launch_us": round(sk_avg_ms * 1e3, 2)}
+
+    out = {
+        "metric": "time to 1e-4 rel. cost gap, Nystrom-precond WAPG (sketch+factor+step+solve)",
+        "value": round(ms_pc / 1e3, 6),
+        "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_pc, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "ell": wl.ell, "sketch_dtype": wl.sketch_dtype,
+                   "solver_dtype": wl.dtype, "factor_dtype": "f64", "reg": wl.reg,
+                   "loss": wl.loss, "lambda": wl.lam, "power_iters": args.power_iters,
+                   "seed": args.seed},
+        "plain_apg_s": round(ms_pl / 1e3, 6),
+        "speedup_vs_plain": round(ms_pl / ms_pc, 4),
+        "iters_to_gap": {"precond": k_pc, "plain": k_pl, "reference_iters": ref_iters},
+        "fstar": fstar, "fstar_resolved": bool(fstar_resolved),
+        "L": {"precond": info_pc["L"], "plain": info_pl["L"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(wl, kp, args.power_iters, info_pc["alpha"], args.seed)
+        log(f"cpu baseline leg took {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
