@@ -141,6 +141,14 @@ void nys_pc_destroy(nys_pc pc);
  * (nys_status of the device-side factorisation).  Any pointer may be NULL. */
 nys_status nys_pc_info(nys_pc pc, double* shat, double* nu, int32_t* k_eff,
                        int32_t* status, void* stream);
+/* Diagnostics of the factorisation (host out, synchronises `stream`): up to
+ * n (<= 16) doubles: [0] nu used, [1] s_K value used in P, [2] mu,
+ * [3] ||P^{-1}||_2, [4] retained columns, [5] status word, [6] shift
+ * escalations, [7] Jacobi sweeps of the shift estimate, [8] Jacobi sweeps of
+ * the ell x ell eigenproblem, [9..15] device timestamps of the factor kernel's
+ * phases (100 MHz wall clock). */
+nys_status nys_pc_diag(nys_pc pc, double* out, int32_t n, void* stream);
+
 /* Device pointer to U (ell*N, u_dtype) and its sizes. */
 nys_status nys_pc_u(nys_pc pc, const void** u, int64_t* N, int64_t* ell,
                     int32_t* u_dtype);

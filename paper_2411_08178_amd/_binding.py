@@ -77,6 +77,7 @@ def lib():
             "nys_factor": [vp, vp, i32, i64, i64, C.POINTER(FactorOpts), C.POINTER(vp), vp],
             "nys_pc_info": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32), C.POINTER(i32), vp],
             "nys_pc_u": [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)],
+            "nys_pc_diag": [vp, C.POINTER(dbl), i32, vp],
             "nys_pc_copy_u": [vp, vp, vp],
             "nys_apply": [vp, i32, i32, vp, vp, i64, vp],
             "prox_weighted": [C.POINTER(RegDesc), dbl, vp, i32, vp, vp, vp, vp],
@@ -213,6 +214,14 @@ class Preconditioner:
         _check(lib().nys_pc_info(self.handle, shat, C.byref(nu), C.byref(keff), C.byref(st),
                                  _stream()))
         return dict(shat=np.array(shat[:]), nu=nu.value, k_eff=keff.value, status=st.value)
+
+    def diag(self):
+        out = (C.c_double * 16)()
+        _check(lib().nys_pc_diag(self.handle, out, 16, _stream()))
+        v = list(out)
+        return dict(nu=v[0], s_tail=v[1], mu=v[2], pinv_norm=v[3], k_eff=int(v[4]),
+                    status=int(v[5]), escalations=int(v[6]), sweeps_shift=int(v[7]),
+                    sweeps_eig=int(v[8]), stamps=v[9:16])
 
     def U(self) -> torch.Tensor:
         out = torch.empty((self.ell, self.N), dtype=self.u_dtype, device="cuda")

@@ -128,6 +128,9 @@ struct nys_op_s {
   nys_op_desc d{};
   int64_t N = 0, M = 0;
   std::vector<double> psf;        // k*k row-major
+  // psf[a][b] = sep_u[a] * sep_v[b] when sep != 0 (rank-1 PSF, e.g. Gaussian)
+  int sep = 0;
+  double sep_u[32] = {}, sep_v[32] = {};
   nys::DevBuf psf_dev;            // [flipped psf f64 | psf f64 | flipped f32 | psf f32]
   nys::DevBuf trig;               // per view: cos, sin (f64) then (f32)
   nys::DevBuf tmp0, tmp1;         // intermediates of composed operators

@@ -2,7 +2,9 @@
 // eq. (6): Gram of [Omega Y], ell x ell FP64 algebra on one workgroup,
 // U = Y_nu R in one pass, and P^{-1} / P applications.
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -97,117 +99,331 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks,
   }
 }
 
-// ================================================================ FP64 factor
-// One workgroup.  G is the 2 ell x 2 ell Gram: OO = G[0:l, 0:l],
-// OY = G[0:l, l:2l], YY = G[l:2l, l:2l].  Work buffers are l x l FP64 each.
-struct FactorWork {
-  double *Gs, *Cc, *Mv, *X, *M, *V, *R, *ev;
+// ---------------------------------------------------------------- MFMA Gram
+// BF16 / FP32 columns: G = Z Z^T with Z = [Omega; Y] (2 ell rows of N), on
+// the matrix cores.  Rows are split in groups of 32; the upper-triangular
+// 32 x 32 tiles are spread over the 4 waves of a block, and each block sums
+// one chunk of N.  The reduction index n is handed to the lanes in runs of 8
+// consecutive pixels (lane l takes n0 + 8 (l / 32) + i), the same for both
+// operands, so every product pairs equal n.  Output tile layout of the
+// 32 x 32 MFMA: register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4,
+// column l % 32.  Partials are FP32 per block; gram_mfma_reduce sums them in
+// FP64 in a fixed order.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+
+template <int NRG>
+struct GramTiles {
+  static constexpr int NTRI = NRG * (NRG + 1) / 2;
+  static constexpr int TPW = (NTRI + 3) / 4;
+  // tile index -> (ti, tj), ti <= tj, row-major over the upper triangle
+  static __device__ __forceinline__ void ij(int t, int& ti, int& tj) {
+    ti = 0;
+    while (t >= NRG - ti) { t -= NRG - ti; ++ti; }
+    tj = ti + t;
+  }
 };
 
-__device__ void block_jacobi_eig(double* M, double* V, int L, double* ev, int max_sweeps) {
-  // cyclic Jacobi with round-robin (tournament) ordering: each round rotates
-  // m/2 disjoint index pairs in parallel.
+// One 16-byte chunk (8 bf16 / 4 float) of row `a` of Z starting at element n,
+// zero past N or past row 2 ell.  N is a multiple of the chunk length here.
+template <class S>
+__device__ __forceinline__ uint4 gram_chunk(const S* __restrict__ omega, const S* __restrict__ Y,
+                                            int64_t N, int ell, int a, int64_t n) {
+  if (a >= 2 * ell || n >= N) return make_uint4(0, 0, 0, 0);
+  const S* row = a < ell ? omega + static_cast<size_t>(a) * N : Y + static_cast<size_t>(a - ell) * N;
+  return *reinterpret_cast<const uint4*>(row + n);
+}
+
+// Stage = 128 bytes of every row of Z (64 bf16 or 32 float pixels), staged
+// through LDS so that global loads are 128-byte runs of one row (8 lanes per
+// row) instead of 32 rows per instruction; the row pitch is padded by 16 B.
+template <class S, int NRG>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const S* __restrict__ omega,
+                                                        const S* __restrict__ Y, int64_t N,
+                                                        int ell, int64_t chunk,
+                                                        float* __restrict__ part) {
+  using Tl = GramTiles<NRG>;
+  constexpr int ROWS = 32 * NRG;
+  constexpr int EPC = 16 / sizeof(S);      // elements per 16-byte chunk
+  constexpr int KT = 8 * EPC;              // pixels per stage
+  constexpr int PITCH = 144;               // bytes per LDS row
+  __shared__ __align__(16) unsigned char lds[ROWS * PITCH];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  const int lr = lane & 31, lh = lane >> 5;
+  // loader mapping: thread t handles chunk (row 32 g + t / 8, column t % 8)
+  const int ld_row = tid >> 3, ld_col = tid & 7;
+  floatx16_t acc[Tl::TPW];
+#pragma unroll
+  for (int t = 0; t < Tl::TPW; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+  uint4 pre[NRG];
+#pragma unroll
+  for (int g = 0; g < NRG; ++g)
+    pre[g] = gram_chunk<S>(omega, Y, N, ell, 32 * g + ld_row, n0 + ld_col * EPC);
+  for (int64_t n = n0; n < n1; n += KT) {
+#pragma unroll
+    for (int g = 0; g < NRG; ++g)
+      *reinterpret_cast<uint4*>(lds + (32 * g + ld_row) * PITCH + ld_col * 16) = pre[g];
+    __syncthreads();
+    if (n + KT < n1) {
+#pragma unroll
+      for (int g = 0; g < NRG; ++g)
+        pre[g] = gram_chunk<S>(omega, Y, N, ell, 32 * g + ld_row, n + KT + ld_col * EPC);
+    }
+    if constexpr (sizeof(S) == 2) {
+      // 4 MFMA steps of 16 pixels; lane l supplies pixels 16 kk + 8 (l / 32) + 0..7
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        bf16x8_t fr[NRG];
+#pragma unroll
+        for (int g = 0; g < NRG; ++g) {
+          uint4 u = *reinterpret_cast<const uint4*>(lds + (32 * g + lr) * PITCH + 32 * kk + 16 * lh);
+          __builtin_memcpy(&fr[g], &u, 16);
+        }
+        int tile = 0;
+#pragma unroll
+        for (int ti = 0; ti < NRG; ++ti)
+#pragma unroll
+          for (int tj = ti; tj < NRG; ++tj, ++tile)
+            if ((tile & 3) == wave)
+              acc[tile >> 2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fr[ti], fr[tj], acc[tile >> 2], 0, 0, 0);
+      }
+    } else {
+      // 2 sub-steps of 16 pixels; lane l holds pixels 16 sb + 8 (l / 32) + 0..7
+      // and feeds element i to the i-th 32x32x2 MFMA
+#pragma unroll
+      for (int sb = 0; sb < 2; ++sb) {
+        float fr[NRG][8];
+#pragma unroll
+        for (int g = 0; g < NRG; ++g) {
+          const unsigned char* src = lds + (32 * g + lr) * PITCH + 64 * sb + 32 * lh;
+          float4 u = *reinterpret_cast<const float4*>(src);
+          float4 v = *reinterpret_cast<const float4*>(src + 16);
+          fr[g][0] = u.x; fr[g][1] = u.y; fr[g][2] = u.z; fr[g][3] = u.w;
+          fr[g][4] = v.x; fr[g][5] = v.y; fr[g][6] = v.z; fr[g][7] = v.w;
+        }
+        int tile = 0;
+#pragma unroll
+        for (int ti = 0; ti < NRG; ++ti)
+#pragma unroll
+          for (int tj = ti; tj < NRG; ++tj, ++tile)
+            if ((tile & 3) == wave) {
+#pragma unroll
+              for (int i = 0; i < 8; ++i)
+                acc[tile >> 2] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti][i], fr[tj][i], acc[tile >> 2], 0, 0, 0);
+            }
+      }
+    }
+    __syncthreads();
+  }
+  float* dst = part + static_cast<size_t>(blockIdx.x) * Tl::NTRI * 1024;
+#pragma unroll
+  for (int t = 0; t < Tl::TPW; ++t) {
+    const int tile = wave + 4 * t;
+    if (tile < Tl::NTRI) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r / 4) + 4 * lh + (r & 3);
+        dst[tile * 1024 + row * 32 + lr] = acc[t][r];
+      }
+    }
+  }
+}
+
+template <int NRG>
+__global__ __launch_bounds__(256) void gram_mfma_reduce(const float* __restrict__ part, int nblk,
+                                                        int ell, double* __restrict__ G) {
+  using Tl = GramTiles<NRG>;
+  const int m = 2 * ell;
+  const int total = Tl::NTRI * 1024;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int tile = e >> 10, r = e & 1023;
+    int ti, tj;
+    Tl::ij(tile, ti, tj);
+    const int gi = 32 * ti + (r >> 5), gj = 32 * tj + (r & 31);
+    if (gi >= m || gj >= m) continue;
+    double acc8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int b = 0;
+    for (; b + 8 <= nblk; b += 8)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        acc8[u] += static_cast<double>(part[static_cast<size_t>(b + u) * total + e]);
+    for (; b < nblk; ++b) acc8[0] += static_cast<double>(part[static_cast<size_t>(b) * total + e]);
+    const double sacc = ((acc8[0] + acc8[1]) + (acc8[2] + acc8[3])) +
+                        ((acc8[4] + acc8[5]) + (acc8[6] + acc8[7]));
+    G[gi * m + gj] = sacc;
+    G[gj * m + gi] = sacc;
+  }
+}
+
+template <class S, int NRG>
+static nys_status gram_mfma_launch(const S* omega, const S* Y, int64_t N, int ell, float* part,
+                                   int nblk, int64_t chunk, double* G, hipStream_t st) {
+  hipLaunchKernelGGL((gram_mfma_kernel<S, NRG>), dim3(nblk), dim3(256), 0, st, omega, Y, N, ell,
+                     chunk, part);
+  NYS_TRY(launch_check("gram_mfma_kernel"));
+  hipLaunchKernelGGL((gram_mfma_reduce<NRG>), dim3(cdiv(GramTiles<NRG>::NTRI * 1024, 256)),
+                     dim3(256), 0, st, part, nblk, ell, G);
+  return launch_check("gram_mfma_reduce");
+}
+
+template <class S>
+static nys_status gram_mfma(const S* omega, const S* Y, int64_t N, int ell, float* part, int nblk,
+                            int64_t chunk, double* G, hipStream_t st) {
+  switch ((2 * ell + 31) / 32) {
+    case 1: return gram_mfma_launch<S, 1>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    case 2: return gram_mfma_launch<S, 2>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    case 3: return gram_mfma_launch<S, 3>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    case 4: return gram_mfma_launch<S, 4>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    case 5: return gram_mfma_launch<S, 5>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    case 6: return gram_mfma_launch<S, 6>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    case 7: return gram_mfma_launch<S, 7>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    case 8: return gram_mfma_launch<S, 8>(omega, Y, N, ell, part, nblk, chunk, G, st);
+    default: break;
+  }
+  set_error("gram: ell out of range");
+  return NYS_EINVAL;
+}
+
+// ================================================================ FP64 factor
+// One workgroup of kFT threads.  The matrix being worked on (L x L FP64)
+// lives in LDS (dynamic shared memory); the eigenvector matrix V, the
+// Cholesky factor copy and the triangular-solve outputs live in the global
+// work buffer.  G is the 2L x 2L Gram: OO = G[0:L, 0:L], OY = G[0:L, L:2L],
+// YY = G[L:2L, L:2L].
+constexpr int kFT = 512;
+
+struct FactorWork {
+  double *Cg, *X, *Mg, *V, *R, *ev;
+};
+
+// Cyclic Jacobi for a symmetric L x L matrix M (full storage) with the
+// round-robin ordering: each round rotates L/2 disjoint index pairs, and
+// M <- J^T M J is applied as independent 2 x 2 block updates (one barrier per
+// round).  Accumulates V <- V J when V != nullptr.  On exit ev = diag(M).
+__device__ int jacobi_sym(double* M, double* V, int L, double* ev, int max_sweeps) {
   __shared__ double rc[64], rs[64];
   __shared__ int rp[64], rq[64];
-  __shared__ double red[256];
+  __shared__ int nrot;
+  __shared__ double dmax;
+  int sweeps = 0;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int m = (L + 1) & ~1;   // even number of slots; slot >= L is a dummy
-  for (int e = tid; e < L * L; e += nt) V[e] = (e / L == e % L) ? 1.0 : 0.0;
-  __syncthreads();
+  const int m = (L + 1) & ~1;      // slot L (odd L) is a dummy
+  const int np = m / 2;
+  if (V)
+    for (int e = tid; e < L * L; e += nt) V[e] = (e / L == e % L) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // off-diagonal and total Frobenius norms
-    double off = 0, tot = 0;
-    for (int e = tid; e < L * L; e += nt) {
-      double v = M[e] * M[e];
-      tot += v;
-      if (e / L != e % L) off += v;
+    if (tid == 0) {
+      nrot = 0;
+      double d = 0;
+      for (int i = 0; i < L; ++i) d = fmax(d, fabs(M[i * L + i]));
+      dmax = d;
     }
-    red[tid] = off;
     __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    double offs = red[0];
-    __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    double tots = red[0];
-    __syncthreads();
-    if (offs <= 1e-32 * tots || tots == 0.0) break;
+    sweeps = sweep + 1;
     for (int r = 0; r < m - 1; ++r) {
-      const int npairs = m / 2;
-      for (int p = tid; p < npairs; p += nt) {
+      // rotation of pair p; an off-diagonal entry below
+      // max(1e-15 sqrt(|a_ii a_jj|), 1e-17 max_k |a_kk|) is set to zero instead
+      // (the floor sits above the rounding left by the two-sided updates); the
+      // sweep loop ends after a sweep without rotations
+      for (int p = tid; p < np; p += nt) {
         int a = (p == 0) ? 0 : ((p - 1 + r) % (m - 1)) + 1;
-        int bq = m - 1 - p;
-        int b = ((bq - 1 + r) % (m - 1)) + 1;
+        int b = ((m - 2 - p + r) % (m - 1)) + 1;
         int i = a < b ? a : b, j = a < b ? b : a;
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         if (j < L) {
-          double apq = M[i * L + j];
-          if (apq != 0.0) {
-            double tau = (M[j * L + j] - M[i * L + i]) / (2.0 * apq);
+          const double apq = M[i * L + j];
+          const double app = M[i * L + i], aqq = M[j * L + j];
+          if (fabs(apq) > fmax(1e-15 * sqrt(fabs(app) * fabs(aqq)), 1e-17 * dmax)) {
+            double tau = (aqq - app) / (2.0 * apq);
             double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            sn = t * c;
+            atomicAdd(&nrot, 1);
+          } else if (apq != 0.0) {
+            M[i * L + j] = 0.0;
+            M[j * L + i] = 0.0;
           }
         }
-        rc[p] = c; rs[p] = s; rp[p] = i; rq[p] = j;
+        rc[p] = c; rs[p] = sn; rp[p] = i; rq[p] = j;
       }
       __syncthreads();
-      // rows: M <- J^T M
-      for (int e = tid; e < npairs * L; e += nt) {
-        int p = e / L, col = e - p * L;
-        int i = rp[p], j = rq[p];
-        if (j >= L || rs[p] == 0.0) continue;
-        double c = rc[p], s = rs[p];
-        double mi = M[i * L + col], mj = M[j * L + col];
-        M[i * L + col] = c * mi - s * mj;
-        M[j * L + col] = s * mi + c * mj;
+      // ordered block (P, Q): rows {i1, j1} x cols {i2, j2}; B' = R_P^T B R_Q
+      for (int e = tid; e < np * np; e += nt) {
+        const int P = e / np, Q = e - P * np;
+        const double c1 = rc[P], s1 = rs[P], c2 = rc[Q], s2 = rs[Q];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int i1 = rp[P], j1 = rq[P], i2 = rp[Q], j2 = rq[Q];
+        const bool r1 = j1 < L, r2 = j2 < L;
+        double b00 = M[i1 * L + i2];
+        double b01 = r2 ? M[i1 * L + j2] : 0.0;
+        double b10 = r1 ? M[j1 * L + i2] : 0.0;
+        double b11 = (r1 && r2) ? M[j1 * L + j2] : 0.0;
+        // left: rows
+        double t00 = c1 * b00 - s1 * b10, t01 = c1 * b01 - s1 * b11;
+        double t10 = s1 * b00 + c1 * b10, t11 = s1 * b01 + c1 * b11;
+        // right: columns
+        double u00 = c2 * t00 - s2 * t01, u01 = s2 * t00 + c2 * t01;
+        double u10 = c2 * t10 - s2 * t11, u11 = s2 * t10 + c2 * t11;
+        if (P == Q) { u01 = 0.0; u10 = 0.0; }   // the rotation annihilates the pair
+        M[i1 * L + i2] = u00;
+        if (r2) M[i1 * L + j2] = u01;
+        if (r1) M[j1 * L + i2] = u10;
+        if (r1 && r2) M[j1 * L + j2] = u11;
       }
-      __syncthreads();
-      // columns: M <- M J, V <- V J
-      for (int e = tid; e < npairs * L; e += nt) {
-        int p = e / L, row = e - p * L;
-        int i = rp[p], j = rq[p];
-        if (j >= L || rs[p] == 0.0) continue;
-        double c = rc[p], s = rs[p];
-        double mi = M[row * L + i], mj = M[row * L + j];
-        M[row * L + i] = c * mi - s * mj;
-        M[row * L + j] = s * mi + c * mj;
-        double vi = V[row * L + i], vj = V[row * L + j];
-        V[row * L + i] = c * vi - s * vj;
-        V[row * L + j] = s * vi + c * vj;
+      if (V) {
+        for (int e = tid; e < np * L; e += nt) {
+          const int P = e / L, row = e - P * L;
+          const int i = rp[P], j = rq[P];
+          if (j >= L || rs[P] == 0.0) continue;
+          const double c = rc[P], sn = rs[P];
+          double vi = V[row * L + i], vj = V[row * L + j];
+          V[row * L + i] = c * vi - sn * vj;
+          V[row * L + j] = sn * vi + c * vj;
+        }
       }
       __syncthreads();
     }
+    if (nrot == 0) break;
+    __syncthreads();
   }
   for (int e = tid; e < L; e += nt) ev[e] = M[e * L + e];
   __syncthreads();
+  return sweeps;
 }
 
-__global__ __launch_bounds__(256) void factor_kernel(const double* __restrict__ G, int L,
+__global__ __launch_bounds__(kFT) void factor_kernel(const double* __restrict__ G, int L,
                                                      int64_t N, int nu_mode, int tail,
                                                      double mu_in, int max_esc, FactorWork w,
-                                                     double* __restrict__ meta) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int m = 2 * L;
-  __shared__ double sh_nu, sh_diag;
+                                                     int nlds, double* __restrict__ meta) {
+  // L x L matrices: the working matrix S, the Cholesky factor C, the
+  // eigenvectors V and the solve output X; the first `nlds` of them live in
+  // dynamic LDS, the rest in the global work buffer.
+  extern __shared__ double lds_mat[];
+  __shared__ double sh_nu, ev_s[PcMeta::kMaxEll];
   __shared__ int sh_fail;
   __shared__ int order[PcMeta::kMaxEll];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = 2 * L;
+  const size_t LL = static_cast<size_t>(L) * L;
+  double* S = nlds >= 1 ? lds_mat : w.Mg;
+  double* Cm = nlds >= 2 ? lds_mat + LL : w.Cg;
+  double* Vm = nlds >= 3 ? lds_mat + 2 * LL : w.V;
+  double* Xm = nlds >= 4 ? lds_mat + 3 * LL : w.X;
   const double eps = 2.220446049250313e-16;
+  if (tid == 0) meta[PcMeta::kScalars + 8 + 7] = static_cast<double>(wall_clock64());
   // ---- shift nu
   if (nu_mode == 0) {
-    for (int e = tid; e < L * L; e += nt) w.M[e] = G[(L + e / L) * m + L + e % L];
+    for (int e = tid; e < L * L; e += nt) S[e] = G[(L + e / L) * m + L + e % L];
     __syncthreads();
-    block_jacobi_eig(w.M, w.V, L, w.ev, 40);
+    const int sw = jacobi_sym(S, nullptr, L, ev_s, 40);
+    if (tid == 0) meta[PcMeta::kSweeps0] = sw;
     if (tid == 0) {
       double mx = 0;
-      for (int i = 0; i < L; ++i) mx = fmax(mx, w.ev[i]);
+      for (int i = 0; i < L; ++i) mx = fmax(mx, ev_s[i]);
       sh_nu = sqrt(static_cast<double>(N)) * eps * sqrt(fmax(mx, 0.0));
     }
   } else if (tid == 0) {
@@ -217,33 +433,33 @@ __global__ __launch_bounds__(256) void factor_kernel(const double* __restrict__ 
   }
   __syncthreads();
   double nu = sh_nu;
-  // ---- shifted Cholesky with escalation
+  if (tid == 0) meta[PcMeta::kScalars + 9] = static_cast<double>(wall_clock64());
+  // ---- shifted Cholesky (right-looking, in place in S) with escalation
   int esc = 0;
   for (;; ++esc) {
     for (int e = tid; e < L * L; e += nt) {
       int i = e / L, j = e - i * L;
       double oy = 0.5 * (G[i * m + L + j] + G[j * m + L + i]);
       double oo = 0.5 * (G[i * m + j] + G[j * m + i]);
-      w.Gs[e] = oy + nu * oo;
-      w.Cc[e] = 0.0;
+      S[e] = oy + nu * oo;
     }
     if (tid == 0) sh_fail = 0;
     __syncthreads();
     for (int j = 0; j < L; ++j) {
       if (tid == 0) {
-        double d = w.Gs[j * L + j];
-        for (int k = 0; k < j; ++k) d -= w.Cc[j * L + k] * w.Cc[j * L + k];
+        double d = S[j * L + j];
         if (!(d > 0.0) || !isfinite(d)) { sh_fail = 1; d = 1.0; }
-        sh_diag = sqrt(d);
-        w.Cc[j * L + j] = sh_diag;
+        S[j * L + j] = sqrt(d);
       }
       __syncthreads();
       if (sh_fail) break;
-      double djj = sh_diag;
-      for (int i = j + 1 + tid; i < L; i += nt) {
-        double s = w.Gs[i * L + j];
-        for (int k = 0; k < j; ++k) s -= w.Cc[i * L + k] * w.Cc[j * L + k];
-        w.Cc[i * L + j] = s / djj;
+      const double djj = S[j * L + j];
+      for (int i = j + 1 + tid; i < L; i += nt) S[i * L + j] /= djj;
+      __syncthreads();
+      const int rem = L - j - 1;
+      for (int e = tid; e < rem * rem; e += nt) {
+        int i = j + 1 + e / rem, k = j + 1 + e % rem;
+        if (k <= i) S[i * L + k] -= S[i * L + j] * S[k * L + j];
       }
       __syncthreads();
     }
@@ -264,67 +480,77 @@ __global__ __launch_bounds__(256) void factor_kernel(const double* __restrict__ 
     for (int e = tid; e < L * L; e += nt) w.R[e] = 0.0;
     return;
   }
-  // ---- Mv = Y_nu^T Y_nu = YY + nu (OY + OY^T) + nu^2 OO
+  if (tid == 0) meta[PcMeta::kScalars + 10] = static_cast<double>(wall_clock64());
+  // lower factor C (the upper part of S is stale)
   for (int e = tid; e < L * L; e += nt) {
     int i = e / L, j = e - i * L;
-    w.Mv[e] = G[(L + i) * m + L + j] + nu * (G[i * m + L + j] + G[j * m + L + i]) +
-              nu * nu * G[i * m + j];
+    Cm[e] = j <= i ? S[e] : 0.0;
   }
   __syncthreads();
-  // ---- X = C^{-1} Mv (column j per thread), then M = C^{-1} X^T
+  // ---- X = C^{-1} Mv with Mv = Y_nu^T Y_nu = YY + nu (OY + OY^T) + nu^2 OO,
+  // one right-hand side column per thread
   for (int j = tid; j < L; j += nt)
     for (int i = 0; i < L; ++i) {
-      double s = w.Mv[i * L + j];
-      for (int k = 0; k < i; ++k) s -= w.Cc[i * L + k] * w.X[k * L + j];
-      w.X[i * L + j] = s / w.Cc[i * L + i];
+      double sacc = G[(L + i) * m + L + j] + nu * (G[i * m + L + j] + G[j * m + L + i]) +
+                    nu * nu * G[i * m + j];
+      for (int k = 0; k < i; ++k) sacc -= Cm[i * L + k] * Xm[k * L + j];
+      Xm[i * L + j] = sacc / Cm[i * L + i];
     }
   __syncthreads();
+  if (tid == 0) meta[PcMeta::kScalars + 11] = static_cast<double>(wall_clock64());
+  // ---- M = C^{-1} X^T, into S
   for (int j = tid; j < L; j += nt)
     for (int i = 0; i < L; ++i) {
-      double s = w.X[j * L + i];                       // (X^T)[i][j]
-      for (int k = 0; k < i; ++k) s -= w.Cc[i * L + k] * w.M[k * L + j];
-      w.M[i * L + j] = s / w.Cc[i * L + i];
+      double sacc = Xm[j * L + i];
+      for (int k = 0; k < i; ++k) sacc -= Cm[i * L + k] * S[k * L + j];
+      S[i * L + j] = sacc / Cm[i * L + i];
     }
   __syncthreads();
   for (int e = tid; e < L * L; e += nt) {
     int i = e / L, j = e - i * L;
     if (i < j) {
-      double a = 0.5 * (w.M[i * L + j] + w.M[j * L + i]);
-      w.M[i * L + j] = a;
-      w.M[j * L + i] = a;
+      double a = 0.5 * (S[i * L + j] + S[j * L + i]);
+      S[i * L + j] = a;
+      S[j * L + i] = a;
     }
   }
   __syncthreads();
+  if (tid == 0) meta[PcMeta::kScalars + 12] = static_cast<double>(wall_clock64());
   // ---- eigen-decomposition M = V diag(S^2) V^T, descending order
-  block_jacobi_eig(w.M, w.V, L, w.ev, 60);
+  {
+    const int sw = jacobi_sym(S, Vm, L, ev_s, 60);
+    if (tid == 0) meta[PcMeta::kSweeps1] = sw;
+  }
   if (tid == 0) {
     for (int i = 0; i < L; ++i) order[i] = i;
     for (int i = 0; i < L; ++i) {           // selection sort, descending
       int best = i;
       for (int k = i + 1; k < L; ++k)
-        if (w.ev[order[k]] > w.ev[order[best]]) best = k;
+        if (ev_s[order[k]] > ev_s[order[best]]) best = k;
       int t = order[i]; order[i] = order[best]; order[best] = t;
     }
   }
   __syncthreads();
+  if (tid == 0) meta[PcMeta::kScalars + 13] = static_cast<double>(wall_clock64());
   // ---- R = C^{-T} V S^{-1} (column k per thread, back substitution)
   for (int k = tid; k < L; k += nt) {
-    int src = order[k];
-    double s2 = w.ev[src];
-    double inv = s2 > 0 ? 1.0 / sqrt(s2) : 0.0;
+    const int src = order[k];
+    const double s2 = ev_s[src];
+    const double inv = s2 > 0 ? 1.0 / sqrt(s2) : 0.0;
     for (int i = L - 1; i >= 0; --i) {
-      double s = w.V[i * L + src];
-      for (int q = i + 1; q < L; ++q) s -= w.Cc[q * L + i] * w.R[q * L + k];
-      w.R[i * L + k] = s / w.Cc[i * L + i];
+      double sacc = Vm[i * L + src];
+      for (int q = i + 1; q < L; ++q) sacc -= Cm[q * L + i] * w.R[q * L + k];
+      w.R[i * L + k] = sacc / Cm[i * L + i];
     }
     for (int i = 0; i < L; ++i) w.R[i * L + k] *= inv;
   }
   __syncthreads();
+  if (tid == 0) meta[PcMeta::kScalars + 14] = static_cast<double>(wall_clock64());
   // ---- spectrum and preconditioner coefficients
   if (tid == 0) {
     int keff = 0;
     for (int k = 0; k < L; ++k) {
-      double sh = fmax(0.0, w.ev[order[k]] - nu);
+      double sh = fmax(0.0, ev_s[order[k]] - nu);
       meta[PcMeta::kShat + k] = sh;
       if (sh > 0) keff = k + 1;
     }
@@ -497,25 +723,57 @@ static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
   chunk = (chunk + kGK - 1) / kGK * kGK;
   nchunks = (N + chunk - 1) / chunk;
   size_t part_d = static_cast<size_t>(nchunks) * ntri * kGT * kGT;
+  // MFMA Gram (BF16 / FP32): one block per chunk of at least 256 pixels
+  int64_t mfma_blocks = std::min<int64_t>(256, std::max<int64_t>(1, N / 256));
+  int64_t mfma_chunk = (N + mfma_blocks - 1) / mfma_blocks;
+  mfma_chunk = (mfma_chunk + 63) / 64 * 64;
+  mfma_blocks = (N + mfma_chunk - 1) / mfma_chunk;
+  {
+    const int nrg = (2 * L + 31) / 32;
+    const size_t mfma_d = (static_cast<size_t>(mfma_blocks) * nrg * (nrg + 1) / 2 * 1024 + 1) / 2;
+    part_d = std::max(part_d, mfma_d);
+  }
   size_t G_d = static_cast<size_t>(m) * m;
-  size_t w_d = 7 * static_cast<size_t>(L) * L + L;
+  size_t w_d = 5 * static_cast<size_t>(L) * L + L;
   NYS_TRY(pc->work.ensure(sizeof(double) * (part_d + G_d + w_d)));
   double* part = pc->work.as<double>();
   double* G = part + part_d;
   double* wb = G + G_d;
   FactorWork w;
   size_t LL = static_cast<size_t>(L) * L;
-  w.Gs = wb; w.Cc = wb + LL; w.Mv = wb + 2 * LL; w.X = wb + 3 * LL; w.M = wb + 4 * LL;
-  w.V = wb + 5 * LL; w.R = wb + 6 * LL; w.ev = wb + 7 * LL;
+  w.Cg = wb; w.X = wb + LL; w.Mg = wb + 2 * LL; w.V = wb + 3 * LL; w.R = wb + 4 * LL;
+  w.ev = wb + 5 * LL;
   using C = typename Io<S>::C;
-  hipLaunchKernelGGL((gram_partial_kernel<S, C>), dim3(static_cast<unsigned>(nchunks), ntri),
-                     dim3(256), 0, st, omega, Y, N, L, chunk, ntiles, part);
-  NYS_TRY(launch_check("gram_partial_kernel"));
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(64), dim3(256), 0, st, part,
-                     static_cast<int>(nchunks), ntiles, L, G);
-  NYS_TRY(launch_check("gram_reduce_kernel"));
-  hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(256), 0, st, G, L, N, o.nu_mode, o.tail, o.mu,
-                     o.max_escalations < 0 ? 6 : o.max_escalations, w, pc->meta.as<double>());
+  // MFMA path for BF16 / FP32 when every column is a whole number of 16-byte
+  // chunks; the VALU tile kernel otherwise (and for FP64)
+  bool use_mfma = false;
+  if constexpr (!std::is_same<S, double>::value) use_mfma = (N % (16 / sizeof(S))) == 0;
+  if (!use_mfma) {
+    hipLaunchKernelGGL((gram_partial_kernel<S, C>), dim3(static_cast<unsigned>(nchunks), ntri),
+                       dim3(256), 0, st, omega, Y, N, L, chunk, ntiles, part);
+    NYS_TRY(launch_check("gram_partial_kernel"));
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(64), dim3(256), 0, st, part,
+                       static_cast<int>(nchunks), ntiles, L, G);
+    NYS_TRY(launch_check("gram_reduce_kernel"));
+  } else {
+    if constexpr (!std::is_same<S, double>::value)
+      NYS_TRY(gram_mfma<S>(omega, Y, N, L, reinterpret_cast<float*>(part), mfma_blocks, mfma_chunk,
+                           G, st));
+  }
+  // as many L x L matrices in LDS as the device allows per workgroup
+  int dev = 0, maxsh = 0;
+  NYS_CHECK_HIP(hipGetDevice(&dev));
+  NYS_CHECK_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t avail = maxsh > 8192 ? static_cast<size_t>(maxsh) - 8192 : 0;
+  const int nlds = static_cast<int>(std::min<size_t>(4, avail / (sizeof(double) * LL)));
+  const size_t lds = sizeof(double) * LL * nlds;
+  if (lds > 64 * 1024) {
+    NYS_CHECK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(factor_kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>(lds)));
+  }
+  hipLaunchKernelGGL(factor_kernel, dim3(1), dim3(kFT), lds, st, G, L, N, o.nu_mode, o.tail, o.mu,
+                     o.max_escalations < 0 ? 6 : o.max_escalations, w, nlds, pc->meta.as<double>());
   NYS_TRY(launch_check("factor_kernel"));
   dim3 ug(cdiv(N, 256), cdiv(L, kUK));
   if (pc->u_dtype == NYS_F64) {
@@ -632,4 +890,14 @@ extern "C" nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const 
                             ncols, st);
   return pc_apply<float>(pc, inverse != 0, static_cast<const float*>(v), static_cast<float*>(out),
                          ncols, st);
+}
+
+extern "C" nys_status nys_pc_diag(nys_pc pc, double* out, int32_t n, void* stream) {
+  NYS_REQUIRE(pc && out && n > 0, "nys_pc_diag: bad argument");
+  std::vector<double> meta(PcMeta::kTotal);
+  NYS_CHECK_HIP(hipStreamSynchronize(as_stream(stream)));
+  NYS_CHECK_HIP(hipMemcpy(meta.data(), pc->meta.p, sizeof(double) * PcMeta::kTotal,
+                          hipMemcpyDeviceToHost));
+  for (int i = 0; i < n && i < 16; ++i) out[i] = meta[PcMeta::kScalars + i];
+  return NYS_OK;
 }

@@ -42,6 +42,8 @@ struct PcMeta {
   static constexpr int kKeff = kScalars + 4;
   static constexpr int kStatus = kScalars + 5;
   static constexpr int kEscal = kScalars + 6;
+  static constexpr int kSweeps0 = kScalars + 7;   // Jacobi sweeps: shift estimate
+  static constexpr int kSweeps1 = kScalars + 8;   // Jacobi sweeps: B^T B
   static constexpr int kTotal = kScalars + 16;
 };
 

@@ -498,6 +498,24 @@ extern "C" nys_status nys_op_create(const nys_op_desc* desc, nys_op* out) {
       op->d.factor = f;
       op->M = static_cast<int64_t>(d.n1 / f) * (d.n2 / f);
       op->psf.assign(d.psf, d.psf + k * k);
+      {
+        // rank-1 test, pivoting on the largest entry: psf = u v^T exactly up
+        // to rounding enables the separable kernels
+        int ap = 0, bp = 0;
+        double mx = 0;
+        for (int a = 0; a < k; ++a)
+          for (int b = 0; b < k; ++b)
+            if (std::fabs(op->psf[a * k + b]) > mx) { mx = std::fabs(op->psf[a * k + b]); ap = a; bp = b; }
+        double err = 0;
+        if (mx > 0) {
+          for (int a = 0; a < k; ++a) op->sep_u[a] = op->psf[a * k + bp];
+          for (int b = 0; b < k; ++b) op->sep_v[b] = op->psf[ap * k + b] / op->psf[ap * k + bp];
+          for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+              err = std::fmax(err, std::fabs(op->psf[a * k + b] - op->sep_u[a] * op->sep_v[b]));
+        }
+        op->sep = (mx > 0 && err <= 1e-14 * mx) ? 1 : 0;
+      }
       std::vector<double> h64(2 * k * k);
       std::vector<float> h32(2 * k * k);
       for (int a = 0; a < k; ++a)

@@ -92,13 +92,19 @@ def test_sketch_blur(dt, n, ell):
     assert rel(host(Y), sv.sketch(prob, host(om))) < TOL[dt]
 
 
-@pytest.mark.parametrize("dt,n,ell", [("bf16", 128, 5), ("f32", 128, 3), ("bf16", 96, 4),
-                                      ("f32", 72, 2)])
-def test_sketch_super_resolution(dt, n, ell):
-    """Fused path for n divisible by 64, unfused chain otherwise."""
+@pytest.mark.parametrize("dt,n,ell,k,sep", [("bf16", 128, 5, 7, True), ("f32", 128, 3, 7, True),
+                                             ("bf16", 96, 4, 7, True), ("f32", 72, 2, 7, True),
+                                             ("bf16", 192, 3, 9, True), ("f32", 64, 2, 5, True),
+                                             ("f32", 128, 2, 3, True), ("f32", 128, 2, 7, False),
+                                             ("bf16", 64, 3, 9, False)])
+def test_sketch_super_resolution(dt, n, ell, k, sep):
+    """Fused separable path for n divisible by 64 and a rank-1 PSF, fused 2-D
+    path for other PSFs, unfused chain otherwise."""
     P = need_gpu()
-    banner(f"sketch SR {dt} n={n} ell={ell}")
-    h = W.gaussian_psf(7, 1.2)
+    banner(f"sketch SR {dt} n={n} ell={ell} k={k} sep={sep}")
+    h = W.gaussian_psf(k, 1.2)
+    if not sep:
+        h = h + 0.02 * W.gaussian((k, k), 30)      # rank > 1
     op = P.Operator(P.OP_BLURDOWN, n, n, psf=h, factor=2, wavelet_levels=3)
     om = dev(W.omega(ell, n, n, 7), dt)
     Y = P.nys_sketch(op, om)
