@@ -149,11 +149,12 @@ nys_status nys_pc_info(nys_pc pc, double* shat, double* nu, int32_t* k_eff,
  * phases (100 MHz wall clock). */
 nys_status nys_pc_diag(nys_pc pc, double* out, int32_t n, void* stream);
 
-/* Device pointer to U (ell*N, u_dtype) and its sizes. */
-nys_status nys_pc_u(nys_pc pc, const void** u, int64_t* N, int64_t* ell,
+/* Device pointer to U and its sizes: column k of U starts at element k * ldu
+ * (ldu >= N; the library pads the pitch), dtype u_dtype. */
+nys_status nys_pc_u(nys_pc pc, const void** u, int64_t* N, int64_t* ell, int64_t* ldu,
                     int32_t* u_dtype);
 
-/* Copies U (ell*N, u_dtype) into the caller's device buffer `dst`. */
+/* Copies U into the caller's device buffer `dst`, packed as ell*N (u_dtype). */
 nys_status nys_pc_copy_u(nys_pc pc, void* dst, void* stream);
 
 /* out = P^{-1} v (inverse != 0) or P v, for `ncols` stacked vectors of

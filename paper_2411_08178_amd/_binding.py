@@ -76,7 +76,8 @@ def lib():
             "nys_sketch": [vp, i32, vp, vp, i64, vp],
             "nys_factor": [vp, vp, i32, i64, i64, C.POINTER(FactorOpts), C.POINTER(vp), vp],
             "nys_pc_info": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32), C.POINTER(i32), vp],
-            "nys_pc_u": [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)],
+            "nys_pc_u": [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                         C.POINTER(i32)],
             "nys_pc_diag": [vp, C.POINTER(dbl), i32, vp],
             "nys_pc_copy_u": [vp, vp, vp],
             "nys_apply": [vp, i32, i32, vp, vp, i64, vp],

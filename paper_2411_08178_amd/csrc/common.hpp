@@ -138,6 +138,8 @@ struct nys_op_s {
 
 struct nys_pc_s {
   int64_t N = 0, ell = 0;
+  int64_t ldu = 0;                // pitch of U's columns (elements), >= N
+  int64_t ell_pad = 0;            // rows of U allocated: ell rounded up to 16, zero padded
   int32_t u_dtype = NYS_F32;
   int32_t tail = 0;
   double pinv_norm_cache = -1.0;  // ||P^{-1}|| once read back from the device

@@ -376,7 +376,7 @@ __device__ int jacobi_sym(double* M, double* V, int L, double* ev, int max_sweep
       }
       if (V) {
         for (int e = tid; e < np * L; e += nt) {
-          const int P = e / L, row = e - P * L;
+          const int row = e / np, P = e - row * np;   // consecutive threads: one row
           const int i = rp[P], j = rq[P];
           if (j >= L || rs[P] == 0.0) continue;
           const double c = rc[P], sn = rs[P];
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(256) void form_u_kernel(const S* __restrict__ omega
                                                      const S* __restrict__ Y,
                                                      const double* __restrict__ R,
                                                      const double* __restrict__ meta, int64_t N,
-                                                     int L, T* __restrict__ U) {
+                                                     int L, int64_t ldu, T* __restrict__ U) {
   __shared__ C Rs[PcMeta::kMaxEll][kUK];
   const int k0 = blockIdx.y * kUK;
   for (int e = threadIdx.x; e < L * kUK; e += blockDim.x) {
@@ -610,105 +610,8 @@ __global__ __launch_bounds__(256) void form_u_kernel(const S* __restrict__ omega
   }
 #pragma unroll
   for (int kk = 0; kk < kUK; ++kk)
-    if (k0 + kk < L) U[static_cast<size_t>(k0 + kk) * N + n] = static_cast<T>(acc[kk]);
+    if (k0 + kk < L) U[static_cast<size_t>(k0 + kk) * ldu + n] = static_cast<T>(acc[kk]);
 }
-
-// ================================================================ apply
-// c = U^T v per column (partials over row chunks), coef . c, out = v + U (coef . c)
-constexpr int kAK = 32, kAChunk = 1024;
-
-template <class T>
-__global__ __launch_bounds__(256) void utv_partial_kernel(const T* __restrict__ U,
-                                                          const T* __restrict__ v, int64_t N,
-                                                          int L, int nchunks,
-                                                          double* __restrict__ part) {
-  const int k0 = blockIdx.y * kAK;
-  const int col = blockIdx.z;
-  const T* vc = v + static_cast<size_t>(col) * N;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * kAChunk;
-  T acc[kAK];
-#pragma unroll
-  for (int kk = 0; kk < kAK; ++kk) acc[kk] = 0;
-  for (int64_t n = n0 + threadIdx.x; n < n0 + kAChunk && n < N; n += 256) {
-    T x = vc[n];
-#pragma unroll
-    for (int kk = 0; kk < kAK; ++kk)
-      if (k0 + kk < L) acc[kk] += U[static_cast<size_t>(k0 + kk) * N + n] * x;
-  }
-  __shared__ double red[4][kAK];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int kk = 0; kk < kAK; ++kk) {
-    double s = static_cast<double>(acc[kk]);
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) red[wv][kk] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < kAK && k0 + threadIdx.x < L) {
-    double s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-    part[(static_cast<size_t>(col) * nchunks + blockIdx.x) * L + k0 + threadIdx.x] = s;
-  }
-}
-
-__global__ void coef_reduce_kernel(const double* __restrict__ part, int nchunks, int L,
-                                   const double* __restrict__ coef, double* __restrict__ cd) {
-  const int col = blockIdx.x;
-  for (int k = threadIdx.x; k < L; k += blockDim.x) {
-    double s = 0;
-    for (int c = 0; c < nchunks; ++c) s += part[(static_cast<size_t>(col) * nchunks + c) * L + k];
-    cd[static_cast<size_t>(col) * L + k] = coef[k] * s;
-  }
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void u_update_kernel(const T* __restrict__ U,
-                                                       const T* __restrict__ v,
-                                                       const double* __restrict__ cd, int64_t N,
-                                                       int L, T* __restrict__ out) {
-  __shared__ T cs[PcMeta::kMaxEll];
-  const int col = blockIdx.y;
-  for (int k = threadIdx.x; k < L; k += blockDim.x) cs[k] = static_cast<T>(cd[static_cast<size_t>(col) * L + k]);
-  __syncthreads();
-  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (n >= N) return;
-  T acc = v[static_cast<size_t>(col) * N + n];
-  for (int k = 0; k < L; ++k) acc += U[static_cast<size_t>(k) * N + n] * cs[k];
-  out[static_cast<size_t>(col) * N + n] = acc;
-}
-
-template <class T>
-nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
-                     hipStream_t st) {
-  const int64_t N = pc->N;
-  const int L = static_cast<int>(pc->ell);
-  const int nchunks = static_cast<int>(cdiv(N, kAChunk));
-  NYS_TRY(pc->work.ensure(sizeof(double) * static_cast<size_t>(ncols) * nchunks * L));
-  double* part = pc->work.as<double>();
-  hipLaunchKernelGGL((utv_partial_kernel<T>), dim3(nchunks, cdiv(L, kAK), ncols), dim3(256), 0, st,
-                     pc->U.as<T>(), v, N, L, nchunks, part);
-  NYS_TRY(launch_check("utv_partial_kernel"));
-  const double* coef = pc->meta.as<double>() + (inverse ? PcMeta::kD : PcMeta::kE);
-  hipLaunchKernelGGL(coef_reduce_kernel, dim3(ncols), dim3(128), 0, st, part, nchunks, L, coef, cd);
-  return launch_check("coef_reduce_kernel");
-}
-
-template nys_status pc_coeffs<double>(nys_pc, bool, const double*, int64_t, double*, hipStream_t);
-template nys_status pc_coeffs<float>(nys_pc, bool, const float*, int64_t, double*, hipStream_t);
-
-template <class T>
-nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, hipStream_t st) {
-  const int64_t N = pc->N;
-  const int L = static_cast<int>(pc->ell);
-  NYS_TRY(pc->work2.ensure(sizeof(double) * static_cast<size_t>(ncols) * L));
-  double* cd = pc->work2.as<double>();
-  NYS_TRY(pc_coeffs<T>(pc, inverse, v, ncols, cd, st));
-  hipLaunchKernelGGL((u_update_kernel<T>), dim3(cdiv(N, 256), ncols), dim3(256), 0, st,
-                     pc->U.as<T>(), v, cd, N, L, out);
-  return launch_check("u_update_kernel");
-}
-
-template nys_status pc_apply<double>(nys_pc, bool, const double*, double*, int64_t, hipStream_t);
-template nys_status pc_apply<float>(nys_pc, bool, const float*, float*, int64_t, hipStream_t);
 
 template <class S>
 static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
@@ -778,10 +681,10 @@ static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
   dim3 ug(cdiv(N, 256), cdiv(L, kUK));
   if (pc->u_dtype == NYS_F64) {
     hipLaunchKernelGGL((form_u_kernel<S, double, double>), ug, dim3(256), 0, st, omega, Y, w.R,
-                       pc->meta.as<double>(), N, L, pc->U.as<double>());
+                       pc->meta.as<double>(), N, L, pc->ldu, pc->U.as<double>());
   } else {
     hipLaunchKernelGGL((form_u_kernel<S, float, C>), ug, dim3(256), 0, st, omega, Y, w.R,
-                       pc->meta.as<double>(), N, L, pc->U.as<float>());
+                       pc->meta.as<double>(), N, L, pc->ldu, pc->U.as<float>());
   }
   return launch_check("form_u_kernel");
 }
@@ -806,8 +709,18 @@ extern "C" nys_status nys_factor(const void* omega, const void* Y, nys_dtype in_
   pc->ell = ell;
   pc->u_dtype = o.u_dtype;
   pc->tail = o.tail;
-  nys_status s = pc->U.ensure(dtype_size(static_cast<nys_dtype>(o.u_dtype)) * N * ell);
+  // column pitch: a multiple of 64 elements, plus 96 for large images so the
+  // ell columns are not a power of two apart
+  pc->ldu = (N + 63) / 64 * 64 + (N >= 16384 ? 96 : 0);
+  pc->ell_pad = (ell + 15) / 16 * 16;
+  const size_t ubytes = dtype_size(static_cast<nys_dtype>(o.u_dtype)) * pc->ldu * pc->ell_pad;
+  nys_status s = pc->U.ensure(ubytes);
+  if (s == NYS_OK && hipMemset(pc->U.p, 0, ubytes) != hipSuccess) {
+    set_error("nys_factor: hipMemset of U failed");
+    s = NYS_EHIP;
+  }
   if (s == NYS_OK) s = pc->meta.ensure(sizeof(double) * PcMeta::kTotal);
+
   if (s == NYS_OK) {
     hipStream_t st = as_stream(stream);
     switch (in_dt) {
@@ -863,9 +776,10 @@ extern "C" nys_status nys_pc_info(nys_pc pc, double* shat, double* nu, int32_t* 
 }
 
 extern "C" nys_status nys_pc_u(nys_pc pc, const void** u, int64_t* N, int64_t* ell,
-                               int32_t* u_dtype) {
+                               int64_t* ldu, int32_t* u_dtype) {
   NYS_REQUIRE(pc, "nys_pc_u: null pc");
   if (u) *u = pc->U.p;
+  if (ldu) *ldu = pc->ldu;
   if (N) *N = pc->N;
   if (ell) *ell = pc->ell;
   if (u_dtype) *u_dtype = pc->u_dtype;
@@ -874,9 +788,9 @@ extern "C" nys_status nys_pc_u(nys_pc pc, const void** u, int64_t* N, int64_t* e
 
 extern "C" nys_status nys_pc_copy_u(nys_pc pc, void* dst, void* stream) {
   NYS_REQUIRE(pc && dst, "nys_pc_copy_u: bad argument");
-  NYS_CHECK_HIP(hipMemcpyAsync(dst, pc->U.p,
-                               dtype_size(static_cast<nys_dtype>(pc->u_dtype)) * pc->N * pc->ell,
-                               hipMemcpyDeviceToDevice, as_stream(stream)));
+  const size_t es = dtype_size(static_cast<nys_dtype>(pc->u_dtype));
+  NYS_CHECK_HIP(hipMemcpy2DAsync(dst, es * pc->N, pc->U.p, es * pc->ldu, es * pc->N, pc->ell,
+                                 hipMemcpyDeviceToDevice, as_stream(stream)));
   return NYS_OK;
 }
 

@@ -27,6 +27,16 @@ template <class T>
 nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
                      hipStream_t st);
 
+// x = s - lam (t + U cd) for one column (pinv.hip).
+template <class T>
+nys_status pc_x_from_pinv(nys_pc pc, const T* s, const T* t, const double* cd, double lam, T* x,
+                          hipStream_t st);
+// P-weighted l1 prox by semismooth Newton (Thm. 1, pinv.hip); gamma_state
+// (ell FP64, may be null) is the warm start and receives the root.
+template <class T>
+nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
+                    double* gamma_state, hipStream_t st, int* trials_out = nullptr);
+
 // Layout of the FP64 metadata block of a preconditioner (pc->meta).
 struct PcMeta {
   static constexpr int kMaxEll = 128;

@@ -1,0 +1,925 @@
+// Applications of the Nystrom preconditioner (eq. (6)) and the P-weighted l1
+// prox of Thm. 1, the two places where the tall U (N x ell) is streamed.
+//
+// U is stored column by column with a padded pitch (pc->ldu >= N elements),
+// so its ell columns do not sit a power of two apart in memory.
+//
+// Reductions U^T w: every thread accumulates its pixels for all ell entries,
+// a butterfly reduce-scatter across the 64 lanes leaves entry k on lane k,
+// the waves of a block are summed in FP64 into one partial per block, and a
+// one-block tail kernel adds the partials in a fixed order and finishes the
+// step.  Results are therefore bitwise reproducible.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace nys {
+
+// ---------------------------------------------------------------- helpers
+// Butterfly reduce-scatter over the 64 lanes of acc[NV] (NV in 16..128).  On
+// return lane l holds, in acc[j] for j < max(NV / 64, 1), the wave sum of
+// entry k = j + max(NV / 64, 1) * l (NV >= 64), or of entry k = l % NV
+// (NV < 64).
+template <int CNT, int O, int NV, class A>
+__device__ __forceinline__ void butterfly_level(A (&acc)[NV], int lane) {
+  if constexpr (O >= 1 && CNT >= 2) {
+    constexpr int half = CNT / 2;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      A send = up ? acc[j] : acc[j + half];
+      A keep = up ? acc[j + half] : acc[j];
+      acc[j] = keep + __shfl_xor(send, O, 64);
+    }
+    butterfly_level<half, O / 2, NV>(acc, lane);
+  }
+}
+
+template <int NV, class A>
+__device__ __forceinline__ void butterfly_reduce(A (&acc)[NV], int lane) {
+  // fold the lane bits that NV does not need (NV < 64)
+#pragma unroll
+  for (int o = 32; o >= NV && o >= 1; o >>= 1)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] += __shfl_xor(acc[j], o, 64);
+  butterfly_level<NV, (NV >= 64 ? 32 : NV / 2), NV>(acc, lane);
+}
+
+// Map of the reduce-scatter: entry held by (lane, j).
+template <int NV>
+__device__ __forceinline__ int butterfly_entry(int lane, int j) {
+  return NV >= 64 ? j + (NV / 64) * lane : (lane % NV);
+}
+
+// Sum a block's per-thread acc[NV] into out (FP64, NV entries); all threads
+// must call it.  red must hold (blockDim.x / 64) * NV doubles.
+template <int NV, class A>
+__device__ __forceinline__ void block_reduce(A (&acc)[NV], double* red, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  butterfly_reduce<NV>(acc, lane);
+  constexpr int PER = NV >= 64 ? NV / 64 : 1;
+  if (NV >= 64 || lane < NV) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) red[wave * NV + butterfly_entry<NV>(lane, j)] = static_cast<double>(acc[j]);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NV; k += blockDim.x) {
+    double sacc = 0;
+    for (int w = 0; w < nw; ++w) sacc += red[w * NV + k];
+    out[k] = sacc;
+  }
+  __syncthreads();
+}
+
+// out[k] = sum_{b < nblk} part[b * L + k] for k < L (L <= 128), with all
+// threads of the block: blockDim / L slices of the blocks, four accumulators
+// each, combined in a fixed order.  red: blockDim.x doubles of LDS.
+__device__ __forceinline__ void tail_sum(const double* __restrict__ part, int nblk, int L,
+                                         double* red, double* out) {
+  const int S = blockDim.x / L;
+  const int k = threadIdx.x % L, sl = threadIdx.x / L;
+  if (sl < S) {
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int b = sl;
+    for (; b + 3 * S < nblk; b += 4 * S) {
+      a0 += part[static_cast<size_t>(b) * L + k];
+      a1 += part[static_cast<size_t>(b + S) * L + k];
+      a2 += part[static_cast<size_t>(b + 2 * S) * L + k];
+      a3 += part[static_cast<size_t>(b + 3 * S) * L + k];
+    }
+    for (; b < nblk; b += S) a0 += part[static_cast<size_t>(b) * L + k];
+    red[sl * L + k] = (a0 + a1) + (a2 + a3);
+  }
+  __syncthreads();
+  for (int kk = threadIdx.x; kk < L; kk += blockDim.x) {
+    double sacc = 0;
+    for (int q = 0; q < S; ++q) sacc += red[q * L + kk];
+    out[kk] = sacc;
+  }
+  __syncthreads();
+}
+
+// ================================================================ U^T v
+// Block (b, col): pixels of chunk b, all rows of U in groups of 16 (rows past
+// ell are zero padding): part[col][b][k] = sum over the chunk of U[k][n] v[n].
+template <class T>
+__global__ __launch_bounds__(1024) void ut_partial_kernel(const T* __restrict__ U, int64_t ldu,
+                                                          const T* __restrict__ v, int64_t N,
+                                                          int Lp, int64_t chunk,
+                                                          double* __restrict__ part) {
+  __shared__ double red[1024];
+  __shared__ double bsum[16];
+  const int nblk = gridDim.x, col = blockIdx.y;
+  const int bs = blockDim.x;
+  const T* vc = v + static_cast<size_t>(col) * N;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  constexpr int VW = 16 / sizeof(T);       // elements per 16-byte load
+  for (int g = 0; g < Lp / 16; ++g) {
+    T acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0;
+    if ((N % VW) == 0) {
+      // 16-byte loads: VW consecutive pixels per thread (chunk is a multiple of 64)
+      for (int64_t n = n0 + VW * threadIdx.x; n < n1; n += VW * bs) {
+        T x[VW];
+        __builtin_memcpy(x, vc + n, 16);
+        const T* p = U + static_cast<size_t>(16 * g) * ldu + n;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          T u[VW];
+          __builtin_memcpy(u, p, 16);
+#pragma unroll
+          for (int i = 0; i < VW; ++i) acc[k] += u[i] * x[i];
+          p += ldu;
+        }
+      }
+    } else {
+      for (int64_t n = n0 + threadIdx.x; n < n1; n += bs) {
+        const T x = vc[n];
+        const T* p = U + static_cast<size_t>(16 * g) * ldu + n;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          acc[k] += p[0] * x;
+          p += ldu;
+        }
+      }
+    }
+    block_reduce<16>(acc, red, bsum);
+    if (threadIdx.x < 16)
+      part[(static_cast<size_t>(col) * nblk + blockIdx.x) * Lp + 16 * g + threadIdx.x] = bsum[threadIdx.x];
+  }
+}
+
+// cd[col][k] = coef[k] * sum_b part[col][b][k]   (one block)
+__global__ __launch_bounds__(1024) void ut_tail_kernel(const double* __restrict__ part, int nblk,
+                                                       int L, int Lp, int ncols,
+                                                       const double* __restrict__ coef,
+                                                       double* __restrict__ cd) {
+  __shared__ double red[1024];
+  __shared__ double bsum[128];
+  for (int c = 0; c < ncols; ++c) {
+    tail_sum(part + static_cast<size_t>(c) * nblk * Lp, nblk, Lp, red, bsum);
+    for (int k = threadIdx.x; k < L; k += blockDim.x) cd[static_cast<size_t>(c) * L + k] = coef[k] * bsum[k];
+    __syncthreads();
+  }
+}
+
+// out = v + U cd   (one column of cd per image)
+template <class T>
+__global__ __launch_bounds__(256) void u_update_kernel(const T* __restrict__ U, int64_t ldu,
+                                                       const T* __restrict__ v,
+                                                       const double* __restrict__ cd, int64_t N,
+                                                       int L, T* __restrict__ out) {
+  __shared__ T cs[PcMeta::kMaxEll];
+  const int col = blockIdx.y;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) cs[k] = static_cast<T>(cd[static_cast<size_t>(col) * L + k]);
+  __syncthreads();
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (n >= N) return;
+  T acc = v[static_cast<size_t>(col) * N + n];
+  for (int k = 0; k < L; ++k) acc += U[static_cast<size_t>(k) * ldu + n] * cs[k];
+  out[static_cast<size_t>(col) * N + n] = acc;
+}
+
+// x = s - lam (t + U cd)   (P^{-1} t = t + U (d . U^T t))
+template <class T>
+__global__ __launch_bounds__(256) void x_from_pinv_kernel(const T* __restrict__ s,
+                                                          const T* __restrict__ t,
+                                                          const T* __restrict__ U, int64_t ldu,
+                                                          const double* __restrict__ cd,
+                                                          int64_t N, int L, T lam,
+                                                          T* __restrict__ x) {
+  __shared__ T cs[PcMeta::kMaxEll];
+  for (int k = threadIdx.x; k < L; k += blockDim.x) cs[k] = static_cast<T>(cd[k]);
+  __syncthreads();
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (n >= N) return;
+  T acc = t[n];
+  for (int k = 0; k < L; ++k) acc += U[static_cast<size_t>(k) * ldu + n] * cs[k];
+  x[n] = s[n] - lam * acc;
+}
+
+// launch geometry of the streaming reductions over N
+static void red_geometry(int64_t N, int& nblk, int64_t& chunk) {
+  int64_t nb = std::min<int64_t>(256, std::max<int64_t>(1, (N + 1023) / 1024));
+  chunk = (N + nb - 1) / nb;
+  chunk = (chunk + 63) / 64 * 64;
+  nblk = static_cast<int>((N + chunk - 1) / chunk);
+}
+
+template <class T>
+nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
+                     hipStream_t st) {
+  const int L = static_cast<int>(pc->ell), Lp = static_cast<int>(pc->ell_pad);
+  int nblk;
+  int64_t chunk;
+  red_geometry(pc->N, nblk, chunk);
+  NYS_TRY(pc->work.ensure(sizeof(double) * static_cast<size_t>(ncols) * nblk * Lp));
+  double* part = pc->work.as<double>();
+  const double* coef = pc->meta.as<double>() + (inverse ? PcMeta::kD : PcMeta::kE);
+  hipLaunchKernelGGL((ut_partial_kernel<T>), dim3(nblk, static_cast<unsigned>(ncols)), dim3(1024),
+                     0, st, pc->U.as<T>(), pc->ldu, v, pc->N, Lp, chunk, part);
+  NYS_TRY(launch_check("ut_partial_kernel"));
+  hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, part, nblk, L, Lp,
+                     static_cast<int>(ncols), coef, cd);
+  return launch_check("ut_tail_kernel");
+}
+
+template <class T>
+nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, hipStream_t st) {
+  const int64_t N = pc->N;
+  const int L = static_cast<int>(pc->ell);
+  NYS_TRY(pc->work2.ensure(sizeof(double) * static_cast<size_t>(ncols) * L));
+  double* cd = pc->work2.as<double>();
+  NYS_TRY(pc_coeffs<T>(pc, inverse, v, ncols, cd, st));
+  hipLaunchKernelGGL((u_update_kernel<T>), dim3(cdiv(N, 256), ncols), dim3(256), 0, st,
+                     pc->U.as<T>(), pc->ldu, v, cd, N, L, out);
+  return launch_check("u_update_kernel");
+}
+
+template <class T>
+nys_status pc_x_from_pinv(nys_pc pc, const T* s, const T* t, const double* cd, double lam, T* x,
+                          hipStream_t st) {
+  hipLaunchKernelGGL((x_from_pinv_kernel<T>), dim3(cdiv(pc->N, 256)), dim3(256), 0, st, s, t,
+                     pc->U.as<T>(), pc->ldu, cd, pc->N, static_cast<int>(pc->ell),
+                     static_cast<T>(lam), x);
+  return launch_check("x_from_pinv_kernel");
+}
+
+template nys_status pc_coeffs<double>(nys_pc, bool, const double*, int64_t, double*, hipStream_t);
+template nys_status pc_coeffs<float>(nys_pc, bool, const float*, int64_t, double*, hipStream_t);
+template nys_status pc_apply<double>(nys_pc, bool, const double*, double*, int64_t, hipStream_t);
+template nys_status pc_apply<float>(nys_pc, bool, const float*, float*, int64_t, hipStream_t);
+template nys_status pc_x_from_pinv<double>(nys_pc, const double*, const double*, const double*,
+                                           double, double*, hipStream_t);
+template nys_status pc_x_from_pinv<float>(nys_pc, const float*, const float*, const double*,
+                                          double, float*, hipStream_t);
+
+// ================================================================ SSN (l1)
+// prox of lam ||.||_1 in the norm of P = I + U diag(e) U^T (Thm. 1):
+// gamma solves F(gamma) = gamma - diag(e) U^T (soft_lam(s - U gamma) - s) = 0;
+// semismooth Newton with the Jacobian I + diag(e) U^T D U, D = diag(|s - U
+// gamma| > lam), and backtracking on ||F||.  The device holds the state and
+// takes every decision; the host only polls the `done` flag.
+struct SsnState {
+  static constexpr int kGamma = 0;                       // accepted gamma
+  static constexpr int kTry = PcMeta::kMaxEll;           // trial gamma
+  static constexpr int kDelta = 2 * PcMeta::kMaxEll;     // Newton direction
+  static constexpr int kF = 3 * PcMeta::kMaxEll;         // F at gamma
+  static constexpr int kS = 4 * PcMeta::kMaxEll;         // scalars
+  static constexpr int kNF = kS + 0, kT = kS + 1, kDone = kS + 2, kHalv = kS + 3,
+                       kHave = kS + 4, kNeedGram = kS + 5, kTrials = kS + 6, kSteps = kS + 7;
+  static constexpr int kTotal = kS + 16;
+};
+
+// Evaluation at the trial point in one pass over U: r = s - U g, x = soft(r),
+// mask = |r| > lam, partial U^T (x - s) per block.
+template <class T, int ROWS, int LP = (ROWS <= 16 ? 16 : ROWS <= 32 ? 32 : ROWS <= 64 ? 64 : 128)>
+__global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, int64_t ldu,
+                                                       const T* __restrict__ s, int64_t N, int L,
+                                                       int64_t chunk, T lam,
+                                                       const double* __restrict__ state,
+                                                       uint8_t* __restrict__ mask,
+                                                       double* __restrict__ part) {
+  __shared__ double red[8 * LP];
+  __shared__ double bsum[LP];
+  __shared__ T g[LP];
+  if (state[SsnState::kDone] != 0.0) return;
+  for (int k = threadIdx.x; k < LP; k += blockDim.x) g[k] = k < L ? static_cast<T>(state[SsnState::kTry + k]) : T(0);
+  __syncthreads();
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  T acc[LP];
+#pragma unroll
+  for (int k = 0; k < LP; ++k) acc[k] = 0;
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    T u[LP];
+    T r = s[n];
+    const T* p = U + n;
+#pragma unroll
+    for (int k = 0; k < LP; ++k) {
+      if (k < ROWS) {
+        u[k] = p[0];
+        p += ldu;
+      } else {
+        u[k] = T(0);
+      }
+      r -= u[k] * g[k];
+    }
+    const T ar = fabs(r);
+    const T xv = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
+    const T d = xv - s[n];
+    mask[n] = ar > lam ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < LP; ++k) acc[k] += u[k] * d;
+  }
+  block_reduce<LP>(acc, red, bsum);
+  for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
+}
+
+// F(g_try) = g_try - e . U^T (x - s) from the partials, its norm, and the
+// decision: accept (and stop, or ask for a Newton step) or backtrack.
+__global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restrict__ part, int nblk,
+                                                         int L, const double* __restrict__ meta,
+                                                         double* __restrict__ state, double tol,
+                                                         int max_halvings) {
+  __shared__ double red[512];
+  __shared__ double bsum[PcMeta::kMaxEll];
+  __shared__ double Ft[PcMeta::kMaxEll];
+  __shared__ int accepted;
+  if (state[SsnState::kDone] != 0.0) return;
+  tail_sum(part, nblk, L, red, bsum);
+  double sq = 0;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    const double f = state[SsnState::kTry + k] - meta[PcMeta::kE + k] * bsum[k];
+    Ft[k] = f;
+    sq += f * f;
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double nFt = sqrt(red[0]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    state[SsnState::kTrials] += 1.0;
+    const bool have = state[SsnState::kHave] != 0.0;
+    const double nF = state[SsnState::kNF], t = state[SsnState::kT];
+    const bool accept = !have || nFt <= (1.0 - 1e-4 * t) * nF ||
+                        state[SsnState::kHalv] >= max_halvings || !isfinite(nFt);
+    state[SsnState::kNeedGram] = 0.0;
+    if (accept) {
+      state[SsnState::kHave] = 1.0;
+      state[SsnState::kNF] = nFt;
+      double gn = 0;
+      for (int k = 0; k < L; ++k) gn += state[SsnState::kTry + k] * state[SsnState::kTry + k];
+      if (nFt <= tol * (1.0 + sqrt(gn)) || !isfinite(nFt)) state[SsnState::kDone] = 1.0;
+      else state[SsnState::kNeedGram] = 1.0;
+    } else {
+      const double tn = 0.5 * t;
+      state[SsnState::kT] = tn;
+      state[SsnState::kHalv] += 1.0;
+      for (int k = 0; k < L; ++k)
+        state[SsnState::kTry + k] = state[SsnState::kGamma + k] + tn * state[SsnState::kDelta + k];
+    }
+    accepted = accept ? 1 : 0;
+  }
+  __syncthreads();
+  if (accepted)
+    for (int k = threadIdx.x; k < L; k += blockDim.x) {
+      state[SsnState::kGamma + k] = state[SsnState::kTry + k];
+      state[SsnState::kF + k] = Ft[k];
+    }
+}
+
+// ---- masked Gram on the matrix cores
+typedef float floatx16_v __attribute__((ext_vector_type(16)));
+
+// Stage: 128 bytes (32 float pixels) of each of the 32 NRG rows of U, masked
+// by D, through LDS; 32 x 32 tiles of the upper triangle over 4 waves, as in
+// the Gram of the factorisation.  Partials per block in FP32.
+template <int NRG>
+__global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__ U, int64_t ldu,
+                                                       const uint8_t* __restrict__ mask,
+                                                       int64_t N, int L, int64_t chunk,
+                                                       const double* __restrict__ meta,
+                                                       const double* __restrict__ state,
+                                                       float* __restrict__ part) {
+  constexpr int NTRI = NRG * (NRG + 1) / 2;
+  constexpr int ROWS = 32 * NRG;
+  constexpr int PITCH = 144;
+  constexpr int LDSB = ROWS * PITCH > NTRI * 4096 ? ROWS * PITCH : NTRI * 4096;
+  __shared__ __align__(16) unsigned char lds[LDSB];
+  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int ld_row = tid >> 3, ld_col = tid & 7;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  floatx16_v acc[NTRI];
+#pragma unroll
+  for (int t = 0; t < NTRI; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+  for (int64_t n = n0; n < n1; n += 32) {
+    // masked chunk of 4 pixels of row 32 g + ld_row
+    const int64_t nn = n + 4 * ld_col;
+    uint32_t mk = 0;
+    if (nn + 4 <= N) {
+      mk = *reinterpret_cast<const uint32_t*>(mask + nn);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mk |= (nn + i < N ? static_cast<uint32_t>(mask[nn + i]) : 0u) << (8 * i);
+    }
+#pragma unroll
+    for (int g = 0; g < NRG; ++g) {
+      const int row = 32 * g + ld_row;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < L && nn < N) {
+        const float* src = U + static_cast<size_t>(row) * ldu + nn;
+        if (nn + 4 <= N) {
+          val = *reinterpret_cast<const float4*>(src);
+        } else {
+          val.x = src[0];
+          val.y = nn + 1 < N ? src[1] : 0.f;
+          val.z = nn + 2 < N ? src[2] : 0.f;
+          val.w = nn + 3 < N ? src[3] : 0.f;
+        }
+      }
+      val.x = (mk & 0xffu) ? val.x : 0.f;
+      val.y = (mk & 0xff00u) ? val.y : 0.f;
+      val.z = (mk & 0xff0000u) ? val.z : 0.f;
+      val.w = (mk & 0xff000000u) ? val.w : 0.f;
+      *reinterpret_cast<float4*>(lds + row * PITCH + ld_col * 16) = val;
+    }
+    __syncthreads();
+    // wave w: pixels 8 w .. 8 w + 7 of the stage; lane l feeds pixel
+    // 8 w + 4 (l / 32) + i to the i-th 32x32x2 MFMA (i < 4) of every tile
+    {
+      float fr[NRG][4];
+#pragma unroll
+      for (int g = 0; g < NRG; ++g) {
+        float4 u = *reinterpret_cast<const float4*>(lds + (32 * g + lr) * PITCH + 32 * wave + 16 * lh);
+        fr[g][0] = u.x; fr[g][1] = u.y; fr[g][2] = u.z; fr[g][3] = u.w;
+      }
+      int tile = 0;
+#pragma unroll
+      for (int ti = 0; ti < NRG; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NRG; ++tj, ++tile)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            acc[tile] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti][i], fr[tj][i], acc[tile], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // sum the four waves' tiles in LDS (fixed order), then one partial per block
+  float* sum = reinterpret_cast<float*>(lds);     // NTRI * 1024 floats
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < NTRI; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int idx = t * 1024 + (8 * (r / 4) + 4 * lh + (r & 3)) * 32 + lr;
+          sum[idx] = (w == 0 ? 0.f : sum[idx]) + acc[t][r];
+        }
+    }
+    __syncthreads();
+  }
+  float* dst = part + static_cast<size_t>(blockIdx.x) * NTRI * 1024;
+  for (int e = tid; e < NTRI * 1024; e += 256) dst[e] = sum[e];
+}
+
+// Stage 2 of the Gram reduction: block (e, q) sums partials q, q + 16, ... of
+// entries 256 e .. 256 e + 255 (FP64, fixed order) into part2[q][entry].
+template <int NRG>
+__global__ __launch_bounds__(256) void ssn_gram_stage2_kernel(const float* __restrict__ part,
+                                                              int nblk,
+                                                              const double* __restrict__ state,
+                                                              double* __restrict__ part2) {
+  constexpr int NTRI = NRG * (NRG + 1) / 2;
+  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
+  const int e = blockIdx.x * 256 + threadIdx.x, q = blockIdx.y;
+  if (e >= NTRI * 1024) return;
+  const size_t stride = static_cast<size_t>(NTRI) * 1024;
+  double a0 = 0, a1 = 0;
+  int b = q;
+  for (; b + 16 < nblk; b += 32) {
+    a0 += static_cast<double>(part[b * stride + e]);
+    a1 += static_cast<double>(part[(b + 16) * stride + e]);
+  }
+  for (; b < nblk; b += 16) a0 += static_cast<double>(part[b * stride + e]);
+  part2[q * stride + e] = a0 + a1;
+}
+
+// ---- Newton direction: J delta = -F(gamma), J = I + diag(e) M, by LU with
+// partial pivoting (pivot rows left in place, pivot order recorded).  A is
+// J in LDS with pitch L + 1.  Sets delta, the trial point gamma + delta and
+// resets the line search.
+__device__ void ssn_set_direction(const double* __restrict__ sol, int L, double* __restrict__ state) {
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    state[SsnState::kDelta + k] = sol[k];
+    state[SsnState::kTry + k] = state[SsnState::kGamma + k] + sol[k];
+  }
+  if (threadIdx.x == 0) {
+    state[SsnState::kT] = 1.0;
+    state[SsnState::kHalv] = 0.0;
+    state[SsnState::kSteps] += 1.0;
+  }
+}
+
+// L <= 64, 256 threads: lane r of wave q holds J[r][16 q .. 16 q + 15] in
+// registers; the wave owning column j picks the pivot and the multipliers,
+// every wave eliminates its own columns (one barrier per column).
+__device__ void lu_regs64(double* __restrict__ A, int L, double* __restrict__ state) {
+  __shared__ double fbuf[2][64];
+  __shared__ int pbuf[2];
+  __shared__ int porder[64];
+  __shared__ double sol[64], rhs_s[64];
+  const int tid = threadIdx.x, q = tid >> 6, r = tid & 63;
+  const int LP1 = L + 1;
+  double a[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * q + c;
+    a[c] = (r < L && col < L) ? A[r * LP1 + col] : (r == col ? 1.0 : 0.0);
+  }
+  double rh = (r < L) ? -state[SsnState::kF + r] : 0.0;   // kept by every wave
+  bool used = r >= L;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    if (j < L) {
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int qj = j >> 4, cj = j & 15;
+      if (q == qj) {
+        double best = used ? -1.0 : fabs(a[cj]);
+        int bi = used ? -1 : r;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const double ob = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(bi, o, 64);
+          if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ob; bi = oi; }
+        }
+        const double piv = __shfl(a[cj], bi, 64);
+        fbuf[j & 1][r] = (used || r == bi) ? 0.0 : a[cj] / piv;
+        if (r == 0) { pbuf[j & 1] = bi; porder[j] = bi; }
+      }
+      __syncthreads();
+      const int p = __builtin_amdgcn_readfirstlane(pbuf[j & 1]);
+      const double f = fbuf[j & 1][r];
+      if (r == p) used = true;
+      if (q >= qj) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const double pc = __shfl(a[c], p, 64);
+          if (16 * q + c > j) a[c] -= f * pc;
+        }
+      }
+      const double rp = __shfl(rh, p, 64);
+      rh -= f * rp;
+    }
+  }
+  // eliminated matrix and right-hand side back to LDS, then back substitution
+  // on wave 0: unknown j from pivot row porder[j]
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int col = 16 * q + c;
+    if (r < L && col < L) A[r * LP1 + col] = a[c];
+  }
+  if (q == 0) rhs_s[r] = rh;
+  __syncthreads();
+  if (q == 0) {
+    double rr = rhs_s[r];
+    for (int j = L - 1; j >= 0; --j) {
+      const int p = porder[j];
+      const double rp = __shfl(rr, p, 64);
+      const double d = rp / A[p * LP1 + j];
+      if (r == 0) sol[j] = d;
+      if (r < L) rr -= A[r * LP1 + j] * d;
+    }
+  }
+  __syncthreads();
+  ssn_set_direction(sol, L, state);
+}
+
+// Any L <= 128: elimination on wave 0 alone (lane r owns rows r and r + 64).
+__device__ void lu_wave(double* __restrict__ A, int L, double* __restrict__ state) {
+  __shared__ double rhs[PcMeta::kMaxEll], sol[PcMeta::kMaxEll];
+  __shared__ int porder[PcMeta::kMaxEll];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int LP1 = L + 1;
+  for (int i = tid; i < L; i += blockDim.x) rhs[i] = -state[SsnState::kF + i];
+  __syncthreads();
+  if (wave == 0) {
+    const int r0 = lane, r1 = lane + 64;
+    bool used0 = r0 >= L, used1 = r1 >= L;
+    for (int j = 0; j < L; ++j) {
+      double best = -1.0;
+      int bi = -1;
+      if (!used0) { best = fabs(A[r0 * LP1 + j]); bi = r0; }
+      if (!used1) { const double v = fabs(A[r1 * LP1 + j]); if (v > best) { best = v; bi = r1; } }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ob; bi = oi; }
+      }
+      const int p = bi;
+      if (lane == 0) porder[j] = p;
+      if (p == r0) used0 = true;
+      if (p == r1) used1 = true;
+      const double idp = 1.0 / A[p * LP1 + j];
+      const double rp = rhs[p];
+      if (!used0) {
+        const double f = A[r0 * LP1 + j] * idp;
+        for (int k = j + 1; k < L; ++k) A[r0 * LP1 + k] -= f * A[p * LP1 + k];
+        rhs[r0] -= f * rp;
+      }
+      if (!used1) {
+        const double f = A[r1 * LP1 + j] * idp;
+        for (int k = j + 1; k < L; ++k) A[r1 * LP1 + k] -= f * A[p * LP1 + k];
+        rhs[r1] -= f * rp;
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+    }
+    for (int j = L - 1; j >= 0; --j) {
+      const int p = porder[j];
+      double ps = 0;
+      for (int k = j + 1 + lane; k < L; k += 64) ps += A[p * LP1 + k] * sol[k];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) ps += __shfl_xor(ps, o, 64);
+      if (lane == 0) sol[j] = (rhs[p] - ps) / A[p * LP1 + j];
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  ssn_set_direction(sol, L, state);
+}
+
+__device__ __forceinline__ void ssn_lu(double* A, int L, double* state) {
+  if (L <= 64) lu_regs64(A, L, state);
+  else lu_wave(A, L, state);
+}
+
+// One block: J = I + diag(e) M with M = sum of the 16 stage-2 partials, then
+// the LU solve.
+template <int NRG>
+__global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict__ part2, int L,
+                                                        const double* __restrict__ meta,
+                                                        double* __restrict__ state) {
+  constexpr int NTRI = NRG * (NRG + 1) / 2;
+  extern __shared__ double A[];
+  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
+  const int LP1 = L + 1;
+  const size_t stride = static_cast<size_t>(NTRI) * 1024;
+  for (int e = threadIdx.x; e < NTRI * 1024; e += blockDim.x) {
+    const int tile = e >> 10, rr = e & 1023;
+    int ti = 0, t = tile;
+    while (t >= NRG - ti) { t -= NRG - ti; ++ti; }
+    const int tj = ti + t;
+    const int gi = 32 * ti + (rr >> 5), gj = 32 * tj + (rr & 31);
+    if (gi >= L || gj >= L || (ti == tj && gi > gj)) continue;
+    double sacc = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) sacc += part2[b * stride + e];
+    A[gi * LP1 + gj] = (gi == gj ? 1.0 : 0.0) + meta[PcMeta::kE + gi] * sacc;
+    if (gi != gj) A[gj * LP1 + gi] = meta[PcMeta::kE + gj] * sacc;
+  }
+  __syncthreads();
+  ssn_lu(A, L, state);
+}
+
+// FP64 U: masked Gram on the vector units, one 64 x 64 output tile per block
+// and chunk, then the same reduction + solve in a second small kernel.
+__global__ __launch_bounds__(256) void ssn_gram_f64_kernel(const double* __restrict__ U,
+                                                           int64_t ldu,
+                                                           const uint8_t* __restrict__ mask,
+                                                           const double* __restrict__ state,
+                                                           int64_t N, int L, int64_t chunk,
+                                                           double* __restrict__ part) {
+  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
+  const int ti = blockIdx.y, tj = blockIdx.z;
+  if (tj < ti) return;
+  __shared__ double As[32][65];
+  __shared__ double Bs[32][65];
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+  for (int64_t nb = n0; nb < n1; nb += 32) {
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+      int c = e / 32, kk = e - c * 32;
+      int64_t n = nb + kk;
+      int ka = ti * 64 + c, kb = tj * 64 + c;
+      bool on = n < n1 && mask[n];
+      As[kk][c] = (on && ka < L) ? U[static_cast<size_t>(ka) * ldu + n] : 0.0;
+      Bs[kk][c] = (on && kb < L) ? U[static_cast<size_t>(kb) * ldu + n] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 32; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q] = As[kk][ty * 4 + q];
+        b[q] = Bs[kk][tx * 4 + q];
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+    }
+    __syncthreads();
+  }
+  const size_t LL = static_cast<size_t>(L) * L;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int ia = ti * 64 + ty * 4 + p, ib = tj * 64 + tx * 4 + q;
+      if (ia < L && ib < L) {
+        part[blockIdx.x * LL + static_cast<size_t>(ia) * L + ib] = acc[p][q];
+        part[blockIdx.x * LL + static_cast<size_t>(ib) * L + ia] = acc[p][q];
+      }
+    }
+}
+
+__global__ __launch_bounds__(256) void ssn_solve_f64_kernel(const double* __restrict__ part,
+                                                            int nchunks, int L,
+                                                            const double* __restrict__ meta,
+                                                            double* __restrict__ state) {
+  extern __shared__ double A[];
+  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
+  const size_t LL = static_cast<size_t>(L) * L;
+  for (size_t e = threadIdx.x; e < LL; e += blockDim.x) {
+    const int i = static_cast<int>(e / L), j = static_cast<int>(e % L);
+    double sacc = 0;
+    for (int c = 0; c < nchunks; ++c) sacc += part[c * LL + e];
+    A[i * (L + 1) + j] = (i == j ? 1.0 : 0.0) + meta[PcMeta::kE + i] * sacc;
+  }
+  __syncthreads();
+  ssn_lu(A, L, state);
+}
+
+// x = soft(s - U gamma)
+template <class T>
+__global__ __launch_bounds__(256) void ssn_final_kernel(const T* __restrict__ U, int64_t ldu,
+                                                        const T* __restrict__ s,
+                                                        const double* __restrict__ state,
+                                                        int64_t N, int L, T lam, T* __restrict__ x) {
+  __shared__ T g[PcMeta::kMaxEll];
+  for (int k = threadIdx.x; k < L; k += blockDim.x) g[k] = static_cast<T>(state[SsnState::kGamma + k]);
+  __syncthreads();
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (n >= N) return;
+  T r = s[n];
+  for (int k = 0; k < L; ++k) r -= U[static_cast<size_t>(k) * ldu + n] * g[k];
+  const T ar = fabs(r);
+  x[n] = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
+}
+
+// Initialise the Newton state from the warm start gamma (g_try = gamma).
+__global__ void ssn_init_kernel(double* __restrict__ state, const double* __restrict__ gamma0, int L) {
+  for (int k = threadIdx.x; k < L; k += blockDim.x) {
+    double g = gamma0 ? gamma0[k] : 0.0;
+    state[SsnState::kGamma + k] = g;
+    state[SsnState::kTry + k] = g;
+    state[SsnState::kDelta + k] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    state[SsnState::kNF] = 0; state[SsnState::kT] = 1; state[SsnState::kDone] = 0;
+    state[SsnState::kHalv] = 0; state[SsnState::kHave] = 0; state[SsnState::kNeedGram] = 0;
+    state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0;
+  }
+}
+
+__global__ void ssn_store_gamma_kernel(const double* __restrict__ state, double* __restrict__ gamma, int L) {
+  for (int k = threadIdx.x; k < L; k += blockDim.x) gamma[k] = state[SsnState::kGamma + k];
+}
+
+template <class T, int ROWS>
+static void launch_ssn_eval(nys_pc pc, const T* s, T lam, double* state, uint8_t* mask,
+                            double* part, int nblk, int64_t chunk, hipStream_t st) {
+  hipLaunchKernelGGL((ssn_eval_kernel<T, ROWS>), dim3(nblk), dim3(512), 0, st, pc->U.as<T>(),
+                     pc->ldu, s, pc->N, static_cast<int>(pc->ell), chunk, lam, state, mask, part);
+}
+
+template <class T>
+static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8_t* mask,
+                              double* part, int nblk, int64_t chunk, double tol, hipStream_t st) {
+  switch (pc->ell_pad) {
+    case 16: launch_ssn_eval<T, 16>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    case 32: launch_ssn_eval<T, 32>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    case 48: launch_ssn_eval<T, 48>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    case 64: launch_ssn_eval<T, 64>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    case 80: launch_ssn_eval<T, 80>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    case 96: launch_ssn_eval<T, 96>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    case 112: launch_ssn_eval<T, 112>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    default: launch_ssn_eval<T, 128>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+  }
+  NYS_TRY(launch_check("ssn_eval_kernel"));
+  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(512), 0, st, part, nblk,
+                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30);
+  return launch_check("ssn_decide_kernel");
+}
+
+template <int NRG>
+static nys_status launch_ssn_newton(nys_pc pc, const uint8_t* mask, double* state, float* part,
+                                    int nblk, int64_t chunk, hipStream_t st) {
+  constexpr int NTRI = NRG * (NRG + 1) / 2;
+  hipLaunchKernelGGL((ssn_gram_kernel<NRG>), dim3(nblk), dim3(256), 0, st, pc->U.as<float>(),
+                     pc->ldu, mask, pc->N, static_cast<int>(pc->ell), chunk, pc->meta.as<double>(),
+                     state, part);
+  NYS_TRY(launch_check("ssn_gram_kernel"));
+  double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
+  hipLaunchKernelGGL((ssn_gram_stage2_kernel<NRG>), dim3(NTRI * 4, 16), dim3(256), 0, st, part, nblk,
+                     state, part2);
+  NYS_TRY(launch_check("ssn_gram_stage2_kernel"));
+  const size_t lds = sizeof(double) * pc->ell * (pc->ell + 1);
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_solve_kernel<NRG>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  hipLaunchKernelGGL((ssn_solve_kernel<NRG>), dim3(1), dim3(256), lds, st, part2,
+                     static_cast<int>(pc->ell), pc->meta.as<double>(), state);
+  return launch_check("ssn_solve_kernel");
+}
+
+template <class T>
+nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
+                    double* gamma_state, hipStream_t st, int* trials_out) {
+  const int64_t N = pc->N;
+  const int L = static_cast<int>(pc->ell);
+  int nblk;
+  int64_t chunk;
+  red_geometry(N, nblk, chunk);
+  // Gram: fewer, longer chunks (the last block reduces their partials)
+  const int64_t gblk = std::min<int64_t>(256, std::max<int64_t>(1, (N + 1023) / 1024));
+  int64_t gchunk = (N + gblk - 1) / gblk;
+  gchunk = (gchunk + 31) / 32 * 32;
+  const int ngb = static_cast<int>((N + gchunk - 1) / gchunk);
+  const int nrg = (L + 31) / 32;
+  const size_t LL = static_cast<size_t>(L) * L;
+  size_t gpart_d;
+  if (sizeof(T) == 4)
+    gpart_d = (static_cast<size_t>(ngb) * nrg * (nrg + 1) / 2 * 1024 + 1) / 2 +
+              static_cast<size_t>(16) * nrg * (nrg + 1) / 2 * 1024 + 1;
+  else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
+  const size_t need = SsnState::kTotal + static_cast<size_t>(nblk) * L + gpart_d + LL;
+  NYS_TRY(pc->work2.ensure(sizeof(double) * need + N + 256));
+  double* state = pc->work2.as<double>();
+  double* part = state + SsnState::kTotal;
+  double* gpart = part + static_cast<size_t>(nblk) * L;
+  double* Mj = gpart + gpart_d;
+  uint8_t* mask = reinterpret_cast<uint8_t*>(Mj + LL);
+  const T lam = static_cast<T>(lam_bar);
+  const double tol = reg.newton_tol > 0 ? reg.newton_tol : (sizeof(T) == 8 ? 1e-12 : 1e-6);
+  const int max_trials = reg.max_newton > 0 ? reg.max_newton : 60;
+  hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
+  NYS_TRY(launch_check("ssn_init_kernel"));
+  int trial = 0;
+  for (; trial < max_trials; ++trial) {
+    NYS_TRY(launch_eval<T>(pc, s, lam, state, mask, part, nblk, chunk, tol, st));
+    if constexpr (sizeof(T) == 4) {
+      float* gp = reinterpret_cast<float*>(gpart);
+      switch (nrg) {
+        case 1: NYS_TRY(launch_ssn_newton<1>(pc, mask, state, gp, ngb, gchunk, st)); break;
+        case 2: NYS_TRY(launch_ssn_newton<2>(pc, mask, state, gp, ngb, gchunk, st)); break;
+        case 3: NYS_TRY(launch_ssn_newton<3>(pc, mask, state, gp, ngb, gchunk, st)); break;
+        default: NYS_TRY(launch_ssn_newton<4>(pc, mask, state, gp, ngb, gchunk, st)); break;
+      }
+    } else {
+      const int ntile = static_cast<int>(cdiv(L, 64));
+      const int nch = static_cast<int>(cdiv(N, 4096));
+      hipLaunchKernelGGL(ssn_gram_f64_kernel, dim3(nch, ntile, ntile), dim3(256), 0, st,
+                         reinterpret_cast<const double*>(pc->U.p), pc->ldu, mask, state, N, L,
+                         static_cast<int64_t>(4096), gpart);
+      NYS_TRY(launch_check("ssn_gram_f64_kernel"));
+      const size_t lds = sizeof(double) * (LL + L);
+      if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_solve_f64_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+      hipLaunchKernelGGL(ssn_solve_f64_kernel, dim3(1), dim3(256), lds, st, gpart, nch, L,
+                         pc->meta.as<double>(), state);
+      NYS_TRY(launch_check("ssn_solve_f64_kernel"));
+    }
+    // poll the done flag after the 2nd trial and then after every trial
+    if (trial >= 1) {
+      double done = 0;
+      NYS_CHECK_HIP(hipMemcpyAsync(&done, state + SsnState::kDone, sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+      NYS_CHECK_HIP(hipStreamSynchronize(st));
+      if (done != 0.0) break;
+    }
+  }
+  if (trials_out) *trials_out = trial + 1;
+  hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, pc->U.as<T>(),
+                     pc->ldu, s, state, N, L, lam, x);
+  NYS_TRY(launch_check("ssn_final_kernel"));
+  if (gamma_state) {
+    hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
+    NYS_TRY(launch_check("ssn_store_gamma_kernel"));
+  }
+  return NYS_OK;
+}
+
+template nys_status ssn_prox<double>(const nys_reg_desc&, double, nys_pc, const double*, double*,
+                                     double*, hipStream_t, int*);
+template nys_status ssn_prox<float>(const nys_reg_desc&, double, nys_pc, const float*, float*,
+                                    double*, hipStream_t, int*);
+
+}  // namespace nys

@@ -76,24 +76,6 @@ __global__ __launch_bounds__(256) void lt_kernel(const T* __restrict__ q, int re
   out[o] = s ? s[o] - lam * v : v;
 }
 
-// x = s - lam (t + U cd)   (P^{-1} t = t + U (d . U^T t))
-template <class T>
-__global__ __launch_bounds__(256) void x_from_pinv_kernel(const T* __restrict__ s,
-                                                          const T* __restrict__ t,
-                                                          const T* __restrict__ U,
-                                                          const double* __restrict__ cd,
-                                                          int64_t N, int L, T lam,
-                                                          T* __restrict__ x) {
-  __shared__ T cs[PcMeta::kMaxEll];
-  for (int k = threadIdx.x; k < L; k += blockDim.x) cs[k] = static_cast<T>(cd[k]);
-  __syncthreads();
-  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (n >= N) return;
-  T acc = t[n];
-  for (int k = 0; k < L; ++k) acc += U[static_cast<size_t>(k) * N + n] * cs[k];
-  x[n] = s[n] - lam * acc;
-}
-
 template <class T>
 __device__ __forceinline__ void project_group(int reg, T* v) {
   if (reg == NYS_REG_TV) {
@@ -206,9 +188,7 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
                          static_cast<const T*>(nullptr), T(0), tbuf);
       NYS_TRY(launch_check("lt_kernel"));
       NYS_TRY(pc_coeffs<T>(pc, true, tbuf, 1, cd, st));
-      hipLaunchKernelGGL((x_from_pinv_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, s, tbuf,
-                         pc->U.as<T>(), cd, N, L, static_cast<T>(lam_bar), x);
-      NYS_TRY(launch_check("x_from_pinv_kernel"));
+      NYS_TRY(pc_x_from_pinv<T>(pc, s, tbuf, cd, lam_bar, x, st));
     }
     if (last) break;
     double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
@@ -221,282 +201,6 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
   return NYS_OK;
 }
 
-// ================================================================ SSN (L1)
-// Device state of the Newton iteration (FP64):
-struct SsnState {
-  static constexpr int kGamma = 0;                       // accepted gamma
-  static constexpr int kTry = PcMeta::kMaxEll;           // trial gamma
-  static constexpr int kDelta = 2 * PcMeta::kMaxEll;     // Newton direction
-  static constexpr int kF = 3 * PcMeta::kMaxEll;         // F at gamma
-  static constexpr int kS = 4 * PcMeta::kMaxEll;         // scalars
-  static constexpr int kNF = kS + 0, kT = kS + 1, kDone = kS + 2, kHalv = kS + 3,
-                       kHave = kS + 4, kNeedGram = kS + 5, kTrials = kS + 6, kSteps = kS + 7;
-  static constexpr int kTotal = kS + 16;
-};
-
-// r = s - U g_try; x = soft(r); mask = |r| > lam; partial sums of U^T (x - s)
-// over a chunk of kSsnChunk entries per block.
-constexpr int kSsnChunk = 1024;
-
-template <class T>
-__global__ __launch_bounds__(256) void ssn_eval_kernel(const T* __restrict__ U, const T* __restrict__ s,
-                                                       const double* __restrict__ state, int64_t N,
-                                                       int L, T lam, uint8_t* __restrict__ mask,
-                                                       double* __restrict__ part) {
-  if (state[SsnState::kDone] != 0.0) return;
-  __shared__ T g[PcMeta::kMaxEll];
-  __shared__ T dv[kSsnChunk];
-  __shared__ double red[4][32];
-  for (int k = threadIdx.x; k < L; k += blockDim.x) g[k] = static_cast<T>(state[SsnState::kTry + k]);
-  __syncthreads();
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * kSsnChunk;
-  for (int e = threadIdx.x; e < kSsnChunk; e += 256) {
-    int64_t n = n0 + e;
-    T d = 0;
-    if (n < N) {
-      T r = s[n];
-      for (int k = 0; k < L; ++k) r -= U[static_cast<size_t>(k) * N + n] * g[k];
-      T ar = fabs(r);
-      T xv = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
-      d = xv - s[n];
-      mask[n] = ar > lam ? 1 : 0;
-    }
-    dv[e] = d;
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int k0 = 0; k0 < L; k0 += 32) {
-    T a[32];
-#pragma unroll
-    for (int kk = 0; kk < 32; ++kk) a[kk] = 0;
-    for (int e = threadIdx.x; e < kSsnChunk; e += 256) {
-      int64_t n = n0 + e;
-      if (n >= N) break;
-      T d = dv[e];
-#pragma unroll
-      for (int kk = 0; kk < 32; ++kk)
-        if (k0 + kk < L) a[kk] += U[static_cast<size_t>(k0 + kk) * N + n] * d;
-    }
-#pragma unroll
-    for (int kk = 0; kk < 32; ++kk) {
-      double v = static_cast<double>(a[kk]);
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) red[wv][kk] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 32 && k0 + threadIdx.x < L)
-      part[static_cast<size_t>(blockIdx.x) * L + k0 + threadIdx.x] =
-          red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-    __syncthreads();
-  }
-}
-
-// Reduce the partials to F(g_try) = g_try - e . U^T(x - s), then accept or
-// backtrack; on acceptance test convergence.
-__global__ void ssn_decide_kernel(const double* __restrict__ part, int nchunks, int L,
-                                  const double* __restrict__ meta, double* __restrict__ state,
-                                  double tol, int max_halvings) {
-  if (state[SsnState::kDone] != 0.0) return;
-  __shared__ double Ft[PcMeta::kMaxEll];
-  __shared__ double red[128];
-  const int tid = threadIdx.x;
-  double sq = 0;
-  for (int k = tid; k < L; k += blockDim.x) {
-    double u = 0;
-    for (int c = 0; c < nchunks; ++c) u += part[static_cast<size_t>(c) * L + k];
-    double f = state[SsnState::kTry + k] - meta[PcMeta::kE + k] * u;
-    Ft[k] = f;
-    sq += f * f;
-  }
-  red[tid] = sq;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
-    __syncthreads();
-  }
-  const double nFt = sqrt(red[0]);
-  __syncthreads();
-  if (tid == 0) {
-    state[SsnState::kTrials] += 1.0;
-    const bool have = state[SsnState::kHave] != 0.0;
-    const double nF = state[SsnState::kNF], t = state[SsnState::kT];
-    bool accept = !have || nFt <= (1.0 - 1e-4 * t) * nF || state[SsnState::kHalv] >= max_halvings ||
-                  !isfinite(nFt);
-    state[SsnState::kNeedGram] = 0.0;
-    if (accept) {
-      state[SsnState::kHave] = 1.0;
-      state[SsnState::kNF] = nFt;
-      double gn = 0;
-      for (int k = 0; k < L; ++k) gn += state[SsnState::kTry + k] * state[SsnState::kTry + k];
-      if (nFt <= tol * (1.0 + sqrt(gn)) || !isfinite(nFt)) state[SsnState::kDone] = 1.0;
-      else state[SsnState::kNeedGram] = 1.0;
-    } else {
-      double tn = 0.5 * t;
-      state[SsnState::kT] = tn;
-      state[SsnState::kHalv] += 1.0;
-      for (int k = 0; k < L; ++k)
-        state[SsnState::kTry + k] = state[SsnState::kGamma + k] + tn * state[SsnState::kDelta + k];
-    }
-  }
-  __syncthreads();
-  const bool accepted_now = state[SsnState::kNeedGram] != 0.0 ||
-                            (state[SsnState::kDone] != 0.0);
-  if (accepted_now)
-    for (int k = tid; k < L; k += blockDim.x) {
-      state[SsnState::kGamma + k] = state[SsnState::kTry + k];
-      state[SsnState::kF + k] = Ft[k];
-    }
-}
-
-// Masked Gram partials: sum over active n (mask set by the evaluation of the
-// accepted point) of U[:,n] U[:,n]^T; one 64 x 64 output tile per block.
-template <class T>
-__global__ __launch_bounds__(256) void ssn_gram_kernel(const T* __restrict__ U,
-                                                       const uint8_t* __restrict__ mask,
-                                                       const double* __restrict__ state, int64_t N,
-                                                       int L, double* __restrict__ part) {
-  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
-  const int ti = blockIdx.y, tj = blockIdx.z;
-  if (tj < ti) return;
-  __shared__ T As[32][65];
-  __shared__ T Bs[32][65];
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * kSsnChunk;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0;
-  for (int64_t nb = n0; nb < n0 + kSsnChunk && nb < N; nb += 32) {
-    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-      int c = e / 32, kk = e - c * 32;
-      int64_t n = nb + kk;
-      int ka = ti * 64 + c, kb = tj * 64 + c;
-      bool on = n < N && mask[n];
-      As[kk][c] = (on && ka < L) ? U[static_cast<size_t>(ka) * N + n] : T(0);
-      Bs[kk][c] = (on && kb < L) ? U[static_cast<size_t>(kb) * N + n] : T(0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 32; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[kk][ty * 4 + q];
-        b[q] = Bs[kk][tx * 4 + q];
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
-    }
-    __syncthreads();
-  }
-  const size_t LL = static_cast<size_t>(L) * L;
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int ia = ti * 64 + ty * 4 + p, ib = tj * 64 + tx * 4 + q;
-      if (ia < L && ib < L) {
-        part[blockIdx.x * LL + static_cast<size_t>(ia) * L + ib] = static_cast<double>(acc[p][q]);
-        part[blockIdx.x * LL + static_cast<size_t>(ib) * L + ia] = static_cast<double>(acc[p][q]);
-      }
-    }
-}
-
-__global__ void ssn_gram_reduce_kernel(const double* __restrict__ part, int nchunks, int L,
-                                       const double* __restrict__ state, double* __restrict__ M) {
-  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
-  const size_t LL = static_cast<size_t>(L) * L;
-  for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < LL;
-       e += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    double s = 0;
-    for (int c = 0; c < nchunks; ++c) s += part[c * LL + e];
-    M[e] = s;
-  }
-}
-
-// Newton direction: (I + diag(e) M) delta = -F by Gaussian elimination with
-// partial pivoting (one workgroup, FP64); then g_try = gamma + delta.
-__global__ __launch_bounds__(256) void ssn_solve_kernel(double* __restrict__ M, int L,
-                                                        const double* __restrict__ meta,
-                                                        double* __restrict__ state) {
-  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int W = L + 1;   // augmented matrix in M's buffer would alias; use LDS rows
-  __shared__ int piv;
-  // build J in place: J = I + diag(e) M, augmented column b = -F in a separate array
-  extern __shared__ double rhs_s[];
-  for (size_t e = tid; e < static_cast<size_t>(L) * L; e += nt) {
-    int i = static_cast<int>(e / L), j = static_cast<int>(e % L);
-    M[e] = (i == j ? 1.0 : 0.0) + meta[PcMeta::kE + i] * M[e];
-  }
-  for (int i = tid; i < L; i += nt) rhs_s[i] = -state[SsnState::kF + i];
-  __syncthreads();
-  (void)W;
-  for (int col = 0; col < L; ++col) {
-    if (tid == 0) {
-      int p = col;
-      double best = fabs(M[col * L + col]);
-      for (int r = col + 1; r < L; ++r) {
-        double v = fabs(M[r * L + col]);
-        if (v > best) { best = v; p = r; }
-      }
-      piv = p;
-    }
-    __syncthreads();
-    const int p = piv;
-    if (p != col) {
-      for (int j = tid; j < L; j += nt) {
-        double t = M[col * L + j]; M[col * L + j] = M[p * L + j]; M[p * L + j] = t;
-      }
-      if (tid == 0) { double t = rhs_s[col]; rhs_s[col] = rhs_s[p]; rhs_s[p] = t; }
-    }
-    __syncthreads();
-    const double d = M[col * L + col];
-    for (int r = col + 1 + tid; r < L; r += nt) {
-      double f = M[r * L + col] / d;
-      if (f != 0.0) {
-        for (int j = col; j < L; ++j) M[r * L + j] -= f * M[col * L + j];
-        rhs_s[r] -= f * rhs_s[col];
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    for (int i = L - 1; i >= 0; --i) {
-      double s = rhs_s[i];
-      for (int j = i + 1; j < L; ++j) s -= M[i * L + j] * rhs_s[j];
-      rhs_s[i] = s / M[i * L + i];
-    }
-    state[SsnState::kT] = 1.0;
-    state[SsnState::kHalv] = 0.0;
-    state[SsnState::kSteps] += 1.0;
-  }
-  __syncthreads();
-  for (int k = tid; k < L; k += nt) {
-    state[SsnState::kDelta + k] = rhs_s[k];
-    state[SsnState::kTry + k] = state[SsnState::kGamma + k] + rhs_s[k];
-  }
-}
-
-// x = soft(s - U gamma)
-template <class T>
-__global__ __launch_bounds__(256) void ssn_final_kernel(const T* __restrict__ U, const T* __restrict__ s,
-                                                        const double* __restrict__ state, int64_t N,
-                                                        int L, T lam, T* __restrict__ x) {
-  __shared__ T g[PcMeta::kMaxEll];
-  for (int k = threadIdx.x; k < L; k += blockDim.x) g[k] = static_cast<T>(state[SsnState::kGamma + k]);
-  __syncthreads();
-  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (n >= N) return;
-  T r = s[n];
-  for (int k = 0; k < L; ++k) r -= U[static_cast<size_t>(k) * N + n] * g[k];
-  T ar = fabs(r);
-  x[n] = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
-}
-
 template <class T>
 __global__ void soft_kernel(const T* __restrict__ s, T lam, int64_t N, T* __restrict__ x) {
   const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -504,82 +208,6 @@ __global__ void soft_kernel(const T* __restrict__ s, T lam, int64_t N, T* __rest
   T r = s[n];
   T ar = fabs(r);
   x[n] = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
-}
-
-// Initialise the Newton state from the warm start gamma (g_try = gamma).
-__global__ void ssn_init_kernel(double* __restrict__ state, const double* __restrict__ gamma0, int L) {
-  for (int k = threadIdx.x; k < L; k += blockDim.x) {
-    double g = gamma0 ? gamma0[k] : 0.0;
-    state[SsnState::kGamma + k] = g;
-    state[SsnState::kTry + k] = g;
-    state[SsnState::kDelta + k] = 0.0;
-  }
-  if (threadIdx.x == 0) {
-    state[SsnState::kNF] = 0; state[SsnState::kT] = 1; state[SsnState::kDone] = 0;
-    state[SsnState::kHalv] = 0; state[SsnState::kHave] = 0; state[SsnState::kNeedGram] = 0;
-    state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0;
-  }
-}
-
-__global__ void ssn_store_gamma_kernel(const double* __restrict__ state, double* __restrict__ gamma, int L) {
-  for (int k = threadIdx.x; k < L; k += blockDim.x) gamma[k] = state[SsnState::kGamma + k];
-}
-
-template <class T>
-static nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                           double* gamma_state, hipStream_t st) {
-  const int64_t N = pc->N;
-  const int L = static_cast<int>(pc->ell);
-  const int nchunks = static_cast<int>(cdiv(N, kSsnChunk));
-  const size_t LL = static_cast<size_t>(L) * L;
-  size_t need = SsnState::kTotal + static_cast<size_t>(nchunks) * L + nchunks * LL + LL;
-  NYS_TRY(pc->work2.ensure(sizeof(double) * need + N + 256));
-  double* state = pc->work2.as<double>();
-  double* part = state + SsnState::kTotal;
-  double* gpart = part + static_cast<size_t>(nchunks) * L;
-  double* M = gpart + nchunks * LL;
-  uint8_t* mask = reinterpret_cast<uint8_t*>(M + LL);
-  const T lam = static_cast<T>(lam_bar);
-  const double tol = reg.newton_tol > 0 ? reg.newton_tol : (sizeof(T) == 8 ? 1e-12 : 1e-6);
-  const int max_trials = reg.max_newton > 0 ? reg.max_newton : 60;
-  hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
-  NYS_TRY(launch_check("ssn_init_kernel"));
-  const T* U = pc->U.as<T>();
-  const double* meta = pc->meta.as<double>();
-  const int ntile = static_cast<int>(cdiv(L, 64));
-  for (int trial = 0; trial < max_trials; ++trial) {
-    hipLaunchKernelGGL((ssn_eval_kernel<T>), dim3(nchunks), dim3(256), 0, st, U, s, state, N, L,
-                       lam, mask, part);
-    NYS_TRY(launch_check("ssn_eval_kernel"));
-    hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(128), 0, st, part, nchunks, L, meta,
-                       state, tol, 30);
-    NYS_TRY(launch_check("ssn_decide_kernel"));
-    hipLaunchKernelGGL((ssn_gram_kernel<T>), dim3(nchunks, ntile, ntile), dim3(256), 0, st, U,
-                       mask, state, N, L, gpart);
-    NYS_TRY(launch_check("ssn_gram_kernel"));
-    hipLaunchKernelGGL(ssn_gram_reduce_kernel, dim3(cdiv(LL, 256)), dim3(256), 0, st, gpart,
-                       nchunks, L, state, M);
-    NYS_TRY(launch_check("ssn_gram_reduce_kernel"));
-    hipLaunchKernelGGL(ssn_solve_kernel, dim3(1), dim3(256), sizeof(double) * L, st, M, L, meta,
-                       state);
-    NYS_TRY(launch_check("ssn_solve_kernel"));
-    // read the done flag every other trial so a converged solve stops early
-    if ((trial & 1) == 1) {
-      double done = 0;
-      NYS_CHECK_HIP(hipMemcpyAsync(&done, state + SsnState::kDone, sizeof(double),
-                                   hipMemcpyDeviceToHost, st));
-      NYS_CHECK_HIP(hipStreamSynchronize(st));
-      if (done != 0.0) break;
-    }
-  }
-  hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, U, s, state, N,
-                     L, lam, x);
-  NYS_TRY(launch_check("ssn_final_kernel"));
-  if (gamma_state) {
-    hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
-    NYS_TRY(launch_check("ssn_store_gamma_kernel"));
-  }
-  return NYS_OK;
 }
 
 template <class T>
