@@ -116,7 +116,7 @@ constexpr int kT2P = 68;  // pitch of the horizontally up-correlated rows
 template <class S, int K>
 __global__ __launch_bounds__(256) void sketch_sr_sep_kernel(const S* __restrict__ omega,
                                                             S* __restrict__ Y, SepPsf f,
-                                                            int n1, int n2) {
+                                                            int n1, int n2, int64_t ncols) {
   using Gm = SrGeom<K>;
   static_assert(Gm::TR0 >= 0 && Gm::TR0 + Gm::NTR <= kR, "region too small");
   static_assert(Gm::TR0 + 2 * (Gm::NG * Gm::G - 1) + K <= kR, "phase 1 reads past the region");
@@ -126,8 +126,18 @@ __global__ __launch_bounds__(256) void sketch_sr_sep_kernel(const S* __restrict_
   __shared__ __align__(16) float A[kR * kXP];   // region; later the decimated samples Z
   __shared__ __align__(16) float B[kR * kTP];   // row-filtered T; later T2
   const int tid = threadIdx.x;
-  const int P0 = blockIdx.y * kT, Q0 = blockIdx.x * kT;
-  const size_t colbase = static_cast<size_t>(blockIdx.z) * n1 * n2;
+  // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+  // XCDs, so workgroup id i runs on XCD i % 8.  Each XCD takes a contiguous
+  // run of (column, tile row, tile column) work items, so neighbouring tiles,
+  // whose halos overlap, share one L2.
+  const int tiles_x = n2 / kT, tiles_y = n1 / kT;
+  const int total = tiles_x * tiles_y * static_cast<int>(ncols);
+  const int per_xcd = (total + 7) / 8;
+  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (w >= total) return;
+  const int col = w / (tiles_x * tiles_y), t = w - col * tiles_x * tiles_y;
+  const int P0 = (t / tiles_x) * kT, Q0 = (t % tiles_x) * kT;
+  const size_t colbase = static_cast<size_t>(col) * n1 * n2;
   const S* src = omega + colbase;
 
   // ---- phase 0: 10 x 10 Haar blocks of the region, synthesised in registers
@@ -384,9 +394,10 @@ static void launch_sep(const nys_op_s* op, const S* omega, S* Y, int64_t ell, hi
     f.gu[a] = a < K ? static_cast<float>(op->sep_u[K - 1 - a]) : 0.f;
     f.gv[a] = a < K ? static_cast<float>(op->sep_v[K - 1 - a]) : 0.f;
   }
-  dim3 grid(d.n2 / kT, d.n1 / kT, static_cast<unsigned>(ell));
-  hipLaunchKernelGGL((sketch_sr_sep_kernel<S, K>), grid, dim3(256), 0, st, omega, Y, f, d.n1,
-                     d.n2);
+  const int64_t total = static_cast<int64_t>(d.n2 / kT) * (d.n1 / kT) * ell;
+  const unsigned blocks = static_cast<unsigned>((total + 7) / 8 * 8);
+  hipLaunchKernelGGL((sketch_sr_sep_kernel<S, K>), dim3(blocks), dim3(256), 0, st, omega, Y, f,
+                     d.n1, d.n2, ell);
 }
 
 template <class S>
