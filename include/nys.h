@@ -229,6 +229,45 @@ nys_status solve(const nys_problem* prob, nys_pc pc, nys_dtype dt,
                  const nys_solve_opts* opts, void* x_out, double* costs,
                  double* info, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Unrolled, differentiable WAPG (Alg. 3) with the P-weighted TV prox (dual
+ * FISTA of eqs. (17)-(22), warm-started across outer iterations): a fixed
+ * number n_outer of outer and n_inner of inner iterations, a fixed step
+ * alpha, u^1 = x^1 = 0, Q = 0.  The forward keeps u_k and the dual Q_k of
+ * every outer iteration in the workspace; the backward recomputes one outer
+ * iteration at a time from them and returns the exact vector-Jacobian
+ * products with respect to the measurements y and the weight lambda (the
+ * projection onto the dual ball is differentiated where it is smooth).
+ * Operator, preconditioner (U, Lambda depend on A only) and alpha are
+ * constants of the map.  Least-squares data term; reg TV or TV_ANISO.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_outer;   /* unrolled outer iterations K */
+  int32_t n_inner;   /* dual iterations per outer iteration */
+  double alpha;      /* step, > 0 */
+} nys_unroll_opts;
+
+/* Bytes of device workspace for `batch` instances (host out). */
+nys_status nys_unrolled_workspace(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                                  const nys_unroll_opts* opts, int32_t batch, size_t* bytes);
+
+/* x[b] (N values) = K unrolled iterations on y[b] (M values) with weight
+ * lambda[b] (host array), b < batch; prob->y and prob->lambda are ignored.
+ * ws: device workspace of ws_bytes >= nys_unrolled_workspace(...), kept for
+ * the backward. */
+nys_status unrolled_forward(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                            const nys_unroll_opts* opts, int32_t batch, const void* y,
+                            const double* lambda, void* x, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Given bar_x = dLoss/dx (batch x N), writes bar_y = dLoss/dy (batch x M,
+ * device) and bar_lambda (host, batch doubles; the stream is synchronised).
+ * Same arguments and workspace as the forward call. */
+nys_status unrolled_backward(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                             const nys_unroll_opts* opts, int32_t batch, const void* y,
+                             const double* lambda, const void* bar_x, void* bar_y,
+                             double* bar_lambda, void* ws, size_t ws_bytes, void* stream);
+
 /* F(x) = f(x) + lambda g(x) for one column, FP64 accumulation, written to the
  * device double `cost`. */
 nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void* x,

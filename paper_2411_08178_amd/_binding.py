@@ -56,6 +56,10 @@ class SolveOpts(C.Structure):
                 ("warm_start", C.c_int32), ("use_graph", C.c_int32)]
 
 
+class UnrollOpts(C.Structure):
+    _fields_ = [("n_outer", C.c_int32), ("n_inner", C.c_int32), ("alpha", C.c_double)]
+
+
 _lib = None
 
 
@@ -86,6 +90,12 @@ def lib():
             "solve": [C.POINTER(Problem), vp, i32, C.POINTER(SolveOpts), vp, vp,
                       C.POINTER(dbl), vp],
             "nys_cost": [C.POINTER(Problem), i32, vp, vp, vp],
+            "nys_unrolled_workspace": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32,
+                                       C.POINTER(C.c_size_t)],
+            "unrolled_forward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
+                                 C.POINTER(dbl), vp, vp, C.c_size_t, vp],
+            "unrolled_backward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
+                                  C.POINTER(dbl), vp, vp, C.POINTER(dbl), vp, C.c_size_t, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -314,3 +324,90 @@ def nys_cost(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, x: torch.T
     out = torch.empty(1, dtype=torch.float64, device=x.device)
     _check(lib().nys_cost(C.byref(p), _dt(x), _ptr(x), _ptr(out), _stream()))
     return out
+
+
+# ---------------------------------------------------------------- autograd
+class OpForwardFn(torch.autograd.Function):
+    """y = A x; the backward applies the hand-written adjoint kernel A^T."""
+
+    @staticmethod
+    def forward(ctx, x, op):
+        ctx.op = op
+        return op_forward(op, x.contiguous())
+
+    @staticmethod
+    def backward(ctx, gy):
+        return op_adjoint(ctx.op, gy.contiguous()), None
+
+
+class OpAdjointFn(torch.autograd.Function):
+    """x = A^T y; the backward applies A."""
+
+    @staticmethod
+    def forward(ctx, y, op):
+        ctx.op = op
+        return op_adjoint(op, y.contiguous())
+
+    @staticmethod
+    def backward(ctx, gx):
+        return op_forward(ctx.op, gx.contiguous()), None
+
+
+class PinvFn(torch.autograd.Function):
+    """P^{-1} v; P^{-1} is symmetric, so the backward applies it again."""
+
+    @staticmethod
+    def forward(ctx, v, pc):
+        ctx.pc = pc
+        return nys_apply(pc, v.contiguous(), inverse=True)
+
+    @staticmethod
+    def backward(ctx, g):
+        return nys_apply(ctx.pc, g.contiguous(), inverse=True), None
+
+
+class UnrolledWAPGFn(torch.autograd.Function):
+    """K unrolled WAPG iterations with the P-weighted TV prox (`unrolled_forward`
+    / `unrolled_backward` of the C ABI); gradients w.r.t. y and lambda."""
+
+    @staticmethod
+    def forward(ctx, y, lam, op, reg, pc, n_outer, n_inner, alpha):
+        batch = y.shape[0]
+        y = y.contiguous()
+        lam_h = lam.detach().to("cpu", torch.float64).contiguous()
+        p = _problem(op, y, reg, 1.0, LOSS_LS, 0.0)
+        o = UnrollOpts(n_outer, n_inner, alpha)
+        nb = C.c_size_t()
+        _check(lib().nys_unrolled_workspace(C.byref(p), pc.handle if pc else None, _dt(y),
+                                            C.byref(o), batch, C.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=y.device)
+        x = torch.empty((batch, op.n1, op.n2), dtype=y.dtype, device=y.device)
+        lam_p = lam_h.numpy().ctypes.data_as(C.POINTER(C.c_double))
+        _check(lib().unrolled_forward(C.byref(p), pc.handle if pc else None, _dt(y), C.byref(o),
+                                      batch, _ptr(y), lam_p, _ptr(x), _ptr(ws), nb.value,
+                                      _stream()))
+        ctx.save_for_backward(y)
+        ctx.args = (op, reg, pc, o, lam_h, ws, lam.dtype, lam.device)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (y,) = ctx.saved_tensors
+        op, reg, pc, o, lam_h, ws, ldt, ldev = ctx.args
+        batch = y.shape[0]
+        p = _problem(op, y, reg, 1.0, LOSS_LS, 0.0)
+        gy = torch.empty_like(y)
+        glam = (C.c_double * batch)()
+        lam_p = lam_h.numpy().ctypes.data_as(C.POINTER(C.c_double))
+        _check(lib().unrolled_backward(C.byref(p), pc.handle if pc else None, _dt(y), C.byref(o),
+                                       batch, _ptr(y), lam_p, _ptr(gx.contiguous()), _ptr(gy),
+                                       glam, _ptr(ws), ws.numel(), _stream()))
+        gl = torch.tensor(list(glam), dtype=ldt, device=ldev)
+        return gy, gl, None, None, None, None, None, None
+
+
+def unrolled_wapg(op: Operator, y: torch.Tensor, lam: torch.Tensor, reg: RegDesc,
+                  pc: Optional[Preconditioner], n_outer: int, n_inner: int, alpha: float):
+    """x (batch, n1, n2) = unrolled WAPG on y (batch, *meas_shape) with weights
+    lam (batch,); differentiable w.r.t. y and lam."""
+    return UnrolledWAPGFn.apply(y, lam, op, reg, pc, n_outer, n_inner, alpha)
