@@ -60,6 +60,7 @@ struct PcMeta {
 // Weighted prox (prox.hip).  state as in prox_weighted.
 template <class T>
 nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    void* state, hipStream_t st, double* scratch_dev = nullptr);
+                    void* state, hipStream_t st, void* work = nullptr);
+template <class T> size_t prox_ws_bytes(const nys_reg_desc& reg);
 
 }  // namespace nys

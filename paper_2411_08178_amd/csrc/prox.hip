@@ -211,8 +211,15 @@ __global__ void soft_kernel(const T* __restrict__ s, T lam, int64_t N, T* __rest
 }
 
 template <class T>
+size_t prox_ws_bytes(const nys_reg_desc& reg) {
+  const size_t N = static_cast<size_t>(reg.n1) * reg.n2;
+  const int nch = reg.kind == NYS_REG_HS1 ? 3 : 2;
+  return sizeof(double) * PcMeta::kMaxEll + sizeof(T) * (static_cast<size_t>(nch) * N * 2 + N) + 256;
+}
+
+template <class T>
 nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    void* state, hipStream_t st, double* scratch_dev) {
+                    void* state, hipStream_t st, void* work) {
   const int64_t N = static_cast<int64_t>(reg.n1) * reg.n2;
   if (reg.kind == NYS_REG_L1) {
     if (!pc) {
@@ -223,28 +230,28 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     return ssn_prox<T>(reg, lam_bar, pc, s, x, static_cast<double*>(state), st);
   }
   const int nch = reg.kind == NYS_REG_HS1 ? 3 : 2;
-  // work: Q (if no state), R, t, cd
+  // work: [cd: kMaxEll doubles | R | Q (when no state) | t]; the caller's
+  // buffer of prox_ws_bytes, else a per-thread one
   static thread_local DevBuf fallback;
-  nys_status r = NYS_OK;
-  DevBuf& buf = fallback;
-  // layout: [cd: kMaxEll doubles | R | Q (when no state) | t]
-  size_t need = sizeof(double) * PcMeta::kMaxEll +
-                sizeof(T) * (static_cast<size_t>(nch) * N * (state ? 1 : 2) + N);
-  NYS_TRY(buf.ensure(need));
-  double* cd = buf.as<double>();
-  T* base = reinterpret_cast<T*>(cd + PcMeta::kMaxEll);
-  T* Q = state ? static_cast<T*>(state) : base + static_cast<size_t>(nch) * N;
-  T* R = base;
-  T* tbuf = base + static_cast<size_t>(nch) * N * (state ? 1 : 2);
+  char* base = static_cast<char*>(work);
+  if (!base) {
+    NYS_TRY(fallback.ensure(prox_ws_bytes<T>(reg)));
+    base = static_cast<char*>(fallback.p);
+  }
+  double* cd = reinterpret_cast<double*>(base);
+  T* R = reinterpret_cast<T*>(cd + PcMeta::kMaxEll);
+  T* Q = state ? static_cast<T*>(state) : R + static_cast<size_t>(nch) * N;
+  T* tbuf = R + static_cast<size_t>(nch) * N * 2;
   if (!state) NYS_TRY(fill_zero<T>(Q, static_cast<size_t>(nch) * N, st));
-  r = dual_prox<T>(reg, lam_bar, pc, s, x, Q, R, tbuf, cd, st);
-  return r;
+  return dual_prox<T>(reg, lam_bar, pc, s, x, Q, R, tbuf, cd, st);
 }
 
 template nys_status prox_run<double>(const nys_reg_desc&, double, nys_pc, const double*, double*,
-                                     void*, hipStream_t, double*);
+                                     void*, hipStream_t, void*);
 template nys_status prox_run<float>(const nys_reg_desc&, double, nys_pc, const float*, float*,
-                                    void*, hipStream_t, double*);
+                                    void*, hipStream_t, void*);
+template size_t prox_ws_bytes<double>(const nys_reg_desc&);
+template size_t prox_ws_bytes<float>(const nys_reg_desc&);
 template nys_status fill_zero<double>(double*, size_t, hipStream_t);
 template nys_status fill_zero<float>(float*, size_t, hipStream_t);
 

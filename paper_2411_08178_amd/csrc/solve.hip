@@ -148,16 +148,44 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const T* __restrict__ a, int
 
 constexpr int kRedBlocks = 256;
 
-struct SolveBufs {
-  void* meas;     // M
-  void* g;        // N
-  void* s;        // N
-  void* xn;       // N
-  void* u;        // N
-  void* v;        // N (power method)
-  void* state;    // prox warm start
-  double* part;   // 2 * kRedBlocks
-  double* norms;  // power-method norms
+// Workspace of one solve, carved from one device buffer:
+// meas (M), g, s, xn, u, v (N each), state (TV/HS dual or SSN gamma),
+// part (2 kRedBlocks doubles), norms (8 doubles), prox work.
+template <class T>
+struct SolveWs {
+  T *meas, *g, *s, *xn, *u, *v;
+  void* state;
+  double *part, *norms;
+  void* prox;
+  static int nch(const nys_reg_desc& r) { return r.kind == NYS_REG_HS1 ? 3 : (r.kind == NYS_REG_L1 ? 0 : 2); }
+  static size_t state_bytes(const nys_problem& p, nys_pc pc) {
+    const int c = nch(p.reg);
+    return c ? sizeof(T) * c * p.op->N : (pc ? sizeof(double) * pc->ell : 0);
+  }
+  static size_t bytes(const nys_problem& p, nys_pc pc) {
+    auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    return r256(sizeof(T) * (p.op->M + 5 * p.op->N)) + r256(state_bytes(p, pc)) +
+           r256(sizeof(double) * (2 * kRedBlocks + 8)) + prox_ws_bytes<T>(p.reg) + 256;
+  }
+  SolveWs(const nys_problem& p, nys_pc pc, void* base_v) {
+    auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    char* base = static_cast<char*>(base_v);
+    const int64_t N = p.op->N, M = p.op->M;
+    meas = reinterpret_cast<T*>(base);
+    g = meas + M;
+    s = g + N;
+    xn = s + N;
+    u = xn + N;
+    v = u + N;
+    char* after = base + r256(sizeof(T) * (M + 5 * N));
+    const size_t sb = state_bytes(p, pc);
+    state = sb ? after : nullptr;
+    after += r256(sb);
+    part = reinterpret_cast<double*>(after);
+    norms = part + 2 * kRedBlocks;
+    after += r256(sizeof(double) * (2 * kRedBlocks + 8));
+    prox = after;
+  }
 };
 
 template <class T>
@@ -204,82 +232,95 @@ static nys_status power_step(const nys_problem& p, nys_pc pc, T* v, T* g, T* mea
   return launch_check("scale_by_norm_kernel");
 }
 
+// Power method (no host synchronisation): the estimate of
+// lambda_max(P^{-1} A^T A) is left in w.norms[0] on the device.
+template <class T>
+nys_status power_enqueue(const nys_problem& p, nys_pc pc, const T* v0, int iters, void* wsb,
+                         hipStream_t st) {
+  SolveWs<T> w(p, pc, wsb);
+  const int64_t N = p.op->N;
+  NYS_CHECK_HIP(hipMemcpyAsync(w.g, v0, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL((sumsq_kernel<T>), dim3(kRedBlocks), dim3(256), 0, st, w.g, N, w.part);
+  NYS_TRY(launch_check("sumsq_kernel"));
+  hipLaunchKernelGGL((scale_by_norm_kernel<T>), dim3(std::min<int64_t>(cdiv(N, 256), 1024)),
+                     dim3(256), 0, st, w.g, w.v, N, w.part, kRedBlocks, w.norms);
+  NYS_TRY(launch_check("scale_by_norm_kernel"));
+  for (int it = 0; it < iters; ++it)
+    NYS_TRY(power_step<T>(p, pc, w.v, w.g, w.meas, w.part, w.norms, st));
+  return NYS_OK;
+}
+
+// WAPG outer iterations with a known step (no host synchronisation for the
+// TV / HS priors once pc->pinv_norm_cache is set).
+template <class T>
+nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_iter,
+                        int warm_start, T* x, double* costs, void* wsb, hipStream_t st) {
+  SolveWs<T> w(p, pc, wsb);
+  nys_op op = p.op;
+  const int64_t N = op->N, M = op->M;
+  const int nch = SolveWs<T>::nch(p.reg);
+  const double lam_bar = alpha * p.lambda;
+  NYS_TRY(fill_zero<T>(x, N, st));
+  NYS_TRY(fill_zero<T>(w.u, N, st));
+  if (nch) NYS_TRY(fill_zero<T>(static_cast<T*>(w.state), static_cast<size_t>(nch) * N, st));
+  else if (w.state) NYS_TRY(fill_zero<double>(static_cast<double*>(w.state), pc->ell, st));
+  double t_prev = 1.0;
+  for (int k = 0; k < max_iter; ++k) {
+    // s = u - alpha P^{-1} grad f(u)
+    NYS_TRY(op_fwd<T>(op, w.u, w.meas, 1, st));
+    hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, w.meas,
+                       static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
+    NYS_TRY(launch_check("residual_kernel"));
+    NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
+    if (pc) NYS_TRY(pc_apply<T>(pc, true, w.g, w.g, 1, st));
+    hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
+                       static_cast<T>(alpha), N, w.s);
+    NYS_TRY(launch_check("step_kernel"));
+    // x+ = prox^P_{alpha lambda g}(s)
+    NYS_TRY(prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? w.state : nullptr, st, w.prox));
+    // momentum
+    const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
+    const double beta = (t_prev - 1.0) / t;
+    hipLaunchKernelGGL((momentum_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.xn, x, w.u,
+                       static_cast<T>(beta), N);
+    NYS_TRY(launch_check("momentum_kernel"));
+    t_prev = t;
+    if (costs) NYS_TRY(cost_impl<T>(p, x, costs + k, w.meas, w.part, st));
+  }
+  return NYS_OK;
+}
+
+template nys_status power_enqueue<float>(const nys_problem&, nys_pc, const float*, int, void*, hipStream_t);
+template nys_status power_enqueue<double>(const nys_problem&, nys_pc, const double*, int, void*, hipStream_t);
+template nys_status wapg_enqueue<float>(const nys_problem&, nys_pc, double, int, int, float*, double*, void*, hipStream_t);
+template nys_status wapg_enqueue<double>(const nys_problem&, nys_pc, double, int, int, double*, double*, void*, hipStream_t);
+
+template <class T>
+size_t solve_ws_bytes(const nys_problem& p, nys_pc pc) { return SolveWs<T>::bytes(p, pc); }
+template size_t solve_ws_bytes<float>(const nys_problem&, nys_pc);
+template size_t solve_ws_bytes<double>(const nys_problem&, nys_pc);
+
 template <class T>
 static nys_status solve_impl(const nys_problem& p, nys_pc pc, const nys_solve_opts& o, T* x,
                              double* costs, double* info, hipStream_t st) {
-  nys_op op = p.op;
-  const int64_t N = op->N, M = op->M;
-  const int nch = p.reg.kind == NYS_REG_HS1 ? 3 : (p.reg.kind == NYS_REG_L1 ? 0 : 2);
-  size_t state_bytes = nch ? sizeof(T) * nch * N : (pc ? sizeof(double) * pc->ell : 0);
-  // workspace: meas, g, s, xn, u, v, state, part, norms
-  size_t bytes = sizeof(T) * (M + 5 * N) + 256 + state_bytes + 256 +
-                 sizeof(double) * (2 * kRedBlocks + 8);
   static thread_local DevBuf ws;
-  NYS_TRY(ws.ensure(bytes + 256));
-  char* base = static_cast<char*>(ws.p);
-  T* meas = reinterpret_cast<T*>(base);
-  T* g = meas + M;
-  T* s = g + N;
-  T* xn = s + N;
-  T* u = xn + N;
-  T* v = u + N;
-  // align the FP64 / state region that follows the T arrays to 256 bytes
-  char* after = reinterpret_cast<char*>(
-      (reinterpret_cast<uintptr_t>(v + N) + 255) & ~static_cast<uintptr_t>(255));
-  void* state = state_bytes ? after : nullptr;
-  double* part = reinterpret_cast<double*>(after + ((state_bytes + 255) / 256) * 256);
-  double* norms = part + 2 * kRedBlocks;
-
+  NYS_TRY(ws.ensure(SolveWs<T>::bytes(p, pc)));
+  SolveWs<T> w(p, pc, ws.p);
   const double curv = p.loss == NYS_LOSS_HUBER ? 1.0 / p.delta : 1.0;
   double alpha = o.alpha;
   double Lest = 0.0;
   if (!(alpha > 0)) {
     NYS_REQUIRE(o.power_v0 && o.power_iters > 0, "solve: power_v0 / power_iters needed when alpha <= 0");
-    // v = v0 / ||v0||
-    NYS_CHECK_HIP(hipMemcpyAsync(g, o.power_v0, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL((sumsq_kernel<T>), dim3(kRedBlocks), dim3(256), 0, st, g, N, part);
-    NYS_TRY(launch_check("sumsq_kernel"));
-    hipLaunchKernelGGL((scale_by_norm_kernel<T>), dim3(std::min<int64_t>(cdiv(N, 256), 1024)),
-                       dim3(256), 0, st, g, v, N, part, kRedBlocks, norms);
-    NYS_TRY(launch_check("scale_by_norm_kernel"));
-    for (int it = 0; it < o.power_iters; ++it)
-      NYS_TRY(power_step<T>(p, pc, v, g, meas, part, norms, st));
+    NYS_TRY(power_enqueue<T>(p, pc, static_cast<const T*>(o.power_v0), o.power_iters, ws.p, st));
     double lam = 0;
-    NYS_CHECK_HIP(hipMemcpyAsync(&lam, norms, sizeof(double), hipMemcpyDeviceToHost, st));
+    NYS_CHECK_HIP(hipMemcpyAsync(&lam, w.norms, sizeof(double), hipMemcpyDeviceToHost, st));
     NYS_CHECK_HIP(hipStreamSynchronize(st));
     Lest = curv * lam;
     const double safety = o.safety > 0 ? o.safety : 1.01;
     NYS_REQUIRE(Lest > 0 && std::isfinite(Lest), "solve: power method gave L = %g", Lest);
     alpha = 1.0 / (safety * Lest);
   }
-  const double lam_bar = alpha * p.lambda;
-  NYS_TRY(fill_zero<T>(x, N, st));
-  NYS_TRY(fill_zero<T>(u, N, st));
-  if (nch) NYS_TRY(fill_zero<T>(static_cast<T*>(state), static_cast<size_t>(nch) * N, st));
-  else if (state) NYS_TRY(fill_zero<double>(static_cast<double*>(state), pc->ell, st));
-  double t_prev = 1.0;
-  for (int k = 0; k < o.max_iter; ++k) {
-    // s = u - alpha P^{-1} grad f(u)
-    NYS_TRY(op_fwd<T>(op, u, meas, 1, st));
-    hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, meas,
-                       static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
-    NYS_TRY(launch_check("residual_kernel"));
-    NYS_TRY(op_adj<T>(op, meas, g, 1, st));
-    if (pc) NYS_TRY(pc_apply<T>(pc, true, g, g, 1, st));
-    hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, u, g,
-                       static_cast<T>(alpha), N, s);
-    NYS_TRY(launch_check("step_kernel"));
-    // x+ = prox^P_{alpha lambda g}(s)
-    NYS_TRY(prox_run<T>(p.reg, lam_bar, pc, s, xn, o.warm_start ? state : nullptr, st));
-    // momentum
-    const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
-    const double beta = (t_prev - 1.0) / t;
-    hipLaunchKernelGGL((momentum_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, xn, x, u,
-                       static_cast<T>(beta), N);
-    NYS_TRY(launch_check("momentum_kernel"));
-    t_prev = t;
-    if (costs) NYS_TRY(cost_impl<T>(p, x, costs + k, meas, part, st));
-  }
+  NYS_TRY(wapg_enqueue<T>(p, pc, alpha, o.max_iter, o.warm_start, x, costs, ws.p, st));
   if (info) {
     NYS_CHECK_HIP(hipStreamSynchronize(st));
     info[0] = alpha;
