@@ -268,6 +268,77 @@ nys_status unrolled_backward(const nys_problem* prob, nys_pc pc, nys_dtype dt,
                              const double* lambda, const void* bar_x, void* bar_y,
                              double* bar_lambda, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched reconstruction: many periodic-blur problems of different sizes
+ * solved together, every step of every instance in shared launches that are
+ * captured once into a HIP graph.  Instance i solves eq. (4) with
+ * f = 1/2 ||h_i * x - y_i||^2 and lambda_i g(x), g = TV, anisotropic TV or
+ * HS1 (one kind for the batch), by WAPG (Alg. 3) from x = u = 0 with the
+ * P-weighted prox of the dual iterations (eqs. (17)-(22)).  With
+ * precondition = 1, P is the Nystrom preconditioner of eq. (6) built from the
+ * sketch Y = A^T A Omega (Alg. 1, step 2) and the shifted factorisation
+ * (Alg. 1, steps 3-7); with precondition = 0, P = I (plain APG).  The step is
+ * 1 / (safety L) with L from power_iters power-method steps on P^{-1} A^T A
+ * (the constant of eq. (15)).  Images, sketches and iterates are FP32, the
+ * factorisation and all reductions FP64.
+ *
+ * batch_solve_create checks the items, allocates every buffer of the batch,
+ * times the stencil tile heights (tune = 1; the table is kept per process),
+ * and captures the pipeline into a graph; it synchronises `stream`.  The graph
+ * keeps the item pointers: y, omega, v0, x and costs must stay valid and may
+ * be refilled between runs.  batch_solve_run enqueues one graph launch on
+ * `stream`; runs of one plan must not overlap.
+ * ------------------------------------------------------------------------- */
+typedef struct nys_batch_s* nys_batch;
+
+typedef struct {
+  int32_t n1, n2;         /* image rows and columns; n1 * n2 a multiple of 4 */
+  int32_t psf_k;          /* PSF size, odd, 1..31 */
+  const double* psf;      /* host, psf_k x psf_k row-major, centre (k-1)/2,
+                             separable (rank 1, e.g. Gaussian); copied */
+  int32_t ell;            /* sketch size 1..64 (ignored when precondition = 0) */
+  double lambda;          /* regularisation weight, >= 0 */
+  const float* y;         /* n1 x n2 measurements */
+  const float* omega;     /* ell x n1 x n2 test images, 16-byte aligned */
+  const float* v0;        /* n1 x n2 power-method start (not all zero) */
+  float* x;               /* n1 x n2 reconstruction (written by each run) */
+  double* costs;          /* max_iter FP64 costs F(x_k), or NULL */
+} nys_batch_item;
+
+typedef struct {
+  int32_t reg;            /* NYS_REG_TV, NYS_REG_TV_ANISO or NYS_REG_HS1 */
+  int32_t max_iter;       /* outer WAPG iterations */
+  int32_t n_inner;        /* dual iterations per prox */
+  int32_t power_iters;    /* >= 1 */
+  int32_t precondition;   /* 1: Nystrom P; 0: P = I */
+  int32_t warm_start;     /* 1: dual variable kept across outer iterations */
+  int32_t nu_mode, tail;  /* shift and tail rules as in nys_factor_opts */
+  double mu;              /* < 0: mu = nu */
+  double safety;          /* <= 0: 1.01 */
+  int32_t tune;           /* 1: run the tile autotuner */
+} nys_batch_opts;
+
+nys_status batch_solve_create(const nys_batch_item* items, int32_t count,
+                              const nys_batch_opts* opts, nys_batch* out, void* stream);
+nys_status batch_solve_run(nys_batch b, void* stream);
+/* Host out[6] for instance i after a run (synchronises `stream`): alpha, L,
+ * ||P^{-1}||, nu, factorisation status (nys_status), k_eff. */
+nys_status batch_solve_info(nys_batch b, int32_t i, double* out, void* stream);
+/* Host shat[ell_i]: the Nystrom eigenvalue estimates of instance i. */
+nys_status batch_solve_shat(nys_batch b, int32_t i, double* shat, void* stream);
+/* Device views of instance i's sketch Y (ell x N) and U (ell columns of
+ * pitch *ldu); NULL without a preconditioner.  Owned by the plan. */
+nys_status batch_solve_buffers(nys_batch b, int32_t i, const float** Y, const float** U,
+                               int64_t* ldu);
+/* Copies instance i's sketch Y (what = 0) or U (what = 1), ell x N compact,
+ * into dst (device, ell * N floats) on `stream`. */
+nys_status batch_solve_copy(nys_batch b, int32_t i, int32_t what, float* dst, void* stream);
+/* Tile table of the plan's stencil classes: row taps, column taps, tile rows
+ * (host arrays of `cap` entries, NULL allowed); *count = number of classes. */
+nys_status batch_solve_tiles(nys_batch b, int32_t* nt_r, int32_t* nt_c, int32_t* ty,
+                             int32_t cap, int32_t* count);
+void batch_solve_destroy(nys_batch b);
+
 /* F(x) = f(x) + lambda g(x) for one column, FP64 accumulation, written to the
  * device double `cost`. */
 nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void* x,

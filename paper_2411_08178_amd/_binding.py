@@ -60,6 +60,20 @@ class UnrollOpts(C.Structure):
     _fields_ = [("n_outer", C.c_int32), ("n_inner", C.c_int32), ("alpha", C.c_double)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("psf_k", C.c_int32),
+                ("psf", C.POINTER(C.c_double)), ("ell", C.c_int32), ("lam", C.c_double),
+                ("y", C.c_void_p), ("omega", C.c_void_p), ("v0", C.c_void_p),
+                ("x", C.c_void_p), ("costs", C.c_void_p)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("reg", C.c_int32), ("max_iter", C.c_int32), ("n_inner", C.c_int32),
+                ("power_iters", C.c_int32), ("precondition", C.c_int32),
+                ("warm_start", C.c_int32), ("nu_mode", C.c_int32), ("tail", C.c_int32),
+                ("mu", C.c_double), ("safety", C.c_double), ("tune", C.c_int32)]
+
+
 _lib = None
 
 
@@ -96,6 +110,15 @@ def lib():
                                  C.POINTER(dbl), vp, vp, C.c_size_t, vp],
             "unrolled_backward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
                                   C.POINTER(dbl), vp, vp, C.POINTER(dbl), vp, C.c_size_t, vp],
+            "batch_solve_create": [C.POINTER(BatchItem), i32, C.POINTER(BatchOpts),
+                                   C.POINTER(vp), vp],
+            "batch_solve_run": [vp, vp],
+            "batch_solve_info": [vp, i32, C.POINTER(dbl), vp],
+            "batch_solve_shat": [vp, i32, C.POINTER(dbl), vp],
+            "batch_solve_buffers": [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64)],
+            "batch_solve_copy": [vp, i32, i32, vp, vp],
+            "batch_solve_tiles": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), i32,
+                                  C.POINTER(i32)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -105,6 +128,8 @@ def lib():
         L.nys_op_destroy.restype = None
         L.nys_pc_destroy.argtypes = [vp]
         L.nys_pc_destroy.restype = None
+        L.batch_solve_destroy.argtypes = [vp]
+        L.batch_solve_destroy.restype = None
         L.nys_last_error.restype = C.c_char_p
         L.nys_version.restype = C.c_char_p
         _lib = L
@@ -411,3 +436,86 @@ def unrolled_wapg(op: Operator, y: torch.Tensor, lam: torch.Tensor, reg: RegDesc
     """x (batch, n1, n2) = unrolled WAPG on y (batch, *meas_shape) with weights
     lam (batch,); differentiable w.r.t. y and lam."""
     return UnrolledWAPGFn.apply(y, lam, op, reg, pc, n_outer, n_inner, alpha)
+
+
+class BatchSolver:
+    """Plan of many periodic-blur reconstructions solved in one graph launch.
+
+    items: list of dicts with keys psf (k x k numpy float64, separable),
+    y (n1 x n2 float32 CUDA tensor), lam, v0 (n1 x n2 float32), and, when
+    precondition is true, ell and omega (ell x n1 x n2 float32).  Outputs
+    x[i] (float32) and, with record_costs, costs[i] (float64, max_iter).
+    The plan keeps references to every tensor it reads or writes.
+    """
+
+    def __init__(self, items, reg: int = REG_TV, max_iter: int = 100, n_inner: int = 20,
+                 power_iters: int = 100, precondition: bool = True, warm_start: bool = True,
+                 nu_mode: int = 0, tail: int = 0, mu: float = -1.0, safety: float = 1.01,
+                 tune: bool = True, record_costs: bool = False):
+        self.handle = None
+        self._keep = []
+        self.x, self.costs = [], []
+        arr = (BatchItem * len(items))()
+        for i, it in enumerate(items):
+            y = it["y"]
+            n1, n2 = y.shape
+            psf = np.ascontiguousarray(it["psf"], dtype=np.float64)
+            x = torch.empty_like(y)
+            c = (torch.zeros(max_iter, dtype=torch.float64, device=y.device)
+                 if record_costs else None)
+            om = it.get("omega") if precondition else None
+            self._keep += [psf, y, it["v0"], x, c, om]
+            self.x.append(x)
+            self.costs.append(c)
+            arr[i].n1, arr[i].n2 = n1, n2
+            arr[i].psf_k = psf.shape[0]
+            arr[i].psf = psf.ctypes.data_as(C.POINTER(C.c_double))
+            arr[i].ell = int(it.get("ell", 0)) if precondition else 0
+            arr[i].lam = float(it["lam"])
+            arr[i].y = _ptr(y)
+            arr[i].omega = _ptr(om)
+            arr[i].v0 = _ptr(it["v0"])
+            arr[i].x = _ptr(x)
+            arr[i].costs = _ptr(c)
+        o = BatchOpts(reg, max_iter, n_inner, power_iters, int(precondition), int(warm_start),
+                      nu_mode, tail, mu, safety, int(tune))
+        h = C.c_void_p()
+        _check(lib().batch_solve_create(arr, len(items), C.byref(o), C.byref(h), _stream()))
+        self.handle = h
+        self.count = len(items)
+
+    def run(self):
+        _check(lib().batch_solve_run(self.handle, _stream()))
+        return self.x
+
+    def info(self, i: int):
+        out = (C.c_double * 6)()
+        _check(lib().batch_solve_info(self.handle, i, out, _stream()))
+        return dict(alpha=out[0], L=out[1], pinv_norm=out[2], nu=out[3], status=int(out[4]),
+                    k_eff=int(out[5]))
+
+    def shat(self, i: int, ell: int):
+        out = (C.c_double * ell)()
+        _check(lib().batch_solve_shat(self.handle, i, out, _stream()))
+        return np.array(out[:], dtype=np.float64)
+
+    def sketch(self, i: int, n1: int, n2: int, ell: int):
+        """(Y, U) of instance i copied out: ell x n1 x n2 and ell x N, float32."""
+        dev = self.x[i].device
+        Y = torch.empty(ell, n1, n2, dtype=torch.float32, device=dev)
+        U = torch.empty(ell, n1 * n2, dtype=torch.float32, device=dev)
+        _check(lib().batch_solve_copy(self.handle, i, 0, _ptr(Y), _stream()))
+        _check(lib().batch_solve_copy(self.handle, i, 1, _ptr(U), _stream()))
+        return Y, U
+
+    def tiles(self):
+        cap = 64
+        a, b, c = (C.c_int32 * cap)(), (C.c_int32 * cap)(), (C.c_int32 * cap)()
+        n = C.c_int32()
+        _check(lib().batch_solve_tiles(self.handle, a, b, c, cap, C.byref(n)))
+        return [(a[i], b[i], c[i]) for i in range(min(n.value, cap))]
+
+    def __del__(self):
+        if self.handle is not None and _lib is not None:
+            _lib.batch_solve_destroy(self.handle)
+            self.handle = None

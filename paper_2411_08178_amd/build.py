@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnys.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["ops.hip", "sketch_sr.hip", "factor.hip", "pinv.hip", "prox.hip", "solve.hip", "unrolled.hip"]
+SOURCES = ["ops.hip", "sketch_sr.hip", "factor.hip", "pinv.hip", "prox.hip", "solve.hip", "unrolled.hip",
+           "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,1029 @@
+// Many periodic-blur reconstructions of different sizes solved together.
+//
+// Each instance solves eq. (4) with f = 1/2 ||h * x - y||^2 and a TV / HS1
+// prior by WAPG (Alg. 3) preconditioned with P of eq. (6), which is built
+// from the sketch Y = A^T A Omega (Alg. 1, step 2) and the shifted Nystrom
+// factorisation (Alg. 1, steps 3-7); the step follows the power-method bound
+// of L_f^P (the constant of eq. (15)).  Every launch covers all instances:
+//   * A^T A of a periodic blur is the periodic correlation with the
+//     autocorrelation of the PSF, separable for a separable PSF.  One
+//     persistent kernel applies it (and H, H^T) to every (instance, column,
+//     tile) item, pulling items from eight work queues, one per XCD, each
+//     holding a contiguous run of tiles so that neighbouring tiles share that
+//     XCD's L2;
+//   * the Gram, the FP64 factorisation (one workgroup per instance) and U
+//     are batched over segment tables;
+//   * the WAPG loop, its P^{-1} applications and the inner dual iterations
+//     of the P-weighted prox run as batched launches.
+// The whole pipeline is captured once into a HIP graph; a run is one graph
+// launch.  Tile heights of the stencil kernel come from a timing autotuner
+// run when the plan is created.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "batch.hpp"
+#include "common.hpp"
+#include "internal.hpp"
+#include "stencil.hpp"
+
+namespace nys {
+
+template <class T> nys_status fill_zero(T* p, size_t n, hipStream_t st);
+
+// ================================================================ stencil
+constexpr int kStW = 64;          // tile columns: one wave64 row
+constexpr int kStMaxTaps = 61;    // autocorrelation of a 31-tap PSF factor
+constexpr int kQueues = 8;        // one work queue per XCD
+
+// out[c][i][j] = sum_{a,b} tr[a] tc[b] in[c][(i + lo_r + a) mod n1][(j + lo_c + b) mod n2]
+//                (- sub[i][j] when sub != null); columns cstride elements apart.
+struct StTask {
+  const float* in;
+  float* out;
+  const float* sub;
+  int64_t cstride;
+  int32_t n1, n2;
+  int32_t lo_r, nt_r, lo_c, nt_c;
+  int32_t taps;     // offset of nt_r row taps, then nt_c column taps
+  int32_t ty;       // tile rows
+};
+
+struct StItem {
+  int32_t task, col, y0, x0;
+};
+
+__host__ __device__ inline int st_lds_floats(int ty, int nt_r, int nt_c) {
+  const int hr = ty + nt_r - 1;
+  return hr * (kStW + nt_c - 1) + hr * kStW;
+}
+
+__device__ __forceinline__ int wrap_idx(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Persistent: block b serves queue b % 8 first (its XCD), then the others.
+// Each queue is a contiguous range of items; ctr[q] counts tickets of queue
+// q, ctr[8] counts blocks that finished, and the last block to finish resets
+// all counters, so consecutive launches on one stream reuse them.
+__global__ __launch_bounds__(256) void bstencil_kernel(const StTask* __restrict__ tasks,
+                                                       const StItem* __restrict__ items,
+                                                       const int* __restrict__ qbase,
+                                                       const float* __restrict__ taps,
+                                                       int* __restrict__ ctr) {
+  extern __shared__ float sm[];
+  __shared__ float s_tr[kStMaxTaps], s_tc[kStMaxTaps];
+  __shared__ int s_ticket;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int home = blockIdx.x % kQueues;
+  for (int qi = 0; qi < kQueues; ++qi) {
+    const int q = (home + qi) % kQueues;
+    const int q0 = qbase[q], qn = qbase[q + 1] - q0;
+    for (;;) {
+      if (tid == 0) s_ticket = atomicAdd(&ctr[q], 1);
+      __syncthreads();
+      const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+      __syncthreads();
+      if (t >= qn) break;
+      const StItem I = items[q0 + t];
+      const StTask T = tasks[I.task];
+      if (tid < T.nt_r) s_tr[tid] = taps[T.taps + tid];
+      else if (tid < T.nt_r + T.nt_c) s_tc[tid - T.nt_r] = taps[T.taps + tid];
+      const int rows = min(T.ty, T.n1 - I.y0);
+      const int hr = rows + T.nt_r - 1, wc = kStW + T.nt_c - 1;
+      float* tin = sm;
+      float* mid = sm + hr * wc;
+      const float* src = T.in + static_cast<int64_t>(I.col) * T.cstride;
+      const int gj0 = wrap_idx(I.x0 + T.lo_c + lane, T.n2);
+      const bool two = lane + kStW < wc;
+      const int gj1 = two ? wrap_idx(I.x0 + T.lo_c + lane + kStW, T.n2) : 0;
+      for (int r = wave; r < hr; r += 4) {
+        const float* row = src + static_cast<int64_t>(wrap_idx(I.y0 + T.lo_r + r, T.n1)) * T.n2;
+        tin[r * wc + lane] = row[gj0];
+        if (two) tin[r * wc + lane + kStW] = row[gj1];
+      }
+      __syncthreads();
+      for (int r = wave; r < hr; r += 4) {
+        const float* p = tin + r * wc + lane;
+        float acc = 0.f;
+        for (int b = 0; b < T.nt_c; ++b) acc = fmaf(s_tc[b], p[b], acc);
+        mid[r * kStW + lane] = acc;
+      }
+      __syncthreads();
+      const int j = I.x0 + lane;
+      float* dst = T.out + static_cast<int64_t>(I.col) * T.cstride;
+      for (int r = wave; r < rows; r += 4) {
+        const float* p = mid + r * kStW + lane;
+        float acc = 0.f;
+        for (int a = 0; a < T.nt_r; ++a) acc = fmaf(s_tr[a], p[a * kStW], acc);
+        if (j < T.n2) {
+          const int64_t o = static_cast<int64_t>(I.y0 + r) * T.n2 + j;
+          if (T.sub) acc -= T.sub[o];
+          dst[o] = acc;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0 && atomicAdd(&ctr[kQueues], 1) == static_cast<int>(gridDim.x) - 1) {
+    for (int q = 0; q < kQueues; ++q) atomicExch(&ctr[q], 0);
+    atomicExch(&ctr[kQueues], 0);
+  }
+}
+
+// ================================================================ pixel kernels
+// All over 1024-pixel blocks (256 threads x 4) of a segment table.
+#define BSEG_PROLOGUE                                              \
+  const BSeg& sg = seg[seg_find(seg, nseg, blockIdx.x)];          \
+  const BDesc& D = d[sg.inst];                                    \
+  const int64_t lb = blockIdx.x - sg.first;                       \
+  const int64_t base = lb * 1024;
+
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// D.part[lb] = sum of squares of the block (source f[fsrc], or v0 if fsrc < 0)
+__global__ __launch_bounds__(256) void bsumsq_kernel(const BDesc* __restrict__ d,
+                                                     const BSeg* __restrict__ seg, int nseg,
+                                                     int fsrc) {
+  __shared__ double red[256];
+  BSEG_PROLOGUE
+  const float* src = fsrc >= 0 ? D.f[fsrc] : D.v0;
+  double s = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t n = base + q * 256 + threadIdx.x;
+    if (n < D.N) {
+      const double v = src[n];
+      s += v * v;
+    }
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) D.part[lb] = s;
+}
+
+// f[fdst] = src / ||src||, scal[kNorm] = ||src|| (every block sums the
+// instance's partials in the same order)
+__global__ __launch_bounds__(256) void bnormalize_kernel(const BDesc* __restrict__ d,
+                                                         const BSeg* __restrict__ seg, int nseg,
+                                                         int fsrc, int fdst) {
+  __shared__ double nrm;
+  BSEG_PROLOGUE
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int64_t b = 0; b < sg.nblk; ++b) s += D.part[b];
+    nrm = sqrt(s);
+    if (lb == 0) D.scal[BScal::kNorm] = nrm;
+  }
+  __syncthreads();
+  const float inv = static_cast<float>(nrm > 0 ? 1.0 / nrm : 0.0);
+  const float* src = fsrc >= 0 ? D.f[fsrc] : D.v0;
+  float* dst = D.f[fdst];
+  for (int q = 0; q < 4; ++q) {
+    const int64_t n = base + q * 256 + threadIdx.x;
+    if (n < D.N) dst[n] = src[n] * inv;
+  }
+}
+
+// Step sizes from the power-method estimate (curvature 1 for the LS loss):
+// alpha = 1 / (safety L), lam_bar = alpha lambda, dual step
+// 1 / (lam_bar ||L||^2 ||P^{-1}||).
+__global__ void bscalars_kernel(const BDesc* __restrict__ d, int n, double safety,
+                                double lnorm2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BDesc& D = d[i];
+  const double L = D.scal[BScal::kNorm];
+  const double alpha = (L > 0 && isfinite(L)) ? 1.0 / (safety * L) : 0.0;
+  double pn = D.ell > 0 ? D.meta[PcMeta::kPinvNorm] : 1.0;
+  if (!(pn >= 1.0) || !isfinite(pn)) pn = 1.0;
+  const double lam_bar = alpha * D.lambda;
+  D.scal[BScal::kL] = L;
+  D.scal[BScal::kAlpha] = alpha;
+  D.scal[BScal::kLamBar] = lam_bar;
+  D.scal[BScal::kPinvNorm] = pn;
+  D.scal[BScal::kDualStep] = lam_bar > 0 ? 1.0 / (lam_bar * lnorm2 * pn) : 0.0;
+}
+
+// f[fout] = L^T f[fq]  (adjoint of the regulariser's map)
+__global__ __launch_bounds__(256) void blt_kernel(const BDesc* __restrict__ d,
+                                                  const BSeg* __restrict__ seg, int nseg, int reg,
+                                                  int fq, int fout) {
+  BSEG_PROLOGUE
+  const float* q = D.f[fq];
+  float* out = D.f[fout];
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = base + k * 256 + threadIdx.x;
+    if (n >= D.N) break;
+    const int i = static_cast<int>(n / D.n2), j = static_cast<int>(n - static_cast<int64_t>(i) * D.n2);
+    out[n] = lt_at(q, reg, i, j, D.n1, D.n2);
+  }
+}
+
+// accelerated projected dual step on every pixel, step = scal[kDualStep]
+__global__ __launch_bounds__(256) void bdual_update_kernel(const BDesc* __restrict__ d,
+                                                           const BSeg* __restrict__ seg, int nseg,
+                                                           int reg, float beta) {
+  BSEG_PROLOGUE
+  const float step = static_cast<float>(D.scal[BScal::kDualStep]);
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = base + k * 256 + threadIdx.x;
+    if (n >= D.N) break;
+    const int i = static_cast<int>(n / D.n2), j = static_cast<int>(n - static_cast<int64_t>(i) * D.n2);
+    dual_update_at<float>(D.f[kFldXN], D.f[kFldQ], D.f[kFldR], reg, i, j, D.n1, D.n2, step, beta);
+  }
+}
+
+// u = x+ + beta (x+ - x); x = x+  (flat over the packed images)
+__global__ __launch_bounds__(256) void bmomentum_kernel(const float* __restrict__ xn,
+                                                        float* __restrict__ x,
+                                                        float* __restrict__ u, float beta,
+                                                        int64_t n) {
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const float a = xn[e];
+    u[e] = a + beta * (a - x[e]);
+    x[e] = a;
+  }
+}
+
+// D.part[lb] = sum over the block of 1/2 (Hx - y)^2 + lambda g(x)  (Hx in f[kFldW])
+__global__ __launch_bounds__(256) void bcost_partial_kernel(const BDesc* __restrict__ d,
+                                                            const BSeg* __restrict__ seg, int nseg,
+                                                            int term) {
+  __shared__ double red[256];
+  BSEG_PROLOGUE
+  double s = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = base + k * 256 + threadIdx.x;
+    if (n < D.N)
+      s += term_at<float>(D.f[kFldW], D.y, n, kSq, 0.f, D.n1, D.n2) +
+           D.lambda * term_at<float>(D.f[kFldX], nullptr, n, term, 0.f, D.n1, D.n2);
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) D.part[lb] = s;
+}
+
+// costs[k] = sum of the instance's partials (blockIdx.x = segment)
+__global__ void bcost_tail_kernel(const BDesc* __restrict__ d, const BSeg* __restrict__ seg,
+                                  int k) {
+  const BSeg& sg = seg[blockIdx.x];
+  const BDesc& D = d[sg.inst];
+  if (threadIdx.x != 0 || !D.costs) return;
+  double s = 0;
+  for (int64_t b = 0; b < sg.nblk; ++b) s += D.part[b];
+  D.costs[k] = s;
+}
+
+__global__ __launch_bounds__(256) void bcopy_out_kernel(const BDesc* __restrict__ d,
+                                                        const BSeg* __restrict__ seg, int nseg) {
+  BSEG_PROLOGUE
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = base + k * 256 + threadIdx.x;
+    if (n < D.N) D.x_out[n] = D.f[kFldX][n];
+  }
+}
+
+#undef BSEG_PROLOGUE
+
+// ================================================================ autotuner
+// Tile height per (row taps, column taps), chosen by timing the sketch items
+// of that class at every candidate height; shared by the plans of a process.
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, int> g_tile_table;
+constexpr int kTyCandidates[] = {8, 16, 32, 64};
+constexpr int kTyDefault = 32;
+
+}  // namespace nys
+
+using namespace nys;
+
+// ================================================================ plan
+struct nys_batch_s {
+  nys_batch_opts o{};
+  int count = 0;
+  int nch = 2;
+  DevBuf arena;
+  DevBuf tables;
+  int* ctr = nullptr;                        // stencil counters (in tables)
+  std::vector<BDesc> hd;                     // host copy of the descriptors
+  std::vector<int64_t> pix_off;              // packed offsets of the images
+  int64_t P = 0;                             // packed image length
+  BDesc* dd = nullptr;                       // device descriptors
+  BLaunch pix, red, upix, fac, gram;
+  int kgroups = 0;
+  int max_ell = 0;
+  int64_t lds_doubles = 0;
+  int64_t stencil_lds_max = 0;
+  // stencil launches: tasks, items, queue bases, LDS bytes
+  struct St {
+    const StTask* tasks = nullptr;
+    const StItem* items = nullptr;
+    const int* qbase = nullptr;
+    int64_t nitems = 0;
+    size_t lds = 0;
+  } st_sketch, st_phi_v, st_grad, st_aty, st_hx;
+  const float* taps = nullptr;
+  std::vector<std::pair<int, int>> tiles;    // (taps class packed, ty) used
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool have_costs = false;
+};
+
+namespace nys {
+namespace {
+
+// Host builder of one device table region: appends POD arrays, 256-byte aligned.
+struct TableBuilder {
+  std::vector<unsigned char> bytes;
+  template <class T>
+  size_t add(const std::vector<T>& v) {
+    const size_t off = (bytes.size() + 255) / 256 * 256;
+    bytes.resize(off + sizeof(T) * v.size());
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), sizeof(T) * v.size());
+    return off;
+  }
+};
+
+nys_status rank1_psf(const double* psf, int k, std::vector<double>& u, std::vector<double>& v) {
+  int ap = 0, bp = 0;
+  double mx = 0;
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b)
+      if (std::fabs(psf[a * k + b]) > mx) { mx = std::fabs(psf[a * k + b]); ap = a; bp = b; }
+  NYS_REQUIRE(mx > 0, "batch_solve_create: zero PSF");
+  u.assign(k, 0.0);
+  v.assign(k, 0.0);
+  for (int a = 0; a < k; ++a) u[a] = psf[a * k + bp];
+  for (int b = 0; b < k; ++b) v[b] = psf[ap * k + b] / psf[ap * k + bp];
+  double err = 0;
+  for (int a = 0; a < k; ++a)
+    for (int b = 0; b < k; ++b) err = std::fmax(err, std::fabs(psf[a * k + b] - u[a] * v[b]));
+  NYS_REQUIRE(err <= 1e-12 * mx, "batch_solve_create: PSF is not separable (rank-1 residual %g)", err);
+  return NYS_OK;
+}
+
+// r[d + k - 1] = sum_a w[a] w[a + d], d = -(k-1) .. k-1
+std::vector<double> autocorr(const std::vector<double>& w) {
+  const int k = static_cast<int>(w.size());
+  std::vector<double> r(2 * k - 1, 0.0);
+  for (int dd = -(k - 1); dd <= k - 1; ++dd) {
+    double s = 0;
+    for (int a = 0; a < k; ++a)
+      if (a + dd >= 0 && a + dd < k) s += w[a] * w[a + dd];
+    r[dd + k - 1] = s;
+  }
+  return r;
+}
+
+struct TaskSpec {
+  StTask t;
+  int ncols;
+};
+
+// Items of a list of tasks, split into kQueues contiguous queues.
+void build_items(const std::vector<TaskSpec>& ts, std::vector<StItem>& items,
+                 std::vector<int>& qbase) {
+  items.clear();
+  for (size_t i = 0; i < ts.size(); ++i) {
+    const StTask& t = ts[i].t;
+    for (int c = 0; c < ts[i].ncols; ++c)
+      for (int y0 = 0; y0 < t.n1; y0 += t.ty)
+        for (int x0 = 0; x0 < t.n2; x0 += kStW) items.push_back({static_cast<int32_t>(i), c, y0, x0});
+  }
+  qbase.assign(kQueues + 1, 0);
+  const int64_t n = static_cast<int64_t>(items.size());
+  for (int q = 0; q <= kQueues; ++q) qbase[q] = static_cast<int>(n * q / kQueues);
+}
+
+size_t tasks_lds(const std::vector<TaskSpec>& ts) {
+  size_t m = 0;
+  for (const auto& s : ts) m = std::max<size_t>(m, sizeof(float) * st_lds_floats(s.t.ty, s.t.nt_r, s.t.nt_c));
+  return m;
+}
+
+int stencil_grid(size_t lds) {
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t per_cu = 160 * 1024;
+  int bpc = lds > 0 ? static_cast<int>(per_cu / (lds + 1024)) : 8;
+  bpc = std::max(1, std::min(8, bpc));
+  return ncu * bpc;
+}
+
+nys_status stencil_launch(const nys_batch_s::St& s, const float* taps, int* ctr, hipStream_t st) {
+  if (s.nitems == 0) return NYS_OK;
+  hipLaunchKernelGGL(bstencil_kernel, dim3(stencil_grid(s.lds)), dim3(256), s.lds, st, s.tasks,
+                     s.items, s.qbase, taps, ctr);
+  return launch_check("bstencil_kernel");
+}
+
+}  // namespace
+}  // namespace nys
+
+namespace {
+
+using namespace nys;
+
+nys_status plan_destroy(nys_batch_s* b) {
+  if (!b) return NYS_OK;
+  if (b->cs) (void)hipStreamSynchronize(b->cs);
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cs) (void)hipStreamDestroy(b->cs);
+  b->arena.release();
+  b->tables.release();
+  delete b;
+  return NYS_OK;
+}
+
+// Capture the whole pipeline on b->cs.
+nys_status enqueue_all(nys_batch_s* b) {
+  hipStream_t st = b->cs;
+  const nys_batch_opts& o = b->o;
+  const bool pc = o.precondition != 0;
+  const BDesc* d = b->dd;
+  const int nseg = b->pix.nseg;
+  const int reg = o.reg;
+  // ---- sketch and factorisation (Alg. 1)
+  if (pc) {
+    NYS_TRY(stencil_launch(b->st_sketch, b->taps, b->ctr, st));
+    NYS_TRY(batch_factor_enqueue(d, b->gram, b->fac, b->upix, b->kgroups, b->max_ell,
+                                 b->lds_doubles, o.nu_mode, o.tail, o.mu, 6, st));
+  }
+  // ---- power method on P^{-1} A^T A
+  const dim3 pg(static_cast<unsigned>(b->pix.nblk));
+  hipLaunchKernelGGL(bsumsq_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, -1);
+  NYS_TRY(launch_check("bsumsq_kernel"));
+  hipLaunchKernelGGL(bnormalize_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, -1, int(kFldV));
+  NYS_TRY(launch_check("bnormalize_kernel"));
+  for (int it = 0; it < o.power_iters; ++it) {
+    NYS_TRY(stencil_launch(b->st_phi_v, b->taps, b->ctr, st));
+    if (pc) {
+      NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldW, st));
+      NYS_TRY(batch_combine(d, b->pix.seg, nseg, b->pix.nblk, -1, kFldW, kFldW, -1, st));
+    }
+    hipLaunchKernelGGL(bsumsq_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, int(kFldW));
+    NYS_TRY(launch_check("bsumsq_kernel"));
+    hipLaunchKernelGGL(bnormalize_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, int(kFldW),
+                       int(kFldV));
+    NYS_TRY(launch_check("bnormalize_kernel"));
+  }
+  const double safety = o.safety > 0 ? o.safety : 1.01;
+  const double lnorm2 = reg == NYS_REG_HS1 ? 34.0 : 8.0;
+  hipLaunchKernelGGL(bscalars_kernel, dim3(cdiv(b->count, 64)), dim3(64), 0, st, d, b->count,
+                     safety, lnorm2);
+  NYS_TRY(launch_check("bscalars_kernel"));
+  // ---- WAPG (Alg. 3) from x = u = 0, dual variable 0
+  NYS_TRY(stencil_launch(b->st_aty, b->taps, b->ctr, st));
+  const BDesc& d0 = b->hd[0];
+  NYS_TRY(fill_zero<float>(d0.f[kFldX], b->P, st));
+  NYS_TRY(fill_zero<float>(d0.f[kFldU], b->P, st));
+  NYS_TRY(fill_zero<float>(d0.f[kFldQ], static_cast<size_t>(b->nch) * b->P, st));
+  const int term = reg == NYS_REG_TV ? kTV : reg == NYS_REG_TV_ANISO ? kTVAniso : kHS1;
+  double t_prev = 1.0;
+  for (int k = 0; k < o.max_iter; ++k) {
+    // s = u - alpha P^{-1} A^T (A u - y), with A^T A u - A^T y from one stencil pass
+    NYS_TRY(stencil_launch(b->st_grad, b->taps, b->ctr, st));
+    if (pc) NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldG, st));
+    NYS_TRY(batch_combine(d, b->pix.seg, nseg, b->pix.nblk, kFldU, kFldG, kFldS, BScal::kAlpha, st));
+    // x+ = prox^P_{lam_bar g}(s): accelerated projected gradient on the dual
+    if (!o.warm_start) NYS_TRY(fill_zero<float>(d0.f[kFldQ], static_cast<size_t>(b->nch) * b->P, st));
+    NYS_CHECK_HIP(hipMemcpyAsync(d0.f[kFldR], d0.f[kFldQ], sizeof(float) * b->nch * b->P,
+                                 hipMemcpyDeviceToDevice, st));
+    double tau = 1.0;
+    for (int it = 0; it <= o.n_inner; ++it) {
+      const bool last = it == o.n_inner;
+      hipLaunchKernelGGL(blt_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg,
+                         int(last ? kFldQ : kFldR), int(kFldT));
+      NYS_TRY(launch_check("blt_kernel"));
+      if (pc) NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldT, st));
+      NYS_TRY(batch_combine(d, b->pix.seg, nseg, b->pix.nblk, kFldS, kFldT, kFldXN, BScal::kLamBar, st));
+      if (last) break;
+      const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
+      const double beta = (tau - 1.0) / tau_n;
+      hipLaunchKernelGGL(bdual_update_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg,
+                         static_cast<float>(beta));
+      NYS_TRY(launch_check("bdual_update_kernel"));
+      tau = tau_n;
+    }
+    const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
+    const double beta = (t_prev - 1.0) / t;
+    hipLaunchKernelGGL(bmomentum_kernel, dim3(std::min<int64_t>(cdiv(b->P, 256), 4096)), dim3(256),
+                       0, st, d0.f[kFldXN], d0.f[kFldX], d0.f[kFldU], static_cast<float>(beta), b->P);
+    NYS_TRY(launch_check("bmomentum_kernel"));
+    t_prev = t;
+    if (b->have_costs) {
+      NYS_TRY(stencil_launch(b->st_hx, b->taps, b->ctr, st));
+      hipLaunchKernelGGL(bcost_partial_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, term);
+      NYS_TRY(launch_check("bcost_partial_kernel"));
+      hipLaunchKernelGGL(bcost_tail_kernel, dim3(nseg), dim3(64), 0, st, d, b->pix.seg, k);
+      NYS_TRY(launch_check("bcost_tail_kernel"));
+    }
+  }
+  hipLaunchKernelGGL(bcopy_out_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg);
+  return launch_check("bcopy_out_kernel");
+}
+
+}  // namespace
+
+extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t count,
+                                         const nys_batch_opts* opts, nys_batch* out,
+                                         void* stream) {
+  NYS_REQUIRE(items && opts && out && count >= 1, "batch_solve_create: bad argument");
+  const nys_batch_opts o = *opts;
+  NYS_REQUIRE(o.reg == NYS_REG_TV || o.reg == NYS_REG_TV_ANISO || o.reg == NYS_REG_HS1,
+              "batch_solve_create: reg must be TV, TV_ANISO or HS1");
+  NYS_REQUIRE(o.max_iter >= 0 && o.n_inner >= 0 && o.power_iters >= 1,
+              "batch_solve_create: bad iteration counts");
+  NYS_REQUIRE(o.nu_mode == 0 || o.nu_mode == 1, "batch_solve_create: nu_mode must be 0 or 1");
+  NYS_REQUIRE(o.tail == 0 || o.tail == 1, "batch_solve_create: tail must be 0 or 1");
+  const bool pc = o.precondition != 0;
+  hipStream_t ust = as_stream(stream);
+  auto* b = new nys_batch_s();
+  b->o = o;
+  b->count = count;
+  b->nch = o.reg == NYS_REG_HS1 ? 3 : 2;
+  auto fail = [&](nys_status s) { plan_destroy(b); return s; };
+
+  // ---- per-instance sizes, taps
+  std::vector<double> tap_host;
+  std::vector<int> taps_aa(count), taps_h(count), taps_hf(count), kk(count);
+  b->pix_off.resize(count);
+  int64_t P = 0;
+  int max_ell = 0;
+  for (int i = 0; i < count; ++i) {
+    const nys_batch_item& it = items[i];
+    if (!(it.n1 >= 1 && it.n2 >= 1 && (static_cast<int64_t>(it.n1) * it.n2) % 4 == 0)) {
+      set_error("batch_solve_create: item %d: n1 * n2 must be a positive multiple of 4", i);
+      return fail(NYS_EINVAL);
+    }
+    if (!(it.psf_k >= 1 && it.psf_k <= 31 && it.psf_k % 2 == 1 && it.psf)) {
+      set_error("batch_solve_create: item %d: psf_k must be odd in [1, 31]", i);
+      return fail(NYS_EINVAL);
+    }
+    if (!it.y || !it.v0 || !it.x || !(it.lambda >= 0)) {
+      set_error("batch_solve_create: item %d: y, v0, x and lambda >= 0 are required", i);
+      return fail(NYS_EINVAL);
+    }
+    if (pc && !(it.ell >= 1 && it.ell <= 64 && it.omega &&
+                (reinterpret_cast<uintptr_t>(it.omega) & 15) == 0 &&
+                it.ell <= static_cast<int64_t>(it.n1) * it.n2)) {
+      set_error("batch_solve_create: item %d: ell in [1, 64] and a 16-byte aligned omega are required", i);
+      return fail(NYS_EINVAL);
+    }
+    std::vector<double> u, v;
+    nys_status s = rank1_psf(it.psf, it.psf_k, u, v);
+    if (s != NYS_OK) return fail(s);
+    const int k = it.psf_k;
+    kk[i] = k;
+    // A^T A: correlation with (u * u)(v * v)^T over offsets -(k-1)..(k-1)
+    const std::vector<double> ru = autocorr(u), rv = autocorr(v);
+    taps_aa[i] = static_cast<int>(tap_host.size());
+    tap_host.insert(tap_host.end(), ru.begin(), ru.end());
+    tap_host.insert(tap_host.end(), rv.begin(), rv.end());
+    // H^T: correlation with the PSF (u, v), offsets -c..k-1-c
+    taps_h[i] = static_cast<int>(tap_host.size());
+    tap_host.insert(tap_host.end(), u.begin(), u.end());
+    tap_host.insert(tap_host.end(), v.begin(), v.end());
+    // H: correlation with the flipped PSF
+    taps_hf[i] = static_cast<int>(tap_host.size());
+    tap_host.insert(tap_host.end(), u.rbegin(), u.rend());
+    tap_host.insert(tap_host.end(), v.rbegin(), v.rend());
+    b->pix_off[i] = P;
+    P += (static_cast<int64_t>(it.n1) * it.n2 + 63) / 64 * 64;
+    if (pc) max_ell = std::max(max_ell, it.ell);
+    if (it.costs) b->have_costs = true;
+  }
+  b->P = P;
+
+  // ---- arena layout
+  struct Off { size_t Y, U, meta, G, gpart, fwork, part, cd, scal; };
+  std::vector<Off> off(count);
+  size_t cur = 0;
+  auto take = [&](size_t bytes) { size_t o0 = cur; cur += (bytes + 255) / 256 * 256; return o0; };
+  const size_t fields_off = take(0);
+  cur += 0;
+  size_t field_off[kNumFields];
+  for (int f = 0; f < kNumFields; ++f) {
+    const int ch = (f == kFldQ || f == kFldR) ? b->nch : 1;
+    field_off[f] = take(sizeof(float) * ch * P);
+  }
+  (void)fields_off;
+  std::vector<int64_t> red_nblk(count), red_chunk(count), gram_nblk(count), gram_chunk(count);
+  for (int i = 0; i < count; ++i) {
+    const nys_batch_item& it = items[i];
+    const int64_t N = static_cast<int64_t>(it.n1) * it.n2;
+    const int ell = pc ? it.ell : 0;
+    const int ell_pad = (ell + 15) / 16 * 16;
+    const int64_t ldu = (N + 63) / 64 * 64 + (N >= 16384 ? 96 : 0);
+    // U^T v reduction: <= 256 blocks of >= 1024 pixels, chunk a multiple of 64
+    int64_t nb = std::min<int64_t>(256, std::max<int64_t>(1, (N + 1023) / 1024));
+    int64_t ch = ((N + nb - 1) / nb + 63) / 64 * 64;
+    red_nblk[i] = (N + ch - 1) / ch;
+    red_chunk[i] = ch;
+    // Gram: <= 256 chunks of >= 4096 pixels, chunk a multiple of 32;
+    // 64 x 64 tile pairs of the 2 ell x 2 ell result
+    nb = std::min<int64_t>(256, std::max<int64_t>(1, N / 4096));
+    ch = ((N + nb - 1) / nb + 31) / 32 * 32;
+    gram_nblk[i] = (N + ch - 1) / ch;
+    gram_chunk[i] = ch;
+    const int ntl = (2 * ell + 63) / 64;
+    const int ntri = ntl * (ntl + 1) / 2;
+    const int64_t pblk = (N + 1023) / 1024;
+    Off& q = off[i];
+    q.Y = take(sizeof(float) * ell * N);
+    q.U = take(sizeof(float) * ldu * std::max(ell_pad, 1));
+    q.meta = take(sizeof(double) * PcMeta::kTotal);
+    q.G = take(sizeof(double) * 4 * ell * ell);
+    q.gpart = take(sizeof(double) * gram_nblk[i] * ntri * 4096);
+    q.fwork = take(sizeof(double) * (5 * ell * ell + ell + 1));
+    q.part = take(sizeof(double) * std::max<int64_t>(red_nblk[i] * std::max(ell_pad, 16), pblk));
+    q.cd = take(sizeof(double) * std::max(ell_pad, 16));
+    q.scal = take(sizeof(double) * BScal::kTotal);
+    BDesc D{};
+    D.n1 = it.n1;
+    D.n2 = it.n2;
+    D.N = N;
+    D.ell = ell;
+    D.ell_pad = ell_pad;
+    D.ldu = ldu;
+    D.lambda = it.lambda;
+    b->hd.push_back(D);
+  }
+  {
+    nys_status s = b->arena.ensure(cur + 256);
+    if (s != NYS_OK) return fail(s);
+    if (hipMemsetAsync(b->arena.p, 0, cur, ust) != hipSuccess) {
+      set_error("batch_solve_create: clearing the arena failed");
+      return fail(NYS_EHIP);
+    }
+  }
+  char* A = b->arena.as<char>();
+  for (int i = 0; i < count; ++i) {
+    BDesc& D = b->hd[i];
+    const nys_batch_item& it = items[i];
+    const Off& q = off[i];
+    D.omega = pc ? it.omega : nullptr;
+    D.y = it.y;
+    D.v0 = it.v0;
+    D.Y = reinterpret_cast<float*>(A + q.Y);
+    D.U = reinterpret_cast<float*>(A + q.U);
+    D.meta = reinterpret_cast<double*>(A + q.meta);
+    D.G = reinterpret_cast<double*>(A + q.G);
+    D.gpart = reinterpret_cast<double*>(A + q.gpart);
+    D.fwork = reinterpret_cast<double*>(A + q.fwork);
+    D.part = reinterpret_cast<double*>(A + q.part);
+    D.cd = reinterpret_cast<double*>(A + q.cd);
+    D.scal = reinterpret_cast<double*>(A + q.scal);
+    D.costs = it.costs;
+    D.x_out = it.x;
+    for (int f = 0; f < kNumFields; ++f) {
+      const int ch = (f == kFldQ || f == kFldR) ? b->nch : 1;
+      D.f[f] = reinterpret_cast<float*>(A + field_off[f]) + ch * b->pix_off[i];
+    }
+  }
+
+  // ---- segment tables
+  auto segs = [&](const std::vector<int>& inst, auto nblk_of, auto chunk_of) {
+    std::vector<BSeg> v;
+    int64_t first = 0;
+    for (int i : inst) {
+      BSeg s{};
+      s.first = first;
+      s.nblk = nblk_of(i);
+      s.chunk = chunk_of(i);
+      s.inst = i;
+      v.push_back(s);
+      first += s.nblk;
+    }
+    return std::make_pair(v, first);
+  };
+  std::vector<int> all(count);
+  for (int i = 0; i < count; ++i) all[i] = i;
+  auto pixs = segs(all, [&](int i) { return (b->hd[i].N + 1023) / 1024; }, [](int) { return int64_t(1024); });
+  auto reds = segs(all, [&](int i) { return red_nblk[i]; }, [&](int i) { return red_chunk[i]; });
+  auto upxs = segs(all, [&](int i) { return (b->hd[i].N + 255) / 256; }, [](int) { return int64_t(256); });
+  auto facs = segs(all, [](int) { return int64_t(1); }, [](int) { return int64_t(0); });
+  auto grms = segs(all, [&](int i) { return gram_nblk[i]; }, [&](int i) { return gram_chunk[i]; });
+
+  // ---- stencil tasks (tile heights from the autotuner table)
+  auto ty_for = [&](int nt_r, int nt_c) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto itr = g_tile_table.find({nt_r, nt_c});
+    return itr == g_tile_table.end() ? kTyDefault : itr->second;
+  };
+  auto mk = [&](int i, const float* in, float* outp, const float* sub, int64_t cstride, int ncols,
+                int which) {
+    const BDesc& D = b->hd[i];
+    const int k = kk[i], c = (k - 1) / 2;
+    TaskSpec s{};
+    s.t.in = in;
+    s.t.out = outp;
+    s.t.sub = sub;
+    s.t.cstride = cstride;
+    s.t.n1 = D.n1;
+    s.t.n2 = D.n2;
+    if (which == 0) {           // A^T A
+      s.t.lo_r = -(k - 1); s.t.nt_r = 2 * k - 1; s.t.lo_c = -(k - 1); s.t.nt_c = 2 * k - 1;
+      s.t.taps = taps_aa[i];
+    } else {                    // H^T (which 1) or H (which 2)
+      s.t.lo_r = -c; s.t.nt_r = k; s.t.lo_c = -c; s.t.nt_c = k;
+      s.t.taps = which == 1 ? taps_h[i] : taps_hf[i];
+    }
+    s.t.ty = ty_for(s.t.nt_r, s.t.nt_c);
+    s.ncols = ncols;
+    return s;
+  };
+  std::vector<TaskSpec> t_sketch, t_phi, t_grad, t_aty, t_hx;
+  for (int i = 0; i < count; ++i) {
+    BDesc& D = b->hd[i];
+    if (pc) t_sketch.push_back(mk(i, D.omega, D.Y, nullptr, D.N, D.ell, 0));
+    t_phi.push_back(mk(i, D.f[kFldV], D.f[kFldW], nullptr, D.N, 1, 0));
+    t_grad.push_back(mk(i, D.f[kFldU], D.f[kFldG], D.f[kFldB], D.N, 1, 0));
+    t_aty.push_back(mk(i, D.y, D.f[kFldB], nullptr, D.N, 1, 1));
+    t_hx.push_back(mk(i, D.f[kFldX], D.f[kFldW], nullptr, D.N, 1, 2));
+  }
+  std::vector<float> tapf(tap_host.begin(), tap_host.end());
+
+  // device tables: taps, descriptors, segments, counters, then the stencil
+  // tables (rebuilt after tuning)
+  auto upload_tables = [&](bool with_stencils) -> nys_status {
+    TableBuilder tb;
+    const size_t o_taps = tb.add(tapf);
+    const size_t o_desc = tb.add(b->hd);
+    const size_t o_pix = tb.add(pixs.first);
+    const size_t o_red = tb.add(reds.first);
+    const size_t o_upx = tb.add(upxs.first);
+    const size_t o_fac = tb.add(facs.first);
+    const size_t o_gram = tb.add(grms.first);
+    const size_t o_ctr = tb.add(std::vector<int>(kQueues + 1 + 63, 0));
+    struct StOff { size_t tasks, items, qbase; int64_t n; size_t lds; };
+    std::vector<TaskSpec>* lists[5] = {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx};
+    StOff so[5] = {};
+    if (with_stencils) {
+      for (int l = 0; l < 5; ++l) {
+        std::vector<StTask> tv;
+        for (auto& s : *lists[l]) tv.push_back(s.t);
+        std::vector<StItem> iv;
+        std::vector<int> qb;
+        build_items(*lists[l], iv, qb);
+        so[l].tasks = tb.add(tv);
+        so[l].items = tb.add(iv);
+        so[l].qbase = tb.add(qb);
+        so[l].n = static_cast<int64_t>(iv.size());
+        so[l].lds = tasks_lds(*lists[l]);
+      }
+    }
+    NYS_TRY(b->tables.ensure(tb.bytes.size() + 256));
+    NYS_CHECK_HIP(hipMemcpyAsync(b->tables.p, tb.bytes.data(), tb.bytes.size(),
+                                 hipMemcpyHostToDevice, ust));
+    NYS_CHECK_HIP(hipStreamSynchronize(ust));
+    char* T = b->tables.as<char>();
+    b->taps = reinterpret_cast<const float*>(T + o_taps);
+    b->dd = reinterpret_cast<BDesc*>(T + o_desc);
+    b->pix = {reinterpret_cast<const BSeg*>(T + o_pix), static_cast<int>(pixs.first.size()), pixs.second};
+    b->red = {reinterpret_cast<const BSeg*>(T + o_red), static_cast<int>(reds.first.size()), reds.second};
+    b->upix = {reinterpret_cast<const BSeg*>(T + o_upx), static_cast<int>(upxs.first.size()), upxs.second};
+    b->fac = {reinterpret_cast<const BSeg*>(T + o_fac), pc ? static_cast<int>(facs.first.size()) : 0, facs.second};
+    b->gram = {reinterpret_cast<const BSeg*>(T + o_gram), static_cast<int>(grms.first.size()),
+               grms.second};
+    b->ctr = reinterpret_cast<int*>(T + o_ctr);
+    nys_batch_s::St* sts[5] = {&b->st_sketch, &b->st_phi_v, &b->st_grad, &b->st_aty, &b->st_hx};
+    for (int l = 0; l < 5; ++l) {
+      sts[l]->tasks = reinterpret_cast<const StTask*>(T + so[l].tasks);
+      sts[l]->items = reinterpret_cast<const StItem*>(T + so[l].items);
+      sts[l]->qbase = reinterpret_cast<const int*>(T + so[l].qbase);
+      sts[l]->nitems = with_stencils ? so[l].n : 0;
+      sts[l]->lds = so[l].lds;
+    }
+    return NYS_OK;
+  };
+  {
+    nys_status s = upload_tables(false);
+    if (s != NYS_OK) return fail(s);
+  }
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(bstencil_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          static_cast<int>(sizeof(float) * st_lds_floats(64, kStMaxTaps, kStMaxTaps))) !=
+      hipSuccess) {
+    set_error("batch_solve_create: hipFuncSetAttribute failed");
+    return fail(NYS_EHIP);
+  }
+
+  // ---- autotuner: time every candidate tile height on the sketch items of
+  // each tap class not yet in the table (A^T A columns of the real inputs)
+  if (o.tune && pc) {
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (size_t i = 0; i < t_sketch.size(); ++i)
+      classes[{t_sketch[i].t.nt_r, t_sketch[i].t.nt_c}].push_back(static_cast<int>(i));
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      set_error("batch_solve_create: hipEventCreate failed");
+      return fail(NYS_EHIP);
+    }
+    DevBuf tb;
+    for (auto& cl : classes) {
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tile_table.count(cl.first)) continue;
+      }
+      double best_t = 1e300;
+      int best_ty = kTyDefault;
+      for (int ty : kTyCandidates) {
+        std::vector<TaskSpec> ts;
+        for (int i : cl.second) {
+          TaskSpec s = t_sketch[i];
+          s.t.ty = ty;
+          ts.push_back(s);
+        }
+        std::vector<StTask> tv;
+        for (auto& s : ts) tv.push_back(s.t);
+        std::vector<StItem> iv;
+        std::vector<int> qb;
+        build_items(ts, iv, qb);
+        TableBuilder tbb;
+        const size_t ot = tbb.add(tv), oi = tbb.add(iv), oq = tbb.add(qb);
+        if (tb.ensure(tbb.bytes.size() + 256) != NYS_OK ||
+            hipMemcpyAsync(tb.p, tbb.bytes.data(), tbb.bytes.size(), hipMemcpyHostToDevice, ust) != hipSuccess) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          tb.release();
+          set_error("batch_solve_create: autotuner upload failed");
+          return fail(NYS_EHIP);
+        }
+        nys_batch_s::St s;
+        s.tasks = reinterpret_cast<const StTask*>(tb.as<char>() + ot);
+        s.items = reinterpret_cast<const StItem*>(tb.as<char>() + oi);
+        s.qbase = reinterpret_cast<const int*>(tb.as<char>() + oq);
+        s.nitems = static_cast<int64_t>(iv.size());
+        s.lds = tasks_lds(ts);
+        float ms = 0;
+        nys_status st2 = stencil_launch(s, b->taps, b->ctr, ust);        // warm-up
+        if (st2 == NYS_OK && hipEventRecord(e0, ust) == hipSuccess) {
+          for (int rep = 0; rep < 3 && st2 == NYS_OK; ++rep) st2 = stencil_launch(s, b->taps, b->ctr, ust);
+          if (st2 == NYS_OK && (hipEventRecord(e1, ust) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            st2 = NYS_EHIP;
+        }
+        if (st2 != NYS_OK) {
+          (void)hipStreamSynchronize(ust);
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          tb.release();
+          return fail(st2 == NYS_EHIP ? NYS_EHIP : st2);
+        }
+        if (ms < best_t) { best_t = ms; best_ty = ty; }
+      }
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tile_table[cl.first] = best_ty;
+    }
+    (void)hipStreamSynchronize(ust);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tb.release();
+    // re-derive tile heights from the table
+    for (auto* l : {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx})
+      for (auto& s : *l) s.t.ty = ty_for(s.t.nt_r, s.t.nt_c);
+  }
+  for (auto* l : {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx})
+    for (auto& s : *l) {
+      const int key = s.t.nt_r * 256 + s.t.nt_c;
+      bool seen = false;
+      for (auto& pr : b->tiles) seen |= pr.first == key;
+      if (!seen) b->tiles.push_back({key, s.t.ty});
+    }
+  {
+    nys_status s = upload_tables(true);
+    if (s != NYS_OK) return fail(s);
+  }
+
+  // ---- batched factor: LDS for up to four ell x ell FP64 matrices
+  if (pc) {
+    int dev = 0, maxsh = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const int64_t avail = maxsh > 8192 ? (maxsh - 8192) / 8 : 0;
+    const int64_t want = 4 * static_cast<int64_t>(max_ell) * max_ell;
+    b->lds_doubles = std::min(avail, want);
+    b->kgroups = (max_ell + 31) / 32;
+    b->max_ell = max_ell;
+    nys_status s = batch_factor_prepare(b->lds_doubles * 8);
+    if (s != NYS_OK) return fail(s);
+  }
+
+  // ---- capture the pipeline
+  if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess) {
+    set_error("batch_solve_create: hipStreamCreate failed");
+    return fail(NYS_EHIP);
+  }
+  if (hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    set_error("batch_solve_create: hipStreamBeginCapture failed");
+    return fail(NYS_EHIP);
+  }
+  nys_status es = enqueue_all(b);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(b->cs, &g);
+  if (es != NYS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(es);
+  }
+  if (ee != hipSuccess || !g) {
+    set_error("batch_solve_create: hipStreamEndCapture failed: %s", hipGetErrorString(ee));
+    return fail(NYS_EHIP);
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+    set_error("batch_solve_create: hipGraphInstantiate failed");
+    return fail(NYS_EHIP);
+  }
+  *out = b;
+  return NYS_OK;
+}
+
+extern "C" nys_status batch_solve_run(nys_batch b, void* stream) {
+  NYS_REQUIRE(b && b->exec, "batch_solve_run: bad plan");
+  NYS_CHECK_HIP(hipGraphLaunch(b->exec, as_stream(stream)));
+  return NYS_OK;
+}
+
+extern "C" nys_status batch_solve_info(nys_batch b, int32_t i, double* out, void* stream) {
+  NYS_REQUIRE(b && out && i >= 0 && i < b->count, "batch_solve_info: bad argument");
+  NYS_CHECK_HIP(hipStreamSynchronize(as_stream(stream)));
+  double sc[BScal::kTotal];
+  NYS_CHECK_HIP(hipMemcpy(sc, b->hd[i].scal, sizeof sc, hipMemcpyDeviceToHost));
+  double meta[PcMeta::kTotal] = {};
+  if (b->hd[i].ell > 0)
+    NYS_CHECK_HIP(hipMemcpy(meta, b->hd[i].meta, sizeof meta, hipMemcpyDeviceToHost));
+  out[0] = sc[BScal::kAlpha];
+  out[1] = sc[BScal::kL];
+  out[2] = sc[BScal::kPinvNorm];
+  out[3] = b->hd[i].ell > 0 ? meta[PcMeta::kNu] : 0.0;
+  out[4] = b->hd[i].ell > 0 ? meta[PcMeta::kStatus] : static_cast<double>(NYS_OK);
+  out[5] = b->hd[i].ell > 0 ? meta[PcMeta::kKeff] : 0.0;
+  return NYS_OK;
+}
+
+extern "C" nys_status batch_solve_shat(nys_batch b, int32_t i, double* shat, void* stream) {
+  NYS_REQUIRE(b && shat && i >= 0 && i < b->count && b->hd[i].ell > 0,
+              "batch_solve_shat: bad argument");
+  NYS_CHECK_HIP(hipStreamSynchronize(as_stream(stream)));
+  NYS_CHECK_HIP(hipMemcpy(shat, b->hd[i].meta + PcMeta::kShat, sizeof(double) * b->hd[i].ell,
+                          hipMemcpyDeviceToHost));
+  return NYS_OK;
+}
+
+extern "C" nys_status batch_solve_buffers(nys_batch b, int32_t i, const float** Y, const float** U,
+                                          int64_t* ldu) {
+  NYS_REQUIRE(b && i >= 0 && i < b->count, "batch_solve_buffers: bad argument");
+  if (Y) *Y = b->hd[i].ell > 0 ? b->hd[i].Y : nullptr;
+  if (U) *U = b->hd[i].ell > 0 ? b->hd[i].U : nullptr;
+  if (ldu) *ldu = b->hd[i].ldu;
+  return NYS_OK;
+}
+
+extern "C" nys_status batch_solve_copy(nys_batch b, int32_t i, int32_t what, float* dst,
+                                       void* stream) {
+  NYS_REQUIRE(b && dst && i >= 0 && i < b->count && (what == 0 || what == 1) && b->hd[i].ell > 0,
+              "batch_solve_copy: bad argument");
+  const BDesc& D = b->hd[i];
+  const size_t es = sizeof(float);
+  if (what == 0)
+    NYS_CHECK_HIP(hipMemcpyAsync(dst, D.Y, es * D.N * D.ell, hipMemcpyDeviceToDevice,
+                                 as_stream(stream)));
+  else
+    NYS_CHECK_HIP(hipMemcpy2DAsync(dst, es * D.N, D.U, es * D.ldu, es * D.N, D.ell,
+                                   hipMemcpyDeviceToDevice, as_stream(stream)));
+  return NYS_OK;
+}
+
+extern "C" nys_status batch_solve_tiles(nys_batch b, int32_t* nt_r, int32_t* nt_c, int32_t* ty,
+                                        int32_t cap, int32_t* count) {
+  NYS_REQUIRE(b && count, "batch_solve_tiles: bad argument");
+  const int n = static_cast<int>(b->tiles.size());
+  for (int i = 0; i < n && i < cap; ++i) {
+    if (nt_r) nt_r[i] = b->tiles[i].first / 256;
+    if (nt_c) nt_c[i] = b->tiles[i].first % 256;
+    if (ty) ty[i] = b->tiles[i].second;
+  }
+  *count = n;
+  return NYS_OK;
+}
+
+extern "C" void batch_solve_destroy(nys_batch b) { plan_destroy(b); }

@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "batch.hpp"
 
 namespace nys {
 
@@ -18,17 +19,18 @@ namespace nys {
 // the chunk partials in FP64 in a fixed order.
 constexpr int kGT = 64, kGK = 32;
 
-template <class S, class C>
-__global__ __launch_bounds__(256) void gram_partial_kernel(
-    const S* __restrict__ omega, const S* __restrict__ Y, int64_t N, int ell, int64_t chunk,
-    int ntiles, double* __restrict__ part) {
-  // map blockIdx.y to an upper-triangular tile pair (ti <= tj)
-  int t = blockIdx.y, ti = 0;
+__host__ __device__ inline void tri_pair(int t, int ntiles, int& ti, int& tj) {
+  ti = 0;
   while (t >= ntiles - ti) { t -= ntiles - ti; ++ti; }
-  const int tj = ti + t;
+  tj = ti + t;
+}
+
+template <class S, class C>
+__device__ __forceinline__ void gram_partial_body(const S* __restrict__ omega,
+                                                  const S* __restrict__ Y, int64_t N, int ell,
+                                                  int64_t n0, int64_t n1, int ti, int tj,
+                                                  double* __restrict__ dst) {
   const int m = 2 * ell;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
-  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
   __shared__ C As[kGK][kGT + 1];
   __shared__ C Bs[kGK][kGT + 1];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -68,8 +70,6 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(
     }
     __syncthreads();
   }
-  const int ntri = ntiles * (ntiles + 1) / 2;
-  double* dst = part + (static_cast<size_t>(blockIdx.x) * ntri + blockIdx.y) * kGT * kGT;
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -77,13 +77,45 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(
       dst[(ty * 4 + p) * kGT + tx * 4 + q] = static_cast<double>(acc[p][q]);
 }
 
-__global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks, int ntiles,
-                                   int ell, double* __restrict__ G) {
+template <class S, class C>
+__global__ __launch_bounds__(256) void gram_partial_kernel(
+    const S* __restrict__ omega, const S* __restrict__ Y, int64_t N, int ell, int64_t chunk,
+    int ntiles, double* __restrict__ part) {
+  // blockIdx.y -> upper-triangular tile pair (ti <= tj)
+  int ti, tj;
+  tri_pair(blockIdx.y, ntiles, ti, tj);
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  const int ntri = ntiles * (ntiles + 1) / 2;
+  gram_partial_body<S, C>(omega, Y, N, ell, n0, n1, ti, tj,
+                          part + (static_cast<size_t>(blockIdx.x) * ntri + blockIdx.y) * kGT * kGT);
+}
+
+// Batched FP32 columns with FP64 accumulation: block -> (instance, chunk),
+// blockIdx.y = tile pair (blocks past the instance's pairs exit).
+__global__ __launch_bounds__(256) void bgram_kernel(const BDesc* __restrict__ d,
+                                                    const BSeg* __restrict__ seg, int nseg) {
+  const BSeg& sg = seg[seg_find(seg, nseg, blockIdx.x)];
+  const BDesc& D = d[sg.inst];
+  const int ntiles = (2 * D.ell + kGT - 1) / kGT;
+  const int ntri = ntiles * (ntiles + 1) / 2;
+  if (static_cast<int>(blockIdx.y) >= ntri) return;
+  int ti, tj;
+  tri_pair(blockIdx.y, ntiles, ti, tj);
+  const int64_t lb = blockIdx.x - sg.first;
+  const int64_t n0 = lb * sg.chunk;
+  const int64_t n1 = (n0 + sg.chunk < D.N) ? n0 + sg.chunk : D.N;
+  gram_partial_body<float, double>(D.omega, D.Y, D.N, D.ell, n0, n1, ti, tj,
+                                   D.gpart + (static_cast<size_t>(lb) * ntri + blockIdx.y) * kGT * kGT);
+}
+
+__device__ __forceinline__ void gram_reduce_body(const double* __restrict__ part, int nchunks,
+                                                 int ntiles, int ell, double* __restrict__ G,
+                                                 int64_t e0, int64_t estride) {
   const int ntri = ntiles * (ntiles + 1) / 2;
   const int m = 2 * ell;
   const int64_t total = static_cast<int64_t>(ntri) * kGT * kGT;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  for (int64_t e = e0; e < total; e += estride) {
     int tri = static_cast<int>(e / (kGT * kGT));
     int r = static_cast<int>(e % (kGT * kGT));
     int i = r / kGT, j = r - i * kGT;
@@ -97,6 +129,22 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks,
     G[gi * m + gj] = s;
     G[gj * m + gi] = s;
   }
+}
+
+__global__ void gram_reduce_kernel(const double* __restrict__ part, int nchunks, int ntiles,
+                                   int ell, double* __restrict__ G) {
+  gram_reduce_body(part, nchunks, ntiles, ell, G,
+                   blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x,
+                   static_cast<int64_t>(gridDim.x) * blockDim.x);
+}
+
+// Batched: blockIdx.y = segment of the Gram launch.
+__global__ void bgram_reduce(const BDesc* __restrict__ d, const BSeg* __restrict__ seg) {
+  const BSeg& sg = seg[blockIdx.y];
+  const BDesc& D = d[sg.inst];
+  gram_reduce_body(D.gpart, static_cast<int>(sg.nblk), (2 * D.ell + kGT - 1) / kGT, D.ell, D.G,
+                   blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x,
+                   static_cast<int64_t>(gridDim.x) * blockDim.x);
 }
 
 // ---------------------------------------------------------------- MFMA Gram
@@ -138,10 +186,9 @@ __device__ __forceinline__ uint4 gram_chunk(const S* __restrict__ omega, const S
 // through LDS so that global loads are 128-byte runs of one row (8 lanes per
 // row) instead of 32 rows per instruction; the row pitch is padded by 16 B.
 template <class S, int NRG>
-__global__ __launch_bounds__(256) void gram_mfma_kernel(const S* __restrict__ omega,
-                                                        const S* __restrict__ Y, int64_t N,
-                                                        int ell, int64_t chunk,
-                                                        float* __restrict__ part) {
+__device__ __forceinline__ void gram_mfma_body(const S* __restrict__ omega,
+                                               const S* __restrict__ Y, int64_t N, int ell,
+                                               int64_t n0, int64_t n1, float* __restrict__ dst) {
   using Tl = GramTiles<NRG>;
   constexpr int ROWS = 32 * NRG;
   constexpr int EPC = 16 / sizeof(S);      // elements per 16-byte chunk
@@ -149,8 +196,6 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const S* __restrict__ om
   constexpr int PITCH = 144;               // bytes per LDS row
   __shared__ __align__(16) unsigned char lds[ROWS * PITCH];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
-  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
   const int lr = lane & 31, lh = lane >> 5;
   // loader mapping: thread t handles chunk (row 32 g + t / 8, column t % 8)
   const int ld_row = tid >> 3, ld_col = tid & 7;
@@ -219,7 +264,6 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const S* __restrict__ om
     }
     __syncthreads();
   }
-  float* dst = part + static_cast<size_t>(blockIdx.x) * Tl::NTRI * 1024;
 #pragma unroll
   for (int t = 0; t < Tl::TPW; ++t) {
     const int tile = wave + 4 * t;
@@ -233,13 +277,25 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(const S* __restrict__ om
   }
 }
 
+template <class S, int NRG>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(const S* __restrict__ omega,
+                                                        const S* __restrict__ Y, int64_t N,
+                                                        int ell, int64_t chunk,
+                                                        float* __restrict__ part) {
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  gram_mfma_body<S, NRG>(omega, Y, N, ell, n0, n1,
+                         part + static_cast<size_t>(blockIdx.x) * GramTiles<NRG>::NTRI * 1024);
+}
+
 template <int NRG>
-__global__ __launch_bounds__(256) void gram_mfma_reduce(const float* __restrict__ part, int nblk,
-                                                        int ell, double* __restrict__ G) {
+__device__ __forceinline__ void gram_mfma_reduce_body(const float* __restrict__ part, int nblk,
+                                                 int ell, double* __restrict__ G, int e0,
+                                                 int estride) {
   using Tl = GramTiles<NRG>;
   const int m = 2 * ell;
   const int total = Tl::NTRI * 1024;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+  for (int e = e0; e < total; e += estride) {
     const int tile = e >> 10, r = e & 1023;
     int ti, tj;
     Tl::ij(tile, ti, tj);
@@ -257,6 +313,13 @@ __global__ __launch_bounds__(256) void gram_mfma_reduce(const float* __restrict_
     G[gi * m + gj] = sacc;
     G[gj * m + gi] = sacc;
   }
+}
+
+template <int NRG>
+__global__ __launch_bounds__(256) void gram_mfma_reduce(const float* __restrict__ part, int nblk,
+                                                        int ell, double* __restrict__ G) {
+  gram_mfma_reduce_body<NRG>(part, nblk, ell, G, blockIdx.x * blockDim.x + threadIdx.x,
+                        gridDim.x * blockDim.x);
 }
 
 template <class S, int NRG>
@@ -395,10 +458,9 @@ __device__ int jacobi_sym(double* M, double* V, int L, double* ev, int max_sweep
   return sweeps;
 }
 
-__global__ __launch_bounds__(kFT) void factor_kernel(const double* __restrict__ G, int L,
-                                                     int64_t N, int nu_mode, int tail,
-                                                     double mu_in, int max_esc, FactorWork w,
-                                                     int nlds, double* __restrict__ meta) {
+__device__ void factor_body(const double* __restrict__ G, int L, int64_t N, int nu_mode,
+                            int tail, double mu_in, int max_esc, FactorWork w, int nlds,
+                            double* __restrict__ meta) {
   // L x L matrices: the working matrix S, the Cholesky factor C, the
   // eigenvectors V and the solve output X; the first `nlds` of them live in
   // dynamic LDS, the rest in the global work buffer.
@@ -580,25 +642,54 @@ __global__ __launch_bounds__(kFT) void factor_kernel(const double* __restrict__ 
   }
 }
 
+__global__ __launch_bounds__(kFT) void factor_kernel(const double* __restrict__ G, int L,
+                                                     int64_t N, int nu_mode, int tail,
+                                                     double mu_in, int max_esc, FactorWork w,
+                                                     int nlds, double* __restrict__ meta) {
+  factor_body(G, L, N, nu_mode, tail, mu_in, max_esc, w, nlds, meta);
+}
+
+static __host__ __device__ FactorWork factor_work(double* wb, int L) {
+  const size_t LL = static_cast<size_t>(L) * L;
+  FactorWork w;
+  w.Cg = wb; w.X = wb + LL; w.Mg = wb + 2 * LL; w.V = wb + 3 * LL; w.R = wb + 4 * LL;
+  w.ev = wb + 5 * LL;
+  return w;
+}
+
+// L x L matrices that fit in `lds_doubles` of dynamic LDS (at most 4)
+static __host__ __device__ int factor_nlds(int L, size_t lds_doubles) {
+  const size_t LL = static_cast<size_t>(L) * L;
+  const size_t k = lds_doubles / LL;
+  return static_cast<int>(k < 4 ? k : 4);
+}
+
+// Batched: one workgroup per instance (blockIdx.x = segment).
+__global__ __launch_bounds__(kFT) void bfactor_kernel(const BDesc* __restrict__ d,
+                                                      const BSeg* __restrict__ seg, int nu_mode,
+                                                      int tail, double mu_in, int max_esc,
+                                                      int64_t lds_doubles) {
+  const BDesc& D = d[seg[blockIdx.x].inst];
+  factor_body(D.G, D.ell, D.N, nu_mode, tail, mu_in, max_esc, factor_work(D.fwork, D.ell),
+              factor_nlds(D.ell, static_cast<size_t>(lds_doubles)), D.meta);
+}
+
 // ================================================================ U
 // U[k][n] = sum_j (Y[j][n] + nu Omega[j][n]) R[j][k]; KC outputs per thread.
 constexpr int kUK = 32;
 
 template <class S, class T, class C>
-__global__ __launch_bounds__(256) void form_u_kernel(const S* __restrict__ omega,
-                                                     const S* __restrict__ Y,
-                                                     const double* __restrict__ R,
-                                                     const double* __restrict__ meta, int64_t N,
-                                                     int L, int64_t ldu, T* __restrict__ U) {
+__device__ __forceinline__ void form_u_body(const S* __restrict__ omega, const S* __restrict__ Y,
+                                            const double* __restrict__ R,
+                                            const double* __restrict__ meta, int64_t N, int L,
+                                            int64_t ldu, T* __restrict__ U, int k0, int64_t n) {
   __shared__ C Rs[PcMeta::kMaxEll][kUK];
-  const int k0 = blockIdx.y * kUK;
   for (int e = threadIdx.x; e < L * kUK; e += blockDim.x) {
     int j = e / kUK, kk = e - j * kUK;
     Rs[j][kk] = (k0 + kk < L) ? static_cast<C>(R[j * L + k0 + kk]) : C(0);
   }
   __syncthreads();
   const C nu = static_cast<C>(meta[PcMeta::kNu]);
-  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (n >= N) return;
   C acc[kUK];
 #pragma unroll
@@ -611,6 +702,29 @@ __global__ __launch_bounds__(256) void form_u_kernel(const S* __restrict__ omega
 #pragma unroll
   for (int kk = 0; kk < kUK; ++kk)
     if (k0 + kk < L) U[static_cast<size_t>(k0 + kk) * ldu + n] = static_cast<T>(acc[kk]);
+}
+
+template <class S, class T, class C>
+__global__ __launch_bounds__(256) void form_u_kernel(const S* __restrict__ omega,
+                                                     const S* __restrict__ Y,
+                                                     const double* __restrict__ R,
+                                                     const double* __restrict__ meta, int64_t N,
+                                                     int L, int64_t ldu, T* __restrict__ U) {
+  form_u_body<S, T, C>(omega, Y, R, meta, N, L, ldu, U, blockIdx.y * kUK,
+                       blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x);
+}
+
+// Batched: block -> (instance, 256 pixels), blockIdx.y = group of kUK columns.
+// A failed factorisation leaves R = 0 and therefore U = 0.
+__global__ __launch_bounds__(256) void bform_u_kernel(const BDesc* __restrict__ d,
+                                                      const BSeg* __restrict__ seg, int nseg) {
+  const BSeg& sg = seg[seg_find(seg, nseg, blockIdx.x)];
+  const BDesc& D = d[sg.inst];
+  const int k0 = blockIdx.y * kUK;
+  if (k0 >= D.ell) return;
+  const int64_t n = (blockIdx.x - sg.first) * 256 + threadIdx.x;
+  form_u_body<float, float, float>(D.omega, D.Y, factor_work(D.fwork, D.ell).R, D.meta, D.N,
+                                   D.ell, D.ldu, D.U, k0, n);
 }
 
 template <class S>
@@ -647,12 +761,15 @@ static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
   w.Cg = wb; w.X = wb + LL; w.Mg = wb + 2 * LL; w.V = wb + 3 * LL; w.R = wb + 4 * LL;
   w.ev = wb + 5 * LL;
   using C = typename Io<S>::C;
-  // MFMA path for BF16 / FP32 when every column is a whole number of 16-byte
-  // chunks; the VALU tile kernel otherwise (and for FP64)
+  // BF16 columns: MFMA with FP32 accumulation when every column is a whole
+  // number of 16-byte chunks.  FP32 and FP64 columns: the VALU tile kernel
+  // with FP64 accumulation (products of FP32 values are exact in FP64), since
+  // the Gram route squares the condition number of the sketch.
   bool use_mfma = false;
-  if constexpr (!std::is_same<S, double>::value) use_mfma = (N % (16 / sizeof(S))) == 0;
+  if constexpr (std::is_same<S, uint16_t>::value) use_mfma = (N % (16 / sizeof(S))) == 0;
+  using Acc = typename std::conditional<std::is_same<S, uint16_t>::value, float, double>::type;
   if (!use_mfma) {
-    hipLaunchKernelGGL((gram_partial_kernel<S, C>), dim3(static_cast<unsigned>(nchunks), ntri),
+    hipLaunchKernelGGL((gram_partial_kernel<S, Acc>), dim3(static_cast<unsigned>(nchunks), ntri),
                        dim3(256), 0, st, omega, Y, N, L, chunk, ntiles, part);
     NYS_TRY(launch_check("gram_partial_kernel"));
     hipLaunchKernelGGL(gram_reduce_kernel, dim3(64), dim3(256), 0, st, part,
@@ -687,6 +804,34 @@ static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
                        pc->meta.as<double>(), N, L, pc->ldu, pc->U.as<float>());
   }
   return launch_check("form_u_kernel");
+}
+
+nys_status batch_factor_prepare(int64_t lds_bytes) {
+  if (lds_bytes > 64 * 1024)
+    NYS_CHECK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(bfactor_kernel),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>(lds_bytes)));
+  return NYS_OK;
+}
+
+nys_status batch_factor_enqueue(const BDesc* d, const BLaunch& gram, const BLaunch& fac,
+                                const BLaunch& upix, int kgroups, int max_ell, int64_t lds_doubles,
+                                int nu_mode, int tail, double mu, int max_esc, hipStream_t st) {
+  const int ntiles = (2 * max_ell + kGT - 1) / kGT;
+  const int ntri = ntiles * (ntiles + 1) / 2;
+  hipLaunchKernelGGL(bgram_kernel, dim3(static_cast<unsigned>(gram.nblk), ntri), dim3(256), 0, st,
+                     d, gram.seg, gram.nseg);
+  NYS_TRY(launch_check("bgram_kernel"));
+  hipLaunchKernelGGL(bgram_reduce, dim3(cdiv(ntri * kGT * kGT, 256), gram.nseg), dim3(256), 0, st,
+                     d, gram.seg);
+  NYS_TRY(launch_check("bgram_reduce"));
+  hipLaunchKernelGGL(bfactor_kernel, dim3(fac.nseg), dim3(kFT),
+                     static_cast<size_t>(lds_doubles) * sizeof(double), st, d, fac.seg, nu_mode,
+                     tail, mu, max_esc, lds_doubles);
+  NYS_TRY(launch_check("bfactor_kernel"));
+  hipLaunchKernelGGL(bform_u_kernel, dim3(static_cast<unsigned>(upix.nblk), kgroups), dim3(256), 0,
+                     st, d, upix.seg, upix.nseg);
+  return launch_check("bform_u_kernel");
 }
 
 }  // namespace nys

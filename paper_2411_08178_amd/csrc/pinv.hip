@@ -16,6 +16,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "batch.hpp"
 
 namespace nys {
 
@@ -107,17 +108,12 @@ __device__ __forceinline__ void tail_sum(const double* __restrict__ part, int nb
 // Block (b, col): pixels of chunk b, all rows of U in groups of 16 (rows past
 // ell are zero padding): part[col][b][k] = sum over the chunk of U[k][n] v[n].
 template <class T>
-__global__ __launch_bounds__(1024) void ut_partial_kernel(const T* __restrict__ U, int64_t ldu,
-                                                          const T* __restrict__ v, int64_t N,
-                                                          int Lp, int64_t chunk,
-                                                          double* __restrict__ part) {
+__device__ __forceinline__ void ut_partial_body(const T* __restrict__ U, int64_t ldu,
+                                                const T* __restrict__ vc, int64_t N, int Lp,
+                                                int64_t n0, int64_t n1, double* __restrict__ dst) {
   __shared__ double red[1024];
   __shared__ double bsum[16];
-  const int nblk = gridDim.x, col = blockIdx.y;
   const int bs = blockDim.x;
-  const T* vc = v + static_cast<size_t>(col) * N;
-  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
-  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
   constexpr int VW = 16 / sizeof(T);       // elements per 16-byte load
   for (int g = 0; g < Lp / 16; ++g) {
     T acc[16];
@@ -150,9 +146,106 @@ __global__ __launch_bounds__(1024) void ut_partial_kernel(const T* __restrict__ 
       }
     }
     block_reduce<16>(acc, red, bsum);
-    if (threadIdx.x < 16)
-      part[(static_cast<size_t>(col) * nblk + blockIdx.x) * Lp + 16 * g + threadIdx.x] = bsum[threadIdx.x];
+    if (threadIdx.x < 16) dst[16 * g + threadIdx.x] = bsum[threadIdx.x];
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void ut_partial_kernel(const T* __restrict__ U, int64_t ldu,
+                                                          const T* __restrict__ v, int64_t N,
+                                                          int Lp, int64_t chunk,
+                                                          double* __restrict__ part) {
+  const int nblk = gridDim.x, col = blockIdx.y;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  ut_partial_body<T>(U, ldu, v + static_cast<size_t>(col) * N, N, Lp, n0, n1,
+                     part + (static_cast<size_t>(col) * nblk + blockIdx.x) * Lp);
+}
+
+// ---------------------------------------------------------------- batched
+// Block (1024 threads) -> (instance, chunk): D.part[b][k] = sum U[k][n] v[n].
+__global__ __launch_bounds__(1024) void but_partial_kernel(const BDesc* __restrict__ d,
+                                                           const BSeg* __restrict__ seg, int nseg,
+                                                           int fsrc) {
+  const BSeg& sg = seg[seg_find(seg, nseg, blockIdx.x)];
+  const BDesc& D = d[sg.inst];
+  const int64_t lb = blockIdx.x - sg.first;
+  const int64_t n0 = lb * sg.chunk;
+  const int64_t n1 = (n0 + sg.chunk < D.N) ? n0 + sg.chunk : D.N;
+  ut_partial_body<float>(D.U, D.ldu, D.f[fsrc], D.N, D.ell_pad, n0, n1,
+                         D.part + static_cast<size_t>(lb) * D.ell_pad);
+}
+
+// One block per segment: D.cd[k] = d_k * sum_b D.part[b][k]  (d of eq. (6)).
+__global__ __launch_bounds__(1024) void but_tail_kernel(const BDesc* __restrict__ d,
+                                                        const BSeg* __restrict__ seg) {
+  __shared__ double red[1024];
+  __shared__ double bsum[128];
+  const BSeg& sg = seg[blockIdx.x];
+  const BDesc& D = d[sg.inst];
+  tail_sum(D.part, static_cast<int>(sg.nblk), D.ell_pad, red, bsum);
+  for (int k = threadIdx.x; k < D.ell; k += blockDim.x) D.cd[k] = D.meta[PcMeta::kD + k] * bsum[k];
+}
+
+// out = s + c (t + U cd) over 1024-pixel blocks, c = -scal[sidx] (sidx >= 0)
+// or 1; s = 0 when fs < 0; no U term without a preconditioner (ell = 0).
+// P^{-1} t = t + U (d . U^T t) (eq. (6)).
+__global__ __launch_bounds__(256) void bcombine_kernel(const BDesc* __restrict__ d,
+                                                       const BSeg* __restrict__ seg, int nseg,
+                                                       int fs, int ft, int fout, int sidx) {
+  __shared__ float cs[PcMeta::kMaxEll];
+  const BSeg& sg = seg[seg_find(seg, nseg, blockIdx.x)];
+  const BDesc& D = d[sg.inst];
+  const int L = D.ell;
+  for (int k = threadIdx.x; k < L; k += blockDim.x) cs[k] = static_cast<float>(D.cd[k]);
+  __syncthreads();
+  const float c = sidx >= 0 ? -static_cast<float>(D.scal[sidx]) : 1.f;
+  const float* t = D.f[ft];            // may alias out
+  const float* sv = fs >= 0 ? D.f[fs] : nullptr;
+  float* out = D.f[fout];
+  const float* __restrict__ U = D.U;
+  const int64_t base = (blockIdx.x - sg.first) * 1024;
+  if ((D.N & 3) == 0) {
+    const int64_t n = base + 4 * threadIdx.x;
+    if (n >= D.N) return;
+    float4 a = *reinterpret_cast<const float4*>(t + n);
+    const float* p = U + n;
+    for (int k = 0; k < L; ++k) {
+      const float4 u = *reinterpret_cast<const float4*>(p);
+      a.x += u.x * cs[k]; a.y += u.y * cs[k]; a.z += u.z * cs[k]; a.w += u.w * cs[k];
+      p += D.ldu;
+    }
+    float4 r = make_float4(c * a.x, c * a.y, c * a.z, c * a.w);
+    if (sv) {
+      const float4 s4 = *reinterpret_cast<const float4*>(sv + n);
+      r.x += s4.x; r.y += s4.y; r.z += s4.z; r.w += s4.w;
+    }
+    *reinterpret_cast<float4*>(out + n) = r;
+  } else {
+    for (int q = 0; q < 4; ++q) {
+      const int64_t n = base + q * 256 + threadIdx.x;
+      if (n >= D.N) break;
+      float a = t[n];
+      for (int k = 0; k < L; ++k) a += U[static_cast<size_t>(k) * D.ldu + n] * cs[k];
+      out[n] = (sv ? sv[n] : 0.f) + c * a;
+    }
+  }
+}
+
+nys_status batch_pinv_coeffs(const BDesc* d, const BSeg* rseg, int nrseg, int64_t rblk, int fsrc,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(but_partial_kernel, dim3(static_cast<unsigned>(rblk)), dim3(1024), 0, st, d,
+                     rseg, nrseg, fsrc);
+  NYS_TRY(launch_check("but_partial_kernel"));
+  hipLaunchKernelGGL(but_tail_kernel, dim3(nrseg), dim3(1024), 0, st, d, rseg);
+  return launch_check("but_tail_kernel");
+}
+
+nys_status batch_combine(const BDesc* d, const BSeg* pseg, int npseg, int64_t pblk, int fs,
+                         int ft, int fout, int sidx, hipStream_t st) {
+  hipLaunchKernelGGL(bcombine_kernel, dim3(static_cast<unsigned>(pblk)), dim3(256), 0, st, d,
+                     pseg, npseg, fs, ft, fout, sidx);
+  return launch_check("bcombine_kernel");
 }
 
 // cd[col][k] = coef[k] * sum_b part[col][b][k]   (one block)

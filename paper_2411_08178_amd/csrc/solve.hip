@@ -6,6 +6,7 @@
 
 #include "common.hpp"
 #include "internal.hpp"
+#include "stencil.hpp"
 
 namespace nys {
 
@@ -44,41 +45,6 @@ __global__ void momentum_kernel(const T* __restrict__ xn, T* __restrict__ x, T* 
 }
 
 // ---------------------------------------------------------------- reductions
-// Block sums (FP64) of a per-element term; `which` selects the term.
-enum Term { kSq = 0, kHuber = 1, kAbs = 2, kTV = 3, kTVAniso = 4, kHS1 = 5 };
-
-template <class T>
-__device__ __forceinline__ double term_at(const T* a, const T* b, int64_t i, int which, T delta,
-                                          int n1, int n2) {
-  switch (which) {
-    case kSq: { double r = static_cast<double>(a[i]) - static_cast<double>(b[i]); return 0.5 * r * r; }
-    case kHuber: {
-      double r = static_cast<double>(a[i]) - static_cast<double>(b[i]);
-      double ar = fabs(r), d = static_cast<double>(delta);
-      return ar <= d ? r * r / (2 * d) : ar - d / 2;
-    }
-    case kAbs: return fabs(static_cast<double>(a[i]));
-    default: break;
-  }
-  const int r = static_cast<int>(i / n2), c = static_cast<int>(i % n2);
-  auto X = [&](int rr, int cc) -> double {
-    rr = rr < 0 ? 0 : (rr >= n1 ? n1 - 1 : rr);
-    cc = cc < 0 ? 0 : (cc >= n2 ? n2 - 1 : cc);
-    return static_cast<double>(a[static_cast<int64_t>(rr) * n2 + cc]);
-  };
-  if (which == kTV || which == kTVAniso) {
-    double d1 = r >= 1 ? X(r, c) - X(r - 1, c) : 0.0;
-    double d2 = c >= 1 ? X(r, c) - X(r, c - 1) : 0.0;
-    return which == kTV ? sqrt(d1 * d1 + d2 * d2) : fabs(d1) + fabs(d2);
-  }
-  double v11 = X(r - 1, c) - 2 * X(r, c) + X(r + 1, c);
-  double v22 = X(r, c - 1) - 2 * X(r, c) + X(r, c + 1);
-  double v12 = 0.25 * (X(r + 1, c + 1) - X(r + 1, c - 1) - X(r - 1, c + 1) + X(r - 1, c - 1));
-  double m = 0.5 * (v11 + v22), h = 0.5 * (v11 - v22);
-  double rad = sqrt(h * h + v12 * v12);
-  return fabs(m + rad) + fabs(m - rad);
-}
-
 template <class T>
 __global__ __launch_bounds__(256) void term_sum_kernel(const T* __restrict__ a, const T* __restrict__ b,
                                                        int64_t n, int which, T delta, int n1, int n2,

@@ -1,0 +1,159 @@
+// Pixel stencils shared by the prox, the cost and the batched solver:
+// the regulariser's linear map L (finite differences, Hessian), its adjoint,
+// the projection onto the dual ball, and the per-pixel cost terms.
+#pragma once
+
+#include "common.hpp"
+
+namespace nys {
+
+// ================================================================ stencils
+// Regulariser channels: TV (2): d1 = X[i,j]-X[i-1,j] (0 on row 0),
+// d2 = X[i,j]-X[i,j-1] (0 on column 0).  HS1 (3): v11, v22, v12 with
+// replicate padding, v12 counted twice in the pairing.
+template <class T>
+__device__ __forceinline__ T ldc(const T* x, int i, int j, int n1, int n2) {
+  i = i < 0 ? 0 : (i >= n1 ? n1 - 1 : i);
+  j = j < 0 ? 0 : (j >= n2 ? n2 - 1 : j);
+  return x[static_cast<size_t>(i) * n2 + j];
+}
+
+// Sum of q over {(i, j) : clip(i + di) = ip, clip(j + dj) = jp}.
+template <class T>
+__device__ __forceinline__ T rep_adj(const T* q, int ip, int jp, int di, int dj, int n1, int n2) {
+  int is[2], js[2], ni = 0, nj = 0;
+  if (di == 0) { is[ni++] = ip; }
+  else if (di < 0) { if (ip + 1 < n1) is[ni++] = ip + 1; if (ip == 0) is[ni++] = 0; }
+  else { if (ip >= 1) is[ni++] = ip - 1; if (ip == n1 - 1) is[ni++] = n1 - 1; }
+  if (dj == 0) { js[nj++] = jp; }
+  else if (dj < 0) { if (jp + 1 < n2) js[nj++] = jp + 1; if (jp == 0) js[nj++] = 0; }
+  else { if (jp >= 1) js[nj++] = jp - 1; if (jp == n2 - 1) js[nj++] = n2 - 1; }
+  T s = 0;
+  for (int a = 0; a < ni; ++a)
+    for (int b = 0; b < nj; ++b) s += q[static_cast<size_t>(is[a]) * n2 + js[b]];
+  return s;
+}
+
+template <class T>
+__device__ __forceinline__ T lt_at(const T* q, int reg, int i, int j, int n1, int n2) {
+  const size_t N = static_cast<size_t>(n1) * n2;
+  const size_t o = static_cast<size_t>(i) * n2 + j;
+  if (reg != NYS_REG_HS1) {
+    const T* q1 = q;
+    const T* q2 = q + N;
+    T v = 0;
+    if (i >= 1) v += q1[o];
+    if (i + 1 < n1) v -= q1[o + n2];
+    if (j >= 1) v += q2[o];
+    if (j + 1 < n2) v -= q2[o + 1];
+    return v;
+  }
+  const T* q11 = q;
+  const T* q22 = q + N;
+  const T* q12 = q + 2 * N;
+  T v = rep_adj(q11, i, j, -1, 0, n1, n2) - T(2) * q11[o] + rep_adj(q11, i, j, 1, 0, n1, n2);
+  v += rep_adj(q22, i, j, 0, -1, n1, n2) - T(2) * q22[o] + rep_adj(q22, i, j, 0, 1, n1, n2);
+  v += T(0.5) * (rep_adj(q12, i, j, 1, 1, n1, n2) - rep_adj(q12, i, j, 1, -1, n1, n2) -
+                 rep_adj(q12, i, j, -1, 1, n1, n2) + rep_adj(q12, i, j, -1, -1, n1, n2));
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ void project_group(int reg, T* v) {
+  if (reg == NYS_REG_TV) {
+    T nrm = sqrt(v[0] * v[0] + v[1] * v[1]);
+    if (nrm > T(1)) { v[0] /= nrm; v[1] /= nrm; }
+  } else if (reg == NYS_REG_TV_ANISO) {
+    v[0] = fmin(T(1), fmax(T(-1), v[0]));
+    v[1] = fmin(T(1), fmax(T(-1), v[1]));
+  } else {
+    // symmetric [[a, b], [b, c]]: clip eigenvalues to [-1, 1]
+    T a = v[0], c = v[1], b = v[2];
+    T m = T(0.5) * (a + c), h = T(0.5) * (a - c);
+    T r = sqrt(h * h + b * b);
+    T l1 = m + r, l2 = m - r;
+    if (l1 <= T(1) && l2 >= T(-1)) return;
+    T u1 = fmin(T(1), fmax(T(-1), l1)), u2 = fmin(T(1), fmax(T(-1), l2));
+    T avg = T(0.5) * (u1 + u2);
+    if (r > T(0)) {
+      T g = (u1 - u2) / (T(2) * r);
+      v[0] = avg + g * h;
+      v[1] = avg - g * h;
+      v[2] = g * b;
+    } else {
+      v[0] = avg; v[1] = avg; v[2] = 0;
+    }
+  }
+}
+
+// One pixel of the accelerated dual step: Q+ = Proj(R + step L x),
+// R = Q+ + beta (Q+ - Q), Q = Q+ (channels N = n1 n2 apart).
+template <class T>
+__device__ __forceinline__ void dual_update_at(const T* __restrict__ x, T* __restrict__ Q,
+                                               T* __restrict__ R, int reg, int i, int j, int n1,
+                                               int n2, T step, T beta) {
+  const size_t N = static_cast<size_t>(n1) * n2;
+  const size_t o = static_cast<size_t>(i) * n2 + j;
+  T lx[3];
+  int nch;
+  if (reg != NYS_REG_HS1) {
+    T xc = x[o];
+    lx[0] = i >= 1 ? xc - x[o - n2] : T(0);
+    lx[1] = j >= 1 ? xc - x[o - 1] : T(0);
+    nch = 2;
+  } else {
+    T xc = x[o];
+    lx[0] = ldc(x, i - 1, j, n1, n2) - T(2) * xc + ldc(x, i + 1, j, n1, n2);
+    lx[1] = ldc(x, i, j - 1, n1, n2) - T(2) * xc + ldc(x, i, j + 1, n1, n2);
+    lx[2] = T(0.25) * (ldc(x, i + 1, j + 1, n1, n2) - ldc(x, i + 1, j - 1, n1, n2) -
+                       ldc(x, i - 1, j + 1, n1, n2) + ldc(x, i - 1, j - 1, n1, n2));
+    nch = 3;
+  }
+  T v[3], qo[3];
+  for (int c = 0; c < nch; ++c) {
+    qo[c] = Q[c * N + o];
+    v[c] = R[c * N + o] + step * lx[c];
+  }
+  project_group(reg, v);
+  for (int c = 0; c < nch; ++c) {
+    Q[c * N + o] = v[c];
+    R[c * N + o] = v[c] + beta * (v[c] - qo[c]);
+  }
+}
+
+// Per-element cost terms (FP64); `which` selects the term.
+enum Term { kSq = 0, kHuber = 1, kAbs = 2, kTV = 3, kTVAniso = 4, kHS1 = 5 };
+
+template <class T>
+__device__ __forceinline__ double term_at(const T* a, const T* b, int64_t i, int which, T delta,
+                                          int n1, int n2) {
+  switch (which) {
+    case kSq: { double r = static_cast<double>(a[i]) - static_cast<double>(b[i]); return 0.5 * r * r; }
+    case kHuber: {
+      double r = static_cast<double>(a[i]) - static_cast<double>(b[i]);
+      double ar = fabs(r), d = static_cast<double>(delta);
+      return ar <= d ? r * r / (2 * d) : ar - d / 2;
+    }
+    case kAbs: return fabs(static_cast<double>(a[i]));
+    default: break;
+  }
+  const int r = static_cast<int>(i / n2), c = static_cast<int>(i % n2);
+  auto X = [&](int rr, int cc) -> double {
+    rr = rr < 0 ? 0 : (rr >= n1 ? n1 - 1 : rr);
+    cc = cc < 0 ? 0 : (cc >= n2 ? n2 - 1 : cc);
+    return static_cast<double>(a[static_cast<int64_t>(rr) * n2 + cc]);
+  };
+  if (which == kTV || which == kTVAniso) {
+    double d1 = r >= 1 ? X(r, c) - X(r - 1, c) : 0.0;
+    double d2 = c >= 1 ? X(r, c) - X(r, c - 1) : 0.0;
+    return which == kTV ? sqrt(d1 * d1 + d2 * d2) : fabs(d1) + fabs(d2);
+  }
+  double v11 = X(r - 1, c) - 2 * X(r, c) + X(r + 1, c);
+  double v22 = X(r, c - 1) - 2 * X(r, c) + X(r, c + 1);
+  double v12 = 0.25 * (X(r + 1, c + 1) - X(r + 1, c - 1) - X(r - 1, c + 1) + X(r - 1, c - 1));
+  double m = 0.5 * (v11 + v22), h = 0.5 * (v11 - v22);
+  double rad = sqrt(h * h + v12 * v12);
+  return fabs(m + rad) + fabs(m - rad);
+}
+
+}  // namespace nys
