@@ -13,8 +13,13 @@ found by untimed runs that record the cost, then the timed runs repeat the
 solve with exactly that many iterations and no cost recording.
 
 Prints one JSON line.  Usage:
-    python bench.py [--steps K] [--warmup W] [--workload sr512|ct512|deblur128]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload sr512|ct512|deblur128|batch64]
                     [--no-cpu-baseline] [--copy-calibration]
+
+The batched workload (64 deblurring problems of uneven sizes, one graph
+launch per solve of the whole batch) times the batch to the point where every
+instance has reached the gap.
 """
 from __future__ import annotations
 
@@ -39,6 +44,7 @@ WORKLOAD_KEYS = {
     "sr512": "sr512_haar_bf16",
     "ct512": "ct512_hs1_f32",
     "deblur128": "deblur128_tv_f64",
+    "batch64": "batch64_deblur_f32",
 }
 
 
@@ -127,6 +133,27 @@ def sketch_traffic(wl):
     return d["traffic_bytes_per_launch"]
 
 
+def copy_peak(torch):
+    """Measured stream-copy rate (GB/s): an elementwise kernel reading 1 GiB
+    and writing 1 GiB, best of 5, events on the launch stream."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    stream = torch.cuda.current_stream()
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        torch.mul(a, 1.0, out=b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return round(2 * (1 << 30) / (best * 1e-3) / 1e9, 1)
+
+
 def first_below(costs, fstar, gap):
     g = (costs - fstar) / abs(fstar)
     idx = np.nonzero(g <= gap)[0]
@@ -180,6 +207,181 @@ def cpu_baseline(wl, k_pc, power_iters, alpha, seed=0):
                            wapg_iter_s=t_it))
 
 
+# ---------------------------------------------------------------- batch
+class BatchSetup:
+    """The 64 deblurring problems of the batched workload, on the GPU."""
+
+    def __init__(self, P, torch, wl, seed=0):
+        self.specs = W.batch_instances(wl.count, seed)
+        self.items = []
+        for s in self.specs:
+            n = s.n
+            h = W.gaussian_psf(s.psf_k, s.psf_sigma)
+            op = P.Operator(P.OP_BLUR, n, n, psf=h)
+            xt = torch.from_numpy(W.phantom_blocks(n, s.seed)).float().cuda()
+            noise = torch.from_numpy(W.gaussian((n, n), s.seed)).float().cuda()
+            y = (P.op_forward(op, xt) + wl.noise_sigma * noise).contiguous()
+            om = torch.from_numpy(W.omega(s.ell, n, n, s.seed)).float().cuda().contiguous()
+            v0 = torch.from_numpy(W.gaussian((n, n), s.seed, stream=7)).float().cuda().contiguous()
+            self.items.append(dict(psf=h, y=y, lam=s.lam, ell=s.ell, omega=om, v0=v0))
+        self.N = [s.n * s.n for s in self.specs]
+        self.sketch_bytes = sum(2 * 4 * s.ell * s.n * s.n for s in self.specs)
+
+
+def batch_plan(P, B, wl, precondition, iters, power_iters, record):
+    return P.BatchSolver(B.items, reg=P.REG_TV, max_iter=iters, n_inner=wl.inner,
+                         power_iters=power_iters, precondition=precondition,
+                         record_costs=record, tune=True)
+
+
+def cpu_baseline_batch(wl, B, k_pc, power_iters, seed=0):
+    """The FP64 oracle on a bounded sample of the batch (two instances of
+    different sizes), extrapolated per pixel to all instances (seconds)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import nystrom as onys
+    from oracle import solver as sv
+    sample = [s for s in B.specs if s.n == 256][:1] + [s for s in B.specs if s.n == 512][:1]
+    per_px = dict(sketch_col=[], factor_col=[], power=[], wapg=[])
+    for s in sample:
+        n = s.n
+        h = W.gaussian_psf(s.psf_k, s.psf_sigma)
+        prob = sv.Problem("blur", n, None, s.lam, "tv", h=h)
+        prob.y = prob.A(W.phantom_blocks(n, s.seed)) + wl.noise_sigma * W.gaussian((n, n), s.seed)
+        om = W.round_dtype(W.omega(s.ell, n, n, s.seed), "f32")
+        ncols = 8
+        t0 = time.perf_counter()
+        Y = np.stack([prob.phi(om[k]) for k in range(ncols)])
+        per_px["sketch_col"].append((time.perf_counter() - t0) / ncols / (n * n))
+        d = 0.01 + 0.24 * np.abs(W.gaussian((n * n,), seed, stream=8))
+        Yfull = d[None, :] * om.reshape(s.ell, -1)
+        t0 = time.perf_counter()
+        r = onys.nystrom(Yfull, om.reshape(s.ell, -1))
+        per_px["factor_col"].append((time.perf_counter() - t0) / (n * n * s.ell))
+        pc = sv.Precond(r["U"], r["shat"], r["nu"], "sqrt")
+        t0 = time.perf_counter()
+        sv.lipschitz(prob, pc, W.gaussian((n, n), s.seed, stream=7), 10)
+        per_px["power"].append((time.perf_counter() - t0) / 10 / (n * n))
+        it = 4
+        t0 = time.perf_counter()
+        sv.wapg(prob, pc, 0.5, it, inner=wl.inner, record_cost=False)
+        per_px["wapg"].append((time.perf_counter() - t0) / it / (n * n))
+        del Y
+    m = {k: float(np.mean(v)) for k, v in per_px.items()}
+    total = 0.0
+    for s in B.specs:
+        N = s.n * s.n
+        total += (m["sketch_col"] * N * s.ell + m["factor_col"] * N * s.ell +
+                  m["power"] * N * power_iters + m["wapg"] * N * k_pc)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    desc = (f"oracle on instances n={[s.n for s in sample]}: 8 sketch columns, full Alg. 1 "
+            f"factor, 10 power steps, 4 WAPG iterations each; per-pixel costs extrapolated to "
+            f"all {len(B.specs)} instances ({k_pc} iterations); numpy/scipy FP64, "
+            f"BLAS threads {threads}")
+    return dict(value=total, unit="s", cores=threads, kind="oracle", sample=desc,
+                parts={k + "_per_px_s": v for k, v in m.items()})
+
+
+def main_batch(args, P, torch, wl):
+    log(f"workload {wl.name}: {wl.count} instances")
+    B = BatchSetup(P, torch, wl, args.seed)
+    torch.cuda.synchronize()
+    ref_iters = args.ref_iters
+    t0 = time.perf_counter()
+    ref_pc = batch_plan(P, B, wl, True, ref_iters, args.power_iters, True)
+    ref_pc.run()
+    ref_pl = batch_plan(P, B, wl, False, ref_iters, args.power_iters, True)
+    ref_pl.run()
+    torch.cuda.synchronize()
+    c_pc = np.stack([c.cpu().numpy() for c in ref_pc.costs])
+    c_pl = np.stack([c.cpu().numpy() for c in ref_pl.costs])
+    fstar = np.minimum(c_pc.min(axis=1), c_pl.min(axis=1))
+    k_pc = [first_below(c_pc[i], fstar[i], GAP) for i in range(len(fstar))]
+    k_pl = [first_below(c_pl[i], fstar[i], GAP) for i in range(len(fstar))]
+    reached_pc = all(k is not None for k in k_pc)
+    reached_pl = all(k is not None for k in k_pl)
+    kp = max(k if k is not None else ref_iters for k in k_pc)
+    kq = max(k if k is not None else ref_iters for k in k_pl)
+    Lpc = [ref_pc.info(i)["L"] for i in range(len(fstar))]
+    log(f"reference runs ({ref_iters} its) {time.perf_counter() - t0:.1f}s; batch iterations "
+        f"to gap: precond {kp} (all reached: {reached_pc}), plain {kq} (all reached: {reached_pl})")
+    del ref_pc, ref_pl
+    stream = torch.cuda.current_stream()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+
+    def timed(plan):
+        for _ in range(args.warmup):
+            plan.run()
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for _ in range(args.steps):
+            plan.run()
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return t_start.elapsed_time(t_end) / args.steps
+
+    plan_pc = batch_plan(P, B, wl, True, kp, args.power_iters, False)
+    ms_pc = timed(plan_pc)
+    # roofline: the batched sketch A^T A Omega over all instances (one
+    # persistent launch), a burst bracketed by events on the launch stream
+    burst = 10
+    plan_pc.sketch_only()
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(burst):
+        plan_pc.sketch_only()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    sk_ms = t_start.elapsed_time(t_end) / burst
+    tiles = plan_pc.tiles()
+    del plan_pc
+    plan_pl = batch_plan(P, B, wl, False, kq, args.power_iters, False)
+    ms_pl = timed(plan_pl)
+    del plan_pl
+    log(f"preconditioned {ms_pc:.1f} ms ({kp} its), plain {ms_pl:.1f} ms ({kq} its); "
+        f"batched sketch {sk_ms * 1e3:.1f} us")
+    achieved = B.sketch_bytes / (sk_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "batched sketch (A^T A Omega, all instances, one launch)",
+            "bytes_per_launch": B.sketch_bytes, "avg_launch_us": round(sk_ms * 1e3, 2)}
+    roof["measured_copy_peak"] = copy_peak(torch)
+    roof["frac_of_copy_peak"] = round(achieved / roof["measured_copy_peak"], 4)
+    out = {
+        "metric": "time to 1e-4 rel. cost gap, Nystrom-precond WAPG (sketch+factor+step+solve)",
+        "value": round(ms_pc / 1e3, 6),
+        "gap_reached": {"precond": reached_pc, "plain": reached_pl},
+        "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_pc, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "instances": wl.count,
+                   "sizes": sorted(set(s.n for s in B.specs)), "pixels": int(sum(B.N)),
+                   "ell_total": int(sum(s.ell for s in B.specs)), "solver_dtype": "f32",
+                   "factor_dtype": "f64", "reg": "tv", "inner": wl.inner,
+                   "power_iters": args.power_iters, "seed": args.seed, "tiles": tiles},
+        "plain_apg_s": round(ms_pl / 1e3, 6),
+        "speedup_vs_plain": round(ms_pl / ms_pc, 4),
+        "iters_to_gap": {"precond": kp, "plain": kq, "reference_iters": ref_iters,
+                         "precond_per_instance_median": float(np.median(
+                             [k if k is not None else ref_iters for k in k_pc])),
+                         "plain_per_instance_median": float(np.median(
+                             [k if k is not None else ref_iters for k in k_pl]))},
+        "L_precond_range": [float(min(Lpc)), float(max(Lpc))],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline_batch(wl, B, kp, args.power_iters, args.seed)
+        log(f"cpu baseline leg took {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
@@ -221,6 +423,10 @@ def main():
         return
 
     wl = W.workload(WORKLOAD_KEYS[args.workload])
+    if wl.count > 1:
+        if args.ref_iters == 20000:
+            args.ref_iters = 300
+        return main_batch(args, P, torch, wl)
     log(f"workload {wl.name}: n={wl.n} ell={wl.ell} sketch={wl.sketch_dtype} solver={wl.dtype}")
     S = Setup(P, torch, wl, args.seed)
     torch.cuda.synchronize()
@@ -299,6 +505,8 @@ def main():
             "kernel": "sketch (A^T A Omega)", "bytes_per_launch": sk_bytes,
             "avg_launch_us": round(sk_avg_ms * 1e3, 2),
             "sketch_in_step_us": round(float(np.mean(sk_ms)) * 1e3, 2)}
+    roof["measured_copy_peak"] = copy_peak(torch)
+    roof["frac_of_copy_peak"] = round(achieved / roof["measured_copy_peak"], 4)
 
     out = {
         "metric": "time to 1e-4 rel. cost gap, Nystrom-precond WAPG (sketch+factor+step+solve)",

@@ -321,6 +321,11 @@ typedef struct {
 nys_status batch_solve_create(const nys_batch_item* items, int32_t count,
                               const nys_batch_opts* opts, nys_batch* out, void* stream);
 nys_status batch_solve_run(nys_batch b, void* stream);
+/* Enqueues only the sketches Y_i = A_i^T A_i Omega_i of every instance (the
+ * first step of a run) on `stream`; the plan must have a preconditioner.  It
+ * shares the plan's work-queue counters with batch_solve_run: the two must
+ * not overlap. */
+nys_status batch_solve_sketch(nys_batch b, void* stream);
 /* Host out[6] for instance i after a run (synchronises `stream`): alpha, L,
  * ||P^{-1}||, nu, factorisation status (nys_status), k_eff. */
 nys_status batch_solve_info(nys_batch b, int32_t i, double* out, void* stream);

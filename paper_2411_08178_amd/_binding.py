@@ -113,6 +113,7 @@ def lib():
             "batch_solve_create": [C.POINTER(BatchItem), i32, C.POINTER(BatchOpts),
                                    C.POINTER(vp), vp],
             "batch_solve_run": [vp, vp],
+            "batch_solve_sketch": [vp, vp],
             "batch_solve_info": [vp, i32, C.POINTER(dbl), vp],
             "batch_solve_shat": [vp, i32, C.POINTER(dbl), vp],
             "batch_solve_buffers": [vp, i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64)],
@@ -487,6 +488,10 @@ class BatchSolver:
     def run(self):
         _check(lib().batch_solve_run(self.handle, _stream()))
         return self.x
+
+    def sketch_only(self):
+        """Enqueue only the sketches of every instance (first step of run)."""
+        _check(lib().batch_solve_sketch(self.handle, _stream()))
 
     def info(self, i: int):
         out = (C.c_double * 6)()

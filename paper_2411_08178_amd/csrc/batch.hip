@@ -59,14 +59,174 @@ struct StItem {
   int32_t task, col, y0, x0;
 };
 
+// Row pitch (floats) of the register-blocked path for NT taps: the tile's
+// 64 + NT - 1 input columns plus at least 4 floats of slack for the float4
+// window reads of the horizontal pass.
+__host__ __device__ constexpr int st_pitch(int nt) { return (kStW + nt - 1 + 7) & ~3; }
+
+__host__ __device__ inline bool st_fast(int ty, int nt_r, int nt_c) {
+  return nt_r == nt_c && nt_r <= 29 && (nt_r & 1) && (ty & 7) == 0;
+}
+
 __host__ __device__ inline int st_lds_floats(int ty, int nt_r, int nt_c) {
   const int hr = ty + nt_r - 1;
+  if (st_fast(ty, nt_r, nt_c)) return (hr + ty) * st_pitch(nt_r);
   return hr * (kStW + nt_c - 1) + hr * kStW;
 }
 
 __device__ __forceinline__ int wrap_idx(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
+}
+
+// Loads rows [0, hr) x columns [0, wc) (wc <= 128) of the periodic input
+// window starting at (y0 + lo_r, x0 + lo_c) into tin (row pitch `pitch`).
+// Eight rows per batch are loaded into registers before any is stored, so a
+// thread keeps up to 16 global loads in flight.
+__device__ __forceinline__ void st_load_window(const StTask& T, const StItem& I, int hr, int wc,
+                                               int pitch, float* tin) {
+  constexpr int kLB = 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* src = T.in + static_cast<int64_t>(I.col) * T.cstride;
+  const int gj0 = wrap_idx(I.x0 + T.lo_c + lane, T.n2);
+  const bool two = lane + kStW < wc;
+  const int gj1 = two ? wrap_idx(I.x0 + T.lo_c + lane + kStW, T.n2) : gj0;
+  for (int r0 = wave; r0 < hr; r0 += 4 * kLB) {
+    float va[kLB], vb[kLB];
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+      const int r = r0 + 4 * t;
+      const int gr = wrap_idx(I.y0 + T.lo_r + (r < hr ? r : 0), T.n1);
+      const float* row = src + static_cast<int64_t>(gr) * T.n2;
+      va[t] = row[gj0];
+      vb[t] = row[gj1];
+    }
+#pragma unroll
+    for (int t = 0; t < kLB; ++t) {
+      const int r = r0 + 4 * t;
+      if (r < hr) {
+        tin[r * pitch + lane] = va[t];
+        if (two) tin[r * pitch + lane + kStW] = vb[t];
+      }
+    }
+  }
+}
+
+// One tile with NT taps per axis (odd, <= 29) and a tile height that is a
+// multiple of 8: the vertical pass first, over the 64 + NT - 1 input columns,
+// then the horizontal pass.  Vertical: a thread owns one column and 8
+// consecutive output rows and slides the NT taps (registers) down the
+// column, so each LDS value it reads feeds up to NT accumulators.
+// Horizontal: a thread owns 4 consecutive outputs of a row and reads its
+// NT + 3 inputs as float4 runs.  The periodic halo is loaded whole even for
+// a ragged last tile; only rows and columns inside the image are stored.
+template <int NT>
+__device__ __forceinline__ void st_tile_fast(const StTask& T, const StItem& I, float* sm,
+                                             const float* s_tr, const float* s_tc) {
+  constexpr int WC = kStW + NT - 1;
+  constexpr int WP = st_pitch(NT);
+  const int tid = threadIdx.x;
+  const int ty = T.ty;
+  const int HR = ty + NT - 1;
+  float* tin = sm;
+  float* mid = sm + HR * WP;
+  st_load_window(T, I, HR, WC, WP, tin);
+  __syncthreads();
+  // row taps live only through the vertical pass, column taps only through
+  // the horizontal one (fewer registers, more resident workgroups)
+  float tr[NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a) tr[a] = s_tr[a];
+  const int nrb = ty >> 3;
+  for (int u = tid; u < nrb * WC; u += 256) {
+    const int rb = u / WC, q = u - rb * WC;
+    float acc[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) acc[o] = 0.f;
+    const float* p = tin + (rb * 8) * WP + q;
+#pragma unroll
+    for (int m = 0; m < 8 + NT - 1; ++m) {
+      const float v = p[m * WP];
+#pragma unroll
+      for (int a = 0; a < NT; ++a) {
+        const int o = m - a;
+        if (o >= 0 && o < 8) acc[o] = fmaf(tr[a], v, acc[o]);
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) mid[(rb * 8 + o) * WP + q] = acc[o];
+  }
+  __syncthreads();
+  const int rows = min(ty, T.n1 - I.y0);
+  float* dst = T.out + static_cast<int64_t>(I.col) * T.cstride;
+  const bool vec = (T.n2 & 3) == 0;
+  float tc[NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a) tc[a] = s_tc[a];
+  for (int u = tid; u < rows * 16; u += 256) {
+    const int r = u >> 4, g = u & 15;
+    const float* p = mid + r * WP + 4 * g;
+    constexpr int NW = (NT + 3 + 3) / 4;
+    float w[4 * NW];
+#pragma unroll
+    for (int e = 0; e < NW; ++e) {
+      const float4 x = *reinterpret_cast<const float4*>(p + 4 * e);
+      w[4 * e] = x.x; w[4 * e + 1] = x.y; w[4 * e + 2] = x.z; w[4 * e + 3] = x.w;
+    }
+    float o4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < NT; ++b) acc = fmaf(tc[b], w[k + b], acc);
+      o4[k] = acc;
+    }
+    const int j = I.x0 + 4 * g;
+    const int64_t o = static_cast<int64_t>(I.y0 + r) * T.n2 + j;
+    if (vec && j + 3 < T.n2) {
+      float4 v = make_float4(o4[0], o4[1], o4[2], o4[3]);
+      if (T.sub) {
+        const float4 sb = *reinterpret_cast<const float4*>(T.sub + o);
+        v.x -= sb.x; v.y -= sb.y; v.z -= sb.z; v.w -= sb.w;
+      }
+      *reinterpret_cast<float4*>(dst + o) = v;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (j + k < T.n2) dst[o + k] = T.sub ? o4[k] - T.sub[o + k] : o4[k];
+    }
+  }
+}
+
+// Generic tile: any tap counts and tile height, runtime loops.
+__device__ __forceinline__ void st_tile_generic(const StTask& T, const StItem& I, float* sm,
+                                                const float* s_tr, const float* s_tc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rows = min(T.ty, T.n1 - I.y0);
+  const int hr = rows + T.nt_r - 1, wc = kStW + T.nt_c - 1;
+  float* tin = sm;
+  float* mid = sm + hr * wc;
+  st_load_window(T, I, hr, wc, wc, tin);
+  __syncthreads();
+  for (int r = wave; r < hr; r += 4) {
+    const float* p = tin + r * wc + lane;
+    float acc = 0.f;
+    for (int b = 0; b < T.nt_c; ++b) acc = fmaf(s_tc[b], p[b], acc);
+    mid[r * kStW + lane] = acc;
+  }
+  __syncthreads();
+  const int j = I.x0 + lane;
+  float* dst = T.out + static_cast<int64_t>(I.col) * T.cstride;
+  for (int r = wave; r < rows; r += 4) {
+    const float* p = mid + r * kStW + lane;
+    float acc = 0.f;
+    for (int a = 0; a < T.nt_r; ++a) acc = fmaf(s_tr[a], p[a * kStW], acc);
+    if (j < T.n2) {
+      const int64_t o = static_cast<int64_t>(I.y0 + r) * T.n2 + j;
+      if (T.sub) acc -= T.sub[o];
+      dst[o] = acc;
+    }
+  }
 }
 
 // Persistent: block b serves queue b % 8 first (its XCD), then the others.
@@ -81,54 +241,48 @@ __global__ __launch_bounds__(256) void bstencil_kernel(const StTask* __restrict_
   extern __shared__ float sm[];
   __shared__ float s_tr[kStMaxTaps], s_tc[kStMaxTaps];
   __shared__ int s_ticket;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int home = blockIdx.x % kQueues;
   for (int qi = 0; qi < kQueues; ++qi) {
     const int q = (home + qi) % kQueues;
     const int q0 = qbase[q], qn = qbase[q + 1] - q0;
-    for (;;) {
-      if (tid == 0) s_ticket = atomicAdd(&ctr[q], 1);
-      __syncthreads();
-      const int t = __builtin_amdgcn_readfirstlane(s_ticket);
-      __syncthreads();
-      if (t >= qn) break;
+    if (tid == 0) s_ticket = atomicAdd(&ctr[q], 1);
+    __syncthreads();
+    int t = __builtin_amdgcn_readfirstlane(s_ticket);
+    __syncthreads();
+    while (t < qn) {
+      // the next ticket is requested now; its latency overlaps this tile
+      int nxt = 0;
+      if (tid == 0) nxt = atomicAdd(&ctr[q], 1);
       const StItem I = items[q0 + t];
       const StTask T = tasks[I.task];
       if (tid < T.nt_r) s_tr[tid] = taps[T.taps + tid];
       else if (tid < T.nt_r + T.nt_c) s_tc[tid - T.nt_r] = taps[T.taps + tid];
-      const int rows = min(T.ty, T.n1 - I.y0);
-      const int hr = rows + T.nt_r - 1, wc = kStW + T.nt_c - 1;
-      float* tin = sm;
-      float* mid = sm + hr * wc;
-      const float* src = T.in + static_cast<int64_t>(I.col) * T.cstride;
-      const int gj0 = wrap_idx(I.x0 + T.lo_c + lane, T.n2);
-      const bool two = lane + kStW < wc;
-      const int gj1 = two ? wrap_idx(I.x0 + T.lo_c + lane + kStW, T.n2) : 0;
-      for (int r = wave; r < hr; r += 4) {
-        const float* row = src + static_cast<int64_t>(wrap_idx(I.y0 + T.lo_r + r, T.n1)) * T.n2;
-        tin[r * wc + lane] = row[gj0];
-        if (two) tin[r * wc + lane + kStW] = row[gj1];
-      }
       __syncthreads();
-      for (int r = wave; r < hr; r += 4) {
-        const float* p = tin + r * wc + lane;
-        float acc = 0.f;
-        for (int b = 0; b < T.nt_c; ++b) acc = fmaf(s_tc[b], p[b], acc);
-        mid[r * kStW + lane] = acc;
-      }
-      __syncthreads();
-      const int j = I.x0 + lane;
-      float* dst = T.out + static_cast<int64_t>(I.col) * T.cstride;
-      for (int r = wave; r < rows; r += 4) {
-        const float* p = mid + r * kStW + lane;
-        float acc = 0.f;
-        for (int a = 0; a < T.nt_r; ++a) acc = fmaf(s_tr[a], p[a * kStW], acc);
-        if (j < T.n2) {
-          const int64_t o = static_cast<int64_t>(I.y0 + r) * T.n2 + j;
-          if (T.sub) acc -= T.sub[o];
-          dst[o] = acc;
+      if (st_fast(T.ty, T.nt_r, T.nt_c)) {
+        switch (T.nt_r) {
+          case 1: st_tile_fast<1>(T, I, sm, s_tr, s_tc); break;
+          case 3: st_tile_fast<3>(T, I, sm, s_tr, s_tc); break;
+          case 5: st_tile_fast<5>(T, I, sm, s_tr, s_tc); break;
+          case 7: st_tile_fast<7>(T, I, sm, s_tr, s_tc); break;
+          case 9: st_tile_fast<9>(T, I, sm, s_tr, s_tc); break;
+          case 11: st_tile_fast<11>(T, I, sm, s_tr, s_tc); break;
+          case 13: st_tile_fast<13>(T, I, sm, s_tr, s_tc); break;
+          case 15: st_tile_fast<15>(T, I, sm, s_tr, s_tc); break;
+          case 17: st_tile_fast<17>(T, I, sm, s_tr, s_tc); break;
+          case 19: st_tile_fast<19>(T, I, sm, s_tr, s_tc); break;
+          case 21: st_tile_fast<21>(T, I, sm, s_tr, s_tc); break;
+          case 23: st_tile_fast<23>(T, I, sm, s_tr, s_tc); break;
+          case 25: st_tile_fast<25>(T, I, sm, s_tr, s_tc); break;
+          case 27: st_tile_fast<27>(T, I, sm, s_tr, s_tc); break;
+          default: st_tile_fast<29>(T, I, sm, s_tr, s_tc); break;
         }
+      } else {
+        st_tile_generic(T, I, sm, s_tr, s_tc);
       }
+      if (tid == 0) s_ticket = nxt;
+      __syncthreads();
+      t = __builtin_amdgcn_readfirstlane(s_ticket);
       __syncthreads();
     }
   }
@@ -175,20 +329,29 @@ __global__ __launch_bounds__(256) void bsumsq_kernel(const BDesc* __restrict__ d
   if (threadIdx.x == 0) D.part[lb] = s;
 }
 
-// f[fdst] = src / ||src||, scal[kNorm] = ||src|| (every block sums the
-// instance's partials in the same order)
+// Sum of an instance's block partials, fixed order (blockIdx.x = segment):
+// which = 0: scal[kNorm] = sqrt(sum); which = 1: costs[k] = sum.
+__global__ __launch_bounds__(256) void bpart_tail_kernel(const BDesc* __restrict__ d,
+                                                         const BSeg* __restrict__ seg, int which,
+                                                         int k) {
+  __shared__ double red[256];
+  const BSeg& sg = seg[blockIdx.x];
+  const BDesc& D = d[sg.inst];
+  double s = 0;
+  for (int64_t b = threadIdx.x; b < sg.nblk; b += blockDim.x) s += D.part[b];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) {
+    if (which == 0) D.scal[BScal::kNorm] = sqrt(s);
+    else if (D.costs) D.costs[k] = s;
+  }
+}
+
+// f[fdst] = src / scal[kNorm]
 __global__ __launch_bounds__(256) void bnormalize_kernel(const BDesc* __restrict__ d,
                                                          const BSeg* __restrict__ seg, int nseg,
                                                          int fsrc, int fdst) {
-  __shared__ double nrm;
   BSEG_PROLOGUE
-  if (threadIdx.x == 0) {
-    double s = 0;
-    for (int64_t b = 0; b < sg.nblk; ++b) s += D.part[b];
-    nrm = sqrt(s);
-    if (lb == 0) D.scal[BScal::kNorm] = nrm;
-  }
-  __syncthreads();
+  const double nrm = D.scal[BScal::kNorm];
   const float inv = static_cast<float>(nrm > 0 ? 1.0 / nrm : 0.0);
   const float* src = fsrc >= 0 ? D.f[fsrc] : D.v0;
   float* dst = D.f[fdst];
@@ -277,17 +440,6 @@ __global__ __launch_bounds__(256) void bcost_partial_kernel(const BDesc* __restr
   if (threadIdx.x == 0) D.part[lb] = s;
 }
 
-// costs[k] = sum of the instance's partials (blockIdx.x = segment)
-__global__ void bcost_tail_kernel(const BDesc* __restrict__ d, const BSeg* __restrict__ seg,
-                                  int k) {
-  const BSeg& sg = seg[blockIdx.x];
-  const BDesc& D = d[sg.inst];
-  if (threadIdx.x != 0 || !D.costs) return;
-  double s = 0;
-  for (int64_t b = 0; b < sg.nblk; ++b) s += D.part[b];
-  D.costs[k] = s;
-}
-
 __global__ __launch_bounds__(256) void bcopy_out_kernel(const BDesc* __restrict__ d,
                                                         const BSeg* __restrict__ seg, int nseg) {
   BSEG_PROLOGUE
@@ -323,7 +475,7 @@ struct nys_batch_s {
   std::vector<int64_t> pix_off;              // packed offsets of the images
   int64_t P = 0;                             // packed image length
   BDesc* dd = nullptr;                       // device descriptors
-  BLaunch pix, red, upix, fac, gram;
+  BLaunch pix, cmb, red, upix, fac, gram;
   int kgroups = 0;
   int max_ell = 0;
   int64_t lds_doubles = 0;
@@ -471,16 +623,20 @@ nys_status enqueue_all(nys_batch_s* b) {
   const dim3 pg(static_cast<unsigned>(b->pix.nblk));
   hipLaunchKernelGGL(bsumsq_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, -1);
   NYS_TRY(launch_check("bsumsq_kernel"));
+  hipLaunchKernelGGL(bpart_tail_kernel, dim3(nseg), dim3(256), 0, st, d, b->pix.seg, 0, 0);
+  NYS_TRY(launch_check("bpart_tail_kernel"));
   hipLaunchKernelGGL(bnormalize_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, -1, int(kFldV));
   NYS_TRY(launch_check("bnormalize_kernel"));
   for (int it = 0; it < o.power_iters; ++it) {
     NYS_TRY(stencil_launch(b->st_phi_v, b->taps, b->ctr, st));
     if (pc) {
       NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldW, st));
-      NYS_TRY(batch_combine(d, b->pix.seg, nseg, b->pix.nblk, -1, kFldW, kFldW, -1, st));
+      NYS_TRY(batch_combine(d, b->cmb.seg, b->cmb.nseg, b->cmb.nblk, -1, kFldW, kFldW, -1, st));
     }
     hipLaunchKernelGGL(bsumsq_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, int(kFldW));
     NYS_TRY(launch_check("bsumsq_kernel"));
+    hipLaunchKernelGGL(bpart_tail_kernel, dim3(nseg), dim3(256), 0, st, d, b->pix.seg, 0, 0);
+    NYS_TRY(launch_check("bpart_tail_kernel"));
     hipLaunchKernelGGL(bnormalize_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, int(kFldW),
                        int(kFldV));
     NYS_TRY(launch_check("bnormalize_kernel"));
@@ -502,7 +658,7 @@ nys_status enqueue_all(nys_batch_s* b) {
     // s = u - alpha P^{-1} A^T (A u - y), with A^T A u - A^T y from one stencil pass
     NYS_TRY(stencil_launch(b->st_grad, b->taps, b->ctr, st));
     if (pc) NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldG, st));
-    NYS_TRY(batch_combine(d, b->pix.seg, nseg, b->pix.nblk, kFldU, kFldG, kFldS, BScal::kAlpha, st));
+    NYS_TRY(batch_combine(d, b->cmb.seg, b->cmb.nseg, b->cmb.nblk, kFldU, kFldG, kFldS, BScal::kAlpha, st));
     // x+ = prox^P_{lam_bar g}(s): accelerated projected gradient on the dual
     if (!o.warm_start) NYS_TRY(fill_zero<float>(d0.f[kFldQ], static_cast<size_t>(b->nch) * b->P, st));
     NYS_CHECK_HIP(hipMemcpyAsync(d0.f[kFldR], d0.f[kFldQ], sizeof(float) * b->nch * b->P,
@@ -514,7 +670,7 @@ nys_status enqueue_all(nys_batch_s* b) {
                          int(last ? kFldQ : kFldR), int(kFldT));
       NYS_TRY(launch_check("blt_kernel"));
       if (pc) NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldT, st));
-      NYS_TRY(batch_combine(d, b->pix.seg, nseg, b->pix.nblk, kFldS, kFldT, kFldXN, BScal::kLamBar, st));
+      NYS_TRY(batch_combine(d, b->cmb.seg, b->cmb.nseg, b->cmb.nblk, kFldS, kFldT, kFldXN, BScal::kLamBar, st));
       if (last) break;
       const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
       const double beta = (tau - 1.0) / tau_n;
@@ -533,8 +689,8 @@ nys_status enqueue_all(nys_batch_s* b) {
       NYS_TRY(stencil_launch(b->st_hx, b->taps, b->ctr, st));
       hipLaunchKernelGGL(bcost_partial_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, term);
       NYS_TRY(launch_check("bcost_partial_kernel"));
-      hipLaunchKernelGGL(bcost_tail_kernel, dim3(nseg), dim3(64), 0, st, d, b->pix.seg, k);
-      NYS_TRY(launch_check("bcost_tail_kernel"));
+      hipLaunchKernelGGL(bpart_tail_kernel, dim3(nseg), dim3(256), 0, st, d, b->pix.seg, 1, k);
+      NYS_TRY(launch_check("bpart_tail_kernel"));
     }
   }
   hipLaunchKernelGGL(bcopy_out_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg);
@@ -631,13 +787,14 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     const nys_batch_item& it = items[i];
     const int64_t N = static_cast<int64_t>(it.n1) * it.n2;
     const int ell = pc ? it.ell : 0;
-    const int ell_pad = (ell + 15) / 16 * 16;
+    // rows of U rounded to 16, 32 or 64 (zero padding) for the U^T v kernel
+    const int ell_pad = ell == 0 ? 0 : ell <= 16 ? 16 : ell <= 32 ? 32 : 64;
     const int64_t ldu = (N + 63) / 64 * 64 + (N >= 16384 ? 96 : 0);
-    // U^T v reduction: <= 256 blocks of >= 1024 pixels, chunk a multiple of 64
-    int64_t nb = std::min<int64_t>(256, std::max<int64_t>(1, (N + 1023) / 1024));
-    int64_t ch = ((N + nb - 1) / nb + 63) / 64 * 64;
+    // U^T v reduction: chunks of 8192 pixels
+    int64_t ch = 8192;
     red_nblk[i] = (N + ch - 1) / ch;
     red_chunk[i] = ch;
+    int64_t nb;
     // Gram: <= 256 chunks of >= 4096 pixels, chunk a multiple of 32;
     // 64 x 64 tile pairs of the 2 ell x 2 ell result
     nb = std::min<int64_t>(256, std::max<int64_t>(1, N / 4096));
@@ -718,6 +875,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   std::vector<int> all(count);
   for (int i = 0; i < count; ++i) all[i] = i;
   auto pixs = segs(all, [&](int i) { return (b->hd[i].N + 1023) / 1024; }, [](int) { return int64_t(1024); });
+  auto cmbs = segs(all, [&](int i) { return (b->hd[i].N + 4095) / 4096; }, [](int) { return int64_t(4096); });
   auto reds = segs(all, [&](int i) { return red_nblk[i]; }, [&](int i) { return red_chunk[i]; });
   auto upxs = segs(all, [&](int i) { return (b->hd[i].N + 255) / 256; }, [](int) { return int64_t(256); });
   auto facs = segs(all, [](int) { return int64_t(1); }, [](int) { return int64_t(0); });
@@ -769,6 +927,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     const size_t o_taps = tb.add(tapf);
     const size_t o_desc = tb.add(b->hd);
     const size_t o_pix = tb.add(pixs.first);
+    const size_t o_cmb = tb.add(cmbs.first);
     const size_t o_red = tb.add(reds.first);
     const size_t o_upx = tb.add(upxs.first);
     const size_t o_fac = tb.add(facs.first);
@@ -799,6 +958,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     b->taps = reinterpret_cast<const float*>(T + o_taps);
     b->dd = reinterpret_cast<BDesc*>(T + o_desc);
     b->pix = {reinterpret_cast<const BSeg*>(T + o_pix), static_cast<int>(pixs.first.size()), pixs.second};
+    b->cmb = {reinterpret_cast<const BSeg*>(T + o_cmb), static_cast<int>(cmbs.first.size()), cmbs.second};
     b->red = {reinterpret_cast<const BSeg*>(T + o_red), static_cast<int>(reds.first.size()), reds.second};
     b->upix = {reinterpret_cast<const BSeg*>(T + o_upx), static_cast<int>(upxs.first.size()), upxs.second};
     b->fac = {reinterpret_cast<const BSeg*>(T + o_fac), pc ? static_cast<int>(facs.first.size()) : 0, facs.second};
@@ -961,6 +1121,11 @@ extern "C" nys_status batch_solve_run(nys_batch b, void* stream) {
   NYS_REQUIRE(b && b->exec, "batch_solve_run: bad plan");
   NYS_CHECK_HIP(hipGraphLaunch(b->exec, as_stream(stream)));
   return NYS_OK;
+}
+
+extern "C" nys_status batch_solve_sketch(nys_batch b, void* stream) {
+  NYS_REQUIRE(b && b->o.precondition, "batch_solve_sketch: plan without a preconditioner");
+  return stencil_launch(b->st_sketch, b->taps, b->ctr, as_stream(stream));
 }
 
 extern "C" nys_status batch_solve_info(nys_batch b, int32_t i, double* out, void* stream) {

@@ -163,17 +163,49 @@ __global__ __launch_bounds__(1024) void ut_partial_kernel(const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------- batched
-// Block (1024 threads) -> (instance, chunk): D.part[b][k] = sum U[k][n] v[n].
-__global__ __launch_bounds__(1024) void but_partial_kernel(const BDesc* __restrict__ d,
-                                                           const BSeg* __restrict__ seg, int nseg,
-                                                           int fsrc) {
+// U^T v over one pixel chunk with all NV = 16, 32 or 64 rows of U held in
+// registers: every thread streams 16-byte runs of v and of each U row, and
+// the block reduces once at the end.  red: (blockDim / 64) * 64 doubles.
+template <int NV>
+__device__ __forceinline__ void ut_rows_body(const float* __restrict__ U, int64_t ldu,
+                                             const float* __restrict__ v, int64_t n0, int64_t n1,
+                                             double* red, double* bsum,
+                                             double* __restrict__ dst) {
+  float acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+  for (int64_t n = n0 + 4 * threadIdx.x; n < n1; n += 4 * blockDim.x) {
+    const float4 x = *reinterpret_cast<const float4*>(v + n);
+    const float* p = U + n;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const float4 u = *reinterpret_cast<const float4*>(p + k * ldu);
+      acc[k] = fmaf(u.x, x.x, fmaf(u.y, x.y, fmaf(u.z, x.z, fmaf(u.w, x.w, acc[k]))));
+    }
+  }
+  block_reduce<NV>(acc, red, bsum);
+  for (int k = threadIdx.x; k < NV; k += blockDim.x) dst[k] = bsum[k];
+}
+
+// Block (256 threads) -> (instance, chunk): D.part[b][k] = sum U[k][n] v[n].
+// Batched instances have ell_pad in {16, 32, 64} and N % 4 == 0.
+__global__ __launch_bounds__(256) void but_partial_kernel(const BDesc* __restrict__ d,
+                                                          const BSeg* __restrict__ seg, int nseg,
+                                                          int fsrc) {
+  __shared__ double red[4 * 64];
+  __shared__ double bsum[64];
   const BSeg& sg = seg[seg_find(seg, nseg, blockIdx.x)];
   const BDesc& D = d[sg.inst];
   const int64_t lb = blockIdx.x - sg.first;
   const int64_t n0 = lb * sg.chunk;
   const int64_t n1 = (n0 + sg.chunk < D.N) ? n0 + sg.chunk : D.N;
-  ut_partial_body<float>(D.U, D.ldu, D.f[fsrc], D.N, D.ell_pad, n0, n1,
-                         D.part + static_cast<size_t>(lb) * D.ell_pad);
+  double* dst = D.part + static_cast<size_t>(lb) * D.ell_pad;
+  const float* v = D.f[fsrc];
+  switch (D.ell_pad) {
+    case 16: ut_rows_body<16>(D.U, D.ldu, v, n0, n1, red, bsum, dst); break;
+    case 32: ut_rows_body<32>(D.U, D.ldu, v, n0, n1, red, bsum, dst); break;
+    default: ut_rows_body<64>(D.U, D.ldu, v, n0, n1, red, bsum, dst); break;
+  }
 }
 
 // One block per segment: D.cd[k] = d_k * sum_b D.part[b][k]  (d of eq. (6)).
@@ -187,9 +219,9 @@ __global__ __launch_bounds__(1024) void but_tail_kernel(const BDesc* __restrict_
   for (int k = threadIdx.x; k < D.ell; k += blockDim.x) D.cd[k] = D.meta[PcMeta::kD + k] * bsum[k];
 }
 
-// out = s + c (t + U cd) over 1024-pixel blocks, c = -scal[sidx] (sidx >= 0)
-// or 1; s = 0 when fs < 0; no U term without a preconditioner (ell = 0).
-// P^{-1} t = t + U (d . U^T t) (eq. (6)).
+// out = s + c (t + U cd) over the pixel chunk of a block, c = -scal[sidx]
+// (sidx >= 0) or 1; s = 0 when fs < 0; no U term without a preconditioner
+// (ell = 0).  P^{-1} t = t + U (d . U^T t) (eq. (6)).  N % 4 == 0.
 __global__ __launch_bounds__(256) void bcombine_kernel(const BDesc* __restrict__ d,
                                                        const BSeg* __restrict__ seg, int nseg,
                                                        int fs, int ft, int fout, int sidx) {
@@ -204,16 +236,29 @@ __global__ __launch_bounds__(256) void bcombine_kernel(const BDesc* __restrict__
   const float* sv = fs >= 0 ? D.f[fs] : nullptr;
   float* out = D.f[fout];
   const float* __restrict__ U = D.U;
-  const int64_t base = (blockIdx.x - sg.first) * 1024;
-  if ((D.N & 3) == 0) {
-    const int64_t n = base + 4 * threadIdx.x;
-    if (n >= D.N) return;
+  const int64_t ldu = D.ldu;
+  const int64_t n0 = (blockIdx.x - sg.first) * sg.chunk;
+  const int64_t n1 = (n0 + sg.chunk < D.N) ? n0 + sg.chunk : D.N;
+  for (int64_t n = n0 + 4 * threadIdx.x; n < n1; n += 4 * blockDim.x) {
     float4 a = *reinterpret_cast<const float4*>(t + n);
     const float* p = U + n;
-    for (int k = 0; k < L; ++k) {
+    int k = 0;
+    for (; k + 4 <= L; k += 4) {
+      const float4 u0 = *reinterpret_cast<const float4*>(p);
+      const float4 u1 = *reinterpret_cast<const float4*>(p + ldu);
+      const float4 u2 = *reinterpret_cast<const float4*>(p + 2 * ldu);
+      const float4 u3 = *reinterpret_cast<const float4*>(p + 3 * ldu);
+      const float c0 = cs[k], c1 = cs[k + 1], c2 = cs[k + 2], c3 = cs[k + 3];
+      a.x += u0.x * c0 + u1.x * c1 + u2.x * c2 + u3.x * c3;
+      a.y += u0.y * c0 + u1.y * c1 + u2.y * c2 + u3.y * c3;
+      a.z += u0.z * c0 + u1.z * c1 + u2.z * c2 + u3.z * c3;
+      a.w += u0.w * c0 + u1.w * c1 + u2.w * c2 + u3.w * c3;
+      p += 4 * ldu;
+    }
+    for (; k < L; ++k) {
       const float4 u = *reinterpret_cast<const float4*>(p);
       a.x += u.x * cs[k]; a.y += u.y * cs[k]; a.z += u.z * cs[k]; a.w += u.w * cs[k];
-      p += D.ldu;
+      p += ldu;
     }
     float4 r = make_float4(c * a.x, c * a.y, c * a.z, c * a.w);
     if (sv) {
@@ -221,20 +266,12 @@ __global__ __launch_bounds__(256) void bcombine_kernel(const BDesc* __restrict__
       r.x += s4.x; r.y += s4.y; r.z += s4.z; r.w += s4.w;
     }
     *reinterpret_cast<float4*>(out + n) = r;
-  } else {
-    for (int q = 0; q < 4; ++q) {
-      const int64_t n = base + q * 256 + threadIdx.x;
-      if (n >= D.N) break;
-      float a = t[n];
-      for (int k = 0; k < L; ++k) a += U[static_cast<size_t>(k) * D.ldu + n] * cs[k];
-      out[n] = (sv ? sv[n] : 0.f) + c * a;
-    }
   }
 }
 
 nys_status batch_pinv_coeffs(const BDesc* d, const BSeg* rseg, int nrseg, int64_t rblk, int fsrc,
                              hipStream_t st) {
-  hipLaunchKernelGGL(but_partial_kernel, dim3(static_cast<unsigned>(rblk)), dim3(1024), 0, st, d,
+  hipLaunchKernelGGL(but_partial_kernel, dim3(static_cast<unsigned>(rblk)), dim3(256), 0, st, d,
                      rseg, nrseg, fsrc);
   NYS_TRY(launch_check("but_partial_kernel"));
   hipLaunchKernelGGL(but_tail_kernel, dim3(nrseg), dim3(1024), 0, st, d, rseg);

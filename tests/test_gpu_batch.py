@@ -161,3 +161,45 @@ def test_batch_tile_table_and_errors():
     bad = dict(inst[0], ell=65)
     with pytest.raises(P.NysError):
         P.BatchSolver([bad], max_iter=1, n_inner=1, power_iters=2)
+
+
+def test_batch_rectangular_wide_psf_and_sketch_only():
+    """Rectangular images, a width that is not a multiple of 4, a PSF wider
+    than the image (the periodic halo wraps more than once), and the
+    sketch-only entry point on refilled test images."""
+    P = need_gpu()
+    banner("batch rectangular / wide PSF / sketch only")
+    shapes = [(20, 36, 5, 1.0, 4, 1e-3), (12, 9, 15, 3.0, 4, 2e-3), (70, 44, 9, 1.5, 8, 5e-4)]
+    inst = []
+    for i, (n1, n2, k, sg, ell, lam) in enumerate(shapes):
+        h = W.gaussian_psf(k, sg)
+        prob = sv.Problem("blur", n1, None, lam, "tv", h=h)
+        xt = W.phantom_blocks(max(n1, n2), 800 + i)[:n1, :n2]
+        yd = dev(prob.A(xt) + 0.01 * W.gaussian((n1, n2), 800 + i), "f32")
+        prob.y = host(yd)
+        inst.append(dict(prob=prob, psf=h, y=yd, lam=lam, ell=ell, n1=n1, n2=n2,
+                         omega=dev(W.omega(ell, n1, n2, 800 + i), "f32"),
+                         v0=dev(W.gaussian((n1, n2), 900 + i), "f32")))
+    plan = P.BatchSolver(inst, max_iter=4, n_inner=5, power_iters=30, record_costs=True)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, it in enumerate(inst):
+        n1, n2, ell, prob = it["n1"], it["n2"], it["ell"], it["prob"]
+        banner(f"batch rect instance {i} {n1}x{n2}")
+        Y, U = plan.sketch(i, n1, n2, ell)
+        om = host(it["omega"])
+        assert rel(host(Y), sv.sketch(prob, om)) < 1e-5
+        ref = onys.nystrom(host(Y).reshape(ell, -1), om.reshape(ell, -1))
+        opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+        info = plan.info(i)
+        assert rel(plan.shat(i, ell), ref["shat"]) < 1e-5
+        xr, cr = sv.wapg(prob, opc, info["alpha"], 4, inner=5, x0=np.zeros((n1, n2)))
+        assert rel(host(plan.x[i]), xr) < 1e-4
+        _check_costs(host(plan.costs[i]), cr)
+    for i, it in enumerate(inst):
+        it["omega"].copy_(dev(W.omega(it["ell"], it["n1"], it["n2"], 950 + i), "f32"))
+    plan.sketch_only()
+    torch.cuda.synchronize()
+    for i, it in enumerate(inst):
+        Y, _ = plan.sketch(i, it["n1"], it["n2"], it["ell"])
+        assert rel(host(Y), sv.sketch(it["prob"], host(it["omega"]))) < 1e-5

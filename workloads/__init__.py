@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "rng", "gaussian_psf", "phantom_blocks", "phantom_ellipses", "omega",
     "gaussian", "salt_pepper_masks", "round_bf16", "round_dtype",
-    "Workload", "WORKLOADS", "workload",
+    "Workload", "WORKLOADS", "workload", "BatchInstance", "batch_instances",
 ]
 
 
@@ -162,6 +162,7 @@ class Workload:
     huber_delta: float = 0.0
     outer: int = 100
     inner: int = 20
+    count: int = 1          # instances (the batched workload)
 
     @property
     def m_shape(self):
@@ -190,7 +191,45 @@ WORKLOADS = {
     "ct256_tv_unrolled": Workload(
         "ct256_tv_unrolled", "ct", 256, "tv", 2e-4, 48, "f32", "f32",
         views=180, bins=367, noise_rel_max=0.01, outer=20, inner=20),
+    # 64 independent deblurring problems of uneven sizes solved together;
+    # per-instance parameters from batch_instances (n and ell are maxima).
+    "batch64_deblur_f32": Workload(
+        "batch64_deblur_f32", "blur", 1024, "tv", 0.0, 64, "f32", "f32",
+        noise_sigma=0.01, outer=100, inner=20, count=64),
 }
+
+BATCH_SIZES = (128, 256, 384, 512, 768, 1024)
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchInstance:
+    """One problem of the batched workload."""
+    n: int
+    psf_k: int
+    psf_sigma: float
+    lam: float
+    ell: int
+    seed: int
+
+
+def batch_instances(count: int = 64, seed: int = 0,
+                    sizes=BATCH_SIZES) -> list:
+    """Draw the batched deblurring problems.
+
+    Side uniform over `sizes`; PSF standard deviation U[0.8, 3]; PSF size the
+    odd number 2 ceil(2.5 sigma) + 1 clipped to [5, 15]; TV weight
+    log-uniform on [5e-4, 5e-3]; sketch size uniform over {16, 32, 64}.
+    """
+    g = rng(seed, 6)
+    out = []
+    for i in range(count):
+        n = int(g.choice(np.asarray(sizes)))
+        sigma = float(g.uniform(0.8, 3.0))
+        k = int(min(15, max(5, 2 * int(np.ceil(2.5 * sigma)) + 1)))
+        lam = float(np.exp(g.uniform(np.log(5e-4), np.log(5e-3))))
+        ell = int(g.choice(np.asarray((16, 32, 64))))
+        out.append(BatchInstance(n, k, sigma, lam, ell, 1000 * seed + i))
+    return out
 
 
 def workload(name: str, **overrides) -> Workload:
