@@ -134,6 +134,7 @@ struct nys_op_s {
   nys::DevBuf psf_dev;            // [flipped psf f64 | psf f64 | flipped f32 | psf f32]
   nys::DevBuf trig;               // per view: cos, sin (f64) then (f32)
   nys::DevBuf tmp0, tmp1;         // intermediates of composed operators
+  mutable nys::DevBuf xT;         // transposed images (parallel-beam forward)
 };
 
 struct nys_pc_s {

@@ -156,84 +156,118 @@ __global__ __launch_bounds__(256) void haar_kernel(const SI* __restrict__ in,
 }
 
 // ================================================================ Joseph
-// Interpolation coordinate of the ray (s, view) at stepped-axis coordinate t:
-// (s - t * b) / a + c, with (a, b) = (cos, sin) on the row branch and
-// (sin, cos) on the column branch.  Forward and adjoint share this function
-// so both use identical weights.
-template <class C>
-__device__ __forceinline__ C joseph_coord(C s, C t, C a, C b, C c) {
-  return (s - t * b) / a + c;
-}
-
+// A view is stepped along image rows when |cos| >= |sin| (the "row branch")
+// and along columns otherwise.  With (a, b) = (cos, sin) on the row branch
+// and (sin, cos) on the column branch, the ray of detector coordinate s meets
+// the stepped line at centred coordinate t at the interpolation coordinate
+// f(t) = (s - t b) / a + c, c = (n - 1) / 2, and takes
+// (1 - w) x[q] + w x[q + 1] with q = floor(f), w = f - q, weighted 1 / |a|.
+// The forward evaluates f(t) = f0 + t g (f0 = s / a + c, g = -b / a) and
+// reads a transposed copy of the image on column-branch views, so that every
+// view walks rows and neighbouring rays read neighbouring pixels.
+// Coordinates and interpolation weights are computed in FP64 (on MI355X the
+// FP64 vector rate equals the unpacked FP32 rate); they reach a few hundred,
+// where FP32 rounding would put ~1e-5 errors into every weight.  Samples are
+// accumulated in the compute type C.
 template <class SI, class SO, class C>
 __global__ __launch_bounds__(256) void joseph_fwd_kernel(
-    const SI* __restrict__ x, SO* __restrict__ p, int n, int V, int B,
-    const C* __restrict__ trig) {
+    const SI* __restrict__ x, const SI* __restrict__ xT, SO* __restrict__ p, int n, int V, int B,
+    const double* __restrict__ trig) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   if (b >= B) return;
-  const SI* img = x + static_cast<size_t>(blockIdx.z) * n * n;
-  const C ct = trig[2 * v], st = trig[2 * v + 1];
-  const C c = C(0.5) * C(n - 1);
-  const C s = C(b) - C(0.5) * C(B - 1);
+  const double ct = trig[2 * v], st = trig[2 * v + 1];
   const bool rows = fabs(ct) >= fabs(st);
-  const C a = rows ? ct : st, bb = rows ? st : ct;
+  const double a = rows ? ct : st, bb = rows ? st : ct;
+  const SI* img = (rows ? x : xT) + static_cast<size_t>(blockIdx.z) * n * n;
+  const double c = 0.5 * (n - 1);
+  const double s = b - 0.5 * (B - 1);
+  const double ia = 1.0 / a;
+  const double f0 = s * ia + c, g = -bb * ia;
+  // steps whose coordinate can fall in [-1, n), widened by one step each way
+  // (the bounds are clamped to [-2, n + 1] before the integer conversion: a
+  // nearly axis-parallel ray has a tiny |g| and bounds far outside)
+  int t0 = 0, t1 = n - 1;
+  if (g != 0.0) {
+    double ta = (-1.0 - f0) / g + c, tb = (n - f0) / g + c;
+    if (ta > tb) { const double tt = ta; ta = tb; tb = tt; }
+    ta = fmin(fmax(ta, -2.0), n + 1.0);
+    tb = fmin(fmax(tb, -2.0), n + 1.0);
+    t0 = max(0, static_cast<int>(floor(ta)) - 1);
+    t1 = min(n - 1, static_cast<int>(ceil(tb)) + 1);
+  } else if (!(f0 >= -1.0 && f0 < n)) {
+    t1 = -1;
+  }
   C acc = 0;
-  for (int t = 0; t < n; ++t) {
-    C f = joseph_coord<C>(s, C(t) - c, a, bb, c);
-    C fl = floor(f);
-    int q = static_cast<int>(fl);
-    C w = f - fl;
+  for (int t = t0; t <= t1; ++t) {
+    const double f = f0 + (t - c) * g;
+    const double fl = floor(f);
+    const int q = static_cast<int>(fl);
+    const C w = static_cast<C>(f - fl);
     if (q >= -1 && q < n) {
-      C lo = 0, hi = 0;
-      if (rows) {
-        if (q >= 0) lo = Io<SI>::ld(img, static_cast<size_t>(t) * n + q);
-        if (q + 1 < n) hi = Io<SI>::ld(img, static_cast<size_t>(t) * n + q + 1);
-      } else {
-        if (q >= 0) lo = Io<SI>::ld(img, static_cast<size_t>(q) * n + t);
-        if (q + 1 < n) hi = Io<SI>::ld(img, static_cast<size_t>(q + 1) * n + t);
-      }
+      const SI* row = img + static_cast<size_t>(t) * n;
+      const C lo = q >= 0 ? Io<SI>::ld(row, q) : C(0);
+      const C hi = q + 1 < n ? Io<SI>::ld(row, q + 1) : C(0);
       acc += (C(1) - w) * lo + w * hi;
     }
   }
-  Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b, acc / fabs(a));
+  Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b,
+             acc * static_cast<C>(1.0 / fabs(a)));
 }
 
-// Gather-form transpose: pixel (i, j) collects, per view, the (at most two)
-// rays whose interpolation pair contains it.  Candidate bins are searched
-// around the exact inverse map and confirmed with joseph_coord.
+// out[k][j][i] = in[k][i][j] (n x n images), 32 x 32 tiles through LDS.
+template <class T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                        int n) {
+  __shared__ T tile[32][33];
+  const size_t off = static_cast<size_t>(blockIdx.z) * n * n;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx;
+    if (i < n && j < n) tile[r][tx] = in[off + static_cast<size_t>(i) * n + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = j0 + r, i = i0 + tx;
+    if (i < n && j < n) out[off + static_cast<size_t>(j) * n + i] = tile[tx][r];
+  }
+}
+
+// Gather-form transpose: pixel (i, j) has stepped coordinate t and
+// interpolated index q on each view; the rays that weight it are those with
+// |f(t) - q| < 1, i.e. the bins within |a| of its exact bin coordinate
+// bc = (q - c) a + t b + (B - 1) / 2 (at most two), with weight
+// (1 - |bin - bc| / |a|) / |a| -- the forward's interpolation weight.
 template <class SI, class SO, class C>
 __global__ __launch_bounds__(256) void joseph_adj_kernel(
     const SI* __restrict__ p, SO* __restrict__ x, int n, int V, int B,
-    const C* __restrict__ trig) {
+    const double* __restrict__ trig, const double* __restrict__ inv_abs_a) {
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= n || j >= n) return;
   const SI* sino = p + static_cast<size_t>(blockIdx.z) * V * B;
-  const C c = C(0.5) * C(n - 1);
-  const C half = C(0.5) * C(B - 1);
+  const double c = 0.5 * (n - 1);
+  const double half = 0.5 * (B - 1);
   C acc = 0;
   for (int v = 0; v < V; ++v) {
-    const C ct = trig[2 * v], st = trig[2 * v + 1];
+    const double ct = trig[2 * v], st = trig[2 * v + 1];
     const bool rows = fabs(ct) >= fabs(st);
-    const C a = rows ? ct : st, bb = rows ? st : ct;
-    // stepped coordinate t and interpolated index q of this pixel
-    const int ts = rows ? i : j, q = rows ? j : i;
-    const C t = C(ts) - c;
-    const C smid = (C(q) - c) * a + t * bb + half;
-    const int b0 = static_cast<int>(floor(smid));
+    const double a = rows ? ct : st, bb = rows ? st : ct;
+    const double ia = inv_abs_a[v], aa = fabs(a);
+    const double t = (rows ? i : j) - c;
+    const double q = (rows ? j : i) - c;
+    const double bc = q * a + t * bb + half;
+    const int b0 = static_cast<int>(floor(bc - aa)) + 1;
+    const SI* row = sino + static_cast<size_t>(v) * B;
     C part = 0;
-    for (int bq = b0 - 2; bq <= b0 + 2; ++bq) {
-      if (bq < 0 || bq >= B) continue;
-      C f = joseph_coord<C>(C(bq) - half, t, a, bb, c);
-      C fl = floor(f);
-      int qq = static_cast<int>(fl);
-      C w = f - fl;
-      C val = Io<SI>::ld(sino, static_cast<size_t>(v) * B + bq);
-      if (qq == q) part += (C(1) - w) * val;
-      else if (qq == q - 1) part += w * val;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int bq = b0 + k;
+      const double wgt = (1.0 - fabs(bq - bc) * ia) * ia;
+      if (bq >= 0 && bq < B && wgt > 0.0) part += static_cast<C>(wgt) * Io<SI>::ld(row, bq);
     }
-    acc += part / fabs(a);
+    acc += part;
   }
   Io<SO>::st(x, static_cast<size_t>(blockIdx.z) * n * n + static_cast<size_t>(i) * n + j, acc);
 }
@@ -248,10 +282,15 @@ template <> const float* psf_ptr<float>(const nys_op_s* op, bool flipped) {
   int kk = op->d.psf_size * op->d.psf_size;
   return reinterpret_cast<const float*>(op->psf_dev.as<double>() + 2 * kk) + (flipped ? 0 : kk);
 }
+// trig layout: cos, sin per view (FP64), then 1 / |a| per view (FP64), then
+// the same two tables in FP32.
 template <class C> const C* trig_ptr(const nys_op_s* op);
 template <> const double* trig_ptr<double>(const nys_op_s* op) { return op->trig.as<double>(); }
 template <> const float* trig_ptr<float>(const nys_op_s* op) {
-  return reinterpret_cast<const float*>(op->trig.as<double>() + 2 * op->d.n_views);
+  return reinterpret_cast<const float*>(op->trig.as<double>() + 3 * op->d.n_views);
+}
+template <class C> const C* inva_ptr(const nys_op_s* op) {
+  return trig_ptr<C>(op) + 2 * op->d.n_views;
 }
 
 template <class SI, class SO, class C>
@@ -298,9 +337,14 @@ template <class SI, class SO, class C>
 static nys_status launch_joseph_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t ncols,
                                     hipStream_t st) {
   const int n = op->d.n1, V = op->d.n_views, B = op->d.n_bins;
+  NYS_TRY(op->xT.ensure(sizeof(SI) * static_cast<size_t>(n) * n * ncols));
+  SI* xT = op->xT.as<SI>();
+  hipLaunchKernelGGL((transpose_kernel<SI>), dim3(cdiv(n, 32), cdiv(n, 32), static_cast<unsigned>(ncols)),
+                     dim3(256), 0, st, x, xT, n);
+  NYS_TRY(launch_check("transpose_kernel"));
   dim3 grid(cdiv(B, 256), V, static_cast<unsigned>(ncols));
-  hipLaunchKernelGGL((joseph_fwd_kernel<SI, SO, C>), grid, dim3(256), 0, st, x, p, n, V, B,
-                     trig_ptr<C>(op));
+  hipLaunchKernelGGL((joseph_fwd_kernel<SI, SO, C>), grid, dim3(256), 0, st, x, xT, p, n, V, B,
+                     trig_ptr<double>(op));
   return launch_check("joseph_fwd_kernel");
 }
 
@@ -310,7 +354,7 @@ static nys_status launch_joseph_adj(const nys_op_s* op, const SI* p, SO* x, int6
   const int n = op->d.n1, V = op->d.n_views, B = op->d.n_bins;
   dim3 grid(cdiv(n, 64), cdiv(n, 4), static_cast<unsigned>(ncols));
   hipLaunchKernelGGL((joseph_adj_kernel<SI, SO, C>), grid, dim3(256), 0, st, p, x, n, V, B,
-                     trig_ptr<C>(op));
+                     trig_ptr<double>(op), inva_ptr<double>(op));
   return launch_check("joseph_adj_kernel");
 }
 
@@ -539,20 +583,30 @@ extern "C" nys_status nys_op_create(const nys_op_desc* desc, nys_op* out) {
         return NYS_EINVAL;
       }
       op->M = static_cast<int64_t>(d.n_views) * d.n_bins;
-      std::vector<double> t64(2 * d.n_views);
-      std::vector<float> t32(2 * d.n_views);
-      for (int v = 0; v < d.n_views; ++v) {
-        double th = M_PI * v / d.n_views;
-        t64[2 * v] = std::cos(th);
-        t64[2 * v + 1] = std::sin(th);
-        t32[2 * v] = static_cast<float>(t64[2 * v]);
-        t32[2 * v + 1] = static_cast<float>(t64[2 * v + 1]);
+      // per view: cos, sin, then 1 / |a| with a the cosine on row-branch
+      // views (|cos| >= |sin|) and the sine otherwise
+      const int V = d.n_views;
+      std::vector<double> t64(3 * V);
+      std::vector<float> t32(3 * V);
+      for (int v = 0; v < V; ++v) {
+        double th = M_PI * v / V;
+        const double cv = std::cos(th), sv = std::sin(th);
+        t64[2 * v] = cv;
+        t64[2 * v + 1] = sv;
+        t32[2 * v] = static_cast<float>(cv);
+        t32[2 * v + 1] = static_cast<float>(sv);
       }
-      st = op->trig.ensure(d.n_views * 2 * (8 + 4));
+      for (int v = 0; v < V; ++v) {
+        // the kernels pick the branch from the rounded values of each precision
+        const double c64 = t64[2 * v], s64 = t64[2 * v + 1];
+        t64[2 * V + v] = 1.0 / std::fabs(std::fabs(c64) >= std::fabs(s64) ? c64 : s64);
+        const float c32 = t32[2 * v], s32 = t32[2 * v + 1];
+        t32[2 * V + v] = 1.0f / std::fabs(std::fabs(c32) >= std::fabs(s32) ? c32 : s32);
+      }
+      st = op->trig.ensure(V * 3 * (8 + 4));
       if (st == NYS_OK) {
-        hipMemcpy(op->trig.p, t64.data(), 8 * 2 * d.n_views, hipMemcpyHostToDevice);
-        hipMemcpy(op->trig.as<double>() + 2 * d.n_views, t32.data(), 4 * 2 * d.n_views,
-                  hipMemcpyHostToDevice);
+        hipMemcpy(op->trig.p, t64.data(), 8 * 3 * V, hipMemcpyHostToDevice);
+        hipMemcpy(op->trig.as<double>() + 3 * V, t32.data(), 4 * 3 * V, hipMemcpyHostToDevice);
       }
       break;
     }
@@ -576,6 +630,7 @@ extern "C" void nys_op_destroy(nys_op op) {
   if (!op) return;
   op->psf_dev.release();
   op->trig.release();
+  op->xT.release();
   op->tmp0.release();
   op->tmp1.release();
   delete op;

@@ -117,6 +117,20 @@ def test_sketch_super_resolution(dt, n, ell, k, sep):
         assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
+def test_joseph_full_size_ct_f32():
+    """512^2 image, 720 views x 736 bins (the CT workload's launch shape):
+    forward and adjoint against the oracle on a phantom and a sinogram."""
+    P = need_gpu()
+    banner("joseph full size 512^2 720x736 f32")
+    n, V, B = 512, 720, 736
+    op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=V, bins=B)
+    xd = dev(W.phantom_ellipses(n, 11), "f32")
+    p = P.op_forward(op, xd)
+    assert rel(host(p), ops.joseph(host(xd), V, B)) < TOL["f32"]
+    q = dev(W.gaussian((V, B), 12), "f32")
+    assert rel(host(P.op_adjoint(op, q)), ops.joseph_adjoint(host(q), n)) < TOL["f32"]
+
+
 def test_sketch_ct_f32():
     P = need_gpu()
     banner("sketch CT f32")
