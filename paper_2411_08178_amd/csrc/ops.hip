@@ -198,18 +198,27 @@ __global__ __launch_bounds__(256) void joseph_fwd_kernel(
   } else if (!(f0 >= -1.0 && f0 < n)) {
     t1 = -1;
   }
+  // four steps per round: the eight loads are issued before any is used
+  // (indices clamped into the image, out-of-image samples weighted 0)
   C acc = 0;
-  for (int t = t0; t <= t1; ++t) {
-    const double f = f0 + (t - c) * g;
-    const double fl = floor(f);
-    const int q = static_cast<int>(fl);
-    const C w = static_cast<C>(f - fl);
-    if (q >= -1 && q < n) {
-      const SI* row = img + static_cast<size_t>(t) * n;
-      const C lo = q >= 0 ? Io<SI>::ld(row, q) : C(0);
-      const C hi = q + 1 < n ? Io<SI>::ld(row, q + 1) : C(0);
-      acc += (C(1) - w) * lo + w * hi;
+  for (int t = t0; t <= t1; t += 4) {
+    C wl[4], wh[4], lo[4], hi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tt = min(t + u, t1);
+      const double f = f0 + (tt - c) * g;
+      const double fl = floor(f);
+      const int q = static_cast<int>(fl);
+      const C w = static_cast<C>(f - fl);
+      const bool in = t + u <= t1;
+      wl[u] = (in && q >= 0 && q < n) ? C(1) - w : C(0);
+      wh[u] = (in && q >= -1 && q + 1 < n) ? w : C(0);
+      const SI* row = img + static_cast<size_t>(tt) * n;
+      lo[u] = Io<SI>::ld(row, min(max(q, 0), n - 1));
+      hi[u] = Io<SI>::ld(row, min(max(q + 1, 0), n - 1));
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += wl[u] * lo[u] + wh[u] * hi[u];
   }
   Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b,
              acc * static_cast<C>(1.0 / fabs(a)));
@@ -249,25 +258,34 @@ __global__ __launch_bounds__(256) void joseph_adj_kernel(
   const SI* sino = p + static_cast<size_t>(blockIdx.z) * V * B;
   const double c = 0.5 * (n - 1);
   const double half = 0.5 * (B - 1);
+  // four views per round: the eight loads are issued before any is used
+  // (bins clamped into the detector, bins outside weighted 0)
   C acc = 0;
-  for (int v = 0; v < V; ++v) {
-    const double ct = trig[2 * v], st = trig[2 * v + 1];
-    const bool rows = fabs(ct) >= fabs(st);
-    const double a = rows ? ct : st, bb = rows ? st : ct;
-    const double ia = inv_abs_a[v], aa = fabs(a);
-    const double t = (rows ? i : j) - c;
-    const double q = (rows ? j : i) - c;
-    const double bc = q * a + t * bb + half;
-    const int b0 = static_cast<int>(floor(bc - aa)) + 1;
-    const SI* row = sino + static_cast<size_t>(v) * B;
-    C part = 0;
+  for (int v0 = 0; v0 < V; v0 += 4) {
+    C wt[8], val[8];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int bq = b0 + k;
-      const double wgt = (1.0 - fabs(bq - bc) * ia) * ia;
-      if (bq >= 0 && bq < B && wgt > 0.0) part += static_cast<C>(wgt) * Io<SI>::ld(row, bq);
+    for (int u = 0; u < 4; ++u) {
+      const int v = min(v0 + u, V - 1);
+      const double ct = trig[2 * v], st = trig[2 * v + 1];
+      const bool rows = fabs(ct) >= fabs(st);
+      const double a = rows ? ct : st, bb = rows ? st : ct;
+      const double ia = inv_abs_a[v], aa = fabs(a);
+      const double t = (rows ? i : j) - c;
+      const double q = (rows ? j : i) - c;
+      const double bc = q * a + t * bb + half;
+      const int b0 = static_cast<int>(floor(bc - aa)) + 1;
+      const SI* row = sino + static_cast<size_t>(v) * B;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int bq = b0 + k;
+        const double wgt = (1.0 - fabs(bq - bc) * ia) * ia;
+        const bool use = v0 + u < V && bq >= 0 && bq < B && wgt > 0.0;
+        wt[2 * u + k] = use ? static_cast<C>(wgt) : C(0);
+        val[2 * u + k] = Io<SI>::ld(row, min(max(bq, 0), B - 1));
+      }
     }
-    acc += part;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc += wt[e] * val[e];
   }
   Io<SO>::st(x, static_cast<size_t>(blockIdx.z) * n * n + static_cast<size_t>(i) * n + j, acc);
 }

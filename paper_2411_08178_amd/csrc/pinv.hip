@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "internal.hpp"
@@ -187,6 +188,39 @@ __device__ __forceinline__ void ut_rows_body(const float* __restrict__ U, int64_
   for (int k = threadIdx.x; k < NV; k += blockDim.x) dst[k] = bsum[k];
 }
 
+// Rows [0, Lp) of U (Lp a multiple of 16) in pieces of 64, 32 and 16 rows,
+// each a pass over the chunk with all its rows in registers.
+__device__ __forceinline__ void ut_rows_any(const float* __restrict__ U, int64_t ldu,
+                                            const float* __restrict__ v, int Lp, int64_t n0,
+                                            int64_t n1, double* red, double* bsum,
+                                            double* __restrict__ dst) {
+  int k0 = 0;
+  for (; k0 + 64 <= Lp; k0 += 64) {
+    ut_rows_body<64>(U + k0 * ldu, ldu, v, n0, n1, red, bsum, dst + k0);
+    __syncthreads();
+  }
+  if (k0 + 32 <= Lp) {
+    ut_rows_body<32>(U + k0 * ldu, ldu, v, n0, n1, red, bsum, dst + k0);
+    __syncthreads();
+    k0 += 32;
+  }
+  if (k0 + 16 <= Lp) ut_rows_body<16>(U + k0 * ldu, ldu, v, n0, n1, red, bsum, dst + k0);
+}
+
+// Single preconditioner, FP32 U, N % 4 == 0: block (chunk, column).
+__global__ __launch_bounds__(256) void ut_rows_kernel(const float* __restrict__ U, int64_t ldu,
+                                                      const float* __restrict__ v, int64_t N,
+                                                      int Lp, int64_t chunk,
+                                                      double* __restrict__ part) {
+  __shared__ double red[4 * 64];
+  __shared__ double bsum[64];
+  const int nblk = gridDim.x, col = blockIdx.y;
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  ut_rows_any(U, ldu, v + static_cast<size_t>(col) * N, Lp, n0, n1, red, bsum,
+              part + (static_cast<size_t>(col) * nblk + blockIdx.x) * Lp);
+}
+
 // Block (256 threads) -> (instance, chunk): D.part[b][k] = sum U[k][n] v[n].
 // Batched instances have ell_pad in {16, 32, 64} and N % 4 == 0.
 __global__ __launch_bounds__(256) void but_partial_kernel(const BDesc* __restrict__ d,
@@ -352,6 +386,16 @@ nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double*
   NYS_TRY(pc->work.ensure(sizeof(double) * static_cast<size_t>(ncols) * nblk * Lp));
   double* part = pc->work.as<double>();
   const double* coef = pc->meta.as<double>() + (inverse ? PcMeta::kD : PcMeta::kE);
+  if constexpr (std::is_same<T, float>::value) {
+    if ((pc->N & 3) == 0) {
+      hipLaunchKernelGGL(ut_rows_kernel, dim3(nblk, static_cast<unsigned>(ncols)), dim3(256), 0, st,
+                         pc->U.as<float>(), pc->ldu, v, pc->N, Lp, chunk, part);
+      NYS_TRY(launch_check("ut_rows_kernel"));
+      hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, part, nblk, L, Lp,
+                         static_cast<int>(ncols), coef, cd);
+      return launch_check("ut_tail_kernel");
+    }
+  }
   hipLaunchKernelGGL((ut_partial_kernel<T>), dim3(nblk, static_cast<unsigned>(ncols)), dim3(1024),
                      0, st, pc->U.as<T>(), pc->ldu, v, pc->N, Lp, chunk, part);
   NYS_TRY(launch_check("ut_partial_kernel"));
@@ -646,6 +690,15 @@ __device__ void ssn_set_direction(const double* __restrict__ sol, int L, double*
   }
 }
 
+// Value of v on lane `lane` (wave-uniform index) through the scalar unit.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffu), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+  return __longlong_as_double((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                              static_cast<unsigned>(lo));
+}
+
 // L <= 64, 256 threads: lane r of wave q holds J[r][16 q .. 16 q + 15] in
 // registers; the wave owning column j picks the pivot and the multipliers,
 // every wave eliminates its own columns (one barrier per column).
@@ -690,11 +743,11 @@ __device__ void lu_regs64(double* __restrict__ A, int L, double* __restrict__ st
       if (q >= qj) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          const double pc = __shfl(a[c], p, 64);
+          const double pc = readlane_f64(a[c], p);
           if (16 * q + c > j) a[c] -= f * pc;
         }
       }
-      const double rp = __shfl(rh, p, 64);
+      const double rp = readlane_f64(rh, p);
       rh -= f * rp;
     }
   }
@@ -710,8 +763,8 @@ __device__ void lu_regs64(double* __restrict__ A, int L, double* __restrict__ st
   if (q == 0) {
     double rr = rhs_s[r];
     for (int j = L - 1; j >= 0; --j) {
-      const int p = porder[j];
-      const double rp = __shfl(rr, p, 64);
+      const int p = __builtin_amdgcn_readfirstlane(porder[j]);
+      const double rp = readlane_f64(rr, p);
       const double d = rp / A[p * LP1 + j];
       if (r == 0) sol[j] = d;
       if (r < L) rr -= A[r * LP1 + j] * d;
