@@ -699,55 +699,61 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
                               static_cast<unsigned>(lo));
 }
 
-// L <= 64, 256 threads: lane r of wave q holds J[r][16 q .. 16 q + 15] in
-// registers; the wave owning column j picks the pivot and the multipliers,
-// every wave eliminates its own columns (one barrier per column).
+__device__ __forceinline__ float readlane_r(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double readlane_r(double v, int lane) { return readlane_f64(v, lane); }
+
+// L <= 64, 256 threads, arithmetic in R (float for an FP32 U: the Newton
+// direction only has to resolve F to the FP32 stopping tolerance; double
+// otherwise): lane r of wave q holds J[r][16 q .. 16 q + 15] in registers;
+// the wave owning column j picks the pivot (largest |J[r][j]| over rows not
+// yet used, lowest row on ties) and the multipliers, every wave eliminates
+// its own columns (one barrier per column).
+template <class R>
 __device__ void lu_regs64(double* __restrict__ A, int L, double* __restrict__ state) {
-  __shared__ double fbuf[2][64];
+  __shared__ R fbuf[2][64];
   __shared__ int pbuf[2];
   __shared__ int porder[64];
-  __shared__ double sol[64], rhs_s[64];
+  __shared__ double sol[64];
+  __shared__ R rhs_s[64];
   const int tid = threadIdx.x, q = tid >> 6, r = tid & 63;
   const int LP1 = L + 1;
-  double a[16];
+  R a[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     const int col = 16 * q + c;
-    a[c] = (r < L && col < L) ? A[r * LP1 + col] : (r == col ? 1.0 : 0.0);
+    a[c] = static_cast<R>((r < L && col < L) ? A[r * LP1 + col] : (r == col ? 1.0 : 0.0));
   }
-  double rh = (r < L) ? -state[SsnState::kF + r] : 0.0;   // kept by every wave
+  R rh = static_cast<R>((r < L) ? -state[SsnState::kF + r] : 0.0);   // kept by every wave
   bool used = r >= L;
 #pragma unroll
   for (int j = 0; j < 64; ++j) {
     if (j < L) {
-      constexpr int dummy = 0;
-      (void)dummy;
       const int qj = j >> 4, cj = j & 15;
       if (q == qj) {
-        double best = used ? -1.0 : fabs(a[cj]);
-        int bi = used ? -1 : r;
+        const R val = used ? R(-1) : static_cast<R>(fabs(a[cj]));
+        R m = val;
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-          const double ob = __shfl_xor(best, o, 64);
-          const int oi = __shfl_xor(bi, o, 64);
-          if (ob > best || (ob == best && oi >= 0 && (bi < 0 || oi < bi))) { best = ob; bi = oi; }
-        }
-        const double piv = __shfl(a[cj], bi, 64);
-        fbuf[j & 1][r] = (used || r == bi) ? 0.0 : a[cj] / piv;
+        for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        const unsigned long long hit = __ballot(!used && val == m);
+        const int bi = __ffsll(static_cast<unsigned long long>(hit)) - 1;
+        const R piv = readlane_r(a[cj], bi);
+        fbuf[j & 1][r] = (used || r == bi) ? R(0) : a[cj] / piv;
         if (r == 0) { pbuf[j & 1] = bi; porder[j] = bi; }
       }
       __syncthreads();
       const int p = __builtin_amdgcn_readfirstlane(pbuf[j & 1]);
-      const double f = fbuf[j & 1][r];
+      const R f = fbuf[j & 1][r];
       if (r == p) used = true;
       if (q >= qj) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          const double pc = readlane_f64(a[c], p);
+          const R pc = readlane_r(a[c], p);
           if (16 * q + c > j) a[c] -= f * pc;
         }
       }
-      const double rp = readlane_f64(rh, p);
+      const R rp = readlane_r(rh, p);
       rh -= f * rp;
     }
   }
@@ -756,18 +762,18 @@ __device__ void lu_regs64(double* __restrict__ A, int L, double* __restrict__ st
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     const int col = 16 * q + c;
-    if (r < L && col < L) A[r * LP1 + col] = a[c];
+    if (r < L && col < L) A[r * LP1 + col] = static_cast<double>(a[c]);
   }
   if (q == 0) rhs_s[r] = rh;
   __syncthreads();
   if (q == 0) {
-    double rr = rhs_s[r];
+    R rr = rhs_s[r];
     for (int j = L - 1; j >= 0; --j) {
       const int p = __builtin_amdgcn_readfirstlane(porder[j]);
-      const double rp = readlane_f64(rr, p);
-      const double d = rp / A[p * LP1 + j];
-      if (r == 0) sol[j] = d;
-      if (r < L) rr -= A[r * LP1 + j] * d;
+      const R rp = readlane_r(rr, p);
+      const R d = rp / static_cast<R>(A[p * LP1 + j]);
+      if (r == 0) sol[j] = static_cast<double>(d);
+      if (r < L) rr -= static_cast<R>(A[r * LP1 + j]) * d;
     }
   }
   __syncthreads();
@@ -830,8 +836,9 @@ __device__ void lu_wave(double* __restrict__ A, int L, double* __restrict__ stat
   ssn_set_direction(sol, L, state);
 }
 
+template <class R>
 __device__ __forceinline__ void ssn_lu(double* A, int L, double* state) {
-  if (L <= 64) lu_regs64(A, L, state);
+  if (L <= 64) lu_regs64<R>(A, L, state);
   else lu_wave(A, L, state);
 }
 
@@ -860,7 +867,7 @@ __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict
     if (gi != gj) A[gj * LP1 + gi] = meta[PcMeta::kE + gj] * sacc;
   }
   __syncthreads();
-  ssn_lu(A, L, state);
+  ssn_lu<float>(A, L, state);
 }
 
 // FP64 U: masked Gram on the vector units, one 64 x 64 output tile per block
@@ -936,7 +943,7 @@ __global__ __launch_bounds__(256) void ssn_solve_f64_kernel(const double* __rest
     A[i * (L + 1) + j] = (i == j ? 1.0 : 0.0) + meta[PcMeta::kE + i] * sacc;
   }
   __syncthreads();
-  ssn_lu(A, L, state);
+  ssn_lu<double>(A, L, state);
 }
 
 // x = soft(s - U gamma)
