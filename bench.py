@@ -171,11 +171,15 @@ def cpu_baseline(wl, k_pc, power_iters, alpha, seed=0):
     prob, _ = sv.problem_from_workload(wl, seed=seed)
     n, ell = wl.n, wl.ell
     om = W.round_dtype(W.omega(ell, n, n, seed), wl.sketch_dtype)
-    # sketch: a few columns, scaled to ell
-    ncols = 4 if wl.op == "ct" else 32
+    # sketch: a few columns, scaled to ell; the sample sizes below follow the
+    # measured cost of one A^T A application so that the leg stays bounded
     t0 = time.perf_counter()
-    for k in range(ncols):
-        prob.phi(om[k])
+    prob.phi(om[0])
+    t_phi = time.perf_counter() - t0
+    ncols = int(min(32, max(1, 6.0 // max(t_phi, 1e-3))))
+    t0 = time.perf_counter()
+    for k in range(1, ncols + 1):
+        prob.phi(om[k % ell])
     t_col = (time.perf_counter() - t0) / ncols
     # factorisation on all ell columns: its cost does not depend on the
     # values, so the sketch of a positive diagonal operator of the same shape
@@ -188,12 +192,12 @@ def cpu_baseline(wl, k_pc, power_iters, alpha, seed=0):
     pc = sv.Precond(r["U"], r["shat"], r["nu"], "sqrt")
     # power method: a few steps, scaled
     v = W.gaussian((n, n), seed, stream=7)
-    pi = 30
+    pi = int(min(30, max(1, 4.0 // max(t_phi, 1e-3))))
     t0 = time.perf_counter()
     sv.lipschitz(prob, pc, v, pi)
     t_pow = (time.perf_counter() - t0) / pi
     # WAPG: a few outer iterations, scaled
-    it = 60
+    it = int(min(60, max(1, 8.0 // max(t_phi, 1e-3))))
     t0 = time.perf_counter()
     sv.wapg(prob, pc, alpha, it, inner=wl.inner, record_cost=False)
     t_it = (time.perf_counter() - t0) / it
