@@ -191,6 +191,13 @@ WORKLOADS = {
     "ct256_tv_unrolled": Workload(
         "ct256_tv_unrolled", "ct", 256, "tv", 2e-4, 48, "f32", "f32",
         views=180, bins=367, noise_rel_max=0.01, outer=20, inner=20),
+    # l_p - l_1 deblurring by IRM (Alg. 2) with CG or Nystrom-PCG per outer
+    # iteration: 9x9 Gaussian PSF sigma 1.6, 5 % salt + 5 % pepper, p = 1
+    # (also run with p = 0.5), anisotropic TV weight lambda = 0.05, smoothing
+    # eps = 1e-6, sketch size 100, PCG tolerance 1e-4, 20 IRM iterations.
+    "irm256_l1l1_f32": Workload(
+        "irm256_l1l1_f32", "blur", 256, "tv_aniso", 0.05, 100, "f32", "f32",
+        psf_k=9, psf_sigma=1.6, noise_sigma=0.0, salt_pepper=0.05, outer=20, inner=0),
     # 64 independent deblurring problems of uneven sizes solved together;
     # per-instance parameters from batch_instances (n and ell are maxima).
     "batch64_deblur_f32": Workload(
