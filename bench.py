@@ -14,12 +14,14 @@ solve with exactly that many iterations and no cost recording.
 
 Prints one JSON line.  Usage:
     python bench.py [--steps K] [--warmup W]
-                    [--workload sr512|ct512|deblur128|batch64]
+                    [--workload sr512|ct512|deblur128|batch64|irm256]
                     [--no-cpu-baseline] [--copy-calibration]
 
 The batched workload (64 deblurring problems of uneven sizes, one graph
 launch per solve of the whole batch) times the batch to the point where every
-instance has reached the gap.
+instance has reached the gap.  The IRM workload (l_1 - l_1 deblurring by
+Alg. 2) times its fixed schedule of outer iterations with Nystrom-PCG against
+plain CG x-updates.
 """
 from __future__ import annotations
 
@@ -45,6 +47,7 @@ WORKLOAD_KEYS = {
     "ct512": "ct512_hs1_f32",
     "deblur128": "deblur128_tv_f64",
     "batch64": "batch64_deblur_f32",
+    "irm256": "irm256_l1l1_f32",
 }
 
 
@@ -386,6 +389,151 @@ def main_batch(args, P, torch, wl):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------- IRM
+def lp_objective_gpu(P, torch, op, x, y, lam, p, q, eps):
+    """Smoothed l_p - l_q objective of x (A x on the GPU, sums in FP64)."""
+    r = (P.op_forward(op, x) - y).double()
+    xd = x.double()
+    g1 = torch.zeros_like(xd)
+    g2 = torch.zeros_like(xd)
+    g1[1:, :] = xd[1:, :] - xd[:-1, :]
+    g2[:, 1:] = xd[:, 1:] - xd[:, :-1]
+    f = float(((r * r + eps) ** (p / 2)).sum()) / p
+    g = float(((g1 * g1 + eps) ** (q / 2)).sum() + ((g2 * g2 + eps) ** (q / 2)).sum()) / q
+    return f + lam * g
+
+
+def cpu_baseline_irm(wl, h, y_host, its_pc, seed=0):
+    """The FP64 oracle on a bounded sample (the sketch of Phi_1, Alg. 1, a few
+    PCG steps), extrapolated to the GPU run's step counts (seconds)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import irm as oi
+    from oracle import nystrom as onys
+    from oracle import operators as ops
+    n, ell, eps = wl.n, wl.ell, 1e-6
+    A = lambda v: ops.blur(v, h)
+    At = lambda v: ops.blur_adjoint(v, h)
+    x = np.zeros((n, n))
+    wf = oi.weights(A(x) - y_host, 1.0, eps)
+    wg = oi.weights(ops.grad(x), 1.0, eps)
+    phi = lambda v: (At(wf * A(v.reshape(n, n))) +
+                     wl.lam * ops.grad_adjoint(wg * ops.grad(v.reshape(n, n)))).reshape(-1)
+    om = W.round_dtype(W.omega(ell, n, n, seed), "f32")
+    ncols = 8
+    t0 = time.perf_counter()
+    Y = np.stack([phi(om[k]) for k in range(ncols)])
+    t_col = (time.perf_counter() - t0) / ncols
+    Yfull = np.concatenate([Y, (0.5 + W.gaussian((ell - ncols, 1), seed, 9) ** 2) *
+                            om[ncols:].reshape(ell - ncols, -1)])
+    t0 = time.perf_counter()
+    r = onys.nystrom(Yfull, om.reshape(ell, -1))
+    t_fac = time.perf_counter() - t0
+    b = At(wf * y_host).reshape(-1)
+    pinv = lambda v: onys.pinv_apply(v, r["U"], r["shat"], r["nu"], "plain")
+    steps = 30
+    t0 = time.perf_counter()
+    oi.pcg(phi, b, np.zeros(n * n), 1e-30, steps, pinv)
+    t_step = (time.perf_counter() - t0) / steps
+    total = len(its_pc) * (t_col * ell + t_fac) + sum(its_pc) * t_step
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return dict(value=total, unit="s", cores=threads, kind="oracle",
+                sample=(f"oracle: {ncols} sketch columns of Phi_1 (x{ell}), Alg. 1 on a full-size "
+                        f"stand-in, {steps} PCG steps; extrapolated to {len(its_pc)} outer "
+                        f"iterations and {sum(its_pc)} PCG steps; numpy/scipy FP64, BLAS threads "
+                        f"{threads}"),
+                parts=dict(sketch_col_s=t_col, factor_s=t_fac, pcg_step_s=t_step))
+
+
+def main_irm(args, P, torch, wl):
+    n = wl.n
+    h = W.gaussian_psf(wl.psf_k, wl.psf_sigma)
+    op = P.Operator(P.OP_BLUR, n, n, psf=h)
+    xt = torch.from_numpy(W.phantom_blocks(n, args.seed)).float().cuda()
+    y = P.op_forward(op, xt)
+    salt, pepper = W.salt_pepper_masks((n, n), args.seed, wl.salt_pepper)
+    y[torch.from_numpy(salt).cuda()] = 1.0
+    y[torch.from_numpy(pepper).cuda()] = 0.0
+    y = y.contiguous()
+    om = torch.from_numpy(W.omega(wl.ell, n, n, args.seed)).float().cuda().contiguous()
+    eps, p, q, tol, outer = 1e-6, args.irm_p, 1.0, 1e-4, wl.outer
+    log(f"workload {wl.name}: n={n} ell={wl.ell} p={p} outer={outer} PCG tol={tol}")
+    stream = torch.cuda.current_stream()
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+
+    def run(omega):
+        return P.irm_solve(op, y, wl.lam, p=p, q=q, eps=eps, max_outer=outer, max_cg=20000,
+                           cg_tol=tol, omega=omega)
+
+    def timed(omega):
+        for _ in range(args.warmup):
+            run(omega)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        for _ in range(args.steps):
+            x, its = run(omega)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        return t_start.elapsed_time(t_end) / args.steps, x, its
+
+    ms_pc, x_pc, its_pc = timed(om)
+    ms_cg, x_cg, its_cg = timed(None)
+    f_pc = lp_objective_gpu(P, torch, op, x_pc, y, wl.lam, p, q, eps)
+    f_cg = lp_objective_gpu(P, torch, op, x_cg, y, wl.lam, p, q, eps)
+    log(f"PCG {ms_pc:.1f} ms ({sum(its_pc)} steps), CG {ms_cg:.1f} ms ({sum(its_cg)} steps); "
+        f"objective {f_pc:.8g} vs {f_cg:.8g}")
+    # roofline: one P^{-1} application (two passes over U, ell x N FP32)
+    Yb = P.nys_sketch(op, om)
+    pc = P.nys_factor(om, Yb, wl.ell, u_dtype=torch.float32, tail="plain")
+    v = torch.randn(n, n, device="cuda")
+    out = torch.empty_like(v)
+    P.nys_apply(pc, v, out=out)
+    torch.cuda.synchronize()
+    burst = 50
+    t_start.record(stream)
+    for _ in range(burst):
+        P.nys_apply(pc, v, out=out)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ap_ms = t_start.elapsed_time(t_end) / burst
+    ap_bytes = 2 * 4 * wl.ell * n * n + 3 * 4 * n * n
+    achieved = ap_bytes / (ap_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "P^-1 application (U^T v, then v + U c; U is ell x N FP32)",
+            "bytes_per_launch": ap_bytes, "avg_launch_us": round(ap_ms * 1e3, 2)}
+    roof["measured_copy_peak"] = copy_peak(torch)
+    roof["frac_of_copy_peak"] = round(achieved / roof["measured_copy_peak"], 4)
+    out_j = {
+        "metric": "IRM wall time (Alg. 2, fixed outer iterations, CG tol 1e-4): Nystrom-PCG vs CG",
+        "value": round(ms_pc / 1e3, 6),
+        "unit": "s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_pc, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": n, "ell": wl.ell, "p": p, "q": q, "eps": eps,
+                   "lambda": wl.lam, "outer": outer, "cg_tol": tol, "psf": [wl.psf_k, wl.psf_sigma],
+                   "salt_pepper": wl.salt_pepper, "seed": args.seed, "tail": "plain"},
+        "plain_cg_s": round(ms_cg / 1e3, 6),
+        "speedup_vs_plain": round(ms_cg / ms_pc, 4),
+        "saved_time": round((ms_cg - ms_pc) / ms_cg, 4),
+        "cg_steps": {"pcg_total": int(sum(its_pc)), "cg_total": int(sum(its_cg)),
+                     "pcg": its_pc, "cg": its_cg},
+        "objective": {"pcg": f_pc, "cg": f_cg},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out_j["cpu_baseline"] = cpu_baseline_irm(wl, h, y.double().cpu().numpy(), its_pc, args.seed)
+        log(f"cpu baseline leg took {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(out_j), flush=True)
+
+
 # ---------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
@@ -399,6 +547,8 @@ def main():
                     help="iterations of the untimed F* runs of both methods")
     ap.add_argument("--tail", default="sqrt", choices=["sqrt", "plain"],
                     help="s_K in P: its square root (the paper's heuristic) or itself")
+    ap.add_argument("--irm-p", type=float, default=1.0,
+                    help="data-term exponent p of the IRM workload (the paper runs 0.5 ... 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
@@ -431,6 +581,8 @@ def main():
         if args.ref_iters == 20000:
             args.ref_iters = 300
         return main_batch(args, P, torch, wl)
+    if wl.name.startswith("irm"):
+        return main_irm(args, P, torch, wl)
     log(f"workload {wl.name}: n={wl.n} ell={wl.ell} sketch={wl.sketch_dtype} solver={wl.dtype}")
     S = Setup(P, torch, wl, args.seed)
     torch.cuda.synchronize()

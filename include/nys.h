@@ -344,6 +344,40 @@ nys_status batch_solve_tiles(nys_batch b, int32_t* nt_r, int32_t* nt_c, int32_t*
                              int32_t cap, int32_t* count);
 void batch_solve_destroy(nys_batch b);
 
+/* ---------------------------------------------------------------------------
+ * l_p - l_q reconstruction by the alternating minimisation method (Alg. 2):
+ *   min_x 1/p sum_m |(A x - y)_m|^p + lambda/q sum_l |(L x)_l|^q
+ * with L the first differences of the TV regulariser (each component its own
+ * group; prob->reg is not used) and |r| smoothed to sqrt(r^2 + eps).  Outer
+ * iteration k sets W_f = |A x - y|^{p-2}, W_g = |L x|^{q-2} (element-wise) at
+ * the previous iterate and solves Phi_k x = A^T W_f y,
+ * Phi_k = A^T W_f A + lambda L^T W_g L, by conjugate gradients from the
+ * previous iterate until ||b - Phi_k x|| <= cg_tol ||b|| or max_cg steps.  With
+ * ell > 0 the CG is preconditioned by the Nystrom P of eq. (6), rebuilt at
+ * every outer iteration from Y = Phi_k Omega (Alg. 1).  Stops after
+ * max_outer iterations or when ||x_k - x_{k-1}|| <= outer_tol ||x_k||.
+ * Synchronises `stream` (CG scalars are read back every step).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double p, q;          /* exponents of the data and regulariser terms, in (0, 2] */
+  double eps;           /* smoothing, > 0 */
+  int32_t max_outer;    /* outer (IRM) iterations */
+  double outer_tol;     /* relative change that stops the outer loop (0: never) */
+  int32_t max_cg;       /* CG steps per outer iteration */
+  double cg_tol;        /* relative residual of the x-update */
+  int32_t nu_mode;      /* as nys_factor_opts */
+  int32_t tail;         /* as nys_factor_opts; 1 = s_K as printed in eq. (6) */
+  double mu;            /* < 0: mu = nu */
+} nys_irm_opts;
+
+/* x (N values, dtype dt = F64 or F32) from x0 (N values, or NULL for 0);
+ * omega: ell x N test images (dtype dt) or NULL with ell = 0 (plain CG).
+ * cg_iters (host, max_outer entries, may be NULL) receives the CG steps of
+ * every outer iteration and *outer_done (host, may be NULL) their count. */
+nys_status irm_solve(const nys_problem* prob, nys_dtype dt, const nys_irm_opts* opts,
+                     const void* omega, int64_t ell, const void* x0, void* x,
+                     int32_t* cg_iters, int32_t* outer_done, void* stream);
+
 /* F(x) = f(x) + lambda g(x) for one column, FP64 accumulation, written to the
  * device double `cost`. */
 nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void* x,

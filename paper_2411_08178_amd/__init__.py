@@ -12,4 +12,5 @@ from ._binding import (  # noqa: F401
     F64, F32, BF16, OP_BLUR, OP_BLURDOWN, OP_PARALLEL_BEAM, OP_IDENTITY,
     REG_TV, REG_TV_ANISO, REG_HS1, REG_L1, LOSS_LS, LOSS_HUBER,
     OpForwardFn, OpAdjointFn, PinvFn, UnrolledWAPGFn, unrolled_wapg, BatchSolver,
+    irm_solve,
 )

@@ -60,6 +60,13 @@ class UnrollOpts(C.Structure):
     _fields_ = [("n_outer", C.c_int32), ("n_inner", C.c_int32), ("alpha", C.c_double)]
 
 
+class IrmOpts(C.Structure):
+    _fields_ = [("p", C.c_double), ("q", C.c_double), ("eps", C.c_double),
+                ("max_outer", C.c_int32), ("outer_tol", C.c_double), ("max_cg", C.c_int32),
+                ("cg_tol", C.c_double), ("nu_mode", C.c_int32), ("tail", C.c_int32),
+                ("mu", C.c_double)]
+
+
 class BatchItem(C.Structure):
     _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("psf_k", C.c_int32),
                 ("psf", C.POINTER(C.c_double)), ("ell", C.c_int32), ("lam", C.c_double),
@@ -110,6 +117,8 @@ def lib():
                                  C.POINTER(dbl), vp, vp, C.c_size_t, vp],
             "unrolled_backward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
                                   C.POINTER(dbl), vp, vp, C.POINTER(dbl), vp, C.c_size_t, vp],
+            "irm_solve": [C.POINTER(Problem), i32, C.POINTER(IrmOpts), vp, i64, vp, vp,
+                          C.POINTER(i32), C.POINTER(i32), vp],
             "batch_solve_create": [C.POINTER(BatchItem), i32, C.POINTER(BatchOpts),
                                    C.POINTER(vp), vp],
             "batch_solve_run": [vp, vp],
@@ -524,3 +533,25 @@ class BatchSolver:
         if self.handle is not None and _lib is not None:
             _lib.batch_solve_destroy(self.handle)
             self.handle = None
+
+
+def irm_solve(op: Operator, y: torch.Tensor, lam: float, p: float = 1.0, q: float = 1.0,
+              eps: float = 1e-6, max_outer: int = 20, outer_tol: float = 0.0,
+              max_cg: int = 1000, cg_tol: float = 1e-4, omega: Optional[torch.Tensor] = None,
+              x0: Optional[torch.Tensor] = None, tail: str = "plain", mu: float = -1.0,
+              nu_mode: int = 0):
+    """l_p - l_q reconstruction by Alg. 2 (CG, or Nystrom-PCG when omega is
+    given).  Returns (x, cg_iterations_per_outer_iteration)."""
+    dt = _dt(y)
+    n1, n2 = op.n1, op.n2
+    x = torch.empty((n1, n2), dtype=y.dtype, device=y.device)
+    rd = reg_desc("tv_aniso", n1, n2)
+    prob = _problem(op, y, rd, lam, LOSS_LS, 0.0)
+    o = IrmOpts(p, q, eps, max_outer, outer_tol, max_cg, cg_tol, nu_mode,
+                0 if tail == "sqrt" else 1, mu)
+    its = (C.c_int32 * max_outer)()
+    done = C.c_int32()
+    ell = 0 if omega is None else omega.shape[0]
+    _check(lib().irm_solve(C.byref(prob), dt, C.byref(o), _ptr(omega), ell, _ptr(x0), _ptr(x),
+                           its, C.byref(done), _stream()))
+    return x, [its[i] for i in range(done.value)]

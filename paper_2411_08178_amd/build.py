@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnys.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["ops.hip", "sketch_sr.hip", "factor.hip", "pinv.hip", "prox.hip", "solve.hip", "unrolled.hip",
-           "batch.hip"]
+           "batch.hip", "irm.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -834,6 +834,26 @@ nys_status batch_factor_enqueue(const BDesc* d, const BLaunch& gram, const BLaun
   return launch_check("bform_u_kernel");
 }
 
+// Alg. 1 steps 3-8 again on a handle made by nys_factor for the same N, ell
+// and storage type, reusing its buffers (U's padding rows stay zero).
+nys_status factor_refresh(nys_pc pc, const void* omega, const void* Y, nys_dtype in_dt,
+                          const nys_factor_opts& o, hipStream_t st) {
+  pc->pinv_norm_cache = -1.0;
+  pc->tail = o.tail;
+  const int L = static_cast<int>(pc->ell);
+  switch (in_dt) {
+    case NYS_F64:
+      return factor_impl<double>(static_cast<const double*>(omega), static_cast<const double*>(Y),
+                                 pc->N, L, o, pc, st);
+    case NYS_F32:
+      return factor_impl<float>(static_cast<const float*>(omega), static_cast<const float*>(Y),
+                                pc->N, L, o, pc, st);
+    default:
+      set_error("factor_refresh: dtype must be F64 or F32");
+      return NYS_EINVAL;
+  }
+}
+
 }  // namespace nys
 
 using namespace nys;

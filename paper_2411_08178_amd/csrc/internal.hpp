@@ -57,6 +57,11 @@ struct PcMeta {
   static constexpr int kTotal = kScalars + 16;
 };
 
+// Alg. 1 steps 3-8 on an existing handle of the same N, ell and dtype
+// (factor.hip).
+nys_status factor_refresh(nys_pc pc, const void* omega, const void* Y, nys_dtype in_dt,
+                          const nys_factor_opts& o, hipStream_t st);
+
 // Weighted prox (prox.hip).  state as in prox_weighted.
 template <class T>
 nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,

@@ -1,0 +1,91 @@
+"""IRM (Alg. 2) with CG and with Nystrom-PCG x-updates against the FP64
+oracle: the CG step counts of every outer iteration and the iterate."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_util import banner, dev, host, need_gpu, rel
+from oracle import irm as oi
+from oracle import operators as ops
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n, seed, k=7, sigma=1.6):
+    h = W.gaussian_psf(k, sigma)
+    xt = W.phantom_blocks(n, seed)
+    y = ops.blur(xt, h)
+    salt, pepper = W.salt_pepper_masks(y.shape, seed, 0.05)
+    y = np.where(salt, 1.0, np.where(pepper, 0.0, y))
+    return h, y
+
+
+@pytest.mark.parametrize("with_pc", [False, True])
+@pytest.mark.parametrize("p", [1.0, 0.5])
+def test_irm_f64_matches_oracle(with_pc, p):
+    P = need_gpu()
+    banner(f"irm f64 p={p} pc={with_pc}")
+    n, lam, eps, ell = 32, 0.03, 1e-4, 16
+    h, y = _problem(n, 41)
+    op = P.Operator(P.OP_BLUR, n, n, psf=h)
+    yd = dev(y)
+    om = W.omega(ell, n, n, 42) if with_pc else None
+    x, its = P.irm_solve(op, yd, lam, p=p, q=1.0, eps=eps, max_outer=5, max_cg=800,
+                         cg_tol=1e-8, omega=dev(om) if with_pc else None)
+    A = lambda v: ops.blur(v, h)
+    At = lambda v: ops.blur_adjoint(v, h)
+    ref = oi.irm(A, At, host(yd), lam, p, 1.0, eps, np.zeros((n, n)), 5, 0.0, 1e-8, 800,
+                 omega=om, tail="plain")
+    # the stopping test ||r|| <= 1e-8 ||b|| is a threshold decision taken after
+    # 50-300 CG steps whose rounding differs between the two sides (CG on these
+    # ill-conditioned systems amplifies it, more so for the non-convex p = 0.5
+    # whose weights reach eps^(-3/4) = 1e3): step counts agree within 2 % (at
+    # least one step), and the iterates differ at the level the tolerance
+    # leaves open
+    assert rel(host(x), ref.x) < 1e-6, rel(host(x), ref.x)
+    assert len(its) == len(ref.cg_iters)
+    assert all(abs(a - b) <= max(1, 0.02 * b) for a, b in zip(its, ref.cg_iters)), \
+        (its, ref.cg_iters)
+
+
+def test_irm_f32_pcg_tolerance_1e4():
+    """FP32 at the workload's PCG tolerance: the iterate within FP32 CG
+    rounding of the oracle's and the same step counts up to a few."""
+    P = need_gpu()
+    banner("irm f32 pc")
+    n, lam, eps, ell = 48, 0.05, 1e-6, 24
+    h, y = _problem(n, 43, k=9)
+    op = P.Operator(P.OP_BLUR, n, n, psf=h)
+    yd = dev(y, "f32")
+    om = W.round_dtype(W.omega(ell, n, n, 44), "f32")
+    x, its = P.irm_solve(op, yd, lam, p=1.0, q=1.0, eps=eps, max_outer=4, max_cg=1000,
+                         cg_tol=1e-4, omega=dev(om, "f32"))
+    A = lambda v: ops.blur(v, h)
+    At = lambda v: ops.blur_adjoint(v, h)
+    ref = oi.irm(A, At, host(yd), lam, 1.0, 1.0, eps, np.zeros((n, n)), 4, 0.0, 1e-4, 1000,
+                 omega=om, tail="plain")
+    assert len(its) == len(ref.cg_iters)
+    assert all(abs(a - b) <= max(3, 0.1 * b) for a, b in zip(its, ref.cg_iters))
+    assert rel(host(x), ref.x) < 2e-3
+
+
+def test_irm_pcg_needs_fewer_steps_and_reaches_the_same_objective():
+    """Property at a larger size (96^2, sketch 64): the preconditioned
+    x-updates take fewer CG steps, and both runs reach the same smoothed
+    objective within the CG tolerance's effect."""
+    P = need_gpu()
+    banner("irm pcg vs cg 96^2")
+    n, lam, eps, ell = 96, 0.05, 1e-6, 64
+    h, y = _problem(n, 45, k=9)
+    op = P.Operator(P.OP_BLUR, n, n, psf=h)
+    yd = dev(y, "f32")
+    om = dev(W.omega(ell, n, n, 46), "f32")
+    x1, it1 = P.irm_solve(op, yd, lam, eps=eps, max_outer=6, cg_tol=1e-4, max_cg=3000)
+    x2, it2 = P.irm_solve(op, yd, lam, eps=eps, max_outer=6, cg_tol=1e-4, max_cg=3000, omega=om)
+    assert sum(it2) < sum(it1)
+    A = lambda v: ops.blur(v, h)
+    f1 = oi.lp_objective(host(x1), A, host(yd), lam, 1.0, 1.0, eps)
+    f2 = oi.lp_objective(host(x2), A, host(yd), lam, 1.0, 1.0, eps)
+    assert abs(f1 - f2) <= 1e-3 * abs(f1)
+    assert torch.isfinite(x2).all()
