@@ -411,7 +411,7 @@ def cpu_baseline_irm(wl, h, y_host, its_pc, seed=0):
     from oracle import irm as oi
     from oracle import nystrom as onys
     from oracle import operators as ops
-    n, ell, eps = wl.n, wl.ell, 1e-6
+    n, ell, eps = wl.n, wl.ell, wl.smooth_eps
     A = lambda v: ops.blur(v, h)
     At = lambda v: ops.blur_adjoint(v, h)
     x = np.zeros((n, n))
@@ -456,7 +456,7 @@ def main_irm(args, P, torch, wl):
     y[torch.from_numpy(pepper).cuda()] = 0.0
     y = y.contiguous()
     om = torch.from_numpy(W.omega(wl.ell, n, n, args.seed)).float().cuda().contiguous()
-    eps, p, q, tol, outer = 1e-6, args.irm_p, 1.0, 1e-4, wl.outer
+    eps, p, q, tol, outer = wl.smooth_eps, args.irm_p, 1.0, 1e-4, wl.outer
     log(f"workload {wl.name}: n={n} ell={wl.ell} p={p} outer={outer} PCG tol={tol}")
     stream = torch.cuda.current_stream()
     t_start = torch.cuda.Event(enable_timing=True)

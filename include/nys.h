@@ -373,10 +373,12 @@ typedef struct {
 /* x (N values, dtype dt = F64 or F32) from x0 (N values, or NULL for 0);
  * omega: ell x N test images (dtype dt) or NULL with ell = 0 (plain CG).
  * cg_iters (host, max_outer entries, may be NULL) receives the CG steps of
- * every outer iteration and *outer_done (host, may be NULL) their count. */
+ * every outer iteration and *outer_done (host, may be NULL) their count;
+ * info (host, 3 * max_outer doubles, may be NULL) receives per outer
+ * iteration the factorisation status (nys_status), k_eff and the shift nu. */
 nys_status irm_solve(const nys_problem* prob, nys_dtype dt, const nys_irm_opts* opts,
                      const void* omega, int64_t ell, const void* x0, void* x,
-                     int32_t* cg_iters, int32_t* outer_done, void* stream);
+                     int32_t* cg_iters, int32_t* outer_done, double* info, void* stream);
 
 /* F(x) = f(x) + lambda g(x) for one column, FP64 accumulation, written to the
  * device double `cost`. */

@@ -118,7 +118,7 @@ def lib():
             "unrolled_backward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
                                   C.POINTER(dbl), vp, vp, C.POINTER(dbl), vp, C.c_size_t, vp],
             "irm_solve": [C.POINTER(Problem), i32, C.POINTER(IrmOpts), vp, i64, vp, vp,
-                          C.POINTER(i32), C.POINTER(i32), vp],
+                          C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl), vp],
             "batch_solve_create": [C.POINTER(BatchItem), i32, C.POINTER(BatchOpts),
                                    C.POINTER(vp), vp],
             "batch_solve_run": [vp, vp],
@@ -539,7 +539,7 @@ def irm_solve(op: Operator, y: torch.Tensor, lam: float, p: float = 1.0, q: floa
               eps: float = 1e-6, max_outer: int = 20, outer_tol: float = 0.0,
               max_cg: int = 1000, cg_tol: float = 1e-4, omega: Optional[torch.Tensor] = None,
               x0: Optional[torch.Tensor] = None, tail: str = "plain", mu: float = -1.0,
-              nu_mode: int = 0):
+              nu_mode: int = 0, return_info: bool = False):
     """l_p - l_q reconstruction by Alg. 2 (CG, or Nystrom-PCG when omega is
     given).  Returns (x, cg_iterations_per_outer_iteration)."""
     dt = _dt(y)
@@ -550,8 +550,13 @@ def irm_solve(op: Operator, y: torch.Tensor, lam: float, p: float = 1.0, q: floa
     o = IrmOpts(p, q, eps, max_outer, outer_tol, max_cg, cg_tol, nu_mode,
                 0 if tail == "sqrt" else 1, mu)
     its = (C.c_int32 * max_outer)()
+    info = (C.c_double * (3 * max_outer))()
     done = C.c_int32()
     ell = 0 if omega is None else omega.shape[0]
     _check(lib().irm_solve(C.byref(prob), dt, C.byref(o), _ptr(omega), ell, _ptr(x0), _ptr(x),
-                           its, C.byref(done), _stream()))
+                           its, C.byref(done), info, _stream()))
+    if return_info:
+        fac = [dict(status=int(info[3 * i]), k_eff=int(info[3 * i + 1]), nu=info[3 * i + 2])
+               for i in range(done.value)] if ell else []
+        return x, [its[i] for i in range(done.value)], fac
     return x, [its[i] for i in range(done.value)]

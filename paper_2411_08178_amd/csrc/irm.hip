@@ -232,7 +232,8 @@ struct Irm {
 
 template <class T>
 nys_status irm_impl(const nys_problem& p, const nys_irm_opts& o, const T* omega, int64_t ell,
-                    const T* x0, T* x, int32_t* cg_iters, int32_t* outer_done, hipStream_t st) {
+                    const T* x0, T* x, int32_t* cg_iters, int32_t* outer_done, double* info,
+                    hipStream_t st) {
   Irm<T> w(p, st);
   NYS_TRY(w.alloc());
   const int64_t N = w.N, M = w.M;
@@ -275,6 +276,15 @@ nys_status irm_impl(const nys_problem& p, const nys_irm_opts& o, const T* omega,
       } else {
         status = factor_refresh(pc, omega, Y, dt, fo, st);
         if (status != NYS_OK) { nys_pc_destroy(pc); return status; }
+      }
+      if (info) {
+        double nu = 0;
+        int32_t keff = 0, fst = 0;
+        status = nys_pc_info(pc, nullptr, &nu, &keff, &fst, st);
+        if (status != NYS_OK) { nys_pc_destroy(pc); return status; }
+        info[3 * (k - 1) + 0] = fst;
+        info[3 * (k - 1) + 1] = keff;
+        info[3 * (k - 1) + 2] = nu;
       }
     }
     // PCG from x
@@ -331,7 +341,8 @@ using namespace nys;
 
 extern "C" nys_status irm_solve(const nys_problem* prob, nys_dtype dt, const nys_irm_opts* opts,
                                 const void* omega, int64_t ell, const void* x0, void* x,
-                                int32_t* cg_iters, int32_t* outer_done, void* stream) {
+                                int32_t* cg_iters, int32_t* outer_done, double* info,
+                                void* stream) {
   NYS_REQUIRE(prob && prob->op && prob->y && opts && x, "irm_solve: bad argument");
   NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "irm_solve: dtype must be F64 or F32");
   const nys_irm_opts& o = *opts;
@@ -349,8 +360,8 @@ extern "C" nys_status irm_solve(const nys_problem* prob, nys_dtype dt, const nys
   if (dt == NYS_F64)
     return irm_impl<double>(*prob, o, static_cast<const double*>(omega), ell,
                             static_cast<const double*>(x0), static_cast<double*>(x), cg_iters,
-                            outer_done, st);
+                            outer_done, info, st);
   return irm_impl<float>(*prob, o, static_cast<const float*>(omega), ell,
                          static_cast<const float*>(x0), static_cast<float*>(x), cg_iters,
-                         outer_done, st);
+                         outer_done, info, st);
 }
