@@ -218,7 +218,6 @@ typedef struct {
   int32_t power_iters;     /* power-method steps (alpha <= 0) */
   const void* power_v0;    /* N start values, solver dtype (alpha <= 0) */
   int32_t warm_start;      /* keep Q / gamma across outer iterations */
-  int32_t use_graph;       /* capture one outer iteration in a hipGraph */
 } nys_solve_opts;
 
 /* x_out: N values (solver dtype dt = F64 or F32).  costs: device, max_iter

@@ -53,7 +53,7 @@ class Problem(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("alpha", C.c_double), ("safety", C.c_double),
                 ("power_iters", C.c_int32), ("power_v0", C.c_void_p),
-                ("warm_start", C.c_int32), ("use_graph", C.c_int32)]
+                ("warm_start", C.c_int32)]
 
 
 class UnrollOpts(C.Structure):
@@ -339,12 +339,12 @@ def _problem(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, loss: int,
 def solve(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, pc: Optional[Preconditioner],
           max_iter: int, alpha: float = -1.0, power_v0: Optional[torch.Tensor] = None,
           power_iters: int = 100, safety: float = 1.01, loss: int = LOSS_LS, delta: float = 0.0,
-          warm_start: bool = True, record_cost: bool = True, use_graph: bool = False):
+          warm_start: bool = True, record_cost: bool = True):
     """WAPG (plain APG when pc is None).  Returns (x, costs or None, info)."""
     p = _problem(op, y, reg, lam, loss, delta)
     o = SolveOpts(max_iter, alpha, safety, power_iters,
                   power_v0.data_ptr() if power_v0 is not None else None,
-                  1 if warm_start else 0, 1 if use_graph else 0)
+                  1 if warm_start else 0)
     x = torch.empty((op.n1, op.n2), dtype=y.dtype, device=y.device)
     costs = torch.empty(max(max_iter, 1), dtype=torch.float64, device=y.device) if record_cost else None
     info = (C.c_double * 8)()
