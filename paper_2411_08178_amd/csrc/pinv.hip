@@ -502,26 +502,32 @@ __global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restric
                                                          int L, const double* __restrict__ meta,
                                                          double* __restrict__ state, double tol,
                                                          int max_halvings) {
-  __shared__ double red[512];
+  __shared__ double red[512], red2[512];
   __shared__ double bsum[PcMeta::kMaxEll];
   __shared__ double Ft[PcMeta::kMaxEll];
   __shared__ int accepted;
+  __shared__ double tn_s;
   if (state[SsnState::kDone] != 0.0) return;
   tail_sum(part, nblk, L, red, bsum);
-  double sq = 0;
+  double sq = 0, gq = 0;
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
-    const double f = state[SsnState::kTry + k] - meta[PcMeta::kE + k] * bsum[k];
+    const double tk = state[SsnState::kTry + k];
+    const double f = tk - meta[PcMeta::kE + k] * bsum[k];
     Ft[k] = f;
     sq += f * f;
+    gq += tk * tk;
   }
   red[threadIdx.x] = sq;
+  red2[threadIdx.x] = gq;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (threadIdx.x < o) {
+      red[threadIdx.x] += red[threadIdx.x + o];
+      red2[threadIdx.x] += red2[threadIdx.x + o];
+    }
     __syncthreads();
   }
-  const double nFt = sqrt(red[0]);
-  __syncthreads();
+  const double nFt = sqrt(red[0]), gn = sqrt(red2[0]);
   if (threadIdx.x == 0) {
     state[SsnState::kTrials] += 1.0;
     const bool have = state[SsnState::kHave] != 0.0;
@@ -532,25 +538,26 @@ __global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restric
     if (accept) {
       state[SsnState::kHave] = 1.0;
       state[SsnState::kNF] = nFt;
-      double gn = 0;
-      for (int k = 0; k < L; ++k) gn += state[SsnState::kTry + k] * state[SsnState::kTry + k];
-      if (nFt <= tol * (1.0 + sqrt(gn)) || !isfinite(nFt)) state[SsnState::kDone] = 1.0;
+      if (nFt <= tol * (1.0 + gn) || !isfinite(nFt)) state[SsnState::kDone] = 1.0;
       else state[SsnState::kNeedGram] = 1.0;
     } else {
-      const double tn = 0.5 * t;
-      state[SsnState::kT] = tn;
+      tn_s = 0.5 * t;
+      state[SsnState::kT] = tn_s;
       state[SsnState::kHalv] += 1.0;
-      for (int k = 0; k < L; ++k)
-        state[SsnState::kTry + k] = state[SsnState::kGamma + k] + tn * state[SsnState::kDelta + k];
     }
     accepted = accept ? 1 : 0;
   }
   __syncthreads();
-  if (accepted)
+  if (accepted) {
     for (int k = threadIdx.x; k < L; k += blockDim.x) {
       state[SsnState::kGamma + k] = state[SsnState::kTry + k];
       state[SsnState::kF + k] = Ft[k];
     }
+  } else {
+    const double tn = tn_s;
+    for (int k = threadIdx.x; k < L; k += blockDim.x)
+      state[SsnState::kTry + k] = state[SsnState::kGamma + k] + tn * state[SsnState::kDelta + k];
+  }
 }
 
 // ---- masked Gram on the matrix cores
@@ -582,8 +589,9 @@ __global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__
   for (int t = 0; t < NTRI; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-  for (int64_t n = n0; n < n1; n += 32) {
-    // masked chunk of 4 pixels of row 32 g + ld_row
+  // masked 4-pixel chunk of row 32 g + ld_row at pixel n + 4 ld_col, zero
+  // past N or past row L
+  auto load_stage = [&](int64_t n, float4 (&val)[NRG]) {
     const int64_t nn = n + 4 * ld_col;
     uint32_t mk = 0;
     if (nn + 4 <= N) {
@@ -595,25 +603,34 @@ __global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__
 #pragma unroll
     for (int g = 0; g < NRG; ++g) {
       const int row = 32 * g + ld_row;
-      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (row < L && nn < N) {
         const float* src = U + static_cast<size_t>(row) * ldu + nn;
         if (nn + 4 <= N) {
-          val = *reinterpret_cast<const float4*>(src);
+          v = *reinterpret_cast<const float4*>(src);
         } else {
-          val.x = src[0];
-          val.y = nn + 1 < N ? src[1] : 0.f;
-          val.z = nn + 2 < N ? src[2] : 0.f;
-          val.w = nn + 3 < N ? src[3] : 0.f;
+          v.x = src[0];
+          v.y = nn + 1 < N ? src[1] : 0.f;
+          v.z = nn + 2 < N ? src[2] : 0.f;
+          v.w = nn + 3 < N ? src[3] : 0.f;
         }
       }
-      val.x = (mk & 0xffu) ? val.x : 0.f;
-      val.y = (mk & 0xff00u) ? val.y : 0.f;
-      val.z = (mk & 0xff0000u) ? val.z : 0.f;
-      val.w = (mk & 0xff000000u) ? val.w : 0.f;
-      *reinterpret_cast<float4*>(lds + row * PITCH + ld_col * 16) = val;
+      v.x = (mk & 0xffu) ? v.x : 0.f;
+      v.y = (mk & 0xff00u) ? v.y : 0.f;
+      v.z = (mk & 0xff0000u) ? v.z : 0.f;
+      v.w = (mk & 0xff000000u) ? v.w : 0.f;
+      val[g] = v;
     }
+  };
+  // the next stage's loads are issued before this stage's MFMAs
+  float4 pre[NRG];
+  if (n0 < n1) load_stage(n0, pre);
+  for (int64_t n = n0; n < n1; n += 32) {
+#pragma unroll
+    for (int g = 0; g < NRG; ++g)
+      *reinterpret_cast<float4*>(lds + (32 * g + ld_row) * PITCH + ld_col * 16) = pre[g];
     __syncthreads();
+    if (n + 32 < n1) load_stage(n + 32, pre);
     // wave w: pixels 8 w .. 8 w + 7 of the stage; lane l feeds pixel
     // 8 w + 4 (l / 32) + i to the i-th 32x32x2 MFMA (i < 4) of every tile
     {
@@ -699,6 +716,34 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
                               static_cast<unsigned>(lo));
 }
 
+// Maximum of v over the 64 lanes through DPP moves (quad permutes, row
+// mirrors, then the row broadcasts that carry each row's maximum into the
+// next rows); lane 63 ends with the wave maximum.  Lanes outside a row mask
+// keep their value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_max(float v) {
+  const int o = __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK,
+                                            0xf, false);
+  return fmaxf(v, __int_as_float(o));
+}
+
+__device__ __forceinline__ float wave_max_f32(float v) {
+  v = dpp_max<0xb1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+  v = dpp_max<0x4e, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+  v = dpp_max<0x141, 0xf>(v);   // row_half_mirror
+  v = dpp_max<0x140, 0xf>(v);   // row_mirror
+  v = dpp_max<0x142, 0xa>(v);   // row_bcast15 into rows 1 and 3
+  v = dpp_max<0x143, 0xc>(v);   // row_bcast31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ float wave_max_r(float v) { return wave_max_f32(v); }
+__device__ __forceinline__ double wave_max_r(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 __device__ __forceinline__ float readlane_r(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
@@ -733,9 +778,7 @@ __device__ void lu_regs64(double* __restrict__ A, int L, double* __restrict__ st
       const int qj = j >> 4, cj = j & 15;
       if (q == qj) {
         const R val = used ? R(-1) : static_cast<R>(fabs(a[cj]));
-        R m = val;
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        const R m = wave_max_r(val);
         const unsigned long long hit = __ballot(!used && val == m);
         const int bi = __ffsll(static_cast<unsigned long long>(hit)) - 1;
         const R piv = readlane_r(a[cj], bi);
