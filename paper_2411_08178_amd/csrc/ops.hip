@@ -27,9 +27,10 @@ void set_error(const char* fmt, ...) {
 // out[i, j] = sum_{a,b} g[a, b] in[(f i - c + a) mod n1, (f j - c + b) mod n2]
 // on an output grid o1 x o2.  g = flipped PSF gives H (f = 1) or S H (f > 1);
 // g = PSF gives H^T.
-constexpr int kCorTH = 16, kCorTW = 64;
+constexpr int kCorTW = 64;
 
-template <class SI, class SO, class C>
+// TH output rows per workgroup (16, or 4 when the grid would be small)
+template <class SI, class SO, class C, int TH>
 __global__ __launch_bounds__(256) void correlate_kernel(
     const SI* __restrict__ in, SO* __restrict__ out, const C* __restrict__ g,
     int k, int n1, int n2, int o1, int o2, int f) {
@@ -37,8 +38,8 @@ __global__ __launch_bounds__(256) void correlate_kernel(
   C* sg = reinterpret_cast<C*>(smem_raw);
   C* tile = sg + k * k;
   const int c = (k - 1) / 2;
-  const int i0 = blockIdx.y * kCorTH, j0 = blockIdx.x * kCorTW;
-  const int th = f * (kCorTH - 1) + k, tw = f * (kCorTW - 1) + k;
+  const int i0 = blockIdx.y * TH, j0 = blockIdx.x * kCorTW;
+  const int th = f * (TH - 1) + k, tw = f * (kCorTW - 1) + k;
   const SI* src = in + static_cast<size_t>(blockIdx.z) * n1 * n2;
   for (int t = threadIdx.x; t < k * k; t += blockDim.x) sg[t] = g[t];
   const int r0 = f * i0 - c, q0 = f * j0 - c;
@@ -51,7 +52,7 @@ __global__ __launch_bounds__(256) void correlate_kernel(
   __syncthreads();
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   SO* dst = out + static_cast<size_t>(blockIdx.z) * o1 * o2;
-  for (int rr = ty; rr < kCorTH; rr += 4) {
+  for (int rr = ty; rr < TH; rr += 4) {
     int oi = i0 + rr, oj = j0 + tx;
     if (oi >= o1 || oj >= o2) continue;
     C acc = 0;
@@ -67,14 +68,15 @@ __global__ __launch_bounds__(256) void correlate_kernel(
 
 // Adjoint of blur + decimation: out[p, q] = sum_{a,b} h[a, b] Z[p - c + a, q - c + b]
 // with Z the zero-filled upsampling (by f) of the m1 x m2 input.
-constexpr int kUpTH = 32, kUpTW = 64;
+constexpr int kUpTW = 64;
 
 __host__ __device__ inline int floor_div(int a, int b) {
   int q = a / b;
   return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
-template <class SI, class SO, class C>
+// TH output rows per workgroup (32, or 8 when the grid would be small)
+template <class SI, class SO, class C, int TH>
 __global__ __launch_bounds__(256) void upcorrelate_kernel(
     const SI* __restrict__ in, SO* __restrict__ out, const C* __restrict__ h,
     int k, int m1, int m2, int f) {
@@ -82,8 +84,8 @@ __global__ __launch_bounds__(256) void upcorrelate_kernel(
   C* sh = reinterpret_cast<C*>(smem_raw);
   C* tile = sh + k * k;
   const int n1 = m1 * f, n2 = m2 * f, c = (k - 1) / 2;
-  const int p0 = blockIdx.y * kUpTH, q0 = blockIdx.x * kUpTW;
-  const int R0 = floor_div(p0 - c, f), R1 = floor_div(p0 + kUpTH - 1 - c + k - 1, f);
+  const int p0 = blockIdx.y * TH, q0 = blockIdx.x * kUpTW;
+  const int R0 = floor_div(p0 - c, f), R1 = floor_div(p0 + TH - 1 - c + k - 1, f);
   const int C0 = floor_div(q0 - c, f), C1 = floor_div(q0 + kUpTW - 1 - c + k - 1, f);
   const int th = R1 - R0 + 1, tw = C1 - C0 + 1;
   const SI* src = in + static_cast<size_t>(blockIdx.z) * m1 * m2;
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(256) void upcorrelate_kernel(
   SO* dst = out + static_cast<size_t>(blockIdx.z) * n1 * n2;
   const int q = q0 + tx;
   int bs = (c - q) % f; if (bs < 0) bs += f;
-  for (int rr = ty; rr < kUpTH; rr += 4) {
+  for (int rr = ty; rr < TH; rr += 4) {
     int p = p0 + rr;
     if (p >= n1 || q >= n2) continue;
     int as = (c - p) % f; if (as < 0) as += f;
@@ -316,10 +318,17 @@ static nys_status launch_correlate(const nys_op_s* op, const SI* in, SO* out, bo
                                    int n1, int n2, int f, int64_t ncols, hipStream_t st) {
   const int k = op->d.psf_size;
   const int o1 = n1 / f, o2 = n2 / f;
-  dim3 grid(cdiv(o2, kCorTW), cdiv(o1, kCorTH), static_cast<unsigned>(ncols));
-  size_t sm = sizeof(C) * (k * k + (f * (kCorTH - 1) + k) * (f * (kCorTW - 1) + k));
-  hipLaunchKernelGGL((correlate_kernel<SI, SO, C>), grid, dim3(256), sm, st, in, out,
-                     psf_ptr<C>(op, flipped), k, n1, n2, o1, o2, f);
+  // 16-row tiles when that still gives >= 512 workgroups, else 4-row tiles
+  const bool tall = static_cast<int64_t>(cdiv(o2, kCorTW)) * cdiv(o1, 16) * ncols >= 512;
+  const int TH = tall ? 16 : 4;
+  dim3 grid(cdiv(o2, kCorTW), cdiv(o1, TH), static_cast<unsigned>(ncols));
+  size_t sm = sizeof(C) * (k * k + (f * (TH - 1) + k) * (f * (kCorTW - 1) + k));
+  if (tall)
+    hipLaunchKernelGGL((correlate_kernel<SI, SO, C, 16>), grid, dim3(256), sm, st, in, out,
+                       psf_ptr<C>(op, flipped), k, n1, n2, o1, o2, f);
+  else
+    hipLaunchKernelGGL((correlate_kernel<SI, SO, C, 4>), grid, dim3(256), sm, st, in, out,
+                       psf_ptr<C>(op, flipped), k, n1, n2, o1, o2, f);
   return launch_check("correlate_kernel");
 }
 
@@ -328,11 +337,18 @@ static nys_status launch_upcorrelate(const nys_op_s* op, const SI* in, SO* out, 
                                      int m2, int f, int64_t ncols, hipStream_t st) {
   const int k = op->d.psf_size;
   const int n1 = m1 * f, n2 = m2 * f;
-  dim3 grid(cdiv(n2, kUpTW), cdiv(n1, kUpTH), static_cast<unsigned>(ncols));
-  int th = (kUpTH - 1 + k - 1) / f + 2, tw = (kUpTW - 1 + k - 1) / f + 2;
+  // 32-row tiles when that still gives >= 512 workgroups, else 8-row tiles
+  const bool tall = static_cast<int64_t>(cdiv(n2, kUpTW)) * cdiv(n1, 32) * ncols >= 512;
+  const int TH = tall ? 32 : 8;
+  dim3 grid(cdiv(n2, kUpTW), cdiv(n1, TH), static_cast<unsigned>(ncols));
+  int th = (TH - 1 + k - 1) / f + 2, tw = (kUpTW - 1 + k - 1) / f + 2;
   size_t sm = sizeof(C) * (k * k + th * tw);
-  hipLaunchKernelGGL((upcorrelate_kernel<SI, SO, C>), grid, dim3(256), sm, st, in, out,
-                     psf_ptr<C>(op, false), k, m1, m2, f);
+  if (tall)
+    hipLaunchKernelGGL((upcorrelate_kernel<SI, SO, C, 32>), grid, dim3(256), sm, st, in, out,
+                       psf_ptr<C>(op, false), k, m1, m2, f);
+  else
+    hipLaunchKernelGGL((upcorrelate_kernel<SI, SO, C, 8>), grid, dim3(256), sm, st, in, out,
+                       psf_ptr<C>(op, false), k, m1, m2, f);
   return launch_check("upcorrelate_kernel");
 }
 
