@@ -749,78 +749,62 @@ __device__ __forceinline__ float readlane_r(float v, int lane) {
 }
 __device__ __forceinline__ double readlane_r(double v, int lane) { return readlane_f64(v, lane); }
 
-// L <= 64, 256 threads, arithmetic in R (float for an FP32 U: the Newton
-// direction only has to resolve F to the FP32 stopping tolerance; double
-// otherwise): lane r of wave q holds J[r][16 q .. 16 q + 15] in registers;
-// the wave owning column j picks the pivot (largest |J[r][j]| over rows not
-// yet used, lowest row on ties) and the multipliers, every wave eliminates
-// its own columns (one barrier per column).
-template <class R>
-__device__ void lu_regs64(double* __restrict__ A, int L, double* __restrict__ state) {
-  __shared__ R fbuf[2][64];
-  __shared__ int pbuf[2];
-  __shared__ int porder[64];
-  __shared__ double sol[64];
-  __shared__ R rhs_s[64];
-  const int tid = threadIdx.x, q = tid >> 6, r = tid & 63;
+// L <= LM (16, 32 or 64) on wave 0 alone, arithmetic in R (float for an FP32
+// U: the Newton direction only has to resolve F to the FP32 stopping
+// tolerance; double otherwise).  Lane r holds row r of J in LM registers and
+// the right-hand side; the fully unrolled elimination addresses columns by
+// constant register index and reads the pivot row through the scalar unit,
+// so there is no barrier and no LDS traffic per column.  Partial pivoting
+// (largest |J[r][j]| over the rows not yet used, lowest row on ties) with
+// the pivot rows left in place; the back substitution runs in the same wave
+// and lane j ends with delta_j.
+template <class R, int LM>
+__device__ void lu_wave_regs(const double* __restrict__ A, int L, double* __restrict__ state) {
+  const int r = threadIdx.x;
   const int LP1 = L + 1;
-  R a[16];
+  R a[LM];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int col = 16 * q + c;
-    a[c] = static_cast<R>((r < L && col < L) ? A[r * LP1 + col] : (r == col ? 1.0 : 0.0));
-  }
-  R rh = static_cast<R>((r < L) ? -state[SsnState::kF + r] : 0.0);   // kept by every wave
+  for (int c = 0; c < LM; ++c)
+    a[c] = (r < L && c < L) ? static_cast<R>(A[r * LP1 + c]) : (r == c ? R(1) : R(0));
+  R rh = (r < L) ? static_cast<R>(-state[SsnState::kF + r]) : R(0);
   bool used = r >= L;
+  int piv = 0;   // lane j: the pivot row of column j
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
+  for (int j = 0; j < LM; ++j) {
     if (j < L) {
-      const int qj = j >> 4, cj = j & 15;
-      if (q == qj) {
-        const R val = used ? R(-1) : static_cast<R>(fabs(a[cj]));
-        const R m = wave_max_r(val);
-        const unsigned long long hit = __ballot(!used && val == m);
-        const int bi = __ffsll(static_cast<unsigned long long>(hit)) - 1;
-        const R piv = readlane_r(a[cj], bi);
-        fbuf[j & 1][r] = (used || r == bi) ? R(0) : a[cj] / piv;
-        if (r == 0) { pbuf[j & 1] = bi; porder[j] = bi; }
-      }
-      __syncthreads();
-      const int p = __builtin_amdgcn_readfirstlane(pbuf[j & 1]);
-      const R f = fbuf[j & 1][r];
+      const R val = used ? R(-1) : static_cast<R>(fabs(a[j]));
+      const R m = wave_max_r(val);
+      const unsigned long long hit = __ballot(!used && val == m);
+      const int p = __builtin_amdgcn_readfirstlane(__ffsll(static_cast<unsigned long long>(hit)) - 1);
+      const R inv = R(1) / readlane_r(a[j], p);
+      const R f = (used || r == p) ? R(0) : a[j] * inv;
       if (r == p) used = true;
-      if (q >= qj) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const R pc = readlane_r(a[c], p);
-          if (16 * q + c > j) a[c] -= f * pc;
-        }
-      }
-      const R rp = readlane_r(rh, p);
-      rh -= f * rp;
+      for (int k = j + 1; k < LM; ++k) a[k] -= f * readlane_r(a[k], p);
+      rh -= f * readlane_r(rh, p);
+      if (r == j) piv = p;
     }
   }
-  // eliminated matrix and right-hand side back to LDS, then back substitution
-  // on wave 0: unknown j from pivot row porder[j]
+  R sol = 0;
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    const int col = 16 * q + c;
-    if (r < L && col < L) A[r * LP1 + col] = static_cast<double>(a[c]);
-  }
-  if (q == 0) rhs_s[r] = rh;
-  __syncthreads();
-  if (q == 0) {
-    R rr = rhs_s[r];
-    for (int j = L - 1; j >= 0; --j) {
-      const int p = __builtin_amdgcn_readfirstlane(porder[j]);
-      const R rp = readlane_r(rr, p);
-      const R d = rp / static_cast<R>(A[p * LP1 + j]);
-      if (r == 0) sol[j] = static_cast<double>(d);
-      if (r < L) rr -= static_cast<R>(A[r * LP1 + j]) * d;
+  for (int j = LM - 1; j >= 0; --j) {
+    if (j < L) {
+      const int p = __builtin_amdgcn_readlane(piv, j);
+      const R d = readlane_r(rh, p) / readlane_r(a[j], p);
+      if (r == j) sol = d;
+      rh -= a[j] * d;
     }
   }
-  __syncthreads();
-  ssn_set_direction(sol, L, state);
+  if (r < L) {
+    const double dv = static_cast<double>(sol);
+    state[SsnState::kDelta + r] = dv;
+    state[SsnState::kTry + r] = state[SsnState::kGamma + r] + dv;
+  }
+  if (r == 0) {
+    state[SsnState::kT] = 1.0;
+    state[SsnState::kHalv] = 0.0;
+    state[SsnState::kSteps] += 1.0;
+  }
 }
 
 // Any L <= 128: elimination on wave 0 alone (lane r owns rows r and r + 64).
@@ -879,9 +863,83 @@ __device__ void lu_wave(double* __restrict__ A, int L, double* __restrict__ stat
   ssn_set_direction(sol, L, state);
 }
 
+// FP32 elimination on the diagonal, wave 0 alone, lane r holding row r of J
+// and the right-hand side.  Every leading principal block of J = I + diag(e) M
+// is I + E_k M_k with M_k a principal block of U^T D U (0 <= M_k <= I) and
+// e > -1, so E_k M_k (similar to M_k^1/2 E_k M_k^1/2) has real eigenvalues
+// above -1 and no leading minor vanishes: LU without row exchanges exists,
+// and the pivot row of step j is row j, read through the scalar unit with a
+// constant lane index.  A pivot below 2^-12 max |J| (lost accuracy) or a
+// non-finite result returns false, and the caller redoes the solve with
+// partial pivoting.
+template <int LM>
+__device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __restrict__ state) {
+  const int r = threadIdx.x;
+  const int LP1 = L + 1;
+  float a[LM];
+  float amax = 0.f;
+#pragma unroll
+  for (int c = 0; c < LM; ++c) {
+    a[c] = (r < L && c < L) ? static_cast<float>(A[r * LP1 + c]) : (r == c ? 1.f : 0.f);
+    amax = fmaxf(amax, fabsf(a[c]));
+  }
+  amax = wave_max_f32(amax);
+  const float thresh = 0x1p-12f * amax;
+  float rh = (r < L) ? static_cast<float>(-state[SsnState::kF + r]) : 0.f;
+  float invd = 0.f;   // lane j: 1 / u_jj
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < LM; ++j) {
+    if (j < L) {
+      const float pv = readlane_r(a[j], j);
+      ok = ok && fabsf(pv) >= thresh;
+      const float inv = __builtin_amdgcn_rcpf(pv);
+      const float f = r > j ? a[j] * inv : 0.f;
+      if (r == j) invd = inv;
+      // groups of 16 columns: no more than 16 broadcast values live at once
+#pragma unroll
+      for (int k = j + 1; k < LM; ++k) {
+        a[k] -= f * readlane_r(a[k], j);
+        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+      }
+      rh -= f * readlane_r(rh, j);
+    }
+  }
+  if (!ok) return false;
+  float sol = 0.f;
+#pragma unroll
+  for (int j = LM - 1; j >= 0; --j) {
+    if (j < L) {
+      const float d = readlane_r(rh, j) * readlane_r(invd, j);
+      if (r == j) sol = d;
+      rh -= a[j] * d;
+    }
+  }
+  if (__ballot(!isfinite(sol)) != 0) return false;
+  if (r < L) {
+    const double dv = static_cast<double>(sol);
+    state[SsnState::kDelta + r] = dv;
+    state[SsnState::kTry + r] = state[SsnState::kGamma + r] + dv;
+  }
+  if (r == 0) {
+    state[SsnState::kT] = 1.0;
+    state[SsnState::kHalv] = 0.0;
+    state[SsnState::kSteps] += 1.0;
+  }
+  return true;
+}
+
+template <class R, int LM>
+__device__ __forceinline__ void lu_wave_any(const double* A, int L, double* state) {
+  if (threadIdx.x >= 64) return;
+  lu_wave_regs<R, LM>(A, L, state);
+}
+
 template <class R>
 __device__ __forceinline__ void ssn_lu(double* A, int L, double* state) {
-  if (L <= 64) lu_regs64<R>(A, L, state);
+  if (L <= 16) lu_wave_any<R, 16>(A, L, state);
+  else if (L <= 32) lu_wave_any<R, 32>(A, L, state);
+  else if (L <= 64) lu_wave_any<R, 64>(A, L, state);
   else lu_wave(A, L, state);
 }
 
@@ -910,7 +968,19 @@ __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict
     if (gi != gj) A[gj * LP1 + gi] = meta[PcMeta::kE + gj] * sacc;
   }
   __syncthreads();
-  ssn_lu<float>(A, L, state);
+  // elimination on the diagonal; the compact pivoted elimination of the whole
+  // block only if that reports lost accuracy
+  __shared__ int diag_ok;
+  if constexpr (NRG <= 2) {
+    if (threadIdx.x < 64) {
+      const bool ok = lu_wave_diag<NRG == 1 ? 32 : 64>(A, L, state);
+      if (threadIdx.x == 0) diag_ok = ok ? 1 : 0;
+    }
+  } else {
+    if (threadIdx.x == 0) diag_ok = 0;
+  }
+  __syncthreads();
+  if (!diag_ok) lu_wave(A, L, state);
 }
 
 // FP64 U: masked Gram on the vector units, one 64 x 64 output tile per block

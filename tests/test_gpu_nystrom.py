@@ -131,14 +131,18 @@ def test_prox_dual(reg, dt, with_pc):
     assert rel(host(x2), xr2) < TOL[dt] * 10
 
 
-@pytest.mark.parametrize("dt,tail", [("f64", "sqrt"), ("f64", "plain"), ("f32", "sqrt")])
-def test_prox_l1_ssn(dt, tail):
+# ell = 8 and 40 / 64 take the register eliminations sized 32 and 64 (40: a
+# ragged last group of columns), ell = 100 the elimination of the whole block;
+# the plain tail gives e up to s_1 / s_ell - 1 >> 1, the sqrt tail e < 0
+@pytest.mark.parametrize("dt,tail,ell", [("f64", "sqrt", 8), ("f64", "plain", 8), ("f32", "sqrt", 8),
+                                         ("f32", "sqrt", 40), ("f32", "plain", 64),
+                                         ("f32", "sqrt", 100), ("f64", "plain", 64)])
+def test_prox_l1_ssn(dt, tail, ell):
     P = need_gpu()
-    banner(f"prox l1 ssn {dt} {tail}")
+    banner(f"prox l1 ssn {dt} {tail} ell={ell}")
     n = 48
     h = W.gaussian_psf(7, 1.2)
     prob = sv.Problem("blurdown", n, None, 0.0, "l1", h=h, factor=2, levels=3)
-    ell = 8
     om = W.omega(ell, n, n, 16)
     Y = sv.sketch(prob, om)
     omd, Yd = dev(om, "f64"), dev(Y, "f64")
