@@ -563,25 +563,38 @@ __global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restric
 // ---- masked Gram on the matrix cores
 typedef float floatx16_v __attribute__((ext_vector_type(16)));
 
-// Stage: 128 bytes (32 float pixels) of each of the 32 NRG rows of U, masked
-// by D, through LDS; 32 x 32 tiles of the upper triangle over 4 waves, as in
-// the Gram of the factorisation.  Partials per block in FP32.
+// One pass over an FP32 U at the trial point g (Thm. 1): per pixel
+// r = s - U g, x = soft_lam(r), d = x - s and D = [|r| > lam]; per block the
+// partial U^T d (FP64) for F(g) and the partial masked Gram U^T D U (FP32
+// matrix cores) for the Newton step that follows if g is accepted.  Stages
+// of 32 pixels of the 32 NRG rows (and of s) go through LDS; two stages of
+// loads are in flight.
 template <int NRG>
-__global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__ U, int64_t ldu,
-                                                       const uint8_t* __restrict__ mask,
-                                                       int64_t N, int L, int64_t chunk,
-                                                       const double* __restrict__ meta,
-                                                       const double* __restrict__ state,
-                                                       float* __restrict__ part) {
+__global__ __launch_bounds__(256) void ssn_evalgram_kernel(const float* __restrict__ U,
+                                                           int64_t ldu,
+                                                           const float* __restrict__ s,
+                                                           int64_t N, int L, int64_t chunk,
+                                                           float lam,
+                                                           const double* __restrict__ state,
+                                                           double* __restrict__ part,
+                                                           float* __restrict__ gpart) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   constexpr int ROWS = 32 * NRG;
-  constexpr int PITCH = 144;
-  constexpr int LDSB = ROWS * PITCH > NTRI * 4096 ? ROWS * PITCH : NTRI * 4096;
+  constexpr int PITCH = 144;                          // bytes per LDS row: 32 floats + pad
+  constexpr int UB = ROWS * PITCH;
+  constexpr int LDSB = UB > NTRI * 4096 ? UB : NTRI * 4096;
+  constexpr int UPT = (ROWS * 4 + 255) / 256;         // (row, 8-pixel octet) units per thread
   __shared__ __align__(16) unsigned char lds[LDSB];
-  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
+  __shared__ __align__(16) float s_st[32];            // s of the stage
+  __shared__ __align__(16) float d_st[32];            // x - s of the stage
+  __shared__ __align__(16) float m_st[32];            // D of the stage (1 or 0)
+  __shared__ float gs[ROWS];
+  __shared__ double ud[ROWS];
+  if (state[SsnState::kDone] != 0.0) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 31, lh = lane >> 5;
   const int ld_row = tid >> 3, ld_col = tid & 7;
+  for (int k = tid; k < ROWS; k += 256) gs[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
   const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
   floatx16_v acc[NTRI];
@@ -589,24 +602,22 @@ __global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__
   for (int t = 0; t < NTRI; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-  // masked 4-pixel chunk of row 32 g + ld_row at pixel n + 4 ld_col, zero
-  // past N or past row L
-  auto load_stage = [&](int64_t n, float4 (&val)[NRG]) {
-    const int64_t nn = n + 4 * ld_col;
-    uint32_t mk = 0;
-    if (nn + 4 <= N) {
-      mk = *reinterpret_cast<const uint32_t*>(mask + nn);
-    } else {
+  double accd[UPT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) mk |= (nn + i < N ? static_cast<uint32_t>(mask[nn + i]) : 0u) << (8 * i);
-    }
+  for (int u = 0; u < UPT; ++u) accd[u] = 0.0;
+
+  // 4-pixel chunk at pixel n + 4 ld_col of rows 32 g + ld_row (zero past N
+  // or row L), and of s on the first 8 threads
+  auto load_stage = [&](int64_t n, float4 (&val)[NRG], float4& sv) {
+    const int64_t nn = n + 4 * ld_col;
+    const bool full = nn + 4 <= N;
 #pragma unroll
     for (int g = 0; g < NRG; ++g) {
       const int row = 32 * g + ld_row;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (row < L && nn < N) {
         const float* src = U + static_cast<size_t>(row) * ldu + nn;
-        if (nn + 4 <= N) {
+        if (full) {
           v = *reinterpret_cast<const float4*>(src);
         } else {
           v.x = src[0];
@@ -615,30 +626,73 @@ __global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__
           v.w = nn + 3 < N ? src[3] : 0.f;
         }
       }
-      v.x = (mk & 0xffu) ? v.x : 0.f;
-      v.y = (mk & 0xff00u) ? v.y : 0.f;
-      v.z = (mk & 0xff0000u) ? v.z : 0.f;
-      v.w = (mk & 0xff000000u) ? v.w : 0.f;
       val[g] = v;
     }
+    sv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < 8 && nn < N) {
+      if (full) {
+        sv = *reinterpret_cast<const float4*>(s + nn);
+      } else {
+        sv.x = s[nn];
+        sv.y = nn + 1 < N ? s[nn + 1] : 0.f;
+        sv.z = nn + 2 < N ? s[nn + 2] : 0.f;
+        sv.w = nn + 3 < N ? s[nn + 3] : 0.f;
+      }
+    }
   };
-  // the next stage's loads are issued before this stage's MFMAs
-  float4 pre[NRG];
-  if (n0 < n1) load_stage(n0, pre);
-  for (int64_t n = n0; n < n1; n += 32) {
+
+  auto process = [&](int64_t n, float4 (&val)[NRG], float4& sv) {
 #pragma unroll
     for (int g = 0; g < NRG; ++g)
-      *reinterpret_cast<float4*>(lds + (32 * g + ld_row) * PITCH + ld_col * 16) = pre[g];
+      *reinterpret_cast<float4*>(lds + (32 * g + ld_row) * PITCH + ld_col * 16) = val[g];
+    if (tid < 8) *reinterpret_cast<float4*>(s_st + 4 * tid) = sv;
     __syncthreads();
-    if (n + 32 < n1) load_stage(n + 32, pre);
-    // wave w: pixels 8 w .. 8 w + 7 of the stage; lane l feeds pixel
-    // 8 w + 4 (l / 32) + i to the i-th 32x32x2 MFMA (i < 4) of every tile
+    if (n + 64 < n1) load_stage(n + 64, val, sv);
+    // r of pixel p = tid / 8 from 8 lanes, rows g8, g8 + 8, ...
     {
+      const int p = tid >> 3, g8 = tid & 7;
+      float part_r = 0.f;
+#pragma unroll
+      for (int i = 0; i < ROWS / 8; ++i) {
+        const int k = g8 + 8 * i;
+        part_r += *reinterpret_cast<const float*>(lds + k * PITCH + 4 * p) * gs[k];
+      }
+      part_r += __shfl_xor(part_r, 1, 64);
+      part_r += __shfl_xor(part_r, 2, 64);
+      part_r += __shfl_xor(part_r, 4, 64);
+      if (g8 == 0) {
+        const float r = s_st[p] - part_r;
+        const float ar = fabsf(r);
+        const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
+        d_st[p] = xv - s_st[p];
+        m_st[p] = ar > lam ? 1.f : 0.f;
+      }
+    }
+    __syncthreads();
+    // U^T d: unit (row, octet q) sums 8 pixels in FP32, then adds in FP64
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+      const int unit = tid + 256 * u;
+      if (unit < ROWS * 4) {
+        const int row = unit >> 2, q = unit & 3;
+        const float4 u0 = *reinterpret_cast<const float4*>(lds + row * PITCH + 32 * q);
+        const float4 u1 = *reinterpret_cast<const float4*>(lds + row * PITCH + 32 * q + 16);
+        const float4 d0 = *reinterpret_cast<const float4*>(d_st + 8 * q);
+        const float4 d1 = *reinterpret_cast<const float4*>(d_st + 8 * q + 4);
+        const float t = u0.x * d0.x + u0.y * d0.y + u0.z * d0.z + u0.w * d0.w +
+                        u1.x * d1.x + u1.y * d1.y + u1.z * d1.z + u1.w * d1.w;
+        accd[u] += static_cast<double>(t);
+      }
+    }
+    // masked Gram: wave w takes pixels 8 w .. 8 w + 7; lane l feeds pixel
+    // 8 w + 4 (l / 32) + i to the i-th 32x32x2 MFMA of every tile
+    {
+      const float4 mk = *reinterpret_cast<const float4*>(m_st + 8 * wave + 4 * lh);
       float fr[NRG][4];
 #pragma unroll
       for (int g = 0; g < NRG; ++g) {
-        float4 u = *reinterpret_cast<const float4*>(lds + (32 * g + lr) * PITCH + 32 * wave + 16 * lh);
-        fr[g][0] = u.x; fr[g][1] = u.y; fr[g][2] = u.z; fr[g][3] = u.w;
+        const float4 v = *reinterpret_cast<const float4*>(lds + (32 * g + lr) * PITCH + 32 * wave + 16 * lh);
+        fr[g][0] = v.x * mk.x; fr[g][1] = v.y * mk.y; fr[g][2] = v.z * mk.z; fr[g][3] = v.w * mk.w;
       }
       int tile = 0;
 #pragma unroll
@@ -650,8 +704,26 @@ __global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__
             acc[tile] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti][i], fr[tj][i], acc[tile], 0, 0, 0);
     }
     __syncthreads();
+  };
+
+  float4 pa[NRG], pb[NRG];
+  float4 sa, sb;
+  if (n0 < n1) load_stage(n0, pa, sa);
+  if (n0 + 32 < n1) load_stage(n0 + 32, pb, sb);
+  for (int64_t n = n0; n < n1; n += 64) {
+    process(n, pa, sa);
+    if (n + 32 < n1) process(n + 32, pb, sb);
   }
-  // sum the four waves' tiles in LDS (fixed order), then one partial per block
+  // U^T d: the 4 octets of a row sit on 4 adjacent lanes
+#pragma unroll
+  for (int u = 0; u < UPT; ++u) {
+    double v = accd[u];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    const int unit = tid + 256 * u;
+    if (unit < ROWS * 4 && (unit & 3) == 0) ud[unit >> 2] = v;
+  }
+  // Gram: the four waves' tiles summed in LDS (fixed order)
   float* sum = reinterpret_cast<float*>(lds);     // NTRI * 1024 floats
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
@@ -665,8 +737,9 @@ __global__ __launch_bounds__(256) void ssn_gram_kernel(const float* __restrict__
     }
     __syncthreads();
   }
-  float* dst = part + static_cast<size_t>(blockIdx.x) * NTRI * 1024;
+  float* dst = gpart + static_cast<size_t>(blockIdx.x) * NTRI * 1024;
   for (int e = tid; e < NTRI * 1024; e += 256) dst[e] = sum[e];
+  for (int k = tid; k < L; k += 256) part[static_cast<size_t>(blockIdx.x) * L + k] = ud[k];
 }
 
 // Stage 2 of the Gram reduction: block (e, q) sums partials q, q + 16, ... of
@@ -1121,14 +1194,20 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
   return launch_check("ssn_decide_kernel");
 }
 
+// One trial of the FP32 Newton iteration: the fused evaluation + masked Gram
+// at the trial point, the decision, and (if it asks for one) the Newton step.
 template <int NRG>
-static nys_status launch_ssn_newton(nys_pc pc, const uint8_t* mask, double* state, float* part,
-                                    int nblk, int64_t chunk, hipStream_t st) {
+static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double* state,
+                                   double* fpart, float* part, int nblk, int64_t chunk, double tol,
+                                   hipStream_t st) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
-  hipLaunchKernelGGL((ssn_gram_kernel<NRG>), dim3(nblk), dim3(256), 0, st, pc->U.as<float>(),
-                     pc->ldu, mask, pc->N, static_cast<int>(pc->ell), chunk, pc->meta.as<double>(),
-                     state, part);
-  NYS_TRY(launch_check("ssn_gram_kernel"));
+  const int L = static_cast<int>(pc->ell);
+  hipLaunchKernelGGL((ssn_evalgram_kernel<NRG>), dim3(nblk), dim3(256), 0, st, pc->U.as<float>(),
+                     pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part);
+  NYS_TRY(launch_check("ssn_evalgram_kernel"));
+  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(512), 0, st, fpart, nblk, L,
+                     pc->meta.as<double>(), state, tol, 30);
+  NYS_TRY(launch_check("ssn_decide_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
   hipLaunchKernelGGL((ssn_gram_stage2_kernel<NRG>), dim3(NTRI * 4, 16), dim3(256), 0, st, part, nblk,
                      state, part2);
@@ -1162,11 +1241,11 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     gpart_d = (static_cast<size_t>(ngb) * nrg * (nrg + 1) / 2 * 1024 + 1) / 2 +
               static_cast<size_t>(16) * nrg * (nrg + 1) / 2 * 1024 + 1;
   else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
-  const size_t need = SsnState::kTotal + static_cast<size_t>(nblk) * L + gpart_d + LL;
+  const size_t need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
   NYS_TRY(pc->work2.ensure(sizeof(double) * need + N + 256));
   double* state = pc->work2.as<double>();
   double* part = state + SsnState::kTotal;
-  double* gpart = part + static_cast<size_t>(nblk) * L;
+  double* gpart = part + static_cast<size_t>(std::max(nblk, ngb)) * L;
   double* Mj = gpart + gpart_d;
   uint8_t* mask = reinterpret_cast<uint8_t*>(Mj + LL);
   const T lam = static_cast<T>(lam_bar);
@@ -1176,16 +1255,18 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   NYS_TRY(launch_check("ssn_init_kernel"));
   int trial = 0;
   for (; trial < max_trials; ++trial) {
-    NYS_TRY(launch_eval<T>(pc, s, lam, state, mask, part, nblk, chunk, tol, st));
     if constexpr (sizeof(T) == 4) {
       float* gp = reinterpret_cast<float*>(gpart);
+      const float* sf = reinterpret_cast<const float*>(s);
+      const float lf = static_cast<float>(lam);
       switch (nrg) {
-        case 1: NYS_TRY(launch_ssn_newton<1>(pc, mask, state, gp, ngb, gchunk, st)); break;
-        case 2: NYS_TRY(launch_ssn_newton<2>(pc, mask, state, gp, ngb, gchunk, st)); break;
-        case 3: NYS_TRY(launch_ssn_newton<3>(pc, mask, state, gp, ngb, gchunk, st)); break;
-        default: NYS_TRY(launch_ssn_newton<4>(pc, mask, state, gp, ngb, gchunk, st)); break;
+        case 1: NYS_TRY(launch_ssn_trial<1>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
+        case 2: NYS_TRY(launch_ssn_trial<2>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
+        case 3: NYS_TRY(launch_ssn_trial<3>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
+        default: NYS_TRY(launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
       }
     } else {
+      NYS_TRY(launch_eval<T>(pc, s, lam, state, mask, part, nblk, chunk, tol, st));
       const int ntile = static_cast<int>(cdiv(L, 64));
       const int nch = static_cast<int>(cdiv(N, 4096));
       hipLaunchKernelGGL(ssn_gram_f64_kernel, dim3(nch, ntile, ntile), dim3(256), 0, st,
