@@ -566,28 +566,30 @@ typedef float floatx16_v __attribute__((ext_vector_type(16)));
 // One pass over an FP32 U at the trial point g (Thm. 1): per pixel
 // r = s - U g, x = soft_lam(r), d = x - s and D = [|r| > lam]; per block the
 // partial U^T d (FP64) for F(g) and the partial masked Gram U^T D U (FP32
-// matrix cores) for the Newton step that follows if g is accepted.  Stages
-// of 32 pixels of the 32 NRG rows (and of s) go through LDS; two stages of
-// loads are in flight.
+// matrix cores) for the Newton step that follows if g is accepted.
+// Stages of 32 pixels of the 32 NRG rows (and of s) go through three LDS
+// buffers in a software pipeline with one barrier per stage: iteration n
+// stores stage n + 1, evaluates stage n and feeds stage n - 1 to the Gram and
+// U^T d; the loads of stages n + 2 and n + 3 are in flight meanwhile.
 template <int NRG>
-__global__ __launch_bounds__(256) void ssn_evalgram_kernel(const float* __restrict__ U,
-                                                           int64_t ldu,
-                                                           const float* __restrict__ s,
-                                                           int64_t N, int L, int64_t chunk,
-                                                           float lam,
-                                                           const double* __restrict__ state,
-                                                           double* __restrict__ part,
-                                                           float* __restrict__ gpart) {
+__global__ __launch_bounds__(256, NRG <= 2 ? 2 : 1) void ssn_evalgram_kernel(const float* __restrict__ U,
+                                                              int64_t ldu,
+                                                              const float* __restrict__ s,
+                                                              int64_t N, int L, int64_t chunk,
+                                                              float lam,
+                                                              const double* __restrict__ state,
+                                                              double* __restrict__ part,
+                                                              float* __restrict__ gpart) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   constexpr int ROWS = 32 * NRG;
   constexpr int PITCH = 144;                          // bytes per LDS row: 32 floats + pad
   constexpr int UB = ROWS * PITCH;
-  constexpr int LDSB = UB > NTRI * 4096 ? UB : NTRI * 4096;
+  constexpr int LDSB = 3 * UB > NTRI * 4096 ? 3 * UB : NTRI * 4096;
   constexpr int UPT = (ROWS * 4 + 255) / 256;         // (row, 8-pixel octet) units per thread
   __shared__ __align__(16) unsigned char lds[LDSB];
-  __shared__ __align__(16) float s_st[32];            // s of the stage
-  __shared__ __align__(16) float d_st[32];            // x - s of the stage
-  __shared__ __align__(16) float m_st[32];            // D of the stage (1 or 0)
+  __shared__ __align__(16) float s_st[2][32];         // s of a stage
+  __shared__ __align__(16) float d_st[2][32];         // x - s of a stage
+  __shared__ __align__(16) float m_st[2][32];         // D of a stage (1 or 0)
   __shared__ float gs[ROWS];
   __shared__ double ud[ROWS];
   if (state[SsnState::kDone] != 0.0) return;
@@ -597,6 +599,7 @@ __global__ __launch_bounds__(256) void ssn_evalgram_kernel(const float* __restri
   for (int k = tid; k < ROWS; k += 256) gs[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
   const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  const int64_t S = n1 > n0 ? (n1 - n0 + 31) / 32 : 0;
   floatx16_v acc[NTRI];
 #pragma unroll
   for (int t = 0; t < NTRI; ++t)
@@ -606,10 +609,10 @@ __global__ __launch_bounds__(256) void ssn_evalgram_kernel(const float* __restri
 #pragma unroll
   for (int u = 0; u < UPT; ++u) accd[u] = 0.0;
 
-  // 4-pixel chunk at pixel n + 4 ld_col of rows 32 g + ld_row (zero past N
-  // or row L), and of s on the first 8 threads
-  auto load_stage = [&](int64_t n, float4 (&val)[NRG], float4& sv) {
-    const int64_t nn = n + 4 * ld_col;
+  // stage k: 4-pixel chunk at pixel 4 ld_col of rows 32 g + ld_row (zero
+  // past N or row L), and of s on the first 8 threads
+  auto load_stage = [&](int64_t k, float4 (&val)[NRG], float4& sv) {
+    const int64_t nn = n0 + 32 * k + 4 * ld_col;
     const bool full = nn + 4 <= N;
 #pragma unroll
     for (int g = 0; g < NRG; ++g) {
@@ -640,45 +643,48 @@ __global__ __launch_bounds__(256) void ssn_evalgram_kernel(const float* __restri
       }
     }
   };
-
-  auto process = [&](int64_t n, float4 (&val)[NRG], float4& sv) {
+  auto ubuf = [&](int64_t k) { return lds + static_cast<int>(k % 3) * UB; };
+  auto store_stage = [&](int64_t k, const float4 (&val)[NRG], const float4& sv) {
+    unsigned char* b = ubuf(k);
 #pragma unroll
     for (int g = 0; g < NRG; ++g)
-      *reinterpret_cast<float4*>(lds + (32 * g + ld_row) * PITCH + ld_col * 16) = val[g];
-    if (tid < 8) *reinterpret_cast<float4*>(s_st + 4 * tid) = sv;
-    __syncthreads();
-    if (n + 64 < n1) load_stage(n + 64, val, sv);
-    // r of pixel p = tid / 8 from 8 lanes, rows g8, g8 + 8, ...
-    {
-      const int p = tid >> 3, g8 = tid & 7;
-      float part_r = 0.f;
+      *reinterpret_cast<float4*>(b + (32 * g + ld_row) * PITCH + ld_col * 16) = val[g];
+    if (tid < 8) *reinterpret_cast<float4*>(&s_st[k & 1][4 * tid]) = sv;
+  };
+  // r of pixel p = tid / 8 from the 8 lanes taking rows g8, g8 + 8, ...
+  auto eval = [&](int64_t k) {
+    const unsigned char* b = ubuf(k);
+    const int p = tid >> 3, g8 = tid & 7;
+    float pr = 0.f;
 #pragma unroll
-      for (int i = 0; i < ROWS / 8; ++i) {
-        const int k = g8 + 8 * i;
-        part_r += *reinterpret_cast<const float*>(lds + k * PITCH + 4 * p) * gs[k];
-      }
-      part_r += __shfl_xor(part_r, 1, 64);
-      part_r += __shfl_xor(part_r, 2, 64);
-      part_r += __shfl_xor(part_r, 4, 64);
-      if (g8 == 0) {
-        const float r = s_st[p] - part_r;
-        const float ar = fabsf(r);
-        const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
-        d_st[p] = xv - s_st[p];
-        m_st[p] = ar > lam ? 1.f : 0.f;
-      }
+    for (int i = 0; i < ROWS / 8; ++i) {
+      const int row = g8 + 8 * i;
+      pr += *reinterpret_cast<const float*>(b + row * PITCH + 4 * p) * gs[row];
     }
-    __syncthreads();
+    pr += __shfl_xor(pr, 1, 64);
+    pr += __shfl_xor(pr, 2, 64);
+    pr += __shfl_xor(pr, 4, 64);
+    if (g8 == 0) {
+      const float sp = s_st[k & 1][p];
+      const float r = sp - pr;
+      const float ar = fabsf(r);
+      const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
+      d_st[k & 1][p] = xv - sp;
+      m_st[k & 1][p] = ar > lam ? 1.f : 0.f;
+    }
+  };
+  auto gram = [&](int64_t k) {
+    const unsigned char* b = ubuf(k);
     // U^T d: unit (row, octet q) sums 8 pixels in FP32, then adds in FP64
 #pragma unroll
     for (int u = 0; u < UPT; ++u) {
       const int unit = tid + 256 * u;
       if (unit < ROWS * 4) {
         const int row = unit >> 2, q = unit & 3;
-        const float4 u0 = *reinterpret_cast<const float4*>(lds + row * PITCH + 32 * q);
-        const float4 u1 = *reinterpret_cast<const float4*>(lds + row * PITCH + 32 * q + 16);
-        const float4 d0 = *reinterpret_cast<const float4*>(d_st + 8 * q);
-        const float4 d1 = *reinterpret_cast<const float4*>(d_st + 8 * q + 4);
+        const float4 u0 = *reinterpret_cast<const float4*>(b + row * PITCH + 32 * q);
+        const float4 u1 = *reinterpret_cast<const float4*>(b + row * PITCH + 32 * q + 16);
+        const float4 d0 = *reinterpret_cast<const float4*>(&d_st[k & 1][8 * q]);
+        const float4 d1 = *reinterpret_cast<const float4*>(&d_st[k & 1][8 * q + 4]);
         const float t = u0.x * d0.x + u0.y * d0.y + u0.z * d0.z + u0.w * d0.w +
                         u1.x * d1.x + u1.y * d1.y + u1.z * d1.z + u1.w * d1.w;
         accd[u] += static_cast<double>(t);
@@ -686,33 +692,44 @@ __global__ __launch_bounds__(256) void ssn_evalgram_kernel(const float* __restri
     }
     // masked Gram: wave w takes pixels 8 w .. 8 w + 7; lane l feeds pixel
     // 8 w + 4 (l / 32) + i to the i-th 32x32x2 MFMA of every tile
-    {
-      const float4 mk = *reinterpret_cast<const float4*>(m_st + 8 * wave + 4 * lh);
-      float fr[NRG][4];
+    const float4 mk = *reinterpret_cast<const float4*>(&m_st[k & 1][8 * wave + 4 * lh]);
+    float fr[NRG][4];
 #pragma unroll
-      for (int g = 0; g < NRG; ++g) {
-        const float4 v = *reinterpret_cast<const float4*>(lds + (32 * g + lr) * PITCH + 32 * wave + 16 * lh);
-        fr[g][0] = v.x * mk.x; fr[g][1] = v.y * mk.y; fr[g][2] = v.z * mk.z; fr[g][3] = v.w * mk.w;
-      }
-      int tile = 0;
-#pragma unroll
-      for (int ti = 0; ti < NRG; ++ti)
-#pragma unroll
-        for (int tj = ti; tj < NRG; ++tj, ++tile)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            acc[tile] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti][i], fr[tj][i], acc[tile], 0, 0, 0);
+    for (int g = 0; g < NRG; ++g) {
+      const float4 v = *reinterpret_cast<const float4*>(b + (32 * g + lr) * PITCH + 32 * wave + 16 * lh);
+      fr[g][0] = v.x * mk.x; fr[g][1] = v.y * mk.y; fr[g][2] = v.z * mk.z; fr[g][3] = v.w * mk.w;
     }
+    int tile = 0;
+#pragma unroll
+    for (int ti = 0; ti < NRG; ++ti)
+#pragma unroll
+      for (int tj = ti; tj < NRG; ++tj, ++tile)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[tile] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti][i], fr[tj][i], acc[tile], 0, 0, 0);
+  };
+  // even stages pass through ra, odd ones through rb
+  float4 ra[NRG], rb[NRG];
+  float4 sa, sb;
+  if (S > 0) load_stage(0, ra, sa);
+  if (S > 1) load_stage(1, rb, sb);
+  if (S > 0) {
+    store_stage(0, ra, sa);
+    if (S > 2) load_stage(2, ra, sa);
+  }
+  __syncthreads();
+  auto iter = [&](int64_t n, float4 (&R)[NRG], float4& sR) {
+    if (n + 1 < S) {
+      store_stage(n + 1, R, sR);
+      if (n + 3 < S) load_stage(n + 3, R, sR);
+    }
+    if (n < S) eval(n);
+    if (n >= 1) gram(n - 1);
     __syncthreads();
   };
-
-  float4 pa[NRG], pb[NRG];
-  float4 sa, sb;
-  if (n0 < n1) load_stage(n0, pa, sa);
-  if (n0 + 32 < n1) load_stage(n0 + 32, pb, sb);
-  for (int64_t n = n0; n < n1; n += 64) {
-    process(n, pa, sa);
-    if (n + 32 < n1) process(n + 32, pb, sb);
+  for (int64_t n = 0; n <= S; n += 2) {
+    iter(n, rb, sb);
+    if (n + 1 <= S) iter(n + 1, ra, sa);
   }
   // U^T d: the 4 octets of a row sit on 4 adjacent lanes
 #pragma unroll
@@ -1230,7 +1247,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   int64_t chunk;
   red_geometry(N, nblk, chunk);
   // Gram: fewer, longer chunks (the last block reduces their partials)
-  const int64_t gblk = std::min<int64_t>(256, std::max<int64_t>(1, (N + 1023) / 1024));
+  const int64_t gblk = std::min<int64_t>(512, std::max<int64_t>(1, (N + 511) / 512));
   int64_t gchunk = (N + gblk - 1) / gblk;
   gchunk = (gchunk + 31) / 32 * 32;
   const int ngb = static_cast<int>((N + gchunk - 1) / gchunk);
