@@ -148,4 +148,9 @@ struct nys_pc_s {
   nys::DevBuf meta;               // FP64 device block, see factor.hip
   nys::DevBuf work;               // scratch of nys_apply / prox
   nys::DevBuf work2;
+  // pinned, coherent host words {sequence number, done} written by the
+  // semismooth Newton decision kernel and read by the host without a stream
+  // synchronisation; the sequence number counts decisions
+  double* hflag = nullptr;
+  double flag_seq = 0;
 };

@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <type_traits>
 
@@ -498,16 +500,30 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
 
 // F(g_try) = g_try - e . U^T (x - s) from the partials, its norm, and the
 // decision: accept (and stop, or ask for a Newton step) or backtrack.
+// The host learns the outcome from hflag = {seq, done} in pinned host memory:
+// done is written first, then (after a system-scope fence) the sequence
+// number of this decision, also when an earlier decision had finished.
+__device__ __forceinline__ void ssn_publish(double* hflag, double seq, double done) {
+  if (hflag == nullptr || threadIdx.x != 0) return;
+  __hip_atomic_store(hflag + 1, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __threadfence_system();
+  __hip_atomic_store(hflag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restrict__ part, int nblk,
                                                          int L, const double* __restrict__ meta,
                                                          double* __restrict__ state, double tol,
-                                                         int max_halvings) {
+                                                         int max_halvings, double* hflag,
+                                                         double seq) {
   __shared__ double red[512], red2[512];
   __shared__ double bsum[PcMeta::kMaxEll];
   __shared__ double Ft[PcMeta::kMaxEll];
   __shared__ int accepted;
   __shared__ double tn_s;
-  if (state[SsnState::kDone] != 0.0) return;
+  if (state[SsnState::kDone] != 0.0) {
+    ssn_publish(hflag, seq, 1.0);
+    return;
+  }
   tail_sum(part, nblk, L, red, bsum);
   double sq = 0, gq = 0;
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
@@ -546,6 +562,7 @@ __global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restric
       state[SsnState::kHalv] += 1.0;
     }
     accepted = accept ? 1 : 0;
+    ssn_publish(hflag, seq, state[SsnState::kDone]);
   }
   __syncthreads();
   if (accepted) {
@@ -610,9 +627,21 @@ __global__ __launch_bounds__(256, NRG <= 2 ? 2 : 1) void ssn_evalgram_kernel(con
   for (int u = 0; u < UPT; ++u) accd[u] = 0.0;
 
   // stage k: 4-pixel chunk at pixel 4 ld_col of rows 32 g + ld_row (zero
-  // past N or row L), and of s on the first 8 threads
+  // past N or row L), and of s on the first 8 threads.  A stage inside the
+  // image (block-uniform test) loads without branches, rows >= L from row 0
+  // (zeroed when stored), so that the loads stay in flight.
   auto load_stage = [&](int64_t k, float4 (&val)[NRG], float4& sv) {
-    const int64_t nn = n0 + 32 * k + 4 * ld_col;
+    const int64_t nb = n0 + 32 * k;
+    const int64_t nn = nb + 4 * ld_col;
+    if (nb + 32 <= N) {
+#pragma unroll
+      for (int g = 0; g < NRG; ++g) {
+        const int row = 32 * g + ld_row;
+        val[g] = *reinterpret_cast<const float4*>(U + static_cast<size_t>(row < L ? row : 0) * ldu + nn);
+      }
+      if (wave == 0) sv = *reinterpret_cast<const float4*>(s + nn);
+      return;
+    }
     const bool full = nn + 4 <= N;
 #pragma unroll
     for (int g = 0; g < NRG; ++g) {
@@ -647,8 +676,12 @@ __global__ __launch_bounds__(256, NRG <= 2 ? 2 : 1) void ssn_evalgram_kernel(con
   auto store_stage = [&](int64_t k, const float4 (&val)[NRG], const float4& sv) {
     unsigned char* b = ubuf(k);
 #pragma unroll
-    for (int g = 0; g < NRG; ++g)
-      *reinterpret_cast<float4*>(b + (32 * g + ld_row) * PITCH + ld_col * 16) = val[g];
+    for (int g = 0; g < NRG; ++g) {
+      const bool in = 32 * g + ld_row < L;
+      const float4 v = val[g];
+      *reinterpret_cast<float4*>(b + (32 * g + ld_row) * PITCH + ld_col * 16) =
+          make_float4(in ? v.x : 0.f, in ? v.y : 0.f, in ? v.z : 0.f, in ? v.w : 0.f);
+    }
     if (tid < 8) *reinterpret_cast<float4*>(&s_st[k & 1][4 * tid]) = sv;
   };
   // r of pixel p = tid / 8 from the 8 lanes taking rows g8, g8 + 8, ...
@@ -1207,7 +1240,8 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
   }
   NYS_TRY(launch_check("ssn_eval_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(512), 0, st, part, nblk,
-                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30);
+                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
+                     pc->flag_seq += 1.0);
   return launch_check("ssn_decide_kernel");
 }
 
@@ -1223,7 +1257,7 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
                      pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part);
   NYS_TRY(launch_check("ssn_evalgram_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(512), 0, st, fpart, nblk, L,
-                     pc->meta.as<double>(), state, tol, 30);
+                     pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq += 1.0);
   NYS_TRY(launch_check("ssn_decide_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
   hipLaunchKernelGGL((ssn_gram_stage2_kernel<NRG>), dim3(NTRI * 4, 16), dim3(256), 0, st, part, nblk,
@@ -1236,6 +1270,28 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
   hipLaunchKernelGGL((ssn_solve_kernel<NRG>), dim3(1), dim3(256), lds, st, part2,
                      static_cast<int>(pc->ell), pc->meta.as<double>(), state);
   return launch_check("ssn_solve_kernel");
+}
+
+// Waits until the decision kernel last enqueued on st has published its
+// outcome (sequence number pc->flag_seq).  Spins on the pinned word for up to
+// 2 s, then falls back to a stream synchronisation.
+static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done) {
+  volatile double* f = pc->hflag;
+  const double want = pc->flag_seq;
+  const auto t0 = std::chrono::steady_clock::now();
+  while (f[0] != want) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+      NYS_CHECK_HIP(hipStreamSynchronize(st));
+      if (f[0] != want) {
+        set_error("semismooth Newton decision %.0f not published", want);
+        return NYS_EHIP;
+      }
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  done = f[1] != 0.0;
+  return NYS_OK;
 }
 
 template <class T>
@@ -1265,6 +1321,13 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   double* gpart = part + static_cast<size_t>(std::max(nblk, ngb)) * L;
   double* Mj = gpart + gpart_d;
   uint8_t* mask = reinterpret_cast<uint8_t*>(Mj + LL);
+  if (!pc->hflag) {
+    void* h = nullptr;
+    NYS_CHECK_HIP(hipHostMalloc(&h, 2 * sizeof(double), hipHostMallocCoherent));
+    pc->hflag = static_cast<double*>(h);
+    pc->hflag[0] = pc->hflag[1] = 0.0;
+    pc->flag_seq = 0.0;
+  }
   const T lam = static_cast<T>(lam_bar);
   const double tol = reg.newton_tol > 0 ? reg.newton_tol : (sizeof(T) == 8 ? 1e-12 : 1e-6);
   const int max_trials = reg.max_newton > 0 ? reg.max_newton : 60;
@@ -1298,14 +1361,12 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
                          pc->meta.as<double>(), state);
       NYS_TRY(launch_check("ssn_solve_f64_kernel"));
     }
-    // poll the done flag after the 2nd trial and then after every trial
-    if (trial >= 1) {
-      double done = 0;
-      NYS_CHECK_HIP(hipMemcpyAsync(&done, state + SsnState::kDone, sizeof(double),
-                                   hipMemcpyDeviceToHost, st));
-      NYS_CHECK_HIP(hipStreamSynchronize(st));
-      if (done != 0.0) break;
-    }
+    // the decision of this trial, read from pinned host memory while the
+    // device goes on with the Newton step; the next trial is enqueued only
+    // if it is needed
+    bool done = false;
+    NYS_TRY(ssn_wait_decision(pc, st, done));
+    if (done) break;
   }
   if (trials_out) *trials_out = trial + 1;
   hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, pc->U.as<T>(),
