@@ -174,7 +174,8 @@ nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
  *   gamma = diag(e) U^T (soft(s - U gamma) - s), semismooth Newton with
  *   backtracking on ||F||; x = soft(s - U gamma).  `state` holds gamma
  *   (ell FP64 values) as warm start.  P = I gives x = soft(s).
- * state may be NULL (cold start, not kept).
+ * state may be NULL (cold start, not kept).  x may be s (in place); no other
+ * overlap of s and x is allowed.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t kind;        /* nys_reg_kind */

@@ -80,23 +80,26 @@ __device__ __forceinline__ void block_reduce(A (&acc)[NV], double* red, double* 
 }
 
 // out[k] = sum_{b < nblk} part[b * L + k] for k < L (L <= 128), with all
-// threads of the block: blockDim / L slices of the blocks, four accumulators
-// each, combined in a fixed order.  red: blockDim.x doubles of LDS.
+// threads of the block: blockDim / L slices of the blocks, 32 loads in flight
+// and eight accumulators each, combined in a fixed order.  red: blockDim.x
+// doubles of LDS.
 __device__ __forceinline__ void tail_sum(const double* __restrict__ part, int nblk, int L,
                                          double* red, double* out) {
   const int S = blockDim.x / L;
   const int k = threadIdx.x % L, sl = threadIdx.x / L;
   if (sl < S) {
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    // 32 loads in flight per round, added into 8 accumulators
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int b = sl;
-    for (; b + 3 * S < nblk; b += 4 * S) {
-      a0 += part[static_cast<size_t>(b) * L + k];
-      a1 += part[static_cast<size_t>(b + S) * L + k];
-      a2 += part[static_cast<size_t>(b + 2 * S) * L + k];
-      a3 += part[static_cast<size_t>(b + 3 * S) * L + k];
+    for (; b + 31 * S < nblk; b += 32 * S) {
+      double v[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) v[i] = part[static_cast<size_t>(b + i * S) * L + k];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) a[i & 7] += v[i];
     }
-    for (; b < nblk; b += S) a0 += part[static_cast<size_t>(b) * L + k];
-    red[sl * L + k] = (a0 + a1) + (a2 + a3);
+    for (; b < nblk; b += S) a[0] += part[static_cast<size_t>(b) * L + k];
+    red[sl * L + k] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   __syncthreads();
   for (int kk = threadIdx.x; kk < L; kk += blockDim.x) {
@@ -510,12 +513,12 @@ __device__ __forceinline__ void ssn_publish(double* hflag, double seq, double do
   __hip_atomic_store(hflag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restrict__ part, int nblk,
+__global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restrict__ part, int nblk,
                                                          int L, const double* __restrict__ meta,
                                                          double* __restrict__ state, double tol,
                                                          int max_halvings, double* hflag,
                                                          double seq) {
-  __shared__ double red[512], red2[512];
+  __shared__ double red[1024], red2[1024];
   __shared__ double bsum[PcMeta::kMaxEll];
   __shared__ double Ft[PcMeta::kMaxEll];
   __shared__ int accepted;
@@ -581,215 +584,148 @@ __global__ __launch_bounds__(512) void ssn_decide_kernel(const double* __restric
 typedef float floatx16_v __attribute__((ext_vector_type(16)));
 
 // One pass over an FP32 U at the trial point g (Thm. 1): per pixel
-// r = s - U g, x = soft_lam(r), d = x - s and D = [|r| > lam]; per block the
+// r = s - U g, x = soft_lam(r) (written to xo: the prox itself if g is the
+// accepted final point), d = x - s and D = [|r| > lam]; per block the
 // partial U^T d (FP64) for F(g) and the partial masked Gram U^T D U (FP32
 // matrix cores) for the Newton step that follows if g is accepted.
-// Stages of 32 pixels of the 32 NRG rows (and of s) go through three LDS
-// buffers in a software pipeline with one barrier per stage: iteration n
-// stores stage n + 1, evaluates stage n and feeds stage n - 1 to the Gram and
-// U^T d; the loads of stages n + 2 and n + 3 are in flight meanwhile.
+// Every wave owns stages of 64 pixels: lane p loads the 32 NRG values of
+// pixel p (one coalesced row segment per load), evaluates r, and puts the
+// stage in its own LDS region (pixel-major), from which the MFMAs (32 x 32
+// tiles of the upper triangle, the mask applied to one operand) and U^T d
+// (lane = row) read it; the loads of the wave's next stage are issued before
+// that.  No block barrier until the final reductions.  Rows past L and
+// pixels past the block's range read clamped, finite values and contribute
+// nothing (g is zero past L; d and D are zero outside the range).
+template <int NRG> constexpr int evg_waves() { return NRG <= 2 ? 8 : 4; }
+template <int NRG> constexpr int evg_pitch() { return 32 * NRG + 4; }
+template <int NRG> constexpr size_t evg_lds_bytes() {
+  return sizeof(float) * evg_waves<NRG>() * 64 * evg_pitch<NRG>();
+}
+
 template <int NRG>
-__global__ __launch_bounds__(256, NRG <= 2 ? 2 : 1) void ssn_evalgram_kernel(const float* __restrict__ U,
-                                                              int64_t ldu,
-                                                              const float* __restrict__ s,
-                                                              int64_t N, int L, int64_t chunk,
-                                                              float lam,
-                                                              const double* __restrict__ state,
-                                                              double* __restrict__ part,
-                                                              float* __restrict__ gpart) {
+__global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
+    const float* __restrict__ U, int64_t ldu, const float* __restrict__ s, int64_t N, int L,
+    int64_t chunk, float lam, const double* __restrict__ state, double* __restrict__ part,
+    float* __restrict__ gpart, float* __restrict__ xo) {
+  constexpr int W = evg_waves<NRG>();
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   constexpr int ROWS = 32 * NRG;
-  constexpr int PITCH = 144;                          // bytes per LDS row: 32 floats + pad
-  constexpr int UB = ROWS * PITCH;
-  constexpr int LDSB = 3 * UB > NTRI * 4096 ? 3 * UB : NTRI * 4096;
-  constexpr int UPT = (ROWS * 4 + 255) / 256;         // (row, 8-pixel octet) units per thread
-  __shared__ __align__(16) unsigned char lds[LDSB];
-  __shared__ __align__(16) float s_st[2][32];         // s of a stage
-  __shared__ __align__(16) float d_st[2][32];         // x - s of a stage
-  __shared__ __align__(16) float m_st[2][32];         // D of a stage (1 or 0)
-  __shared__ float gs[ROWS];
-  __shared__ double ud[ROWS];
+  constexpr int PITCH = evg_pitch<NRG>();
+  constexpr int RPL = (ROWS + 63) / 64;       // rows of U^T d per lane
+  extern __shared__ __align__(16) float evg_lds[];
+  __shared__ __align__(16) float gs[ROWS];
+  __shared__ __align__(16) float dw[W][64];
+  __shared__ __align__(16) float mw[W][64];
+  __shared__ double udw[W][ROWS];
   if (state[SsnState::kDone] != 0.0) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 31, lh = lane >> 5;
-  const int ld_row = tid >> 3, ld_col = tid & 7;
-  for (int k = tid; k < ROWS; k += 256) gs[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
+  for (int k = tid; k < ROWS; k += 64 * W) gs[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
+  __syncthreads();
+  float* ws = evg_lds + wave * 64 * PITCH;
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
   const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
-  const int64_t S = n1 > n0 ? (n1 - n0 + 31) / 32 : 0;
+  const int nst = n1 > n0 ? static_cast<int>((n1 - n0 + 63) / 64) : 0;
   floatx16_v acc[NTRI];
 #pragma unroll
   for (int t = 0; t < NTRI; ++t)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
-  double accd[UPT];
+  double udacc[RPL];
 #pragma unroll
-  for (int u = 0; u < UPT; ++u) accd[u] = 0.0;
-
-  // stage k: 4-pixel chunk at pixel 4 ld_col of rows 32 g + ld_row (zero
-  // past N or row L), and of s on the first 8 threads.  A stage inside the
-  // image (block-uniform test) loads without branches, rows >= L from row 0
-  // (zeroed when stored), so that the loads stay in flight.
-  auto load_stage = [&](int64_t k, float4 (&val)[NRG], float4& sv) {
-    const int64_t nb = n0 + 32 * k;
-    const int64_t nn = nb + 4 * ld_col;
-    if (nb + 32 <= N) {
+  for (int i = 0; i < RPL; ++i) udacc[i] = 0.0;
+  float u[ROWS];
+  float sv = 0.f;
+  auto load = [&](int t) {
+    int64_t pix = n0 + 64 * static_cast<int64_t>(t) + lane;
+    pix = pix < N ? pix : N - 1;
 #pragma unroll
-      for (int g = 0; g < NRG; ++g) {
-        const int row = 32 * g + ld_row;
-        val[g] = *reinterpret_cast<const float4*>(U + static_cast<size_t>(row < L ? row : 0) * ldu + nn);
-      }
-      if (wave == 0) sv = *reinterpret_cast<const float4*>(s + nn);
-      return;
+    for (int k = 0; k < ROWS; ++k) {
+      const int row = k < L ? k : L - 1;
+      u[k] = U[static_cast<size_t>(row) * ldu + pix];
     }
-    const bool full = nn + 4 <= N;
-#pragma unroll
-    for (int g = 0; g < NRG; ++g) {
-      const int row = 32 * g + ld_row;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row < L && nn < N) {
-        const float* src = U + static_cast<size_t>(row) * ldu + nn;
-        if (full) {
-          v = *reinterpret_cast<const float4*>(src);
-        } else {
-          v.x = src[0];
-          v.y = nn + 1 < N ? src[1] : 0.f;
-          v.z = nn + 2 < N ? src[2] : 0.f;
-          v.w = nn + 3 < N ? src[3] : 0.f;
-        }
-      }
-      val[g] = v;
-    }
-    sv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (tid < 8 && nn < N) {
-      if (full) {
-        sv = *reinterpret_cast<const float4*>(s + nn);
-      } else {
-        sv.x = s[nn];
-        sv.y = nn + 1 < N ? s[nn + 1] : 0.f;
-        sv.z = nn + 2 < N ? s[nn + 2] : 0.f;
-        sv.w = nn + 3 < N ? s[nn + 3] : 0.f;
-      }
-    }
+    sv = s[pix];
   };
-  auto ubuf = [&](int64_t k) { return lds + static_cast<int>(k % 3) * UB; };
-  auto store_stage = [&](int64_t k, const float4 (&val)[NRG], const float4& sv) {
-    unsigned char* b = ubuf(k);
-#pragma unroll
-    for (int g = 0; g < NRG; ++g) {
-      const bool in = 32 * g + ld_row < L;
-      const float4 v = val[g];
-      *reinterpret_cast<float4*>(b + (32 * g + ld_row) * PITCH + ld_col * 16) =
-          make_float4(in ? v.x : 0.f, in ? v.y : 0.f, in ? v.z : 0.f, in ? v.w : 0.f);
-    }
-    if (tid < 8) *reinterpret_cast<float4*>(&s_st[k & 1][4 * tid]) = sv;
-  };
-  // r of pixel p = tid / 8 from the 8 lanes taking rows g8, g8 + 8, ...
-  auto eval = [&](int64_t k) {
-    const unsigned char* b = ubuf(k);
-    const int p = tid >> 3, g8 = tid & 7;
+  int t = wave;
+  if (t < nst) load(t);
+  for (; t < nst; t += W) {
+    const int64_t px = n0 + 64 * static_cast<int64_t>(t) + lane;
+    const bool in = px < n1;
     float pr = 0.f;
 #pragma unroll
-    for (int i = 0; i < ROWS / 8; ++i) {
-      const int row = g8 + 8 * i;
-      pr += *reinterpret_cast<const float*>(b + row * PITCH + 4 * p) * gs[row];
-    }
-    pr += __shfl_xor(pr, 1, 64);
-    pr += __shfl_xor(pr, 2, 64);
-    pr += __shfl_xor(pr, 4, 64);
-    if (g8 == 0) {
-      const float sp = s_st[k & 1][p];
-      const float r = sp - pr;
-      const float ar = fabsf(r);
-      const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
-      d_st[k & 1][p] = xv - sp;
-      m_st[k & 1][p] = ar > lam ? 1.f : 0.f;
-    }
-  };
-  auto gram = [&](int64_t k) {
-    const unsigned char* b = ubuf(k);
-    // U^T d: unit (row, octet q) sums 8 pixels in FP32, then adds in FP64
+    for (int k = 0; k < ROWS; ++k) pr += u[k] * gs[k];
+    const float r = sv - pr;
+    const float ar = fabsf(r);
+    const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
+    if (in && xo != nullptr) xo[px] = xv;
 #pragma unroll
-    for (int u = 0; u < UPT; ++u) {
-      const int unit = tid + 256 * u;
-      if (unit < ROWS * 4) {
-        const int row = unit >> 2, q = unit & 3;
-        const float4 u0 = *reinterpret_cast<const float4*>(b + row * PITCH + 32 * q);
-        const float4 u1 = *reinterpret_cast<const float4*>(b + row * PITCH + 32 * q + 16);
-        const float4 d0 = *reinterpret_cast<const float4*>(&d_st[k & 1][8 * q]);
-        const float4 d1 = *reinterpret_cast<const float4*>(&d_st[k & 1][8 * q + 4]);
-        const float t = u0.x * d0.x + u0.y * d0.y + u0.z * d0.z + u0.w * d0.w +
-                        u1.x * d1.x + u1.y * d1.y + u1.z * d1.z + u1.w * d1.w;
-        accd[u] += static_cast<double>(t);
+    for (int k = 0; k < ROWS; k += 4)
+      *reinterpret_cast<float4*>(ws + lane * PITCH + k) = make_float4(u[k], u[k + 1], u[k + 2], u[k + 3]);
+    dw[wave][lane] = in ? xv - sv : 0.f;
+    mw[wave][lane] = (in && ar > lam) ? 1.f : 0.f;
+    if (t + W < nst) load(t + W);
+    // masked Gram: k-step j takes pixels 2 j and 2 j + 1 (lane half lh)
+#pragma unroll 4
+    for (int j = 0; j < 32; ++j) {
+      const int p = 2 * j + lh;
+      const float mk = mw[wave][p];
+      float fr[NRG];
+#pragma unroll
+      for (int g = 0; g < NRG; ++g) fr[g] = ws[p * PITCH + 32 * g + lr] * mk;
+      int tile = 0;
+#pragma unroll
+      for (int ti = 0; ti < NRG; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NRG; ++tj, ++tile)
+          acc[tile] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti], fr[tj], acc[tile], 0, 0, 0);
+    }
+    // U^T d, lane = row: 8 pixels in FP32, then added in FP64
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = lane + 64 * i;
+      if (row < ROWS) {
+#pragma unroll 2
+        for (int p = 0; p < 64; p += 8) {
+          const float4 d0 = *reinterpret_cast<const float4*>(&dw[wave][p]);
+          const float4 d1 = *reinterpret_cast<const float4*>(&dw[wave][p + 4]);
+          const float* c = ws + p * PITCH + row;
+          const float tsum = c[0] * d0.x + c[PITCH] * d0.y + c[2 * PITCH] * d0.z + c[3 * PITCH] * d0.w +
+                             c[4 * PITCH] * d1.x + c[5 * PITCH] * d1.y + c[6 * PITCH] * d1.z +
+                             c[7 * PITCH] * d1.w;
+          udacc[i] += static_cast<double>(tsum);
+        }
       }
     }
-    // masked Gram: wave w takes pixels 8 w .. 8 w + 7; lane l feeds pixel
-    // 8 w + 4 (l / 32) + i to the i-th 32x32x2 MFMA of every tile
-    const float4 mk = *reinterpret_cast<const float4*>(&m_st[k & 1][8 * wave + 4 * lh]);
-    float fr[NRG][4];
+  }
+  // U^T d: waves summed in a fixed order
 #pragma unroll
-    for (int g = 0; g < NRG; ++g) {
-      const float4 v = *reinterpret_cast<const float4*>(b + (32 * g + lr) * PITCH + 32 * wave + 16 * lh);
-      fr[g][0] = v.x * mk.x; fr[g][1] = v.y * mk.y; fr[g][2] = v.z * mk.z; fr[g][3] = v.w * mk.w;
-    }
-    int tile = 0;
-#pragma unroll
-    for (int ti = 0; ti < NRG; ++ti)
-#pragma unroll
-      for (int tj = ti; tj < NRG; ++tj, ++tile)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          acc[tile] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti][i], fr[tj][i], acc[tile], 0, 0, 0);
-  };
-  // even stages pass through ra, odd ones through rb
-  float4 ra[NRG], rb[NRG];
-  float4 sa, sb;
-  if (S > 0) load_stage(0, ra, sa);
-  if (S > 1) load_stage(1, rb, sb);
-  if (S > 0) {
-    store_stage(0, ra, sa);
-    if (S > 2) load_stage(2, ra, sa);
+  for (int i = 0; i < RPL; ++i) {
+    const int row = lane + 64 * i;
+    if (row < ROWS) udw[wave][row] = udacc[i];
   }
   __syncthreads();
-  auto iter = [&](int64_t n, float4 (&R)[NRG], float4& sR) {
-    if (n + 1 < S) {
-      store_stage(n + 1, R, sR);
-      if (n + 3 < S) load_stage(n + 3, R, sR);
-    }
-    if (n < S) eval(n);
-    if (n >= 1) gram(n - 1);
-    __syncthreads();
-  };
-  for (int64_t n = 0; n <= S; n += 2) {
-    iter(n, rb, sb);
-    if (n + 1 <= S) iter(n + 1, ra, sa);
-  }
-  // U^T d: the 4 octets of a row sit on 4 adjacent lanes
+  for (int k = tid; k < L; k += 64 * W) {
+    double a = 0.0;
 #pragma unroll
-  for (int u = 0; u < UPT; ++u) {
-    double v = accd[u];
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    const int unit = tid + 256 * u;
-    if (unit < ROWS * 4 && (unit & 3) == 0) ud[unit >> 2] = v;
+    for (int w = 0; w < W; ++w) a += udw[w][k];
+    part[static_cast<size_t>(blockIdx.x) * L + k] = a;
   }
-  // Gram: the four waves' tiles summed in LDS (fixed order)
-  float* sum = reinterpret_cast<float*>(lds);     // NTRI * 1024 floats
-  for (int w = 0; w < 4; ++w) {
+  // Gram: the waves' tiles summed in LDS in a fixed order
+  float* sum = evg_lds;     // NTRI * 1024 floats
+  for (int w = 0; w < W; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int t = 0; t < NTRI; ++t)
+      for (int tt = 0; tt < NTRI; ++tt)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int idx = t * 1024 + (8 * (r / 4) + 4 * lh + (r & 3)) * 32 + lr;
-          sum[idx] = (w == 0 ? 0.f : sum[idx]) + acc[t][r];
+          const int idx = tt * 1024 + (8 * (r / 4) + 4 * lh + (r & 3)) * 32 + lr;
+          sum[idx] = (w == 0 ? 0.f : sum[idx]) + acc[tt][r];
         }
     }
     __syncthreads();
   }
   float* dst = gpart + static_cast<size_t>(blockIdx.x) * NTRI * 1024;
-  for (int e = tid; e < NTRI * 1024; e += 256) dst[e] = sum[e];
-  for (int k = tid; k < L; k += 256) part[static_cast<size_t>(blockIdx.x) * L + k] = ud[k];
+  for (int e = tid; e < NTRI * 1024; e += 64 * W) dst[e] = sum[e];
 }
 
 // Stage 2 of the Gram reduction: block (e, q) sums partials q, q + 16, ... of
@@ -804,14 +740,14 @@ __global__ __launch_bounds__(256) void ssn_gram_stage2_kernel(const float* __res
   const int e = blockIdx.x * 256 + threadIdx.x, q = blockIdx.y;
   if (e >= NTRI * 1024) return;
   const size_t stride = static_cast<size_t>(NTRI) * 1024;
-  double a0 = 0, a1 = 0;
+  double a[4] = {0, 0, 0, 0};
   int b = q;
-  for (; b + 16 < nblk; b += 32) {
-    a0 += static_cast<double>(part[b * stride + e]);
-    a1 += static_cast<double>(part[(b + 16) * stride + e]);
+  for (; b + 48 < nblk; b += 64) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] += static_cast<double>(part[(b + 16 * i) * stride + e]);
   }
-  for (; b < nblk; b += 16) a0 += static_cast<double>(part[b * stride + e]);
-  part2[q * stride + e] = a0 + a1;
+  for (; b < nblk; b += 16) a[0] += static_cast<double>(part[b * stride + e]);
+  part2[q * stride + e] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // ---- Newton direction: J delta = -F(gamma), J = I + diag(e) M, by LU with
@@ -1084,9 +1020,12 @@ __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict
     const int tj = ti + t;
     const int gi = 32 * ti + (rr >> 5), gj = 32 * tj + (rr & 31);
     if (gi >= L || gj >= L || (ti == tj && gi > gj)) continue;
+    double v[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) v[b] = part2[b * stride + e];
     double sacc = 0;
 #pragma unroll
-    for (int b = 0; b < 16; ++b) sacc += part2[b * stride + e];
+    for (int b = 0; b < 16; ++b) sacc += v[b];
     A[gi * LP1 + gj] = (gi == gj ? 1.0 : 0.0) + meta[PcMeta::kE + gi] * sacc;
     if (gi != gj) A[gj * LP1 + gi] = meta[PcMeta::kE + gj] * sacc;
   }
@@ -1239,7 +1178,7 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
     default: launch_ssn_eval<T, 128>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
   }
   NYS_TRY(launch_check("ssn_eval_kernel"));
-  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(512), 0, st, part, nblk,
+  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
                      static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
                      pc->flag_seq += 1.0);
   return launch_check("ssn_decide_kernel");
@@ -1250,13 +1189,17 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
 template <int NRG>
 static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double* state,
                                    double* fpart, float* part, int nblk, int64_t chunk, double tol,
-                                   hipStream_t st) {
+                                   float* x, hipStream_t st) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   const int L = static_cast<int>(pc->ell);
-  hipLaunchKernelGGL((ssn_evalgram_kernel<NRG>), dim3(nblk), dim3(256), 0, st, pc->U.as<float>(),
-                     pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part);
+  constexpr size_t elds = evg_lds_bytes<NRG>();
+  static_assert(elds >= sizeof(float) * NTRI * 1024, "LDS of the fused pass holds the Gram sum");
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_evalgram_kernel<NRG>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(elds));
+  hipLaunchKernelGGL((ssn_evalgram_kernel<NRG>), dim3(nblk), dim3(64 * evg_waves<NRG>()), elds, st,
+                     pc->U.as<float>(), pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part, x);
   NYS_TRY(launch_check("ssn_evalgram_kernel"));
-  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(512), 0, st, fpart, nblk, L,
+  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, fpart, nblk, L,
                      pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq += 1.0);
   NYS_TRY(launch_check("ssn_decide_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
@@ -1302,17 +1245,20 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   int nblk;
   int64_t chunk;
   red_geometry(N, nblk, chunk);
-  // Gram: fewer, longer chunks (the last block reduces their partials)
-  const int64_t gblk = std::min<int64_t>(512, std::max<int64_t>(1, (N + 511) / 512));
+  // fused pass: one block per CU at most, at least two 64-pixel stages per
+  // wave of a block (1024 pixels for 8 waves), chunks a multiple of 64
+  const int nrg0 = (L + 31) / 32;
+  const int64_t per_blk = 64 * 2 * (nrg0 <= 2 ? 8 : 4);
+  const int64_t gblk = std::min<int64_t>(256, std::max<int64_t>(1, (N + per_blk - 1) / per_blk));
   int64_t gchunk = (N + gblk - 1) / gblk;
-  gchunk = (gchunk + 31) / 32 * 32;
+  gchunk = (gchunk + 63) / 64 * 64;
   const int ngb = static_cast<int>((N + gchunk - 1) / gchunk);
   const int nrg = (L + 31) / 32;
   const size_t LL = static_cast<size_t>(L) * L;
   size_t gpart_d;
-  if (sizeof(T) == 4)
-    gpart_d = (static_cast<size_t>(ngb) * nrg * (nrg + 1) / 2 * 1024 + 1) / 2 +
-              static_cast<size_t>(16) * nrg * (nrg + 1) / 2 * 1024 + 1;
+  const size_t ntri = static_cast<size_t>(nrg) * (nrg + 1) / 2;
+  if (sizeof(T) == 4)   // block partials (FP32), then part2 (16 sets)
+    gpart_d = (static_cast<size_t>(ngb) * ntri * 1024 + 1) / 2 + 16 * ntri * 1024 + 1;
   else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
   const size_t need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
   NYS_TRY(pc->work2.ensure(sizeof(double) * need + N + 256));
@@ -1334,16 +1280,20 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
   NYS_TRY(launch_check("ssn_init_kernel"));
   int trial = 0;
+  bool done = false;
   for (; trial < max_trials; ++trial) {
     if constexpr (sizeof(T) == 4) {
       float* gp = reinterpret_cast<float*>(gpart);
       const float* sf = reinterpret_cast<const float*>(s);
+      // x aliasing s (an in-place prox) gets no trial writes
+      float* xf = static_cast<const void*>(x) == static_cast<const void*>(s)
+                      ? nullptr : reinterpret_cast<float*>(x);
       const float lf = static_cast<float>(lam);
       switch (nrg) {
-        case 1: NYS_TRY(launch_ssn_trial<1>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
-        case 2: NYS_TRY(launch_ssn_trial<2>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
-        case 3: NYS_TRY(launch_ssn_trial<3>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
-        default: NYS_TRY(launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, st)); break;
+        case 1: NYS_TRY(launch_ssn_trial<1>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
+        case 2: NYS_TRY(launch_ssn_trial<2>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
+        case 3: NYS_TRY(launch_ssn_trial<3>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
+        default: NYS_TRY(launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
       }
     } else {
       NYS_TRY(launch_eval<T>(pc, s, lam, state, mask, part, nblk, chunk, tol, st));
@@ -1364,14 +1314,17 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     // the decision of this trial, read from pinned host memory while the
     // device goes on with the Newton step; the next trial is enqueued only
     // if it is needed
-    bool done = false;
     NYS_TRY(ssn_wait_decision(pc, st, done));
     if (done) break;
   }
   if (trials_out) *trials_out = trial + 1;
-  hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, pc->U.as<T>(),
-                     pc->ldu, s, state, N, L, lam, x);
-  NYS_TRY(launch_check("ssn_final_kernel"));
+  // the FP32 pass has written soft(s - U g) of its trial point g to x: when
+  // the iteration stopped there (accepted and converged), x is the prox
+  if (!(sizeof(T) == 4 && done && static_cast<const void*>(x) != static_cast<const void*>(s))) {
+    hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, pc->U.as<T>(),
+                       pc->ldu, s, state, N, L, lam, x);
+    NYS_TRY(launch_check("ssn_final_kernel"));
+  }
   if (gamma_state) {
     hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
     NYS_TRY(launch_check("ssn_store_gamma_kernel"));
