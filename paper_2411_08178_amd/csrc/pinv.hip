@@ -586,21 +586,25 @@ typedef float floatx16_v __attribute__((ext_vector_type(16)));
 // One pass over an FP32 U at the trial point g (Thm. 1): per pixel
 // r = s - U g, x = soft_lam(r) (written to xo: the prox itself if g is the
 // accepted final point), d = x - s and D = [|r| > lam]; per block the
-// partial U^T d (FP64) for F(g) and the partial masked Gram U^T D U (FP32
-// matrix cores) for the Newton step that follows if g is accepted.
+// partial U^T d (FP64) for F(g) and the partial masked Gram U^T D U for the
+// Newton step that follows if g is accepted.
 // Every wave owns stages of 64 pixels: lane p loads the 32 NRG values of
 // pixel p (one coalesced row segment per load), evaluates r, and puts the
-// stage in its own LDS region (pixel-major), from which the MFMAs (32 x 32
-// tiles of the upper triangle, the mask applied to one operand) and U^T d
+// stage in its own LDS region (row-major), from which the Gram and U^T d
 // (lane = row) read it; the loads of the wave's next stage are issued before
-// that.  No block barrier until the final reductions.  Rows past L and
-// pixels past the block's range read clamped, finite values and contribute
-// nothing (g is zero past L; d and D are zero outside the range).
+// that.  No block barrier until the final reductions.  The Gram runs on the
+// BF16 matrix cores with every masked value split as hi + lo (hi = bf16(v),
+// lo = bf16(v - hi)): hi hi^T + hi lo^T + lo hi^T in FP32 accumulation, a
+// relative error near 2^-16 -- the Gram only shapes the Newton direction; F
+// itself is evaluated in FP32 with FP64 sums.  Rows past L and pixels past the
+// block's range read clamped, finite values and contribute nothing (g is zero
+// past L; d and D are zero outside the range).
 template <int NRG> constexpr int evg_waves() { return NRG <= 2 ? 8 : 4; }
-template <int NRG> constexpr int evg_pitch() { return 32 * NRG + 4; }
+constexpr int kEvgPitch = 68;   // floats per LDS row of a stage: 64 pixels + pad
 template <int NRG> constexpr size_t evg_lds_bytes() {
-  return sizeof(float) * evg_waves<NRG>() * 64 * evg_pitch<NRG>();
+  return sizeof(float) * evg_waves<NRG>() * 32 * NRG * kEvgPitch;
 }
+typedef __bf16 bf16x8_v __attribute__((ext_vector_type(8)));
 
 template <int NRG>
 __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
@@ -610,7 +614,7 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
   constexpr int W = evg_waves<NRG>();
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   constexpr int ROWS = 32 * NRG;
-  constexpr int PITCH = evg_pitch<NRG>();
+  constexpr int PP = kEvgPitch;
   constexpr int RPL = (ROWS + 63) / 64;       // rows of U^T d per lane
   extern __shared__ __align__(16) float evg_lds[];
   __shared__ __align__(16) float gs[ROWS];
@@ -622,7 +626,7 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
   const int lr = lane & 31, lh = lane >> 5;
   for (int k = tid; k < ROWS; k += 64 * W) gs[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
   __syncthreads();
-  float* ws = evg_lds + wave * 64 * PITCH;
+  float* ws = evg_lds + wave * ROWS * PP;
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
   const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
   const int nst = n1 > n0 ? static_cast<int>((n1 - n0 + 63) / 64) : 0;
@@ -659,39 +663,56 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
     const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
     if (in && xo != nullptr) xo[px] = xv;
 #pragma unroll
-    for (int k = 0; k < ROWS; k += 4)
-      *reinterpret_cast<float4*>(ws + lane * PITCH + k) = make_float4(u[k], u[k + 1], u[k + 2], u[k + 3]);
+    for (int k = 0; k < ROWS; ++k) ws[k * PP + lane] = u[k];
     dw[wave][lane] = in ? xv - sv : 0.f;
     mw[wave][lane] = (in && ar > lam) ? 1.f : 0.f;
     if (t + W < nst) load(t + W);
-    // masked Gram: k-step j takes pixels 2 j and 2 j + 1 (lane half lh)
-#pragma unroll 4
-    for (int j = 0; j < 32; ++j) {
-      const int p = 2 * j + lh;
-      const float mk = mw[wave][p];
-      float fr[NRG];
+    // masked Gram: 4 steps of 16 pixels; lane l supplies row 32 g + l % 32,
+    // pixels 16 kk + 8 (l / 32) + 0..7
 #pragma unroll
-      for (int g = 0; g < NRG; ++g) fr[g] = ws[p * PITCH + 32 * g + lr] * mk;
+    for (int kk = 0; kk < 4; ++kk) {
+      const int p0 = 16 * kk + 8 * lh;
+      const float4 m0 = *reinterpret_cast<const float4*>(&mw[wave][p0]);
+      const float4 m1 = *reinterpret_cast<const float4*>(&mw[wave][p0 + 4]);
+      bf16x8_v hi[NRG], lo[NRG];
+#pragma unroll
+      for (int g = 0; g < NRG; ++g) {
+        const float* src = ws + (32 * g + lr) * PP + p0;
+        const float4 a0 = *reinterpret_cast<const float4*>(src);
+        const float4 a1 = *reinterpret_cast<const float4*>(src + 4);
+        const float v[8] = {a0.x * m0.x, a0.y * m0.y, a0.z * m0.z, a0.w * m0.w,
+                            a1.x * m1.x, a1.y * m1.y, a1.z * m1.z, a1.w * m1.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const __bf16 h = static_cast<__bf16>(v[i]);
+          hi[g][i] = h;
+          lo[g][i] = static_cast<__bf16>(v[i] - static_cast<float>(h));
+        }
+      }
       int tile = 0;
 #pragma unroll
       for (int ti = 0; ti < NRG; ++ti)
 #pragma unroll
-        for (int tj = ti; tj < NRG; ++tj, ++tile)
-          acc[tile] = __builtin_amdgcn_mfma_f32_32x32x2f32(fr[ti], fr[tj], acc[tile], 0, 0, 0);
+        for (int tj = ti; tj < NRG; ++tj, ++tile) {
+          acc[tile] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[ti], hi[tj], acc[tile], 0, 0, 0);
+          acc[tile] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[ti], lo[tj], acc[tile], 0, 0, 0);
+          acc[tile] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[ti], hi[tj], acc[tile], 0, 0, 0);
+        }
     }
     // U^T d, lane = row: 8 pixels in FP32, then added in FP64
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const int row = lane + 64 * i;
       if (row < ROWS) {
+        const float* c = ws + row * PP;
 #pragma unroll 2
         for (int p = 0; p < 64; p += 8) {
+          const float4 c0 = *reinterpret_cast<const float4*>(c + p);
+          const float4 c1 = *reinterpret_cast<const float4*>(c + p + 4);
           const float4 d0 = *reinterpret_cast<const float4*>(&dw[wave][p]);
           const float4 d1 = *reinterpret_cast<const float4*>(&dw[wave][p + 4]);
-          const float* c = ws + p * PITCH + row;
-          const float tsum = c[0] * d0.x + c[PITCH] * d0.y + c[2 * PITCH] * d0.z + c[3 * PITCH] * d0.w +
-                             c[4 * PITCH] * d1.x + c[5 * PITCH] * d1.y + c[6 * PITCH] * d1.z +
-                             c[7 * PITCH] * d1.w;
+          const float tsum = c0.x * d0.x + c0.y * d0.y + c0.z * d0.z + c0.w * d0.w +
+                             c1.x * d1.x + c1.y * d1.y + c1.z * d1.z + c1.w * d1.w;
           udacc[i] += static_cast<double>(tsum);
         }
       }
