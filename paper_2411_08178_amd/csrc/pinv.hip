@@ -456,6 +456,9 @@ struct SsnState {
   static constexpr int kTotal = kS + 16;
 };
 
+// Sets of partial Gram sums left by stage 2 for the Newton solve to add.
+constexpr int kGramSets = 4;
+
 // Evaluation at the trial point in one pass over U: r = s - U g, x = soft(r),
 // mask = |r| > lam, partial U^T (x - s) per block.
 template <class T, int ROWS, int LP = (ROWS <= 16 ? 16 : ROWS <= 32 ? 32 : ROWS <= 64 ? 64 : 128)>
@@ -749,8 +752,9 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
   for (int e = tid; e < NTRI * 1024; e += 64 * W) dst[e] = sum[e];
 }
 
-// Stage 2 of the Gram reduction: block (e, q) sums partials q, q + 16, ... of
-// entries 256 e .. 256 e + 255 (FP64, fixed order) into part2[q][entry].
+// Stage 2 of the Gram reduction: block (e, q) sums partials q, q + Q, ... of
+// entries 256 e .. 256 e + 255 (FP64, fixed order, 16 loads in flight per
+// thread) into part2[q][entry], Q = gridDim.y sets.
 template <int NRG>
 __global__ __launch_bounds__(256) void ssn_gram_stage2_kernel(const float* __restrict__ part,
                                                               int nblk,
@@ -758,16 +762,19 @@ __global__ __launch_bounds__(256) void ssn_gram_stage2_kernel(const float* __res
                                                               double* __restrict__ part2) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
-  const int e = blockIdx.x * 256 + threadIdx.x, q = blockIdx.y;
+  const int e = blockIdx.x * 256 + threadIdx.x, q = blockIdx.y, Q = gridDim.y;
   if (e >= NTRI * 1024) return;
   const size_t stride = static_cast<size_t>(NTRI) * 1024;
   double a[4] = {0, 0, 0, 0};
   int b = q;
-  for (; b + 48 < nblk; b += 64) {
+  for (; b + 15 * Q < nblk; b += 16 * Q) {
+    float v[16];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] += static_cast<double>(part[(b + 16 * i) * stride + e]);
+    for (int i = 0; i < 16; ++i) v[i] = part[(b + i * Q) * stride + e];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i & 3] += static_cast<double>(v[i]);
   }
-  for (; b < nblk; b += 16) a[0] += static_cast<double>(part[b * stride + e]);
+  for (; b < nblk; b += Q) a[0] += static_cast<double>(part[b * stride + e]);
   part2[q * stride + e] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
@@ -1023,8 +1030,8 @@ __device__ __forceinline__ void ssn_lu(double* A, int L, double* state) {
   else lu_wave(A, L, state);
 }
 
-// One block: J = I + diag(e) M with M = sum of the 16 stage-2 partials, then
-// the LU solve.
+// One block: J = I + diag(e) M with M = sum of the kGramSets stage-2
+// partials, then the LU solve.
 template <int NRG>
 __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict__ part2, int L,
                                                         const double* __restrict__ meta,
@@ -1041,12 +1048,12 @@ __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict
     const int tj = ti + t;
     const int gi = 32 * ti + (rr >> 5), gj = 32 * tj + (rr & 31);
     if (gi >= L || gj >= L || (ti == tj && gi > gj)) continue;
-    double v[16];
+    double v[kGramSets];
 #pragma unroll
-    for (int b = 0; b < 16; ++b) v[b] = part2[b * stride + e];
+    for (int b = 0; b < kGramSets; ++b) v[b] = part2[b * stride + e];
     double sacc = 0;
 #pragma unroll
-    for (int b = 0; b < 16; ++b) sacc += v[b];
+    for (int b = 0; b < kGramSets; ++b) sacc += v[b];
     A[gi * LP1 + gj] = (gi == gj ? 1.0 : 0.0) + meta[PcMeta::kE + gi] * sacc;
     if (gi != gj) A[gj * LP1 + gi] = meta[PcMeta::kE + gj] * sacc;
   }
@@ -1224,8 +1231,8 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
                      pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq += 1.0);
   NYS_TRY(launch_check("ssn_decide_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
-  hipLaunchKernelGGL((ssn_gram_stage2_kernel<NRG>), dim3(NTRI * 4, 16), dim3(256), 0, st, part, nblk,
-                     state, part2);
+  hipLaunchKernelGGL((ssn_gram_stage2_kernel<NRG>), dim3(NTRI * 4, kGramSets), dim3(256), 0, st, part,
+                     nblk, state, part2);
   NYS_TRY(launch_check("ssn_gram_stage2_kernel"));
   const size_t lds = sizeof(double) * pc->ell * (pc->ell + 1);
   if (lds > 64 * 1024)
@@ -1278,8 +1285,8 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   const size_t LL = static_cast<size_t>(L) * L;
   size_t gpart_d;
   const size_t ntri = static_cast<size_t>(nrg) * (nrg + 1) / 2;
-  if (sizeof(T) == 4)   // block partials (FP32), then part2 (16 sets)
-    gpart_d = (static_cast<size_t>(ngb) * ntri * 1024 + 1) / 2 + 16 * ntri * 1024 + 1;
+  if (sizeof(T) == 4)   // block partials (FP32), then part2 (kGramSets sets)
+    gpart_d = (static_cast<size_t>(ngb) * ntri * 1024 + 1) / 2 + kGramSets * ntri * 1024 + 1;
   else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
   const size_t need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
   NYS_TRY(pc->work2.ensure(sizeof(double) * need + N + 256));
