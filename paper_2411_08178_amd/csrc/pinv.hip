@@ -504,8 +504,6 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
   for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
 }
 
-// F(g_try) = g_try - e . U^T (x - s) from the partials, its norm, and the
-// decision: accept (and stop, or ask for a Newton step) or backtrack.
 // The host learns the outcome from hflag = {seq, done} in pinned host memory:
 // done is written first, then (after a system-scope fence) the sequence
 // number of this decision, also when an earlier decision had finished.
@@ -516,14 +514,14 @@ __device__ __forceinline__ void ssn_publish(double* hflag, double seq, double do
   __hip_atomic_store(hflag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restrict__ part, int nblk,
-                                                         int L, const double* __restrict__ meta,
-                                                         double* __restrict__ state, double tol,
-                                                         int max_halvings, double* hflag,
-                                                         double seq) {
-  __shared__ double red[1024], red2[1024];
+// The decision on one block of 1024 threads.
+__device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L,
+                                const double* __restrict__ meta, double* __restrict__ state,
+                                double tol, int max_halvings, double* hflag, double seq) {
+  __shared__ double red[1024];
   __shared__ double bsum[PcMeta::kMaxEll];
   __shared__ double Ft[PcMeta::kMaxEll];
+  __shared__ double wsum[2][2];
   __shared__ int accepted;
   __shared__ double tn_s;
   if (state[SsnState::kDone] != 0.0) {
@@ -531,26 +529,28 @@ __global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restri
     return;
   }
   tail_sum(part, nblk, L, red, bsum);
-  double sq = 0, gq = 0;
-  for (int k = threadIdx.x; k < L; k += blockDim.x) {
-    const double tk = state[SsnState::kTry + k];
-    const double f = tk - meta[PcMeta::kE + k] * bsum[k];
-    Ft[k] = f;
-    sq += f * f;
-    gq += tk * tk;
-  }
-  red[threadIdx.x] = sq;
-  red2[threadIdx.x] = gq;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      red[threadIdx.x] += red[threadIdx.x + o];
-      red2[threadIdx.x] += red2[threadIdx.x + o];
+  // ||F||^2 and ||g||^2: L <= 128 entries on waves 0 and 1
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave < 2) {
+    const int k = threadIdx.x;
+    double sq = 0, gq = 0;
+    if (k < L) {
+      const double tk = state[SsnState::kTry + k];
+      const double f = tk - meta[PcMeta::kE + k] * bsum[k];
+      Ft[k] = f;
+      sq = f * f;
+      gq = tk * tk;
     }
-    __syncthreads();
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      sq += __shfl_xor(sq, o, 64);
+      gq += __shfl_xor(gq, o, 64);
+    }
+    if (lane == 0) { wsum[wave][0] = sq; wsum[wave][1] = gq; }
   }
-  const double nFt = sqrt(red[0]), gn = sqrt(red2[0]);
+  __syncthreads();
   if (threadIdx.x == 0) {
+    const double nFt = sqrt(wsum[0][0] + wsum[1][0]), gn = sqrt(wsum[0][1] + wsum[1][1]);
     state[SsnState::kTrials] += 1.0;
     const bool have = state[SsnState::kHave] != 0.0;
     const double nF = state[SsnState::kNF], t = state[SsnState::kT];
@@ -581,6 +581,16 @@ __global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restri
     for (int k = threadIdx.x; k < L; k += blockDim.x)
       state[SsnState::kTry + k] = state[SsnState::kGamma + k] + tn * state[SsnState::kDelta + k];
   }
+}
+
+// F(g_try) = g_try - e . U^T (x - s) from the partials, its norm, and the
+// decision: accept (and stop, or ask for a Newton step) or backtrack.
+__global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restrict__ part, int nblk,
+                                                         int L, const double* __restrict__ meta,
+                                                         double* __restrict__ state, double tol,
+                                                         int max_halvings, double* hflag,
+                                                         double seq) {
+  ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq);
 }
 
 // ---- masked Gram on the matrix cores
@@ -752,29 +762,34 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
   for (int e = tid; e < NTRI * 1024; e += 64 * W) dst[e] = sum[e];
 }
 
-// Stage 2 of the Gram reduction: block (e, q) sums partials q, q + Q, ... of
-// entries 256 e .. 256 e + 255 (FP64, fixed order, 16 loads in flight per
-// thread) into part2[q][entry], Q = gridDim.y sets.
+// The decision (last block) and the Gram stage-2 reduction (the other
+// NTRI * 4 blocks: entries 256 b .. 256 b + 255, the kGramSets sets on the
+// thread quarters) in one launch; the reduction runs whether or not the
+// decision asks for a Newton step, the Newton solve checks.
 template <int NRG>
-__global__ __launch_bounds__(256) void ssn_gram_stage2_kernel(const float* __restrict__ part,
-                                                              int nblk,
-                                                              const double* __restrict__ state,
-                                                              double* __restrict__ part2) {
+__global__ __launch_bounds__(1024) void ssn_decide_gram_kernel(
+    const double* __restrict__ part, int nblk, int L, const double* __restrict__ meta,
+    double* __restrict__ state, double tol, int max_halvings, double* hflag, double seq,
+    const float* __restrict__ gpart, double* __restrict__ part2) {
+  static_assert(kGramSets == 4, "four sets on the thread quarters of 1024");
   constexpr int NTRI = NRG * (NRG + 1) / 2;
-  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
-  const int e = blockIdx.x * 256 + threadIdx.x, q = blockIdx.y, Q = gridDim.y;
+  if (blockIdx.x == gridDim.x - 1) {
+    ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq);
+    return;
+  }
+  const int e = blockIdx.x * 256 + (threadIdx.x & 255), q = threadIdx.x >> 8;
   if (e >= NTRI * 1024) return;
   const size_t stride = static_cast<size_t>(NTRI) * 1024;
   double a[4] = {0, 0, 0, 0};
   int b = q;
-  for (; b + 15 * Q < nblk; b += 16 * Q) {
+  for (; b + 15 * kGramSets < nblk; b += 16 * kGramSets) {
     float v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = part[(b + i * Q) * stride + e];
+    for (int i = 0; i < 16; ++i) v[i] = gpart[(b + i * kGramSets) * stride + e];
 #pragma unroll
     for (int i = 0; i < 16; ++i) a[i & 3] += static_cast<double>(v[i]);
   }
-  for (; b < nblk; b += Q) a[0] += static_cast<double>(part[b * stride + e]);
+  for (; b < nblk; b += kGramSets) a[0] += static_cast<double>(gpart[b * stride + e]);
   part2[q * stride + e] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
@@ -1227,13 +1242,11 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
   hipLaunchKernelGGL((ssn_evalgram_kernel<NRG>), dim3(nblk), dim3(64 * evg_waves<NRG>()), elds, st,
                      pc->U.as<float>(), pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part, x);
   NYS_TRY(launch_check("ssn_evalgram_kernel"));
-  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, fpart, nblk, L,
-                     pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq += 1.0);
-  NYS_TRY(launch_check("ssn_decide_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
-  hipLaunchKernelGGL((ssn_gram_stage2_kernel<NRG>), dim3(NTRI * 4, kGramSets), dim3(256), 0, st, part,
-                     nblk, state, part2);
-  NYS_TRY(launch_check("ssn_gram_stage2_kernel"));
+  hipLaunchKernelGGL((ssn_decide_gram_kernel<NRG>), dim3(NTRI * 4 + 1), dim3(1024), 0, st, fpart, nblk,
+                     L, pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq += 1.0, part,
+                     part2);
+  NYS_TRY(launch_check("ssn_decide_gram_kernel"));
   const size_t lds = sizeof(double) * pc->ell * (pc->ell + 1);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_solve_kernel<NRG>),
