@@ -27,6 +27,11 @@ template <class T>
 nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
                      hipStream_t st);
 
+// s = u - alpha P^{-1} g for one column, one pass over U after the
+// coefficients (pinv.hip).
+template <class T>
+nys_status pc_step(nys_pc pc, const T* u, const T* g, double alpha, T* s, hipStream_t st);
+
 // x = s - lam (t + U cd) for one column (pinv.hip).
 template <class T>
 nys_status pc_x_from_pinv(nys_pc pc, const T* s, const T* t, const double* cd, double lam, T* x,

@@ -421,6 +421,16 @@ nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, 
   return launch_check("u_update_kernel");
 }
 
+// s = u - alpha P^{-1} g: the coefficients d . U^T g, then one pass
+// s = u - alpha (g + U cd).
+template <class T>
+nys_status pc_step(nys_pc pc, const T* u, const T* g, double alpha, T* s, hipStream_t st) {
+  NYS_TRY(pc->work2.ensure(sizeof(double) * pc->ell));
+  double* cd = pc->work2.as<double>();
+  NYS_TRY(pc_coeffs<T>(pc, true, g, 1, cd, st));
+  return pc_x_from_pinv<T>(pc, u, g, cd, alpha, s, st);
+}
+
 template <class T>
 nys_status pc_x_from_pinv(nys_pc pc, const T* s, const T* t, const double* cd, double lam, T* x,
                           hipStream_t st) {
@@ -434,6 +444,9 @@ template nys_status pc_coeffs<double>(nys_pc, bool, const double*, int64_t, doub
 template nys_status pc_coeffs<float>(nys_pc, bool, const float*, int64_t, double*, hipStream_t);
 template nys_status pc_apply<double>(nys_pc, bool, const double*, double*, int64_t, hipStream_t);
 template nys_status pc_apply<float>(nys_pc, bool, const float*, float*, int64_t, hipStream_t);
+template nys_status pc_step<double>(nys_pc, const double*, const double*, double, double*,
+                                    hipStream_t);
+template nys_status pc_step<float>(nys_pc, const float*, const float*, double, float*, hipStream_t);
 template nys_status pc_x_from_pinv<double>(nys_pc, const double*, const double*, const double*,
                                            double, double*, hipStream_t);
 template nys_status pc_x_from_pinv<float>(nys_pc, const float*, const float*, const double*,

@@ -238,10 +238,13 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
                        static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
     NYS_TRY(launch_check("residual_kernel"));
     NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
-    if (pc) NYS_TRY(pc_apply<T>(pc, true, w.g, w.g, 1, st));
-    hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
-                       static_cast<T>(alpha), N, w.s);
-    NYS_TRY(launch_check("step_kernel"));
+    if (pc) {
+      NYS_TRY(pc_step<T>(pc, w.u, w.g, alpha, w.s, st));
+    } else {
+      hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
+                         static_cast<T>(alpha), N, w.s);
+      NYS_TRY(launch_check("step_kernel"));
+    }
     // x+ = prox^P_{alpha lambda g}(s)
     NYS_TRY(prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? w.state : nullptr, st, w.prox));
     // momentum
