@@ -472,15 +472,17 @@ struct SsnState {
 // Sets of partial Gram sums left by stage 2 for the Newton solve to add.
 constexpr int kGramSets = 4;
 
-// Evaluation at the trial point in one pass over U: r = s - U g, x = soft(r),
-// mask = |r| > lam, partial U^T (x - s) per block.
+// Evaluation at the trial point in one pass over U: r = s - U g, x = soft(r)
+// (to xo, if given), mask = |r| > lam (if given), partial U^T (x - s) per
+// block.
 template <class T, int ROWS, int LP = (ROWS <= 16 ? 16 : ROWS <= 32 ? 32 : ROWS <= 64 ? 64 : 128)>
 __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, int64_t ldu,
                                                        const T* __restrict__ s, int64_t N, int L,
                                                        int64_t chunk, T lam,
                                                        const double* __restrict__ state,
                                                        uint8_t* __restrict__ mask,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part,
+                                                       T* __restrict__ xo) {
   __shared__ double red[8 * LP];
   __shared__ double bsum[LP];
   __shared__ T g[LP];
@@ -494,7 +496,9 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
   for (int k = 0; k < LP; ++k) acc[k] = 0;
   for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
     T u[LP];
-    T r = s[n];
+    // (U g)_n first, then one subtraction from s_n: the sum rounds at the
+    // scale of U g, not of s (F is tested near the FP32 rounding level)
+    T ug = 0;
     const T* p = U + n;
 #pragma unroll
     for (int k = 0; k < LP; ++k) {
@@ -504,12 +508,14 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
       } else {
         u[k] = T(0);
       }
-      r -= u[k] * g[k];
+      ug += u[k] * g[k];
     }
+    const T r = s[n] - ug;
     const T ar = fabs(r);
     const T xv = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
     const T d = xv - s[n];
-    mask[n] = ar > lam ? 1 : 0;
+    if (mask != nullptr) mask[n] = ar > lam ? 1 : 0;
+    if (xo != nullptr) xo[n] = xv;
 #pragma unroll
     for (int k = 0; k < LP; ++k) acc[k] += u[k] * d;
   }
@@ -517,12 +523,15 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
   for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
 }
 
-// The host learns the outcome from hflag = {seq, done} in pinned host memory:
-// done is written first, then (after a system-scope fence) the sequence
-// number of this decision, also when an earlier decision had finished.
-__device__ __forceinline__ void ssn_publish(double* hflag, double seq, double done) {
+// The host learns the outcome from hflag = {seq, done, need_gram} in pinned
+// host memory: the outcome is written first, then (after a system-scope
+// fence) the sequence number of this decision, also when an earlier decision
+// had finished.
+__device__ __forceinline__ void ssn_publish(double* hflag, double seq, double done,
+                                            double need_gram) {
   if (hflag == nullptr || threadIdx.x != 0) return;
   __hip_atomic_store(hflag + 1, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(hflag + 2, need_gram, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __threadfence_system();
   __hip_atomic_store(hflag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -538,7 +547,7 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
   __shared__ int accepted;
   __shared__ double tn_s;
   if (state[SsnState::kDone] != 0.0) {
-    ssn_publish(hflag, seq, 1.0);
+    ssn_publish(hflag, seq, 1.0, 0.0);
     return;
   }
   tail_sum(part, nblk, L, red, bsum);
@@ -581,7 +590,7 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
       state[SsnState::kHalv] += 1.0;
     }
     accepted = accept ? 1 : 0;
-    ssn_publish(hflag, seq, state[SsnState::kDone]);
+    ssn_publish(hflag, seq, state[SsnState::kDone], state[SsnState::kNeedGram]);
   }
   __syncthreads();
   if (accepted) {
@@ -609,7 +618,8 @@ __global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restri
 // ---- masked Gram on the matrix cores
 typedef float floatx16_v __attribute__((ext_vector_type(16)));
 
-// One pass over an FP32 U at the trial point g (Thm. 1): per pixel
+// One pass over an FP32 U at the point g (Thm. 1; at state offset gsrc: the
+// trial point, or the accepted point for a Newton step there): per pixel
 // r = s - U g, x = soft_lam(r) (written to xo: the prox itself if g is the
 // accepted final point), d = x - s and D = [|r| > lam]; per block the
 // partial U^T d (FP64) for F(g) and the partial masked Gram U^T D U for the
@@ -636,7 +646,7 @@ template <int NRG>
 __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
     const float* __restrict__ U, int64_t ldu, const float* __restrict__ s, int64_t N, int L,
     int64_t chunk, float lam, const double* __restrict__ state, double* __restrict__ part,
-    float* __restrict__ gpart, float* __restrict__ xo) {
+    float* __restrict__ gpart, float* __restrict__ xo, int gsrc) {
   constexpr int W = evg_waves<NRG>();
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   constexpr int ROWS = 32 * NRG;
@@ -650,7 +660,7 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
   if (state[SsnState::kDone] != 0.0) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 31, lh = lane >> 5;
-  for (int k = tid; k < ROWS; k += 64 * W) gs[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
+  for (int k = tid; k < ROWS; k += 64 * W) gs[k] = k < L ? static_cast<float>(state[gsrc + k]) : 0.f;
   __syncthreads();
   float* ws = evg_lds + wave * ROWS * PP;
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
@@ -775,18 +785,18 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
   for (int e = tid; e < NTRI * 1024; e += 64 * W) dst[e] = sum[e];
 }
 
-// The decision (last block) and the Gram stage-2 reduction (the other
-// NTRI * 4 blocks: entries 256 b .. 256 b + 255, the kGramSets sets on the
+// The decision (last block, if with_decide) and the Gram stage-2 reduction
+// (NTRI * 4 blocks: entries 256 b .. 256 b + 255, the kGramSets sets on the
 // thread quarters) in one launch; the reduction runs whether or not the
 // decision asks for a Newton step, the Newton solve checks.
 template <int NRG>
 __global__ __launch_bounds__(1024) void ssn_decide_gram_kernel(
     const double* __restrict__ part, int nblk, int L, const double* __restrict__ meta,
     double* __restrict__ state, double tol, int max_halvings, double* hflag, double seq,
-    const float* __restrict__ gpart, double* __restrict__ part2) {
+    const float* __restrict__ gpart, double* __restrict__ part2, int with_decide) {
   static_assert(kGramSets == 4, "four sets on the thread quarters of 1024");
   constexpr int NTRI = NRG * (NRG + 1) / 2;
-  if (blockIdx.x == gridDim.x - 1) {
+  if (with_decide && blockIdx.x == gridDim.x - 1) {
     ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq);
     return;
   }
@@ -1063,10 +1073,10 @@ __device__ __forceinline__ void ssn_lu(double* A, int L, double* state) {
 template <int NRG>
 __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict__ part2, int L,
                                                         const double* __restrict__ meta,
-                                                        double* __restrict__ state) {
+                                                        double* __restrict__ state, int force) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   extern __shared__ double A[];
-  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0) return;
+  if (state[SsnState::kDone] != 0.0 || (state[SsnState::kNeedGram] == 0.0 && !force)) return;
   const int LP1 = L + 1;
   const size_t stride = static_cast<size_t>(NTRI) * 1024;
   for (int e = threadIdx.x; e < NTRI * 1024; e += blockDim.x) {
@@ -1188,8 +1198,9 @@ __global__ __launch_bounds__(256) void ssn_final_kernel(const T* __restrict__ U,
   __syncthreads();
   const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (n >= N) return;
-  T r = s[n];
-  for (int k = 0; k < L; ++k) r -= U[static_cast<size_t>(k) * ldu + n] * g[k];
+  T ug = 0;
+  for (int k = 0; k < L; ++k) ug += U[static_cast<size_t>(k) * ldu + n] * g[k];
+  const T r = s[n] - ug;
   const T ar = fabs(r);
   x[n] = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
 }
@@ -1215,23 +1226,24 @@ __global__ void ssn_store_gamma_kernel(const double* __restrict__ state, double*
 
 template <class T, int ROWS>
 static void launch_ssn_eval(nys_pc pc, const T* s, T lam, double* state, uint8_t* mask,
-                            double* part, int nblk, int64_t chunk, hipStream_t st) {
+                            double* part, int nblk, int64_t chunk, T* xo, hipStream_t st) {
   hipLaunchKernelGGL((ssn_eval_kernel<T, ROWS>), dim3(nblk), dim3(512), 0, st, pc->U.as<T>(),
-                     pc->ldu, s, pc->N, static_cast<int>(pc->ell), chunk, lam, state, mask, part);
+                     pc->ldu, s, pc->N, static_cast<int>(pc->ell), chunk, lam, state, mask, part, xo);
 }
 
 template <class T>
 static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8_t* mask,
-                              double* part, int nblk, int64_t chunk, double tol, hipStream_t st) {
+                              double* part, int nblk, int64_t chunk, double tol, hipStream_t st,
+                              T* xo = nullptr) {
   switch (pc->ell_pad) {
-    case 16: launch_ssn_eval<T, 16>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
-    case 32: launch_ssn_eval<T, 32>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
-    case 48: launch_ssn_eval<T, 48>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
-    case 64: launch_ssn_eval<T, 64>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
-    case 80: launch_ssn_eval<T, 80>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
-    case 96: launch_ssn_eval<T, 96>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
-    case 112: launch_ssn_eval<T, 112>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
-    default: launch_ssn_eval<T, 128>(pc, s, lam, state, mask, part, nblk, chunk, st); break;
+    case 16: launch_ssn_eval<T, 16>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
+    case 32: launch_ssn_eval<T, 32>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
+    case 48: launch_ssn_eval<T, 48>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
+    case 64: launch_ssn_eval<T, 64>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
+    case 80: launch_ssn_eval<T, 80>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
+    case 96: launch_ssn_eval<T, 96>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
+    case 112: launch_ssn_eval<T, 112>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
+    default: launch_ssn_eval<T, 128>(pc, s, lam, state, mask, part, nblk, chunk, xo, st); break;
   }
   NYS_TRY(launch_check("ssn_eval_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
@@ -1241,11 +1253,12 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
 }
 
 // One trial of the FP32 Newton iteration: the fused evaluation + masked Gram
-// at the trial point, the decision, and (if it asks for one) the Newton step.
+// at the trial point, the decision, and (if it asks for one) the Newton step;
+// or (newton_at_gamma) the Newton step at the accepted point alone.
 template <int NRG>
 static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double* state,
                                    double* fpart, float* part, int nblk, int64_t chunk, double tol,
-                                   float* x, hipStream_t st) {
+                                   float* x, hipStream_t st, bool newton_at_gamma = false) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   const int L = static_cast<int>(pc->ell);
   constexpr size_t elds = evg_lds_bytes<NRG>();
@@ -1253,26 +1266,29 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_evalgram_kernel<NRG>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(elds));
   hipLaunchKernelGGL((ssn_evalgram_kernel<NRG>), dim3(nblk), dim3(64 * evg_waves<NRG>()), elds, st,
-                     pc->U.as<float>(), pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part, x);
+                     pc->U.as<float>(), pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part, x,
+                     static_cast<int>(newton_at_gamma ? SsnState::kGamma : SsnState::kTry));
   NYS_TRY(launch_check("ssn_evalgram_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
-  hipLaunchKernelGGL((ssn_decide_gram_kernel<NRG>), dim3(NTRI * 4 + 1), dim3(1024), 0, st, fpart, nblk,
-                     L, pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq += 1.0, part,
-                     part2);
+  const int with_decide = newton_at_gamma ? 0 : 1;
+  if (with_decide) pc->flag_seq += 1.0;
+  hipLaunchKernelGGL((ssn_decide_gram_kernel<NRG>), dim3(NTRI * 4 + with_decide), dim3(1024), 0, st,
+                     fpart, nblk, L, pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq,
+                     part, part2, with_decide);
   NYS_TRY(launch_check("ssn_decide_gram_kernel"));
   const size_t lds = sizeof(double) * pc->ell * (pc->ell + 1);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_solve_kernel<NRG>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   hipLaunchKernelGGL((ssn_solve_kernel<NRG>), dim3(1), dim3(256), lds, st, part2,
-                     static_cast<int>(pc->ell), pc->meta.as<double>(), state);
+                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, newton_at_gamma ? 1 : 0);
   return launch_check("ssn_solve_kernel");
 }
 
 // Waits until the decision kernel last enqueued on st has published its
 // outcome (sequence number pc->flag_seq).  Spins on the pinned word for up to
 // 2 s, then falls back to a stream synchronisation.
-static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done) {
+static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool& need_gram) {
   volatile double* f = pc->hflag;
   const double want = pc->flag_seq;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1288,6 +1304,7 @@ static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done) {
   }
   std::atomic_thread_fence(std::memory_order_acquire);
   done = f[1] != 0.0;
+  need_gram = f[2] != 0.0;
   return NYS_OK;
 }
 
@@ -1323,9 +1340,9 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   uint8_t* mask = reinterpret_cast<uint8_t*>(Mj + LL);
   if (!pc->hflag) {
     void* h = nullptr;
-    NYS_CHECK_HIP(hipHostMalloc(&h, 2 * sizeof(double), hipHostMallocCoherent));
+    NYS_CHECK_HIP(hipHostMalloc(&h, 4 * sizeof(double), hipHostMallocCoherent));
     pc->hflag = static_cast<double*>(h);
-    pc->hflag[0] = pc->hflag[1] = 0.0;
+    pc->hflag[0] = pc->hflag[1] = pc->hflag[2] = pc->hflag[3] = 0.0;
     pc->flag_seq = 0.0;
   }
   const T lam = static_cast<T>(lam_bar);
@@ -1334,20 +1351,32 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
   NYS_TRY(launch_check("ssn_init_kernel"));
   int trial = 0;
-  bool done = false;
+  bool done = false, need_gram = false;
+  // FP32: the first trial point (nearly always followed by a Newton step)
+  // runs the fused evaluation + Gram pass; later ones, which mostly confirm
+  // convergence, the evaluation alone, and a Newton step they ask for gets its
+  // Gram pass at the accepted point
+  float* xf = static_cast<const void*>(x) == static_cast<const void*>(s)
+                  ? nullptr : reinterpret_cast<float*>(x);   // x aliasing s gets no trial writes
+  auto fused = [&](bool at_gamma) -> nys_status {
+    float* gp = reinterpret_cast<float*>(gpart);
+    const float* sf = reinterpret_cast<const float*>(s);
+    const float lf = static_cast<float>(lam);
+    float* xo = at_gamma ? nullptr : xf;
+    switch (nrg) {
+      case 1: return launch_ssn_trial<1>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
+      case 2: return launch_ssn_trial<2>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
+      case 3: return launch_ssn_trial<3>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
+      default: return launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
+    }
+  };
   for (; trial < max_trials; ++trial) {
     if constexpr (sizeof(T) == 4) {
-      float* gp = reinterpret_cast<float*>(gpart);
-      const float* sf = reinterpret_cast<const float*>(s);
-      // x aliasing s (an in-place prox) gets no trial writes
-      float* xf = static_cast<const void*>(x) == static_cast<const void*>(s)
-                      ? nullptr : reinterpret_cast<float*>(x);
-      const float lf = static_cast<float>(lam);
-      switch (nrg) {
-        case 1: NYS_TRY(launch_ssn_trial<1>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
-        case 2: NYS_TRY(launch_ssn_trial<2>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
-        case 3: NYS_TRY(launch_ssn_trial<3>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
-        default: NYS_TRY(launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xf, st)); break;
+      if (trial == 0) {
+        NYS_TRY(fused(false));
+      } else {
+        NYS_TRY(launch_eval<float>(pc, reinterpret_cast<const float*>(s), static_cast<float>(lam),
+                                   state, nullptr, part, nblk, chunk, tol, st, xf));
       }
     } else {
       NYS_TRY(launch_eval<T>(pc, s, lam, state, mask, part, nblk, chunk, tol, st));
@@ -1366,15 +1395,15 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
       NYS_TRY(launch_check("ssn_solve_f64_kernel"));
     }
     // the decision of this trial, read from pinned host memory while the
-    // device goes on with the Newton step; the next trial is enqueued only
-    // if it is needed
-    NYS_TRY(ssn_wait_decision(pc, st, done));
+    // device goes on; the next trial is enqueued only if it is needed
+    NYS_TRY(ssn_wait_decision(pc, st, done, need_gram));
     if (done) break;
+    if (sizeof(T) == 4 && trial > 0 && need_gram) NYS_TRY(fused(true));
   }
   if (trials_out) *trials_out = trial + 1;
   // the FP32 pass has written soft(s - U g) of its trial point g to x: when
   // the iteration stopped there (accepted and converged), x is the prox
-  if (!(sizeof(T) == 4 && done && static_cast<const void*>(x) != static_cast<const void*>(s))) {
+  if (!(sizeof(T) == 4 && done && xf != nullptr)) {
     hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, pc->U.as<T>(),
                        pc->ldu, s, state, N, L, lam, x);
     NYS_TRY(launch_check("ssn_final_kernel"));
