@@ -153,4 +153,7 @@ struct nys_pc_s {
   // synchronisation; the sequence number counts decisions
   double* hflag = nullptr;
   double flag_seq = 0;
+  // the FP32 semismooth Newton workspace holds LU factors of a Jacobian of
+  // this preconditioner (cleared whenever the factorisation is redone)
+  bool ssn_lu_valid = false;
 };

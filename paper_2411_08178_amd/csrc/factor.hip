@@ -840,6 +840,7 @@ nys_status factor_refresh(nys_pc pc, const void* omega, const void* Y, nys_dtype
                           const nys_factor_opts& o, hipStream_t st) {
   pc->pinv_norm_cache = -1.0;
   pc->tail = o.tail;
+  pc->ssn_lu_valid = false;
   const int L = static_cast<int>(pc->ell);
   switch (in_dt) {
     case NYS_F64:

@@ -465,12 +465,15 @@ struct SsnState {
   static constexpr int kF = 3 * PcMeta::kMaxEll;         // F at gamma
   static constexpr int kS = 4 * PcMeta::kMaxEll;         // scalars
   static constexpr int kNF = kS + 0, kT = kS + 1, kDone = kS + 2, kHalv = kS + 3,
-                       kHave = kS + 4, kNeedGram = kS + 5, kTrials = kS + 6, kSteps = kS + 7;
+                       kHave = kS + 4, kNeedGram = kS + 5, kTrials = kS + 6, kSteps = kS + 7,
+                       kLuOk = kS + 8;   // FP32: packed LU factors of the last Newton solve stored
   static constexpr int kTotal = kS + 16;
 };
 
 // Sets of partial Gram sums left by stage 2 for the Newton solve to add.
 constexpr int kGramSets = 4;
+// Row pitch (floats) of the stored packed LU factors: 64 x 64, then 64 values 1 / u_rr.
+constexpr int kLuPitch = 64;
 
 // Evaluation at the trial point in one pass over U: r = s - U g, x = soft(r)
 // (to xo, if given), mask = |r| > lam (if given), partial U^T (x - s) per
@@ -523,15 +526,16 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
   for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
 }
 
-// The host learns the outcome from hflag = {seq, done, need_gram} in pinned
+// The host learns the outcome from hflag = {seq, done, need_gram, lu_ok} in pinned
 // host memory: the outcome is written first, then (after a system-scope
 // fence) the sequence number of this decision, also when an earlier decision
 // had finished.
 __device__ __forceinline__ void ssn_publish(double* hflag, double seq, double done,
-                                            double need_gram) {
+                                            double need_gram, double lu_ok) {
   if (hflag == nullptr || threadIdx.x != 0) return;
   __hip_atomic_store(hflag + 1, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __hip_atomic_store(hflag + 2, need_gram, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(hflag + 3, lu_ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   __threadfence_system();
   __hip_atomic_store(hflag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -547,7 +551,7 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
   __shared__ int accepted;
   __shared__ double tn_s;
   if (state[SsnState::kDone] != 0.0) {
-    ssn_publish(hflag, seq, 1.0, 0.0);
+    ssn_publish(hflag, seq, 1.0, 0.0, state[SsnState::kLuOk]);
     return;
   }
   tail_sum(part, nblk, L, red, bsum);
@@ -590,7 +594,8 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
       state[SsnState::kHalv] += 1.0;
     }
     accepted = accept ? 1 : 0;
-    ssn_publish(hflag, seq, state[SsnState::kDone], state[SsnState::kNeedGram]);
+    ssn_publish(hflag, seq, state[SsnState::kDone], state[SsnState::kNeedGram],
+                state[SsnState::kLuOk]);
   }
   __syncthreads();
   if (accepted) {
@@ -998,7 +1003,8 @@ __device__ void lu_wave(double* __restrict__ A, int L, double* __restrict__ stat
 // non-finite result returns false, and the caller redoes the solve with
 // partial pivoting.
 template <int LM>
-__device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __restrict__ state) {
+__device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __restrict__ state,
+                             float* __restrict__ lu) {
   const int r = threadIdx.x;
   const int LP1 = L + 1;
   float a[LM];
@@ -1021,6 +1027,7 @@ __device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __rest
       const float inv = __builtin_amdgcn_rcpf(pv);
       const float f = r > j ? a[j] * inv : 0.f;
       if (r == j) invd = inv;
+      if (r > j) a[j] = f;     // row r keeps its multiplier in the eliminated column
       // groups of 16 columns: no more than 16 broadcast values live at once
 #pragma unroll
       for (int k = j + 1; k < LM; ++k) {
@@ -1045,13 +1052,57 @@ __device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __rest
     const double dv = static_cast<double>(sol);
     state[SsnState::kDelta + r] = dv;
     state[SsnState::kTry + r] = state[SsnState::kGamma + r] + dv;
+    // packed factors (unit lower multipliers below the diagonal, U on and
+    // above) and 1 / u_rr, for chord steps of later calls
+#pragma unroll
+    for (int c = 0; c < LM; ++c)
+      if (c < L) lu[r * kLuPitch + c] = a[c];
+    lu[kLuPitch * kLuPitch + r] = invd;
+  }
+  if (r == 0) {
+    state[SsnState::kT] = 1.0;
+    state[SsnState::kHalv] = 0.0;
+    state[SsnState::kSteps] += 1.0;
+    state[SsnState::kLuOk] = 1.0;
+  }
+  return true;
+}
+
+// Chord step (FP32, L <= LM <= 64): the direction -J0^{-1} F(gamma) with the
+// packed LU factors of an earlier Jacobian J0 of the same preconditioner (the
+// masks of consecutive prox centres differ in few pixels); replays the
+// elimination on the right-hand side, then back-substitutes, on one wave.
+template <int LM>
+__global__ __launch_bounds__(64) void ssn_chord_kernel(const float* __restrict__ lu, int L,
+                                                       double* __restrict__ state) {
+  const int r = threadIdx.x;
+  float a[LM];
+#pragma unroll
+  for (int c = 0; c < LM; ++c) a[c] = (r < L && c < L) ? lu[r * kLuPitch + c] : 0.f;
+  const float invd = r < L ? lu[kLuPitch * kLuPitch + r] : 0.f;
+  float rh = (r < L) ? static_cast<float>(-state[SsnState::kF + r]) : 0.f;
+#pragma unroll
+  for (int j = 0; j < LM; ++j)
+    if (j < L) rh -= (r > j ? a[j] : 0.f) * readlane_r(rh, j);
+  float sol = 0.f;
+#pragma unroll
+  for (int j = LM - 1; j >= 0; --j) {
+    if (j < L) {
+      const float d = readlane_r(rh, j) * readlane_r(invd, j);
+      if (r == j) sol = d;
+      rh -= a[j] * d;
+    }
+  }
+  if (r < L) {
+    const double dv = static_cast<double>(sol);
+    state[SsnState::kDelta + r] = dv;
+    state[SsnState::kTry + r] = state[SsnState::kGamma + r] + dv;
   }
   if (r == 0) {
     state[SsnState::kT] = 1.0;
     state[SsnState::kHalv] = 0.0;
     state[SsnState::kSteps] += 1.0;
   }
-  return true;
 }
 
 template <class R, int LM>
@@ -1073,7 +1124,8 @@ __device__ __forceinline__ void ssn_lu(double* A, int L, double* state) {
 template <int NRG>
 __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict__ part2, int L,
                                                         const double* __restrict__ meta,
-                                                        double* __restrict__ state, int force) {
+                                                        double* __restrict__ state, int force,
+                                                        float* __restrict__ lu) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   extern __shared__ double A[];
   if (state[SsnState::kDone] != 0.0 || (state[SsnState::kNeedGram] == 0.0 && !force)) return;
@@ -1101,14 +1153,17 @@ __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict
   __shared__ int diag_ok;
   if constexpr (NRG <= 2) {
     if (threadIdx.x < 64) {
-      const bool ok = lu_wave_diag<NRG == 1 ? 32 : 64>(A, L, state);
+      const bool ok = lu_wave_diag<NRG == 1 ? 32 : 64>(A, L, state, lu);
       if (threadIdx.x == 0) diag_ok = ok ? 1 : 0;
     }
   } else {
     if (threadIdx.x == 0) diag_ok = 0;
   }
   __syncthreads();
-  if (!diag_ok) lu_wave(A, L, state);
+  if (!diag_ok) {
+    if (threadIdx.x == 0) state[SsnState::kLuOk] = 0.0;   // no stored factors from this path
+    lu_wave(A, L, state);
+  }
 }
 
 // FP64 U: masked Gram on the vector units, one 64 x 64 output tile per block
@@ -1206,7 +1261,10 @@ __global__ __launch_bounds__(256) void ssn_final_kernel(const T* __restrict__ U,
 }
 
 // Initialise the Newton state from the warm start gamma (g_try = gamma).
-__global__ void ssn_init_kernel(double* __restrict__ state, const double* __restrict__ gamma0, int L) {
+// keep_lu = 0 marks the stored LU factors as not belonging to this
+// preconditioner.
+__global__ void ssn_init_kernel(double* __restrict__ state, const double* __restrict__ gamma0, int L,
+                                int keep_lu) {
   for (int k = threadIdx.x; k < L; k += blockDim.x) {
     double g = gamma0 ? gamma0[k] : 0.0;
     state[SsnState::kGamma + k] = g;
@@ -1217,6 +1275,7 @@ __global__ void ssn_init_kernel(double* __restrict__ state, const double* __rest
     state[SsnState::kNF] = 0; state[SsnState::kT] = 1; state[SsnState::kDone] = 0;
     state[SsnState::kHalv] = 0; state[SsnState::kHave] = 0; state[SsnState::kNeedGram] = 0;
     state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0;
+    if (!keep_lu) state[SsnState::kLuOk] = 0;
   }
 }
 
@@ -1258,7 +1317,7 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
 template <int NRG>
 static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double* state,
                                    double* fpart, float* part, int nblk, int64_t chunk, double tol,
-                                   float* x, hipStream_t st, bool newton_at_gamma = false) {
+                                   float* x, float* lu, hipStream_t st, bool newton_at_gamma = false) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   const int L = static_cast<int>(pc->ell);
   constexpr size_t elds = evg_lds_bytes<NRG>();
@@ -1281,14 +1340,16 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_solve_kernel<NRG>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   hipLaunchKernelGGL((ssn_solve_kernel<NRG>), dim3(1), dim3(256), lds, st, part2,
-                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, newton_at_gamma ? 1 : 0);
+                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, newton_at_gamma ? 1 : 0,
+                     lu);
   return launch_check("ssn_solve_kernel");
 }
 
 // Waits until the decision kernel last enqueued on st has published its
 // outcome (sequence number pc->flag_seq).  Spins on the pinned word for up to
 // 2 s, then falls back to a stream synchronisation.
-static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool& need_gram) {
+static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool& need_gram,
+                                    bool& lu_ok) {
   volatile double* f = pc->hflag;
   const double want = pc->flag_seq;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1305,6 +1366,7 @@ static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool&
   std::atomic_thread_fence(std::memory_order_acquire);
   done = f[1] != 0.0;
   need_gram = f[2] != 0.0;
+  lu_ok = f[3] != 0.0;
   return NYS_OK;
 }
 
@@ -1332,12 +1394,15 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     gpart_d = (static_cast<size_t>(ngb) * ntri * 1024 + 1) / 2 + kGramSets * ntri * 1024 + 1;
   else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
   const size_t need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
-  NYS_TRY(pc->work2.ensure(sizeof(double) * need + N + 256));
+  const size_t mask_b = static_cast<size_t>((N + 255) / 256 * 256);
+  const size_t lu_b = sizeof(float) * (kLuPitch * kLuPitch + kLuPitch);
+  NYS_TRY(pc->work2.ensure(sizeof(double) * need + mask_b + lu_b + 256));
   double* state = pc->work2.as<double>();
   double* part = state + SsnState::kTotal;
   double* gpart = part + static_cast<size_t>(std::max(nblk, ngb)) * L;
   double* Mj = gpart + gpart_d;
   uint8_t* mask = reinterpret_cast<uint8_t*>(Mj + LL);
+  float* lu = reinterpret_cast<float*>(mask + mask_b);
   if (!pc->hflag) {
     void* h = nullptr;
     NYS_CHECK_HIP(hipHostMalloc(&h, 4 * sizeof(double), hipHostMallocCoherent));
@@ -1348,14 +1413,23 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   const T lam = static_cast<T>(lam_bar);
   const double tol = reg.newton_tol > 0 ? reg.newton_tol : (sizeof(T) == 8 ? 1e-12 : 1e-6);
   const int max_trials = reg.max_newton > 0 ? reg.max_newton : 60;
-  hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
+  // stored factors are kept only while they belong to this preconditioner
+  const bool fp32_lu = sizeof(T) == 4 && L <= 64;
+  hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L,
+                     (fp32_lu && pc->ssn_lu_valid) ? 1 : 0);
   NYS_TRY(launch_check("ssn_init_kernel"));
   int trial = 0;
-  bool done = false, need_gram = false;
-  // FP32: the first trial point (nearly always followed by a Newton step)
-  // runs the fused evaluation + Gram pass; later ones, which mostly confirm
-  // convergence, the evaluation alone, and a Newton step they ask for gets its
-  // Gram pass at the accepted point
+  bool done = false, need_gram = false, lu_ok = false;
+  // FP32: without stored factors the first trial point (nearly always
+  // followed by a Newton step) runs the fused evaluation + Gram pass; with
+  // them, and at every later trial point, the evaluation runs alone.  A new
+  // direction at an accepted point is then a chord step with the stored
+  // factors of an earlier Jacobian of this preconditioner (once per call), else
+  // a Newton step with its Gram pass at the accepted point (factors stored).
+  // A chord direction that is not accepted at once is replaced by a Newton
+  // step at the accepted point.
+  const bool have_lu = fp32_lu && pc->ssn_lu_valid;
+  bool chord_used = false, last_chord = false;
   float* xf = static_cast<const void*>(x) == static_cast<const void*>(s)
                   ? nullptr : reinterpret_cast<float*>(x);   // x aliasing s gets no trial writes
   auto fused = [&](bool at_gamma) -> nys_status {
@@ -1364,15 +1438,15 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     const float lf = static_cast<float>(lam);
     float* xo = at_gamma ? nullptr : xf;
     switch (nrg) {
-      case 1: return launch_ssn_trial<1>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
-      case 2: return launch_ssn_trial<2>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
-      case 3: return launch_ssn_trial<3>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
-      default: return launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, st, at_gamma);
+      case 1: return launch_ssn_trial<1>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, lu, st, at_gamma);
+      case 2: return launch_ssn_trial<2>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, lu, st, at_gamma);
+      case 3: return launch_ssn_trial<3>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, lu, st, at_gamma);
+      default: return launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, lu, st, at_gamma);
     }
   };
   for (; trial < max_trials; ++trial) {
     if constexpr (sizeof(T) == 4) {
-      if (trial == 0) {
+      if (trial == 0 && !have_lu) {
         NYS_TRY(fused(false));
       } else {
         NYS_TRY(launch_eval<float>(pc, reinterpret_cast<const float*>(s), static_cast<float>(lam),
@@ -1396,10 +1470,26 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     }
     // the decision of this trial, read from pinned host memory while the
     // device goes on; the next trial is enqueued only if it is needed
-    NYS_TRY(ssn_wait_decision(pc, st, done, need_gram));
+    NYS_TRY(ssn_wait_decision(pc, st, done, need_gram, lu_ok));
     if (done) break;
-    if (sizeof(T) == 4 && trial > 0 && need_gram) NYS_TRY(fused(true));
+    if constexpr (sizeof(T) == 4) {
+      const bool fused_here = trial == 0 && !have_lu;   // its Newton step is already enqueued
+      if (!fused_here) {
+        if (need_gram && fp32_lu && lu_ok && !chord_used) {
+          if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);
+          else hipLaunchKernelGGL(ssn_chord_kernel<64>, dim3(1), dim3(64), 0, st, lu, L, state);
+          NYS_TRY(launch_check("ssn_chord_kernel"));
+          chord_used = last_chord = true;
+        } else if (need_gram || last_chord) {
+          NYS_TRY(fused(true));
+          last_chord = false;
+        }
+        // else: a Newton direction being backtracked; the decision has set
+        // the next trial point
+      }
+    }
   }
+  if (fp32_lu) pc->ssn_lu_valid = true;
   if (trials_out) *trials_out = trial + 1;
   // the FP32 pass has written soft(s - U g) of its trial point g to x: when
   // the iteration stopped there (accepted and converged), x is the prox
