@@ -163,6 +163,48 @@ def test_prox_l1_ssn(dt, tail, ell):
     assert rel(host(x0), opx.soft(host(sd), lam_bar)) < TOL[dt]
 
 
+@pytest.mark.parametrize("ell,tail", [(40, "sqrt"), (64, "plain")])
+def test_prox_l1_ssn_repeated_calls(ell, tail):
+    """FP32 prox calls on one preconditioner with drifting centres (as in the
+    outer iterations), then a jump to an unrelated centre and a new
+    preconditioner: later calls start from stored factors of an earlier
+    Jacobian, and every result matches the oracle's prox."""
+    P = need_gpu()
+    banner(f"prox l1 ssn repeated ell={ell} {tail}")
+    n = 48
+    h = W.gaussian_psf(7, 1.2)
+    prob = sv.Problem("blurdown", n, None, 0.0, "l1", h=h, factor=2, levels=3)
+    om = W.omega(ell, n, n, 16)
+    Y = sv.sketch(prob, om)
+    omd, Yd = dev(om, "f64"), dev(Y, "f64")
+    ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], tail)
+    pc = P.nys_factor(omd, Yd, ell, tail=tail, u_dtype=torch.float32)
+    rd = P.reg_desc("l1", n, n)
+    state = P.prox_state(rd, pc, torch.float32)
+    lam_bar = 0.05
+    s0 = W.gaussian((n, n), 17) * 0.1
+    drift = W.gaussian((n, n), 18) * 0.002
+    centres = [s0 + k * drift for k in range(8)] + [W.gaussian((n, n), 19) * 0.1]
+    for k, s in enumerate(centres):
+        sd = dev(s, "f32")
+        x = P.prox_weighted(rd, lam_bar, pc, sd, state)
+        xr, _, _ = opx.prox_l1_weighted(host(sd).reshape(-1), lam_bar, opc.U, opc.e)
+        assert rel(host(x).reshape(-1), xr) < 2e-5, (k, rel(host(x).reshape(-1), xr))
+    # a new factorisation of another sketch: the stored factors belong to the old one
+    om2 = W.omega(ell, n, n, 26)
+    Y2 = sv.sketch(prob, om2)
+    ref2 = onys.nystrom(Y2.reshape(ell, -1), om2.reshape(ell, -1))
+    opc2 = sv.Precond(ref2["U"], ref2["shat"], ref2["nu"], tail)
+    pc2 = P.nys_factor(dev(om2, "f64"), dev(Y2, "f64"), ell, tail=tail, u_dtype=torch.float32)
+    state2 = P.prox_state(rd, pc2, torch.float32)
+    for s in centres[:3]:
+        sd = dev(s, "f32")
+        x = P.prox_weighted(rd, lam_bar, pc2, sd, state2)
+        xr, _, _ = opx.prox_l1_weighted(host(sd).reshape(-1), lam_bar, opc2.U, opc2.e)
+        assert rel(host(x).reshape(-1), xr) < 2e-5
+
+
 def _solve_pair(P, prob_kind, dt, with_pc, iters):
     if prob_kind == "deblur_tv":
         wl = W.workload("deblur128_tv_f64")
