@@ -156,4 +156,5 @@ struct nys_pc_s {
   // the FP32 semismooth Newton workspace holds LU factors of a Jacobian of
   // this preconditioner (cleared whenever the factorisation is redone)
   bool ssn_lu_valid = false;
+  bool ssn_lu_hint = false;   // the last decision read reported stored factors
 };

@@ -1075,6 +1075,11 @@ __device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __rest
 template <int LM>
 __global__ __launch_bounds__(64) void ssn_chord_kernel(const float* __restrict__ lu, int L,
                                                        double* __restrict__ state) {
+  // only after a decision that accepted its point without converging, and
+  // with factors stored
+  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0 ||
+      state[SsnState::kLuOk] == 0.0)
+    return;
   const int r = threadIdx.x;
   float a[LM];
 #pragma unroll
@@ -1444,6 +1449,20 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
       default: return launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, lu, st, at_gamma);
     }
   };
+  // with factors known to be stored, the first trial, its chord step and the
+  // second trial are enqueued together (the chord step runs only if the first
+  // decision asks for a direction; a converged first trial makes the second
+  // one exit at once), and the host waits for the second decision only
+  if (have_lu && pc->ssn_lu_hint && max_trials >= 2) {
+    const float* sf = reinterpret_cast<const float*>(s);
+    const float lf = static_cast<float>(lam);
+    NYS_TRY(launch_eval<float>(pc, sf, lf, state, nullptr, part, nblk, chunk, tol, st, xf));
+    if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);
+    else hipLaunchKernelGGL(ssn_chord_kernel<64>, dim3(1), dim3(64), 0, st, lu, L, state);
+    NYS_TRY(launch_check("ssn_chord_kernel"));
+    chord_used = last_chord = true;
+    trial = 1;
+  }
   for (; trial < max_trials; ++trial) {
     if constexpr (sizeof(T) == 4) {
       if (trial == 0 && !have_lu) {
@@ -1471,6 +1490,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     // the decision of this trial, read from pinned host memory while the
     // device goes on; the next trial is enqueued only if it is needed
     NYS_TRY(ssn_wait_decision(pc, st, done, need_gram, lu_ok));
+    if (fp32_lu) pc->ssn_lu_hint = lu_ok;
     if (done) break;
     if constexpr (sizeof(T) == 4) {
       const bool fused_here = trial == 0 && !have_lu;   // its Newton step is already enqueued
