@@ -36,11 +36,22 @@ nys_status pc_step(nys_pc pc, const T* u, const T* g, double alpha, T* s, hipStr
 template <class T>
 nys_status pc_x_from_pinv(nys_pc pc, const T* s, const T* t, const double* cd, double lam, T* x,
                           hipStream_t st);
+// Prox centre given by the preconditioned gradient step s = u - alpha (g + U cd)
+// (cd: FP64 coefficients d . U^T g from pc_coeffs).
+struct SsnStep {
+  const void* u;
+  const void* g;
+  double alpha;
+  const double* cd;
+};
 // P-weighted l1 prox by semismooth Newton (Thm. 1, pinv.hip); gamma_state
-// (ell FP64, may be null) is the warm start and receives the root.
+// (ell FP64, may be null) is the warm start and receives the root.  With
+// `step`, s is an output buffer: the step is formed into it (by the first
+// evaluation pass where possible).
 template <class T>
 nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    double* gamma_state, hipStream_t st, int* trials_out = nullptr);
+                    double* gamma_state, hipStream_t st, int* trials_out = nullptr,
+                    const SsnStep* step = nullptr);
 
 // Layout of the FP64 metadata block of a preconditioner (pc->meta).
 struct PcMeta {

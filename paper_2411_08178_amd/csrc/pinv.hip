@@ -526,6 +526,59 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
   for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
 }
 
+// The first evaluation with the prox centre given implicitly by the
+// preconditioned gradient step s = u - alpha (g + U cd) (FP32): s_n is formed
+// from the same loads of U as (U g)_n and written out for the later trials;
+// the rest as in ssn_eval_kernel.
+template <int ROWS, int LP = (ROWS <= 16 ? 16 : ROWS <= 32 ? 32 : ROWS <= 64 ? 64 : 128)>
+__global__ __launch_bounds__(512) void ssn_eval_step_kernel(
+    const float* __restrict__ U, int64_t ldu, const float* __restrict__ u,
+    const float* __restrict__ g, float alpha, const double* __restrict__ cd,
+    float* __restrict__ s_out, int64_t N, int L, int64_t chunk, float lam,
+    const double* __restrict__ state, double* __restrict__ part, float* __restrict__ xo) {
+  __shared__ double red[8 * LP];
+  __shared__ double bsum[LP];
+  __shared__ float gam[LP], w[LP];
+  if (state[SsnState::kDone] != 0.0) return;
+  for (int k = threadIdx.x; k < LP; k += blockDim.x) {
+    gam[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
+    w[k] = k < L ? static_cast<float>(alpha * cd[k]) : 0.f;
+  }
+  __syncthreads();
+  const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
+  float acc[LP];
+#pragma unroll
+  for (int k = 0; k < LP; ++k) acc[k] = 0;
+  for (int64_t n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    float uk[LP];
+    float uw = 0.f, ug = 0.f;
+    const float* p = U + n;
+#pragma unroll
+    for (int k = 0; k < LP; ++k) {
+      if (k < ROWS) {
+        uk[k] = p[0];
+        p += ldu;
+      } else {
+        uk[k] = 0.f;
+      }
+      uw += uk[k] * w[k];
+      ug += uk[k] * gam[k];
+    }
+    const float sn = (u[n] - alpha * g[n]) - uw;
+    const float r = sn - ug;
+    const float ar = fabsf(r);
+    const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
+    const float d = xv - sn;
+    s_out[n] = sn;
+    if (xo != nullptr) xo[n] = xv;
+#pragma unroll
+    for (int k = 0; k < LP; ++k) acc[k] += uk[k] * d;
+  }
+  block_reduce<LP>(acc, red, bsum);
+  for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
+}
+
 // The host learns the outcome from hflag = {seq, done, need_gram, lu_ok} in pinned
 // host memory: the outcome is written first, then (after a system-scope
 // fence) the sequence number of this decision, also when an earlier decision
@@ -1316,6 +1369,33 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
   return launch_check("ssn_decide_kernel");
 }
 
+template <int ROWS>
+static void launch_ssn_eval_step(nys_pc pc, const SsnStep& sp, float* s_out, float lam,
+                                 double* state, double* part, int nblk, int64_t chunk, float* xo,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL((ssn_eval_step_kernel<ROWS>), dim3(nblk), dim3(512), 0, st, pc->U.as<float>(),
+                     pc->ldu, static_cast<const float*>(sp.u), static_cast<const float*>(sp.g),
+                     static_cast<float>(sp.alpha), sp.cd, s_out, pc->N, static_cast<int>(pc->ell),
+                     chunk, lam, state, part, xo);
+}
+
+// The first evaluation fused with the gradient step, and its decision.
+static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, float* s_out, float lam,
+                                   double* state, double* part, int nblk, int64_t chunk,
+                                   double tol, float* xo, hipStream_t st) {
+  switch (pc->ell_pad) {
+    case 16: launch_ssn_eval_step<16>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
+    case 32: launch_ssn_eval_step<32>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
+    case 48: launch_ssn_eval_step<48>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
+    default: launch_ssn_eval_step<64>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
+  }
+  NYS_TRY(launch_check("ssn_eval_step_kernel"));
+  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
+                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
+                     pc->flag_seq += 1.0);
+  return launch_check("ssn_decide_kernel");
+}
+
 // One trial of the FP32 Newton iteration: the fused evaluation + masked Gram
 // at the trial point, the decision, and (if it asks for one) the Newton step;
 // or (newton_at_gamma) the Newton step at the accepted point alone.
@@ -1377,7 +1457,7 @@ static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool&
 
 template <class T>
 nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    double* gamma_state, hipStream_t st, int* trials_out) {
+                    double* gamma_state, hipStream_t st, int* trials_out, const SsnStep* step) {
   const int64_t N = pc->N;
   const int L = static_cast<int>(pc->ell);
   int nblk;
@@ -1449,14 +1529,24 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
       default: return launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, lu, st, at_gamma);
     }
   };
-  // with factors known to be stored, the first trial, its chord step and the
+  // With factors known to be stored, the first trial, its chord step and the
   // second trial are enqueued together (the chord step runs only if the first
   // decision asks for a direction; a converged first trial makes the second
-  // one exit at once), and the host waits for the second decision only
-  if (have_lu && pc->ssn_lu_hint && max_trials >= 2) {
+  // one exit at once), and the host waits for the second decision only.
+  // With `step`, s is the output of the gradient step s = u - alpha (g + U cd):
+  // formed by that first evaluation pass, else by a pass of its own first.
+  const bool prelude = have_lu && pc->ssn_lu_hint && max_trials >= 2;
+  if (step != nullptr && !(sizeof(T) == 4 && prelude))
+    NYS_TRY(pc_x_from_pinv<T>(pc, static_cast<const T*>(step->u), static_cast<const T*>(step->g),
+                              step->cd, step->alpha, const_cast<T*>(s), st));
+  if (prelude) {
     const float* sf = reinterpret_cast<const float*>(s);
     const float lf = static_cast<float>(lam);
-    NYS_TRY(launch_eval<float>(pc, sf, lf, state, nullptr, part, nblk, chunk, tol, st, xf));
+    if (step != nullptr)
+      NYS_TRY(launch_eval_step(pc, *step, reinterpret_cast<float*>(const_cast<T*>(s)), lf, state,
+                               part, nblk, chunk, tol, xf, st));
+    else
+      NYS_TRY(launch_eval<float>(pc, sf, lf, state, nullptr, part, nblk, chunk, tol, st, xf));
     if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);
     else hipLaunchKernelGGL(ssn_chord_kernel<64>, dim3(1), dim3(64), 0, st, lu, L, state);
     NYS_TRY(launch_check("ssn_chord_kernel"));
@@ -1526,8 +1616,8 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
 }
 
 template nys_status ssn_prox<double>(const nys_reg_desc&, double, nys_pc, const double*, double*,
-                                     double*, hipStream_t, int*);
+                                     double*, hipStream_t, int*, const SsnStep*);
 template nys_status ssn_prox<float>(const nys_reg_desc&, double, nys_pc, const float*, float*,
-                                    double*, hipStream_t, int*);
+                                    double*, hipStream_t, int*, const SsnStep*);
 
 }  // namespace nys

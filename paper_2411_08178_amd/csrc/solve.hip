@@ -238,7 +238,14 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
                        static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
     NYS_TRY(launch_check("residual_kernel"));
     NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
-    if (pc) {
+    if (pc && p.reg.kind == NYS_REG_L1) {
+      // the step s = u - alpha P^{-1} g is formed inside the prox (by its
+      // first evaluation pass over U where possible)
+      NYS_TRY(pc_coeffs<T>(pc, true, w.g, 1, w.part, st));
+      const SsnStep sp{w.u, w.g, alpha, w.part};
+      NYS_TRY(ssn_prox<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? static_cast<double*>(w.state) : nullptr,
+                          st, nullptr, &sp));
+    } else if (pc) {
       NYS_TRY(pc_step<T>(pc, w.u, w.g, alpha, w.s, st));
     } else {
       hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
@@ -246,7 +253,8 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
       NYS_TRY(launch_check("step_kernel"));
     }
     // x+ = prox^P_{alpha lambda g}(s)
-    NYS_TRY(prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? w.state : nullptr, st, w.prox));
+    if (!(pc && p.reg.kind == NYS_REG_L1))
+      NYS_TRY(prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? w.state : nullptr, st, w.prox));
     // momentum
     const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
     const double beta = (t_prev - 1.0) / t;
