@@ -148,11 +148,11 @@ struct nys_pc_s {
   nys::DevBuf meta;               // FP64 device block, see factor.hip
   nys::DevBuf work;               // scratch of nys_apply / prox
   nys::DevBuf work2;
-  // pinned, coherent host words {sequence number, done} written by the
+  // pinned, coherent host word (8 seq + outcome bits) written by the
   // semismooth Newton decision kernel and read by the host without a stream
   // synchronisation; the sequence number counts decisions
-  double* hflag = nullptr;
-  double flag_seq = 0;
+  unsigned long long* hflag = nullptr;
+  unsigned long long flag_seq = 0;
   // the FP32 semismooth Newton workspace holds LU factors of a Jacobian of
   // this preconditioner (cleared whenever the factorisation is redone)
   bool ssn_lu_valid = false;

@@ -579,24 +579,23 @@ __global__ __launch_bounds__(512) void ssn_eval_step_kernel(
   for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
 }
 
-// The host learns the outcome from hflag = {seq, done, need_gram, lu_ok} in pinned
-// host memory: the outcome is written first, then (after a system-scope
-// fence) the sequence number of this decision, also when an earlier decision
-// had finished.
-__device__ __forceinline__ void ssn_publish(double* hflag, double seq, double done,
-                                            double need_gram, double lu_ok) {
+// The host learns the outcome from one 64-bit word in pinned host memory,
+// hflag = 8 seq + 4 done + 2 need_gram + lu_ok, written by a single
+// system-scope store (no fence: the host reads nothing else the kernel
+// wrote), also when an earlier decision had finished.
+__device__ __forceinline__ void ssn_publish(unsigned long long* hflag, unsigned long long seq,
+                                            double done, double need_gram, double lu_ok) {
   if (hflag == nullptr || threadIdx.x != 0) return;
-  __hip_atomic_store(hflag + 1, done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(hflag + 2, need_gram, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __hip_atomic_store(hflag + 3, lu_ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-  __threadfence_system();
-  __hip_atomic_store(hflag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  const unsigned long long w = (seq << 3) | (done != 0.0 ? 4ull : 0ull) |
+                               (need_gram != 0.0 ? 2ull : 0ull) | (lu_ok != 0.0 ? 1ull : 0ull);
+  __hip_atomic_store(hflag, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // The decision on one block of 1024 threads.
 __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L,
                                 const double* __restrict__ meta, double* __restrict__ state,
-                                double tol, int max_halvings, double* hflag, double seq) {
+                                double tol, int max_halvings, unsigned long long* hflag,
+                                unsigned long long seq) {
   __shared__ double red[1024];
   __shared__ double bsum[PcMeta::kMaxEll];
   __shared__ double Ft[PcMeta::kMaxEll];
@@ -668,8 +667,8 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
 __global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restrict__ part, int nblk,
                                                          int L, const double* __restrict__ meta,
                                                          double* __restrict__ state, double tol,
-                                                         int max_halvings, double* hflag,
-                                                         double seq) {
+                                                         int max_halvings, unsigned long long* hflag,
+                                                         unsigned long long seq) {
   ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq);
 }
 
@@ -850,7 +849,8 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
 template <int NRG>
 __global__ __launch_bounds__(1024) void ssn_decide_gram_kernel(
     const double* __restrict__ part, int nblk, int L, const double* __restrict__ meta,
-    double* __restrict__ state, double tol, int max_halvings, double* hflag, double seq,
+    double* __restrict__ state, double tol, int max_halvings, unsigned long long* hflag,
+    unsigned long long seq,
     const float* __restrict__ gpart, double* __restrict__ part2, int with_decide) {
   static_assert(kGramSets == 4, "four sets on the thread quarters of 1024");
   constexpr int NTRI = NRG * (NRG + 1) / 2;
@@ -1365,7 +1365,7 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
   NYS_TRY(launch_check("ssn_eval_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
                      static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
-                     pc->flag_seq += 1.0);
+                     ++pc->flag_seq);
   return launch_check("ssn_decide_kernel");
 }
 
@@ -1392,7 +1392,7 @@ static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, float* s_out, f
   NYS_TRY(launch_check("ssn_eval_step_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
                      static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
-                     pc->flag_seq += 1.0);
+                     ++pc->flag_seq);
   return launch_check("ssn_decide_kernel");
 }
 
@@ -1415,7 +1415,7 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
   NYS_TRY(launch_check("ssn_evalgram_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
   const int with_decide = newton_at_gamma ? 0 : 1;
-  if (with_decide) pc->flag_seq += 1.0;
+  if (with_decide) ++pc->flag_seq;
   hipLaunchKernelGGL((ssn_decide_gram_kernel<NRG>), dim3(NTRI * 4 + with_decide), dim3(1024), 0, st,
                      fpart, nblk, L, pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq,
                      part, part2, with_decide);
@@ -1435,23 +1435,25 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
 // 2 s, then falls back to a stream synchronisation.
 static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool& need_gram,
                                     bool& lu_ok) {
-  volatile double* f = pc->hflag;
-  const double want = pc->flag_seq;
+  volatile unsigned long long* f = pc->hflag;
+  const unsigned long long want = pc->flag_seq;
   const auto t0 = std::chrono::steady_clock::now();
-  while (f[0] != want) {
+  unsigned long long w = *f;
+  while ((w >> 3) != want) {
     if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
       NYS_CHECK_HIP(hipStreamSynchronize(st));
-      if (f[0] != want) {
-        set_error("semismooth Newton decision %.0f not published", want);
+      w = *f;
+      if ((w >> 3) != want) {
+        set_error("semismooth Newton decision %llu not published", want);
         return NYS_EHIP;
       }
       break;
     }
+    w = *f;
   }
-  std::atomic_thread_fence(std::memory_order_acquire);
-  done = f[1] != 0.0;
-  need_gram = f[2] != 0.0;
-  lu_ok = f[3] != 0.0;
+  done = (w & 4) != 0;
+  need_gram = (w & 2) != 0;
+  lu_ok = (w & 1) != 0;
   return NYS_OK;
 }
 
@@ -1490,10 +1492,10 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   float* lu = reinterpret_cast<float*>(mask + mask_b);
   if (!pc->hflag) {
     void* h = nullptr;
-    NYS_CHECK_HIP(hipHostMalloc(&h, 4 * sizeof(double), hipHostMallocCoherent));
-    pc->hflag = static_cast<double*>(h);
-    pc->hflag[0] = pc->hflag[1] = pc->hflag[2] = pc->hflag[3] = 0.0;
-    pc->flag_seq = 0.0;
+    NYS_CHECK_HIP(hipHostMalloc(&h, sizeof(unsigned long long), hipHostMallocCoherent));
+    pc->hflag = static_cast<unsigned long long*>(h);
+    *pc->hflag = 0;
+    pc->flag_seq = 0;
   }
   const T lam = static_cast<T>(lam_bar);
   const double tol = reg.newton_tol > 0 ? reg.newton_tol : (sizeof(T) == 8 ? 1e-12 : 1e-6);
