@@ -147,14 +147,16 @@ struct nys_pc_s {
   nys::DevBuf U;                  // ell*N
   nys::DevBuf meta;               // FP64 device block, see factor.hip
   nys::DevBuf work;               // scratch of nys_apply / prox
-  nys::DevBuf work2;
+  nys::DevBuf work2;              // cd of nys_apply / the gradient step
+  nys::DevBuf ssn_ws;             // semismooth Newton state, partials, stored LU factors
   // pinned, coherent host word (8 seq + outcome bits) written by the
   // semismooth Newton decision kernel and read by the host without a stream
   // synchronisation; the sequence number counts decisions
   unsigned long long* hflag = nullptr;
   unsigned long long flag_seq = 0;
   // the FP32 semismooth Newton workspace holds LU factors of a Jacobian of
-  // this preconditioner (cleared whenever the factorisation is redone)
+  // this preconditioner (cleared whenever the factorisation is redone or the
+  // workspace is reallocated)
   bool ssn_lu_valid = false;
   bool ssn_lu_hint = false;   // the last decision read reported stored factors
 };

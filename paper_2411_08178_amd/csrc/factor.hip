@@ -923,6 +923,7 @@ extern "C" void nys_pc_destroy(nys_pc pc) {
   pc->meta.release();
   pc->work.release();
   pc->work2.release();
+  pc->ssn_ws.release();
   if (pc->hflag) (void)hipHostFree(pc->hflag);
   delete pc;
 }

@@ -26,6 +26,13 @@ nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, 
 template <class T>
 nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
                      hipStream_t st);
+// The same with the rows of U replaced by those of B (ell_pad rows of len
+// values, pitch ldb; v: ncols columns of len).  With B = A U (the operator
+// applied to U's rows) and v = psi, B^T psi = U^T (A^T psi): the coefficients
+// of P^{-1} A^T psi from a pass over the measurements instead of the image.
+template <class T>
+nys_status pc_coeffs_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, bool inverse, const T* v,
+                        int64_t ncols, double* cd, hipStream_t st);
 
 // s = u - alpha P^{-1} g for one column, one pass over U after the
 // coefficients (pinv.hip).

@@ -382,19 +382,19 @@ static void red_geometry(int64_t N, int& nblk, int64_t& chunk) {
 }
 
 template <class T>
-nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
-                     hipStream_t st) {
+nys_status pc_coeffs_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, bool inverse, const T* v,
+                        int64_t ncols, double* cd, hipStream_t st) {
   const int L = static_cast<int>(pc->ell), Lp = static_cast<int>(pc->ell_pad);
   int nblk;
   int64_t chunk;
-  red_geometry(pc->N, nblk, chunk);
+  red_geometry(len, nblk, chunk);
   NYS_TRY(pc->work.ensure(sizeof(double) * static_cast<size_t>(ncols) * nblk * Lp));
   double* part = pc->work.as<double>();
   const double* coef = pc->meta.as<double>() + (inverse ? PcMeta::kD : PcMeta::kE);
   if constexpr (std::is_same<T, float>::value) {
-    if ((pc->N & 3) == 0) {
+    if ((len & 3) == 0 && (ldb & 3) == 0) {
       hipLaunchKernelGGL(ut_rows_kernel, dim3(nblk, static_cast<unsigned>(ncols)), dim3(256), 0, st,
-                         pc->U.as<float>(), pc->ldu, v, pc->N, Lp, chunk, part);
+                         B, ldb, v, len, Lp, chunk, part);
       NYS_TRY(launch_check("ut_rows_kernel"));
       hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, part, nblk, L, Lp,
                          static_cast<int>(ncols), coef, cd);
@@ -402,11 +402,17 @@ nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double*
     }
   }
   hipLaunchKernelGGL((ut_partial_kernel<T>), dim3(nblk, static_cast<unsigned>(ncols)), dim3(1024),
-                     0, st, pc->U.as<T>(), pc->ldu, v, pc->N, Lp, chunk, part);
+                     0, st, B, ldb, v, len, Lp, chunk, part);
   NYS_TRY(launch_check("ut_partial_kernel"));
   hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, part, nblk, L, Lp,
                      static_cast<int>(ncols), coef, cd);
   return launch_check("ut_tail_kernel");
+}
+
+template <class T>
+nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
+                     hipStream_t st) {
+  return pc_coeffs_on<T>(pc, pc->U.as<T>(), pc->ldu, pc->N, inverse, v, ncols, cd, st);
 }
 
 template <class T>
@@ -440,6 +446,10 @@ nys_status pc_x_from_pinv(nys_pc pc, const T* s, const T* t, const double* cd, d
   return launch_check("x_from_pinv_kernel");
 }
 
+template nys_status pc_coeffs_on<double>(nys_pc, const double*, int64_t, int64_t, bool,
+                                         const double*, int64_t, double*, hipStream_t);
+template nys_status pc_coeffs_on<float>(nys_pc, const float*, int64_t, int64_t, bool, const float*,
+                                        int64_t, double*, hipStream_t);
 template nys_status pc_coeffs<double>(nys_pc, bool, const double*, int64_t, double*, hipStream_t);
 template nys_status pc_coeffs<float>(nys_pc, bool, const float*, int64_t, double*, hipStream_t);
 template nys_status pc_apply<double>(nys_pc, bool, const double*, double*, int64_t, hipStream_t);
@@ -1483,8 +1493,10 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   const size_t need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
   const size_t mask_b = static_cast<size_t>((N + 255) / 256 * 256);
   const size_t lu_b = sizeof(float) * (kLuPitch * kLuPitch + kLuPitch);
-  NYS_TRY(pc->work2.ensure(sizeof(double) * need + mask_b + lu_b + 256));
-  double* state = pc->work2.as<double>();
+  const void* ws_before = pc->ssn_ws.p;
+  NYS_TRY(pc->ssn_ws.ensure(sizeof(double) * need + mask_b + lu_b + 256));
+  if (pc->ssn_ws.p != ws_before) pc->ssn_lu_valid = false;   // a new buffer holds no factors
+  double* state = pc->ssn_ws.as<double>();
   double* part = state + SsnState::kTotal;
   double* gpart = part + static_cast<size_t>(std::max(nblk, ngb)) * L;
   double* Mj = gpart + gpart_d;

@@ -120,6 +120,8 @@ constexpr int kRedBlocks = 256;
 template <class T>
 struct SolveWs {
   T *meas, *g, *s, *xn, *u, *v;
+  T* au;   // A applied to the rows of U (ell_pad x M), when M < N; else null
+  T* ucopy;   // U's rows without the pitch (ell_pad x N), the input of A U
   void* state;
   double *part, *norms;
   void* prox;
@@ -128,10 +130,17 @@ struct SolveWs {
     const int c = nch(p.reg);
     return c ? sizeof(T) * c * p.op->N : (pc ? sizeof(double) * pc->ell : 0);
   }
+  // U^T g with g = A^T psi is (A U)^T psi: a pass over M values per column of
+  // U instead of N, once A U is formed (per solve)
+  static bool use_au(const nys_problem& p, nys_pc pc) { return pc && p.op->M < p.op->N; }
+  static size_t au_bytes(const nys_problem& p, nys_pc pc) {
+    return use_au(p, pc) ? sizeof(T) * static_cast<size_t>(pc->ell_pad) * (p.op->M + p.op->N) : 0;
+  }
   static size_t bytes(const nys_problem& p, nys_pc pc) {
     auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
     return r256(sizeof(T) * (p.op->M + 5 * p.op->N)) + r256(state_bytes(p, pc)) +
-           r256(sizeof(double) * (2 * kRedBlocks + 8)) + prox_ws_bytes<T>(p.reg) + 256;
+           r256(sizeof(double) * (2 * kRedBlocks + 8)) + prox_ws_bytes<T>(p.reg) + 256 +
+           r256(au_bytes(p, pc));
   }
   SolveWs(const nys_problem& p, nys_pc pc, void* base_v) {
     auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
@@ -151,6 +160,9 @@ struct SolveWs {
     norms = part + 2 * kRedBlocks;
     after += r256(sizeof(double) * (2 * kRedBlocks + 8));
     prox = after;
+    after += prox_ws_bytes<T>(p.reg) + 256;
+    au = use_au(p, pc) ? reinterpret_cast<T*>(after) : nullptr;
+    ucopy = au ? au + static_cast<size_t>(pc->ell_pad) * M : nullptr;
   }
 };
 
@@ -230,23 +242,31 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
   NYS_TRY(fill_zero<T>(w.u, N, st));
   if (nch) NYS_TRY(fill_zero<T>(static_cast<T*>(w.state), static_cast<size_t>(nch) * N, st));
   else if (w.state) NYS_TRY(fill_zero<double>(static_cast<double*>(w.state), pc->ell, st));
+  if (w.au) {
+    // A U: U's rows (zero past ell) packed, then the operator on all of them
+    NYS_CHECK_HIP(hipMemcpy2DAsync(w.ucopy, sizeof(T) * N, pc->U.p, sizeof(T) * pc->ldu,
+                                   sizeof(T) * N, pc->ell_pad, hipMemcpyDeviceToDevice, st));
+    NYS_TRY(op_fwd<T>(op, w.ucopy, w.au, pc->ell_pad, st));
+  }
   double t_prev = 1.0;
   for (int k = 0; k < max_iter; ++k) {
-    // s = u - alpha P^{-1} grad f(u)
+    // s = u - alpha P^{-1} grad f(u), grad f(u) = A^T psi(A u - y)
     NYS_TRY(op_fwd<T>(op, w.u, w.meas, 1, st));
     hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, w.meas,
                        static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
     NYS_TRY(launch_check("residual_kernel"));
+    // cd = d . U^T grad (eq. (6)): from (A U)^T psi where A U is held
+    if (w.au) NYS_TRY(pc_coeffs_on<T>(pc, w.au, M, M, true, w.meas, 1, w.part, st));
     NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
+    if (pc && !w.au) NYS_TRY(pc_coeffs<T>(pc, true, w.g, 1, w.part, st));
     if (pc && p.reg.kind == NYS_REG_L1) {
-      // the step s = u - alpha P^{-1} g is formed inside the prox (by its
-      // first evaluation pass over U where possible)
-      NYS_TRY(pc_coeffs<T>(pc, true, w.g, 1, w.part, st));
+      // the step s = u - alpha (grad + U cd) is formed inside the prox (by
+      // its first evaluation pass over U where possible)
       const SsnStep sp{w.u, w.g, alpha, w.part};
       NYS_TRY(ssn_prox<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? static_cast<double*>(w.state) : nullptr,
                           st, nullptr, &sp));
     } else if (pc) {
-      NYS_TRY(pc_step<T>(pc, w.u, w.g, alpha, w.s, st));
+      NYS_TRY(pc_x_from_pinv<T>(pc, w.u, w.g, w.part, alpha, w.s, st));
     } else {
       hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
                          static_cast<T>(alpha), N, w.s);
