@@ -154,6 +154,9 @@ struct nys_pc_s {
   // synchronisation; the sequence number counts decisions
   unsigned long long* hflag = nullptr;
   unsigned long long flag_seq = 0;
+  // warm-start output of the semismooth Newton call being enqueued (may be
+  // null): the decision that ends the iteration writes the root there
+  double* ssn_gout = nullptr;
   // the FP32 semismooth Newton workspace holds LU factors of a Jacobian of
   // this preconditioner (cleared whenever the factorisation is redone or the
   // workspace is reallocated)

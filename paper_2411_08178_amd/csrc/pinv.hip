@@ -601,31 +601,69 @@ __device__ __forceinline__ void ssn_publish(unsigned long long* hflag, unsigned 
   __hip_atomic_store(hflag, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// The decision on one block of 1024 threads.
+// The decision on one block of 1024 threads.  Every global value it reads is
+// requested before the first wait: the block partials (nblk <= 32 blockDim/L
+// of them per thread in one round, FP64 sums in a fixed order), the trial
+// point, e, gamma and delta on the threads k < L, the scalars on thread 0.
+// When the decision ends the iteration and gout is given, the root goes to
+// gout (the caller's warm start).
 __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L,
                                 const double* __restrict__ meta, double* __restrict__ state,
                                 double tol, int max_halvings, unsigned long long* hflag,
-                                unsigned long long seq) {
+                                unsigned long long seq, double* __restrict__ gout) {
   __shared__ double red[1024];
-  __shared__ double bsum[PcMeta::kMaxEll];
   __shared__ double Ft[PcMeta::kMaxEll];
   __shared__ double wsum[2][2];
-  __shared__ int accepted;
+  __shared__ int accepted, finished;
   __shared__ double tn_s;
-  if (state[SsnState::kDone] != 0.0) {
-    ssn_publish(hflag, seq, 1.0, 0.0, state[SsnState::kLuOk]);
+  const int tid = threadIdx.x;
+  const int S = blockDim.x / L;
+  const int k = tid % L, sl = tid / L;
+  const double done0 = state[SsnState::kDone];
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (sl < S) {
+    for (int b = sl; b < nblk; b += 32 * S) {
+      double v[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const int bb = b + i * S;
+        v[i] = bb < nblk ? part[static_cast<size_t>(bb) * L + k] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 32; ++i) a[i & 7] += v[i];
+    }
+  }
+  double tk = 0, ek = 0, gk = 0, dk = 0;
+  if (tid < L) {
+    tk = state[SsnState::kTry + tid];
+    ek = meta[PcMeta::kE + tid];
+    gk = state[SsnState::kGamma + tid];
+    dk = state[SsnState::kDelta + tid];
+  }
+  double have = 0, nF = 0, t = 0, halv = 0, trials = 0, luok = 0;
+  if (tid == 0) {
+    have = state[SsnState::kHave];
+    nF = state[SsnState::kNF];
+    t = state[SsnState::kT];
+    halv = state[SsnState::kHalv];
+    trials = state[SsnState::kTrials];
+    luok = state[SsnState::kLuOk];
+  }
+  if (done0 != 0.0) {
+    ssn_publish(hflag, seq, 1.0, 0.0, luok);
     return;
   }
-  tail_sum(part, nblk, L, red, bsum);
-  // ||F||^2 and ||g||^2: L <= 128 entries on waves 0 and 1
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (sl < S) red[sl * L + k] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  __syncthreads();
+  // F = g_try - e . U^T (x - s), ||F||^2 and ||g_try||^2 on waves 0 and 1
+  const int lane = tid & 63, wave = tid >> 6;
   if (wave < 2) {
-    const int k = threadIdx.x;
     double sq = 0, gq = 0;
-    if (k < L) {
-      const double tk = state[SsnState::kTry + k];
-      const double f = tk - meta[PcMeta::kE + k] * bsum[k];
-      Ft[k] = f;
+    if (tid < L) {
+      double bs = 0;
+      for (int q = 0; q < S; ++q) bs += red[q * L + tid];
+      const double f = tk - ek * bs;
+      Ft[tid] = f;
       sq = f * f;
       gq = tk * tk;
     }
@@ -637,38 +675,37 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
     if (lane == 0) { wsum[wave][0] = sq; wsum[wave][1] = gq; }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     const double nFt = sqrt(wsum[0][0] + wsum[1][0]), gn = sqrt(wsum[0][1] + wsum[1][1]);
-    state[SsnState::kTrials] += 1.0;
-    const bool have = state[SsnState::kHave] != 0.0;
-    const double nF = state[SsnState::kNF], t = state[SsnState::kT];
-    const bool accept = !have || nFt <= (1.0 - 1e-4 * t) * nF ||
-                        state[SsnState::kHalv] >= max_halvings || !isfinite(nFt);
-    state[SsnState::kNeedGram] = 0.0;
+    state[SsnState::kTrials] = trials + 1.0;
+    const bool accept = have == 0.0 || nFt <= (1.0 - 1e-4 * t) * nF || halv >= max_halvings ||
+                        !isfinite(nFt);
+    double done = 0.0, need = 0.0;
     if (accept) {
       state[SsnState::kHave] = 1.0;
       state[SsnState::kNF] = nFt;
-      if (nFt <= tol * (1.0 + gn) || !isfinite(nFt)) state[SsnState::kDone] = 1.0;
-      else state[SsnState::kNeedGram] = 1.0;
+      if (nFt <= tol * (1.0 + gn) || !isfinite(nFt)) done = 1.0;
+      else need = 1.0;
+      state[SsnState::kDone] = done;
     } else {
       tn_s = 0.5 * t;
       state[SsnState::kT] = tn_s;
-      state[SsnState::kHalv] += 1.0;
+      state[SsnState::kHalv] = halv + 1.0;
     }
+    state[SsnState::kNeedGram] = need;
     accepted = accept ? 1 : 0;
-    ssn_publish(hflag, seq, state[SsnState::kDone], state[SsnState::kNeedGram],
-                state[SsnState::kLuOk]);
+    finished = done != 0.0 ? 1 : 0;
+    ssn_publish(hflag, seq, done, need, luok);
   }
   __syncthreads();
-  if (accepted) {
-    for (int k = threadIdx.x; k < L; k += blockDim.x) {
-      state[SsnState::kGamma + k] = state[SsnState::kTry + k];
-      state[SsnState::kF + k] = Ft[k];
+  if (tid < L) {
+    if (accepted) {
+      state[SsnState::kGamma + tid] = tk;
+      state[SsnState::kF + tid] = Ft[tid];
+      if (finished && gout != nullptr) gout[tid] = tk;
+    } else {
+      state[SsnState::kTry + tid] = gk + tn_s * dk;
     }
-  } else {
-    const double tn = tn_s;
-    for (int k = threadIdx.x; k < L; k += blockDim.x)
-      state[SsnState::kTry + k] = state[SsnState::kGamma + k] + tn * state[SsnState::kDelta + k];
   }
 }
 
@@ -678,8 +715,8 @@ __global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restri
                                                          int L, const double* __restrict__ meta,
                                                          double* __restrict__ state, double tol,
                                                          int max_halvings, unsigned long long* hflag,
-                                                         unsigned long long seq) {
-  ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq);
+                                                         unsigned long long seq, double* gout) {
+  ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq, gout);
 }
 
 // ---- masked Gram on the matrix cores
@@ -860,12 +897,12 @@ template <int NRG>
 __global__ __launch_bounds__(1024) void ssn_decide_gram_kernel(
     const double* __restrict__ part, int nblk, int L, const double* __restrict__ meta,
     double* __restrict__ state, double tol, int max_halvings, unsigned long long* hflag,
-    unsigned long long seq,
+    unsigned long long seq, double* gout,
     const float* __restrict__ gpart, double* __restrict__ part2, int with_decide) {
   static_assert(kGramSets == 4, "four sets on the thread quarters of 1024");
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   if (with_decide && blockIdx.x == gridDim.x - 1) {
-    ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq);
+    ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq, gout);
     return;
   }
   const int e = blockIdx.x * 256 + (threadIdx.x & 255), q = threadIdx.x >> 8;
@@ -1375,7 +1412,7 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
   NYS_TRY(launch_check("ssn_eval_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
                      static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
-                     ++pc->flag_seq);
+                     ++pc->flag_seq, pc->ssn_gout);
   return launch_check("ssn_decide_kernel");
 }
 
@@ -1402,7 +1439,7 @@ static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, float* s_out, f
   NYS_TRY(launch_check("ssn_eval_step_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
                      static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
-                     ++pc->flag_seq);
+                     ++pc->flag_seq, pc->ssn_gout);
   return launch_check("ssn_decide_kernel");
 }
 
@@ -1428,7 +1465,7 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
   if (with_decide) ++pc->flag_seq;
   hipLaunchKernelGGL((ssn_decide_gram_kernel<NRG>), dim3(NTRI * 4 + with_decide), dim3(1024), 0, st,
                      fpart, nblk, L, pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq,
-                     part, part2, with_decide);
+                     pc->ssn_gout, part, part2, with_decide);
   NYS_TRY(launch_check("ssn_decide_gram_kernel"));
   const size_t lds = sizeof(double) * pc->ell * (pc->ell + 1);
   if (lds > 64 * 1024)
@@ -1517,6 +1554,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L,
                      (fp32_lu && pc->ssn_lu_valid) ? 1 : 0);
   NYS_TRY(launch_check("ssn_init_kernel"));
+  pc->ssn_gout = gamma_state;   // the deciding kernel stores the root
   int trial = 0;
   bool done = false, need_gram = false, lu_ok = false;
   // FP32: without stored factors the first trial point (nearly always
@@ -1622,7 +1660,8 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
                        pc->ldu, s, state, N, L, lam, x);
     NYS_TRY(launch_check("ssn_final_kernel"));
   }
-  if (gamma_state) {
+  pc->ssn_gout = nullptr;
+  if (gamma_state && !done) {   // the trials ran out: the last accepted point
     hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
     NYS_TRY(launch_check("ssn_store_gamma_kernel"));
   }
