@@ -33,6 +33,17 @@ nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double*
 template <class T>
 nys_status pc_coeffs_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, bool inverse, const T* v,
                         int64_t ncols, double* cd, hipStream_t st);
+// Its two stages: block partials of B^T v (FP64, nblk x ell_pad per column,
+// in pc->work until the next use of that buffer), then their sums times the
+// coefficients.
+struct CoefPartials {
+  const double* part = nullptr;
+  int nblk = 0, ncols = 0;
+};
+template <class T>
+nys_status pc_partials_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, const T* v,
+                          int64_t ncols, CoefPartials* out, hipStream_t st);
+nys_status pc_tail(nys_pc pc, bool inverse, const CoefPartials& cp, double* cd, hipStream_t st);
 
 // s = u - alpha P^{-1} g for one column, one pass over U after the
 // coefficients (pinv.hip).
@@ -49,7 +60,8 @@ struct SsnStep {
   const void* u;
   const void* g;
   double alpha;
-  const double* cd;
+  CoefPartials cp;   // partials of U^T g (one column)
+  double* cd;        // ell FP64 of device workspace for cd where it is stored
 };
 // P-weighted l1 prox by semismooth Newton (Thm. 1, pinv.hip); gamma_state
 // (ell FP64, may be null) is the warm start and receives the root.  With

@@ -382,31 +382,42 @@ static void red_geometry(int64_t N, int& nblk, int64_t& chunk) {
 }
 
 template <class T>
-nys_status pc_coeffs_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, bool inverse, const T* v,
-                        int64_t ncols, double* cd, hipStream_t st) {
-  const int L = static_cast<int>(pc->ell), Lp = static_cast<int>(pc->ell_pad);
+nys_status pc_partials_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, const T* v,
+                          int64_t ncols, CoefPartials* out, hipStream_t st) {
+  const int Lp = static_cast<int>(pc->ell_pad);
   int nblk;
   int64_t chunk;
   red_geometry(len, nblk, chunk);
   NYS_TRY(pc->work.ensure(sizeof(double) * static_cast<size_t>(ncols) * nblk * Lp));
   double* part = pc->work.as<double>();
-  const double* coef = pc->meta.as<double>() + (inverse ? PcMeta::kD : PcMeta::kE);
+  out->part = part;
+  out->nblk = nblk;
+  out->ncols = static_cast<int>(ncols);
   if constexpr (std::is_same<T, float>::value) {
     if ((len & 3) == 0 && (ldb & 3) == 0) {
       hipLaunchKernelGGL(ut_rows_kernel, dim3(nblk, static_cast<unsigned>(ncols)), dim3(256), 0, st,
                          B, ldb, v, len, Lp, chunk, part);
-      NYS_TRY(launch_check("ut_rows_kernel"));
-      hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, part, nblk, L, Lp,
-                         static_cast<int>(ncols), coef, cd);
-      return launch_check("ut_tail_kernel");
+      return launch_check("ut_rows_kernel");
     }
   }
   hipLaunchKernelGGL((ut_partial_kernel<T>), dim3(nblk, static_cast<unsigned>(ncols)), dim3(1024),
                      0, st, B, ldb, v, len, Lp, chunk, part);
-  NYS_TRY(launch_check("ut_partial_kernel"));
-  hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, part, nblk, L, Lp,
-                     static_cast<int>(ncols), coef, cd);
+  return launch_check("ut_partial_kernel");
+}
+
+nys_status pc_tail(nys_pc pc, bool inverse, const CoefPartials& cp, double* cd, hipStream_t st) {
+  const double* coef = pc->meta.as<double>() + (inverse ? PcMeta::kD : PcMeta::kE);
+  hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, cp.part, cp.nblk,
+                     static_cast<int>(pc->ell), static_cast<int>(pc->ell_pad), cp.ncols, coef, cd);
   return launch_check("ut_tail_kernel");
+}
+
+template <class T>
+nys_status pc_coeffs_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, bool inverse, const T* v,
+                        int64_t ncols, double* cd, hipStream_t st) {
+  CoefPartials cp;
+  NYS_TRY(pc_partials_on<T>(pc, B, ldb, len, v, ncols, &cp, st));
+  return pc_tail(pc, inverse, cp, cd, st);
 }
 
 template <class T>
@@ -446,6 +457,10 @@ nys_status pc_x_from_pinv(nys_pc pc, const T* s, const T* t, const double* cd, d
   return launch_check("x_from_pinv_kernel");
 }
 
+template nys_status pc_partials_on<double>(nys_pc, const double*, int64_t, int64_t, const double*,
+                                           int64_t, CoefPartials*, hipStream_t);
+template nys_status pc_partials_on<float>(nys_pc, const float*, int64_t, int64_t, const float*,
+                                          int64_t, CoefPartials*, hipStream_t);
 template nys_status pc_coeffs_on<double>(nys_pc, const double*, int64_t, int64_t, bool,
                                          const double*, int64_t, double*, hipStream_t);
 template nys_status pc_coeffs_on<float>(nys_pc, const float*, int64_t, int64_t, bool, const float*,
@@ -536,25 +551,68 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
   for (int k = threadIdx.x; k < L; k += blockDim.x) part[static_cast<size_t>(blockIdx.x) * L + k] = bsum[k];
 }
 
-// The first evaluation with the prox centre given implicitly by the
-// preconditioned gradient step s = u - alpha (g + U cd) (FP32): s_n is formed
-// from the same loads of U as (U g)_n and written out for the later trials;
-// the rest as in ssn_eval_kernel.
-template <int ROWS, int LP = (ROWS <= 16 ? 16 : ROWS <= 32 ? 32 : ROWS <= 64 ? 64 : 128)>
+// The first trial of a call whose prox centre is the preconditioned gradient
+// step s = u - alpha (g + U cd), cd = d . U^T g (eq. (6); FP32, ROWS <= 64),
+// in one kernel: every block sums the ncb partials of U^T g (pitch ROWS, in a
+// fixed order) into alpha cd itself and takes the trial point from the warm
+// start gamma0 (zero if null); block 0 initialises the Newton state as
+// ssn_init_kernel does; each pixel then forms s_n from the same loads of U as
+// (U g)_n, writes it out for the later trials, and contributes to the partial
+// U^T (x - s) as in ssn_eval_kernel.
+template <int ROWS, int LP = (ROWS <= 16 ? 16 : ROWS <= 32 ? 32 : 64)>
 __global__ __launch_bounds__(512) void ssn_eval_step_kernel(
     const float* __restrict__ U, int64_t ldu, const float* __restrict__ u,
-    const float* __restrict__ g, float alpha, const double* __restrict__ cd,
+    const float* __restrict__ g, float alpha, const double* __restrict__ cpart, int ncb,
+    const double* __restrict__ dcoef, const double* __restrict__ gamma0, int keep_lu,
     float* __restrict__ s_out, int64_t N, int L, int64_t chunk, float lam,
-    const double* __restrict__ state, double* __restrict__ part, float* __restrict__ xo) {
+    double* __restrict__ state, double* __restrict__ part, float* __restrict__ xo) {
   __shared__ double red[8 * LP];
   __shared__ double bsum[LP];
   __shared__ float gam[LP], w[LP];
-  if (state[SsnState::kDone] != 0.0) return;
-  for (int k = threadIdx.x; k < LP; k += blockDim.x) {
-    gam[k] = k < L ? static_cast<float>(state[SsnState::kTry + k]) : 0.f;
-    w[k] = k < L ? static_cast<float>(alpha * cd[k]) : 0.f;
+  {
+    // alpha cd from the partials: 512 / ROWS slices of the blocks, one
+    // predicated round of up to 32 loads per thread
+    const int S = 512 / ROWS;
+    const int k = threadIdx.x % ROWS, sl = threadIdx.x / ROWS;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (sl < S) {
+      for (int b = sl; b < ncb; b += 32 * S) {
+        double v[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) {
+          const int bb = b + i * S;
+          v[i] = bb < ncb ? cpart[static_cast<size_t>(bb) * ROWS + k] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 32; ++i) a[i & 7] += v[i];
+      }
+    }
+    const double g0 = (threadIdx.x < L && gamma0 != nullptr) ? gamma0[threadIdx.x] : 0.0;
+    const double dk = threadIdx.x < L ? dcoef[threadIdx.x] : 0.0;
+    if (sl < S) red[sl * ROWS + k] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    __syncthreads();
+    if (threadIdx.x < LP) {
+      double cs = 0;
+      if (threadIdx.x < L)
+        for (int q = 0; q < S; ++q) cs += red[q * ROWS + threadIdx.x];
+      w[threadIdx.x] = threadIdx.x < L ? static_cast<float>(alpha * dk * cs) : 0.f;
+      gam[threadIdx.x] = threadIdx.x < L ? static_cast<float>(g0) : 0.f;
+    }
+    if (blockIdx.x == 0) {
+      if (threadIdx.x < L) {
+        state[SsnState::kGamma + threadIdx.x] = g0;
+        state[SsnState::kTry + threadIdx.x] = g0;
+        state[SsnState::kDelta + threadIdx.x] = 0.0;
+      }
+      if (threadIdx.x == 0) {
+        state[SsnState::kNF] = 0; state[SsnState::kT] = 1; state[SsnState::kDone] = 0;
+        state[SsnState::kHalv] = 0; state[SsnState::kHave] = 0; state[SsnState::kNeedGram] = 0;
+        state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0;
+        if (!keep_lu) state[SsnState::kLuOk] = 0;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
   const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
   float acc[LP];
@@ -1417,24 +1475,26 @@ static nys_status launch_eval(nys_pc pc, const T* s, T lam, double* state, uint8
 }
 
 template <int ROWS>
-static void launch_ssn_eval_step(nys_pc pc, const SsnStep& sp, float* s_out, float lam,
-                                 double* state, double* part, int nblk, int64_t chunk, float* xo,
-                                 hipStream_t st) {
+static void launch_ssn_eval_step(nys_pc pc, const SsnStep& sp, const double* gamma0, int keep_lu,
+                                 float* s_out, float lam, double* state, double* part, int nblk,
+                                 int64_t chunk, float* xo, hipStream_t st) {
   hipLaunchKernelGGL((ssn_eval_step_kernel<ROWS>), dim3(nblk), dim3(512), 0, st, pc->U.as<float>(),
                      pc->ldu, static_cast<const float*>(sp.u), static_cast<const float*>(sp.g),
-                     static_cast<float>(sp.alpha), sp.cd, s_out, pc->N, static_cast<int>(pc->ell),
-                     chunk, lam, state, part, xo);
+                     static_cast<float>(sp.alpha), sp.cp.part, sp.cp.nblk,
+                     pc->meta.as<double>() + PcMeta::kD, gamma0, keep_lu, s_out, pc->N,
+                     static_cast<int>(pc->ell), chunk, lam, state, part, xo);
 }
 
-// The first evaluation fused with the gradient step, and its decision.
-static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, float* s_out, float lam,
-                                   double* state, double* part, int nblk, int64_t chunk,
-                                   double tol, float* xo, hipStream_t st) {
+// The first trial with the gradient step and the state initialisation fused
+// in, and its decision.
+static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, const double* gamma0, int keep_lu,
+                                   float* s_out, float lam, double* state, double* part, int nblk,
+                                   int64_t chunk, double tol, float* xo, hipStream_t st) {
   switch (pc->ell_pad) {
-    case 16: launch_ssn_eval_step<16>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
-    case 32: launch_ssn_eval_step<32>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
-    case 48: launch_ssn_eval_step<48>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
-    default: launch_ssn_eval_step<64>(pc, sp, s_out, lam, state, part, nblk, chunk, xo, st); break;
+    case 16: launch_ssn_eval_step<16>(pc, sp, gamma0, keep_lu, s_out, lam, state, part, nblk, chunk, xo, st); break;
+    case 32: launch_ssn_eval_step<32>(pc, sp, gamma0, keep_lu, s_out, lam, state, part, nblk, chunk, xo, st); break;
+    case 48: launch_ssn_eval_step<48>(pc, sp, gamma0, keep_lu, s_out, lam, state, part, nblk, chunk, xo, st); break;
+    default: launch_ssn_eval_step<64>(pc, sp, gamma0, keep_lu, s_out, lam, state, part, nblk, chunk, xo, st); break;
   }
   NYS_TRY(launch_check("ssn_eval_step_kernel"));
   hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
@@ -1551,9 +1611,21 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   const int max_trials = reg.max_newton > 0 ? reg.max_newton : 60;
   // stored factors are kept only while they belong to this preconditioner
   const bool fp32_lu = sizeof(T) == 4 && L <= 64;
-  hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L,
-                     (fp32_lu && pc->ssn_lu_valid) ? 1 : 0);
-  NYS_TRY(launch_check("ssn_init_kernel"));
+  const bool have_lu = fp32_lu && pc->ssn_lu_valid;
+  // With factors known to be stored, the first trial, its chord step and the
+  // second trial are enqueued together (the chord step runs only if the first
+  // decision asks for a direction; a converged first trial makes the second
+  // one exit at once), and the host waits for the second decision only.
+  // With `step` there, the first trial also initialises the state and forms
+  // the gradient step from the partials of U^T g; otherwise the step is
+  // formed into s first.
+  const bool prelude = have_lu && pc->ssn_lu_hint && max_trials >= 2;
+  const bool step_fused = sizeof(T) == 4 && prelude && step != nullptr;
+  if (!step_fused) {
+    hipLaunchKernelGGL(ssn_init_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L,
+                       have_lu ? 1 : 0);
+    NYS_TRY(launch_check("ssn_init_kernel"));
+  }
   pc->ssn_gout = gamma_state;   // the deciding kernel stores the root
   int trial = 0;
   bool done = false, need_gram = false, lu_ok = false;
@@ -1565,7 +1637,6 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   // a Newton step with its Gram pass at the accepted point (factors stored).
   // A chord direction that is not accepted at once is replaced by a Newton
   // step at the accepted point.
-  const bool have_lu = fp32_lu && pc->ssn_lu_valid;
   bool chord_used = false, last_chord = false;
   float* xf = static_cast<const void*>(x) == static_cast<const void*>(s)
                   ? nullptr : reinterpret_cast<float*>(x);   // x aliasing s gets no trial writes
@@ -1581,22 +1652,17 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
       default: return launch_ssn_trial<4>(pc, sf, lf, state, part, gp, ngb, gchunk, tol, xo, lu, st, at_gamma);
     }
   };
-  // With factors known to be stored, the first trial, its chord step and the
-  // second trial are enqueued together (the chord step runs only if the first
-  // decision asks for a direction; a converged first trial makes the second
-  // one exit at once), and the host waits for the second decision only.
-  // With `step`, s is the output of the gradient step s = u - alpha (g + U cd):
-  // formed by that first evaluation pass, else by a pass of its own first.
-  const bool prelude = have_lu && pc->ssn_lu_hint && max_trials >= 2;
-  if (step != nullptr && !(sizeof(T) == 4 && prelude))
+  if (step != nullptr && !step_fused) {
+    NYS_TRY(pc_tail(pc, true, step->cp, step->cd, st));
     NYS_TRY(pc_x_from_pinv<T>(pc, static_cast<const T*>(step->u), static_cast<const T*>(step->g),
                               step->cd, step->alpha, const_cast<T*>(s), st));
+  }
   if (prelude) {
     const float* sf = reinterpret_cast<const float*>(s);
     const float lf = static_cast<float>(lam);
-    if (step != nullptr)
-      NYS_TRY(launch_eval_step(pc, *step, reinterpret_cast<float*>(const_cast<T*>(s)), lf, state,
-                               part, nblk, chunk, tol, xf, st));
+    if (step_fused)
+      NYS_TRY(launch_eval_step(pc, *step, gamma_state, 1, reinterpret_cast<float*>(const_cast<T*>(s)),
+                               lf, state, part, nblk, chunk, tol, xf, st));
     else
       NYS_TRY(launch_eval<float>(pc, sf, lf, state, nullptr, part, nblk, chunk, tol, st, xf));
     if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);

@@ -255,17 +255,20 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
     hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, w.meas,
                        static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
     NYS_TRY(launch_check("residual_kernel"));
-    // cd = d . U^T grad (eq. (6)): from (A U)^T psi where A U is held
-    if (w.au) NYS_TRY(pc_coeffs_on<T>(pc, w.au, M, M, true, w.meas, 1, w.part, st));
+    // cd = d . U^T grad (eq. (6)): partials of (A U)^T psi where A U is held,
+    // else of U^T grad
+    CoefPartials cp;
+    if (w.au) NYS_TRY(pc_partials_on<T>(pc, w.au, M, M, w.meas, 1, &cp, st));
     NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
-    if (pc && !w.au) NYS_TRY(pc_coeffs<T>(pc, true, w.g, 1, w.part, st));
+    if (pc && !w.au) NYS_TRY(pc_partials_on<T>(pc, pc->U.as<T>(), pc->ldu, N, w.g, 1, &cp, st));
     if (pc && p.reg.kind == NYS_REG_L1) {
       // the step s = u - alpha (grad + U cd) is formed inside the prox (by
       // its first evaluation pass over U where possible)
-      const SsnStep sp{w.u, w.g, alpha, w.part};
+      const SsnStep sp{w.u, w.g, alpha, cp, w.part};
       NYS_TRY(ssn_prox<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? static_cast<double*>(w.state) : nullptr,
                           st, nullptr, &sp));
     } else if (pc) {
+      NYS_TRY(pc_tail(pc, true, cp, w.part, st));
       NYS_TRY(pc_x_from_pinv<T>(pc, w.u, w.g, w.part, alpha, w.s, st));
     } else {
       hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
