@@ -659,21 +659,33 @@ __device__ __forceinline__ void ssn_publish(unsigned long long* hflag, unsigned 
   __hip_atomic_store(hflag, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Value of v on lane `lane` (wave-uniform index) through the scalar unit.
+__device__ __forceinline__ float readlane_r(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
 // The decision on one block of 1024 threads.  Every global value it reads is
 // requested before the first wait: the block partials (nblk <= 32 blockDim/L
 // of them per thread in one round, FP64 sums in a fixed order), the trial
 // point, e, gamma and delta on the threads k < L, the scalars on thread 0.
 // When the decision ends the iteration and gout is given, the root goes to
-// gout (the caller's warm start).
-__device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L,
+// gout (the caller's warm start).  With LM > 0 (L <= LM <= 64) the packed LU
+// factors of an earlier Jacobian (lu) are requested with the partials, and a
+// decision that accepts without converging is followed, on wave 0, by the
+// chord step of ssn_chord_kernel when the factors are stored.
+template <int LM = 0>
+__device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L,
                                 const double* __restrict__ meta, double* __restrict__ state,
                                 double tol, int max_halvings, unsigned long long* hflag,
-                                unsigned long long seq, double* __restrict__ gout) {
+                                unsigned long long seq, double* __restrict__ gout,
+                                const float* __restrict__ lu = nullptr) {
   __shared__ double red[1024];
   __shared__ double Ft[PcMeta::kMaxEll];
   __shared__ double wsum[2][2];
-  __shared__ int accepted, finished;
+  __shared__ int accepted, finished, chord_go;
   __shared__ double tn_s;
+  __shared__ float lus[LM > 0 ? LM * (LM + 1) : 1];
+  __shared__ float invs[LM > 0 ? LM : 1];
   const int tid = threadIdx.x;
   const int S = blockDim.x / L;
   const int k = tid % L, sl = tid / L;
@@ -698,7 +710,7 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
     gk = state[SsnState::kGamma + tid];
     dk = state[SsnState::kDelta + tid];
   }
-  double have = 0, nF = 0, t = 0, halv = 0, trials = 0, luok = 0;
+  double have = 0, nF = 0, t = 0, halv = 0, trials = 0, luok = 0, steps = 0;
   if (tid == 0) {
     have = state[SsnState::kHave];
     nF = state[SsnState::kNF];
@@ -706,6 +718,15 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
     halv = state[SsnState::kHalv];
     trials = state[SsnState::kTrials];
     luok = state[SsnState::kLuOk];
+    steps = state[SsnState::kSteps];
+  }
+  if constexpr (LM > 0) {
+    // the buffer always exists; its values are used only if stored
+    for (int e = tid; e < L * L; e += blockDim.x) {
+      const int rr = e / L, cc = e - rr * L;
+      lus[rr * (LM + 1) + cc] = lu[rr * kLuPitch + cc];
+    }
+    if (tid < L) invs[tid] = lu[kLuPitch * kLuPitch + tid];
   }
   if (done0 != 0.0) {
     ssn_publish(hflag, seq, 1.0, 0.0, luok);
@@ -753,6 +774,12 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
     state[SsnState::kNeedGram] = need;
     accepted = accept ? 1 : 0;
     finished = done != 0.0 ? 1 : 0;
+    chord_go = (LM > 0 && need != 0.0 && luok != 0.0) ? 1 : 0;
+    if (LM > 0 && chord_go) {
+      state[SsnState::kT] = 1.0;
+      state[SsnState::kHalv] = 0.0;
+      state[SsnState::kSteps] = steps + 1.0;
+    }
     ssn_publish(hflag, seq, done, need, luok);
   }
   __syncthreads();
@@ -765,6 +792,35 @@ __device__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L
       state[SsnState::kTry + tid] = gk + tn_s * dk;
     }
   }
+  if constexpr (LM > 0) {
+    // chord direction -J0^{-1} F at the accepted point: the elimination
+    // replayed on the right-hand side, then back substitution (wave 0)
+    if (chord_go && tid < 64) {
+      const int r = tid;
+      float a[LM];
+#pragma unroll
+      for (int c = 0; c < LM; ++c) a[c] = (r < L && c < L) ? lus[r * (LM + 1) + c] : 0.f;
+      const float invd = r < L ? invs[r] : 0.f;
+      float rh = r < L ? static_cast<float>(-Ft[r]) : 0.f;
+#pragma unroll
+      for (int j = 0; j < LM; ++j)
+        if (j < L) rh -= (r > j ? a[j] : 0.f) * readlane_r(rh, j);
+      float sol = 0.f;
+#pragma unroll
+      for (int j = LM - 1; j >= 0; --j) {
+        if (j < L) {
+          const float d = readlane_r(rh, j) * readlane_r(invd, j);
+          if (r == j) sol = d;
+          rh -= a[j] * d;
+        }
+      }
+      if (r < L) {
+        const double dv = static_cast<double>(sol);
+        state[SsnState::kDelta + r] = dv;
+        state[SsnState::kTry + r] = tk + dv;
+      }
+    }
+  }
 }
 
 // F(g_try) = g_try - e . U^T (x - s) from the partials, its norm, and the
@@ -775,6 +831,16 @@ __global__ __launch_bounds__(1024) void ssn_decide_kernel(const double* __restri
                                                          int max_halvings, unsigned long long* hflag,
                                                          unsigned long long seq, double* gout) {
   ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq, gout);
+}
+
+// The decision followed by the chord step with the stored factors lu, when it
+// accepts without converging (L <= LM).
+template <int LM>
+__global__ __launch_bounds__(1024) void ssn_decide_chord_kernel(
+    const double* __restrict__ part, int nblk, int L, const double* __restrict__ meta,
+    double* __restrict__ state, double tol, int max_halvings, unsigned long long* hflag,
+    unsigned long long seq, double* gout, const float* __restrict__ lu) {
+  ssn_decide_body<LM>(part, nblk, L, meta, state, tol, max_halvings, hflag, seq, gout, lu);
 }
 
 // ---- masked Gram on the matrix cores
@@ -1032,9 +1098,6 @@ __device__ __forceinline__ double wave_max_r(double v) {
   return v;
 }
 
-__device__ __forceinline__ float readlane_r(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
 __device__ __forceinline__ double readlane_r(double v, int lane) { return readlane_f64(v, lane); }
 
 // L <= LM (16, 32 or 64) on wave 0 alone, arithmetic in R (float for an FP32
@@ -1485,11 +1548,34 @@ static void launch_ssn_eval_step(nys_pc pc, const SsnStep& sp, const double* gam
                      static_cast<int>(pc->ell), chunk, lam, state, part, xo);
 }
 
+// The decision on the partials of an evaluation; with lu, followed by the
+// chord step from the stored factors (FP32, L <= 64).
+static nys_status launch_decide(nys_pc pc, double* part, int nblk, double* state, double tol,
+                                const float* lu, hipStream_t st) {
+  const int L = static_cast<int>(pc->ell);
+  if (lu == nullptr) {
+    hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk, L,
+                       pc->meta.as<double>(), state, tol, 30, pc->hflag, ++pc->flag_seq,
+                       pc->ssn_gout);
+    return launch_check("ssn_decide_kernel");
+  }
+  if (L <= 32)
+    hipLaunchKernelGGL(ssn_decide_chord_kernel<32>, dim3(1), dim3(1024), 0, st, part, nblk, L,
+                       pc->meta.as<double>(), state, tol, 30, pc->hflag, ++pc->flag_seq,
+                       pc->ssn_gout, lu);
+  else
+    hipLaunchKernelGGL(ssn_decide_chord_kernel<64>, dim3(1), dim3(1024), 0, st, part, nblk, L,
+                       pc->meta.as<double>(), state, tol, 30, pc->hflag, ++pc->flag_seq,
+                       pc->ssn_gout, lu);
+  return launch_check("ssn_decide_chord_kernel");
+}
+
 // The first trial with the gradient step and the state initialisation fused
-// in, and its decision.
+// in, and its decision (with the chord step when lu is given).
 static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, const double* gamma0, int keep_lu,
                                    float* s_out, float lam, double* state, double* part, int nblk,
-                                   int64_t chunk, double tol, float* xo, hipStream_t st) {
+                                   int64_t chunk, double tol, float* xo, const float* lu,
+                                   hipStream_t st) {
   switch (pc->ell_pad) {
     case 16: launch_ssn_eval_step<16>(pc, sp, gamma0, keep_lu, s_out, lam, state, part, nblk, chunk, xo, st); break;
     case 32: launch_ssn_eval_step<32>(pc, sp, gamma0, keep_lu, s_out, lam, state, part, nblk, chunk, xo, st); break;
@@ -1497,10 +1583,7 @@ static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, const double* g
     default: launch_ssn_eval_step<64>(pc, sp, gamma0, keep_lu, s_out, lam, state, part, nblk, chunk, xo, st); break;
   }
   NYS_TRY(launch_check("ssn_eval_step_kernel"));
-  hipLaunchKernelGGL(ssn_decide_kernel, dim3(1), dim3(1024), 0, st, part, nblk,
-                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, tol, 30, pc->hflag,
-                     ++pc->flag_seq, pc->ssn_gout);
-  return launch_check("ssn_decide_kernel");
+  return launch_decide(pc, part, nblk, state, tol, lu, st);
 }
 
 // One trial of the FP32 Newton iteration: the fused evaluation + masked Gram
@@ -1660,14 +1743,15 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   if (prelude) {
     const float* sf = reinterpret_cast<const float*>(s);
     const float lf = static_cast<float>(lam);
-    if (step_fused)
+    if (step_fused) {
       NYS_TRY(launch_eval_step(pc, *step, gamma_state, 1, reinterpret_cast<float*>(const_cast<T*>(s)),
-                               lf, state, part, nblk, chunk, tol, xf, st));
-    else
+                               lf, state, part, nblk, chunk, tol, xf, lu, st));
+    } else {
       NYS_TRY(launch_eval<float>(pc, sf, lf, state, nullptr, part, nblk, chunk, tol, st, xf));
-    if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);
-    else hipLaunchKernelGGL(ssn_chord_kernel<64>, dim3(1), dim3(64), 0, st, lu, L, state);
-    NYS_TRY(launch_check("ssn_chord_kernel"));
+      if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);
+      else hipLaunchKernelGGL(ssn_chord_kernel<64>, dim3(1), dim3(64), 0, st, lu, L, state);
+      NYS_TRY(launch_check("ssn_chord_kernel"));
+    }
     chord_used = last_chord = true;
     trial = 1;
   }
