@@ -669,10 +669,10 @@ __device__ __forceinline__ float readlane_r(float v, int lane) {
 // of them per thread in one round, FP64 sums in a fixed order), the trial
 // point, e, gamma and delta on the threads k < L, the scalars on thread 0.
 // When the decision ends the iteration and gout is given, the root goes to
-// gout (the caller's warm start).  With LM > 0 (L <= LM <= 64) the packed LU
-// factors of an earlier Jacobian (lu) are requested with the partials, and a
-// decision that accepts without converging is followed, on wave 0, by the
-// chord step of ssn_chord_kernel when the factors are stored.
+// gout (the caller's warm start).  With LM > 0 (L <= LM <= 64) the stored
+// inverse of an earlier Jacobian (lu) is requested with the partials, and a
+// decision that accepts without converging is followed by the chord step of
+// ssn_chord_kernel (16 threads a row) when the inverse is stored.
 template <int LM = 0>
 __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part, int nblk, int L,
                                 const double* __restrict__ meta, double* __restrict__ state,
@@ -685,7 +685,7 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
   __shared__ int accepted, finished, chord_go;
   __shared__ double tn_s;
   __shared__ float lus[LM > 0 ? LM * (LM + 1) : 1];
-  __shared__ float invs[LM > 0 ? LM : 1];
+  __shared__ double tkl[LM > 0 ? LM : 1];
   const int tid = threadIdx.x;
   const int S = blockDim.x / L;
   const int k = tid % L, sl = tid / L;
@@ -726,7 +726,6 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
       const int rr = e / L, cc = e - rr * L;
       lus[rr * (LM + 1) + cc] = lu[rr * kLuPitch + cc];
     }
-    if (tid < L) invs[tid] = lu[kLuPitch * kLuPitch + tid];
   }
   if (done0 != 0.0) {
     ssn_publish(hflag, seq, 1.0, 0.0, luok);
@@ -743,6 +742,7 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
       for (int q = 0; q < S; ++q) bs += red[q * L + tid];
       const double f = tk - ek * bs;
       Ft[tid] = f;
+      if constexpr (LM > 0) tkl[tid] = tk;
       sq = f * f;
       gq = tk * tk;
     }
@@ -793,31 +793,21 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
     }
   }
   if constexpr (LM > 0) {
-    // chord direction -J0^{-1} F at the accepted point: the elimination
-    // replayed on the right-hand side, then back substitution (wave 0)
-    if (chord_go && tid < 64) {
-      const int r = tid;
-      float a[LM];
+    // chord direction -J0^{-1} F at the accepted point
+    if (chord_go) {
+      const int i = tid >> 4, j0 = 4 * (tid & 15);
+      float sacc = 0.f;
+      if (i < L) {
 #pragma unroll
-      for (int c = 0; c < LM; ++c) a[c] = (r < L && c < L) ? lus[r * (LM + 1) + c] : 0.f;
-      const float invd = r < L ? invs[r] : 0.f;
-      float rh = r < L ? static_cast<float>(-Ft[r]) : 0.f;
-#pragma unroll
-      for (int j = 0; j < LM; ++j)
-        if (j < L) rh -= (r > j ? a[j] : 0.f) * readlane_r(rh, j);
-      float sol = 0.f;
-#pragma unroll
-      for (int j = LM - 1; j >= 0; --j) {
-        if (j < L) {
-          const float d = readlane_r(rh, j) * readlane_r(invd, j);
-          if (r == j) sol = d;
-          rh -= a[j] * d;
-        }
+        for (int c = 0; c < 4; ++c)
+          if (j0 + c < L) sacc += lus[i * (LM + 1) + j0 + c] * static_cast<float>(Ft[j0 + c]);
       }
-      if (r < L) {
-        const double dv = static_cast<double>(sol);
-        state[SsnState::kDelta + r] = dv;
-        state[SsnState::kTry + r] = tk + dv;
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) sacc += __shfl_xor(sacc, o, 16);
+      if (i < L && (tid & 15) == 0) {
+        const double dv = -static_cast<double>(sacc);
+        state[SsnState::kDelta + i] = dv;
+        state[SsnState::kTry + i] = tkl[i] + dv;
       }
     }
   }
@@ -1214,73 +1204,85 @@ __device__ void lu_wave(double* __restrict__ A, int L, double* __restrict__ stat
   ssn_set_direction(sol, L, state);
 }
 
-// FP32 elimination on the diagonal, wave 0 alone, lane r holding row r of J
-// and the right-hand side.  Every leading principal block of J = I + diag(e) M
-// is I + E_k M_k with M_k a principal block of U^T D U (0 <= M_k <= I) and
-// e > -1, so E_k M_k (similar to M_k^1/2 E_k M_k^1/2) has real eigenvalues
-// above -1 and no leading minor vanishes: LU without row exchanges exists,
-// and the pivot row of step j is row j, read through the scalar unit with a
-// constant lane index.  A pivot below 2^-12 max |J| (lost accuracy) or a
-// non-finite result returns false, and the caller redoes the solve with
-// partial pivoting.
-template <int LM>
-__device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __restrict__ state,
-                             float* __restrict__ lu) {
-  const int r = threadIdx.x;
+// FP32 inverse of J (L <= 64) by Gauss-Jordan elimination in place, on 1024
+// threads: thread t holds J[i][4q .. 4q + 3] (i = t / 16, q = t % 16; the
+// identity past L) in registers; at step k the holders of row k and of column
+// k publish their old values through LDS (two buffers: one barrier a step),
+// and every thread updates its four entries.  No row exchanges: every leading
+// principal block of J = I + diag(e) M is I + E_k M_k with M_k a principal
+// block of U^T D U (0 <= M_k <= I) and e > -1, so E_k M_k (similar to
+// M_k^1/2 E_k M_k^1/2) has real eigenvalues above -1 and no pivot vanishes.
+// A pivot below 2^-12 max |J| (lost accuracy) or a non-finite entry returns
+// false with nothing written, and the caller solves with partial pivoting.
+// Otherwise it sets the direction -J^{-1} F, the trial point, and stores
+// J^{-1} (row pitch kLuPitch) for the chord steps of later calls.
+__device__ bool gj_inverse_1024(const double* __restrict__ A, int L, double* __restrict__ state,
+                                float* __restrict__ jinv) {
+  __shared__ float rowb[2][64], colb[2][64];
+  __shared__ float wmax[16];
+  __shared__ float Fs[64];
+  const int t = threadIdx.x, i = t >> 4, q = t & 15, j0 = 4 * q;
   const int LP1 = L + 1;
-  float a[LM];
+  float a[4];
+  float m = 0.f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = j0 + c;
+    a[c] = (i < L && j < L) ? static_cast<float>(A[i * LP1 + j]) : (i == j ? 1.f : 0.f);
+    if (i < L && j < L) m = fmaxf(m, fabsf(a[c]));
+  }
+  if (t < 64) Fs[t] = t < L ? static_cast<float>(state[SsnState::kF + t]) : 0.f;
+  m = wave_max_f32(m);
+  if ((t & 63) == 0) wmax[t >> 6] = m;
+  __syncthreads();
   float amax = 0.f;
 #pragma unroll
-  for (int c = 0; c < LM; ++c) {
-    a[c] = (r < L && c < L) ? static_cast<float>(A[r * LP1 + c]) : (r == c ? 1.f : 0.f);
-    amax = fmaxf(amax, fabsf(a[c]));
-  }
-  amax = wave_max_f32(amax);
+  for (int w = 0; w < 16; ++w) amax = fmaxf(amax, wmax[w]);
   const float thresh = 0x1p-12f * amax;
-  float rh = (r < L) ? static_cast<float>(-state[SsnState::kF + r]) : 0.f;
-  float invd = 0.f;   // lane j: 1 / u_jj
-  bool ok = true;
+  bool small = false;
+  for (int k = 0; k < L; ++k) {
+    const int b = k & 1;
+    if (i == k) {
 #pragma unroll
-  for (int j = 0; j < LM; ++j) {
-    if (j < L) {
-      const float pv = readlane_r(a[j], j);
-      ok = ok && fabsf(pv) >= thresh;
-      const float inv = __builtin_amdgcn_rcpf(pv);
-      const float f = r > j ? a[j] * inv : 0.f;
-      if (r == j) invd = inv;
-      if (r > j) a[j] = f;     // row r keeps its multiplier in the eliminated column
-      // groups of 16 columns: no more than 16 broadcast values live at once
+      for (int c = 0; c < 4; ++c) rowb[b][j0 + c] = a[c];
+    }
+    if (q == (k >> 2)) {
+      const int c = k & 3;
+      colb[b][i] = c == 0 ? a[0] : c == 1 ? a[1] : c == 2 ? a[2] : a[3];
+    }
+    __syncthreads();
+    const float p = rowb[b][k];
+    const float f = colb[b][i];
+    const float ip = 1.f / p;
+    small = small || !(fabsf(p) >= thresh);
+    if (i == k) {
 #pragma unroll
-      for (int k = j + 1; k < LM; ++k) {
-        a[k] -= f * readlane_r(a[k], j);
-        if ((k & 15) == 15) __builtin_amdgcn_sched_barrier(0);
-      }
-      rh -= f * readlane_r(rh, j);
+      for (int c = 0; c < 4; ++c) a[c] = (j0 + c == k) ? ip : a[c] * ip;
+    } else {
+      const float fi = f * ip;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] = (j0 + c == k) ? -fi : a[c] - fi * rowb[b][j0 + c];
     }
   }
-  if (!ok) return false;
-  float sol = 0.f;
+  bool bad = small || !isfinite(a[0]) || !isfinite(a[1]) || !isfinite(a[2]) || !isfinite(a[3]);
+  if (__syncthreads_or(bad)) return false;
+  // direction -J^{-1} F: the 16 holders of a row reduce their partial sums
+  float sacc = 0.f;
 #pragma unroll
-  for (int j = LM - 1; j >= 0; --j) {
-    if (j < L) {
-      const float d = readlane_r(rh, j) * readlane_r(invd, j);
-      if (r == j) sol = d;
-      rh -= a[j] * d;
+  for (int c = 0; c < 4; ++c) sacc += a[c] * Fs[j0 + c];
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) sacc += __shfl_xor(sacc, o, 16);
+  if (i < L) {
+    if (q == 0) {
+      const double dv = -static_cast<double>(sacc);
+      state[SsnState::kDelta + i] = dv;
+      state[SsnState::kTry + i] = state[SsnState::kGamma + i] + dv;
     }
-  }
-  if (__ballot(!isfinite(sol)) != 0) return false;
-  if (r < L) {
-    const double dv = static_cast<double>(sol);
-    state[SsnState::kDelta + r] = dv;
-    state[SsnState::kTry + r] = state[SsnState::kGamma + r] + dv;
-    // packed factors (unit lower multipliers below the diagonal, U on and
-    // above) and 1 / u_rr, for chord steps of later calls
 #pragma unroll
-    for (int c = 0; c < LM; ++c)
-      if (c < L) lu[r * kLuPitch + c] = a[c];
-    lu[kLuPitch * kLuPitch + r] = invd;
+    for (int c = 0; c < 4; ++c)
+      if (j0 + c < L) jinv[i * kLuPitch + j0 + c] = a[c];
   }
-  if (r == 0) {
+  if (t == 0) {
     state[SsnState::kT] = 1.0;
     state[SsnState::kHalv] = 0.0;
     state[SsnState::kSteps] += 1.0;
@@ -1289,40 +1291,34 @@ __device__ bool lu_wave_diag(const double* __restrict__ A, int L, double* __rest
   return true;
 }
 
-// Chord step (FP32, L <= LM <= 64): the direction -J0^{-1} F(gamma) with the
-// packed LU factors of an earlier Jacobian J0 of the same preconditioner (the
-// masks of consecutive prox centres differ in few pixels); replays the
-// elimination on the right-hand side, then back-substitutes, on one wave.
-template <int LM>
-__global__ __launch_bounds__(64) void ssn_chord_kernel(const float* __restrict__ lu, int L,
+// Chord step (FP32, L <= 64): the direction -J0^{-1} F(gamma) with the stored
+// inverse of an earlier Jacobian J0 of the same preconditioner (the masks of
+// consecutive prox centres differ in few pixels); lane r forms row r.
+__global__ __launch_bounds__(64) void ssn_chord_kernel(const float* __restrict__ jinv, int L,
                                                        double* __restrict__ state) {
+  __shared__ float Fs[64];
   // only after a decision that accepted its point without converging, and
-  // with factors stored
-  if (state[SsnState::kDone] != 0.0 || state[SsnState::kNeedGram] == 0.0 ||
-      state[SsnState::kLuOk] == 0.0)
-    return;
+  // with an inverse stored; the inverse, F and gamma are requested together
+  // with the flags (the buffer always exists; its values are used only if
+  // stored)
   const int r = threadIdx.x;
-  float a[LM];
+  const double done = state[SsnState::kDone], need = state[SsnState::kNeedGram],
+               luok = state[SsnState::kLuOk];
+  float a[64];
 #pragma unroll
-  for (int c = 0; c < LM; ++c) a[c] = (r < L && c < L) ? lu[r * kLuPitch + c] : 0.f;
-  const float invd = r < L ? lu[kLuPitch * kLuPitch + r] : 0.f;
-  float rh = (r < L) ? static_cast<float>(-state[SsnState::kF + r]) : 0.f;
+  for (int c = 0; c < 64; ++c) a[c] = (r < L && c < L) ? jinv[r * kLuPitch + c] : 0.f;
+  const double fr = r < L ? state[SsnState::kF + r] : 0.0;
+  const double gr = r < L ? state[SsnState::kGamma + r] : 0.0;
+  if (done != 0.0 || need == 0.0 || luok == 0.0) return;
+  Fs[r] = static_cast<float>(fr);
+  __syncthreads();
+  float sacc = 0.f;
 #pragma unroll
-  for (int j = 0; j < LM; ++j)
-    if (j < L) rh -= (r > j ? a[j] : 0.f) * readlane_r(rh, j);
-  float sol = 0.f;
-#pragma unroll
-  for (int j = LM - 1; j >= 0; --j) {
-    if (j < L) {
-      const float d = readlane_r(rh, j) * readlane_r(invd, j);
-      if (r == j) sol = d;
-      rh -= a[j] * d;
-    }
-  }
+  for (int c = 0; c < 64; ++c) sacc += a[c] * Fs[c];
   if (r < L) {
-    const double dv = static_cast<double>(sol);
+    const double dv = -static_cast<double>(sacc);
     state[SsnState::kDelta + r] = dv;
-    state[SsnState::kTry + r] = state[SsnState::kGamma + r] + dv;
+    state[SsnState::kTry + r] = gr + dv;
   }
   if (r == 0) {
     state[SsnState::kT] = 1.0;
@@ -1348,7 +1344,7 @@ __device__ __forceinline__ void ssn_lu(double* A, int L, double* state) {
 // One block: J = I + diag(e) M with M = sum of the kGramSets stage-2
 // partials, then the LU solve.
 template <int NRG>
-__global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict__ part2, int L,
+__global__ __launch_bounds__(1024) void ssn_solve_kernel(const double* __restrict__ part2, int L,
                                                         const double* __restrict__ meta,
                                                         double* __restrict__ state, int force,
                                                         float* __restrict__ lu) {
@@ -1374,18 +1370,10 @@ __global__ __launch_bounds__(256) void ssn_solve_kernel(const double* __restrict
     if (gi != gj) A[gj * LP1 + gi] = meta[PcMeta::kE + gj] * sacc;
   }
   __syncthreads();
-  // elimination on the diagonal; the compact pivoted elimination of the whole
-  // block only if that reports lost accuracy
-  __shared__ int diag_ok;
-  if constexpr (NRG <= 2) {
-    if (threadIdx.x < 64) {
-      const bool ok = lu_wave_diag<NRG == 1 ? 32 : 64>(A, L, state, lu);
-      if (threadIdx.x == 0) diag_ok = ok ? 1 : 0;
-    }
-  } else {
-    if (threadIdx.x == 0) diag_ok = 0;
-  }
-  __syncthreads();
+  // Gauss-Jordan inverse without row exchanges; the compact pivoted
+  // elimination of the whole block only if that reports lost accuracy
+  bool diag_ok = false;
+  if constexpr (NRG <= 2) diag_ok = gj_inverse_1024(A, L, state, lu);
   if (!diag_ok) {
     if (threadIdx.x == 0) state[SsnState::kLuOk] = 0.0;   // no stored factors from this path
     lu_wave(A, L, state);
@@ -1614,7 +1602,7 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_solve_kernel<NRG>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  hipLaunchKernelGGL((ssn_solve_kernel<NRG>), dim3(1), dim3(256), lds, st, part2,
+  hipLaunchKernelGGL((ssn_solve_kernel<NRG>), dim3(1), dim3(1024), lds, st, part2,
                      static_cast<int>(pc->ell), pc->meta.as<double>(), state, newton_at_gamma ? 1 : 0,
                      lu);
   return launch_check("ssn_solve_kernel");
@@ -1748,8 +1736,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
                                lf, state, part, nblk, chunk, tol, xf, lu, st));
     } else {
       NYS_TRY(launch_eval<float>(pc, sf, lf, state, nullptr, part, nblk, chunk, tol, st, xf));
-      if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);
-      else hipLaunchKernelGGL(ssn_chord_kernel<64>, dim3(1), dim3(64), 0, st, lu, L, state);
+      hipLaunchKernelGGL(ssn_chord_kernel, dim3(1), dim3(64), 0, st, lu, L, state);
       NYS_TRY(launch_check("ssn_chord_kernel"));
     }
     chord_used = last_chord = true;
@@ -1788,8 +1775,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
       const bool fused_here = trial == 0 && !have_lu;   // its Newton step is already enqueued
       if (!fused_here) {
         if (need_gram && fp32_lu && lu_ok && !chord_used) {
-          if (L <= 32) hipLaunchKernelGGL(ssn_chord_kernel<32>, dim3(1), dim3(64), 0, st, lu, L, state);
-          else hipLaunchKernelGGL(ssn_chord_kernel<64>, dim3(1), dim3(64), 0, st, lu, L, state);
+          hipLaunchKernelGGL(ssn_chord_kernel, dim3(1), dim3(64), 0, st, lu, L, state);
           NYS_TRY(launch_check("ssn_chord_kernel"));
           chord_used = last_chord = true;
         } else if (need_gram || last_chord) {
