@@ -119,42 +119,47 @@ __global__ __launch_bounds__(256) void upcorrelate_kernel(
 }
 
 // ================================================================ Haar
-// One thread per 2^L x 2^L block; in-place layout.  Analysis applies levels
-// 0..L-1 (stride 1, 2, 4 inside the block), synthesis the reverse order.
+// In-place layout: the coefficients of each 2^L x 2^L block stay in the block.
+// Analysis applies levels 0..L-1 (stride 1, 2, 4 inside the block), synthesis
+// the reverse order; the 2 x 2 step is its own inverse.  B = 2^L consecutive
+// lanes hold the B rows of a block (a wave covers 64 / B neighbouring blocks,
+// so every row load is a contiguous run); at stride s the rows r and r + s of
+// a 2 x 2 group (r a multiple of 2s) trade values through width-B shuffles.
 template <int L, bool kAnalysis, class SI, class SO, class C>
 __global__ __launch_bounds__(256) void haar_kernel(const SI* __restrict__ in,
                                                    SO* __restrict__ out, int n1, int n2) {
   constexpr int B = 1 << L;
   const int nb2 = n2 / B, nb1 = n1 / B;
-  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blk >= nb1 * nb2) return;
-  const int bi = blk / nb2, bj = blk - bi * nb2;
-  const size_t base = static_cast<size_t>(blockIdx.z) * n1 * n2 +
-                      static_cast<size_t>(bi * B) * n2 + bj * B;
-  C v[B][B];
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = gt / B, r = gt % B;
+  const bool live = blk < nb1 * nb2;
+  const int bi = live ? blk / nb2 : 0, bj = live ? blk - bi * nb2 : 0;
+  const size_t row = static_cast<size_t>(blockIdx.z) * n1 * n2 +
+                     static_cast<size_t>(bi * B + r) * n2 + bj * B;
+  C v[B];
 #pragma unroll
-  for (int r = 0; r < B; ++r)
-#pragma unroll
-    for (int q = 0; q < B; ++q) v[r][q] = Io<SI>::ld(in, base + static_cast<size_t>(r) * n2 + q);
+  for (int q = 0; q < B; ++q) v[q] = live ? Io<SI>::ld(in, row + q) : C(0);
 #pragma unroll
   for (int it = 0; it < L; ++it) {
     const int lev = kAnalysis ? it : (L - 1 - it);
     const int s = 1 << lev;
+    const bool part = (r & (s - 1)) == 0;   // rows at this level's spacing
+    const bool top = (r & s) == 0;
 #pragma unroll
-    for (int r = 0; r < B; r += 2 * s)
-#pragma unroll
-      for (int q = 0; q < B; q += 2 * s) {
-        C a = v[r][q], b = v[r][q + s], cc = v[r + s][q], d = v[r + s][q + s];
-        v[r][q] = (a + b + cc + d) * C(0.5);
-        v[r][q + s] = (a - b + cc - d) * C(0.5);
-        v[r + s][q] = (a + b - cc - d) * C(0.5);
-        v[r + s][q + s] = (a - b - cc + d) * C(0.5);
+    for (int q = 0; q < B; q += 2 * s) {
+      const C o0 = __shfl_xor(v[q], s, B), o1 = __shfl_xor(v[q + s], s, B);
+      const C a = top ? v[q] : o0, b = top ? v[q + s] : o1;
+      const C cc = top ? o0 : v[q], d = top ? o1 : v[q + s];
+      if (part) {
+        v[q] = top ? (a + b + cc + d) * C(0.5) : (a + b - cc - d) * C(0.5);
+        v[q + s] = top ? (a - b + cc - d) * C(0.5) : (a - b - cc + d) * C(0.5);
       }
+    }
   }
+  if (live) {
 #pragma unroll
-  for (int r = 0; r < B; ++r)
-#pragma unroll
-    for (int q = 0; q < B; ++q) Io<SO>::st(out, base + static_cast<size_t>(r) * n2 + q, v[r][q]);
+    for (int q = 0; q < B; ++q) Io<SO>::st(out, row + q, v[q]);
+  }
 }
 
 // ================================================================ Joseph
@@ -356,8 +361,8 @@ template <bool kAnalysis, class SI, class SO, class C>
 static nys_status launch_haar(int levels, const SI* in, SO* out, int n1, int n2, int64_t ncols,
                               hipStream_t st) {
   const int B = 1 << levels;
-  const int blocks = (n1 / B) * (n2 / B);
-  dim3 grid(cdiv(blocks, 256), 1, static_cast<unsigned>(ncols));
+  const int64_t lanes = static_cast<int64_t>(n1 / B) * (n2 / B) * B;   // B lanes per block
+  dim3 grid(cdiv(lanes, 256), 1, static_cast<unsigned>(ncols));
   switch (levels) {
     case 1: hipLaunchKernelGGL((haar_kernel<1, kAnalysis, SI, SO, C>), grid, dim3(256), 0, st, in, out, n1, n2); break;
     case 2: hipLaunchKernelGGL((haar_kernel<2, kAnalysis, SI, SO, C>), grid, dim3(256), 0, st, in, out, n1, n2); break;

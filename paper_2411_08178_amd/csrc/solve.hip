@@ -120,8 +120,10 @@ constexpr int kRedBlocks = 256;
 template <class T>
 struct SolveWs {
   T *meas, *g, *s, *xn, *u, *v;
-  T* au;   // A applied to the rows of U (ell_pad x M), when M < N; else null
+  T* au;      // A applied to the rows of U (ell_pad rows, pitch ldau), when M < N; else null
   T* ucopy;   // U's rows without the pitch (ell_pad x N), the input of A U
+  T* aucont;  // A U as the operator writes it (ell_pad x M)
+  int64_t ldau = 0;
   void* state;
   double *part, *norms;
   void* prox;
@@ -133,13 +135,18 @@ struct SolveWs {
   // U^T g with g = A^T psi is (A U)^T psi: a pass over M values per column of
   // U instead of N, once A U is formed (per solve)
   static bool use_au(const nys_problem& p, nys_pc pc) { return pc && p.op->M < p.op->N; }
+  // row pitch of A U: a multiple of 4 values, padded off a power-of-two
+  // stride (rows read together would fall on the same memory channels)
+  static int64_t au_pitch(int64_t M) { return (M + 3) / 4 * 4 + (M >= 16384 ? 96 : 0); }
   static size_t au_bytes(const nys_problem& p, nys_pc pc) {
-    return use_au(p, pc) ? sizeof(T) * static_cast<size_t>(pc->ell_pad) * (p.op->M + p.op->N) : 0;
+    return use_au(p, pc) ? sizeof(T) * static_cast<size_t>(pc->ell_pad) *
+                               (au_pitch(p.op->M) + p.op->N + p.op->M)
+                         : 0;
   }
   static size_t bytes(const nys_problem& p, nys_pc pc) {
     auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
     return r256(sizeof(T) * (p.op->M + 5 * p.op->N)) + r256(state_bytes(p, pc)) +
-           r256(sizeof(double) * (2 * kRedBlocks + 8)) + prox_ws_bytes<T>(p.reg) + 256 +
+           r256(sizeof(double) * (2 * kRedBlocks + 8)) + r256(prox_ws_bytes<T>(p.reg) + 256) +
            r256(au_bytes(p, pc));
   }
   SolveWs(const nys_problem& p, nys_pc pc, void* base_v) {
@@ -160,9 +167,11 @@ struct SolveWs {
     norms = part + 2 * kRedBlocks;
     after += r256(sizeof(double) * (2 * kRedBlocks + 8));
     prox = after;
-    after += prox_ws_bytes<T>(p.reg) + 256;
+    after += r256(prox_ws_bytes<T>(p.reg) + 256);
     au = use_au(p, pc) ? reinterpret_cast<T*>(after) : nullptr;
-    ucopy = au ? au + static_cast<size_t>(pc->ell_pad) * M : nullptr;
+    ldau = au ? au_pitch(M) : 0;
+    ucopy = au ? au + static_cast<size_t>(pc->ell_pad) * ldau : nullptr;
+    aucont = au ? ucopy + static_cast<size_t>(pc->ell_pad) * N : nullptr;
   }
 };
 
@@ -246,7 +255,9 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
     // A U: U's rows (zero past ell) packed, then the operator on all of them
     NYS_CHECK_HIP(hipMemcpy2DAsync(w.ucopy, sizeof(T) * N, pc->U.p, sizeof(T) * pc->ldu,
                                    sizeof(T) * N, pc->ell_pad, hipMemcpyDeviceToDevice, st));
-    NYS_TRY(op_fwd<T>(op, w.ucopy, w.au, pc->ell_pad, st));
+    NYS_TRY(op_fwd<T>(op, w.ucopy, w.aucont, pc->ell_pad, st));
+    NYS_CHECK_HIP(hipMemcpy2DAsync(w.au, sizeof(T) * w.ldau, w.aucont, sizeof(T) * M, sizeof(T) * M,
+                                   pc->ell_pad, hipMemcpyDeviceToDevice, st));
   }
   double t_prev = 1.0;
   for (int k = 0; k < max_iter; ++k) {
@@ -258,7 +269,7 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
     // cd = d . U^T grad (eq. (6)): partials of (A U)^T psi where A U is held,
     // else of U^T grad
     CoefPartials cp;
-    if (w.au) NYS_TRY(pc_partials_on<T>(pc, w.au, M, M, w.meas, 1, &cp, st));
+    if (w.au) NYS_TRY(pc_partials_on<T>(pc, w.au, w.ldau, M, w.meas, 1, &cp, st));
     NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
     if (pc && !w.au) NYS_TRY(pc_partials_on<T>(pc, pc->U.as<T>(), pc->ldu, N, w.g, 1, &cp, st));
     if (pc && p.reg.kind == NYS_REG_L1) {
