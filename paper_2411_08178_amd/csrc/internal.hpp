@@ -8,6 +8,14 @@ namespace nys {
 // y = A x / x = A^T y with the optional wavelet composition (ops.hip).
 template <class T> nys_status op_fwd(nys_op op, const T* x, T* y, int64_t ncols, hipStream_t st);
 template <class T> nys_status op_adj(nys_op op, const T* y, T* x, int64_t ncols, hipStream_t st);
+// out = psi(A x - yobs) in one kernel (psi of the loss: identity for least
+// squares, clip((.) / delta, -1, 1) for Huber; yobs null: out = A x), for the
+// operators where op_fwd_fused_ok holds: blur and blur-decimation with the Haar
+// synthesis of 0..3 levels.
+template <class T> bool op_fwd_fused_ok(nys_op op);
+template <class T>
+nys_status op_fwd_psi(nys_op op, const T* x, const T* yobs, int loss, double delta, T* out,
+                      int64_t ncols, hipStream_t st);
 
 // Fused W H^T S^T S H W^T sketch for factor-2 decimation with 3 Haar levels
 // (sketch_sr.hip).  S is float or uint16_t (bfloat16).

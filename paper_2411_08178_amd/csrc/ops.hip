@@ -318,6 +318,143 @@ template <class C> const C* inva_ptr(const nys_op_s* op) {
   return trig_ptr<C>(op) + 2 * op->d.n_views;
 }
 
+// ================================================================ fused forward
+// psi(A W^T x - y) for the blur and blur-decimation operators, W^T the Haar
+// synthesis of L levels (L = 0: x is the image), in one kernel.  A workgroup
+// takes a kFwdTH x kFwdTW tile of the output grid: it synthesises the
+// 2^L x 2^L coefficient blocks that cover the tile's input window (periodic,
+// B = 2^L lanes a block as in haar_kernel) into LDS, correlates them with the
+// flipped PSF at stride f (the same sums in the same order as
+// correlate_kernel), and applies the loss derivative of residual_kernel
+// (yobs null: the plain forward).
+constexpr int kFwdTH = 8, kFwdTW = 32;
+
+__host__ __device__ inline int fwd_win_blocks(int f, int T, int k, int B) {
+  return (f * (T - 1) + k + B - 1) / B + 1;   // blocks covering any window of that length
+}
+
+template <int L, class T>
+__global__ __launch_bounds__(256) void blur_fwd_fused_kernel(
+    const T* __restrict__ x, T* __restrict__ out, const T* __restrict__ g, int k, int n1, int n2,
+    int o1, int o2, int f, const T* __restrict__ yobs, int loss, T delta) {
+  constexpr int B = 1 << L;
+  extern __shared__ unsigned char smem_raw[];
+  T* sg = reinterpret_cast<T*>(smem_raw);
+  T* win = sg + k * k;
+  const int c = (k - 1) / 2;
+  const int i0 = blockIdx.y * kFwdTH, j0 = blockIdx.x * kFwdTW;
+  const int nbr_max = fwd_win_blocks(f, kFwdTH, k, B), nbc_max = fwd_win_blocks(f, kFwdTW, k, B);
+  const int LW = nbc_max * B;   // LDS row length
+  // block range of the input window [f i0 - c, f (i0 + TH - 1) - c + k - 1]
+  const int bR0 = floor_div(f * i0 - c, B), bC0 = floor_div(f * j0 - c, B);
+  const int nbr = floor_div(f * (i0 + kFwdTH - 1) - c + k - 1, B) - bR0 + 1;
+  const int nbc = floor_div(f * (j0 + kFwdTW - 1) - c + k - 1, B) - bC0 + 1;
+  const size_t plane = static_cast<size_t>(n1) * n2;
+  const T* src = x + static_cast<size_t>(blockIdx.z) * plane;
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x) sg[t] = g[t];
+  const int nb1 = n1 / B, nb2 = n2 / B;
+  const int ntask = nbr * nbc * B;
+  for (int t0 = 0; t0 < ntask; t0 += blockDim.x) {
+    const int task = t0 + threadIdx.x;
+    const bool live = task < ntask;
+    const int blk = live ? task / B : 0, r = task % B;
+    const int lbr = blk / nbc, lbc = blk - lbr * nbc;
+    int gbr = (bR0 + lbr) % nb1; if (gbr < 0) gbr += nb1;
+    int gbc = (bC0 + lbc) % nb2; if (gbc < 0) gbc += nb2;
+    const T* rowp = src + static_cast<size_t>(gbr * B + r) * n2 + gbc * B;
+    T v[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) v[q] = live ? rowp[q] : T(0);
+#pragma unroll
+    for (int it = 0; it < L; ++it) {
+      const int s = 1 << (L - 1 - it);   // synthesis: coarsest level first
+      const bool part = (r & (s - 1)) == 0;
+      const bool top = (r & s) == 0;
+#pragma unroll
+      for (int q = 0; q < B; q += 2 * s) {
+        const T e0 = __shfl_xor(v[q], s, B), e1 = __shfl_xor(v[q + s], s, B);
+        const T a = top ? v[q] : e0, b = top ? v[q + s] : e1;
+        const T cc = top ? e0 : v[q], d = top ? e1 : v[q + s];
+        if (part) {
+          v[q] = top ? (a + b + cc + d) * T(0.5) : (a + b - cc - d) * T(0.5);
+          v[q + s] = top ? (a - b + cc - d) * T(0.5) : (a - b - cc + d) * T(0.5);
+        }
+      }
+    }
+    if (live) {
+      T* wrow = win + static_cast<size_t>(lbr * B + r) * LW + lbc * B;
+#pragma unroll
+      for (int q = 0; q < B; ++q) wrow[q] = v[q];
+    }
+  }
+  __syncthreads();
+  const int ty = threadIdx.x / kFwdTW, tx = threadIdx.x % kFwdTW;
+  const int oi = i0 + ty, oj = j0 + tx;
+  if (oi >= o1 || oj >= o2) return;
+  // window coordinates of the output's first tap
+  const int ly = f * oi - c - bR0 * B, lx = f * oj - c - bC0 * B;
+  T acc = 0;
+  for (int a = 0; a < k; ++a) {
+    const T* row = win + static_cast<size_t>(ly + a) * LW + lx;
+    const T* grow = sg + a * k;
+    for (int b = 0; b < k; ++b) acc += grow[b] * row[b];
+  }
+  const size_t oidx = static_cast<size_t>(blockIdx.z) * o1 * o2 + static_cast<size_t>(oi) * o2 + oj;
+  if (yobs != nullptr) {
+    T v = acc - yobs[oidx];
+    if (loss == NYS_LOSS_HUBER) v = fmin(T(1), fmax(T(-1), v / delta));
+    acc = v;
+  }
+  out[oidx] = acc;
+}
+
+template <class T>
+bool op_fwd_fused_ok(nys_op op) {
+  const auto& d = op->d;
+  if (d.kind != NYS_OP_BLUR && d.kind != NYS_OP_BLURDOWN) return false;
+  const int B = 1 << d.wavelet_levels;
+  const int f = d.kind == NYS_OP_BLURDOWN ? d.factor : 1;
+  return d.wavelet_levels >= 0 && d.wavelet_levels <= 3 && d.n1 % B == 0 && d.n2 % B == 0 &&
+         d.n1 % f == 0 && d.n2 % f == 0;
+}
+
+template <class T>
+nys_status op_fwd_psi(nys_op op, const T* x, const T* yobs, int loss, double delta, T* out,
+                      int64_t ncols, hipStream_t st) {
+  const auto& d = op->d;
+  const int k = d.psf_size, L = d.wavelet_levels, B = 1 << L;
+  const int f = d.kind == NYS_OP_BLURDOWN ? d.factor : 1;
+  const int o1 = d.n1 / f, o2 = d.n2 / f;
+  const size_t sm = sizeof(T) * (static_cast<size_t>(k) * k +
+                                 static_cast<size_t>(fwd_win_blocks(f, kFwdTH, k, B) * B) *
+                                     (fwd_win_blocks(f, kFwdTW, k, B) * B));
+  dim3 grid(cdiv(o2, kFwdTW), cdiv(o1, kFwdTH), static_cast<unsigned>(ncols));
+#define NYS_FWD_FUSED(LL)                                                                          \
+  do {                                                                                             \
+    if (sm > 64 * 1024)                                                                            \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&blur_fwd_fused_kernel<LL, T>),      \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(sm)); \
+    hipLaunchKernelGGL((blur_fwd_fused_kernel<LL, T>), grid, dim3(256), sm, st, x, out,            \
+                       psf_ptr<T>(op, true), k, d.n1, d.n2, o1, o2, f, yobs, loss,                 \
+                       static_cast<T>(delta));                                                     \
+  } while (0)
+  switch (L) {
+    case 0: NYS_FWD_FUSED(0); break;
+    case 1: NYS_FWD_FUSED(1); break;
+    case 2: NYS_FWD_FUSED(2); break;
+    default: NYS_FWD_FUSED(3); break;
+  }
+#undef NYS_FWD_FUSED
+  return launch_check("blur_fwd_fused_kernel");
+}
+
+template bool op_fwd_fused_ok<float>(nys_op);
+template bool op_fwd_fused_ok<double>(nys_op);
+template nys_status op_fwd_psi<float>(nys_op, const float*, const float*, int, double, float*,
+                                      int64_t, hipStream_t);
+template nys_status op_fwd_psi<double>(nys_op, const double*, const double*, int, double,
+                                       double*, int64_t, hipStream_t);
+
 template <class SI, class SO, class C>
 static nys_status launch_correlate(const nys_op_s* op, const SI* in, SO* out, bool flipped,
                                    int n1, int n2, int f, int64_t ncols, hipStream_t st) {

@@ -259,13 +259,18 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
     NYS_CHECK_HIP(hipMemcpy2DAsync(w.au, sizeof(T) * w.ldau, w.aucont, sizeof(T) * M, sizeof(T) * M,
                                    pc->ell_pad, hipMemcpyDeviceToDevice, st));
   }
+  const bool fwd_fused = op_fwd_fused_ok<T>(op);
   double t_prev = 1.0;
   for (int k = 0; k < max_iter; ++k) {
     // s = u - alpha P^{-1} grad f(u), grad f(u) = A^T psi(A u - y)
-    NYS_TRY(op_fwd<T>(op, w.u, w.meas, 1, st));
-    hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, w.meas,
-                       static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
-    NYS_TRY(launch_check("residual_kernel"));
+    if (fwd_fused) {
+      NYS_TRY(op_fwd_psi<T>(op, w.u, static_cast<const T*>(p.y), p.loss, p.delta, w.meas, 1, st));
+    } else {
+      NYS_TRY(op_fwd<T>(op, w.u, w.meas, 1, st));
+      hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, w.meas,
+                         static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
+      NYS_TRY(launch_check("residual_kernel"));
+    }
     // cd = d . U^T grad (eq. (6)): partials of (A U)^T psi where A U is held,
     // else of U^T grad
     CoefPartials cp;
