@@ -491,13 +491,13 @@ struct SsnState {
   static constexpr int kS = 4 * PcMeta::kMaxEll;         // scalars
   static constexpr int kNF = kS + 0, kT = kS + 1, kDone = kS + 2, kHalv = kS + 3,
                        kHave = kS + 4, kNeedGram = kS + 5, kTrials = kS + 6, kSteps = kS + 7,
-                       kLuOk = kS + 8;   // FP32: packed LU factors of the last Newton solve stored
+                       kLuOk = kS + 8;   // FP32: inverse of the last Newton Jacobian stored
   static constexpr int kTotal = kS + 16;
 };
 
 // Sets of partial Gram sums left by stage 2 for the Newton solve to add.
 constexpr int kGramSets = 4;
-// Row pitch (floats) of the stored packed LU factors: 64 x 64, then 64 values 1 / u_rr.
+// Row pitch (floats) of the stored Jacobian inverse (64 x 64).
 constexpr int kLuPitch = 64;
 
 // Evaluation at the trial point in one pass over U: r = s - U g, x = soft(r)
@@ -1660,7 +1660,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
   const size_t need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
   const size_t mask_b = static_cast<size_t>((N + 255) / 256 * 256);
-  const size_t lu_b = sizeof(float) * (kLuPitch * kLuPitch + kLuPitch);
+  const size_t lu_b = sizeof(float) * kLuPitch * kLuPitch;
   const void* ws_before = pc->ssn_ws.p;
   NYS_TRY(pc->ssn_ws.ensure(sizeof(double) * need + mask_b + lu_b + 256));
   if (pc->ssn_ws.p != ws_before) pc->ssn_lu_valid = false;   // a new buffer holds no factors
