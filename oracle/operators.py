@@ -256,7 +256,7 @@ def hessian_adjoint(q: np.ndarray) -> np.ndarray:
 
 def pair(q: np.ndarray, v: np.ndarray, reg: str) -> float:
     """Dual pairing <Q, V> used by the adjoints above."""
-    if reg == "hs1":
+    if reg in ("hs1", "hs2", "hsinf"):
         return float(np.sum(q[..., 0, :, :] * v[..., 0, :, :])
                      + np.sum(q[..., 1, :, :] * v[..., 1, :, :])
                      + 2 * np.sum(q[..., 2, :, :] * v[..., 2, :, :]))

@@ -23,12 +23,17 @@ from . import operators as ops
 # --------------------------------------------------------------------------
 # regulariser pieces
 
+# Hessian Schatten-phi priors (the paper's HS_phi, phi = 1, 2, inf): the
+# groups are the symmetric 2 x 2 Hessians of the appendix example
+HESSIAN_REGS = ("hs1", "hs2", "hsinf")
+
+
 def reg_L(x, reg):
-    return ops.hessian(x) if reg == "hs1" else ops.grad(x)
+    return ops.hessian(x) if reg in HESSIAN_REGS else ops.grad(x)
 
 
 def reg_Lt(q, reg):
-    return ops.hessian_adjoint(q) if reg == "hs1" else ops.grad_adjoint(q)
+    return ops.hessian_adjoint(q) if reg in HESSIAN_REGS else ops.grad_adjoint(q)
 
 
 def sym2_eig(v):
@@ -41,8 +46,9 @@ def sym2_eig(v):
 
 
 def reg_value(x, reg):
-    """||L x||_{1,phi} for 'tv' (phi=2), 'tv_aniso' (phi=1), 'hs1' (Schatten-1),
-    'l1' (plain l1 of x itself)."""
+    """||L x||_{1,phi} for 'tv' (phi=2), 'tv_aniso' (phi=1), 'hs1', 'hs2',
+    'hsinf' (Schatten-1, -2, -inf norm of each Hessian group: the l1, l2,
+    l_inf norm of its eigenvalues), 'l1' (plain l1 of x itself)."""
     if reg == "l1":
         return float(np.sum(np.abs(x)))
     v = reg_L(x, reg)
@@ -50,10 +56,34 @@ def reg_value(x, reg):
         return float(np.sum(np.sqrt(v[..., 0, :, :] ** 2 + v[..., 1, :, :] ** 2)))
     if reg == "tv_aniso":
         return float(np.sum(np.abs(v)))
-    if reg == "hs1":
+    if reg in HESSIAN_REGS:
         w, _ = sym2_eig(v)
-        return float(np.sum(np.abs(w)))
+        if reg == "hs1":
+            return float(np.sum(np.abs(w)))
+        if reg == "hs2":
+            return float(np.sum(np.sqrt(np.sum(w * w, axis=-1))))
+        return float(np.sum(np.max(np.abs(w), axis=-1)))
     raise ValueError(reg)
+
+
+def project_l1_ball(w):
+    """Euclidean projection of every row of w onto the unit l1 ball: the
+    sort-and-threshold rule (soft threshold at the theta that makes the
+    magnitudes sum to 1, for rows outside the ball)."""
+    w = np.asarray(w, dtype=np.float64)
+    a = np.abs(w)
+    out = w.copy()
+    outside = a.sum(axis=-1) > 1.0
+    if not np.any(outside):
+        return out
+    u = -np.sort(-a[outside], axis=-1)          # descending magnitudes
+    css = np.cumsum(u, axis=-1)
+    j = np.arange(1, u.shape[-1] + 1)
+    cond = u - (css - 1.0) / j > 0
+    rho = cond.shape[-1] - 1 - np.argmax(cond[..., ::-1], axis=-1)   # last index where cond holds
+    theta = (css[np.arange(len(rho)), rho] - 1.0) / (rho + 1)
+    out[outside] = np.sign(w[outside]) * np.maximum(a[outside] - theta[:, None], 0.0)
+    return out
 
 
 def project_dual_ball(q, reg):
@@ -63,15 +93,26 @@ def project_dual_ball(q, reg):
     'tv_aniso': each entry clipped to [-1, 1]
     'hs1'     : each symmetric 2 x 2 group onto the unit spectral-norm ball,
                 i.e. its eigenvalues clipped to [-1, 1]
+    'hs2'     : onto the unit Frobenius (Schatten-2) ball: the eigenvalues
+                onto the unit l2 ball
+    'hsinf'   : onto the unit nuclear-norm (Schatten-1) ball: the eigenvalues
+                onto the unit l1 ball
+    (the Frobenius metric of the groups counts v12 = v21 twice, so
+    projecting the eigenvalues is the projection of the group)
     """
     if reg == "tv":
         nrm = np.sqrt(q[..., 0, :, :] ** 2 + q[..., 1, :, :] ** 2)
         return q / np.maximum(1.0, nrm)[..., None, :, :]
     if reg == "tv_aniso":
         return np.clip(q, -1.0, 1.0)
-    if reg == "hs1":
+    if reg in HESSIAN_REGS:
         w, V = sym2_eig(q)
-        w = np.clip(w, -1.0, 1.0)
+        if reg == "hs1":
+            w = np.clip(w, -1.0, 1.0)
+        elif reg == "hs2":
+            w = w / np.maximum(1.0, np.sqrt(np.sum(w * w, axis=-1)))[..., None]
+        else:
+            w = project_l1_ball(w.reshape(-1, 2)).reshape(w.shape)
         m = np.einsum("...ik,...k,...jk->...ij", V, w, V)
         out = np.empty_like(q)
         out[..., 0, :, :] = m[..., 0, 0]
@@ -81,7 +122,7 @@ def project_dual_ball(q, reg):
     raise ValueError(reg)
 
 
-L_NORM2_BOUND = {"tv": 8.0, "tv_aniso": 8.0, "hs1": 34.0}
+L_NORM2_BOUND = {"tv": 8.0, "tv_aniso": 8.0, "hs1": 34.0, "hs2": 34.0, "hsinf": 34.0}
 
 
 def prox_mixed_dual(s, lam_bar, reg, pinv, pinv_norm, n_inner, q0=None,

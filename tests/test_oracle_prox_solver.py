@@ -18,7 +18,7 @@ def _small_precond(N, K, seed, tail="sqrt"):
 
 # --- dual FISTA prox ------------------------------------------------------
 
-@pytest.mark.parametrize("reg", ["tv", "hs1", "tv_aniso"])
+@pytest.mark.parametrize("reg", ["tv", "hs1", "tv_aniso", "hs2", "hsinf"])
 def test_dual_prox_gap_nonnegative_and_vanishing(reg):
     n = 12
     s = W.gaussian((n, n), 1)
@@ -68,6 +68,64 @@ def test_projections_closed_forms():
     Mc = R @ np.diag([1.0, -1.0]) @ R.T
     assert np.allclose(out[:, 0, 1], (Mc[0, 0], Mc[1, 1], Mc[0, 1]))
     assert px.reg_value(np.zeros((4, 4)), "hs1") == 0.0
+
+
+def _hessian_groups(x):
+    """The symmetric 2 x 2 Hessian of every pixel as full matrices."""
+    from oracle import operators as ops
+    v = ops.hessian(x)
+    M = np.empty(v.shape[1:] + (2, 2))
+    M[..., 0, 0], M[..., 1, 1] = v[0], v[1]
+    M[..., 0, 1] = M[..., 1, 0] = v[2]
+    return M
+
+
+def test_hessian_schatten_values_are_the_matrix_norms():
+    # HS_phi of the appendix example: the Schatten-phi norm of every group,
+    # checked against numpy's nuclear, Frobenius and spectral matrix norms
+    x = W.gaussian((9, 7), 12)
+    M = _hessian_groups(x)
+    for reg, ordn in (("hs1", "nuc"), ("hs2", "fro"), ("hsinf", 2)):
+        ref = sum(np.linalg.norm(M[i, j], ordn) for i in range(M.shape[0]) for j in range(M.shape[1]))
+        assert abs(px.reg_value(x, reg) - ref) <= 1e-12 * (1 + ref)
+
+
+@pytest.mark.parametrize("reg,ordn", [("hs2", "fro"), ("hsinf", "nuc")])
+def test_schatten_dual_ball_projection_is_the_nearest_point(reg, ordn):
+    # the dual ball of HS_2 is the Schatten-2 ball, of HS_inf the Schatten-1
+    # ball (1/phi + 1/psi = 1); the projection of a group in the Frobenius
+    # metric, found by a general constrained minimiser over symmetric 2 x 2
+    # matrices
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(7)
+    q = rng.standard_normal((3, 1, 8)) * 1.5
+    out = px.project_dual_ball(q, reg)
+    for k in range(q.shape[-1]):
+        M = np.array([[q[0, 0, k], q[2, 0, k]], [q[2, 0, k], q[1, 0, k]]])
+        inside = np.linalg.norm(M, ordn) <= 1
+        def obj(z):
+            X = np.array([[z[0], z[2]], [z[2], z[1]]])
+            return float(np.sum((X - M) ** 2))
+        cons = {"type": "ineq",
+                "fun": lambda z: 1.0 - np.linalg.norm(np.array([[z[0], z[2]], [z[2], z[1]]]), ordn)}
+        best = None
+        for z0 in (np.zeros(3), 0.3 * np.array([M[0, 0], M[1, 1], M[0, 1]])):
+            r = minimize(obj, z0, constraints=[cons], method="SLSQP",
+                         options={"ftol": 1e-14, "maxiter": 500})
+            if best is None or r.fun < best.fun:
+                best = r
+        got = out[:, 0, k]
+        if inside:
+            assert np.allclose(got, q[:, 0, k], atol=1e-12)
+        else:
+            # on the unit sphere, and no feasible point the minimiser found
+            # is nearer (the nuclear norm's kinks slow the minimiser down, so
+            # compare distances rather than points)
+            Xg = np.array([[got[0], got[2]], [got[2], got[1]]])
+            assert abs(np.linalg.norm(Xg, ordn) - 1.0) < 1e-12
+            assert obj(got) <= best.fun * (1 + 1e-7) + 1e-12, (reg, k, obj(got), best.fun)
+            if reg == "hs2":
+                assert np.allclose(got, best.x, atol=1e-6)
 
 
 # --- l1 prox with the diagonal-plus-low-rank metric (Thm. 1) ---------------
