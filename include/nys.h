@@ -51,8 +51,10 @@ typedef enum {
 typedef enum {
   NYS_REG_TV = 0,        /* isotropic TV, l_{1,2} of first differences */
   NYS_REG_TV_ANISO = 1,  /* anisotropic TV, l_{1,1} */
-  NYS_REG_HS1 = 2,       /* Hessian Schatten-1 */
-  NYS_REG_L1 = 3         /* l1 of the unknown itself (wavelet coefficients) */
+  NYS_REG_HS1 = 2,       /* Hessian Schatten-1 (sum of |eigenvalues| of each 2x2 Hessian) */
+  NYS_REG_L1 = 3,        /* l1 of the unknown itself (wavelet coefficients) */
+  NYS_REG_HS2 = 4,       /* Hessian Schatten-2 (Frobenius norm of each 2x2 Hessian) */
+  NYS_REG_HSINF = 5      /* Hessian Schatten-inf (spectral norm of each 2x2 Hessian) */
 } nys_reg_kind;
 
 typedef enum { NYS_LOSS_LS = 0, NYS_LOSS_HUBER = 1 } nys_loss_kind;
@@ -166,10 +168,13 @@ nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
  * Weighted proximal map (definition in Sec. I-D):
  *   x = argmin_u  lambda_bar g(u) + 1/2 ||u - s||_P^2,   C = R^N,
  * P = I when pc is NULL.
- *  TV / TV_ANISO / HS1: dual accelerated projected gradient on Q for n_inner
- *   iterations (eqs. (17)-(22)); x(Q) = s - lambda_bar P^{-1} L^T Q; the step
- *   is 1 / (lambda_bar ||L||^2 ||P^{-1}||).  `state` holds Q (2*N values for
- *   TV, 3*N for HS1, dtype dt) and is used as the warm start and updated.
+ *  TV / TV_ANISO / HS1 / HS2 / HSINF: dual accelerated projected gradient on
+ *   Q for n_inner iterations (eqs. (17)-(22)); x(Q) = s - lambda_bar P^{-1}
+ *   L^T Q; the step is 1 / (lambda_bar ||L||^2 ||P^{-1}||).  The dual ball of
+ *   eq. (18) is per group: the unit l2 ball (TV), [-1, 1] (TV_ANISO), and for
+ *   the Hessian groups the unit Schatten-inf, -2, -1 ball (HS1, HS2, HSINF).
+ *   `state` holds Q (2*N values for TV, 3*N for the Hessian kinds, dtype dt)
+ *   and is used as the warm start and updated.
  *  L1: Thm. 1 with P = I + U diag(e) U^T: gamma solves
  *   gamma = diag(e) U^T (soft(s - U gamma) - s), semismooth Newton with
  *   backtracking on ||F||; x = soft(s - U gamma).  `state` holds gamma
@@ -180,8 +185,8 @@ nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
 typedef struct {
   int32_t kind;        /* nys_reg_kind */
   int32_t n1, n2;
-  double lnorm2;       /* ||L||^2 bound for the dual step; <= 0: 8 (TV), 34 (HS1) */
-  int32_t n_inner;     /* dual iterations (TV, HS1) */
+  double lnorm2;       /* ||L||^2 bound for the dual step; <= 0: 8 (TV), 34 (Hessian kinds) */
+  int32_t n_inner;     /* dual iterations (TV and Hessian kinds) */
   int32_t max_newton;  /* SSN trial points (L1); <= 0: 60 */
   double newton_tol;   /* ||F|| <= tol (1 + ||gamma||); <= 0: 1e-12 / 1e-6 */
 } nys_reg_desc;
@@ -273,7 +278,8 @@ nys_status unrolled_backward(const nys_problem* prob, nys_pc pc, nys_dtype dt,
  * solved together, every step of every instance in shared launches that are
  * captured once into a HIP graph.  Instance i solves eq. (4) with
  * f = 1/2 ||h_i * x - y_i||^2 and lambda_i g(x), g = TV, anisotropic TV or
- * HS1 (one kind for the batch), by WAPG (Alg. 3) from x = u = 0 with the
+ * a Hessian Schatten prior HS1 / HS2 / HSINF (one kind for the batch), by
+ * WAPG (Alg. 3) from x = u = 0 with the
  * P-weighted prox of the dual iterations (eqs. (17)-(22)).  With
  * precondition = 1, P is the Nystrom preconditioner of eq. (6) built from the
  * sketch Y = A^T A Omega (Alg. 1, step 2) and the shifted factorisation
@@ -306,7 +312,7 @@ typedef struct {
 } nys_batch_item;
 
 typedef struct {
-  int32_t reg;            /* NYS_REG_TV, NYS_REG_TV_ANISO or NYS_REG_HS1 */
+  int32_t reg;            /* NYS_REG_TV, NYS_REG_TV_ANISO, NYS_REG_HS1, _HS2 or _HSINF */
   int32_t max_iter;       /* outer WAPG iterations */
   int32_t n_inner;        /* dual iterations per prox */
   int32_t power_iters;    /* >= 1 */

@@ -13,9 +13,10 @@ library_path = os.path.join(HERE, "libnys.so")
 
 F64, F32, BF16 = 0, 1, 2
 OP_BLUR, OP_BLURDOWN, OP_PARALLEL_BEAM, OP_IDENTITY = 0, 1, 2, 3
-REG_TV, REG_TV_ANISO, REG_HS1, REG_L1 = 0, 1, 2, 3
+REG_TV, REG_TV_ANISO, REG_HS1, REG_L1, REG_HS2, REG_HSINF = 0, 1, 2, 3, 4, 5
 LOSS_LS, LOSS_HUBER = 0, 1
-REG_NAMES = {"tv": REG_TV, "tv_aniso": REG_TV_ANISO, "hs1": REG_HS1, "l1": REG_L1}
+REG_NAMES = {"tv": REG_TV, "tv_aniso": REG_TV_ANISO, "hs1": REG_HS1, "l1": REG_L1,
+             "hs2": REG_HS2, "hsinf": REG_HSINF}
 
 _STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ENOTPD", 4: "ENOTFINITE",
            5: "ENOCONV", 6: "EHIP"}

@@ -642,7 +642,7 @@ nys_status enqueue_all(nys_batch_s* b) {
     NYS_TRY(launch_check("bnormalize_kernel"));
   }
   const double safety = o.safety > 0 ? o.safety : 1.01;
-  const double lnorm2 = reg == NYS_REG_HS1 ? 34.0 : 8.0;
+  const double lnorm2 = reg_hessian(reg) ? 34.0 : 8.0;
   hipLaunchKernelGGL(bscalars_kernel, dim3(cdiv(b->count, 64)), dim3(64), 0, st, d, b->count,
                      safety, lnorm2);
   NYS_TRY(launch_check("bscalars_kernel"));
@@ -652,7 +652,7 @@ nys_status enqueue_all(nys_batch_s* b) {
   NYS_TRY(fill_zero<float>(d0.f[kFldX], b->P, st));
   NYS_TRY(fill_zero<float>(d0.f[kFldU], b->P, st));
   NYS_TRY(fill_zero<float>(d0.f[kFldQ], static_cast<size_t>(b->nch) * b->P, st));
-  const int term = reg == NYS_REG_TV ? kTV : reg == NYS_REG_TV_ANISO ? kTVAniso : kHS1;
+  const int term = reg_term_of(reg);
   double t_prev = 1.0;
   for (int k = 0; k < o.max_iter; ++k) {
     // s = u - alpha P^{-1} A^T (A u - y), with A^T A u - A^T y from one stencil pass
@@ -704,8 +704,8 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
                                          void* stream) {
   NYS_REQUIRE(items && opts && out && count >= 1, "batch_solve_create: bad argument");
   const nys_batch_opts o = *opts;
-  NYS_REQUIRE(o.reg == NYS_REG_TV || o.reg == NYS_REG_TV_ANISO || o.reg == NYS_REG_HS1,
-              "batch_solve_create: reg must be TV, TV_ANISO or HS1");
+  NYS_REQUIRE(o.reg == NYS_REG_TV || o.reg == NYS_REG_TV_ANISO || reg_hessian(o.reg),
+              "batch_solve_create: reg must be TV, TV_ANISO, HS1, HS2 or HSINF");
   NYS_REQUIRE(o.max_iter >= 0 && o.n_inner >= 0 && o.power_iters >= 1,
               "batch_solve_create: bad iteration counts");
   NYS_REQUIRE(o.nu_mode == 0 || o.nu_mode == 1, "batch_solve_create: nu_mode must be 0 or 1");
@@ -715,7 +715,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   auto* b = new nys_batch_s();
   b->o = o;
   b->count = count;
-  b->nch = o.reg == NYS_REG_HS1 ? 3 : 2;
+  b->nch = reg_hessian(o.reg) ? 3 : 2;
   auto fail = [&](nys_status s) { plan_destroy(b); return s; };
 
   // ---- per-instance sizes, taps

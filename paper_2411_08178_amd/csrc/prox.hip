@@ -1,6 +1,6 @@
 // P-weighted proximal maps (definition in Sec. I-D, C = R^N).
 //
-// TV / TV_ANISO / HS1: accelerated projected gradient on the dual variable Q
+// TV / TV_ANISO / Hessian Schatten kinds: accelerated projected gradient on the dual variable Q
 // (eqs. (17)-(22)): each inner iteration computes t = L^T R, applies P^{-1},
 // forms x = s - lam_bar (P^{-1} t), and updates Q, R with the ball
 // projection and momentum.  L1: Thm. 1 with a semismooth Newton method whose
@@ -55,8 +55,8 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
                             T* Q, T* R, T* tbuf, double* cd, hipStream_t st) {
   const int n1 = reg.n1, n2 = reg.n2;
   const int64_t N = static_cast<int64_t>(n1) * n2;
-  const int nch = reg.kind == NYS_REG_HS1 ? 3 : 2;
-  double lnorm2 = reg.lnorm2 > 0 ? reg.lnorm2 : (reg.kind == NYS_REG_HS1 ? 34.0 : 8.0);
+  const int nch = reg_hessian(reg.kind) ? 3 : 2;
+  double lnorm2 = reg.lnorm2 > 0 ? reg.lnorm2 : (reg_hessian(reg.kind) ? 34.0 : 8.0);
   double pinv_norm = 1.0;
   if (pc) {
     if (pc->pinv_norm_cache < 0) {
@@ -109,7 +109,7 @@ __global__ void soft_kernel(const T* __restrict__ s, T lam, int64_t N, T* __rest
 template <class T>
 size_t prox_ws_bytes(const nys_reg_desc& reg) {
   const size_t N = static_cast<size_t>(reg.n1) * reg.n2;
-  const int nch = reg.kind == NYS_REG_HS1 ? 3 : 2;
+  const int nch = reg_hessian(reg.kind) ? 3 : 2;
   return sizeof(double) * PcMeta::kMaxEll + sizeof(T) * (static_cast<size_t>(nch) * N * 2 + N) + 256;
 }
 
@@ -125,7 +125,7 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     }
     return ssn_prox<T>(reg, lam_bar, pc, s, x, static_cast<double*>(state), st);
   }
-  const int nch = reg.kind == NYS_REG_HS1 ? 3 : 2;
+  const int nch = reg_hessian(reg.kind) ? 3 : 2;
   // work: [cd: kMaxEll doubles | R | Q (when no state) | t]; the caller's
   // buffer of prox_ws_bytes, else a per-thread one
   static thread_local DevBuf fallback;
@@ -158,7 +158,7 @@ using namespace nys;
 static nys_status check_reg(const nys_reg_desc* reg, nys_pc pc, nys_dtype dt) {
   NYS_REQUIRE(reg, "null regulariser descriptor");
   NYS_REQUIRE(reg->n1 > 0 && reg->n2 > 0, "bad regulariser image size");
-  NYS_REQUIRE(reg->kind >= NYS_REG_TV && reg->kind <= NYS_REG_L1, "bad regulariser kind");
+  NYS_REQUIRE(reg->kind >= NYS_REG_TV && reg->kind <= NYS_REG_HSINF, "bad regulariser kind");
   NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "prox dtype must be F64 or F32");
   if (pc) {
     NYS_REQUIRE(pc->N == static_cast<int64_t>(reg->n1) * reg->n2, "pc size != image size");
@@ -174,7 +174,7 @@ extern "C" nys_status nys_prox_state_bytes(const nys_reg_desc* reg, nys_pc pc, n
   NYS_REQUIRE(bytes, "null bytes");
   const size_t N = static_cast<size_t>(reg->n1) * reg->n2;
   if (reg->kind == NYS_REG_L1) *bytes = pc ? sizeof(double) * pc->ell : 0;
-  else *bytes = dtype_size(dt) * N * (reg->kind == NYS_REG_HS1 ? 3 : 2);
+  else *bytes = dtype_size(dt) * N * (reg_hessian(reg->kind) ? 3 : 2);
   return NYS_OK;
 }
 

@@ -127,7 +127,7 @@ struct SolveWs {
   void* state;
   double *part, *norms;
   void* prox;
-  static int nch(const nys_reg_desc& r) { return r.kind == NYS_REG_HS1 ? 3 : (r.kind == NYS_REG_L1 ? 0 : 2); }
+  static int nch(const nys_reg_desc& r) { return reg_hessian(r.kind) ? 3 : (r.kind == NYS_REG_L1 ? 0 : 2); }
   static size_t state_bytes(const nys_problem& p, nys_pc pc) {
     const int c = nch(p.reg);
     return c ? sizeof(T) * c * p.op->N : (pc ? sizeof(double) * pc->ell : 0);
@@ -177,12 +177,7 @@ struct SolveWs {
 
 template <class T>
 static int reg_term(const nys_reg_desc& r) {
-  switch (r.kind) {
-    case NYS_REG_TV: return kTV;
-    case NYS_REG_TV_ANISO: return kTVAniso;
-    case NYS_REG_HS1: return kHS1;
-    default: return kAbs;
-  }
+  return reg_term_of(r.kind);
 }
 
 template <class T>

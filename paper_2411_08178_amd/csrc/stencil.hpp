@@ -9,8 +9,12 @@ namespace nys {
 
 // ================================================================ stencils
 // Regulariser channels: TV (2): d1 = X[i,j]-X[i-1,j] (0 on row 0),
-// d2 = X[i,j]-X[i,j-1] (0 on column 0).  HS1 (3): v11, v22, v12 with
-// replicate padding, v12 counted twice in the pairing.
+// d2 = X[i,j]-X[i,j-1] (0 on column 0).  Hessian kinds HS1 / HS2 / HSINF
+// (3): v11, v22, v12 with replicate padding, v12 counted twice in the
+// pairing.
+__host__ __device__ inline bool reg_hessian(int reg) {
+  return reg == NYS_REG_HS1 || reg == NYS_REG_HS2 || reg == NYS_REG_HSINF;
+}
 template <class T>
 __device__ __forceinline__ T ldc(const T* x, int i, int j, int n1, int n2) {
   i = i < 0 ? 0 : (i >= n1 ? n1 - 1 : i);
@@ -38,7 +42,7 @@ template <class T>
 __device__ __forceinline__ T lt_at(const T* q, int reg, int i, int j, int n1, int n2) {
   const size_t N = static_cast<size_t>(n1) * n2;
   const size_t o = static_cast<size_t>(i) * n2 + j;
-  if (reg != NYS_REG_HS1) {
+  if (!reg_hessian(reg)) {
     const T* q1 = q;
     const T* q2 = q + N;
     T v = 0;
@@ -66,14 +70,32 @@ __device__ __forceinline__ void project_group(int reg, T* v) {
   } else if (reg == NYS_REG_TV_ANISO) {
     v[0] = fmin(T(1), fmax(T(-1), v[0]));
     v[1] = fmin(T(1), fmax(T(-1), v[1]));
+  } else if (reg == NYS_REG_HS2) {
+    // unit Frobenius ball (b counted twice): scale the group
+    const T nrm = sqrt(v[0] * v[0] + v[1] * v[1] + T(2) * v[2] * v[2]);
+    if (nrm > T(1)) { v[0] /= nrm; v[1] /= nrm; v[2] /= nrm; }
   } else {
-    // symmetric [[a, b], [b, c]]: clip eigenvalues to [-1, 1]
+    // symmetric [[a, b], [b, c]] = V diag(l1, l2) V^T: the eigenvalues onto
+    // [-1, 1]^2 (HS1: spectral ball) or onto the unit l1 ball (HSINF: nuclear
+    // ball), the eigenvectors kept
     T a = v[0], c = v[1], b = v[2];
     T m = T(0.5) * (a + c), h = T(0.5) * (a - c);
     T r = sqrt(h * h + b * b);
     T l1 = m + r, l2 = m - r;
-    if (l1 <= T(1) && l2 >= T(-1)) return;
-    T u1 = fmin(T(1), fmax(T(-1), l1)), u2 = fmin(T(1), fmax(T(-1), l2));
+    T u1, u2;
+    if (reg == NYS_REG_HS1) {
+      if (l1 <= T(1) && l2 >= T(-1)) return;
+      u1 = fmin(T(1), fmax(T(-1), l1));
+      u2 = fmin(T(1), fmax(T(-1), l2));
+    } else {
+      const T a1 = fabs(l1), a2 = fabs(l2);
+      if (a1 + a2 <= T(1)) return;
+      // soft threshold theta with max(a1 - theta, 0) + max(a2 - theta, 0) = 1
+      const T big = fmax(a1, a2), sml = fmin(a1, a2);
+      const T theta = (big - sml >= T(1)) ? big - T(1) : T(0.5) * (a1 + a2 - T(1));
+      u1 = copysign(fmax(a1 - theta, T(0)), l1);
+      u2 = copysign(fmax(a2 - theta, T(0)), l2);
+    }
     T avg = T(0.5) * (u1 + u2);
     if (r > T(0)) {
       T g = (u1 - u2) / (T(2) * r);
@@ -96,7 +118,7 @@ __device__ __forceinline__ void dual_update_at(const T* __restrict__ x, T* __res
   const size_t o = static_cast<size_t>(i) * n2 + j;
   T lx[3];
   int nch;
-  if (reg != NYS_REG_HS1) {
+  if (!reg_hessian(reg)) {
     T xc = x[o];
     lx[0] = i >= 1 ? xc - x[o - n2] : T(0);
     lx[1] = j >= 1 ? xc - x[o - 1] : T(0);
@@ -122,7 +144,19 @@ __device__ __forceinline__ void dual_update_at(const T* __restrict__ x, T* __res
 }
 
 // Per-element cost terms (FP64); `which` selects the term.
-enum Term { kSq = 0, kHuber = 1, kAbs = 2, kTV = 3, kTVAniso = 4, kHS1 = 5 };
+enum Term { kSq = 0, kHuber = 1, kAbs = 2, kTV = 3, kTVAniso = 4, kHS1 = 5, kHS2 = 6, kHSInf = 7 };
+
+// The cost term of a regulariser kind.
+__host__ __device__ inline int reg_term_of(int reg) {
+  switch (reg) {
+    case NYS_REG_TV: return kTV;
+    case NYS_REG_TV_ANISO: return kTVAniso;
+    case NYS_REG_HS1: return kHS1;
+    case NYS_REG_HS2: return kHS2;
+    case NYS_REG_HSINF: return kHSInf;
+    default: return kAbs;
+  }
+}
 
 template <class T>
 __device__ __forceinline__ double term_at(const T* a, const T* b, int64_t i, int which, T delta,
@@ -153,7 +187,10 @@ __device__ __forceinline__ double term_at(const T* a, const T* b, int64_t i, int
   double v12 = 0.25 * (X(r + 1, c + 1) - X(r + 1, c - 1) - X(r - 1, c + 1) + X(r - 1, c - 1));
   double m = 0.5 * (v11 + v22), h = 0.5 * (v11 - v22);
   double rad = sqrt(h * h + v12 * v12);
-  return fabs(m + rad) + fabs(m - rad);
+  const double e1 = fabs(m + rad), e2 = fabs(m - rad);
+  if (which == kHS2) return sqrt(e1 * e1 + e2 * e2);
+  if (which == kHSInf) return fmax(e1, e2);
+  return e1 + e2;
 }
 
 }  // namespace nys

@@ -59,13 +59,13 @@ def _check_costs(c, cr):
     assert np.max(np.abs(c - cr) / np.abs(cr)) < 5e-4
 
 
-@pytest.mark.parametrize("reg", ["tv", "hs1"])
+@pytest.mark.parametrize("reg", ["tv", "hs1", "hsinf"])
 def test_batch_preconditioned_matches_oracle(reg):
     P = need_gpu()
     banner(f"batch preconditioned {reg}")
     inst = _instances(300, reg=reg)
     iters, inner, piters = 8, 10, 60
-    plan = P.BatchSolver(inst, reg=P.REG_TV if reg == "tv" else P.REG_HS1, max_iter=iters,
+    plan = P.BatchSolver(inst, reg=P.REG_NAMES[reg], max_iter=iters,
                          n_inner=inner, power_iters=piters, record_costs=True, tune=True)
     plan.run()
     torch.cuda.synchronize()

@@ -102,7 +102,9 @@ def test_factor_not_pd_is_reported():
 
 @pytest.mark.parametrize("reg,dt,with_pc", [("tv", "f64", True), ("tv", "f64", False),
                                             ("hs1", "f64", True), ("tv_aniso", "f32", True),
-                                            ("hs1", "f32", False)])
+                                            ("hs1", "f32", False), ("hs2", "f64", True),
+                                            ("hs2", "f32", False), ("hsinf", "f64", True),
+                                            ("hsinf", "f32", True)])
 def test_prox_dual(reg, dt, with_pc):
     P = need_gpu()
     banner(f"prox dual {reg} {dt} pc={with_pc}")
