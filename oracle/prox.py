@@ -126,13 +126,19 @@ L_NORM2_BOUND = {"tv": 8.0, "tv_aniso": 8.0, "hs1": 34.0, "hs2": 34.0, "hsinf": 
 
 
 def prox_mixed_dual(s, lam_bar, reg, pinv, pinv_norm, n_inner, q0=None,
-                    lnorm2=None):
-    """argmin_x 1/2 ||x - s||_P^2 + lam_bar ||L x||_{1,phi}, C = R^N.
+                    lnorm2=None, proj_c=None):
+    """argmin_{x in C} 1/2 ||x - s||_P^2 + lam_bar ||L x||_{1,phi}.
 
     pinv: callable v -> P^{-1} v (identity for the plain method).
+    proj_c: None for C = R^N, else the P-weighted projection onto C
+    (prox^P_{delta_C}, a callable z -> x): then x(Q) = proj_c(s - lam_bar
+    P^{-1} L^T Q) (eq. (21)), the dual gradient -2 lam_bar L x(Q) and the same
+    step (prox^P_{delta_C} is nonexpansive in the P-norm, so the Lipschitz
+    bound of the unconstrained case holds).
     Returns (x, Q).  The returned x is built from the last projected Q, not
     from the extrapolated point (eq. (22)).
     """
+    xq = (lambda z: z) if proj_c is None else proj_c
     if lnorm2 is None:
         lnorm2 = L_NORM2_BOUND[reg]
     if q0 is None:
@@ -142,12 +148,12 @@ def prox_mixed_dual(s, lam_bar, reg, pinv, pinv_norm, n_inner, q0=None,
     R = Q.copy()
     tau = 1.0
     for _ in range(n_inner):
-        x = s - lam_bar * pinv(reg_Lt(R, reg))
+        x = xq(s - lam_bar * pinv(reg_Lt(R, reg)))
         Qn = project_dual_ball(R + step * reg_L(x, reg), reg)
         tau_n = (1.0 + np.sqrt(1.0 + 4.0 * tau * tau)) / 2.0
         R = Qn + ((tau - 1.0) / tau_n) * (Qn - Q)
         Q, tau = Qn, tau_n
-    x = s - lam_bar * pinv(reg_Lt(Q, reg))
+    x = xq(s - lam_bar * pinv(reg_Lt(Q, reg)))
     return x, Q
 
 
@@ -168,6 +174,51 @@ def dual_gap(s, x_of_q, Q, lam_bar, reg, p_apply, pinv):
 def soft(z, t):
     """prox of t ||.||_1: sign(z) max(|z| - t, 0)."""
     return np.sign(z) * np.maximum(np.abs(z) - t, 0.0)
+
+
+def constrained_gap(x_of_q, Q, lam_bar, reg):
+    """Primal minus dual value of the constrained WPM at Q, with x(Q) the
+    minimiser of the Lagrangian over C (eq. (20)): lam_bar (||L x||_{1,phi}
+    - <Q, L x>), nonnegative for Q in the dual ball."""
+    return lam_bar * (reg_value(x_of_q, reg) - ops.pair(Q, reg_L(x_of_q, reg), reg))
+
+
+def prox_box_weighted(z, lo, hi, U, e, gamma0=None, tol=1e-12, maxit=100,
+                      max_halvings=30):
+    """prox^P_{delta_C}(z) for the box C = {lo <= x <= hi}, P = I + U^T
+    diag(e) U: Thm. 1 with h = delta_C, whose unweighted prox is the clip:
+    gamma solves F(gamma) = gamma - diag(e) U (clip(z - U^T gamma) - z) = 0,
+    semismooth Newton with the Jacobian I + diag(e) U D U^T, D the pixels
+    strictly inside the box, and backtracking on ||F||.
+    Returns (x, gamma, newton_steps)."""
+    K = U.shape[0]
+    gamma = np.zeros(K) if gamma0 is None else np.array(gamma0, np.float64)
+    if K == 0:
+        return np.clip(z, lo, hi), gamma, 0
+
+    def F(g):
+        r = z - g @ U
+        return g - e * (U @ (np.clip(r, lo, hi) - z)), r
+
+    Fg, r = F(gamma)
+    steps = 0
+    for steps in range(maxit):
+        nF = np.linalg.norm(Fg)
+        if nF <= tol * (1.0 + np.linalg.norm(gamma)):
+            break
+        active = (r > lo) & (r < hi)
+        Ua = U[:, active]
+        J = np.eye(K) + e[:, None] * (Ua @ Ua.T)
+        delta = np.linalg.solve(J, -Fg)
+        t = 1.0
+        for _ in range(max_halvings):
+            g_try = gamma + t * delta
+            F_try, r_try = F(g_try)
+            if np.linalg.norm(F_try) <= (1.0 - 1e-4 * t) * nF:
+                break
+            t *= 0.5
+        gamma, Fg, r = g_try, F_try, r_try
+    return np.clip(z - gamma @ U, lo, hi), gamma, steps
 
 
 def prox_l1_weighted(s, lam_bar, U, e, gamma0=None, tol=1e-12, maxit=100,

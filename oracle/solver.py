@@ -36,6 +36,7 @@ class Problem:
     levels: int = 0              # Haar levels of the reparametrisation
     loss: str = "ls"
     delta: float = 0.0
+    box: Optional[tuple] = None  # (lo, hi): x restricted to C = {lo <= x <= hi}
 
     # A and A^T of the (possibly reparametrised) problem
     def A(self, x):
@@ -174,8 +175,18 @@ def wapg(problem: Problem, pc: Optional[Precond], alpha: float, outer: int,
                     gamma if warm_start else None, ssn_tol, ssn_maxit)
                 x_new = xv.reshape(n, n)
         else:
+            proj_c = None
+            if problem.box is not None:
+                lo, hi = problem.box
+                if pc is None:
+                    proj_c = lambda z: np.clip(z, lo, hi)
+                else:
+                    proj_c = lambda z: px.prox_box_weighted(
+                        z.reshape(-1), lo, hi, pc.U, pc.e, None, ssn_tol,
+                        ssn_maxit)[0].reshape(z.shape)
             x_new, Q = px.prox_mixed_dual(s, lam_bar, problem.reg, pinv, pnorm,
-                                          inner, Q if warm_start else None)
+                                          inner, Q if warm_start else None,
+                                          proj_c=proj_c)
         t = (1.0 + np.sqrt(1.0 + 4.0 * t_prev * t_prev)) / 2.0
         u = x_new + ((t_prev - 1.0) / t) * (x_new - x)
         x, t_prev = x_new, t

@@ -128,6 +128,73 @@ def test_schatten_dual_ball_projection_is_the_nearest_point(reg, ordn):
                 assert np.allclose(got, best.x, atol=1e-6)
 
 
+# --- constraint sets C != R^N (a box) ---------------------------------------
+
+def test_box_projection_in_the_p_metric_matches_a_bound_constrained_qp():
+    # prox^P_{delta_C}(z) = argmin_{lo <= x <= hi} 1/2 (x - z)^T P (x - z),
+    # by Thm. 1's Newton iteration, against L-BFGS-B on the same QP
+    from scipy.optimize import minimize
+    N, K = 40, 5
+    rng = np.random.default_rng(21)
+    U = np.linalg.qr(rng.standard_normal((N, K)))[0].T
+    for e in (np.array([3.0, 1.5, 0.8, -0.4, -0.7]), np.linspace(5.0, 0.1, K)):
+        P = np.eye(N) + U.T @ (e[:, None] * U)
+        for lo, hi, sc in ((0.0, np.inf, 1.0), (-0.3, 0.5, 1.0), (-1.0, 1.0, 3.0)):
+            z = rng.standard_normal(N) * sc
+            x, gamma, _ = px.prox_box_weighted(z, lo, hi, U, e)
+            r = minimize(lambda v: 0.5 * (v - z) @ P @ (v - z), np.clip(z, lo, hi),
+                         jac=lambda v: P @ (v - z), method="L-BFGS-B",
+                         bounds=[(lo, None if np.isinf(hi) else hi)] * N,
+                         options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 20000})
+            assert np.all(x >= lo - 1e-15) and np.all(x <= hi + 1e-15)
+            assert np.allclose(x, r.x, atol=1e-6), (lo, hi, np.abs(x - r.x).max())
+
+
+def test_box_projection_with_identity_metric_is_the_clip():
+    z = W.gaussian((50,), 31) * 2
+    x, _, _ = px.prox_box_weighted(z, -0.5, 0.25, np.zeros((0, 50)), np.zeros(0))
+    assert np.array_equal(x, np.clip(z, -0.5, 0.25))
+
+
+def test_constrained_dual_prox_matches_smoothed_primal_and_its_gap_vanishes():
+    # argmin_{x >= 0} 1/2||x - s||_P^2 + lam_bar TV(x) on a 6 x 6 image: the
+    # dual iteration with x(Q) = prox^P_{delta_C}(.) against L-BFGS-B with the
+    # bound on the primal with TV smoothed by eps (error O(eps))
+    from scipy.optimize import minimize
+    from oracle import operators as ops
+    n, lam_bar, lo, eps = 6, 0.15, 0.0, 1e-7
+    s = W.gaussian((n, n), 41)
+    pc = _small_precond(n * n, 4, 2)
+    proj = lambda z: px.prox_box_weighted(z.reshape(-1), lo, np.inf, pc.U, pc.e)[0].reshape(z.shape)
+    x, Q = px.prox_mixed_dual(s, lam_bar, "tv", pc.pinv, pc.pinv_norm, 4000, proj_c=proj)
+    assert np.all(x >= lo - 1e-12)
+    gap = px.constrained_gap(x, Q, lam_bar, "tv")
+    assert -1e-10 <= gap < 1e-6
+
+    def obj(v):
+        xx = v.reshape(n, n)
+        d = xx - s
+        g = ops.grad(xx)
+        t = np.sqrt(g[0] ** 2 + g[1] ** 2 + eps * eps)
+        val = 0.5 * np.sum(d * pc.p(d)) + lam_bar * np.sum(t)
+        grad = pc.p(d) + lam_bar * ops.grad_adjoint(g / t[None])
+        return val, grad.reshape(-1)
+    r = minimize(obj, np.maximum(s, 0).reshape(-1), jac=True, method="L-BFGS-B",
+                 bounds=[(lo, None)] * (n * n),
+                 options={"ftol": 1e-16, "gtol": 1e-11, "maxiter": 50000, "maxcor": 50})
+    assert np.allclose(x.reshape(-1), r.x, atol=2e-4), np.abs(x.reshape(-1) - r.x).max()
+
+
+def test_constrained_dual_prox_tiny_lambda_is_the_weighted_projection():
+    n = 7
+    s = W.gaussian((n, n), 43)
+    pc = _small_precond(n * n, 4, 3)
+    proj = lambda z: px.prox_box_weighted(z.reshape(-1), 0.0, np.inf, pc.U, pc.e)[0].reshape(z.shape)
+    x, _ = px.prox_mixed_dual(s, 1e-12, "tv", pc.pinv, pc.pinv_norm, 5, proj_c=proj)
+    assert np.allclose(x, proj(s), atol=1e-10)
+    assert not np.allclose(proj(s), np.clip(s, 0, None))   # the metric matters
+
+
 # --- l1 prox with the diagonal-plus-low-rank metric (Thm. 1) ---------------
 
 def _prox_l1_brute(s, lam_bar, P, iters=20000):
@@ -232,6 +299,27 @@ def test_wapg_rate_bound_and_same_optimum_with_and_without_precond():
     kp = np.argmax(costs_p - Fstar <= 1e-6 * Fstar)
     k0 = np.argmax(costs - Fstar <= 1e-6 * Fstar)
     assert kp < k0
+
+
+def test_wapg_with_nonnegativity_reaches_the_same_feasible_optimum_with_and_without_precond():
+    # C = {x >= 0}: every iterate is feasible, and the plain and the
+    # preconditioned method (P-weighted projection inside the dual iteration)
+    # approach the same constrained optimum
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=5, n=16)
+    prob.box = (0.0, np.inf)
+    n = prob.n
+    L = sv.lipschitz(prob, None, W.gaussian((n, n), 14), 200)
+    x, costs = sv.wapg(prob, None, 1.0 / (1.01 * L), 400, inner=30)
+    pc, _ = sv.build_precond(prob, W.omega(12, n, n, 16), tail="plain")
+    Lp = sv.lipschitz(prob, pc, W.gaussian((n, n), 14), 200)
+    xp, costs_p = sv.wapg(prob, pc, 1.0 / (1.01 * Lp), 400, inner=30)
+    assert x.min() >= 0.0 and xp.min() >= 0.0
+    assert abs(costs[-1] - costs_p[-1]) < 1e-5 * costs[-1]
+    assert np.allclose(x, xp, atol=1e-2 * np.abs(x).max())   # TV optima are flat in places
+    # the unconstrained optimum violates the bound here, so C is active
+    xu, _ = sv.wapg(sv.problem_from_workload(wl, seed=5, n=16)[0], None, 1.0 / (1.01 * L), 400, inner=30)
+    assert xu.min() < -1e-3
 
 
 def test_wapg_tv_decreases_cost():
