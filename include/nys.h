@@ -189,6 +189,13 @@ typedef struct {
   int32_t n_inner;     /* dual iterations (TV and Hessian kinds) */
   int32_t max_newton;  /* SSN trial points (L1); <= 0: 60 */
   double newton_tol;   /* ||F|| <= tol (1 + ||gamma||); <= 0: 1e-12 / 1e-6 */
+  int32_t box;         /* != 0: x restricted to C = {lo <= x_i <= hi} (TV and
+                          Hessian kinds only): x(Q) = prox^P_{delta_C}(s -
+                          lambda_bar P^{-1} L^T Q) in every dual iteration
+                          (eqs. (20)-(22)), the P-weighted projection by Thm. 1
+                          with the clip in place of the soft threshold (the
+                          clip itself when P = I); 0: C = R^N */
+  double lo, hi;       /* the box (lo <= hi; hi may be +inf) */
 } nys_reg_desc;
 
 nys_status prox_weighted(const nys_reg_desc* reg, double lambda_bar, nys_pc pc,

@@ -43,7 +43,8 @@ class FactorOpts(C.Structure):
 class RegDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32),
                 ("lnorm2", C.c_double), ("n_inner", C.c_int32), ("max_newton", C.c_int32),
-                ("newton_tol", C.c_double)]
+                ("newton_tol", C.c_double), ("box", C.c_int32), ("lo", C.c_double),
+                ("hi", C.c_double)]
 
 
 class Problem(C.Structure):
@@ -304,10 +305,14 @@ def nys_apply(pc: Preconditioner, v: torch.Tensor, inverse: bool = True,
     return out
 
 
-def reg_desc(kind, n1, n2, n_inner=20, lnorm2=0.0, max_newton=0, newton_tol=0.0) -> RegDesc:
+def reg_desc(kind, n1, n2, n_inner=20, lnorm2=0.0, max_newton=0, newton_tol=0.0,
+             box=None) -> RegDesc:
+    """box = (lo, hi) restricts x to C = {lo <= x <= hi} (TV and Hessian kinds)."""
     if isinstance(kind, str):
         kind = REG_NAMES[kind]
-    return RegDesc(kind, n1, n2, lnorm2, n_inner, max_newton, newton_tol)
+    lo, hi = box if box is not None else (0.0, 0.0)
+    return RegDesc(kind, n1, n2, lnorm2, n_inner, max_newton, newton_tol,
+                   1 if box is not None else 0, float(lo), float(hi))
 
 
 def prox_state(reg: RegDesc, pc: Optional[Preconditioner], dtype) -> Optional[torch.Tensor]:

@@ -157,6 +157,9 @@ struct nys_pc_s {
   // warm-start output of the semismooth Newton call being enqueued (may be
   // null): the decision that ends the iteration writes the root there
   double* ssn_gout = nullptr;
+  // h of that call: soft threshold (0) or the clip to [lo, hi] (1)
+  int ssn_box = 0;
+  double ssn_lo = 0.0, ssn_hi = 0.0;
   // the FP32 semismooth Newton workspace holds LU factors of a Jacobian of
   // this preconditioner (cleared whenever the factorisation is redone or the
   // workspace is reallocated)

@@ -75,10 +75,24 @@ struct SsnStep {
 // (ell FP64, may be null) is the warm start and receives the root.  With
 // `step`, s is an output buffer: the step is formed into it (by the first
 // evaluation pass where possible).
+// With `box`, h is the indicator of C = {lo <= x <= hi} instead of
+// lam_bar ||.||_1 (lam_bar unused): x = prox^P_{delta_C}(s), the P-weighted
+// projection onto the box, by the same iteration with the clip in place of
+// the soft threshold.
+struct SsnBox {
+  double lo, hi;
+};
+// A box constraint needs a TV or Hessian prior and lo <= hi (not NaN).
+inline nys_status check_box(const nys_reg_desc& r) {
+  if (!r.box) return NYS_OK;
+  NYS_REQUIRE(r.kind != NYS_REG_L1, "box constraint: needs a TV or Hessian prior");
+  NYS_REQUIRE(r.lo <= r.hi, "box constraint: lo must be <= hi");
+  return NYS_OK;
+}
 template <class T>
 nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
                     double* gamma_state, hipStream_t st, int* trials_out = nullptr,
-                    const SsnStep* step = nullptr);
+                    const SsnStep* step = nullptr, const SsnBox* box = nullptr);
 
 // Layout of the FP64 metadata block of a preconditioner (pc->meta).
 struct PcMeta {

@@ -500,6 +500,19 @@ constexpr int kGramSets = 4;
 // Row pitch (floats) of the stored Jacobian inverse (64 x 64).
 constexpr int kLuPitch = 64;
 
+// The unweighted prox of Thm. 1's h and its derivative pattern: the soft
+// threshold at lam (h = lam ||.||_1; D: |r| > lam) or, with box, the clip to
+// [lo, hi] (h the indicator of the box C; D: lo < r < hi).
+template <class T>
+__device__ __forceinline__ T ssn_h_prox(T r, T lam, int box, T lo, T hi) {
+  if (box) return fmin(hi, fmax(lo, r));
+  return fabs(r) > lam ? (r > T(0) ? r - lam : r + lam) : T(0);
+}
+template <class T>
+__device__ __forceinline__ bool ssn_h_active(T r, T lam, int box, T lo, T hi) {
+  return box ? (r > lo && r < hi) : fabs(r) > lam;
+}
+
 // Evaluation at the trial point in one pass over U: r = s - U g, x = soft(r)
 // (to xo, if given), mask = |r| > lam (if given), partial U^T (x - s) per
 // block.
@@ -510,7 +523,7 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
                                                        const double* __restrict__ state,
                                                        uint8_t* __restrict__ mask,
                                                        double* __restrict__ part,
-                                                       T* __restrict__ xo) {
+                                                       T* __restrict__ xo, int box, T lo, T hi) {
   __shared__ double red[8 * LP];
   __shared__ double bsum[LP];
   __shared__ T g[LP];
@@ -539,10 +552,9 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
       ug += u[k] * g[k];
     }
     const T r = s[n] - ug;
-    const T ar = fabs(r);
-    const T xv = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
+    const T xv = ssn_h_prox(r, lam, box, lo, hi);
     const T d = xv - s[n];
-    if (mask != nullptr) mask[n] = ar > lam ? 1 : 0;
+    if (mask != nullptr) mask[n] = ssn_h_active(r, lam, box, lo, hi) ? 1 : 0;
     if (xo != nullptr) xo[n] = xv;
 #pragma unroll
     for (int k = 0; k < LP; ++k) acc[k] += u[k] * d;
@@ -864,7 +876,7 @@ template <int NRG>
 __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
     const float* __restrict__ U, int64_t ldu, const float* __restrict__ s, int64_t N, int L,
     int64_t chunk, float lam, const double* __restrict__ state, double* __restrict__ part,
-    float* __restrict__ gpart, float* __restrict__ xo, int gsrc) {
+    float* __restrict__ gpart, float* __restrict__ xo, int gsrc, int box, float lo, float hi) {
   constexpr int W = evg_waves<NRG>();
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   constexpr int ROWS = 32 * NRG;
@@ -913,13 +925,12 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
 #pragma unroll
     for (int k = 0; k < ROWS; ++k) pr += u[k] * gs[k];
     const float r = sv - pr;
-    const float ar = fabsf(r);
-    const float xv = ar > lam ? (r > 0.f ? r - lam : r + lam) : 0.f;
+    const float xv = ssn_h_prox(r, lam, box, lo, hi);
     if (in && xo != nullptr) xo[px] = xv;
 #pragma unroll
     for (int k = 0; k < ROWS; ++k) ws[k * PP + lane] = u[k];
     dw[wave][lane] = in ? xv - sv : 0.f;
-    mw[wave][lane] = (in && ar > lam) ? 1.f : 0.f;
+    mw[wave][lane] = (in && ssn_h_active(r, lam, box, lo, hi)) ? 1.f : 0.f;
     if (t + W < nst) load(t + W);
     // masked Gram: 4 steps of 16 pixels; lane l supplies row 32 g + l % 32,
     // pixels 16 kk + 8 (l / 32) + 0..7
@@ -1461,7 +1472,8 @@ template <class T>
 __global__ __launch_bounds__(256) void ssn_final_kernel(const T* __restrict__ U, int64_t ldu,
                                                         const T* __restrict__ s,
                                                         const double* __restrict__ state,
-                                                        int64_t N, int L, T lam, T* __restrict__ x) {
+                                                        int64_t N, int L, T lam, T* __restrict__ x,
+                                                        int box, T lo, T hi) {
   __shared__ T g[PcMeta::kMaxEll];
   for (int k = threadIdx.x; k < L; k += blockDim.x) g[k] = static_cast<T>(state[SsnState::kGamma + k]);
   __syncthreads();
@@ -1470,8 +1482,7 @@ __global__ __launch_bounds__(256) void ssn_final_kernel(const T* __restrict__ U,
   T ug = 0;
   for (int k = 0; k < L; ++k) ug += U[static_cast<size_t>(k) * ldu + n] * g[k];
   const T r = s[n] - ug;
-  const T ar = fabs(r);
-  x[n] = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
+  x[n] = ssn_h_prox(r, lam, box, lo, hi);
 }
 
 // Initialise the Newton state from the warm start gamma (g_try = gamma).
@@ -1501,7 +1512,8 @@ template <class T, int ROWS>
 static void launch_ssn_eval(nys_pc pc, const T* s, T lam, double* state, uint8_t* mask,
                             double* part, int nblk, int64_t chunk, T* xo, hipStream_t st) {
   hipLaunchKernelGGL((ssn_eval_kernel<T, ROWS>), dim3(nblk), dim3(512), 0, st, pc->U.as<T>(),
-                     pc->ldu, s, pc->N, static_cast<int>(pc->ell), chunk, lam, state, mask, part, xo);
+                     pc->ldu, s, pc->N, static_cast<int>(pc->ell), chunk, lam, state, mask, part, xo,
+                     pc->ssn_box, static_cast<T>(pc->ssn_lo), static_cast<T>(pc->ssn_hi));
 }
 
 template <class T>
@@ -1589,7 +1601,8 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(elds));
   hipLaunchKernelGGL((ssn_evalgram_kernel<NRG>), dim3(nblk), dim3(64 * evg_waves<NRG>()), elds, st,
                      pc->U.as<float>(), pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part, x,
-                     static_cast<int>(newton_at_gamma ? SsnState::kGamma : SsnState::kTry));
+                     static_cast<int>(newton_at_gamma ? SsnState::kGamma : SsnState::kTry),
+                     pc->ssn_box, static_cast<float>(pc->ssn_lo), static_cast<float>(pc->ssn_hi));
   NYS_TRY(launch_check("ssn_evalgram_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
   const int with_decide = newton_at_gamma ? 0 : 1;
@@ -1637,7 +1650,12 @@ static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool&
 
 template <class T>
 nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    double* gamma_state, hipStream_t st, int* trials_out, const SsnStep* step) {
+                    double* gamma_state, hipStream_t st, int* trials_out, const SsnStep* step,
+                    const SsnBox* box) {
+  NYS_REQUIRE(!(box && step), "ssn_prox: a box projection has no gradient step");
+  pc->ssn_box = box ? 1 : 0;   // read by the launchers of this call
+  pc->ssn_lo = box ? box->lo : 0.0;
+  pc->ssn_hi = box ? box->hi : 0.0;
   const int64_t N = pc->N;
   const int L = static_cast<int>(pc->ell);
   int nblk;
@@ -1793,7 +1811,8 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   // the iteration stopped there (accepted and converged), x is the prox
   if (!(sizeof(T) == 4 && done && xf != nullptr)) {
     hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, pc->U.as<T>(),
-                       pc->ldu, s, state, N, L, lam, x);
+                       pc->ldu, s, state, N, L, lam, x, pc->ssn_box, static_cast<T>(pc->ssn_lo),
+                       static_cast<T>(pc->ssn_hi));
     NYS_TRY(launch_check("ssn_final_kernel"));
   }
   pc->ssn_gout = nullptr;
@@ -1805,8 +1824,8 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
 }
 
 template nys_status ssn_prox<double>(const nys_reg_desc&, double, nys_pc, const double*, double*,
-                                     double*, hipStream_t, int*, const SsnStep*);
+                                     double*, hipStream_t, int*, const SsnStep*, const SsnBox*);
 template nys_status ssn_prox<float>(const nys_reg_desc&, double, nys_pc, const float*, float*,
-                                    double*, hipStream_t, int*, const SsnStep*);
+                                    double*, hipStream_t, int*, const SsnStep*, const SsnBox*);
 
 }  // namespace nys

@@ -1,4 +1,4 @@
-// P-weighted proximal maps (definition in Sec. I-D, C = R^N).
+// P-weighted proximal maps (definition in Sec. I-D; C = R^N or a box).
 //
 // TV / TV_ANISO / Hessian Schatten kinds: accelerated projected gradient on the dual variable Q
 // (eqs. (17)-(22)): each inner iteration computes t = L^T R, applies P^{-1},
@@ -50,9 +50,32 @@ nys_status fill_zero(T* p, size_t n, hipStream_t st) {
   return launch_check("zero_kernel");
 }
 
+// x = clip(x, lo, hi)
+template <class T>
+__global__ void clip_kernel(T* __restrict__ x, T lo, T hi, int64_t N) {
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (n >= N) return;
+  x[n] = fmin(hi, fmax(lo, x[n]));
+}
+
+// x <- prox^P_{delta_C}(x) for the box of reg (eq. (21)): the clip for P = I,
+// else Thm. 1's semismooth Newton with the clip, warm-started from gbox
+template <class T>
+static nys_status project_box(const nys_reg_desc& reg, nys_pc pc, T* x, double* gbox,
+                              hipStream_t st) {
+  const int64_t N = static_cast<int64_t>(reg.n1) * reg.n2;
+  if (!pc) {
+    hipLaunchKernelGGL((clip_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, x,
+                       static_cast<T>(reg.lo), static_cast<T>(reg.hi), N);
+    return launch_check("clip_kernel");
+  }
+  const SsnBox b{reg.lo, reg.hi};
+  return ssn_prox<T>(reg, 0.0, pc, x, x, gbox, st, nullptr, nullptr, &b);
+}
+
 template <class T>
 static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                            T* Q, T* R, T* tbuf, double* cd, hipStream_t st) {
+                            T* Q, T* R, T* tbuf, double* cd, double* gbox, hipStream_t st) {
   const int n1 = reg.n1, n2 = reg.n2;
   const int64_t N = static_cast<int64_t>(n1) * n2;
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
@@ -70,6 +93,7 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
   const double step = 1.0 / (lam_bar * lnorm2 * pinv_norm);
   dim3 g2(cdiv(n2, 64), cdiv(n1, 4));
   NYS_CHECK_HIP(hipMemcpyAsync(R, Q, sizeof(T) * nch * N, hipMemcpyDeviceToDevice, st));
+  if (reg.box && pc) NYS_TRY(fill_zero<double>(gbox, PcMeta::kMaxEll, st));
   const int L = pc ? static_cast<int>(pc->ell) : 0;
   double tau = 1.0;
   for (int it = 0; it <= reg.n_inner; ++it) {
@@ -86,6 +110,8 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
       NYS_TRY(pc_coeffs<T>(pc, true, tbuf, 1, cd, st));
       NYS_TRY(pc_x_from_pinv<T>(pc, s, tbuf, cd, lam_bar, x, st));
     }
+    // x(Q) = prox^P_{delta_C}(s - lam_bar P^{-1} L^T Q) for a box C
+    if (reg.box) NYS_TRY(project_box<T>(reg, pc, x, gbox, st));
     if (last) break;
     double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
     double beta = (tau - 1.0) / tau_n;
@@ -110,7 +136,7 @@ template <class T>
 size_t prox_ws_bytes(const nys_reg_desc& reg) {
   const size_t N = static_cast<size_t>(reg.n1) * reg.n2;
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
-  return sizeof(double) * PcMeta::kMaxEll + sizeof(T) * (static_cast<size_t>(nch) * N * 2 + N) + 256;
+  return sizeof(double) * 2 * PcMeta::kMaxEll + sizeof(T) * (static_cast<size_t>(nch) * N * 2 + N) + 256;
 }
 
 template <class T>
@@ -126,8 +152,8 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     return ssn_prox<T>(reg, lam_bar, pc, s, x, static_cast<double*>(state), st);
   }
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
-  // work: [cd: kMaxEll doubles | R | Q (when no state) | t]; the caller's
-  // buffer of prox_ws_bytes, else a per-thread one
+  // work: [cd, gbox: kMaxEll doubles each | R | Q (when no state) | t]; the
+  // caller's buffer of prox_ws_bytes, else a per-thread one
   static thread_local DevBuf fallback;
   char* base = static_cast<char*>(work);
   if (!base) {
@@ -135,11 +161,12 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     base = static_cast<char*>(fallback.p);
   }
   double* cd = reinterpret_cast<double*>(base);
-  T* R = reinterpret_cast<T*>(cd + PcMeta::kMaxEll);
+  double* gbox = cd + PcMeta::kMaxEll;
+  T* R = reinterpret_cast<T*>(gbox + PcMeta::kMaxEll);
   T* Q = state ? static_cast<T*>(state) : R + static_cast<size_t>(nch) * N;
   T* tbuf = R + static_cast<size_t>(nch) * N * 2;
   if (!state) NYS_TRY(fill_zero<T>(Q, static_cast<size_t>(nch) * N, st));
-  return dual_prox<T>(reg, lam_bar, pc, s, x, Q, R, tbuf, cd, st);
+  return dual_prox<T>(reg, lam_bar, pc, s, x, Q, R, tbuf, cd, gbox, st);
 }
 
 template nys_status prox_run<double>(const nys_reg_desc&, double, nys_pc, const double*, double*,
@@ -165,6 +192,7 @@ static nys_status check_reg(const nys_reg_desc* reg, nys_pc pc, nys_dtype dt) {
     NYS_REQUIRE(pc->u_dtype == static_cast<int32_t>(dt), "pc u_dtype != prox dtype");
   }
   if (reg->kind != NYS_REG_L1) NYS_REQUIRE(reg->n_inner >= 0, "n_inner must be >= 0");
+  NYS_TRY(check_box(*reg));
   return NYS_OK;
 }
 

@@ -354,6 +354,7 @@ static nys_status check_problem(const nys_problem* p, nys_dtype dt) {
   NYS_REQUIRE(p->loss == NYS_LOSS_LS || (p->loss == NYS_LOSS_HUBER && p->delta > 0),
               "solve: bad loss / delta");
   NYS_REQUIRE(p->lambda >= 0, "solve: lambda < 0");
+  NYS_TRY(check_box(p->reg));
   return NYS_OK;
 }
 

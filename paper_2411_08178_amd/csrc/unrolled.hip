@@ -449,6 +449,7 @@ static nys_status check_unroll(const nys_problem* p, nys_pc pc, nys_dtype dt,
   NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "unrolled: dtype must be F64 or F32");
   NYS_REQUIRE(p->reg.kind == NYS_REG_TV || p->reg.kind == NYS_REG_TV_ANISO,
               "unrolled: regulariser must be TV or anisotropic TV");
+  NYS_REQUIRE(!p->reg.box, "unrolled: no box constraint");
   NYS_REQUIRE(static_cast<int64_t>(p->reg.n1) * p->reg.n2 == p->op->N,
               "unrolled: regulariser size != number of unknowns");
   NYS_REQUIRE(p->loss == NYS_LOSS_LS, "unrolled: least-squares data term only");

@@ -133,6 +133,44 @@ def test_prox_dual(reg, dt, with_pc):
     assert rel(host(x2), xr2) < TOL[dt] * 10
 
 
+@pytest.mark.parametrize("reg,dt,with_pc,box", [("tv", "f64", True, (0.0, np.inf)),
+                                                ("tv", "f32", True, (0.0, np.inf)),
+                                                ("hs1", "f64", True, (-0.2, 0.3)),
+                                                ("tv", "f32", False, (-0.1, 0.4))])
+def test_prox_dual_box(reg, dt, with_pc, box):
+    """C = {lo <= x <= hi}: x(Q) = prox^P_{delta_C}(.) in every dual iteration
+    (the P-weighted projection by the semismooth Newton method with the clip)."""
+    P = need_gpu()
+    banner(f"prox dual box {reg} {dt} pc={with_pc} box={box}")
+    n1 = n2 = 29
+    prob, om, Y = _blur_case(n1, 6)
+    s = W.gaussian((n1, n2), 17) * 0.5
+    lam_bar = 0.05
+    sd = dev(s, dt)
+    lo, hi = box
+    if with_pc:
+        omd, Yd = dev(om, "f64"), dev(Y, "f64")
+        ref = onys.nystrom(host(Yd).reshape(6, -1), host(omd).reshape(6, -1))
+        opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+        udt = torch.float64 if dt == "f64" else torch.float32
+        pc = P.nys_factor(omd, Yd, 6, u_dtype=udt)
+        pinv, pnorm = opc.pinv, opc.pinv_norm
+        proj = lambda z: opx.prox_box_weighted(z.reshape(-1), lo, hi, opc.U, opc.e)[0].reshape(z.shape)
+    else:
+        pc, pinv, pnorm = None, (lambda v: v), 1.0
+        proj = lambda z: np.clip(z, lo, hi)
+    rd = P.reg_desc(reg, n1, n2, n_inner=25, box=box)
+    state = P.prox_state(rd, pc, sd.dtype)
+    x = P.prox_weighted(rd, lam_bar, pc, sd, state)
+    xr, Q = opx.prox_mixed_dual(host(sd), lam_bar, reg, pinv, pnorm, 25, proj_c=proj)
+    xh = host(x)
+    assert xh.min() >= lo - 1e-6 and xh.max() <= hi + 1e-6
+    assert rel(xh, xr) < TOL[dt] * 10
+    # the box is active: the unconstrained prox leaves it
+    xu, _ = opx.prox_mixed_dual(host(sd), lam_bar, reg, pinv, pnorm, 25)
+    assert xu.min() < lo - 1e-3 or xu.max() > hi + 1e-3
+
+
 # ell = 8 and 40 / 64 take the register eliminations sized 32 and 64 (40: a
 # ragged last group of columns), ell = 100 the elimination of the whole block;
 # the plain tail gives e up to s_1 / s_ell - 1 >> 1, the sqrt tail e < 0
@@ -240,6 +278,33 @@ def _solve_pair(P, prob_kind, dt, with_pc, iters):
     x, costs, info = P.solve(op, yd, rd, lam, pc, iters, alpha=alpha, loss=loss, delta=delta)
     xr, cr = sv.wapg(prob, opc, alpha, iters, inner=10)
     return host(x), host(costs), xr, cr
+
+
+def test_solve_nonnegative_matches_oracle():
+    """WAPG (Alg. 3) with C = {x >= 0} and the P-weighted projection inside the
+    dual iterations, against the oracle's iterates and costs."""
+    P = need_gpu()
+    banner("solve deblur tv nonneg f64 pc")
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=2, n=40)
+    prob.box = (0.0, np.inf)
+    op = P.Operator(P.OP_BLUR, 40, 40, psf=prob.h)
+    n, ell, iters = prob.n, 8, 12
+    yd = dev(prob.y, "f64")
+    om = W.omega(ell, n, n, 20)
+    omd = dev(om, "f64")
+    Yref = sv.sketch(prob, host(omd))
+    Yd = dev(Yref, "f64")
+    ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+    pc = P.nys_factor(omd, Yd, ell, u_dtype=torch.float64)
+    alpha = 0.9 / sv.lipschitz(prob, opc, W.gaussian((n, n), 21), 200)
+    rd = P.reg_desc("tv", n, n, n_inner=10, box=(0.0, np.inf))
+    x, costs, info = P.solve(op, yd, rd, prob.lam, pc, iters, alpha=alpha, loss=P.LOSS_LS, delta=0.0)
+    xr, cr = sv.wapg(prob, opc, alpha, iters, inner=10)
+    assert host(x).min() >= 0.0
+    assert rel(host(x), xr) < 1e-8
+    assert np.max(np.abs(host(costs) - cr) / np.abs(cr)) < 1e-8
 
 
 @pytest.mark.parametrize("kind,dt,with_pc", [("deblur_tv", "f64", False), ("deblur_tv", "f64", True),
