@@ -110,6 +110,87 @@ def haar_synthesis(w: np.ndarray, levels: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Daubechies-4 wavelets (8 taps, 4 vanishing moments), periodised, in the
+# quadrant (Mallat) layout: level j works on the top-left (n/2^j) x (n/2^j)
+# band, rows then columns, leaving [LL | HL ; LH | HH] there.
+
+def daubechies_filter(p: int = 4) -> np.ndarray:
+    """The minimum-phase Daubechies scaling filter with p vanishing moments
+    (2p taps), by spectral factorisation: |H|^2 = 2 cos^{2p}(w/2) Q(sin^2(w/2))
+    with Q(y) = sum_{k<p} C(p-1+k, k) y^k; each root y of Q gives the pair
+    z, 1/z of z^2 - (2 - 4y) z + 1 = 0, and the root inside the unit circle is
+    kept; h(z) is proportional to (z + 1)^p prod (z - z_j), normalised to a
+    sum of sqrt(2) (coefficients from the highest power down)."""
+    from math import comb
+    q = [comb(p - 1 + k, k) for k in range(p)]
+    zs = []
+    for y in np.roots(q[::-1]):
+        b = 1.0 - 2.0 * y
+        disc = np.sqrt(b * b - 1.0 + 0j)
+        z1, z2 = b + disc, b - disc
+        zs.append(z1 if abs(z1) < 1.0 else z2)
+    poly = np.array([1.0 + 0j])
+    for _ in range(p):
+        poly = np.convolve(poly, [1.0, 1.0])
+    for z in zs:
+        poly = np.convolve(poly, [1.0, -z])
+    h = np.real(poly)
+    return h * (np.sqrt(2.0) / h.sum())
+
+
+def _qmf(h):
+    """Wavelet filter g_k = (-1)^k h_{L-1-k}."""
+    L = len(h)
+    return np.array([(-1) ** k * h[L - 1 - k] for k in range(L)])
+
+
+def _dwt1_matrix(m: int, h) -> np.ndarray:
+    """The m x m periodised one-level analysis: rows i < m/2 give
+    a_i = sum_k h_k x[(2i + k) mod m], rows m/2 + i give d_i with g."""
+    g = _qmf(h)
+    W = np.zeros((m, m))
+    for i in range(m // 2):
+        for k in range(len(h)):
+            W[i, (2 * i + k) % m] += h[k]
+            W[m // 2 + i, (2 * i + k) % m] += g[k]
+    return W
+
+
+def db4_analysis(x: np.ndarray, levels: int) -> np.ndarray:
+    """W x: `levels` levels of the 2-D periodised Daubechies-4 transform."""
+    h = daubechies_filter(4)
+    y = np.array(x, dtype=np.float64, copy=True)
+    m1, m2 = y.shape[-2], y.shape[-1]
+    for _ in range(levels):
+        Wr, Wc = _dwt1_matrix(m2, h), _dwt1_matrix(m1, h)
+        band = y[..., :m1, :m2]
+        y[..., :m1, :m2] = Wc @ (band @ Wr.T)
+        m1, m2 = m1 // 2, m2 // 2
+    return y
+
+
+def db4_synthesis(w: np.ndarray, levels: int) -> np.ndarray:
+    """W^T w: the inverse of db4_analysis (coarsest level first)."""
+    h = daubechies_filter(4)
+    y = np.array(w, dtype=np.float64, copy=True)
+    n1, n2 = y.shape[-2], y.shape[-1]
+    for lev in reversed(range(levels)):
+        m1, m2 = n1 >> lev, n2 >> lev
+        Wr, Wc = _dwt1_matrix(m2, h), _dwt1_matrix(m1, h)
+        band = y[..., :m1, :m2]
+        y[..., :m1, :m2] = Wc.T @ (band @ Wr)
+    return y
+
+
+def wavelet_analysis(x, levels, kind="haar"):
+    return haar_analysis(x, levels) if kind == "haar" else db4_analysis(x, levels)
+
+
+def wavelet_synthesis(w, levels, kind="haar"):
+    return haar_synthesis(w, levels) if kind == "haar" else db4_synthesis(w, levels)
+
+
+# --------------------------------------------------------------------------
 # parallel-beam Joseph projector
 
 def _joseph_view(n: int, n_bins: int, theta: float):

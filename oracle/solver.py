@@ -33,7 +33,8 @@ class Problem:
     factor: int = 1
     views: int = 0
     bins: int = 0
-    levels: int = 0              # Haar levels of the reparametrisation
+    levels: int = 0              # wavelet levels of the reparametrisation
+    wavelet: str = "haar"        # 'haar' | 'db4' (periodised Daubechies-4)
     loss: str = "ls"
     delta: float = 0.0
     box: Optional[tuple] = None  # (lo, hi): x restricted to C = {lo <= x <= hi}
@@ -41,7 +42,7 @@ class Problem:
     # A and A^T of the (possibly reparametrised) problem
     def A(self, x):
         if self.levels:
-            x = ops.haar_synthesis(x, self.levels)
+            x = ops.wavelet_synthesis(x, self.levels, self.wavelet)
         if self.op == "blur":
             return ops.blur(x, self.h)
         if self.op == "blurdown":
@@ -64,7 +65,7 @@ class Problem:
         else:
             raise ValueError(self.op)
         if self.levels:
-            z = ops.haar_analysis(z, self.levels)
+            z = ops.wavelet_analysis(z, self.levels, self.wavelet)
         return z
 
     # data term

@@ -252,3 +252,51 @@ def test_difference_operator_norm_bounds(reg, bound):
         lam = np.linalg.norm(w) / np.linalg.norm(v)
         v = w / np.linalg.norm(w)
     assert lam <= bound and lam > 0.9 * bound - 4
+
+
+# --- Daubechies-4 (next-row wavelet) ---------------------------------------
+
+def test_db4_filter_is_orthonormal_with_four_vanishing_moments_and_minimum_phase():
+    h = ops.daubechies_filter(4)
+    assert len(h) == 8 and abs(h.sum() - np.sqrt(2)) < 1e-14
+    for j in range(4):     # double-shift orthonormality
+        assert abs(sum(h[k] * h[k + 2 * j] for k in range(8 - 2 * j)) - (j == 0)) < 1e-14
+    g = np.array([(-1) ** k * h[7 - k] for k in range(8)])
+    for m in range(4):     # the wavelet filter annihilates polynomials of degree < 4
+        assert abs(sum(k ** m * g[k] for k in range(8))) < 1e-10
+    assert abs(sum(k ** 4 * g[k] for k in range(8))) > 1e-3
+    # minimum phase: apart from the fourfold zero at -1, every zero of
+    # sum_k h_k z^(7-k) lies inside the unit circle, and the energy is front-loaded
+    zeros = np.roots(h)
+    far = zeros[np.abs(zeros + 1) > 1e-2]
+    assert len(far) == 3 and np.all(np.abs(far) < 1)
+    assert h[0] ** 2 + h[1] ** 2 > h[6] ** 2 + h[7] ** 2
+
+
+@pytest.mark.parametrize("shape,levels", [((16, 16), 2), ((32, 16), 3), ((16, 16), 4)])
+def test_db4_transform_is_orthonormal_and_inverted_by_its_transpose(shape, levels):
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(shape)
+    w = ops.db4_analysis(x, levels)
+    assert abs(np.linalg.norm(w) - np.linalg.norm(x)) < 1e-12 * np.linalg.norm(x)
+    assert np.allclose(ops.db4_synthesis(w, levels), x, atol=1e-12)
+    # the dense matrix of the transform is orthogonal, and synthesis is its transpose
+    N = x.size
+    E = np.eye(N).reshape((N,) + shape)
+    M = np.stack([ops.db4_analysis(e, levels).reshape(-1) for e in E], axis=1)
+    assert np.allclose(M @ M.T, np.eye(N), atol=1e-12)
+    z = rng.standard_normal(shape)
+    assert np.allclose(ops.db4_synthesis(z, levels).reshape(-1), M.T @ z.reshape(-1), atol=1e-12)
+
+
+def test_db4_details_vanish_on_cubics():
+    # a cubic in the row index: the first-level detail rows of interior
+    # (non-wrapping) coefficients vanish (four vanishing moments)
+    n = 32
+    t = np.arange(n, dtype=np.float64)
+    x = np.tile((0.3 * t ** 3 - 2 * t ** 2 + t - 5)[:, None], (1, n))
+    w = ops.db4_analysis(x, 1)
+    # column transform: rows n/2 + i hold the details of rows 2i .. 2i + 7
+    interior = [n // 2 + i for i in range(n // 2) if 2 * i + 7 < n]
+    assert np.max(np.abs(w[interior, :n // 2])) < 1e-9 * np.max(np.abs(x))
+    assert np.max(np.abs(w[n // 2 + n // 2 - 1, :n // 2])) > 1.0   # the wrapped one does not
