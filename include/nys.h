@@ -69,10 +69,15 @@ typedef enum { NYS_LOSS_LS = 0, NYS_LOSS_HUBER = 1 } nys_loss_kind;
  *    ray is sampled once per row (|cos| >= |sin|) or per column with linear
  *    interpolation and weight 1/max(|cos|,|sin|) (ray-driven, Joseph).  The
  *    adjoint is the exact transpose, computed in gather form.
- *  wavelet_levels > 0 composes A with Haar synthesis: the unknown is the
- *    coefficient array xbar, x = W^T xbar (invertible-L reparametrisation,
- *    Sec. III-B), in the in-place layout (each level writes LL, HL / LH, HH
- *    at the positions of its 2 x 2 group).
+ *  wavelet_levels > 0 composes A with a wavelet synthesis: the unknown is
+ *    the coefficient array xbar, x = W^T xbar (invertible-L reparametrisation,
+ *    Sec. III-B).  wavelet = NYS_WAVELET_HAAR: orthonormal Haar, 1..3 levels,
+ *    in-place layout (each level writes LL, HL / LH, HH at the positions of
+ *    its 2 x 2 group).  wavelet = NYS_WAVELET_DB4: the periodised orthonormal
+ *    Daubechies wavelet with four vanishing moments (8 taps, the "daub4" of
+ *    the CT experiments), 1..6 levels, quadrant layout (level j transforms the
+ *    top-left (n1 / 2^j) x (n2 / 2^j) band, rows then columns, into
+ *    [LL | HL ; LH | HH]).
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t kind;            /* nys_op_kind */
@@ -81,8 +86,11 @@ typedef struct {
   const double* psf;       /* host, k*k row-major; copied at create */
   int32_t factor;          /* decimation factor (BLURDOWN), >= 1 */
   int32_t n_views, n_bins; /* PARALLEL_BEAM */
-  int32_t wavelet_levels;  /* 0 or Haar levels; n1, n2 divisible by 2^levels */
+  int32_t wavelet_levels;  /* 0 or wavelet levels; n1, n2 divisible by 2^levels */
+  int32_t wavelet;         /* NYS_WAVELET_HAAR (0) or NYS_WAVELET_DB4 (1) */
 } nys_op_desc;
+
+enum { NYS_WAVELET_HAAR = 0, NYS_WAVELET_DB4 = 1 };
 
 typedef struct nys_op_s* nys_op;
 typedef struct nys_pc_s* nys_pc;

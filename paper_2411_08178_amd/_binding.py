@@ -32,7 +32,7 @@ class OpDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32),
                 ("psf_size", C.c_int32), ("psf", C.POINTER(C.c_double)),
                 ("factor", C.c_int32), ("n_views", C.c_int32), ("n_bins", C.c_int32),
-                ("wavelet_levels", C.c_int32)]
+                ("wavelet_levels", C.c_int32), ("wavelet", C.c_int32)]
 
 
 class FactorOpts(C.Structure):
@@ -182,7 +182,7 @@ class Operator:
     """Handle of an operator A (optionally composed with Haar synthesis)."""
 
     def __init__(self, kind: int, n1: int, n2: int, psf=None, factor: int = 1,
-                 views: int = 0, bins: int = 0, wavelet_levels: int = 0):
+                 views: int = 0, bins: int = 0, wavelet_levels: int = 0, wavelet: str = "haar"):
         d = OpDesc()
         d.kind, d.n1, d.n2 = kind, n1, n2
         self._psf = None
@@ -191,6 +191,7 @@ class Operator:
             d.psf_size = self._psf.shape[0]
             d.psf = self._psf.ctypes.data_as(C.POINTER(C.c_double))
         d.factor, d.n_views, d.n_bins, d.wavelet_levels = factor, views, bins, wavelet_levels
+        d.wavelet = {"haar": 0, "db4": 1}[wavelet]
         h = C.c_void_p()
         _check(lib().nys_op_create(C.byref(d), C.byref(h)))
         self.handle = h

@@ -124,8 +124,16 @@ struct OpImpl;  // defined in ops.hip
 }  // namespace nys
 
 // Public handle types.
+// Filters of the periodised Daubechies-4 wavelet: scaling h and wavelet
+// g_k = (-1)^k h_{7-k}, in both precisions (kernel arguments).
+struct Db4Coef {
+  double hd[8], gd[8];
+  float hf[8], gf[8];
+};
+
 struct nys_op_s {
   nys_op_desc d{};
+  Db4Coef db4{};                  // filled when d.wavelet == NYS_WAVELET_DB4
   int64_t N = 0, M = 0;
   std::vector<double> psf;        // k*k row-major
   // psf[a][b] = sep_u[a] * sep_v[b] when sep != 0 (rank-1 PSF, e.g. Gaussian)
@@ -134,6 +142,7 @@ struct nys_op_s {
   nys::DevBuf psf_dev;            // [flipped psf f64 | psf f64 | flipped f32 | psf f32]
   nys::DevBuf trig;               // per view: cos, sin (f64) then (f32)
   nys::DevBuf tmp0, tmp1;         // intermediates of composed operators
+  nys::DevBuf tmp2;               // scratch of the Daubechies-4 passes
   mutable nys::DevBuf xT;         // transposed images (parallel-beam forward)
 };
 

@@ -6,6 +6,9 @@
 // type SO and compute type C, so BF16 sketches accumulate in FP32.
 
 #include <cmath>
+#include <complex>
+#include <type_traits>
+#include <vector>
 #include <cstdarg>
 
 #include "common.hpp"
@@ -412,6 +415,7 @@ template <class T>
 bool op_fwd_fused_ok(nys_op op) {
   const auto& d = op->d;
   if (d.kind != NYS_OP_BLUR && d.kind != NYS_OP_BLURDOWN) return false;
+  if (d.wavelet_levels > 0 && d.wavelet != NYS_WAVELET_HAAR) return false;
   const int B = 1 << d.wavelet_levels;
   const int f = d.kind == NYS_OP_BLURDOWN ? d.factor : 1;
   return d.wavelet_levels >= 0 && d.wavelet_levels <= 3 && d.n1 % B == 0 && d.n2 % B == 0 &&
@@ -509,6 +513,159 @@ static nys_status launch_haar(int levels, const SI* in, SO* out, int n1, int n2,
   return launch_check("haar_kernel");
 }
 
+// ================================================================ Daubechies-4
+// One pass of the periodised two-channel filter bank over the top-left
+// m1 x m2 band (row pitch n2), along rows (kRows) or columns, one thread per
+// output value.  Analysis: a_i = sum_k h_k x[(2i + k) mod m], d_i with g,
+// a in the first half of the line and d in the second.  Synthesis (the
+// transpose): x_j = sum over k with j - k even of h_k a_{((j - k) mod m) / 2}
+// + g_k d_{((j - k) mod m) / 2}.
+template <bool kAnalysis, bool kRows, class TI, class TO, class C>
+__global__ __launch_bounds__(256) void db4_pass_kernel(const TI* __restrict__ in, TO* __restrict__ out,
+                                                       int n1, int n2, int m1, int m2, Db4Coef f) {
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63);   // column in the band
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);    // row in the band
+  if (i >= m1 || j >= m2) return;
+  const size_t plane = static_cast<size_t>(n1) * n2;
+  const TI* src = in + blockIdx.z * plane;
+  const int m = kRows ? m2 : m1, t = kRows ? j : i;     // length and position along the line
+  auto at = [&](int q) -> C {                            // line element q
+    return kRows ? static_cast<C>(Io<TI>::ld(src, static_cast<size_t>(i) * n2 + q))
+                 : static_cast<C>(Io<TI>::ld(src, static_cast<size_t>(q) * n2 + j));
+  };
+  const C* h = std::is_same<C, double>::value ? reinterpret_cast<const C*>(f.hd) : reinterpret_cast<const C*>(f.hf);
+  const C* g = std::is_same<C, double>::value ? reinterpret_cast<const C*>(f.gd) : reinterpret_cast<const C*>(f.gf);
+  C acc = 0;
+  const int half = m / 2;
+  if (kAnalysis) {
+    const bool detail = t >= half;
+    const int b = 2 * (detail ? t - half : t);
+    const C* w = detail ? g : h;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += w[k] * at((b + k) % m);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (((t - k) & 1) != 0) continue;
+      int q = (t - k) % m;
+      if (q < 0) q += m;
+      const int idx = q / 2;
+      acc += h[k] * at(idx) + g[k] * at(half + idx);
+    }
+  }
+  Io<TO>::st(out + blockIdx.z * plane, static_cast<size_t>(i) * n2 + j, acc);
+}
+
+template <class TI, class TO>
+__global__ void convert_kernel(const TI* __restrict__ in, TO* __restrict__ out, size_t n) {
+  for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < n;
+       e += static_cast<size_t>(gridDim.x) * blockDim.x)
+    Io<TO>::st(out, e, static_cast<typename Io<TO>::C>(Io<TI>::ld(in, e)));
+}
+
+// W x (analysis) or W^T x (synthesis) with `levels` Daubechies-4 levels.  The
+// passes go through scratch; every level works on `work` (C values: out
+// itself when SO is C, else a second buffer converted into out once at the
+// end, so a narrow output is rounded only once).  scratch and work each hold
+// n1 n2 ncols values.
+template <bool kAnalysis, class SI, class SO, class C>
+static nys_status launch_db4(const nys_op_s* op, int levels, const SI* in, SO* out, C* scratch,
+                             C* work_buf, int n1, int n2, int64_t ncols, hipStream_t st) {
+  const Db4Coef& f = op->db4;
+  const size_t n = static_cast<size_t>(n1) * n2 * ncols;
+  const dim3 cgrid(std::min<size_t>(cdiv(n, 256), 4096));
+  constexpr bool kSame = std::is_same<SO, C>::value;
+  C* work = kSame ? reinterpret_cast<C*>(out) : work_buf;
+  auto grid = [&](int m1, int m2) { return dim3(cdiv(m2, 64), cdiv(m1, 4), static_cast<unsigned>(ncols)); };
+  if (kAnalysis) {
+    // level 0 reads the input; later levels read work's LL band
+    hipLaunchKernelGGL((db4_pass_kernel<true, true, SI, C, C>), grid(n1, n2), dim3(256), 0, st, in,
+                       scratch, n1, n2, n1, n2, f);
+    hipLaunchKernelGGL((db4_pass_kernel<true, false, C, C, C>), grid(n1, n2), dim3(256), 0, st,
+                       scratch, work, n1, n2, n1, n2, f);
+    for (int lev = 1; lev < levels; ++lev) {
+      const int m1 = n1 >> lev, m2 = n2 >> lev;
+      hipLaunchKernelGGL((db4_pass_kernel<true, true, C, C, C>), grid(m1, m2), dim3(256), 0, st,
+                         work, scratch, n1, n2, m1, m2, f);
+      hipLaunchKernelGGL((db4_pass_kernel<true, false, C, C, C>), grid(m1, m2), dim3(256), 0, st,
+                         scratch, work, n1, n2, m1, m2, f);
+    }
+  } else {
+    // work = in, then the levels coarsest first, columns then rows
+    hipLaunchKernelGGL((convert_kernel<SI, C>), cgrid, dim3(256), 0, st, in, work, n);
+    for (int lev = levels - 1; lev >= 0; --lev) {
+      const int m1 = n1 >> lev, m2 = n2 >> lev;
+      hipLaunchKernelGGL((db4_pass_kernel<false, false, C, C, C>), grid(m1, m2), dim3(256), 0, st,
+                         work, scratch, n1, n2, m1, m2, f);
+      hipLaunchKernelGGL((db4_pass_kernel<false, true, C, C, C>), grid(m1, m2), dim3(256), 0, st,
+                         scratch, work, n1, n2, m1, m2, f);
+    }
+  }
+  if (!kSame) hipLaunchKernelGGL((convert_kernel<C, SO>), cgrid, dim3(256), 0, st, work, out, n);
+  return launch_check("db4_pass_kernel");
+}
+
+// The wavelet of the operator: Haar (haar_kernel) or Daubechies-4.
+template <bool kAnalysis, class SI, class SO, class C>
+static nys_status launch_wavelet(nys_op_s* op, const SI* in, SO* out, int64_t ncols,
+                                 hipStream_t st) {
+  const auto& d = op->d;
+  if (d.wavelet != NYS_WAVELET_DB4)
+    return launch_haar<kAnalysis, SI, SO, C>(d.wavelet_levels, in, out, d.n1, d.n2, ncols, st);
+  const size_t n = static_cast<size_t>(d.n1) * d.n2 * ncols;
+  NYS_TRY(op->tmp2.ensure(sizeof(C) * 2 * n));
+  return launch_db4<kAnalysis, SI, SO, C>(op, d.wavelet_levels, in, out, op->tmp2.as<C>(),
+                                          op->tmp2.as<C>() + n, d.n1, d.n2, ncols, st);
+}
+
+// Filters of the Daubechies-4 wavelet by spectral factorisation (host, FP64):
+// |H|^2 = 2 cos^8(w/2) Q(sin^2(w/2)), Q(y) = 1 + 4y + 10y^2 + 20y^3; the
+// roots of Q (Durand-Kerner iteration) give z from z^2 - (2 - 4y) z + 1 = 0,
+// the root inside the unit circle is kept, h(z) is proportional to
+// (z + 1)^4 prod (z - z_j) (coefficients from the highest power down),
+// normalised to a sum of sqrt(2).
+static Db4Coef db4_filters() {
+  using cd = std::complex<double>;
+  const double q[4] = {1.0 / 20.0, 4.0 / 20.0, 10.0 / 20.0, 1.0};   // monic, y^0 .. y^3
+  cd r[3] = {cd(0.4, 0.9), cd(0.4, 0.9) * cd(0.4, 0.9), cd(0.4, 0.9) * cd(0.4, 0.9) * cd(0.4, 0.9)};
+  for (int it = 0; it < 500; ++it) {
+    for (int a = 0; a < 3; ++a) {
+      cd num = q[3];
+      for (int c = 2; c >= 0; --c) num = num * r[a] + q[c];
+      cd den = 1.0;
+      for (int b = 0; b < 3; ++b)
+        if (b != a) den *= (r[a] - r[b]);
+      r[a] -= num / den;
+    }
+  }
+  std::vector<cd> poly{cd(1.0)};
+  auto mul = [&](cd c0, cd c1) {   // poly *= (c0 z + c1), highest power first
+    std::vector<cd> out(poly.size() + 1, cd(0.0));
+    for (size_t t = 0; t < poly.size(); ++t) {
+      out[t] += poly[t] * c0;
+      out[t + 1] += poly[t] * c1;
+    }
+    poly.swap(out);
+  };
+  for (int t = 0; t < 4; ++t) mul(cd(1.0), cd(1.0));
+  for (int a = 0; a < 3; ++a) {
+    const cd b = 1.0 - 2.0 * r[a];
+    const cd disc = std::sqrt(b * b - 1.0);
+    const cd z1 = b + disc, z2 = b - disc;
+    mul(cd(1.0), -(std::abs(z1) < 1.0 ? z1 : z2));
+  }
+  Db4Coef f{};
+  double sum = 0;
+  for (int k = 0; k < 8; ++k) sum += poly[k].real();
+  for (int k = 0; k < 8; ++k) f.hd[k] = poly[k].real() * (std::sqrt(2.0) / sum);
+  for (int k = 0; k < 8; ++k) f.gd[k] = ((k & 1) ? -1.0 : 1.0) * f.hd[7 - k];
+  for (int k = 0; k < 8; ++k) {
+    f.hf[k] = static_cast<float>(f.hd[k]);
+    f.gf[k] = static_cast<float>(f.gd[k]);
+  }
+  return f;
+}
+
 template <class SI, class SO, class C>
 static nys_status launch_joseph_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t ncols,
                                     hipStream_t st) {
@@ -583,8 +740,7 @@ nys_status op_fwd(nys_op op, const T* x, T* y, int64_t ncols, hipStream_t st) {
   if (d.wavelet_levels > 0) {
     NYS_TRY(op->tmp0.ensure(sizeof(T) * op->N * ncols));
     T* t = op->tmp0.as<T>();
-    NYS_TRY((launch_haar<false, T, T, T>(d.wavelet_levels, x, d.kind == NYS_OP_IDENTITY ? y : t,
-                                        d.n1, d.n2, ncols, st)));
+    NYS_TRY((launch_wavelet<false, T, T, T>(op, x, d.kind == NYS_OP_IDENTITY ? y : t, ncols, st)));
     if (d.kind == NYS_OP_IDENTITY) return NYS_OK;
     src = t;
   } else if (d.kind == NYS_OP_IDENTITY) {
@@ -598,14 +754,14 @@ nys_status op_adj(nys_op op, const T* y, T* x, int64_t ncols, hipStream_t st) {
   const auto& d = op->d;
   if (d.kind == NYS_OP_IDENTITY) {
     if (d.wavelet_levels > 0)
-      return launch_haar<true, T, T, T>(d.wavelet_levels, y, x, d.n1, d.n2, ncols, st);
+      return launch_wavelet<true, T, T, T>(op, y, x, ncols, st);
     return copy_cols(y, x, static_cast<size_t>(op->N) * ncols, st);
   }
   if (d.wavelet_levels > 0) {
     NYS_TRY(op->tmp0.ensure(sizeof(T) * op->N * ncols));
     T* t = op->tmp0.as<T>();
     NYS_TRY((apply_At_plain<T, T, T>(op, y, t, ncols, st)));
-    return launch_haar<true, T, T, T>(d.wavelet_levels, t, x, d.n1, d.n2, ncols, st);
+    return launch_wavelet<true, T, T, T>(op, t, x, ncols, st);
   }
   return apply_At_plain<T, T, T>(op, y, x, ncols, st);
 }
@@ -628,8 +784,8 @@ static nys_status sketch_chain(nys_op op, const S* omega, S* Y, int64_t ell, hip
     NYS_TRY(op->tmp0.ensure(sizeof(C) * N * ell));
     C* t = op->tmp0.as<C>();
     if (wav) {
-      NYS_TRY((launch_haar<false, S, C, C>(d.wavelet_levels, omega, t, d.n1, d.n2, ell, st)));
-      return launch_haar<true, C, S, C>(d.wavelet_levels, t, Y, d.n1, d.n2, ell, st);
+      NYS_TRY((launch_wavelet<false, S, C, C>(op, omega, t, ell, st)));
+      return launch_wavelet<true, C, S, C>(op, t, Y, ell, st);
     }
     NYS_CHECK_HIP(hipMemcpyAsync(Y, omega, sizeof(S) * N * ell, hipMemcpyDeviceToDevice, st));
     return NYS_OK;
@@ -639,10 +795,10 @@ static nys_status sketch_chain(nys_op op, const S* omega, S* Y, int64_t ell, hip
   C* img = op->tmp0.as<C>();
   C* meas = op->tmp1.as<C>();
   if (wav) {
-    NYS_TRY((launch_haar<false, S, C, C>(d.wavelet_levels, omega, img, d.n1, d.n2, ell, st)));
+    NYS_TRY((launch_wavelet<false, S, C, C>(op, omega, img, ell, st)));
     NYS_TRY((apply_A_plain<C, C, C>(op, img, meas, ell, st)));
     NYS_TRY((apply_At_plain<C, C, C>(op, meas, img, ell, st)));
-    return launch_haar<true, C, S, C>(d.wavelet_levels, img, Y, d.n1, d.n2, ell, st);
+    return launch_wavelet<true, C, S, C>(op, img, Y, ell, st);
   }
   NYS_TRY((apply_A_plain<S, C, C>(op, omega, meas, ell, st)));
   return apply_At_plain<C, S, C>(op, meas, Y, ell, st);
@@ -655,13 +811,15 @@ nys_status sketch_dispatch(nys_op op, nys_dtype dt, const void* omega, void* Y, 
       return sketch_chain<double, double>(op, static_cast<const double*>(omega),
                                           static_cast<double*>(Y), ell, st);
     case NYS_F32:
-      if (op->d.kind == NYS_OP_BLURDOWN && op->d.wavelet_levels == 3 && op->d.factor == 2)
+      if (op->d.kind == NYS_OP_BLURDOWN && op->d.wavelet_levels == 3 && op->d.factor == 2 &&
+          op->d.wavelet == NYS_WAVELET_HAAR)
         return sketch_sr_fused<float>(op, static_cast<const float*>(omega),
                                       static_cast<float*>(Y), ell, st);
       return sketch_chain<float, float>(op, static_cast<const float*>(omega),
                                         static_cast<float*>(Y), ell, st);
     case NYS_BF16:
-      if (op->d.kind == NYS_OP_BLURDOWN && op->d.wavelet_levels == 3 && op->d.factor == 2)
+      if (op->d.kind == NYS_OP_BLURDOWN && op->d.wavelet_levels == 3 && op->d.factor == 2 &&
+          op->d.wavelet == NYS_WAVELET_HAAR)
         return sketch_sr_fused<uint16_t>(op, static_cast<const uint16_t*>(omega),
                                          static_cast<uint16_t*>(Y), ell, st);
       return sketch_chain<uint16_t, float>(op, static_cast<const uint16_t*>(omega),
@@ -694,7 +852,9 @@ extern "C" nys_status nys_op_create(const nys_op_desc* desc, nys_op* out) {
   NYS_REQUIRE(desc && out, "nys_op_create: null argument");
   const nys_op_desc& d = *desc;
   NYS_REQUIRE(d.n1 > 0 && d.n2 > 0, "nys_op_create: bad image size %d x %d", d.n1, d.n2);
-  NYS_REQUIRE(d.wavelet_levels >= 0 && d.wavelet_levels <= 3, "wavelet_levels must be 0..3");
+  NYS_REQUIRE(d.wavelet == NYS_WAVELET_HAAR || d.wavelet == NYS_WAVELET_DB4, "unknown wavelet");
+  NYS_REQUIRE(d.wavelet_levels >= 0 && d.wavelet_levels <= (d.wavelet == NYS_WAVELET_DB4 ? 6 : 3),
+              "wavelet_levels must be 0..3 (Haar) or 0..6 (Daubechies-4)");
   if (d.wavelet_levels > 0) {
     int B = 1 << d.wavelet_levels;
     NYS_REQUIRE(d.n1 % B == 0 && d.n2 % B == 0, "image size not divisible by 2^levels");
@@ -702,6 +862,7 @@ extern "C" nys_status nys_op_create(const nys_op_desc* desc, nys_op* out) {
   auto* op = new nys_op_s();
   op->d = d;
   op->d.psf = nullptr;
+  if (d.wavelet == NYS_WAVELET_DB4) op->db4 = db4_filters();
   op->N = static_cast<int64_t>(d.n1) * d.n2;
   nys_status st = NYS_OK;
   switch (d.kind) {
@@ -809,6 +970,7 @@ extern "C" void nys_op_destroy(nys_op op) {
   op->xT.release();
   op->tmp0.release();
   op->tmp1.release();
+  op->tmp2.release();
   delete op;
 }
 

@@ -256,6 +256,13 @@ def _solve_pair(P, prob_kind, dt, with_pc, iters):
         prob, _ = sv.problem_from_workload(wl, seed=3, n=64)
         op = P.Operator(P.OP_BLURDOWN, 64, 64, psf=prob.h, factor=2, wavelet_levels=3)
         reg, lam, loss, delta, ell = "l1", prob.lam, P.LOSS_HUBER, prob.delta, 8
+    elif prob_kind == "sr_l1_db4":
+        # the same problem in 4-level Daubechies-4 coordinates
+        wl = W.workload("sr512_haar_bf16")
+        prob, _ = sv.problem_from_workload(wl, seed=3, n=64)
+        prob.levels, prob.wavelet = 4, "db4"
+        op = P.Operator(P.OP_BLURDOWN, 64, 64, psf=prob.h, factor=2, wavelet_levels=4, wavelet="db4")
+        reg, lam, loss, delta, ell = "l1", prob.lam, P.LOSS_HUBER, prob.delta, 8
     else:
         wl = W.workload("ct512_hs1_f32")
         prob, _ = sv.problem_from_workload(wl, seed=4, n=32, views=36, bins=48)
@@ -309,6 +316,7 @@ def test_solve_nonnegative_matches_oracle():
 
 @pytest.mark.parametrize("kind,dt,with_pc", [("deblur_tv", "f64", False), ("deblur_tv", "f64", True),
                                              ("sr_l1", "f32", False), ("sr_l1", "f32", True),
+                                             ("sr_l1_db4", "f64", True), ("sr_l1_db4", "f32", True),
                                              ("ct_hs1", "f32", True)])
 def test_solve_matches_oracle(kind, dt, with_pc):
     P = need_gpu()

@@ -62,6 +62,39 @@ def test_haar_identity_operator(dt):
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n1,n2,levels", [(64, 64, 4), (96, 48, 3), (32, 32, 5), (16, 16, 1)])
+def test_db4_identity_operator(dt, n1, n2, levels):
+    """Periodised Daubechies-4 (the CT experiments' daub4): W^T and W against
+    the oracle's transform, down to bands narrower than the filter."""
+    P = need_gpu()
+    banner(f"db4 identity {dt} {n1}x{n2} levels={levels}")
+    op = P.Operator(P.OP_IDENTITY, n1, n2, wavelet_levels=levels, wavelet="db4")
+    w = W.gaussian((2, n1, n2), 33)
+    wd = dev(w, dt)
+    assert rel(host(P.op_forward(op, wd)), ops.db4_synthesis(host(wd), levels)) < TOL[dt]
+    assert rel(host(P.op_adjoint(op, wd)), ops.db4_analysis(host(wd), levels)) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_blurdown_db4_operator_and_sketch(dt):
+    P = need_gpu()
+    banner(f"blurdown db4 {dt}")
+    n, k, levels = 64, 7, 4
+    h = W.gaussian_psf(k, 1.2)
+    op = P.Operator(P.OP_BLURDOWN, n, n, psf=h, factor=2, wavelet_levels=levels, wavelet="db4")
+    prob = sv.Problem("blurdown", n, None, 0.0, "l1", h=h, factor=2, levels=levels, wavelet="db4")
+    if dt != "bf16":
+        xd = dev(W.gaussian((2, n, n), 34), dt)
+        y = P.op_forward(op, xd)
+        assert rel(host(y), ops.blurdown(ops.db4_synthesis(host(xd), levels), h, 2)) < TOL[dt]
+        z = P.op_adjoint(op, y)
+        assert rel(host(z), ops.db4_analysis(ops.blurdown_adjoint(host(y), h, 2), levels)) < TOL[dt]
+    om = dev(W.omega(3, n, n, 35), dt)
+    Y = P.nys_sketch(op, om)
+    assert rel(host(Y), sv.sketch(prob, host(om))) < TOL[dt]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("n,V,B", [(32, 24, 45), (64, 90, 92), (47, 13, 70)])
 def test_joseph_pair(dt, n, V, B):
     P = need_gpu()
