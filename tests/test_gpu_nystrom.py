@@ -328,6 +328,38 @@ def test_solve_matches_oracle(kind, dt, with_pc):
     assert np.max(np.abs(c - cr) / np.abs(cr)) < tol
 
 
+def test_sr_full_size_solve_matches_oracle():
+    """The super-resolution workload at its full size (512^2 -> 256^2, Haar-3,
+    Huber, ell = 64, FP32 U and solver): the launch configuration the bench
+    times (fused forward operator, (AU)^T psi, fused step evaluation, chord
+    steps from the stored inverse, Gauss-Jordan Newton solves) against the
+    oracle's FP64 iterates; the preconditioner is built on both sides from the
+    oracle's sketch of the same Omega."""
+    P = need_gpu()
+    banner("solve SR full size 512^2 ell=64 f32")
+    wl = W.workload("sr512_haar_bf16")
+    prob, _ = sv.problem_from_workload(wl, seed=3)
+    n, ell, iters = prob.n, 64, 6
+    assert n == 512
+    op = P.Operator(P.OP_BLURDOWN, n, n, psf=prob.h, factor=2, wavelet_levels=3)
+    yd = dev(prob.y, "f32")
+    prob.y = host(yd)
+    om = W.omega(ell, n, n, 20)
+    Yref = sv.sketch(prob, om)
+    ref = onys.nystrom(Yref.reshape(ell, -1), om.reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+    pc = P.nys_factor(dev(om, "f32"), dev(Yref, "f32"), ell, u_dtype=torch.float32)
+    alpha = 0.9 / sv.lipschitz(prob, opc, W.gaussian((n, n), 21), 60)
+    rd = P.reg_desc("l1", n, n)
+    x, costs, info = P.solve(op, yd, rd, prob.lam, pc, iters, alpha=alpha, loss=P.LOSS_HUBER,
+                             delta=prob.delta)
+    xr, cr = sv.wapg(prob, opc, alpha, iters, ssn_tol=1e-10)
+    ex, ec = rel(host(x), xr), np.max(np.abs(host(costs) - cr) / np.abs(cr))
+    banner(f"full size SR: x rel err {ex:.2e}, cost rel err {ec:.2e}")
+    assert ex < 2e-6      # measured 1.3e-7: FP32 arithmetic, FP64 reductions
+    assert ec < 1e-7      # measured 2.8e-9
+
+
 def test_solve_power_method_step():
     P = need_gpu()
     banner("solve power method")
