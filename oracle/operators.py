@@ -262,6 +262,84 @@ def joseph_adjoint(p: np.ndarray, n: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# fan-beam Joseph projector (flat detector)
+#
+# View v at theta = 2 pi v / V: central ray direction d0 = (-sin, cos), source
+# S = -R_s d0, a flat detector through R_d d0 along e = (cos, sin), bin b at
+# u = (b - (B-1)/2) du.  Every ray is a line n . p = s with the unit normal n
+# proportional to (R_s + R_d) e - u d0 and s = n . S = u R_s / sqrt((R_s +
+# R_d)^2 + u^2); Joseph's sampling of the parallel-beam projector applies to
+# it with (cos, sin) = n.  As R_s -> inf (R_d fixed) n -> e and s -> u: the
+# parallel-beam projector with the detector coordinate u.
+
+def fan_rays(n_views: int, n_bins: int, src: float, det: float, du: float):
+    """Per-ray normals and offsets, arrays (n_views, n_bins): cos, sin, s."""
+    th = 2.0 * np.pi * np.arange(n_views, dtype=np.float64) / n_views
+    u = (np.arange(n_bins, dtype=np.float64) - (n_bins - 1) / 2.0) * du
+    e = np.stack([np.cos(th), np.sin(th)], axis=-1)            # (V, 2)
+    d0 = np.stack([-np.sin(th), np.cos(th)], axis=-1)
+    nv = (src + det) * e[:, None, :] - u[None, :, None] * d0[:, None, :]
+    nrm = np.sqrt((src + det) ** 2 + u * u)[None, :]
+    cs, sn = nv[..., 0] / nrm, nv[..., 1] / nrm
+    s = (u * src)[None, :] / nrm
+    return cs, sn, np.broadcast_to(s, cs.shape).copy()
+
+
+def _joseph_rays(n: int, cs, sn, s):
+    """Joseph samples of arbitrary lines n . p = s (1-D arrays of rays):
+    (lo, w, scale, along_rows) per ray, lo / w shaped (rays, n)."""
+    c = (n - 1) / 2.0
+    t = np.arange(n, dtype=np.float64) - c
+    rows = np.abs(cs) >= np.abs(sn)
+    a = np.where(rows, cs, sn)
+    b = np.where(rows, sn, cs)
+    f = (s[:, None] - t[None, :] * b[:, None]) / a[:, None] + c
+    lo = np.floor(f).astype(np.int64)
+    return lo, f - lo, 1.0 / np.abs(a), rows
+
+
+def fan_joseph(x: np.ndarray, n_views: int, n_bins: int, src: float, det: float,
+               du: float) -> np.ndarray:
+    """Fan-beam projection of an n x n image (or a stack) to (..., V, B)."""
+    n = x.shape[-1]
+    lead = x.shape[:-2]
+    xs = x.reshape((-1, n, n))
+    cs, sn, s = fan_rays(n_views, n_bins, src, det, du)
+    out = np.zeros((xs.shape[0], n_views, n_bins))
+    step = np.broadcast_to(np.arange(n)[None, :], (n_bins, n))
+    for v in range(n_views):
+        lo, w, scale, rows = _joseph_rays(n, cs[v], sn[v], s[v])
+        for q, wq in ((lo, 1.0 - w), (lo + 1, w)):
+            ok = (q >= 0) & (q < n)
+            qc = np.clip(q, 0, n - 1)
+            r = np.where(rows[:, None], step, qc)
+            col = np.where(rows[:, None], qc, step)
+            vals = xs[:, r, col]
+            out[:, v, :] += scale * np.sum(np.where(ok, wq * vals, 0.0), axis=-1)
+    return out.reshape(lead + (n_views, n_bins))
+
+
+def fan_joseph_adjoint(p: np.ndarray, n: int, src: float, det: float, du: float) -> np.ndarray:
+    """Transpose of `fan_joseph`: the same samples, scattered."""
+    n_views, n_bins = p.shape[-2:]
+    lead = p.shape[:-2]
+    ps = p.reshape((-1, n_views, n_bins))
+    cs, sn, s = fan_rays(n_views, n_bins, src, det, du)
+    out = np.zeros((ps.shape[0], n * n))
+    step = np.broadcast_to(np.arange(n)[None, :], (n_bins, n))
+    for v in range(n_views):
+        lo, w, scale, rows = _joseph_rays(n, cs[v], sn[v], s[v])
+        for q, wq in ((lo, 1.0 - w), (lo + 1, w)):
+            ok = (q >= 0) & (q < n)
+            flat = np.where(rows[:, None], step * n + q, q * n + step)
+            idx = flat[ok]
+            for m in range(ps.shape[0]):
+                contrib = (scale[:, None] * wq * ps[m, v, :, None])[ok]
+                out[m] += np.bincount(idx, weights=contrib, minlength=n * n)
+    return out.reshape(lead + (n, n))
+
+
+# --------------------------------------------------------------------------
 # regularisation operators (App. A)
 
 def grad(x: np.ndarray) -> np.ndarray:

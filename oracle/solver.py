@@ -24,7 +24,7 @@ from . import prox as px
 
 @dataclasses.dataclass
 class Problem:
-    op: str                      # 'blur' | 'blurdown' | 'ct' | 'identity'
+    op: str                      # 'blur' | 'blurdown' | 'ct' | 'fan' | 'identity'
     n: int
     y: np.ndarray
     lam: float
@@ -38,6 +38,7 @@ class Problem:
     loss: str = "ls"
     delta: float = 0.0
     box: Optional[tuple] = None  # (lo, hi): x restricted to C = {lo <= x <= hi}
+    fan: tuple = (0.0, 0.0, 1.0)  # 'fan': source radius, detector radius, bin spacing
 
     # A and A^T of the (possibly reparametrised) problem
     def A(self, x):
@@ -49,6 +50,8 @@ class Problem:
             return ops.blurdown(x, self.h, self.factor)
         if self.op == "ct":
             return ops.joseph(x, self.views, self.bins)
+        if self.op == "fan":
+            return ops.fan_joseph(x, self.views, self.bins, *self.fan)
         if self.op == "identity":
             return np.array(x, dtype=np.float64)
         raise ValueError(self.op)
@@ -60,6 +63,8 @@ class Problem:
             z = ops.blurdown_adjoint(r, self.h, self.factor)
         elif self.op == "ct":
             z = ops.joseph_adjoint(r, self.n)
+        elif self.op == "fan":
+            z = ops.fan_joseph_adjoint(r, self.n, *self.fan)
         elif self.op == "identity":
             z = np.array(r, dtype=np.float64)
         else:

@@ -300,3 +300,37 @@ def test_db4_details_vanish_on_cubics():
     interior = [n // 2 + i for i in range(n // 2) if 2 * i + 7 < n]
     assert np.max(np.abs(w[interior, :n // 2])) < 1e-9 * np.max(np.abs(x))
     assert np.max(np.abs(w[n // 2 + n // 2 - 1, :n // 2])) > 1.0   # the wrapped one does not
+
+
+# --- fan-beam Joseph (next-row geometry) ------------------------------------
+
+def test_fan_joseph_is_the_exact_transpose():
+    n, V, B = 8, 6, 11
+    src, det, du = 20.0, 10.0, 1.3
+    E = np.eye(n * n).reshape(n * n, n, n)
+    A = ops.fan_joseph(E, V, B, src, det, du).reshape(n * n, V * B).T
+    Et = np.eye(V * B).reshape(V * B, V, B)
+    At = ops.fan_joseph_adjoint(Et, n, src, det, du).reshape(V * B, n * n).T
+    assert np.allclose(At, A.T, atol=1e-13)
+
+
+def test_fan_joseph_tends_to_the_parallel_beam_projector():
+    # source at infinity: the rays of view v are the parallel rays at angle
+    # 2 pi v / V with the detector coordinate u; views 0 .. V/2 - 1 cover the
+    # parallel-beam views over 180 degrees
+    n, V, B = 24, 8, 31
+    x = np.random.default_rng(4).standard_normal((n, n))
+    fan = ops.fan_joseph(x, V, B, 1e9, 0.0, 1.0)
+    par = ops.joseph(x, V // 2, B)
+    assert np.allclose(fan[: V // 2], par, atol=1e-6 * np.abs(par).max())
+
+
+def test_fan_joseph_central_ray_through_a_disc():
+    # a disc of radius r centred in the image: the central ray of every view
+    # passes through the centre, so its line integral is the chord 2 r
+    n, r = 96, 30.0
+    c = (n - 1) / 2.0
+    i, j = np.mgrid[0:n, 0:n]
+    disc = ((i - c) ** 2 + (j - c) ** 2 <= r * r).astype(np.float64)
+    p = ops.fan_joseph(disc, 12, 41, 150.0, 60.0, 1.5)
+    assert np.all(np.abs(p[:, 20] - 2 * r) <= 1.5)
