@@ -45,7 +45,8 @@ typedef enum {
   NYS_OP_BLUR = 0,           /* periodic k x k blur, n1 x n2 -> n1 x n2 */
   NYS_OP_BLURDOWN = 1,       /* blur then keep every factor-th row/column */
   NYS_OP_PARALLEL_BEAM = 2,  /* Joseph projector, n x n -> views x bins */
-  NYS_OP_IDENTITY = 3        /* A = I (with wavelet_levels: A = W^T) */
+  NYS_OP_IDENTITY = 3,       /* A = I (with wavelet_levels: A = W^T) */
+  NYS_OP_FAN_BEAM = 4        /* Joseph projector, fan beam, flat detector, n x n -> views x bins */
 } nys_op_kind;
 
 typedef enum {
@@ -88,6 +89,14 @@ typedef struct {
   int32_t n_views, n_bins; /* PARALLEL_BEAM */
   int32_t wavelet_levels;  /* 0 or wavelet levels; n1, n2 divisible by 2^levels */
   int32_t wavelet;         /* NYS_WAVELET_HAAR (0) or NYS_WAVELET_DB4 (1) */
+  /* FAN_BEAM, in pixel units: view v at theta = 2 pi v / views; source at
+   * fan_src from the centre opposite the central ray direction (-sin, cos);
+   * a flat detector at fan_det past the centre, perpendicular to it; bin b at
+   * u = (b - (bins - 1) / 2) fan_du along (cos, sin).  Every ray, a line
+   * n . p = s, is sampled as in PARALLEL_BEAM with its own normal n and
+   * offset s; the adjoint is the exact transpose (scattered with atomic
+   * additions, so its summation order is not fixed). */
+  double fan_src, fan_det, fan_du;
 } nys_op_desc;
 
 enum { NYS_WAVELET_HAAR = 0, NYS_WAVELET_DB4 = 1 };

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(HERE, "libnys.so")
 
 F64, F32, BF16 = 0, 1, 2
-OP_BLUR, OP_BLURDOWN, OP_PARALLEL_BEAM, OP_IDENTITY = 0, 1, 2, 3
+OP_BLUR, OP_BLURDOWN, OP_PARALLEL_BEAM, OP_IDENTITY, OP_FAN_BEAM = 0, 1, 2, 3, 4
 REG_TV, REG_TV_ANISO, REG_HS1, REG_L1, REG_HS2, REG_HSINF = 0, 1, 2, 3, 4, 5
 LOSS_LS, LOSS_HUBER = 0, 1
 REG_NAMES = {"tv": REG_TV, "tv_aniso": REG_TV_ANISO, "hs1": REG_HS1, "l1": REG_L1,
@@ -32,7 +32,8 @@ class OpDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n1", C.c_int32), ("n2", C.c_int32),
                 ("psf_size", C.c_int32), ("psf", C.POINTER(C.c_double)),
                 ("factor", C.c_int32), ("n_views", C.c_int32), ("n_bins", C.c_int32),
-                ("wavelet_levels", C.c_int32), ("wavelet", C.c_int32)]
+                ("wavelet_levels", C.c_int32), ("wavelet", C.c_int32),
+                ("fan_src", C.c_double), ("fan_det", C.c_double), ("fan_du", C.c_double)]
 
 
 class FactorOpts(C.Structure):
@@ -182,7 +183,9 @@ class Operator:
     """Handle of an operator A (optionally composed with Haar synthesis)."""
 
     def __init__(self, kind: int, n1: int, n2: int, psf=None, factor: int = 1,
-                 views: int = 0, bins: int = 0, wavelet_levels: int = 0, wavelet: str = "haar"):
+                 views: int = 0, bins: int = 0, wavelet_levels: int = 0, wavelet: str = "haar",
+                 fan=None):
+        """fan = (source radius, detector radius, bin spacing) in pixels (OP_FAN_BEAM)."""
         d = OpDesc()
         d.kind, d.n1, d.n2 = kind, n1, n2
         self._psf = None
@@ -192,6 +195,8 @@ class Operator:
             d.psf = self._psf.ctypes.data_as(C.POINTER(C.c_double))
         d.factor, d.n_views, d.n_bins, d.wavelet_levels = factor, views, bins, wavelet_levels
         d.wavelet = {"haar": 0, "db4": 1}[wavelet]
+        if fan is not None:
+            d.fan_src, d.fan_det, d.fan_du = (float(v) for v in fan)
         h = C.c_void_p()
         _check(lib().nys_op_create(C.byref(d), C.byref(h)))
         self.handle = h
@@ -204,7 +209,7 @@ class Operator:
 
     @property
     def meas_shape(self):
-        if self.kind == OP_PARALLEL_BEAM:
+        if self.kind in (OP_PARALLEL_BEAM, OP_FAN_BEAM):
             return (self.views, self.bins)
         if self.kind == OP_BLURDOWN:
             return (self.n1 // self.factor, self.n2 // self.factor)

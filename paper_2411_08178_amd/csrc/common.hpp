@@ -142,7 +142,8 @@ struct nys_op_s {
   nys::DevBuf psf_dev;            // [flipped psf f64 | psf f64 | flipped f32 | psf f32]
   nys::DevBuf trig;               // per view: cos, sin (f64) then (f32)
   nys::DevBuf tmp0, tmp1;         // intermediates of composed operators
-  nys::DevBuf tmp2;               // scratch of the Daubechies-4 passes
+  nys::DevBuf tmp2;               // scratch of the Daubechies-4 passes and of the
+                                  // fan-beam adjoint's accumulation (narrow outputs)
   mutable nys::DevBuf xT;         // transposed images (parallel-beam forward)
 };
 

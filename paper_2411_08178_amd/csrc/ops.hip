@@ -691,6 +691,145 @@ static nys_status launch_joseph_adj(const nys_op_s* op, const SI* p, SO* x, int6
   return launch_check("joseph_adj_kernel");
 }
 
+// ================================================================ fan beam
+template <class T> nys_status fill_zero(T* p, size_t n, hipStream_t st);   // prox.hip
+
+// The ray (view v, bin b) as the line cs x + sn y = s (FP64): normal
+// proportional to (R_s + R_d) e - u d0 with e = (cos, sin), d0 = (-sin, cos)
+// of theta = 2 pi v / V, s = u R_s / |.|.
+__device__ __forceinline__ void fan_ray(int v, int b, int V, int B, double src, double det,
+                                        double du, double& cs, double& sn, double& s) {
+  const double th = 2.0 * M_PI * v / V;
+  const double ce = cos(th), se = sin(th);
+  const double u = (b - 0.5 * (B - 1)) * du;
+  const double Rt = src + det;
+  const double nrm = sqrt(Rt * Rt + u * u);
+  cs = (Rt * ce + u * se) / nrm;
+  sn = (Rt * se - u * ce) / nrm;
+  s = u * src / nrm;
+}
+
+// Joseph sampling of one line: the stepped index range and, per step t, the
+// interpolation coordinate f0 + (t - c) g along the other axis.
+__device__ __forceinline__ void fan_steps(double cs, double sn, double s, int n, bool& rows,
+                                          double& f0, double& g, double& scale, int& t0, int& t1) {
+  rows = fabs(cs) >= fabs(sn);
+  const double a = rows ? cs : sn, bb = rows ? sn : cs;
+  const double c = 0.5 * (n - 1);
+  f0 = s / a + c;
+  g = -bb / a;
+  scale = 1.0 / fabs(a);
+  t0 = 0;
+  t1 = n - 1;
+  if (g != 0.0) {
+    double ta = (-1.0 - f0) / g + c, tb = (n - f0) / g + c;
+    if (ta > tb) { const double tt = ta; ta = tb; tb = tt; }
+    ta = fmin(fmax(ta, -2.0), n + 1.0);
+    tb = fmin(fmax(tb, -2.0), n + 1.0);
+    t0 = max(0, static_cast<int>(floor(ta)) - 1);
+    t1 = min(n - 1, static_cast<int>(ceil(tb)) + 1);
+  } else if (!(f0 >= -1.0 && f0 < n)) {
+    t1 = -1;
+  }
+}
+
+template <class SI, class SO, class C>
+__global__ __launch_bounds__(256) void fan_fwd_kernel(const SI* __restrict__ x, SO* __restrict__ p,
+                                                      int n, int V, int B, double src, double det,
+                                                      double du) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (b >= B) return;
+  double cs, sn, s, f0, g, scale;
+  fan_ray(v, b, V, B, src, det, du, cs, sn, s);
+  bool rows;
+  int t0, t1;
+  fan_steps(cs, sn, s, n, rows, f0, g, scale, t0, t1);
+  const SI* img = x + static_cast<size_t>(blockIdx.z) * n * n;
+  const double c = 0.5 * (n - 1);
+  C acc = 0;
+  for (int t = t0; t <= t1; ++t) {
+    const double f = f0 + (t - c) * g;
+    const double fl = floor(f);
+    const int q = static_cast<int>(fl);
+    const C w = static_cast<C>(f - fl);
+    const int qa = min(max(q, 0), n - 1), qb = min(max(q + 1, 0), n - 1);
+    const C lo = Io<SI>::ld(img, rows ? static_cast<size_t>(t) * n + qa : static_cast<size_t>(qa) * n + t);
+    const C hi = Io<SI>::ld(img, rows ? static_cast<size_t>(t) * n + qb : static_cast<size_t>(qb) * n + t);
+    if (q >= 0 && q < n) acc += (C(1) - w) * lo;
+    if (q + 1 >= 0 && q + 1 < n) acc += w * hi;
+  }
+  Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b,
+             static_cast<C>(scale) * acc);
+}
+
+// x += A^T p ray by ray (x zeroed by the caller): the forward's samples,
+// scattered with atomic additions.
+template <class SI, class C>
+__global__ __launch_bounds__(256) void fan_adj_kernel(const SI* __restrict__ p, C* __restrict__ x,
+                                                      int n, int V, int B, double src, double det,
+                                                      double du) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (b >= B) return;
+  double cs, sn, s, f0, g, scale;
+  fan_ray(v, b, V, B, src, det, du, cs, sn, s);
+  bool rows;
+  int t0, t1;
+  fan_steps(cs, sn, s, n, rows, f0, g, scale, t0, t1);
+  const C val = static_cast<C>(scale) *
+                static_cast<C>(Io<SI>::ld(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b));
+  if (val == C(0)) return;
+  C* img = x + static_cast<size_t>(blockIdx.z) * n * n;
+  const double c = 0.5 * (n - 1);
+  for (int t = t0; t <= t1; ++t) {
+    const double f = f0 + (t - c) * g;
+    const double fl = floor(f);
+    const int q = static_cast<int>(fl);
+    const C w = static_cast<C>(f - fl);
+    if (q >= 0 && q < n)
+      atomicAdd(img + (rows ? static_cast<size_t>(t) * n + q : static_cast<size_t>(q) * n + t),
+                (C(1) - w) * val);
+    if (q + 1 >= 0 && q + 1 < n)
+      atomicAdd(img + (rows ? static_cast<size_t>(t) * n + q + 1 : static_cast<size_t>(q + 1) * n + t),
+                w * val);
+  }
+}
+
+template <class SI, class SO, class C>
+static nys_status launch_fan_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t ncols,
+                                 hipStream_t st) {
+  const auto& d = op->d;
+  dim3 grid(cdiv(d.n_bins, 256), d.n_views, static_cast<unsigned>(ncols));
+  hipLaunchKernelGGL((fan_fwd_kernel<SI, SO, C>), grid, dim3(256), 0, st, x, p, d.n1, d.n_views,
+                     d.n_bins, d.fan_src, d.fan_det, d.fan_du);
+  return launch_check("fan_fwd_kernel");
+}
+
+template <class SI, class SO, class C>
+static nys_status launch_fan_adj(nys_op_s* op, const SI* p, SO* x, int64_t ncols, hipStream_t st) {
+  const auto& d = op->d;
+  const size_t n = static_cast<size_t>(d.n1) * d.n2 * ncols;
+  C* acc;
+  if constexpr (std::is_same<SO, C>::value) {
+    acc = x;
+  } else {
+    NYS_TRY(op->tmp2.ensure(sizeof(C) * n));
+    acc = op->tmp2.as<C>();
+  }
+  NYS_TRY(fill_zero<C>(acc, n, st));
+  dim3 grid(cdiv(d.n_bins, 256), d.n_views, static_cast<unsigned>(ncols));
+  hipLaunchKernelGGL((fan_adj_kernel<SI, C>), grid, dim3(256), 0, st, p, acc, d.n1, d.n_views,
+                     d.n_bins, d.fan_src, d.fan_det, d.fan_du);
+  NYS_TRY(launch_check("fan_adj_kernel"));
+  if constexpr (!std::is_same<SO, C>::value) {
+    hipLaunchKernelGGL((convert_kernel<C, SO>), dim3(std::min<size_t>(cdiv(n, 256), 4096)),
+                       dim3(256), 0, st, acc, x, n);
+    return launch_check("convert_kernel");
+  }
+  return NYS_OK;
+}
+
 // A applied to an image (no wavelet composition): SI -> SO.
 template <class SI, class SO, class C>
 static nys_status apply_A_plain(nys_op_s* op, const SI* x, SO* y, int64_t ncols, hipStream_t st) {
@@ -702,6 +841,8 @@ static nys_status apply_A_plain(nys_op_s* op, const SI* x, SO* y, int64_t ncols,
       return launch_correlate<SI, SO, C>(op, x, y, true, d.n1, d.n2, d.factor, ncols, st);
     case NYS_OP_PARALLEL_BEAM:
       return launch_joseph_fwd<SI, SO, C>(op, x, y, ncols, st);
+    case NYS_OP_FAN_BEAM:
+      return launch_fan_fwd<SI, SO, C>(op, x, y, ncols, st);
     default: break;
   }
   set_error("apply_A_plain: bad operator kind");
@@ -719,6 +860,8 @@ static nys_status apply_At_plain(nys_op_s* op, const SI* y, SO* x, int64_t ncols
                                            d.factor, ncols, st);
     case NYS_OP_PARALLEL_BEAM:
       return launch_joseph_adj<SI, SO, C>(op, y, x, ncols, st);
+    case NYS_OP_FAN_BEAM:
+      return launch_fan_adj<SI, SO, C>(op, y, x, ncols, st);
     default: break;
   }
   set_error("apply_At_plain: bad operator kind");
@@ -911,6 +1054,18 @@ extern "C" nys_status nys_op_create(const nys_op_desc* desc, nys_op* out) {
         hipMemcpy(op->psf_dev.as<double>() + 2 * k * k, h32.data(), 4 * 2 * k * k,
                   hipMemcpyHostToDevice);
       }
+      break;
+    }
+    case NYS_OP_FAN_BEAM: {
+      if (!(d.n1 == d.n2 && d.n_views > 0 && d.n_bins > 0 && d.fan_src > 0 && d.fan_det >= 0 &&
+            d.fan_du > 0 && std::isfinite(d.fan_src) && std::isfinite(d.fan_det) &&
+            std::isfinite(d.fan_du))) {
+        delete op;
+        set_error("nys_op_create: fan beam needs a square image, views, bins > 0, "
+                  "fan_src > 0, fan_det >= 0, fan_du > 0");
+        return NYS_EINVAL;
+      }
+      op->M = static_cast<int64_t>(d.n_views) * d.n_bins;
       break;
     }
     case NYS_OP_PARALLEL_BEAM: {

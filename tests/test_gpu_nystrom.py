@@ -263,6 +263,15 @@ def _solve_pair(P, prob_kind, dt, with_pc, iters):
         prob.levels, prob.wavelet = 4, "db4"
         op = P.Operator(P.OP_BLURDOWN, 64, 64, psf=prob.h, factor=2, wavelet_levels=4, wavelet="db4")
         reg, lam, loss, delta, ell = "l1", prob.lam, P.LOSS_HUBER, prob.delta, 8
+    elif prob_kind == "fan_tv":
+        # fan-beam CT (views over 360 degrees, flat detector) with TV
+        wl = W.workload("ct512_hs1_f32")
+        geo, V, B = (64.0, 32.0, 1.0), 24, 56
+        prob = sv.Problem("fan", 32, None, wl.lam, "tv", views=V, bins=B, fan=geo)
+        clean = prob.A(W.phantom_ellipses(32, 4))
+        prob.y = clean + wl.noise_rel_max * np.max(clean) * W.gaussian(clean.shape, 4)
+        op = P.Operator(P.OP_FAN_BEAM, 32, 32, views=V, bins=B, fan=geo)
+        reg, lam, loss, delta, ell = "tv", prob.lam, P.LOSS_LS, 0.0, 10
     else:
         wl = W.workload("ct512_hs1_f32")
         prob, _ = sv.problem_from_workload(wl, seed=4, n=32, views=36, bins=48)
@@ -317,7 +326,8 @@ def test_solve_nonnegative_matches_oracle():
 @pytest.mark.parametrize("kind,dt,with_pc", [("deblur_tv", "f64", False), ("deblur_tv", "f64", True),
                                              ("sr_l1", "f32", False), ("sr_l1", "f32", True),
                                              ("sr_l1_db4", "f64", True), ("sr_l1_db4", "f32", True),
-                                             ("ct_hs1", "f32", True)])
+                                             ("ct_hs1", "f32", True), ("fan_tv", "f64", True),
+                                             ("fan_tv", "f32", False)])
 def test_solve_matches_oracle(kind, dt, with_pc):
     P = need_gpu()
     banner(f"solve {kind} {dt} pc={with_pc}")

@@ -175,6 +175,58 @@ def test_sketch_ct_f32():
     assert rel(host(Y), ref) < TOL["f32"]
 
 
+FAN_CASES = [(32, 24, 45, (64.0, 32.0, 1.0)), (47, 13, 70, (90.0, 45.0, 1.3)),
+             (64, 36, 92, (128.0, 64.0, 1.5))]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n,V,B,geo", FAN_CASES)
+def test_fan_pair(dt, n, V, B, geo):
+    """Fan-beam Joseph projector (views over 360 degrees, flat detector) and
+    its atomically scattered transpose against the oracle."""
+    P = need_gpu()
+    banner(f"fan {dt} n={n} V={V} B={B} geo={geo}")
+    op = P.Operator(P.OP_FAN_BEAM, n, n, views=V, bins=B, fan=geo)
+    x = W.gaussian((2, n, n), 4)
+    xd = dev(x, dt)
+    p = P.op_forward(op, xd)
+    assert p.shape == (2, V, B)
+    assert rel(host(p), ops.fan_joseph(host(xd), V, B, *geo)) < TOL[dt]
+    q = dev(W.gaussian((2, V, B), 5), dt)
+    z = P.op_adjoint(op, q)
+    assert rel(host(z), ops.fan_joseph_adjoint(host(q), n, *geo)) < TOL[dt]
+    lhs = float((p.double() * q.double()).sum())
+    rhs = float((xd.double() * z.double()).sum())
+    assert abs(lhs - rhs) <= 10 * TOL[dt] * abs(lhs)
+
+
+def test_fan_full_size_f32():
+    """The paper's fan-beam acquisition: 512^2 image, 100 views over 360
+    degrees, 1024 detector bins (source and detector radii 1024 and 512
+    pixels, bins 1.5 pixels apart), forward and adjoint against the oracle."""
+    P = need_gpu()
+    banner("fan full size 512^2 100x1024 f32")
+    n, V, B, geo = 512, 100, 1024, (1024.0, 512.0, 1.5)
+    op = P.Operator(P.OP_FAN_BEAM, n, n, views=V, bins=B, fan=geo)
+    xd = dev(W.phantom_ellipses(n, 11), "f32")
+    p = P.op_forward(op, xd)
+    assert rel(host(p), ops.fan_joseph(host(xd), V, B, *geo)) < TOL["f32"]
+    q = dev(W.gaussian((V, B), 12), "f32")
+    assert rel(host(P.op_adjoint(op, q)), ops.fan_joseph_adjoint(host(q), n, *geo)) < TOL["f32"]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_sketch_fan(dt):
+    P = need_gpu()
+    banner(f"sketch fan {dt}")
+    n, V, B, ell, geo = 48, 30, 70, 3, (96.0, 48.0, 1.2)
+    op = P.Operator(P.OP_FAN_BEAM, n, n, views=V, bins=B, fan=geo)
+    om = dev(W.omega(ell, n, n, 8), dt)
+    Y = P.nys_sketch(op, om)
+    ref = ops.fan_joseph_adjoint(ops.fan_joseph(host(om), V, B, *geo), n, *geo)
+    assert rel(host(Y), ref) < TOL[dt]
+
+
 def test_sketch_sr_full_size_sampled_columns():
     """512^2 super-resolution workload, ell = 64, BF16: the timed launch
     configuration; the oracle checks 3 sampled columns."""
@@ -202,3 +254,5 @@ def test_operator_argument_errors():
         P.Operator(P.OP_BLURDOWN, 15, 16, psf=np.ones((3, 3)) / 9, factor=2)
     with pytest.raises(P.NysError):
         P.Operator(P.OP_PARALLEL_BEAM, 16, 12, views=4, bins=5)
+    with pytest.raises(P.NysError):
+        P.Operator(P.OP_FAN_BEAM, 16, 16, views=4, bins=5, fan=(0.0, 8.0, 1.0))   # no source radius
