@@ -145,6 +145,11 @@ struct nys_op_s {
   nys::DevBuf tmp2;               // scratch of the Daubechies-4 passes and of the
                                   // fan-beam adjoint's accumulation (narrow outputs)
   mutable nys::DevBuf xT;         // transposed images (parallel-beam forward)
+  // fan beam: per view cos, sin (f64), then per ray (view-major) f0, g and the
+  // step-length scale signed + for steps along rows, - along columns (f64);
+  // filled at creation when the gathered adjoint applies (fan_gather)
+  nys::DevBuf rays;
+  bool fan_gather = false;
 };
 
 struct nys_pc_s {

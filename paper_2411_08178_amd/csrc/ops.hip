@@ -796,6 +796,102 @@ __global__ __launch_bounds__(256) void fan_adj_kernel(const SI* __restrict__ p, 
   }
 }
 
+// Ray table for the gathered adjoint (one thread per ray, plus the per-view
+// trigonometry from the rays of bin 0).
+__global__ __launch_bounds__(256) void fan_table_kernel(double* __restrict__ tab, int n, int V,
+                                                        int B, double src, double det, double du) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= V * B) return;
+  const int v = r / B, b = r - v * B;
+  double cs, sn, s, f0, g, scale;
+  fan_ray(v, b, V, B, src, det, du, cs, sn, s);
+  bool rows;
+  int t0, t1;
+  fan_steps(cs, sn, s, n, rows, f0, g, scale, t0, t1);
+  double* e = tab + 2 * static_cast<size_t>(V) + 3 * static_cast<size_t>(r);
+  e[0] = f0;
+  e[1] = g;
+  e[2] = rows ? scale : -scale;
+  if (b == 0) {
+    const double th = 2.0 * M_PI * v / V;
+    tab[2 * v] = cos(th);
+    tab[2 * v + 1] = sin(th);
+  }
+}
+
+// Fractional bin of the ray from the source through the point (X, Y) (offsets
+// from the image centre, X along columns): the source is at -src d0 and the
+// detector at det d0, d0 = (-sin, cos), bins along e = (cos, sin).
+__device__ __forceinline__ double fan_bin(double X, double Y, double ce, double se, double Rt,
+                                          double src, double inv_du, double half) {
+  return Rt * (X * ce + Y * se) / (src + (Y * ce - X * se)) * inv_du + half;
+}
+
+// x = A^T p gathered pixel by pixel (source outside the image's circumscribed
+// circle).  A ray stepping along rows samples pixel (i, j) at its step t = i
+// iff it crosses row i within one pixel of column j; the rays from the source
+// through that two-pixel segment are a bin interval (the bin of a point is
+// monotone along any segment that misses the source).  Likewise for rays
+// stepping along columns and the column segment.  Every candidate repeats the
+// forward's own sample, so the weights are the transpose's.
+template <class SI, class SO, class C>
+__global__ __launch_bounds__(256) void fan_adj_gather_kernel(
+    const SI* __restrict__ p, SO* __restrict__ x, const double* __restrict__ tab, int n, int V,
+    int B, double src, double det, double du) {
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  const int i = blockIdx.y * 4 + threadIdx.y;
+  if (i >= n || j >= n) return;
+  const double c = 0.5 * (n - 1), half = 0.5 * (B - 1), inv_du = 1.0 / du, Rt = src + det;
+  const double X = j - c, Y = i - c;
+  const SI* pz = p + static_cast<size_t>(blockIdx.z) * V * B;
+  const double* rays = tab + 2 * static_cast<size_t>(V);
+  C acc = 0;
+  for (int v = 0; v < V; ++v) {
+    const double ce = tab[2 * v], se = tab[2 * v + 1];
+    const SI* pv = pz + static_cast<size_t>(v) * B;
+    const double* rv = rays + 3 * static_cast<size_t>(v) * B;
+    // rays stepping along rows, through the segment of row i
+    {
+      const double b1 = fan_bin(X - 1.0, Y, ce, se, Rt, src, inv_du, half);
+      const double b2 = fan_bin(X + 1.0, Y, ce, se, Rt, src, inv_du, half);
+      const int lo = max(0, static_cast<int>(ceil(fmax(fmin(b1, b2), -1.0))));
+      const int hi = min(B - 1, static_cast<int>(floor(fmin(fmax(b1, b2), static_cast<double>(B)))));
+      for (int b = lo; b <= hi; ++b) {
+        const double* e = rv + 3 * b;
+        const double sc = e[2];
+        if (sc <= 0.0) continue;
+        const double f = e[0] + (i - c) * e[1];
+        const double fl = floor(f);
+        const int q = static_cast<int>(fl);
+        const C w = static_cast<C>(f - fl);
+        const C val = static_cast<C>(sc) * static_cast<C>(Io<SI>::ld(pv, b));
+        if (q == j) acc += (C(1) - w) * val;
+        else if (q == j - 1) acc += w * val;
+      }
+    }
+    // rays stepping along columns, through the segment of column j
+    {
+      const double b1 = fan_bin(X, Y - 1.0, ce, se, Rt, src, inv_du, half);
+      const double b2 = fan_bin(X, Y + 1.0, ce, se, Rt, src, inv_du, half);
+      const int lo = max(0, static_cast<int>(ceil(fmax(fmin(b1, b2), -1.0))));
+      const int hi = min(B - 1, static_cast<int>(floor(fmin(fmax(b1, b2), static_cast<double>(B)))));
+      for (int b = lo; b <= hi; ++b) {
+        const double* e = rv + 3 * b;
+        const double sc = e[2];
+        if (sc >= 0.0) continue;
+        const double f = e[0] + (j - c) * e[1];
+        const double fl = floor(f);
+        const int q = static_cast<int>(fl);
+        const C w = static_cast<C>(f - fl);
+        const C val = static_cast<C>(-sc) * static_cast<C>(Io<SI>::ld(pv, b));
+        if (q == i) acc += (C(1) - w) * val;
+        else if (q == i - 1) acc += w * val;
+      }
+    }
+  }
+  Io<SO>::st(x + static_cast<size_t>(blockIdx.z) * n * n, static_cast<size_t>(i) * n + j, acc);
+}
+
 template <class SI, class SO, class C>
 static nys_status launch_fan_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t ncols,
                                  hipStream_t st) {
@@ -809,6 +905,13 @@ static nys_status launch_fan_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t
 template <class SI, class SO, class C>
 static nys_status launch_fan_adj(nys_op_s* op, const SI* p, SO* x, int64_t ncols, hipStream_t st) {
   const auto& d = op->d;
+  if (op->fan_gather) {
+    dim3 grid(cdiv(d.n1, 64), cdiv(d.n1, 4), static_cast<unsigned>(ncols));
+    hipLaunchKernelGGL((fan_adj_gather_kernel<SI, SO, C>), grid, dim3(64, 4), 0, st, p, x,
+                       op->rays.as<double>(), d.n1, d.n_views, d.n_bins, d.fan_src, d.fan_det,
+                       d.fan_du);
+    return launch_check("fan_adj_gather_kernel");
+  }
   const size_t n = static_cast<size_t>(d.n1) * d.n2 * ncols;
   C* acc;
   if constexpr (std::is_same<SO, C>::value) {
@@ -1066,6 +1169,28 @@ extern "C" nys_status nys_op_create(const nys_op_desc* desc, nys_op* out) {
         return NYS_EINVAL;
       }
       op->M = static_cast<int64_t>(d.n_views) * d.n_bins;
+      // the gathered adjoint needs the source outside the circle through the
+      // corners of the image grown by one pixel (n > that radius for n >= 4)
+      op->fan_gather = d.fan_src > d.n1 && d.n1 >= 4;
+      if (op->fan_gather) {
+        const size_t nt = 2 * static_cast<size_t>(d.n_views) + 3 * static_cast<size_t>(op->M);
+        nys_status s = op->rays.ensure(nt * sizeof(double));
+        if (s == NYS_OK) {
+          hipLaunchKernelGGL(fan_table_kernel, dim3(cdiv(op->M, 256)), dim3(256), 0, nullptr,
+                             op->rays.as<double>(), d.n1, d.n_views, d.n_bins, d.fan_src,
+                             d.fan_det, d.fan_du);
+          s = launch_check("fan_table_kernel");
+        }
+        if (s == NYS_OK && hipStreamSynchronize(nullptr) != hipSuccess) {
+          set_error("nys_op_create: fan-beam ray table failed");
+          s = NYS_EHIP;
+        }
+        if (s != NYS_OK) {
+          op->rays.release();
+          delete op;
+          return s;
+        }
+      }
       break;
     }
     case NYS_OP_PARALLEL_BEAM: {
@@ -1126,6 +1251,7 @@ extern "C" void nys_op_destroy(nys_op op) {
   op->tmp0.release();
   op->tmp1.release();
   op->tmp2.release();
+  op->rays.release();
   delete op;
 }
 

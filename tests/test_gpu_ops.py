@@ -175,15 +175,18 @@ def test_sketch_ct_f32():
     assert rel(host(Y), ref) < TOL["f32"]
 
 
+# the last case has the source radius below the image side: its adjoint is
+# the atomically scattered one, the others' the gathered one
 FAN_CASES = [(32, 24, 45, (64.0, 32.0, 1.0)), (47, 13, 70, (90.0, 45.0, 1.3)),
-             (64, 36, 92, (128.0, 64.0, 1.5))]
+             (64, 36, 92, (128.0, 64.0, 1.5)), (32, 20, 50, (30.0, 10.0, 1.0))]
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("n,V,B,geo", FAN_CASES)
 def test_fan_pair(dt, n, V, B, geo):
     """Fan-beam Joseph projector (views over 360 degrees, flat detector) and
-    its atomically scattered transpose against the oracle."""
+    its transpose (gathered per pixel, or scattered per ray) against the
+    oracle."""
     P = need_gpu()
     banner(f"fan {dt} n={n} V={V} B={B} geo={geo}")
     op = P.Operator(P.OP_FAN_BEAM, n, n, views=V, bins=B, fan=geo)
