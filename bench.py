@@ -14,7 +14,7 @@ solve with exactly that many iterations and no cost recording.
 
 Prints one JSON line.  Usage:
     python bench.py [--steps K] [--warmup W]
-                    [--workload sr512|ct512|deblur128|batch64|irm256]
+                    [--workload sr512|ct512|fan512|deblur128|batch64|irm256]
                     [--no-cpu-baseline] [--copy-calibration]
 
 The batched workload (64 deblurring problems of uneven sizes, one graph
@@ -45,9 +45,18 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD_KEYS = {
     "sr512": "sr512_haar_bf16",
     "ct512": "ct512_hs1_f32",
+    "fan512": "fan512_tv_f32",
     "deblur128": "deblur128_tv_f64",
     "batch64": "batch64_deblur_f32",
     "irm256": "irm256_l1l1_f32",
+}
+
+# The paper's wall time for building the preconditioner (Table II; an RTX
+# 3090, 512^2 image, 100 views) where a workload has its geometry, prior and
+# sketch size: context only, another machine and another implementation.
+PAPER_BUILD_S = {
+    "fan512_tv_f32": {"value": 0.09, "unit": "s", "gpu": "RTX 3090", "table": "II",
+                      "geometry": "fan beam", "reg": "tv", "K": 20},
 }
 
 
@@ -66,8 +75,12 @@ class Setup:
         tdt = {"f64": torch.float64, "f32": torch.float32}[wl.dtype]
         sdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[wl.sketch_dtype]
         self.tdt, self.sdt = tdt, sdt
-        if wl.op == "ct":
-            self.op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=wl.views, bins=wl.bins)
+        if wl.op in ("ct", "fan"):
+            if wl.op == "ct":
+                self.op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=wl.views, bins=wl.bins)
+            else:
+                self.op = P.Operator(P.OP_FAN_BEAM, n, n, views=wl.views, bins=wl.bins,
+                                     fan=wl.fan)
             xt = W.phantom_ellipses(n, seed)
             clean = P.op_forward(self.op, torch.from_numpy(xt).to(tdt).cuda())
             cmax = float(clean.abs().max())
@@ -108,6 +121,8 @@ def run_pc(P, S, iters, power_iters, record_cost, ev=None):
     if ev is not None:
         ev[1].record()
     pc = P.nys_factor(S.omega, S.Y, S.wl.ell, u_dtype=S.tdt, tail=getattr(S, "tail", "sqrt"))
+    if ev is not None:
+        ev[2].record()
     x, costs, info = P.solve(S.op, S.y, S.rd, S.wl.lam, pc, iters, power_v0=S.v0,
                              power_iters=power_iters, loss=S.loss, delta=S.delta,
                              record_cost=record_cost)
@@ -615,18 +630,19 @@ def main():
     torch.cuda.synchronize()
     sk_ms = []
     pcs = []
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3 * args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
     for s in range(args.steps):
-        _, _, _, pc = run_pc(P, S, kp, args.power_iters, False, ev=ev[2 * s:2 * s + 2])
+        _, _, _, pc = run_pc(P, S, kp, args.power_iters, False, ev=ev[3 * s:3 * s + 3])
         pcs.append(pc)
     t_end.record(stream)
     torch.cuda.synchronize()
     ms_pc = t_start.elapsed_time(t_end) / args.steps
-    sk_ms = [ev[2 * s].elapsed_time(ev[2 * s + 1]) for s in range(args.steps)]
+    sk_ms = [ev[3 * s].elapsed_time(ev[3 * s + 1]) for s in range(args.steps)]
+    build_ms = [ev[3 * s].elapsed_time(ev[3 * s + 2]) for s in range(args.steps)]
     del pcs
 
     # ---- timed: plain APG
@@ -688,7 +704,12 @@ def main():
         "fstar": fstar, "fstar_resolved": bool(fstar_resolved),
         "L": {"precond": info_pc["L"], "plain": info_pl["L"]},
         "roofline": roof,
+        # building the preconditioner (sketch + factorisation) inside the
+        # timed steps, from the stream's events
+        "precond_build_s": round(float(np.mean(build_ms)) / 1e3, 6),
     }
+    if wl.name in PAPER_BUILD_S:
+        out["paper_precond_build_s"] = PAPER_BUILD_S[wl.name]
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(wl, kp, args.power_iters, info_pc["alpha"], args.seed)

@@ -206,11 +206,11 @@ def problem_from_workload(wl, seed: int = 0, n: Optional[int] = None,
     """Build the synthetic problem of a workload with the oracle's operator."""
     import workloads as W
     n = wl.n if n is None else n
-    if wl.op == "ct":
+    if wl.op in ("ct", "fan"):
         views = wl.views if views is None else views
         bins = wl.bins if bins is None else bins
         xt = W.phantom_ellipses(n, seed)
-        p = Problem("ct", n, None, wl.lam, wl.reg, views=views, bins=bins)
+        p = Problem(wl.op, n, None, wl.lam, wl.reg, views=views, bins=bins, fan=wl.fan)
         clean = p.A(xt)
         y = clean + wl.noise_rel_max * np.max(clean) * W.gaussian(clean.shape, seed)
     else:

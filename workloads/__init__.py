@@ -143,7 +143,7 @@ def round_dtype(a: np.ndarray, dtype: str) -> np.ndarray:
 class Workload:
     """One benchmark workload; sizes and parameters only."""
     name: str
-    op: str                 # 'blur' | 'blurdown' | 'ct'
+    op: str                 # 'blur' | 'blurdown' | 'ct' | 'fan'
     n: int                  # image side (high resolution for 'blurdown')
     reg: str                # 'tv' | 'hs1' | 'l1haar3'
     lam: float
@@ -164,6 +164,7 @@ class Workload:
     inner: int = 20
     count: int = 1          # instances (the batched workload)
     smooth_eps: float = 0.0 # |r| -> sqrt(r^2 + eps) in the IRM weights
+    fan: tuple = (0.0, 0.0, 1.0)   # 'fan': source radius, detector radius, bin spacing (pixels)
 
     @property
     def m_shape(self):
@@ -188,6 +189,15 @@ WORKLOADS = {
     "ct512_hs1_f32": Workload(
         "ct512_hs1_f32", "ct", 512, "hs1", 2e-4, 100, "f32", "f32",
         views=720, bins=736, noise_rel_max=0.01, outer=200, inner=20),
+    # 512^2 fan-beam CT as in the paper's preconditioner timing (100 views
+    # over 360 degrees, 1024 bins over a detector 3x the image width: bins
+    # 1.5 pixels apart; source and detector 1024 and 512 pixels from the
+    # centre), TV, ell = 20; lambda = 2e-3, the smallest of {2e-4, 2e-3,
+    # 1e-2, 5e-2} at which plain APG reaches the 1e-4 gap within 6000 its.
+    "fan512_tv_f32": Workload(
+        "fan512_tv_f32", "fan", 512, "tv", 2e-3, 20, "f32", "f32",
+        views=100, bins=1024, noise_rel_max=0.01, outer=200, inner=20,
+        fan=(1024.0, 512.0, 1.5)),
     # 256^2 CT for the unrolled solver, 180 views x 367 bins, TV, ell = 48.
     "ct256_tv_unrolled": Workload(
         "ct256_tv_unrolled", "ct", 256, "tv", 2e-4, 48, "f32", "f32",
