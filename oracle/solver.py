@@ -152,6 +152,19 @@ def lipschitz(problem, pc: Optional[Precond], v0, iters):
     return problem.curvature() * nys.power_iteration(M, v0.reshape(-1), iters)
 
 
+def rate_constant(problem, pc: Optional[Precond], x_star, v0, iters, x1=None):
+    """L_f^P ||x^1 - x*||_P^2, the constant of the O(1/k^2) bound on WAPG's cost
+    gap (twice it over (k + 1)^2, stated after eq. (15), Sec. IV-B), whose
+    dependence on the sketch size the CT experiments study.  x^1 is the start
+    of Alg. 3 (zero unless given); L_f^P by the power method of `lipschitz`;
+    P = I without a preconditioner."""
+    L = lipschitz(problem, pc, v0, iters)
+    d = (np.zeros_like(x_star) if x1 is None else np.asarray(x1, np.float64)) - x_star
+    pd = d if pc is None else pc.p(d)
+    d2 = float(np.sum(d * pd))
+    return dict(L=L, pdist2=d2, value=L * d2)
+
+
 def wapg(problem: Problem, pc: Optional[Precond], alpha: float, outer: int,
          inner: int = 20, warm_start: bool = True, ssn_tol: float = 1e-12,
          ssn_maxit: int = 100, x0=None, record_cost: bool = True):
