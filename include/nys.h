@@ -181,6 +181,19 @@ nys_status nys_pc_copy_u(nys_pc pc, void* dst, void* stream);
 nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
                      void* out, int64_t ncols, void* stream);
 
+/* Squared P-norm of a difference, the metric of the WAPG rate bound
+ * 2 L_f^P ||x^1 - x^*||_P^2 / (k + 1)^2 stated after eq. (15) (Sec. IV-B):
+ * *out (one device double, written on `stream`) = (a - b)^T P (a - b), or
+ * (a - b)^T P^{-1} (a - b) when inverse != 0; pc = NULL gives P = I.  a, b:
+ * n device values (n = the pc's N, dtype = its u_dtype; F64 or F32 without
+ * a pc); b may be NULL (b = 0).  With a pc the difference and P (a - b) are
+ * rounded to dt; the dot product accumulates in FP64 (without a pc by atomic
+ * additions of block sums, so its last bits depend on their order).  Uses a
+ * workspace held by the pc (allocated on the first call): calls on one pc
+ * must not overlap. */
+nys_status nys_pnorm2(nys_pc pc, int64_t n, int32_t inverse, nys_dtype dt, const void* a,
+                      const void* b, double* out, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Weighted proximal map (definition in Sec. I-D):
  *   x = argmin_u  lambda_bar g(u) + 1/2 ||u - s||_P^2,   C = R^N,

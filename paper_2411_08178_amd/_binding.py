@@ -109,6 +109,7 @@ def lib():
             "nys_pc_diag": [vp, C.POINTER(dbl), i32, vp],
             "nys_pc_copy_u": [vp, vp, vp],
             "nys_apply": [vp, i32, i32, vp, vp, i64, vp],
+            "nys_pnorm2": [vp, i64, i32, i32, vp, vp, vp, vp],
             "prox_weighted": [C.POINTER(RegDesc), dbl, vp, i32, vp, vp, vp, vp],
             "nys_prox_state_bytes": [C.POINTER(RegDesc), vp, i32, C.POINTER(C.c_size_t)],
             "solve": [C.POINTER(Problem), vp, i32, C.POINTER(SolveOpts), vp, vp,
@@ -309,6 +310,32 @@ def nys_apply(pc: Preconditioner, v: torch.Tensor, inverse: bool = True,
     _check(lib().nys_apply(pc.handle, 1 if inverse else 0, _dt(v), _ptr(v), _ptr(out), n,
                            _stream()))
     return out
+
+
+def pnorm2(pc: Optional[Preconditioner], a: torch.Tensor, b: Optional[torch.Tensor] = None,
+           inverse: bool = False) -> float:
+    """(a - b)^T P (a - b) (P^{-1} with inverse; P = I without a pc), FP64."""
+    n = a.numel()
+    if b is not None and (b.shape != a.shape or b.dtype != a.dtype):
+        raise ValueError("pnorm2: a and b must share shape and dtype")
+    out = torch.empty(1, dtype=torch.float64, device=a.device)
+    _check(lib().nys_pnorm2(pc.handle if pc is not None else None, n, 1 if inverse else 0,
+                            _dt(a), _ptr(a), _ptr(b) if b is not None else None, _ptr(out),
+                            _stream()))
+    return float(out.item())
+
+
+def rate_constant(op, y, reg, lam, pc: Optional[Preconditioner], x_star: torch.Tensor,
+                  x1: Optional[torch.Tensor] = None, power_iters: int = 100,
+                  power_v0: Optional[torch.Tensor] = None, loss: int = 0, delta: float = 0.0):
+    """L_f^P ||x^1 - x*||_P^2, the constant of WAPG's rate bound (the cost gap
+    after k iterations is at most twice it over (k + 1)^2).  x^1 is the
+    start (zero by default, as the solver starts); L_f^P from the solver's
+    power method; returns dict(L, pdist2, value)."""
+    _, _, info = solve(op, y, reg, lam, pc, 1, power_v0=power_v0, power_iters=power_iters,
+                       loss=loss, delta=delta, record_cost=False)
+    d2 = pnorm2(pc, x_star.contiguous(), x1.contiguous() if x1 is not None else None)
+    return dict(L=info["L"], pdist2=d2, value=info["L"] * d2)
 
 
 def reg_desc(kind, n1, n2, n_inner=20, lnorm2=0.0, max_newton=0, newton_tol=0.0,

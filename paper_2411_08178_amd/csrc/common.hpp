@@ -164,6 +164,7 @@ struct nys_pc_s {
   nys::DevBuf work;               // scratch of nys_apply / prox
   nys::DevBuf work2;              // cd of nys_apply / the gradient step
   nys::DevBuf ssn_ws;             // semismooth Newton state, partials, stored LU factors
+  nys::DevBuf pn_ws;              // P-norm: difference, P times it, block partials
   // pinned, coherent host word (8 seq + outcome bits) written by the
   // semismooth Newton decision kernel and read by the host without a stream
   // synchronisation; the sequence number counts decisions

@@ -924,6 +924,7 @@ extern "C" void nys_pc_destroy(nys_pc pc) {
   pc->work.release();
   pc->work2.release();
   pc->ssn_ws.release();
+  pc->pn_ws.release();
   if (pc->hflag) (void)hipHostFree(pc->hflag);
   delete pc;
 }
@@ -972,6 +973,114 @@ extern "C" nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const 
                             ncols, st);
   return pc_apply<float>(pc, inverse != 0, static_cast<const float*>(v), static_cast<float*>(out),
                          ncols, st);
+}
+
+// ---------------------------------------------------------------- P-norm
+// (a - b)^T P (a - b): the difference, P (or P^{-1}) applied to it by the
+// regular two-pass application, then an FP64 dot product (block partials and
+// one summing block).
+template <class T>
+__global__ __launch_bounds__(256) void pdiff_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                                                    T* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    d[i] = b ? static_cast<T>(a[i] - b[i]) : a[i];
+}
+
+__device__ __forceinline__ double block_sum_256(double s) {
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void pdot_partial_kernel(const T* __restrict__ d,
+                                                           const T* __restrict__ w, int64_t n,
+                                                           double* __restrict__ part) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s += static_cast<double>(d[i]) * static_cast<double>(w[i]);
+  s = block_sum_256(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// P = I: block sums of (a - b)^2 added to *out (zeroed by the caller).
+template <class T>
+__global__ __launch_bounds__(256) void pdot_plain_kernel(const T* __restrict__ a,
+                                                         const T* __restrict__ b, int64_t n,
+                                                         double* __restrict__ out) {
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double di = static_cast<double>(a[i]) - (b ? static_cast<double>(b[i]) : 0.0);
+    s += di * di;
+  }
+  s = block_sum_256(s);
+  if (threadIdx.x == 0) atomicAdd(out, s);
+}
+
+__global__ void pzero_kernel(double* out) {
+  if (threadIdx.x == 0) out[0] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void pdot_final_kernel(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ out) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+  s = block_sum_256(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+template <class T>
+static nys_status pnorm2_impl(nys_pc pc, int64_t n, bool inverse, const T* a, const T* b,
+                              double* out, hipStream_t st) {
+  if (!pc) {
+    hipLaunchKernelGGL(pzero_kernel, dim3(1), dim3(64), 0, st, out);
+    NYS_TRY(launch_check("pzero_kernel"));
+    hipLaunchKernelGGL((pdot_plain_kernel<T>), dim3(std::min<unsigned>(cdiv(n, 256), 1024)),
+                       dim3(256), 0, st, a, b, n, out);
+    return launch_check("pdot_plain_kernel");
+  }
+  const int64_t N = pc->N;
+  const size_t vb = (static_cast<size_t>(N) * sizeof(T) + 255) / 256 * 256;
+  constexpr int kMaxPart = 1024;
+  NYS_TRY(pc->pn_ws.ensure(2 * vb + kMaxPart * sizeof(double)));
+  char* base = pc->pn_ws.as<char>();
+  T* d = reinterpret_cast<T*>(base);
+  T* w = reinterpret_cast<T*>(base + vb);
+  double* part = reinterpret_cast<double*>(base + 2 * vb);
+  const unsigned nb = std::min<unsigned>(cdiv(N, 256), kMaxPart);
+  hipLaunchKernelGGL((pdiff_kernel<T>), dim3(std::min<unsigned>(cdiv(N, 256), 4096)), dim3(256), 0,
+                     st, a, b, d, N);
+  NYS_TRY(launch_check("pdiff_kernel"));
+  NYS_TRY(pc_apply<T>(pc, inverse, d, w, 1, st));
+  hipLaunchKernelGGL((pdot_partial_kernel<T>), dim3(nb), dim3(256), 0, st, d, w, N, part);
+  NYS_TRY(launch_check("pdot_partial_kernel"));
+  hipLaunchKernelGGL(pdot_final_kernel, dim3(1), dim3(256), 0, st, part, static_cast<int>(nb), out);
+  return launch_check("pdot_final_kernel");
+}
+
+extern "C" nys_status nys_pnorm2(nys_pc pc, int64_t n, int32_t inverse, nys_dtype dt,
+                                 const void* a, const void* b, double* out, void* stream) {
+  NYS_REQUIRE(a && out && n > 0, "nys_pnorm2: bad argument");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "nys_pnorm2: dtype must be F64 or F32");
+  if (pc) {
+    NYS_REQUIRE(n == pc->N, "nys_pnorm2: n must equal the pc's N");
+    NYS_REQUIRE(static_cast<int32_t>(dt) == pc->u_dtype,
+                "nys_pnorm2: dtype must equal the pc's u_dtype");
+  }
+  hipStream_t st = as_stream(stream);
+  if (dt == NYS_F64)
+    return pnorm2_impl<double>(pc, n, inverse != 0, static_cast<const double*>(a),
+                               static_cast<const double*>(b), out, st);
+  return pnorm2_impl<float>(pc, n, inverse != 0, static_cast<const float*>(a),
+                            static_cast<const float*>(b), out, st);
 }
 
 extern "C" nys_status nys_pc_diag(nys_pc pc, double* out, int32_t n, void* stream) {

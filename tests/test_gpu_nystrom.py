@@ -385,3 +385,65 @@ def test_solve_power_method_step():
     prob = sv.Problem("blur", n, host(y), 1e-3, "tv", h=h)
     Lr = sv.lipschitz(prob, None, host(v0), 300)
     assert abs(info["L"] - Lr) < 1e-10
+
+
+def _deblur_pc(P, dt, ell, n=40):
+    """A 40^2 deblurring problem with the preconditioner built on both sides
+    from the oracle's sketch of the same Omega."""
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=2, n=n)
+    om = W.omega(ell, n, n, 20)
+    omd = dev(om, dt)
+    Yd = dev(sv.sketch(prob, host(omd)), dt)
+    ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+    pc = P.nys_factor(omd, Yd, ell, u_dtype=torch.float64 if dt == "f64" else torch.float32)
+    return prob, opc, pc
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_pnorm2_matches_oracle(dt):
+    """(a - b)^T P (a - b), with P^{-1}, and P = I, against the oracle's P."""
+    P = need_gpu()
+    banner(f"pnorm2 {dt}")
+    prob, opc, pc = _deblur_pc(P, dt, 8)
+    n = prob.n
+    ad, bd = dev(W.gaussian((n, n), 30), dt), dev(W.gaussian((n, n), 31), dt)
+    d = host(ad) - host(bd)
+    for inverse in (False, True):
+        got = P.pnorm2(pc, ad, bd, inverse=inverse)
+        ref = float(np.sum(d * (opc.pinv(d) if inverse else opc.p(d))))
+        assert abs(got - ref) <= TOL[dt] * abs(ref)
+    got = P.pnorm2(pc, ad)
+    ref = float(np.sum(host(ad) * opc.p(host(ad))))
+    assert abs(got - ref) <= TOL[dt] * abs(ref)
+    got = P.pnorm2(None, ad, bd)
+    assert abs(got - float(np.sum(d * d))) <= TOL[dt] * float(np.sum(d * d))
+
+
+@pytest.mark.parametrize("ell", [0, 4, 16])
+def test_rate_constant_matches_oracle_across_sketch_sizes(ell):
+    """L_f^P ||x^1 - x*||_P^2 (x^1 = 0, x* from 40 oracle WAPG iterations) for
+    plain APG and two sketch sizes, FP64."""
+    P = need_gpu()
+    banner(f"rate constant ell={ell}")
+    if ell:
+        prob, opc, pc = _deblur_pc(P, "f64", ell)
+    else:
+        wl = W.workload("deblur128_tv_f64")
+        prob, _ = sv.problem_from_workload(wl, seed=2, n=40)
+        opc = pc = None
+    n = prob.n
+    op = P.Operator(P.OP_BLUR, n, n, psf=prob.h)
+    yd = dev(prob.y, "f64")
+    prob.y = host(yd)
+    v0 = W.gaussian((n, n), 21)
+    alpha = 0.9 / sv.lipschitz(prob, opc, v0, 200)
+    xs, _ = sv.wapg(prob, opc, alpha, 40, inner=10, record_cost=False)
+    rd = P.reg_desc("tv", n, n, n_inner=10)
+    got = P.rate_constant(op, yd, rd, prob.lam, pc, dev(xs, "f64"), power_iters=60,
+                          power_v0=dev(v0, "f64"))
+    ref = sv.rate_constant(prob, opc, xs, v0, 60)
+    assert abs(got["L"] - ref["L"]) <= 1e-9 * ref["L"]
+    assert abs(got["pdist2"] - ref["pdist2"]) <= 1e-10 * ref["pdist2"]
+    assert abs(got["value"] - ref["value"]) <= 1e-9 * ref["value"]
