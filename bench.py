@@ -6,6 +6,11 @@ steps 3-8), the step size by the power method, and WAPG (Alg. 3) run for the
 number of outer iterations that reaches a relative cost gap of 1e-4.  Plain
 APG (P = I, with its own power method) is timed the same way beside it.
 
+--rate-sweep K1,K2,... prints instead the constant L_f^P ||x^1 - x*||_P^2 of
+WAPG's rate bound for plain APG and each sketch size (x^1 = 0, x* from a long
+preconditioned run at the workload's own sketch size): the sketch-size study
+of the CT experiments on the synthetic workload.
+
 Inputs are synthetic and seeded (module `workloads`), already resident in
 HBM when the timed region starts.  F* is the smallest cost seen over long
 untimed runs of both methods; the iteration counts that reach the gap are
@@ -16,6 +21,7 @@ Prints one JSON line.  Usage:
     python bench.py [--steps K] [--warmup W]
                     [--workload sr512|ct512|fan512|deblur128|batch64|irm256]
                     [--no-cpu-baseline] [--copy-calibration]
+                    [--rate-sweep 10,20,50,100]
 
 The batched workload (64 deblurring problems of uneven sizes, one graph
 launch per solve of the whole batch) times the batch to the point where every
@@ -550,6 +556,34 @@ def main_irm(args, P, torch, wl):
 
 
 # ---------------------------------------------------------------- main
+def main_rate_sweep(args, P, torch, wl):
+    """The rate constant against the sketch size (one JSON line)."""
+    S = Setup(P, torch, wl, args.seed)
+    S.tail = args.tail
+    t0 = time.perf_counter()
+    x_star, c, _, _ = run_pc(P, S, args.ref_iters, args.power_iters, True)
+    torch.cuda.synchronize()
+    log(f"x* from {args.ref_iters} preconditioned iterations in {time.perf_counter() - t0:.1f}s, "
+        f"F = {float(c[-1]):.10g}")
+    rows = []
+    n = wl.n
+    for K in [0] + [int(k) for k in args.rate_sweep.split(",") if k]:
+        pc = None
+        if K:
+            om = torch.from_numpy(W.round_dtype(W.omega(K, n, n, args.seed), wl.sketch_dtype)) \
+                .to(S.sdt).cuda().contiguous()
+            Y = P.nys_sketch(S.op, om)
+            pc = P.nys_factor(om, Y, K, u_dtype=S.tdt, tail=args.tail)
+        r = P.rate_constant(S.op, S.y, S.rd, wl.lam, pc, x_star, power_iters=args.power_iters,
+                            power_v0=S.v0, loss=S.loss, delta=S.delta)
+        rows.append({"K": K, "L": r["L"], "pdist2": r["pdist2"], "value": r["value"]})
+        log(f"K={K}: L={r['L']:.6g} ||x*||_P^2={r['pdist2']:.6g} constant={r['value']:.6g}")
+        del pc
+    print(json.dumps({"metric": "L_f^P ||x^1 - x*||_P^2 vs sketch size (x^1 = 0)",
+                      "workload": wl.name, "tail": args.tail, "x_star_iters": args.ref_iters,
+                      "power_iters": args.power_iters, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -558,6 +592,8 @@ def main():
     ap.add_argument("--workload", default="sr512", choices=sorted(WORKLOAD_KEYS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--power-iters", type=int, default=100)
+    ap.add_argument("--rate-sweep", default="",
+                    help="comma-separated sketch sizes: print the rate constant per size")
     ap.add_argument("--ref-iters", type=int, default=20000,
                     help="iterations of the untimed F* runs of both methods")
     ap.add_argument("--tail", default="sqrt", choices=["sqrt", "plain"],
@@ -598,6 +634,8 @@ def main():
         return main_batch(args, P, torch, wl)
     if wl.name.startswith("irm"):
         return main_irm(args, P, torch, wl)
+    if args.rate_sweep:
+        return main_rate_sweep(args, P, torch, wl)
     log(f"workload {wl.name}: n={wl.n} ell={wl.ell} sketch={wl.sketch_dtype} solver={wl.dtype}")
     S = Setup(P, torch, wl, args.seed)
     torch.cuda.synchronize()
