@@ -733,22 +733,33 @@ __device__ __forceinline__ void fan_steps(double cs, double sn, double s, int n,
   }
 }
 
+// Lanes per ray (forward) and per pixel (gathered transpose): each takes a
+// contiguous share of the ray's steps (every kFanAdjSeg-th view), summed by
+// shuffles.
+constexpr int kFanSeg = 32;
+constexpr int kFanAdjSeg = 2;
+
 template <class SI, class SO, class C>
 __global__ __launch_bounds__(256) void fan_fwd_kernel(const SI* __restrict__ x, SO* __restrict__ p,
                                                       int n, int V, int B, double src, double det,
                                                       double du) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = gid / kFanSeg, seg = gid % kFanSeg;   // a ray's lanes share a wave
   const int v = blockIdx.y;
-  if (b >= B) return;
-  double cs, sn, s, f0, g, scale;
-  fan_ray(v, b, V, B, src, det, du, cs, sn, s);
-  bool rows;
-  int t0, t1;
-  fan_steps(cs, sn, s, n, rows, f0, g, scale, t0, t1);
+  const bool valid = b < B;
+  double cs = 1.0, sn = 0.0, s = 0.0, f0 = 0.0, g = 0.0, scale = 0.0;
+  bool rows = true;
+  int t0 = 0, t1 = -1;
+  if (valid) {
+    fan_ray(v, b, V, B, src, det, du, cs, sn, s);
+    fan_steps(cs, sn, s, n, rows, f0, g, scale, t0, t1);
+  }
+  const int chunk = (t1 - t0 + kFanSeg) / kFanSeg;   // ceil(len / kFanSeg), len >= 0
+  const int ta = t0 + seg * chunk, tb = min(t1, ta + chunk - 1);
   const SI* img = x + static_cast<size_t>(blockIdx.z) * n * n;
   const double c = 0.5 * (n - 1);
   C acc = 0;
-  for (int t = t0; t <= t1; ++t) {
+  for (int t = ta; t <= tb; ++t) {
     const double f = f0 + (t - c) * g;
     const double fl = floor(f);
     const int q = static_cast<int>(fl);
@@ -759,8 +770,9 @@ __global__ __launch_bounds__(256) void fan_fwd_kernel(const SI* __restrict__ x, 
     if (q >= 0 && q < n) acc += (C(1) - w) * lo;
     if (q + 1 >= 0 && q + 1 < n) acc += w * hi;
   }
-  Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b,
-             static_cast<C>(scale) * acc);
+  for (int o = kFanSeg / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kFanSeg);
+  if (valid && seg == 0)
+    Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b, static_cast<C>(scale) * acc);
 }
 
 // x += A^T p ray by ray (x zeroed by the caller): the forward's samples,
@@ -838,15 +850,17 @@ template <class SI, class SO, class C>
 __global__ __launch_bounds__(256) void fan_adj_gather_kernel(
     const SI* __restrict__ p, SO* __restrict__ x, const double* __restrict__ tab, int n, int V,
     int B, double src, double det, double du) {
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  const int i = blockIdx.y * 4 + threadIdx.y;
-  if (i >= n || j >= n) return;
+  const int64_t gid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t pix = gid / kFanAdjSeg;   // a pixel's lanes share a wave
+  const int vs = static_cast<int>(gid % kFanAdjSeg);
+  const bool valid = pix < static_cast<int64_t>(n) * n;
+  const int i = valid ? static_cast<int>(pix / n) : 0, j = valid ? static_cast<int>(pix % n) : 0;
   const double c = 0.5 * (n - 1), half = 0.5 * (B - 1), inv_du = 1.0 / du, Rt = src + det;
   const double X = j - c, Y = i - c;
-  const SI* pz = p + static_cast<size_t>(blockIdx.z) * V * B;
+  const SI* pz = p + static_cast<size_t>(blockIdx.y) * V * B;
   const double* rays = tab + 2 * static_cast<size_t>(V);
   C acc = 0;
-  for (int v = 0; v < V; ++v) {
+  for (int v = valid ? vs : V; v < V; v += kFanAdjSeg) {
     const double ce = tab[2 * v], se = tab[2 * v + 1];
     const SI* pv = pz + static_cast<size_t>(v) * B;
     const double* rv = rays + 3 * static_cast<size_t>(v) * B;
@@ -889,14 +903,17 @@ __global__ __launch_bounds__(256) void fan_adj_gather_kernel(
       }
     }
   }
-  Io<SO>::st(x + static_cast<size_t>(blockIdx.z) * n * n, static_cast<size_t>(i) * n + j, acc);
+  for (int o = kFanAdjSeg / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kFanAdjSeg);
+  if (valid && vs == 0)
+    Io<SO>::st(x + static_cast<size_t>(blockIdx.y) * n * n, static_cast<size_t>(i) * n + j, acc);
 }
 
 template <class SI, class SO, class C>
 static nys_status launch_fan_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t ncols,
                                  hipStream_t st) {
   const auto& d = op->d;
-  dim3 grid(cdiv(d.n_bins, 256), d.n_views, static_cast<unsigned>(ncols));
+  dim3 grid(cdiv(static_cast<int64_t>(d.n_bins) * kFanSeg, 256), d.n_views,
+            static_cast<unsigned>(ncols));
   hipLaunchKernelGGL((fan_fwd_kernel<SI, SO, C>), grid, dim3(256), 0, st, x, p, d.n1, d.n_views,
                      d.n_bins, d.fan_src, d.fan_det, d.fan_du);
   return launch_check("fan_fwd_kernel");
@@ -906,8 +923,8 @@ template <class SI, class SO, class C>
 static nys_status launch_fan_adj(nys_op_s* op, const SI* p, SO* x, int64_t ncols, hipStream_t st) {
   const auto& d = op->d;
   if (op->fan_gather) {
-    dim3 grid(cdiv(d.n1, 64), cdiv(d.n1, 4), static_cast<unsigned>(ncols));
-    hipLaunchKernelGGL((fan_adj_gather_kernel<SI, SO, C>), grid, dim3(64, 4), 0, st, p, x,
+    dim3 grid(cdiv(static_cast<int64_t>(d.n1) * d.n1 * kFanAdjSeg, 256), static_cast<unsigned>(ncols));
+    hipLaunchKernelGGL((fan_adj_gather_kernel<SI, SO, C>), grid, dim3(256), 0, st, p, x,
                        op->rays.as<double>(), d.n1, d.n_views, d.n_bins, d.fan_src, d.fan_det,
                        d.fan_du);
     return launch_check("fan_adj_gather_kernel");
