@@ -272,6 +272,17 @@ def _solve_pair(P, prob_kind, dt, with_pc, iters):
         prob.y = clean + wl.noise_rel_max * np.max(clean) * W.gaussian(clean.shape, 4)
         op = P.Operator(P.OP_FAN_BEAM, 32, 32, views=V, bins=B, fan=geo)
         reg, lam, loss, delta, ell = "tv", prob.lam, P.LOSS_LS, 0.0, 10
+    elif prob_kind == "fan_l1_db4":
+        # fan-beam CT with the l1 prior on 2-level Daubechies-4 coefficients
+        wl = W.workload("ct512_hs1_f32")
+        geo, V, B = (64.0, 32.0, 1.0), 24, 56
+        prob = sv.Problem("fan", 32, None, 2e-3, "l1", views=V, bins=B, levels=2,
+                          wavelet="db4", fan=geo)
+        clean = prob.A(ops.wavelet_analysis(W.phantom_ellipses(32, 5), 2, "db4"))
+        prob.y = clean + wl.noise_rel_max * np.max(clean) * W.gaussian(clean.shape, 5)
+        op = P.Operator(P.OP_FAN_BEAM, 32, 32, views=V, bins=B, fan=geo, wavelet_levels=2,
+                        wavelet="db4")
+        reg, lam, loss, delta, ell = "l1", prob.lam, P.LOSS_LS, 0.0, 10
     else:
         wl = W.workload("ct512_hs1_f32")
         prob, _ = sv.problem_from_workload(wl, seed=4, n=32, views=36, bins=48)
@@ -327,7 +338,7 @@ def test_solve_nonnegative_matches_oracle():
                                              ("sr_l1", "f32", False), ("sr_l1", "f32", True),
                                              ("sr_l1_db4", "f64", True), ("sr_l1_db4", "f32", True),
                                              ("ct_hs1", "f32", True), ("fan_tv", "f64", True),
-                                             ("fan_tv", "f32", False)])
+                                             ("fan_tv", "f32", False), ("fan_l1_db4", "f64", True)])
 def test_solve_matches_oracle(kind, dt, with_pc):
     P = need_gpu()
     banner(f"solve {kind} {dt} pc={with_pc}")

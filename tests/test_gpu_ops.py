@@ -218,6 +218,23 @@ def test_fan_full_size_f32():
     assert rel(host(P.op_adjoint(op, q)), ops.fan_joseph_adjoint(host(q), n, *geo)) < TOL["f32"]
 
 
+@pytest.mark.parametrize("wavelet,levels", [("haar", 2), ("db4", 3)])
+def test_fan_in_wavelet_coordinates(wavelet, levels):
+    """A W^T with the fan-beam projector (the CT experiments' wavelet prior in
+    coefficient coordinates), forward and adjoint against the oracle, FP64."""
+    P = need_gpu()
+    banner(f"fan {wavelet}-{levels}")
+    n, V, B, geo = 48, 20, 72, (96.0, 48.0, 1.2)
+    op = P.Operator(P.OP_FAN_BEAM, n, n, views=V, bins=B, fan=geo, wavelet_levels=levels,
+                    wavelet=wavelet)
+    prob = sv.Problem("fan", n, None, 0.0, "l1", views=V, bins=B, levels=levels,
+                      wavelet=wavelet, fan=geo)
+    xd = dev(W.gaussian((n, n), 40), "f64")
+    assert rel(host(P.op_forward(op, xd)), prob.A(host(xd))) < TOL["f64"]
+    q = dev(W.gaussian((V, B), 41), "f64")
+    assert rel(host(P.op_adjoint(op, q)), prob.At(host(q))) < TOL["f64"]
+
+
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 def test_sketch_fan(dt):
     P = need_gpu()
