@@ -179,59 +179,105 @@ __global__ __launch_bounds__(256) void haar_kernel(const SI* __restrict__ in,
 // FP64 vector rate equals the unpacked FP32 rate); they reach a few hundred,
 // where FP32 rounding would put ~1e-5 errors into every weight.  Samples are
 // accumulated in the compute type C.
-template <class SI, class SO, class C>
-__global__ __launch_bounds__(256) void joseph_fwd_kernel(
+// One workgroup takes 256 consecutive bins of a view and stages the rows its
+// rays cross in LDS.  Every ray of a view shares the slope g, so at step t
+// the block's rays lie between those of its first and last bin: row t is
+// needed only over [floor(min f), floor(max f) + 1], at most 255 / |a| + 3 <=
+// 364 pixels (|a| >= 1/sqrt 2).  kJosRows rows at a time are copied into LDS
+// (16-byte loads when the rows allow them, zeros outside the image), then
+// every ray takes its kJosRows samples from LDS: out-of-image samples read
+// zeros, so no per-sample bounds test is needed.  Staging replaces two
+// gathered loads per sample (the texture-address rate bounded the gathering
+// form) by two LDS reads.
+constexpr int kJosRows = 16;
+constexpr int kJosWin = 372;   // window: 364 pixels + alignment of its start to 4
+
+template <class SI, class SO, class C, bool kVec>
+__global__ __launch_bounds__(256) void joseph_fwd_lds_kernel(
     const SI* __restrict__ x, const SI* __restrict__ xT, SO* __restrict__ p, int n, int V, int B,
     const double* __restrict__ trig) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ __align__(16) C win[kJosRows][kJosWin];
+  __shared__ int base[kJosRows];
   const int v = blockIdx.y;
-  if (b >= B) return;
+  const int bfirst = blockIdx.x * 256, blast = min(B - 1, bfirst + 255);
+  const int b = bfirst + threadIdx.x;
+  const bool valid = b < B;
   const double ct = trig[2 * v], st = trig[2 * v + 1];
   const bool rows = fabs(ct) >= fabs(st);
   const double a = rows ? ct : st, bb = rows ? st : ct;
   const SI* img = (rows ? x : xT) + static_cast<size_t>(blockIdx.z) * n * n;
   const double c = 0.5 * (n - 1);
-  const double s = b - 0.5 * (B - 1);
   const double ia = 1.0 / a;
-  const double f0 = s * ia + c, g = -bb * ia;
-  // steps whose coordinate can fall in [-1, n), widened by one step each way
-  // (the bounds are clamped to [-2, n + 1] before the integer conversion: a
-  // nearly axis-parallel ray has a tiny |g| and bounds far outside)
-  int t0 = 0, t1 = n - 1;
+  const double g = -bb * ia;
+  const double f0 = (b - 0.5 * (B - 1)) * ia + c;
+  const double fa0 = (bfirst - 0.5 * (B - 1)) * ia + c, fb0 = (blast - 0.5 * (B - 1)) * ia + c;
+  // steps where any of the block's rays can meet the image: the interval
+  // [lo + (t - c) g, hi + (t - c) g] of their coordinates meets [-1, n)
+  // (widened by one step each way, bounds clamped before the conversion)
+  const double lo0 = fmin(fa0, fb0), hi0 = fmax(fa0, fb0);
+  int T0 = 0, T1 = n - 1;
   if (g != 0.0) {
-    double ta = (-1.0 - f0) / g + c, tb = (n - f0) / g + c;
-    if (ta > tb) { const double tt = ta; ta = tb; tb = tt; }
+    double ta = g > 0.0 ? (-1.0 - hi0) / g + c : (n - lo0) / g + c;
+    double tb = g > 0.0 ? (n - lo0) / g + c : (-1.0 - hi0) / g + c;
     ta = fmin(fmax(ta, -2.0), n + 1.0);
     tb = fmin(fmax(tb, -2.0), n + 1.0);
-    t0 = max(0, static_cast<int>(floor(ta)) - 1);
-    t1 = min(n - 1, static_cast<int>(ceil(tb)) + 1);
-  } else if (!(f0 >= -1.0 && f0 < n)) {
-    t1 = -1;
+    T0 = max(0, static_cast<int>(floor(ta)) - 1);
+    T1 = min(n - 1, static_cast<int>(ceil(tb)) + 1);
+  } else if (!(lo0 < n && hi0 >= -1.0)) {
+    T1 = -1;
   }
-  // four steps per round: the eight loads are issued before any is used
-  // (indices clamped into the image, out-of-image samples weighted 0)
   C acc = 0;
-  for (int t = t0; t <= t1; t += 4) {
-    C wl[4], wh[4], lo[4], hi[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int tt = min(t + u, t1);
-      const double f = f0 + (tt - c) * g;
-      const double fl = floor(f);
-      const int q = static_cast<int>(fl);
-      const C w = static_cast<C>(f - fl);
-      const bool in = t + u <= t1;
-      wl[u] = (in && q >= 0 && q < n) ? C(1) - w : C(0);
-      wh[u] = (in && q >= -1 && q + 1 < n) ? w : C(0);
-      const SI* row = img + static_cast<size_t>(tt) * n;
-      lo[u] = Io<SI>::ld(row, min(max(q, 0), n - 1));
-      hi[u] = Io<SI>::ld(row, min(max(q + 1, 0), n - 1));
+  for (int T = T0; T <= T1; T += kJosRows) {
+    const int nr = min(kJosRows, T1 - T + 1);
+    __syncthreads();   // the previous rows are no longer read
+    if (threadIdx.x < nr) {
+      const int t = T + threadIdx.x;
+      const double fa = fa0 + (t - c) * g, fb = fb0 + (t - c) * g;
+      const int lo = static_cast<int>(floor(fmin(fa, fb)));
+      base[threadIdx.x] = lo - (((lo % 4) + 4) % 4);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc += wl[u] * lo[u] + wh[u] * hi[u];
+    __syncthreads();
+    if constexpr (kVec) {
+      static_assert(std::is_same<C, float>::value, "16-byte staging holds float rows");
+      for (int e = threadIdx.x; e < nr * (kJosWin / 4); e += 256) {
+        const int r = e / (kJosWin / 4), k = 4 * (e - r * (kJosWin / 4));
+        const int col = base[r] + k;
+        const SI* row = img + static_cast<size_t>(T + r) * n;
+        float4 q4;
+        if (col >= 0 && col + 3 < n) {
+          q4 = *reinterpret_cast<const float4*>(row + col);
+        } else {
+          q4.x = (col >= 0 && col < n) ? static_cast<float>(row[col]) : 0.f;
+          q4.y = (col + 1 >= 0 && col + 1 < n) ? static_cast<float>(row[col + 1]) : 0.f;
+          q4.z = (col + 2 >= 0 && col + 2 < n) ? static_cast<float>(row[col + 2]) : 0.f;
+          q4.w = (col + 3 >= 0 && col + 3 < n) ? static_cast<float>(row[col + 3]) : 0.f;
+        }
+        *reinterpret_cast<float4*>(&win[r][k]) = q4;
+      }
+    } else {
+      for (int e = threadIdx.x; e < nr * kJosWin; e += 256) {
+        const int r = e / kJosWin, k = e - r * kJosWin;
+        const int col = base[r] + k;
+        win[r][k] = (col >= 0 && col < n)
+                        ? static_cast<C>(Io<SI>::ld(img + static_cast<size_t>(T + r) * n, col))
+                        : C(0);
+      }
+    }
+    __syncthreads();
+    if (valid) {
+      for (int r = 0; r < nr; ++r) {
+        const double f = f0 + ((T + r) - c) * g;
+        const double fl = floor(f);
+        const int q = static_cast<int>(fl);
+        const C w = static_cast<C>(f - fl);
+        const int k = min(max(q - base[r], 0), kJosWin - 2);
+        acc += (C(1) - w) * win[r][k] + w * win[r][k + 1];
+      }
+    }
   }
-  Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b,
-             acc * static_cast<C>(1.0 / fabs(a)));
+  if (valid)
+    Io<SO>::st(p, (static_cast<size_t>(blockIdx.z) * V + v) * B + b,
+               acc * static_cast<C>(1.0 / fabs(a)));
 }
 
 // out[k][j][i] = in[k][i][j] (n x n images), 32 x 32 tiles through LDS.
@@ -676,9 +722,18 @@ static nys_status launch_joseph_fwd(const nys_op_s* op, const SI* x, SO* p, int6
                      dim3(256), 0, st, x, xT, n);
   NYS_TRY(launch_check("transpose_kernel"));
   dim3 grid(cdiv(B, 256), V, static_cast<unsigned>(ncols));
-  hipLaunchKernelGGL((joseph_fwd_kernel<SI, SO, C>), grid, dim3(256), 0, st, x, xT, p, n, V, B,
-                     trig_ptr<double>(op));
-  return launch_check("joseph_fwd_kernel");
+  if constexpr (std::is_same<SI, float>::value) {
+    // 16-byte row loads need 16-byte aligned rows of both images
+    if (n % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(xT) % 16 == 0) {
+      hipLaunchKernelGGL((joseph_fwd_lds_kernel<SI, SO, C, true>), grid, dim3(256), 0, st, x, xT,
+                         p, n, V, B, trig_ptr<double>(op));
+      return launch_check("joseph_fwd_lds_kernel");
+    }
+  }
+  hipLaunchKernelGGL((joseph_fwd_lds_kernel<SI, SO, C, false>), grid, dim3(256), 0, st, x, xT, p,
+                     n, V, B, trig_ptr<double>(op));
+  return launch_check("joseph_fwd_lds_kernel");
 }
 
 template <class SI, class SO, class C>
