@@ -304,46 +304,92 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ in
 // |f(t) - q| < 1, i.e. the bins within |a| of its exact bin coordinate
 // bc = (q - c) a + t b + (B - 1) / 2 (at most two), with weight
 // (1 - |bin - bc| / |a|) / |a| -- the forward's interpolation weight.
-template <class SI, class SO, class C>
-__global__ __launch_bounds__(256) void joseph_adj_kernel(
+// A workgroup takes a 64 x 4 pixel tile; per view the tile reads at most
+// 63 + 3 + 3 consecutive bins, so kJosViews sinogram rows at a time are
+// staged in LDS over a window of kJosBins bins (16-byte loads when the rows
+// allow them, zeros off the detector) and every sample is an LDS read.
+constexpr int kJosViews = 16;
+constexpr int kJosBins = 76;   // 69 bins + alignment of the window start to 4
+template <class SI, class SO, class C, bool kVec>
+__global__ __launch_bounds__(256) void joseph_adj_lds_kernel(
     const SI* __restrict__ p, SO* __restrict__ x, int n, int V, int B,
     const double* __restrict__ trig, const double* __restrict__ inv_abs_a) {
-  const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= n || j >= n) return;
+  __shared__ __align__(16) C win[kJosViews][kJosBins];
+  __shared__ int base[kJosViews];
+  const int i0 = blockIdx.y * 4, j0 = blockIdx.x * 64;
+  const int j = j0 + (threadIdx.x & 63);
+  const int i = i0 + (threadIdx.x >> 6);
+  const bool valid = i < n && j < n;
   const SI* sino = p + static_cast<size_t>(blockIdx.z) * V * B;
   const double c = 0.5 * (n - 1);
   const double half = 0.5 * (B - 1);
-  // four views per round: the eight loads are issued before any is used
-  // (bins clamped into the detector, bins outside weighted 0)
   C acc = 0;
-  for (int v0 = 0; v0 < V; v0 += 4) {
-    C wt[8], val[8];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int v = min(v0 + u, V - 1);
+  for (int V0 = 0; V0 < V; V0 += kJosViews) {
+    const int nv = min(kJosViews, V - V0);
+    __syncthreads();   // the previous views are no longer read
+    if (threadIdx.x < nv) {
+      // lowest bin any pixel of the tile reads on this view (bc is affine in
+      // (i, j): its minimum sits at a corner of the tile)
+      const int v = V0 + threadIdx.x;
       const double ct = trig[2 * v], st = trig[2 * v + 1];
       const bool rows = fabs(ct) >= fabs(st);
-      const double a = rows ? ct : st, bb = rows ? st : ct;
-      const double ia = inv_abs_a[v], aa = fabs(a);
-      const double t = (rows ? i : j) - c;
-      const double q = (rows ? j : i) - c;
-      const double bc = q * a + t * bb + half;
-      const int b0 = static_cast<int>(floor(bc - aa)) + 1;
-      const SI* row = sino + static_cast<size_t>(v) * B;
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int bq = b0 + k;
-        const double wgt = (1.0 - fabs(bq - bc) * ia) * ia;
-        const bool use = v0 + u < V && bq >= 0 && bq < B && wgt > 0.0;
-        wt[2 * u + k] = use ? static_cast<C>(wgt) : C(0);
-        val[2 * u + k] = Io<SI>::ld(row, min(max(bq, 0), B - 1));
+      const double a = rows ? ct : st, bb = rows ? st : ct, aa = fabs(a);
+      const double tl = (rows ? i0 : j0) - c, th = (rows ? i0 + 3 : j0 + 63) - c;
+      const double ql = (rows ? j0 : i0) - c, qh = (rows ? j0 + 63 : i0 + 3) - c;
+      const double bcmin = fmin(ql * a, qh * a) + fmin(tl * bb, th * bb) + half;
+      const int lo = static_cast<int>(floor(bcmin - aa)) + 1;
+      base[threadIdx.x] = lo - (((lo % 4) + 4) % 4);
+    }
+    __syncthreads();
+    if constexpr (kVec) {
+      static_assert(std::is_same<C, float>::value, "16-byte staging holds float rows");
+      for (int e = threadIdx.x; e < nv * (kJosBins / 4); e += 256) {
+        const int r = e / (kJosBins / 4), k = 4 * (e - r * (kJosBins / 4));
+        const int col = base[r] + k;
+        const SI* row = sino + static_cast<size_t>(V0 + r) * B;
+        float4 q4;
+        if (col >= 0 && col + 3 < B) {
+          q4 = *reinterpret_cast<const float4*>(row + col);
+        } else {
+          q4.x = (col >= 0 && col < B) ? static_cast<float>(row[col]) : 0.f;
+          q4.y = (col + 1 >= 0 && col + 1 < B) ? static_cast<float>(row[col + 1]) : 0.f;
+          q4.z = (col + 2 >= 0 && col + 2 < B) ? static_cast<float>(row[col + 2]) : 0.f;
+          q4.w = (col + 3 >= 0 && col + 3 < B) ? static_cast<float>(row[col + 3]) : 0.f;
+        }
+        *reinterpret_cast<float4*>(&win[r][k]) = q4;
+      }
+    } else {
+      for (int e = threadIdx.x; e < nv * kJosBins; e += 256) {
+        const int r = e / kJosBins, k = e - r * kJosBins;
+        const int col = base[r] + k;
+        win[r][k] = (col >= 0 && col < B)
+                        ? static_cast<C>(Io<SI>::ld(sino + static_cast<size_t>(V0 + r) * B, col))
+                        : C(0);
       }
     }
+    __syncthreads();
+    if (valid) {
+      for (int r = 0; r < nv; ++r) {
+        const int v = V0 + r;
+        const double ct = trig[2 * v], st = trig[2 * v + 1];
+        const bool rows = fabs(ct) >= fabs(st);
+        const double a = rows ? ct : st, bb = rows ? st : ct;
+        const double ia = inv_abs_a[v], aa = fabs(a);
+        const double t = (rows ? i : j) - c;
+        const double q = (rows ? j : i) - c;
+        const double bc = q * a + t * bb + half;
+        const int b0 = static_cast<int>(floor(bc - aa)) + 1;
+        const int k = min(max(b0 - base[r], 0), kJosBins - 2);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) acc += wt[e] * val[e];
+        for (int u = 0; u < 2; ++u) {
+          const double wgt = (1.0 - fabs(b0 + u - bc) * ia) * ia;
+          acc += static_cast<C>(wgt > 0.0 ? wgt : 0.0) * win[r][k + u];
+        }
+      }
+    }
   }
-  Io<SO>::st(x, static_cast<size_t>(blockIdx.z) * n * n + static_cast<size_t>(i) * n + j, acc);
+  if (valid)
+    Io<SO>::st(x, static_cast<size_t>(blockIdx.z) * n * n + static_cast<size_t>(i) * n + j, acc);
 }
 
 // ================================================================ launchers
@@ -741,9 +787,16 @@ static nys_status launch_joseph_adj(const nys_op_s* op, const SI* p, SO* x, int6
                                     hipStream_t st) {
   const int n = op->d.n1, V = op->d.n_views, B = op->d.n_bins;
   dim3 grid(cdiv(n, 64), cdiv(n, 4), static_cast<unsigned>(ncols));
-  hipLaunchKernelGGL((joseph_adj_kernel<SI, SO, C>), grid, dim3(256), 0, st, p, x, n, V, B,
-                     trig_ptr<double>(op), inva_ptr<double>(op));
-  return launch_check("joseph_adj_kernel");
+  if constexpr (std::is_same<SI, float>::value) {
+    if (B % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 16 == 0) {
+      hipLaunchKernelGGL((joseph_adj_lds_kernel<SI, SO, C, true>), grid, dim3(256), 0, st, p, x, n,
+                         V, B, trig_ptr<double>(op), inva_ptr<double>(op));
+      return launch_check("joseph_adj_lds_kernel");
+    }
+  }
+  hipLaunchKernelGGL((joseph_adj_lds_kernel<SI, SO, C, false>), grid, dim3(256), 0, st, p, x, n, V,
+                     B, trig_ptr<double>(op), inva_ptr<double>(op));
+  return launch_check("joseph_adj_lds_kernel");
 }
 
 // ================================================================ fan beam
