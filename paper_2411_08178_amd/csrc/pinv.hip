@@ -324,18 +324,29 @@ nys_status batch_combine(const BDesc* d, const BSeg* pseg, int npseg, int64_t pb
   return launch_check("bcombine_kernel");
 }
 
-// cd[col][k] = coef[k] * sum_b part[col][b][k]   (one block)
-__global__ __launch_bounds__(1024) void ut_tail_kernel(const double* __restrict__ part, int nblk,
-                                                       int L, int Lp, int ncols,
-                                                       const double* __restrict__ coef,
-                                                       double* __restrict__ cd) {
-  __shared__ double red[1024];
-  __shared__ double bsum[128];
-  for (int c = 0; c < ncols; ++c) {
-    tail_sum(part + static_cast<size_t>(c) * nblk * Lp, nblk, Lp, red, bsum);
-    for (int k = threadIdx.x; k < L; k += blockDim.x) cd[static_cast<size_t>(c) * L + k] = coef[k] * bsum[k];
+// cd[col][k] = coef[k] * sum_b part[col][b][k], 16 coefficients per
+// workgroup (grid: ceil(L / 16) x ncols): 64 groups of 16 lanes read 128-byte
+// runs of 16 partials per block row, then an LDS tree sums the groups.  The
+// read of the partials (nblk x Lp FP64 per column) is spread over several CUs
+// instead of one.
+__global__ __launch_bounds__(1024) void ut_tail_cols_kernel(const double* __restrict__ part,
+                                                            int nblk, int L, int Lp,
+                                                            const double* __restrict__ coef,
+                                                            double* __restrict__ cd) {
+  __shared__ double red[64][17];
+  const int kk = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int k = blockIdx.x * 16 + kk;
+  const double* pc = part + static_cast<size_t>(blockIdx.y) * nblk * Lp;
+  double s = 0.0;
+  if (k < L)
+    for (int b = grp; b < nblk; b += 64) s += pc[static_cast<size_t>(b) * Lp + k];
+  red[grp][kk] = s;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (grp < w) red[grp][kk] += red[grp + w][kk];
     __syncthreads();
   }
+  if (grp == 0 && k < L) cd[static_cast<size_t>(blockIdx.y) * L + k] = coef[k] * red[0][kk];
 }
 
 // out = v + U cd   (one column of cd per image)
@@ -407,9 +418,10 @@ nys_status pc_partials_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, const
 
 nys_status pc_tail(nys_pc pc, bool inverse, const CoefPartials& cp, double* cd, hipStream_t st) {
   const double* coef = pc->meta.as<double>() + (inverse ? PcMeta::kD : PcMeta::kE);
-  hipLaunchKernelGGL(ut_tail_kernel, dim3(1), dim3(1024), 0, st, cp.part, cp.nblk,
-                     static_cast<int>(pc->ell), static_cast<int>(pc->ell_pad), cp.ncols, coef, cd);
-  return launch_check("ut_tail_kernel");
+  hipLaunchKernelGGL(ut_tail_cols_kernel, dim3(cdiv(pc->ell, 16), static_cast<unsigned>(cp.ncols)),
+                     dim3(1024), 0, st, cp.part, cp.nblk, static_cast<int>(pc->ell),
+                     static_cast<int>(pc->ell_pad), coef, cd);
+  return launch_check("ut_tail_cols_kernel");
 }
 
 template <class T>
