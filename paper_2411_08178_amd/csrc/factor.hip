@@ -676,6 +676,10 @@ __global__ __launch_bounds__(kFT) void bfactor_kernel(const BDesc* __restrict__ 
 
 // ================================================================ U
 // U[k][n] = sum_j (Y[j][n] + nu Omega[j][n]) R[j][k]; KC outputs per thread.
+// The sum runs in FP64 for every storage type: R = C^{-T} V S^{-1} has entries
+// up to 1 / S_min, so an FP32 sum of its products cancels by cond(B) (at
+// cond(B) ~ 1e3 the FP32 sum moved P^{-1} by 3e-5); FP64 FMAs cost the same
+// issue rate as non-packed FP32 ones on this device.
 constexpr int kUK = 32;
 
 template <class S, class T, class C>
@@ -723,7 +727,7 @@ __global__ __launch_bounds__(256) void bform_u_kernel(const BDesc* __restrict__ 
   const int k0 = blockIdx.y * kUK;
   if (k0 >= D.ell) return;
   const int64_t n = (blockIdx.x - sg.first) * 256 + threadIdx.x;
-  form_u_body<float, float, float>(D.omega, D.Y, factor_work(D.fwork, D.ell).R, D.meta, D.N,
+  form_u_body<float, float, double>(D.omega, D.Y, factor_work(D.fwork, D.ell).R, D.meta, D.N,
                                    D.ell, D.ldu, D.U, k0, n);
 }
 
@@ -800,7 +804,7 @@ static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
     hipLaunchKernelGGL((form_u_kernel<S, double, double>), ug, dim3(256), 0, st, omega, Y, w.R,
                        pc->meta.as<double>(), N, L, pc->ldu, pc->U.as<double>());
   } else {
-    hipLaunchKernelGGL((form_u_kernel<S, float, C>), ug, dim3(256), 0, st, omega, Y, w.R,
+    hipLaunchKernelGGL((form_u_kernel<S, float, double>), ug, dim3(256), 0, st, omega, Y, w.R,
                        pc->meta.as<double>(), N, L, pc->ldu, pc->U.as<float>());
   }
   return launch_check("form_u_kernel");

@@ -2,7 +2,7 @@
 against the FP64 oracle, instance by instance.
 
 Each instance: sketch Y = A^T A Omega (Alg. 1, step 2), shifted Nystrom
-factorisation (Alg. 1, steps 3-7), power-method step (eq. (15) constant) and
+factorisation (Alg. 1, steps 3-7), power-method step (the constant of eq. (20)) and
 WAPG (Alg. 3) with the P-weighted TV / HS1 prox.  Sizes are small enough for
 the oracle and leave ragged stencil tiles (n not a multiple of 64 or of the
 tile height); PSF sizes, sketch sizes and weights differ per instance.
@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_util import banner, dev, host, need_gpu, rel
+from gpu_util import TOL, banner, check, dev, host, need_gpu, rel
 from oracle import nystrom as onys
 from oracle import solver as sv
 
@@ -44,19 +44,45 @@ def _instances(seed0, specs=SPECS, reg="tv"):
 
 
 def _host_pinv(z, U, shat, nu):
-    """P^{-1} z of eq. (6) with the sqrt tail, from host copies (test-side)."""
+    """P^{-1} z of eq. (11) with the sqrt tail, from host copies (test-side)."""
     sK = np.sqrt(shat[shat > 0][-1])
     d = np.where(shat > 0, (sK + nu) / (shat + nu) - 1.0, 0.0)
     return z + U.T @ (d * (U @ z))
 
 
-def _check_costs(c, cr):
-    """FP32 iterates: the cost error is a rounding error at the scale of the
-    data term, so it is bounded relative to the first cost (1e-5), and per
-    iteration relative to the cost itself within 5e-4 (a preconditioner with
-    ||P^{-1}|| ~ 20 amplifies FP32 rounding of the late, small costs)."""
-    assert np.max(np.abs(c - cr)) < 1e-5 * abs(cr[0])
-    assert np.max(np.abs(c - cr) / np.abs(cr)) < 5e-4
+def _oracle_pc(Y, om, ell):
+    r = onys.nystrom(Y.reshape(ell, -1), om.reshape(ell, -1))
+    return sv.Precond(r["U"], r["shat"], r["nu"], "sqrt"), r
+
+
+class Floor:
+    """The batched plan factorises its own FP32 sketch, so results downstream
+    of it carry the FP32 error of Y through the factorisation.  The oracle
+    measures that effect on itself: it factorises its FP64 sketch and the same
+    sketch rounded to FP32 and compares.  The GPU's sketch carries FP32
+    accumulation error on top of its rounding (measured 1.2e-7 relative, about
+    twice the rounding alone), so a tolerance is the stated FP32 one, or ten
+    times that self-sensitivity where the factorisation's conditioning makes
+    it larger (a 32^2 instance with a 11 x 11, sigma 2.5 PSF and ell = 64:
+    Nystrom eigenvalues over many decades)."""
+
+    def __init__(self, prob, om, Yref, ell):
+        self.pc64, self.ref = _oracle_pc(Yref, om, ell)
+        self.pc32, _ = _oracle_pc(W.round_dtype(Yref, "f32"), om, ell)
+        self.prob = prob
+
+    @staticmethod
+    def tol(a64, a32):
+        return max(TOL["f32"], 10.0 * rel(a32, a64))
+
+    def pinv(self, z):
+        a = self.pc64.pinv(z)
+        return a, self.tol(a, self.pc32.pinv(z))
+
+    def wapg(self, alpha, iters, inner, **kw):
+        x64, c64 = sv.wapg(self.prob, self.pc64, alpha, iters, inner=inner, **kw)
+        x32, c32 = sv.wapg(self.prob, self.pc32, alpha, iters, inner=inner, **kw)
+        return x64, c64, self.tol(x64, x32), self.tol(np.asarray(c64), np.asarray(c32))
 
 
 @pytest.mark.parametrize("reg", ["tv", "hs1", "hsinf"])
@@ -75,23 +101,24 @@ def test_batch_preconditioned_matches_oracle(reg):
         Y, U = plan.sketch(i, n, n, ell)
         om = host(it["omega"])
         Yref = sv.sketch(prob, om)
-        assert rel(host(Y), Yref) < 1e-5
-        ref = onys.nystrom(host(Y).reshape(ell, -1), om.reshape(ell, -1))
+        check(host(Y), Yref, TOL["f32"], what="sketch")
+        # the oracle factorises its own sketch
+        fl = Floor(prob, om, Yref, ell)
+        ref, opc = fl.ref, fl.pc64
         info = plan.info(i)
         assert info["status"] == 0
         shat = plan.shat(i, ell)
-        assert rel(shat, ref["shat"]) < 1e-5
+        check(shat, ref["shat"], TOL["f32"], what="shat")
         z = W.gaussian((n * n,), 500 + i)
-        opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
-        got = _host_pinv(z, host(U), shat, info["nu"])
-        assert rel(got, opc.pinv(z)) < 1e-4
-        assert abs(info["pinv_norm"] - opc.pinv_norm) < 1e-4 * opc.pinv_norm
+        want, tol = fl.pinv(z)
+        check(_host_pinv(z, host(U), shat, info["nu"]), want, tol, what="P^-1 z")
+        assert abs(info["pinv_norm"] - opc.pinv_norm) < TOL["f32"] * opc.pinv_norm
         Lr = sv.lipschitz(prob, opc, host(it["v0"]), piters)
-        assert abs(info["L"] - Lr) < 1e-4 * Lr
+        assert abs(info["L"] - Lr) < TOL["f32"] * Lr
         assert abs(info["alpha"] * 1.01 * info["L"] - 1.0) < 1e-12
-        xr, cr = sv.wapg(prob, opc, info["alpha"], iters, inner=inner)
-        assert rel(host(plan.x[i]), xr) < 1e-4
-        _check_costs(host(plan.costs[i]), cr)
+        xr, cr, tol_x, tol_c = fl.wapg(info["alpha"], iters, inner)
+        check(host(plan.x[i]), xr, tol_x, what="x after 8 iterations")
+        check(host(plan.costs[i]), cr, tol_c, what="costs")
 
 
 def test_batch_plain_apg_matches_oracle():
@@ -110,8 +137,8 @@ def test_batch_plain_apg_matches_oracle():
         assert abs(info["L"] - Lr) < 1e-5 * Lr
         assert info["pinv_norm"] == 1.0
         xr, cr = sv.wapg(prob, None, info["alpha"], iters, inner=inner)
-        assert rel(host(plan.x[i]), xr) < 1e-4
-        _check_costs(host(plan.costs[i]), cr)
+        check(host(plan.x[i]), xr, TOL["f32"], what="x after 10 iterations")
+        check(host(plan.costs[i]), cr, TOL["f32"], what="costs")
 
 
 def test_batch_replay_is_bitwise_and_inputs_refill():
@@ -135,11 +162,10 @@ def test_batch_replay_is_bitwise_and_inputs_refill():
     torch.cuda.synchronize()
     prob.y = host(it["y"])
     info = plan.info(1)
-    Y, U = plan.sketch(1, prob.n, prob.n, it["ell"])
-    ref = onys.nystrom(host(Y).reshape(it["ell"], -1), host(it["omega"]).reshape(it["ell"], -1))
-    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
-    xr, _ = sv.wapg(prob, opc, info["alpha"], 5, inner=5)
-    assert rel(host(plan.x[1]), xr) < 1e-4
+    om = host(it["omega"])
+    fl = Floor(prob, om, sv.sketch(prob, om), it["ell"])
+    xr, _, tol_x, _ = fl.wapg(info["alpha"], 5, 5)
+    check(host(plan.x[1]), xr, tol_x, what="x of the refilled instance")
     assert torch.equal(plan.x[0], x1[0])
 
 
@@ -188,18 +214,58 @@ def test_batch_rectangular_wide_psf_and_sketch_only():
         banner(f"batch rect instance {i} {n1}x{n2}")
         Y, U = plan.sketch(i, n1, n2, ell)
         om = host(it["omega"])
-        assert rel(host(Y), sv.sketch(prob, om)) < 1e-5
-        ref = onys.nystrom(host(Y).reshape(ell, -1), om.reshape(ell, -1))
-        opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+        Yref = sv.sketch(prob, om)
+        check(host(Y), Yref, TOL["f32"], what="sketch")
+        fl = Floor(prob, om, Yref, ell)
         info = plan.info(i)
-        assert rel(plan.shat(i, ell), ref["shat"]) < 1e-5
-        xr, cr = sv.wapg(prob, opc, info["alpha"], 4, inner=5, x0=np.zeros((n1, n2)))
-        assert rel(host(plan.x[i]), xr) < 1e-4
-        _check_costs(host(plan.costs[i]), cr)
+        check(plan.shat(i, ell), fl.ref["shat"], TOL["f32"], what="shat")
+        xr, cr, tol_x, tol_c = fl.wapg(info["alpha"], 4, 5, x0=np.zeros((n1, n2)))
+        check(host(plan.x[i]), xr, tol_x, what="x after 4 iterations")
+        check(host(plan.costs[i]), cr, tol_c, what="costs")
     for i, it in enumerate(inst):
         it["omega"].copy_(dev(W.omega(it["ell"], it["n1"], it["n2"], 950 + i), "f32"))
     plan.sketch_only()
     torch.cuda.synchronize()
     for i, it in enumerate(inst):
         Y, _ = plan.sketch(i, it["n1"], it["n2"], it["ell"])
-        assert rel(host(Y), sv.sketch(it["prob"], host(it["omega"]))) < 1e-5
+        check(host(Y), sv.sketch(it["prob"], host(it["omega"])), TOL["f32"], what="refilled sketch")
+
+
+# instances of the batched workload's largest sizes: 1024^2 with a 7 x 7 PSF
+# (ell = 16) and 768^2 with a 15 x 15 PSF (ell = 8, the 29-tap A^T A stencil)
+BIG = [(1024, 7, 1.2, 16, 1e-3), (768, 15, 2.8, 8, 4e-3)]
+
+
+def test_batch_workload_sizes_match_oracle():
+    """Sketch (every column), Nystrom eigenvalues, P^{-1} on a probe, the
+    power-method constant and 5 WAPG iterations with 20 dual iterations at
+    the batched workload's largest image sizes, each against the oracle's
+    own sketch and factorisation."""
+    P = need_gpu()
+    banner("batch workload sizes 1024^2 / 768^2")
+    inst = _instances(1000, specs=BIG)
+    iters, inner, piters = 5, 20, 40
+    plan = P.BatchSolver(inst, reg=P.REG_TV, max_iter=iters, n_inner=inner,
+                         power_iters=piters, record_costs=True, tune=True)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, it in enumerate(inst):
+        prob, ell, n = it["prob"], it["ell"], it["prob"].n
+        banner(f"batch big instance {i} n={n} ell={ell}")
+        Y, U = plan.sketch(i, n, n, ell)
+        om = host(it["omega"])
+        Yref = sv.sketch(prob, om)
+        check(host(Y), Yref, TOL["f32"], what="sketch")
+        ref = onys.nystrom(Yref.reshape(ell, -1), om.reshape(ell, -1))
+        info = plan.info(i)
+        assert info["status"] == 0
+        shat = plan.shat(i, ell)
+        check(shat, ref["shat"], TOL["f32"], what="shat")
+        opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+        z = W.gaussian((n * n,), 1500 + i)
+        check(_host_pinv(z, host(U), shat, info["nu"]), opc.pinv(z), TOL["f32"], what="P^-1 z")
+        Lr = sv.lipschitz(prob, opc, host(it["v0"]), piters)
+        assert abs(info["L"] - Lr) < TOL["f32"] * Lr
+        xr, cr = sv.wapg(prob, opc, info["alpha"], iters, inner=inner)
+        check(host(plan.x[i]), xr, TOL["f32"], what="x after 5 iterations")
+        check(host(plan.costs[i]), cr, TOL["f32"], what="costs")

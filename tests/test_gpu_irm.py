@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import workloads as W
-from gpu_util import banner, dev, host, need_gpu, rel
+from gpu_util import banner, check, dev, host, need_gpu, rel
 from oracle import irm as oi
 from oracle import operators as ops
 
@@ -42,8 +42,10 @@ def test_irm_f64_matches_oracle(with_pc, p):
     # ill-conditioned systems amplifies it, more so for the non-convex p = 0.5
     # whose weights reach eps^(-3/4) = 1e3): the iterates agree to the level the
     # tolerance leaves open, and the step counts within 3 % (at least 3 steps;
-    # observed: 99 vs 97 and 313 vs 312 at p = 0.5, at most one step at p = 1)
-    assert rel(host(x), ref.x) < 1e-6, rel(host(x), ref.x)
+    # observed: 99 vs 97 and 313 vs 312 at p = 0.5, at most one step at p = 1;
+    # measured x errors: rel 3e-8 / elem 1e-7 at p = 1, rel 9e-7 / elem 2.6e-6 at
+    # p = 0.5)
+    check(host(x), ref.x, 1e-6, 5e-6)
     assert len(its) == len(ref.cg_iters)
     assert all(abs(a - b) <= max(3, 0.03 * b) for a, b in zip(its, ref.cg_iters)), \
         (its, ref.cg_iters)
@@ -67,7 +69,8 @@ def test_irm_f32_pcg_tolerance_1e4():
                  omega=om, tail="plain")
     assert len(its) == len(ref.cg_iters)
     assert all(abs(a - b) <= max(3, 0.1 * b) for a, b in zip(its, ref.cg_iters))
-    assert rel(host(x), ref.x) < 2e-3
+    # FP32 CG stopped at ||r|| <= 1e-4 ||b||: measured rel 2.8e-4, elem 1.1e-3
+    check(host(x), ref.x, 2e-3)
 
 
 def test_irm_pcg_needs_fewer_steps_and_reaches_the_same_objective():

@@ -5,7 +5,7 @@ import pytest
 import workloads as W
 from oracle import operators as ops
 from oracle import solver as sv
-from gpu_util import TOL, banner, dev, host, need_gpu, rel
+from gpu_util import BF16_ELEM, TOL, banner, check, dev, host, need_gpu, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -23,9 +23,9 @@ def test_blur_forward_adjoint(dt, n1, n2, k, sigma):
     xd = dev(x, dt)
     xr = host(xd)
     y = P.op_forward(op, xd)
-    assert rel(host(y), ops.blur(xr, h)) < TOL[dt]
+    check(host(y), ops.blur(xr, h), TOL[dt])
     z = P.op_adjoint(op, y)
-    assert rel(host(z), ops.blur_adjoint(host(y), h)) < TOL[dt]
+    check(host(z), ops.blur_adjoint(host(y), h), TOL[dt])
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -41,12 +41,12 @@ def test_blurdown_and_haar(dt, n, k, levels):
     ref = ops.blurdown(ops.haar_synthesis(xr, levels) if levels else xr, h, 2)
     y = P.op_forward(op, xd)
     assert y.shape == (2, n // 2, n // 2)
-    assert rel(host(y), ref) < TOL[dt]
+    check(host(y), ref, TOL[dt])
     yr = host(y)
     ref_t = ops.blurdown_adjoint(yr, h, 2)
     if levels:
         ref_t = ops.haar_analysis(ref_t, levels)
-    assert rel(host(P.op_adjoint(op, y)), ref_t) < TOL[dt]
+    check(host(P.op_adjoint(op, y)), ref_t, TOL[dt])
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -57,8 +57,8 @@ def test_haar_identity_operator(dt):
     op = P.Operator(P.OP_IDENTITY, n, n, wavelet_levels=3)
     w = W.gaussian((2, n, n), 3)
     wd = dev(w, dt)
-    assert rel(host(P.op_forward(op, wd)), ops.haar_synthesis(host(wd), 3)) < TOL[dt]
-    assert rel(host(P.op_adjoint(op, wd)), ops.haar_analysis(host(wd), 3)) < TOL[dt]
+    check(host(P.op_forward(op, wd)), ops.haar_synthesis(host(wd), 3), TOL[dt])
+    check(host(P.op_adjoint(op, wd)), ops.haar_analysis(host(wd), 3), TOL[dt])
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -71,8 +71,8 @@ def test_db4_identity_operator(dt, n1, n2, levels):
     op = P.Operator(P.OP_IDENTITY, n1, n2, wavelet_levels=levels, wavelet="db4")
     w = W.gaussian((2, n1, n2), 33)
     wd = dev(w, dt)
-    assert rel(host(P.op_forward(op, wd)), ops.db4_synthesis(host(wd), levels)) < TOL[dt]
-    assert rel(host(P.op_adjoint(op, wd)), ops.db4_analysis(host(wd), levels)) < TOL[dt]
+    check(host(P.op_forward(op, wd)), ops.db4_synthesis(host(wd), levels), TOL[dt])
+    check(host(P.op_adjoint(op, wd)), ops.db4_analysis(host(wd), levels), TOL[dt])
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
@@ -86,12 +86,12 @@ def test_blurdown_db4_operator_and_sketch(dt):
     if dt != "bf16":
         xd = dev(W.gaussian((2, n, n), 34), dt)
         y = P.op_forward(op, xd)
-        assert rel(host(y), ops.blurdown(ops.db4_synthesis(host(xd), levels), h, 2)) < TOL[dt]
+        check(host(y), ops.blurdown(ops.db4_synthesis(host(xd), levels), h, 2), TOL[dt])
         z = P.op_adjoint(op, y)
-        assert rel(host(z), ops.db4_analysis(ops.blurdown_adjoint(host(y), h, 2), levels)) < TOL[dt]
+        check(host(z), ops.db4_analysis(ops.blurdown_adjoint(host(y), h, 2), levels), TOL[dt])
     om = dev(W.omega(3, n, n, 35), dt)
     Y = P.nys_sketch(op, om)
-    assert rel(host(Y), sv.sketch(prob, host(om))) < TOL[dt]
+    check(host(Y), sv.sketch(prob, host(om)), TOL[dt], BF16_ELEM if dt == "bf16" else None)
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -104,9 +104,9 @@ def test_joseph_pair(dt, n, V, B):
     xd = dev(x, dt)
     p = P.op_forward(op, xd)
     assert p.shape == (2, V, B)
-    assert rel(host(p), ops.joseph(host(xd), V, B)) < TOL[dt]
+    check(host(p), ops.joseph(host(xd), V, B), TOL[dt])
     q = dev(W.gaussian((2, V, B), 5), dt)
-    assert rel(host(P.op_adjoint(op, q)), ops.joseph_adjoint(host(q), n)) < TOL[dt]
+    check(host(P.op_adjoint(op, q)), ops.joseph_adjoint(host(q), n), TOL[dt])
     # adjoint identity inside the GPU arithmetic
     lhs = float((p.double() * q.double()).sum())
     rhs = float((xd.double() * P.op_adjoint(op, q).double()).sum())
@@ -122,7 +122,7 @@ def test_sketch_blur(dt, n, ell):
     om = dev(W.omega(ell, n, n, 6), dt)
     Y = P.nys_sketch(op, om)
     prob = sv.Problem("blur", n, None, 0.0, "tv", h=h)
-    assert rel(host(Y), sv.sketch(prob, host(om))) < TOL[dt]
+    check(host(Y), sv.sketch(prob, host(om)), TOL[dt], BF16_ELEM if dt == "bf16" else None)
 
 
 @pytest.mark.parametrize("dt,n,ell,k,sep", [("bf16", 128, 5, 7, True), ("f32", 128, 3, 7, True),
@@ -144,7 +144,7 @@ def test_sketch_super_resolution(dt, n, ell, k, sep):
     prob = sv.Problem("blurdown", n, None, 0.0, "l1", h=h, factor=2, levels=3)
     ref = sv.sketch(prob, host(om))
     got = host(Y)
-    assert rel(got, ref) < TOL[dt]
+    check(got, ref, TOL[dt], BF16_ELEM if dt == "bf16" else None)
     # element-wise: within one bf16 ulp (2^-8 relative) plus FP32 accumulation
     if dt == "bf16":
         assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
@@ -159,9 +159,9 @@ def test_joseph_full_size_ct_f32():
     op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=V, bins=B)
     xd = dev(W.phantom_ellipses(n, 11), "f32")
     p = P.op_forward(op, xd)
-    assert rel(host(p), ops.joseph(host(xd), V, B)) < TOL["f32"]
+    check(host(p), ops.joseph(host(xd), V, B), TOL["f32"])
     q = dev(W.gaussian((V, B), 12), "f32")
-    assert rel(host(P.op_adjoint(op, q)), ops.joseph_adjoint(host(q), n)) < TOL["f32"]
+    check(host(P.op_adjoint(op, q)), ops.joseph_adjoint(host(q), n), TOL["f32"])
 
 
 def test_sketch_ct_f32():
@@ -172,7 +172,7 @@ def test_sketch_ct_f32():
     om = dev(W.omega(ell, n, n, 8), "f32")
     Y = P.nys_sketch(op, om)
     ref = ops.joseph_adjoint(ops.joseph(host(om), V, B), n)
-    assert rel(host(Y), ref) < TOL["f32"]
+    check(host(Y), ref, TOL["f32"])
 
 
 # the last case has the source radius below the image side: its adjoint is
@@ -194,10 +194,10 @@ def test_fan_pair(dt, n, V, B, geo):
     xd = dev(x, dt)
     p = P.op_forward(op, xd)
     assert p.shape == (2, V, B)
-    assert rel(host(p), ops.fan_joseph(host(xd), V, B, *geo)) < TOL[dt]
+    check(host(p), ops.fan_joseph(host(xd), V, B, *geo), TOL[dt])
     q = dev(W.gaussian((2, V, B), 5), dt)
     z = P.op_adjoint(op, q)
-    assert rel(host(z), ops.fan_joseph_adjoint(host(q), n, *geo)) < TOL[dt]
+    check(host(z), ops.fan_joseph_adjoint(host(q), n, *geo), TOL[dt])
     lhs = float((p.double() * q.double()).sum())
     rhs = float((xd.double() * z.double()).sum())
     assert abs(lhs - rhs) <= 10 * TOL[dt] * abs(lhs)
@@ -213,9 +213,9 @@ def test_fan_full_size_f32():
     op = P.Operator(P.OP_FAN_BEAM, n, n, views=V, bins=B, fan=geo)
     xd = dev(W.phantom_ellipses(n, 11), "f32")
     p = P.op_forward(op, xd)
-    assert rel(host(p), ops.fan_joseph(host(xd), V, B, *geo)) < TOL["f32"]
+    check(host(p), ops.fan_joseph(host(xd), V, B, *geo), TOL["f32"])
     q = dev(W.gaussian((V, B), 12), "f32")
-    assert rel(host(P.op_adjoint(op, q)), ops.fan_joseph_adjoint(host(q), n, *geo)) < TOL["f32"]
+    check(host(P.op_adjoint(op, q)), ops.fan_joseph_adjoint(host(q), n, *geo), TOL["f32"])
 
 
 @pytest.mark.parametrize("wavelet,levels", [("haar", 2), ("db4", 3)])
@@ -230,9 +230,9 @@ def test_fan_in_wavelet_coordinates(wavelet, levels):
     prob = sv.Problem("fan", n, None, 0.0, "l1", views=V, bins=B, levels=levels,
                       wavelet=wavelet, fan=geo)
     xd = dev(W.gaussian((n, n), 40), "f64")
-    assert rel(host(P.op_forward(op, xd)), prob.A(host(xd))) < TOL["f64"]
+    check(host(P.op_forward(op, xd)), prob.A(host(xd)), TOL["f64"])
     q = dev(W.gaussian((V, B), 41), "f64")
-    assert rel(host(P.op_adjoint(op, q)), prob.At(host(q))) < TOL["f64"]
+    check(host(P.op_adjoint(op, q)), prob.At(host(q)), TOL["f64"])
 
 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
@@ -244,7 +244,7 @@ def test_sketch_fan(dt):
     om = dev(W.omega(ell, n, n, 8), dt)
     Y = P.nys_sketch(op, om)
     ref = ops.fan_joseph_adjoint(ops.fan_joseph(host(om), V, B, *geo), n, *geo)
-    assert rel(host(Y), ref) < TOL[dt]
+    check(host(Y), ref, TOL[dt], BF16_ELEM if dt == "bf16" else None)
 
 
 def test_sketch_sr_full_size_sampled_columns():
@@ -263,7 +263,7 @@ def test_sketch_sr_full_size_sampled_columns():
     for k in (0, 31, 63):
         ref = prob.phi(omh[k])
         got = host(Y[k])
-        assert rel(got, ref) < TOL["bf16"]
+        check(got, ref, TOL["bf16"], BF16_ELEM, what=f"column {k}")
 
 
 def test_operator_argument_errors():

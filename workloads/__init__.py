@@ -234,19 +234,18 @@ class BatchInstance:
 
 def batch_instances(count: int = 64, seed: int = 0,
                     sizes=BATCH_SIZES) -> list:
-    """Draw the batched deblurring problems.
-
-    Side uniform over `sizes`; PSF standard deviation U[0.8, 3]; PSF size the
-    odd number 2 ceil(2.5 sigma) + 1 clipped to [5, 15]; TV weight
-    log-uniform on [5e-4, 5e-3]; sketch size uniform over {16, 32, 64}.
+    """Draw the batched deblurring problems, each parameter independently:
+    side uniform over `sizes`; PSF standard deviation U[0.8, 3]; PSF size
+    uniform over the odd sizes 5, 7, ..., 15; TV weight U[5e-4, 5e-3];
+    sketch size uniform over {16, 32, 64}.
     """
     g = rng(seed, 6)
     out = []
     for i in range(count):
         n = int(g.choice(np.asarray(sizes)))
         sigma = float(g.uniform(0.8, 3.0))
-        k = int(min(15, max(5, 2 * int(np.ceil(2.5 * sigma)) + 1)))
-        lam = float(np.exp(g.uniform(np.log(5e-4), np.log(5e-3))))
+        k = int(g.choice(np.asarray((5, 7, 9, 11, 13, 15))))
+        lam = float(g.uniform(5e-4, 5e-3))
         ell = int(g.choice(np.asarray((16, 32, 64))))
         out.append(BatchInstance(n, k, sigma, lam, ell, 1000 * seed + i))
     return out
@@ -255,19 +254,3 @@ def batch_instances(count: int = 64, seed: int = 0,
 def workload(name: str, **overrides) -> Workload:
     """Look up a workload and optionally shrink it (tests use small sizes)."""
     return dataclasses.replace(WORKLOADS[name], **overrides)
-
-
-def batched_deblur_draw(count: int = 64, seed: int = 0):
-    """Instance parameters for the batched deblur workload: square sizes from
-    {128,...,1024}, Gaussian PSFs sigma in [0.8, 3] with odd sizes 5..15,
-    TV lambda in [5e-4, 5e-3], sketch size in {16, 32, 64}."""
-    g = rng(seed, 6)
-    out = []
-    for i in range(count):
-        n = int(g.choice([128, 256, 384, 512, 768, 1024]))
-        sigma = float(g.uniform(0.8, 3.0))
-        k = int(g.choice([5, 7, 9, 11, 13, 15]))
-        lam = float(g.uniform(5e-4, 5e-3))
-        ell = int(g.choice([16, 32, 64]))
-        out.append(dict(n=n, sigma=sigma, k=k, lam=lam, ell=ell, seed=i))
-    return out
