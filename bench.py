@@ -18,14 +18,17 @@ found by untimed runs that record the cost, then the timed runs repeat the
 solve with exactly that many iterations and no cost recording.
 
 Prints one JSON line.  Usage:
-    python bench.py [--steps K] [--warmup W]
-                    [--workload sr512|ct512|fan512|deblur128|batch64|irm256]
-                    [--no-cpu-baseline] [--copy-calibration]
+    python bench.py [--steps K] [--warmup W] [--tail sqrt|plain]
+                    [--workload batch64|sr512|ct512|fan512|deblur128|irm256]
+                    [--no-cpu-baseline] [--no-oracle-err] [--copy-calibration]
                     [--rate-sweep 10,20,50,100]
+    python bench.py --workload batch64 --make-fstar [--fstar-range a:b]
 
-The batched workload (64 deblurring problems of uneven sizes, one graph
-launch per solve of the whole batch) times the batch to the point where every
-instance has reached the gap.  The IRM workload (l_1 - l_1 deblurring by
+The default workload is the batched one (64 deblurring problems of uneven
+sizes, one graph launch per solve of the whole batch), the largest of the
+benchmark configurations that fits one GPU; it times the batch to the point
+where every instance has reached the gap.  Its F* per instance comes from a
+stored table of long FP64 runs of both methods (--make-fstar writes it).  The IRM workload (l_1 - l_1 deblurring by
 Alg. 2) times its fixed schedule of outer iterations with Nystrom-PCG against
 plain CG x-updates.
 """
@@ -236,30 +239,108 @@ def cpu_baseline(wl, k_pc, power_iters, alpha, seed=0):
 
 
 # ---------------------------------------------------------------- batch
+FSTAR_DIR = os.path.join(ROOT, "bench_fstar")
+FSTAR_INNER, FSTAR_ITERS = 200, 1000
+
+
+def batch_problem(P, torch, s, noise_sigma):
+    """Operator, PSF and float32 measurements of one instance of the batched
+    workload, formed on the GPU."""
+    n = s.n
+    h = W.gaussian_psf(s.psf_k, s.psf_sigma)
+    op = P.Operator(P.OP_BLUR, n, n, psf=h)
+    xt = torch.from_numpy(W.phantom_blocks(n, s.seed)).float().cuda()
+    noise = torch.from_numpy(W.gaussian((n, n), s.seed)).float().cuda()
+    y = (P.op_forward(op, xt) + noise_sigma * noise).contiguous()
+    return op, h, y
+
+
 class BatchSetup:
     """The 64 deblurring problems of the batched workload, on the GPU."""
 
     def __init__(self, P, torch, wl, seed=0):
         self.specs = W.batch_instances(wl.count, seed)
         self.items = []
+        self.omega_host = []
         for s in self.specs:
             n = s.n
-            h = W.gaussian_psf(s.psf_k, s.psf_sigma)
-            op = P.Operator(P.OP_BLUR, n, n, psf=h)
-            xt = torch.from_numpy(W.phantom_blocks(n, s.seed)).float().cuda()
-            noise = torch.from_numpy(W.gaussian((n, n), s.seed)).float().cuda()
-            y = (P.op_forward(op, xt) + wl.noise_sigma * noise).contiguous()
-            om = torch.from_numpy(W.omega(s.ell, n, n, s.seed)).float().cuda().contiguous()
+            _, h, y = batch_problem(P, torch, s, wl.noise_sigma)
+            om_h = torch.from_numpy(W.omega(s.ell, n, n, s.seed)).float().pin_memory()
+            om = om_h.cuda().contiguous()
             v0 = torch.from_numpy(W.gaussian((n, n), s.seed, stream=7)).float().cuda().contiguous()
+            self.omega_host.append(om_h)
             self.items.append(dict(psf=h, y=y, lam=s.lam, ell=s.ell, omega=om, v0=v0))
         self.N = [s.n * s.n for s in self.specs]
         self.sketch_bytes = sum(2 * 4 * s.ell * s.n * s.n for s in self.specs)
+        self.omega_bytes = sum(4 * s.ell * s.n * s.n for s in self.specs)
 
 
-def batch_plan(P, B, wl, precondition, iters, power_iters, record):
+def batch_plan(P, B, wl, precondition, iters, power_iters, record, tail="sqrt"):
     return P.BatchSolver(B.items, reg=P.REG_TV, max_iter=iters, n_inner=wl.inner,
                          power_iters=power_iters, precondition=precondition,
-                         record_costs=record, tune=True)
+                         tail=0 if tail == "sqrt" else 1, record_costs=record, tune=True)
+
+
+def fstar_path(wl, seed, tail):
+    return os.path.join(FSTAR_DIR, f"{wl.name}_seed{seed}.json")
+
+
+def make_fstar(args, P, torch, wl):
+    """F* of every instance of the batched workload: the smallest cost of two
+    long FP64 runs, plain APG and Nystrom-preconditioned WAPG (the instance's
+    own sketch size, sqrt tail), each with FSTAR_INNER dual iterations per
+    prox so that the proximal steps are nearly exact; the two must agree to
+    1e-8 relative.  Written to bench_fstar/ (instances a:b with --fstar-range
+    merge into an existing table)."""
+    specs = W.batch_instances(wl.count, args.seed)
+    a, b = (int(v) for v in args.fstar_range.split(":")) if args.fstar_range else (0, len(specs))
+    path = args.fstar_out or fstar_path(wl, args.seed, "sqrt")
+    table = json.load(open(path)) if os.path.exists(path) else {
+        "workload": wl.name, "seed": args.seed, "inner": FSTAR_INNER, "iters": FSTAR_ITERS,
+        "dtype": "f64", "methods": ["plain APG", "Nystrom WAPG, sqrt tail"],
+        "instances": [None] * len(specs)}
+    for i in range(a, b):
+        s = specs[i]
+        t0 = time.perf_counter()
+        op, h, y32 = batch_problem(P, torch, s, wl.noise_sigma)
+        y = y32.double().contiguous()
+        n = s.n
+        rd = P.reg_desc("tv", n, n, n_inner=FSTAR_INNER)
+        v0 = torch.from_numpy(W.gaussian((n, n), s.seed, stream=7)).cuda().contiguous()
+        _, c_pl, _ = P.solve(op, y, rd, s.lam, None, FSTAR_ITERS, power_v0=v0,
+                             power_iters=args.power_iters)
+        om = torch.from_numpy(W.omega(s.ell, n, n, s.seed)).cuda().contiguous()
+        pc = P.nys_factor(om, P.nys_sketch(op, om), s.ell, u_dtype=torch.float64)
+        _, c_pc, _ = P.solve(op, y, rd, s.lam, pc, FSTAR_ITERS, power_v0=v0,
+                             power_iters=args.power_iters)
+        m_pl, m_pc = float(c_pl.min()), float(c_pc.min())
+        fs = min(m_pl, m_pc)
+        res = abs(m_pl - m_pc) <= 1e-8 * abs(fs)
+        table["instances"][i] = dict(n=n, psf_k=s.psf_k, psf_sigma=s.psf_sigma, lam=s.lam,
+                                     ell=s.ell, fstar=fs, min_plain=m_pl, min_precond=m_pc,
+                                     resolved=bool(res))
+        log(f"instance {i} n={n} ell={s.ell}: F*={fs!r} plain {m_pl!r} precond {m_pc!r} "
+            f"agree {abs(m_pl - m_pc) / abs(fs):.2e} ({time.perf_counter() - t0:.1f}s)")
+        del pc, om
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        json.dump(table, open(path, "w"), indent=1)
+    print(json.dumps({"fstar_table": os.path.relpath(path, ROOT), "done": [a, b]}), flush=True)
+
+
+def load_fstar(wl, seed, specs):
+    """F* per instance from the stored FP64 table, or None (entries that do not
+    match the instance draw are rejected)."""
+    path = fstar_path(wl, seed, "sqrt")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    out = []
+    for s, e in zip(specs, t["instances"]):
+        if e is None or e["n"] != s.n or e["ell"] != s.ell or e["psf_k"] != s.psf_k or \
+                abs(e["lam"] - s.lam) > 1e-15 * s.lam:
+            return None
+        out.append(e)
+    return out if len(out) == len(specs) else None
 
 
 def cpu_baseline_batch(wl, B, k_pc, power_iters, seed=0):
@@ -310,20 +391,74 @@ def cpu_baseline_batch(wl, B, k_pc, power_iters, seed=0):
                 parts={k + "_per_px_s": v for k, v in m.items()})
 
 
+def oracle_err_batch(P, torch, wl, B, tail, seed=0):
+    """Errors of the timed launch configuration against the FP64 oracle on one
+    instance of the batch (the smallest): three sketch columns, P^{-1} on a
+    probe (both sides factorising their own sketch) and the iterate after six
+    WAPG iterations.  The instance runs alone through the same batched solver
+    (one graph, same kernels)."""
+    from oracle import nystrom as onys
+    from oracle import solver as sv
+    i = int(np.argmin([s.n * s.n * s.ell * s.psf_k for s in B.specs]))
+    s = B.specs[i]
+    it = B.items[i]
+    n, ell = s.n, s.ell
+    plan = P.BatchSolver([it], reg=P.REG_TV, max_iter=6, n_inner=wl.inner, power_iters=60,
+                         tail=0 if tail == "sqrt" else 1, record_costs=True, tune=False)
+    plan.run()
+    torch.cuda.synchronize()
+    prob = sv.Problem("blur", n, it["y"].double().cpu().numpy(), s.lam, "tv", h=it["psf"])
+    om = it["omega"].double().cpu().numpy()
+    Yg, Ug = plan.sketch(0, n, n, ell)
+    Yref = sv.sketch(prob, om)
+    rel = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    cols = [0, ell // 2, ell - 1]
+    e_sk = max(rel(Yg[k].double().cpu().numpy(), Yref[k]) for k in cols)
+    r = onys.nystrom(Yref.reshape(ell, -1), om.reshape(ell, -1))
+    opc = sv.Precond(r["U"], r["shat"], r["nu"], tail)
+    info = plan.info(0)
+    shat = plan.shat(0, ell)
+    U = Ug.double().cpu().numpy()
+    z = W.gaussian((n * n,), seed + 77)
+    sK = np.sqrt(shat[-1]) if tail == "sqrt" else shat[-1]
+    d = (sK + info["nu"]) / (shat + info["nu"]) - 1.0
+    e_pinv = rel(z + U.T @ (d * (U @ z)), opc.pinv(z))
+    xr, _ = sv.wapg(prob, opc, info["alpha"], 6, inner=wl.inner)
+    e_x = rel(plan.x[0].double().cpu().numpy(), xr)
+    return {"instance": i, "n": n, "ell": ell, "psf_k": s.psf_k, "sketch_cols": e_sk,
+            "pinv_probe": e_pinv, "x_after_6_iterations": e_x, "norm": "relative 2-norm"}
+
+
 def main_batch(args, P, torch, wl):
     log(f"workload {wl.name}: {wl.count} instances")
+    t0 = time.perf_counter()
     B = BatchSetup(P, torch, wl, args.seed)
     torch.cuda.synchronize()
+    log(f"inputs generated in {time.perf_counter() - t0:.1f}s: {sum(B.N)} pixels, "
+        f"{sum(s.ell for s in B.specs)} sketch columns, {B.sketch_bytes / 1e9:.2f} GB Omega + Y")
+    tail = args.tail
     ref_iters = args.ref_iters
     t0 = time.perf_counter()
-    ref_pc = batch_plan(P, B, wl, True, ref_iters, args.power_iters, True)
+    ref_pc = batch_plan(P, B, wl, True, ref_iters, args.power_iters, True, tail)
     ref_pc.run()
-    ref_pl = batch_plan(P, B, wl, False, ref_iters, args.power_iters, True)
+    ref_pl = batch_plan(P, B, wl, False, ref_iters, args.power_iters, True, tail)
     ref_pl.run()
     torch.cuda.synchronize()
     c_pc = np.stack([c.cpu().numpy() for c in ref_pc.costs])
     c_pl = np.stack([c.cpu().numpy() for c in ref_pl.costs])
-    fstar = np.minimum(c_pc.min(axis=1), c_pl.min(axis=1))
+    table = load_fstar(wl, args.seed, B.specs)
+    if table is not None:
+        fstar = np.array([e["fstar"] for e in table])
+        resolved = [bool(e["resolved"]) for e in table]
+        fsrc = (f"FP64 runs of both methods, {FSTAR_INNER} dual iterations, {FSTAR_ITERS} "
+                f"iterations ({os.path.relpath(fstar_path(wl, args.seed, tail), ROOT)})")
+    else:
+        fstar = np.minimum(c_pc.min(axis=1), c_pl.min(axis=1))
+        resolved = [False] * len(fstar)
+        fsrc = f"smallest FP32 cost of the {ref_iters}-iteration reference runs (no FP64 table)"
+    # F* is a lower bound of every cost: the FP32 runs may undercut it only by
+    # their own cost-evaluation rounding
+    undercut = float(np.max((fstar - np.minimum(c_pc.min(axis=1), c_pl.min(axis=1))) / fstar))
     k_pc = [first_below(c_pc[i], fstar[i], GAP) for i in range(len(fstar))]
     k_pl = [first_below(c_pl[i], fstar[i], GAP) for i in range(len(fstar))]
     reached_pc = all(k is not None for k in k_pc)
@@ -331,8 +466,12 @@ def main_batch(args, P, torch, wl):
     kp = max(k if k is not None else ref_iters for k in k_pc)
     kq = max(k if k is not None else ref_iters for k in k_pl)
     Lpc = [ref_pc.info(i)["L"] for i in range(len(fstar))]
-    log(f"reference runs ({ref_iters} its) {time.perf_counter() - t0:.1f}s; batch iterations "
-        f"to gap: precond {kp} (all reached: {reached_pc}), plain {kq} (all reached: {reached_pl})")
+    floor_pc = float(np.max((c_pc[:, -1] - fstar) / fstar))
+    floor_pl = float(np.max((c_pl[:, -1] - fstar) / fstar))
+    log(f"reference runs ({ref_iters} its) {time.perf_counter() - t0:.1f}s; F* from {fsrc}; "
+        f"resolved {sum(resolved)}/{len(resolved)}; largest undercut {undercut:.2e}; "
+        f"batch iterations to gap: precond {kp} (all: {reached_pc}), plain {kq} (all: {reached_pl}); "
+        f"gap after {ref_iters}: precond {floor_pc:.2e}, plain {floor_pl:.2e}")
     del ref_pc, ref_pl
     stream = torch.cuda.current_stream()
     t_start = torch.cuda.Event(enable_timing=True)
@@ -349,7 +488,7 @@ def main_batch(args, P, torch, wl):
         torch.cuda.synchronize()
         return t_start.elapsed_time(t_end) / args.steps
 
-    plan_pc = batch_plan(P, B, wl, True, kp, args.power_iters, False)
+    plan_pc = batch_plan(P, B, wl, True, kp, args.power_iters, False, tail)
     ms_pc = timed(plan_pc)
     # roofline: the batched sketch A^T A Omega over all instances (one
     # persistent launch), a burst bracketed by events on the launch stream
@@ -364,15 +503,23 @@ def main_batch(args, P, torch, wl):
     sk_ms = t_start.elapsed_time(t_end) / burst
     tiles = plan_pc.tiles()
     del plan_pc
-    plan_pl = batch_plan(P, B, wl, False, kq, args.power_iters, False)
+    plan_pl = batch_plan(P, B, wl, False, kq, args.power_iters, False, tail)
     ms_pl = timed(plan_pl)
     del plan_pl
+    # Omega from pinned host memory to HBM (reported beside the value, which
+    # starts with every input resident in HBM)
+    t_start.record(stream)
+    for it, om_h in zip(B.items, B.omega_host):
+        it["omega"].copy_(om_h, non_blocking=True)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    up_ms = t_start.elapsed_time(t_end)
     log(f"preconditioned {ms_pc:.1f} ms ({kp} its), plain {ms_pl:.1f} ms ({kq} its); "
-        f"batched sketch {sk_ms * 1e3:.1f} us")
+        f"batched sketch {sk_ms * 1e3:.1f} us; Omega upload {up_ms:.1f} ms")
     achieved = B.sketch_bytes / (sk_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "batched sketch (A^T A Omega, all instances, one launch)",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": batch_sketch_traffic(wl, args.seed),
+            "kernel": "bstencil_kernel: batched sketch A^T A Omega, all instances, one launch",
             "bytes_per_launch": B.sketch_bytes, "avg_launch_us": round(sk_ms * 1e3, 2)}
     roof["measured_copy_peak"] = copy_peak(torch)
     roof["frac_of_copy_peak"] = round(achieved / roof["measured_copy_peak"], 4)
@@ -391,23 +538,48 @@ def main_batch(args, P, torch, wl):
         "config": {"workload": wl.name, "instances": wl.count,
                    "sizes": sorted(set(s.n for s in B.specs)), "pixels": int(sum(B.N)),
                    "ell_total": int(sum(s.ell for s in B.specs)), "solver_dtype": "f32",
-                   "factor_dtype": "f64", "reg": "tv", "inner": wl.inner,
+                   "factor_dtype": "f64", "reg": "tv", "inner": wl.inner, "tail": tail,
                    "power_iters": args.power_iters, "seed": args.seed, "tiles": tiles},
         "plain_apg_s": round(ms_pl / 1e3, 6),
         "speedup_vs_plain": round(ms_pl / ms_pc, 4),
+        "omega_upload_s": round(up_ms / 1e3, 6),
+        "value_with_omega_upload_s": round((ms_pc + up_ms) / 1e3, 6),
         "iters_to_gap": {"precond": kp, "plain": kq, "reference_iters": ref_iters,
                          "precond_per_instance_median": float(np.median(
                              [k if k is not None else ref_iters for k in k_pc])),
                          "plain_per_instance_median": float(np.median(
                              [k if k is not None else ref_iters for k in k_pl]))},
+        "fstar": {"source": fsrc, "resolved": int(sum(resolved)), "instances": len(resolved),
+                  "tolerance": 1e-8, "largest_undercut": undercut,
+                  "gap_after_reference": {"precond": floor_pc, "plain": floor_pl}},
         "L_precond_range": [float(min(Lpc)), float(max(Lpc))],
         "roofline": roof,
     }
+    if not args.no_oracle_err:
+        t0 = time.perf_counter()
+        out["oracle_err"] = oracle_err_batch(P, torch, wl, B, tail, args.seed)
+        log(f"oracle error leg took {time.perf_counter() - t0:.1f}s")
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline_batch(wl, B, kp, args.power_iters, args.seed)
         log(f"cpu baseline leg took {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
+
+
+def batch_sketch_traffic(wl, seed):
+    """HBM bytes of one batched sketch launch from the committed rocprofv3
+    counter summary, or None when the stencil source changed since it was
+    taken or the workload differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "bstencil_batch64_hbm.json")
+    src = os.path.join(ROOT, "paper_2411_08178_amd", "csrc", "batch.hip")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("workload") != wl.name or d.get("seed") != seed or \
+            hashlib.sha1(open(src, "rb").read()).hexdigest() != d["source_sha1"]:
+        return None
+    return d["traffic_bytes_per_launch"]
 
 
 # ---------------------------------------------------------------- IRM
@@ -589,7 +761,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sr512", choices=sorted(WORKLOAD_KEYS))
+    ap.add_argument("--workload", default="batch64", choices=sorted(WORKLOAD_KEYS))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--power-iters", type=int, default=100)
     ap.add_argument("--rate-sweep", default="",
@@ -601,6 +773,14 @@ def main():
     ap.add_argument("--irm-p", type=float, default=1.0,
                     help="data-term exponent p of the IRM workload (the paper runs 0.5 ... 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-err", action="store_true",
+                    help="skip the FP64-oracle error leg")
+    ap.add_argument("--make-fstar", action="store_true",
+                    help="batched workload: compute the FP64 F* table (long runs of both methods)")
+    ap.add_argument("--fstar-out", default="",
+                    help="path of the F* table to write (--make-fstar; default bench_fstar/)")
+    ap.add_argument("--fstar-range", default="",
+                    help="a:b -- instances of the F* table to compute (--make-fstar)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -629,6 +809,8 @@ def main():
 
     wl = W.workload(WORKLOAD_KEYS[args.workload])
     if wl.count > 1:
+        if args.make_fstar:
+            return make_fstar(args, P, torch, wl)
         if args.ref_iters == 20000:
             args.ref_iters = 300
         return main_batch(args, P, torch, wl)

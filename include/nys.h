@@ -8,13 +8,23 @@
  * - Array pointers are DEVICE pointers unless a comment says "host".  They are
  *   owned by the caller; the library never frees or keeps them past the call
  *   (handles copy what they need).
+ * - Workspaces: every call that needs device scratch takes `ws` / `ws_bytes`,
+ *   a caller-owned device buffer (256-byte aligned) of at least the size its
+ *   *_workspace_size query returns for the same arguments.  The library
+ *   allocates device memory only when a handle is created (nys_op_create,
+ *   nys_factor, batch_solve_create; irm_solve with a sketch creates one
+ *   preconditioner handle per call) and frees it in the handle's destroy
+ *   call.  A workspace may be reused once the work enqueued with it has run;
+ *   two calls whose work may overlap need two workspaces.  Too small a
+ *   workspace is EINVAL, returned before anything is enqueued.
  * - Images are row-major n1 x n2; a stack of `ncols` images is contiguous
  *   ([col][n1][n2]).  The tall N x K matrices of the paper (Omega, Y, U) are
  *   stored column by column, i.e. as K images.  Sinograms are [view][bin].
  * - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
  *   enqueue work and return; argument errors are returned synchronously before
- *   anything is enqueued.  Numerical failures are recorded in the handle's
- *   device status word and read by nys_pc_info / the solve info array.
+ *   anything is enqueued.  Numerical failures are recorded in device status
+ *   words (the preconditioner's, read by nys_pc_info; the solve's, the first
+ *   int32 of its workspace) and returned by the calls that synchronise.
  * - Storage types: NYS_F64, NYS_F32, NYS_BF16 (bfloat16, FP32 accumulation).
  * - Handles are not safe for concurrent use from several streams.
  * - On any non-OK status, nys_last_error() returns a message (thread-local).
@@ -94,8 +104,9 @@ typedef struct {
    * a flat detector at fan_det past the centre, perpendicular to it; bin b at
    * u = (b - (bins - 1) / 2) fan_du along (cos, sin).  Every ray, a line
    * n . p = s, is sampled as in PARALLEL_BEAM with its own normal n and
-   * offset s; the adjoint is the exact transpose (scattered with atomic
-   * additions, so its summation order is not fixed). */
+   * offset s; the adjoint is the exact transpose, gathered per pixel (no
+   * atomics) when the source lies outside the image's circumscribed circle,
+   * else scattered with atomic additions (summation order not fixed). */
   double fan_src, fan_det, fan_du;
 } nys_op_desc;
 
@@ -110,13 +121,16 @@ void nys_op_destroy(nys_op op);
 /* Number of unknowns N and of measurements M of one column (host out). */
 nys_status nys_op_shape(nys_op op, int64_t* n_unknowns, int64_t* n_meas);
 
+/* Workspace bytes of op_forward / op_adjoint on `ncols` columns of dtype dt
+ * (host out; 0 when the operator needs none). */
+nys_status nys_op_workspace_size(nys_op op, nys_dtype dt, int64_t ncols, size_t* bytes);
 /* y = A x for `ncols` stacked columns; x: ncols*N, y: ncols*M, dtype F64 or
  * F32.  x and y must not overlap. */
 nys_status op_forward(nys_op op, nys_dtype dt, const void* x, void* y,
-                      int64_t ncols, void* stream);
+                      int64_t ncols, void* ws, size_t ws_bytes, void* stream);
 /* x = A^T y for `ncols` stacked columns. */
 nys_status op_adjoint(nys_op op, nys_dtype dt, const void* y, void* x,
-                      int64_t ncols, void* stream);
+                      int64_t ncols, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Sketch, Alg. 1 step 2 (and Sec. III-C, on-the-fly batched evaluation):
@@ -124,11 +138,12 @@ nys_status op_adjoint(nys_op op, nys_dtype dt, const void* y, void* x,
  * Phi = W A^T A W^T), all `ell` columns in one batched launch sequence.
  * omega, Y: ell*N in dtype `dt`; BF16 keeps FP32 accumulation inside.
  * ------------------------------------------------------------------------- */
+nys_status nys_sketch_workspace_size(nys_op op, nys_dtype dt, int64_t ell, size_t* bytes);
 nys_status nys_sketch(nys_op op, nys_dtype dt, const void* omega, void* Y,
-                      int64_t ell, void* stream);
+                      int64_t ell, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Nystrom factorisation, Alg. 1 steps 3-8, and the preconditioner of eq. (6):
+ * Nystrom factorisation, Alg. 1 steps 3-8, and the preconditioner of eq. (11):
  *   nu; Y_nu = Y + nu Omega; C = chol(Omega^T Y_nu) (lower, symmetrised);
  *   B = Y_nu C^{-T}; [U, S] = svd(B); shat = max(0, S^2 - nu).
  * B is not formed: the ell x ell FP64 matrix C^{-1} Y_nu^T Y_nu C^{-T} is
@@ -149,10 +164,13 @@ typedef struct {
 } nys_factor_opts;
 
 /* omega, Y: ell*N in dtype in_dt (F64, F32 or BF16).  ell <= 128.
- * The handle owns U (ell*N in u_dtype) and the FP64 spectrum. */
+ * The handle owns U (ell*N in u_dtype), the FP64 spectrum and the semismooth
+ * Newton buffers, allocated here; the factorisation's scratch (Gram partials,
+ * the 2 ell x 2 ell Gram, the ell x ell FP64 matrices) is the workspace. */
+nys_status nys_factor_workspace_size(int64_t N, int64_t ell, size_t* bytes);
 nys_status nys_factor(const void* omega, const void* Y, nys_dtype in_dt,
                       int64_t N, int64_t ell, const nys_factor_opts* opts,
-                      nys_pc* out, void* stream);
+                      void* ws, size_t ws_bytes, nys_pc* out, void* stream);
 void nys_pc_destroy(nys_pc pc);
 
 /* Synchronises `stream` and copies to host: shat (ell values, descending,
@@ -176,39 +194,44 @@ nys_status nys_pc_u(nys_pc pc, const void** u, int64_t* N, int64_t* ell, int64_t
 /* Copies U into the caller's device buffer `dst`, packed as ell*N (u_dtype). */
 nys_status nys_pc_copy_u(nys_pc pc, void* dst, void* stream);
 
-/* out = P^{-1} v (inverse != 0) or P v, for `ncols` stacked vectors of
- * length N, dtype = the pc's u_dtype.  out may equal v. */
+/* out = P^{-1} v (inverse != 0) or P v (eq. (11)), for `ncols` stacked
+ * vectors of length N, dtype = the pc's u_dtype.  out may equal v.  The
+ * workspace holds the coefficients and the block partials of U^T v. */
+nys_status nys_apply_workspace_size(nys_pc pc, int64_t ncols, size_t* bytes);
 nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
-                     void* out, int64_t ncols, void* stream);
+                     void* out, int64_t ncols, void* ws, size_t ws_bytes, void* stream);
 
 /* Squared P-norm of a difference, the metric of the WAPG rate bound
- * 2 L_f^P ||x^1 - x^*||_P^2 / (k + 1)^2 stated after eq. (15) (Sec. IV-B):
+ * 2 L_f^P ||x^1 - x^*||_P^2 / (k + 1)^2 stated after eq. (20) (Sec. III-B):
  * *out (one device double, written on `stream`) = (a - b)^T P (a - b), or
  * (a - b)^T P^{-1} (a - b) when inverse != 0; pc = NULL gives P = I.  a, b:
  * n device values (n = the pc's N, dtype = its u_dtype; F64 or F32 without
  * a pc); b may be NULL (b = 0).  With a pc the difference and P (a - b) are
- * rounded to dt; the dot product accumulates in FP64 (without a pc by atomic
- * additions of block sums, so its last bits depend on their order).  Uses a
- * workspace held by the pc (allocated on the first call): calls on one pc
- * must not overlap. */
+ * rounded to dt; the dot product accumulates in FP64 block partials summed
+ * in a fixed order. */
+nys_status nys_pnorm2_workspace_size(nys_pc pc, int64_t n, nys_dtype dt, size_t* bytes);
 nys_status nys_pnorm2(nys_pc pc, int64_t n, int32_t inverse, nys_dtype dt, const void* a,
-                      const void* b, double* out, void* stream);
+                      const void* b, double* out, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Weighted proximal map (definition in Sec. I-D):
+ * Weighted proximal map (eq. (5), Sec. I-D):
  *   x = argmin_u  lambda_bar g(u) + 1/2 ||u - s||_P^2,   C = R^N,
  * P = I when pc is NULL.
  *  TV / TV_ANISO / HS1 / HS2 / HSINF: dual accelerated projected gradient on
- *   Q for n_inner iterations (eqs. (17)-(22)); x(Q) = s - lambda_bar P^{-1}
+ *   Q for n_inner iterations (eqs. (21)-(29)); x(Q) = s - lambda_bar P^{-1}
  *   L^T Q; the step is 1 / (lambda_bar ||L||^2 ||P^{-1}||).  The dual ball of
- *   eq. (18) is per group: the unit l2 ball (TV), [-1, 1] (TV_ANISO), and for
+ *   eq. (23) is per group: the unit l2 ball (TV), [-1, 1] (TV_ANISO), and for
  *   the Hessian groups the unit Schatten-inf, -2, -1 ball (HS1, HS2, HSINF).
  *   `state` holds Q (2*N values for TV, 3*N for the Hessian kinds, dtype dt)
  *   and is used as the warm start and updated.
  *  L1: Thm. 1 with P = I + U diag(e) U^T: gamma solves
  *   gamma = diag(e) U^T (soft(s - U gamma) - s), semismooth Newton with
  *   backtracking on ||F||; x = soft(s - U gamma).  `state` holds gamma
- *   (ell FP64 values) as warm start.  P = I gives x = soft(s).
+ *   (ell FP64 values) as warm start.  P = I gives x = soft(s).  The call
+ *   waits for the device's Newton decisions and returns NYS_ENOTFINITE when
+ *   ||F|| is not finite (the warm start is then left as it was) and
+ *   NYS_ENOCONV when max_newton trial points end without convergence (x and
+ *   the warm start then hold the last accepted point).
  * state may be NULL (cold start, not kept).  x may be s (in place); no other
  * overlap of s and x is allowed.
  * ------------------------------------------------------------------------- */
@@ -222,15 +245,17 @@ typedef struct {
   int32_t box;         /* != 0: x restricted to C = {lo <= x_i <= hi} (TV and
                           Hessian kinds only): x(Q) = prox^P_{delta_C}(s -
                           lambda_bar P^{-1} L^T Q) in every dual iteration
-                          (eqs. (20)-(22)), the P-weighted projection by Thm. 1
+                          (eqs. (26), (29)), the P-weighted projection by Thm. 1
                           with the clip in place of the soft threshold (the
                           clip itself when P = I); 0: C = R^N */
   double lo, hi;       /* the box (lo <= hi; hi may be +inf) */
 } nys_reg_desc;
 
+nys_status nys_prox_workspace_size(const nys_reg_desc* reg, nys_pc pc, nys_dtype dt,
+                                   size_t* bytes);
 nys_status prox_weighted(const nys_reg_desc* reg, double lambda_bar, nys_pc pc,
                          nys_dtype dt, const void* s, void* x, void* state,
-                         void* stream);
+                         void* ws, size_t ws_bytes, void* stream);
 /* Bytes of `state` for prox_weighted (host out). */
 nys_status nys_prox_state_bytes(const nys_reg_desc* reg, nys_pc pc,
                                 nys_dtype dt, size_t* bytes);
@@ -265,15 +290,24 @@ typedef struct {
 
 /* x_out: N values (solver dtype dt = F64 or F32).  costs: device, max_iter
  * FP64 values F(x^{k+1}) or NULL.  info (host, 8 doubles, may be NULL):
- * [0] alpha used, [1] L estimate, [2] status word, [3] SSN trial points of
- * the last outer iteration.  Synchronises the stream when info != NULL. */
+ * [0] alpha used, [1] L estimate, [2] status, [3] reserved.
+ * The first int32 of the workspace is the solve's device status word: 0, or
+ * NYS_ENOTFINITE when x_out holds a NaN or infinity at the end (set by the
+ * last kernel of the call).  With info != NULL the stream is synchronised and
+ * the call returns that status (NYS_ENOTFINITE) or NYS_ENOCONV when an l1
+ * prox ran out of Newton trial points (the iteration goes on from its last
+ * accepted point); without info it returns NYS_ENOCONV in that case and the
+ * word is left for the caller to read.  A power method that meets non-finite
+ * values returns NYS_ENOTFINITE before the iteration starts. */
+nys_status nys_workspace_size(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                              size_t* bytes);
 nys_status solve(const nys_problem* prob, nys_pc pc, nys_dtype dt,
                  const nys_solve_opts* opts, void* x_out, double* costs,
-                 double* info, void* stream);
+                 double* info, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Unrolled, differentiable WAPG (Alg. 3) with the P-weighted TV prox (dual
- * FISTA of eqs. (17)-(22), warm-started across outer iterations): a fixed
+ * FISTA of eqs. (21)-(29), warm-started across outer iterations): a fixed
  * number n_outer of outer and n_inner of inner iterations, a fixed step
  * alpha, u^1 = x^1 = 0, Q = 0.  The forward keeps u_k and the dual Q_k of
  * every outer iteration in the workspace; the backward recomputes one outer
@@ -317,12 +351,12 @@ nys_status unrolled_backward(const nys_problem* prob, nys_pc pc, nys_dtype dt,
  * f = 1/2 ||h_i * x - y_i||^2 and lambda_i g(x), g = TV, anisotropic TV or
  * a Hessian Schatten prior HS1 / HS2 / HSINF (one kind for the batch), by
  * WAPG (Alg. 3) from x = u = 0 with the
- * P-weighted prox of the dual iterations (eqs. (17)-(22)).  With
- * precondition = 1, P is the Nystrom preconditioner of eq. (6) built from the
+ * P-weighted prox of the dual iterations (eqs. (21)-(29)).  With
+ * precondition = 1, P is the Nystrom preconditioner of eq. (11) built from the
  * sketch Y = A^T A Omega (Alg. 1, step 2) and the shifted factorisation
  * (Alg. 1, steps 3-7); with precondition = 0, P = I (plain APG).  The step is
  * 1 / (safety L) with L from power_iters power-method steps on P^{-1} A^T A
- * (the constant of eq. (15)).  Images, sketches and iterates are FP32, the
+ * (the constant of eq. (20)).  Images, sketches and iterates are FP32, the
  * factorisation and all reductions FP64.
  *
  * batch_solve_create checks the items, allocates every buffer of the batch,
@@ -396,7 +430,7 @@ void batch_solve_destroy(nys_batch b);
  * the previous iterate and solves Phi_k x = A^T W_f y,
  * Phi_k = A^T W_f A + lambda L^T W_g L, by conjugate gradients from the
  * previous iterate until ||b - Phi_k x|| <= cg_tol ||b|| or max_cg steps.  With
- * ell > 0 the CG is preconditioned by the Nystrom P of eq. (6), rebuilt at
+ * ell > 0 the CG is preconditioned by the Nystrom P of eq. (11), rebuilt at
  * every outer iteration from Y = Phi_k Omega (Alg. 1).  Stops after
  * max_outer iterations or when ||x_k - x_{k-1}|| <= outer_tol ||x_k||.
  * Synchronises `stream` (CG scalars are read back every step).
@@ -409,7 +443,7 @@ typedef struct {
   int32_t max_cg;       /* CG steps per outer iteration */
   double cg_tol;        /* relative residual of the x-update */
   int32_t nu_mode;      /* as nys_factor_opts */
-  int32_t tail;         /* as nys_factor_opts; 1 = s_K as printed in eq. (6) */
+  int32_t tail;         /* as nys_factor_opts; 1 = s_K as printed in eq. (11) */
   double mu;            /* < 0: mu = nu */
 } nys_irm_opts;
 
@@ -419,14 +453,18 @@ typedef struct {
  * every outer iteration and *outer_done (host, may be NULL) their count;
  * info (host, 3 * max_outer doubles, may be NULL) receives per outer
  * iteration the factorisation status (nys_status), k_eff and the shift nu. */
+nys_status irm_workspace_size(const nys_problem* prob, nys_dtype dt, int64_t ell,
+                              size_t* bytes);
 nys_status irm_solve(const nys_problem* prob, nys_dtype dt, const nys_irm_opts* opts,
                      const void* omega, int64_t ell, const void* x0, void* x,
-                     int32_t* cg_iters, int32_t* outer_done, double* info, void* stream);
+                     int32_t* cg_iters, int32_t* outer_done, double* info, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /* F(x) = f(x) + lambda g(x) for one column, FP64 accumulation, written to the
  * device double `cost`. */
+nys_status nys_cost_workspace_size(const nys_problem* prob, nys_dtype dt, size_t* bytes);
 nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void* x,
-                    double* cost, void* stream);
+                    double* cost, void* ws, size_t ws_bytes, void* stream);
 
 /* Message of the last non-OK status on this thread. */
 const char* nys_last_error(void);

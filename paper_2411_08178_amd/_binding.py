@@ -99,22 +99,32 @@ def lib():
         sig = {
             "nys_op_create": [C.POINTER(OpDesc), C.POINTER(vp)],
             "nys_op_shape": [vp, C.POINTER(i64), C.POINTER(i64)],
-            "op_forward": [vp, i32, vp, vp, i64, vp],
-            "op_adjoint": [vp, i32, vp, vp, i64, vp],
-            "nys_sketch": [vp, i32, vp, vp, i64, vp],
-            "nys_factor": [vp, vp, i32, i64, i64, C.POINTER(FactorOpts), C.POINTER(vp), vp],
+            "nys_op_workspace_size": [vp, i32, i64, C.POINTER(C.c_size_t)],
+            "nys_sketch_workspace_size": [vp, i32, i64, C.POINTER(C.c_size_t)],
+            "nys_factor_workspace_size": [i64, i64, C.POINTER(C.c_size_t)],
+            "nys_apply_workspace_size": [vp, i64, C.POINTER(C.c_size_t)],
+            "nys_pnorm2_workspace_size": [vp, i64, i32, C.POINTER(C.c_size_t)],
+            "nys_prox_workspace_size": [C.POINTER(RegDesc), vp, i32, C.POINTER(C.c_size_t)],
+            "nys_workspace_size": [C.POINTER(Problem), vp, i32, C.POINTER(C.c_size_t)],
+            "nys_cost_workspace_size": [C.POINTER(Problem), i32, C.POINTER(C.c_size_t)],
+            "irm_workspace_size": [C.POINTER(Problem), i32, i64, C.POINTER(C.c_size_t)],
+            "op_forward": [vp, i32, vp, vp, i64, vp, C.c_size_t, vp],
+            "op_adjoint": [vp, i32, vp, vp, i64, vp, C.c_size_t, vp],
+            "nys_sketch": [vp, i32, vp, vp, i64, vp, C.c_size_t, vp],
+            "nys_factor": [vp, vp, i32, i64, i64, C.POINTER(FactorOpts), vp, C.c_size_t,
+                           C.POINTER(vp), vp],
             "nys_pc_info": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i32), C.POINTER(i32), vp],
             "nys_pc_u": [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                          C.POINTER(i32)],
             "nys_pc_diag": [vp, C.POINTER(dbl), i32, vp],
             "nys_pc_copy_u": [vp, vp, vp],
-            "nys_apply": [vp, i32, i32, vp, vp, i64, vp],
-            "nys_pnorm2": [vp, i64, i32, i32, vp, vp, vp, vp],
-            "prox_weighted": [C.POINTER(RegDesc), dbl, vp, i32, vp, vp, vp, vp],
+            "nys_apply": [vp, i32, i32, vp, vp, i64, vp, C.c_size_t, vp],
+            "nys_pnorm2": [vp, i64, i32, i32, vp, vp, vp, vp, C.c_size_t, vp],
+            "prox_weighted": [C.POINTER(RegDesc), dbl, vp, i32, vp, vp, vp, vp, C.c_size_t, vp],
             "nys_prox_state_bytes": [C.POINTER(RegDesc), vp, i32, C.POINTER(C.c_size_t)],
             "solve": [C.POINTER(Problem), vp, i32, C.POINTER(SolveOpts), vp, vp,
-                      C.POINTER(dbl), vp],
-            "nys_cost": [C.POINTER(Problem), i32, vp, vp, vp],
+                      C.POINTER(dbl), vp, C.c_size_t, vp],
+            "nys_cost": [C.POINTER(Problem), i32, vp, vp, vp, C.c_size_t, vp],
             "nys_unrolled_workspace": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32,
                                        C.POINTER(C.c_size_t)],
             "unrolled_forward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
@@ -122,7 +132,7 @@ def lib():
             "unrolled_backward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
                                   C.POINTER(dbl), vp, vp, C.POINTER(dbl), vp, C.c_size_t, vp],
             "irm_solve": [C.POINTER(Problem), i32, C.POINTER(IrmOpts), vp, i64, vp, vp,
-                          C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl), vp],
+                          C.POINTER(i32), C.POINTER(i32), C.POINTER(dbl), vp, C.c_size_t, vp],
             "batch_solve_create": [C.POINTER(BatchItem), i32, C.POINTER(BatchOpts),
                                    C.POINTER(vp), vp],
             "batch_solve_run": [vp, vp],
@@ -180,6 +190,19 @@ def _ptr(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr())
 
 
+def _workspace(query, *args):
+    """A device workspace of the size the library's query returns: (tensor or
+    None, pointer, bytes).  Allocated by torch on the current stream (the
+    library allocates nothing per call); 256-byte aligned."""
+    nb = C.c_size_t()
+    _check(query(*args, C.byref(nb)))
+    if nb.value == 0:
+        return None, None, 0
+    t = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    off = (-t.data_ptr()) % 256
+    return t, C.c_void_p(t.data_ptr() + off), nb.value
+
+
 class Operator:
     """Handle of an operator A (optionally composed with Haar synthesis)."""
 
@@ -233,7 +256,8 @@ def op_forward(op: Operator, x: torch.Tensor, out: Optional[torch.Tensor] = None
     lead = x.shape[:-2] if x.dim() >= 2 and x.shape[-2:] == (op.n1, op.n2) else (n,)
     if out is None:
         out = torch.empty(tuple(lead) + op.meas_shape, dtype=x.dtype, device=x.device)
-    _check(lib().op_forward(op.handle, _dt(x), _ptr(x), _ptr(out), n, _stream()))
+    ws, wp, wb = _workspace(lib().nys_op_workspace_size, op.handle, _dt(x), n)
+    _check(lib().op_forward(op.handle, _dt(x), _ptr(x), _ptr(out), n, wp, wb, _stream()))
     return out
 
 
@@ -242,7 +266,8 @@ def op_adjoint(op: Operator, y: torch.Tensor, out: Optional[torch.Tensor] = None
     lead = y.shape[:-2] if y.dim() >= 2 else (n,)
     if out is None:
         out = torch.empty(tuple(lead) + (op.n1, op.n2), dtype=y.dtype, device=y.device)
-    _check(lib().op_adjoint(op.handle, _dt(y), _ptr(y), _ptr(out), n, _stream()))
+    ws, wp, wb = _workspace(lib().nys_op_workspace_size, op.handle, _dt(y), n)
+    _check(lib().op_adjoint(op.handle, _dt(y), _ptr(y), _ptr(out), n, wp, wb, _stream()))
     return out
 
 
@@ -250,7 +275,9 @@ def nys_sketch(op: Operator, omega: torch.Tensor, out: Optional[torch.Tensor] = 
     ell = _ncols(omega, op.N)
     if out is None:
         out = torch.empty_like(omega)
-    _check(lib().nys_sketch(op.handle, _dt(omega), _ptr(omega), _ptr(out), ell, _stream()))
+    ws, wp, wb = _workspace(lib().nys_sketch_workspace_size, op.handle, _dt(omega), ell)
+    _check(lib().nys_sketch(op.handle, _dt(omega), _ptr(omega), _ptr(out), ell, wp, wb,
+                            _stream()))
     return out
 
 
@@ -297,8 +324,9 @@ def nys_factor(omega: torch.Tensor, Y: torch.Tensor, ell: int, nu_mode: int = 0,
     N = omega.numel() // ell
     o = FactorOpts(nu_mode, 0 if tail == "sqrt" else 1, mu, max_escalations, _DT[u_dtype])
     h = C.c_void_p()
-    _check(lib().nys_factor(_ptr(omega), _ptr(Y), _dt(omega), N, ell, C.byref(o), C.byref(h),
-                            _stream()))
+    ws, wp, wb = _workspace(lib().nys_factor_workspace_size, N, ell)
+    _check(lib().nys_factor(_ptr(omega), _ptr(Y), _dt(omega), N, ell, C.byref(o), wp, wb,
+                            C.byref(h), _stream()))
     return Preconditioner(h, N, ell, _DT[u_dtype])
 
 
@@ -307,8 +335,9 @@ def nys_apply(pc: Preconditioner, v: torch.Tensor, inverse: bool = True,
     n = _ncols(v, pc.N)
     if out is None:
         out = torch.empty_like(v)
+    ws, wp, wb = _workspace(lib().nys_apply_workspace_size, pc.handle, n)
     _check(lib().nys_apply(pc.handle, 1 if inverse else 0, _dt(v), _ptr(v), _ptr(out), n,
-                           _stream()))
+                           wp, wb, _stream()))
     return out
 
 
@@ -319,9 +348,10 @@ def pnorm2(pc: Optional[Preconditioner], a: torch.Tensor, b: Optional[torch.Tens
     if b is not None and (b.shape != a.shape or b.dtype != a.dtype):
         raise ValueError("pnorm2: a and b must share shape and dtype")
     out = torch.empty(1, dtype=torch.float64, device=a.device)
-    _check(lib().nys_pnorm2(pc.handle if pc is not None else None, n, 1 if inverse else 0,
-                            _dt(a), _ptr(a), _ptr(b) if b is not None else None, _ptr(out),
-                            _stream()))
+    h = pc.handle if pc is not None else None
+    ws, wp, wb = _workspace(lib().nys_pnorm2_workspace_size, h, n, _dt(a))
+    _check(lib().nys_pnorm2(h, n, 1 if inverse else 0, _dt(a), _ptr(a),
+                            _ptr(b) if b is not None else None, _ptr(out), wp, wb, _stream()))
     return float(out.item())
 
 
@@ -362,8 +392,10 @@ def prox_weighted(reg: RegDesc, lam_bar: float, pc: Optional[Preconditioner], s:
                   state: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None):
     if out is None:
         out = torch.empty_like(s)
-    _check(lib().prox_weighted(C.byref(reg), lam_bar, pc.handle if pc else None, _dt(s), _ptr(s),
-                               _ptr(out), _ptr(state), _stream()))
+    h = pc.handle if pc else None
+    ws, wp, wb = _workspace(lib().nys_prox_workspace_size, C.byref(reg), h, _dt(s))
+    _check(lib().prox_weighted(C.byref(reg), lam_bar, h, _dt(s), _ptr(s), _ptr(out), _ptr(state),
+                               wp, wb, _stream()))
     return out
 
 
@@ -387,16 +419,19 @@ def solve(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, pc: Optional[
     x = torch.empty((op.n1, op.n2), dtype=y.dtype, device=y.device)
     costs = torch.empty(max(max_iter, 1), dtype=torch.float64, device=y.device) if record_cost else None
     info = (C.c_double * 8)()
-    _check(lib().solve(C.byref(p), pc.handle if pc else None, _dt(y), C.byref(o), _ptr(x),
-                       _ptr(costs), info, _stream()))
-    return x, costs, dict(alpha=info[0], L=info[1], status=int(info[2]), ssn_trials=info[3])
+    h = pc.handle if pc else None
+    ws, wp, wb = _workspace(lib().nys_workspace_size, C.byref(p), h, _dt(y))
+    _check(lib().solve(C.byref(p), h, _dt(y), C.byref(o), _ptr(x), _ptr(costs), info, wp, wb,
+                       _stream()))
+    return x, costs, dict(alpha=info[0], L=info[1], status=int(info[2]))
 
 
 def nys_cost(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, x: torch.Tensor,
              loss: int = LOSS_LS, delta: float = 0.0) -> torch.Tensor:
     p = _problem(op, y, reg, lam, loss, delta)
     out = torch.empty(1, dtype=torch.float64, device=x.device)
-    _check(lib().nys_cost(C.byref(p), _dt(x), _ptr(x), _ptr(out), _stream()))
+    ws, wp, wb = _workspace(lib().nys_cost_workspace_size, C.byref(p), _dt(x))
+    _check(lib().nys_cost(C.byref(p), _dt(x), _ptr(x), _ptr(out), wp, wb, _stream()))
     return out
 
 
@@ -455,6 +490,8 @@ class UnrolledWAPGFn(torch.autograd.Function):
         _check(lib().nys_unrolled_workspace(C.byref(p), pc.handle if pc else None, _dt(y),
                                             C.byref(o), batch, C.byref(nb)))
         ws = torch.empty(nb.value, dtype=torch.uint8, device=y.device)
+        if ws.data_ptr() % 256:
+            raise NysError(1, "unrolled workspace is not 256-byte aligned")
         x = torch.empty((batch, op.n1, op.n2), dtype=y.dtype, device=y.device)
         lam_p = lam_h.numpy().ctypes.data_as(C.POINTER(C.c_double))
         _check(lib().unrolled_forward(C.byref(p), pc.handle if pc else None, _dt(y), C.byref(o),
@@ -592,8 +629,9 @@ def irm_solve(op: Operator, y: torch.Tensor, lam: float, p: float = 1.0, q: floa
     info = (C.c_double * (3 * max_outer))()
     done = C.c_int32()
     ell = 0 if omega is None else omega.shape[0]
+    ws, wp, wb = _workspace(lib().irm_workspace_size, C.byref(prob), dt, ell)
     _check(lib().irm_solve(C.byref(prob), dt, C.byref(o), _ptr(omega), ell, _ptr(x0), _ptr(x),
-                           its, C.byref(done), info, _stream()))
+                           its, C.byref(done), info, wp, wb, _stream()))
     if return_info:
         fac = [dict(status=int(info[3 * i]), k_eff=int(info[3 * i + 1]), nu=info[3 * i + 2])
                for i in range(done.value)] if ell else []

@@ -83,7 +83,48 @@ inline size_t dtype_size(nys_dtype d) {
 }
 
 // ---------------------------------------------------------------- buffers
-// Device buffer owned by a handle; grows on demand, freed by the owner.
+// Caller-owned device scratch of one call, handed out as a stack: take()
+// returns the next 256-byte aligned part, Mark restores the top on scope
+// exit.  Exhaustion is an argument error (the caller's workspace is smaller
+// than the size query returned); nothing is ever allocated.
+struct Scratch {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  Scratch() = default;
+  Scratch(void* p, size_t n) : base(static_cast<char*>(p)), cap(p ? n : 0) {}
+  template <class T> T* take(size_t count) {
+    const size_t b = (count * sizeof(T) + 255) / 256 * 256;
+    if (off + b > cap) {
+      set_error("workspace of %zu bytes is too small (needs more than %zu)", cap, off + b);
+      return nullptr;
+    }
+    T* p = reinterpret_cast<T*>(base + off);
+    off += b;
+    return p;
+  }
+  struct Mark {
+    Scratch* s;
+    size_t off;
+    explicit Mark(Scratch* sc) : s(sc), off(sc ? sc->off : 0) {}
+    ~Mark() { if (s) s->off = off; }
+  };
+};
+
+inline constexpr size_t ws_round(size_t b) { return (b + 255) / 256 * 256; }
+
+// ptr = count values of type T from the scratch bound to a handle.
+#define NYS_TAKE(scr, T, ptr, count)                                         \
+  do {                                                                       \
+    if (!(scr)) {                                                            \
+      ::nys::set_error("no workspace bound to the handle");                  \
+      return NYS_EINVAL;                                                     \
+    }                                                                        \
+    ptr = (scr)->template take<T>(count);                                    \
+    if (!ptr) return NYS_EINVAL;                                             \
+  } while (0)
+
+// Device buffer owned by a handle, allocated when the handle is created and
+// freed by its destroy call.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -141,10 +182,10 @@ struct nys_op_s {
   double sep_u[32] = {}, sep_v[32] = {};
   nys::DevBuf psf_dev;            // [flipped psf f64 | psf f64 | flipped f32 | psf f32]
   nys::DevBuf trig;               // per view: cos, sin (f64) then (f32)
-  nys::DevBuf tmp0, tmp1;         // intermediates of composed operators
-  nys::DevBuf tmp2;               // scratch of the Daubechies-4 passes and of the
-                                  // fan-beam adjoint's accumulation (narrow outputs)
-  mutable nys::DevBuf xT;         // transposed images (parallel-beam forward)
+  // the caller's workspace while a call enqueues work (null otherwise):
+  // intermediates of composed operators, Daubechies-4 pass scratch, the
+  // fan-beam adjoint's accumulation, transposed images of the parallel beam
+  nys::Scratch* scr = nullptr;
   // fan beam: per view cos, sin (f64), then per ray (view-major) f0, g and the
   // step-length scale signed + for steps along rows, - along columns (f64);
   // filled at creation when the gathered adjoint applies (fan_gather)
@@ -161,10 +202,11 @@ struct nys_pc_s {
   double pinv_norm_cache = -1.0;  // ||P^{-1}|| once read back from the device
   nys::DevBuf U;                  // ell*N
   nys::DevBuf meta;               // FP64 device block, see factor.hip
-  nys::DevBuf work;               // scratch of nys_apply / prox
-  nys::DevBuf work2;              // cd of nys_apply / the gradient step
   nys::DevBuf ssn_ws;             // semismooth Newton state, partials, stored LU factors
-  nys::DevBuf pn_ws;              // P-norm: difference, P times it, block partials
+                                  // (allocated with the handle)
+  // the caller's workspace while a call enqueues work (null otherwise):
+  // block partials of U^T v, coefficients
+  nys::Scratch* scr = nullptr;
   // pinned, coherent host word (8 seq + outcome bits) written by the
   // semismooth Newton decision kernel and read by the host without a stream
   // synchronisation; the sequence number counts decisions
@@ -182,3 +224,35 @@ struct nys_pc_s {
   bool ssn_lu_valid = false;
   bool ssn_lu_hint = false;   // the last decision read reported stored factors
 };
+
+namespace nys {
+// A caller's workspace of ws_bytes for a call that needs `need` bytes:
+// large enough, non-null when needed, 256-byte aligned.
+inline nys_status check_workspace(const void* ws, size_t ws_bytes, size_t need, const char* what) {
+  NYS_REQUIRE(ws_bytes >= need, "%s: workspace of %zu bytes < %zu", what, ws_bytes, need);
+  NYS_REQUIRE(need == 0 || ws, "%s: null workspace", what);
+  NYS_REQUIRE(reinterpret_cast<uintptr_t>(ws) % 256 == 0, "%s: workspace not 256-byte aligned",
+              what);
+  return NYS_OK;
+}
+
+// Binds a caller's workspace to the handles of one call while it enqueues
+// work (the previous binding, if any, is restored on exit).
+struct WsBind {
+  Scratch s;
+  nys_op op;
+  nys_pc pc;
+  Scratch* prev_op = nullptr;
+  Scratch* prev_pc = nullptr;
+  WsBind(void* ws, size_t bytes, nys_op o, nys_pc p) : s(ws, bytes), op(o), pc(p) {
+    if (op) { prev_op = op->scr; op->scr = &s; }
+    if (pc) { prev_pc = pc->scr; pc->scr = &s; }
+  }
+  WsBind(const WsBind&) = delete;
+  WsBind& operator=(const WsBind&) = delete;
+  ~WsBind() {
+    if (op) op->scr = prev_op;
+    if (pc) pc->scr = prev_pc;
+  }
+};
+}  // namespace nys

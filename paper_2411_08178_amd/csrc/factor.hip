@@ -731,33 +731,50 @@ __global__ __launch_bounds__(256) void bform_u_kernel(const BDesc* __restrict__ 
                                    D.ell, D.ldu, D.U, k0, n);
 }
 
-template <class S>
-static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
-                              const nys_factor_opts& o, nys_pc pc, hipStream_t st) {
-  const int m = 2 * L;
-  const int ntiles = static_cast<int>(cdiv(m, kGT));
-  const int ntri = ntiles * (ntiles + 1) / 2;
-  int64_t nchunks = N / 4096;
-  if (nchunks < 1) nchunks = 1;
-  if (nchunks > 256) nchunks = 256;
-  int64_t chunk = (N + nchunks - 1) / nchunks;
-  chunk = (chunk + kGK - 1) / kGK * kGK;
-  nchunks = (N + chunk - 1) / chunk;
-  size_t part_d = static_cast<size_t>(nchunks) * ntri * kGT * kGT;
-  // MFMA Gram (BF16 / FP32): one block per chunk of at least 256 pixels
-  int64_t mfma_blocks = std::min<int64_t>(256, std::max<int64_t>(1, N / 256));
-  int64_t mfma_chunk = (N + mfma_blocks - 1) / mfma_blocks;
-  mfma_chunk = (mfma_chunk + 63) / 64 * 64;
-  mfma_blocks = (N + mfma_chunk - 1) / mfma_chunk;
-  {
+// Launch geometry and scratch of Alg. 1 steps 3-8 for N pixels and L
+// columns: the VALU Gram's pixel chunks and 32 x 32 tiles, the MFMA Gram's
+// blocks, and the FP64 scratch (Gram partials, the 2L x 2L Gram, the factor's
+// L x L matrices).
+struct FactorGeom {
+  int ntiles, ntri;
+  int64_t nchunks, chunk, mfma_blocks, mfma_chunk;
+  size_t part_d, G_d, w_d;
+  FactorGeom(int64_t N, int L) {
+    const int m = 2 * L;
+    ntiles = static_cast<int>(cdiv(m, kGT));
+    ntri = ntiles * (ntiles + 1) / 2;
+    nchunks = std::min<int64_t>(256, std::max<int64_t>(1, N / 4096));
+    chunk = (N + nchunks - 1) / nchunks;
+    chunk = (chunk + kGK - 1) / kGK * kGK;
+    nchunks = (N + chunk - 1) / chunk;
+    part_d = static_cast<size_t>(nchunks) * ntri * kGT * kGT;
+    // MFMA Gram (BF16): one block per chunk of at least 256 pixels
+    mfma_blocks = std::min<int64_t>(256, std::max<int64_t>(1, N / 256));
+    mfma_chunk = (N + mfma_blocks - 1) / mfma_blocks;
+    mfma_chunk = (mfma_chunk + 63) / 64 * 64;
+    mfma_blocks = (N + mfma_chunk - 1) / mfma_chunk;
     const int nrg = (2 * L + 31) / 32;
     const size_t mfma_d = (static_cast<size_t>(mfma_blocks) * nrg * (nrg + 1) / 2 * 1024 + 1) / 2;
     part_d = std::max(part_d, mfma_d);
+    G_d = static_cast<size_t>(m) * m;
+    w_d = 5 * static_cast<size_t>(L) * L + L;
   }
-  size_t G_d = static_cast<size_t>(m) * m;
-  size_t w_d = 5 * static_cast<size_t>(L) * L + L;
-  NYS_TRY(pc->work.ensure(sizeof(double) * (part_d + G_d + w_d)));
-  double* part = pc->work.as<double>();
+  size_t bytes() const { return ws_round(sizeof(double) * (part_d + G_d + w_d)); }
+};
+
+size_t factor_ws_bytes(int64_t N, int L) { return FactorGeom(N, L).bytes(); }
+
+template <class S>
+static nys_status factor_impl(const S* omega, const S* Y, int64_t N, int L,
+                              const nys_factor_opts& o, nys_pc pc, hipStream_t st) {
+  const FactorGeom g(N, L);
+  const int ntiles = g.ntiles, ntri = g.ntri;
+  const int64_t nchunks = g.nchunks, chunk = g.chunk, mfma_blocks = g.mfma_blocks,
+                mfma_chunk = g.mfma_chunk;
+  const size_t part_d = g.part_d, G_d = g.G_d;
+  Scratch::Mark mark(pc->scr);
+  double* part = nullptr;
+  NYS_TAKE(pc->scr, double, part, part_d + G_d + g.w_d);
   double* G = part + part_d;
   double* wb = G + G_d;
   FactorWork w;
@@ -859,21 +876,11 @@ nys_status factor_refresh(nys_pc pc, const void* omega, const void* Y, nys_dtype
   }
 }
 
-}  // namespace nys
-
-using namespace nys;
-
-extern "C" nys_status nys_factor(const void* omega, const void* Y, nys_dtype in_dt, int64_t N,
-                                 int64_t ell, const nys_factor_opts* opts, nys_pc* out,
-                                 void* stream) {
-  NYS_REQUIRE(omega && Y && out && N > 0, "nys_factor: bad argument");
-  NYS_REQUIRE(ell >= 1 && ell <= PcMeta::kMaxEll, "nys_factor: ell must be in [1, %d]", PcMeta::kMaxEll);
-  NYS_REQUIRE(ell <= N, "nys_factor: ell > N");
-  nys_factor_opts o{0, 0, -1.0, 6, NYS_F32};
-  if (opts) o = *opts;
-  NYS_REQUIRE(o.u_dtype == NYS_F64 || o.u_dtype == NYS_F32, "nys_factor: u_dtype must be F64/F32");
-  NYS_REQUIRE(o.nu_mode == 0 || o.nu_mode == 1, "nys_factor: nu_mode must be 0 or 1");
-  NYS_REQUIRE(o.tail == 0 || o.tail == 1, "nys_factor: tail must be 0 or 1");
+// A preconditioner handle for N pixels and ell columns with its own buffers,
+// allocated once here: U (padding rows zeroed on the stream), the FP64
+// metadata, the semismooth Newton buffer and the pinned decision word.
+nys_status pc_create(int64_t N, int64_t ell, const nys_factor_opts& o, nys_pc* out,
+                     hipStream_t st) {
   auto* pc = new nys_pc_s();
   pc->N = N;
   pc->ell = ell;
@@ -883,16 +890,63 @@ extern "C" nys_status nys_factor(const void* omega, const void* Y, nys_dtype in_
   // ell columns are not a power of two apart
   pc->ldu = (N + 63) / 64 * 64 + (N >= 16384 ? 96 : 0);
   pc->ell_pad = (ell + 15) / 16 * 16;
-  const size_t ubytes = dtype_size(static_cast<nys_dtype>(o.u_dtype)) * pc->ldu * pc->ell_pad;
-  nys_status s = pc->U.ensure(ubytes);
-  if (s == NYS_OK && hipMemset(pc->U.p, 0, ubytes) != hipSuccess) {
-    set_error("nys_factor: hipMemset of U failed");
-    s = NYS_EHIP;
-  }
+  const size_t ues = dtype_size(static_cast<nys_dtype>(o.u_dtype));
+  const size_t ucount = static_cast<size_t>(pc->ldu) * pc->ell_pad;
+  nys_status s = pc->U.ensure(ues * ucount);
   if (s == NYS_OK) s = pc->meta.ensure(sizeof(double) * PcMeta::kTotal);
-
+  if (s == NYS_OK) s = pc->ssn_ws.ensure(ssn_ws_bytes(N, static_cast<int>(ell), ues));
   if (s == NYS_OK) {
-    hipStream_t st = as_stream(stream);
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(unsigned long long), hipHostMallocCoherent) != hipSuccess) {
+      set_error("hipHostMalloc of the decision word failed");
+      s = NYS_ENOMEM;
+    } else {
+      pc->hflag = static_cast<unsigned long long*>(h);
+      *pc->hflag = 0;
+      pc->flag_seq = 0;
+    }
+  }
+  if (s == NYS_OK)
+    s = o.u_dtype == NYS_F64 ? fill_zero<double>(pc->U.as<double>(), ucount, st)
+                             : fill_zero<float>(pc->U.as<float>(), ucount, st);
+  if (s != NYS_OK) {
+    nys_pc_destroy(pc);
+    return s;
+  }
+  *out = pc;
+  return NYS_OK;
+}
+
+}  // namespace nys
+
+using namespace nys;
+
+extern "C" nys_status nys_factor_workspace_size(int64_t N, int64_t ell, size_t* bytes) {
+  NYS_REQUIRE(bytes && N > 0 && ell >= 1 && ell <= PcMeta::kMaxEll,
+              "nys_factor_workspace_size: bad argument");
+  *bytes = factor_ws_bytes(N, static_cast<int>(ell));
+  return NYS_OK;
+}
+
+extern "C" nys_status nys_factor(const void* omega, const void* Y, nys_dtype in_dt, int64_t N,
+                                 int64_t ell, const nys_factor_opts* opts, void* ws,
+                                 size_t ws_bytes, nys_pc* out, void* stream) {
+  NYS_REQUIRE(omega && Y && out && N > 0, "nys_factor: bad argument");
+  NYS_REQUIRE(ell >= 1 && ell <= PcMeta::kMaxEll, "nys_factor: ell must be in [1, %d]", PcMeta::kMaxEll);
+  NYS_REQUIRE(ell <= N, "nys_factor: ell > N");
+  NYS_REQUIRE(in_dt == NYS_F64 || in_dt == NYS_F32 || in_dt == NYS_BF16, "nys_factor: bad dtype");
+  nys_factor_opts o{0, 0, -1.0, 6, NYS_F32};
+  if (opts) o = *opts;
+  NYS_REQUIRE(o.u_dtype == NYS_F64 || o.u_dtype == NYS_F32, "nys_factor: u_dtype must be F64/F32");
+  NYS_REQUIRE(o.nu_mode == 0 || o.nu_mode == 1, "nys_factor: nu_mode must be 0 or 1");
+  NYS_REQUIRE(o.tail == 0 || o.tail == 1, "nys_factor: tail must be 0 or 1");
+  NYS_TRY(check_workspace(ws, ws_bytes, factor_ws_bytes(N, static_cast<int>(ell)), "nys_factor"));
+  hipStream_t st = as_stream(stream);
+  nys_pc pc = nullptr;
+  nys_status s = pc_create(N, ell, o, &pc, st);
+  if (s != NYS_OK) return s;
+  if (s == NYS_OK) {
+    WsBind bind(ws, ws_bytes, nullptr, pc);
     switch (in_dt) {
       case NYS_F64:
         s = factor_impl<double>(static_cast<const double*>(omega), static_cast<const double*>(Y), N,
@@ -902,13 +956,9 @@ extern "C" nys_status nys_factor(const void* omega, const void* Y, nys_dtype in_
         s = factor_impl<float>(static_cast<const float*>(omega), static_cast<const float*>(Y), N,
                                static_cast<int>(ell), o, pc, st);
         break;
-      case NYS_BF16:
+      default:
         s = factor_impl<uint16_t>(static_cast<const uint16_t*>(omega),
                                   static_cast<const uint16_t*>(Y), N, static_cast<int>(ell), o, pc, st);
-        break;
-      default:
-        set_error("nys_factor: bad dtype");
-        s = NYS_EINVAL;
     }
   }
   if (s != NYS_OK) {
@@ -925,10 +975,7 @@ extern "C" void nys_pc_destroy(nys_pc pc) {
   (void)hipDeviceSynchronize();
   pc->U.release();
   pc->meta.release();
-  pc->work.release();
-  pc->work2.release();
   pc->ssn_ws.release();
-  pc->pn_ws.release();
   if (pc->hflag) (void)hipHostFree(pc->hflag);
   delete pc;
 }
@@ -967,10 +1014,18 @@ extern "C" nys_status nys_pc_copy_u(nys_pc pc, void* dst, void* stream) {
   return NYS_OK;
 }
 
+extern "C" nys_status nys_apply_workspace_size(nys_pc pc, int64_t ncols, size_t* bytes) {
+  NYS_REQUIRE(pc && bytes && ncols > 0, "nys_apply_workspace_size: bad argument");
+  *bytes = pc_ws_bytes(pc, ncols);
+  return NYS_OK;
+}
+
 extern "C" nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v, void* out,
-                                int64_t ncols, void* stream) {
+                                int64_t ncols, void* ws, size_t ws_bytes, void* stream) {
   NYS_REQUIRE(pc && v && out && ncols > 0 && ncols <= 65535, "nys_apply: bad argument");
   NYS_REQUIRE(static_cast<int32_t>(dt) == pc->u_dtype, "nys_apply: dtype must equal the pc's u_dtype");
+  NYS_TRY(check_workspace(ws, ws_bytes, pc_ws_bytes(pc, ncols), "nys_apply"));
+  WsBind bind(ws, ws_bytes, nullptr, pc);
   hipStream_t st = as_stream(stream);
   if (dt == NYS_F64)
     return pc_apply<double>(pc, inverse != 0, static_cast<const double*>(v), static_cast<double*>(out),
@@ -1014,11 +1069,11 @@ __global__ __launch_bounds__(256) void pdot_partial_kernel(const T* __restrict__
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// P = I: block sums of (a - b)^2 added to *out (zeroed by the caller).
+// P = I: block sums of (a - b)^2 (b may be null).
 template <class T>
 __global__ __launch_bounds__(256) void pdot_plain_kernel(const T* __restrict__ a,
                                                          const T* __restrict__ b, int64_t n,
-                                                         double* __restrict__ out) {
+                                                         double* __restrict__ part) {
   double s = 0.0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -1026,11 +1081,7 @@ __global__ __launch_bounds__(256) void pdot_plain_kernel(const T* __restrict__ a
     s += di * di;
   }
   s = block_sum_256(s);
-  if (threadIdx.x == 0) atomicAdd(out, s);
-}
-
-__global__ void pzero_kernel(double* out) {
-  if (threadIdx.x == 0) out[0] = 0.0;
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 __global__ __launch_bounds__(256) void pdot_final_kernel(const double* __restrict__ part, int nb,
@@ -1041,37 +1092,51 @@ __global__ __launch_bounds__(256) void pdot_final_kernel(const double* __restric
   if (threadIdx.x == 0) out[0] = s;
 }
 
+constexpr int kPnParts = 1024;
+
+// Workspace of nys_pnorm2: the difference and P (or P^{-1}) times it, the
+// dot product's block partials, the application's scratch.
+static size_t pnorm2_ws_bytes(nys_pc pc, int64_t n, size_t es) {
+  if (!pc) return ws_round(sizeof(double) * kPnParts);
+  return 2 * ws_round(es * static_cast<size_t>(n)) + ws_round(sizeof(double) * kPnParts) +
+         pc_ws_bytes(pc, 1);
+}
+
 template <class T>
-static nys_status pnorm2_impl(nys_pc pc, int64_t n, bool inverse, const T* a, const T* b,
-                              double* out, hipStream_t st) {
+static nys_status pnorm2_impl(nys_pc pc, Scratch* scr, int64_t n, bool inverse, const T* a,
+                              const T* b, double* out, hipStream_t st) {
+  double* part = nullptr;
+  NYS_TAKE(scr, double, part, kPnParts);
+  const unsigned nb = std::min<unsigned>(cdiv(n, 256), kPnParts);
   if (!pc) {
-    hipLaunchKernelGGL(pzero_kernel, dim3(1), dim3(64), 0, st, out);
-    NYS_TRY(launch_check("pzero_kernel"));
-    hipLaunchKernelGGL((pdot_plain_kernel<T>), dim3(std::min<unsigned>(cdiv(n, 256), 1024)),
-                       dim3(256), 0, st, a, b, n, out);
-    return launch_check("pdot_plain_kernel");
+    hipLaunchKernelGGL((pdot_plain_kernel<T>), dim3(nb), dim3(256), 0, st, a, b, n, part);
+    NYS_TRY(launch_check("pdot_plain_kernel"));
+  } else {
+    T* d = nullptr;
+    T* w = nullptr;
+    NYS_TAKE(scr, T, d, n);
+    NYS_TAKE(scr, T, w, n);
+    hipLaunchKernelGGL((pdiff_kernel<T>), dim3(std::min<unsigned>(cdiv(n, 256), 4096)), dim3(256), 0,
+                       st, a, b, d, n);
+    NYS_TRY(launch_check("pdiff_kernel"));
+    NYS_TRY(pc_apply<T>(pc, inverse, d, w, 1, st));
+    hipLaunchKernelGGL((pdot_partial_kernel<T>), dim3(nb), dim3(256), 0, st, d, w, n, part);
+    NYS_TRY(launch_check("pdot_partial_kernel"));
   }
-  const int64_t N = pc->N;
-  const size_t vb = (static_cast<size_t>(N) * sizeof(T) + 255) / 256 * 256;
-  constexpr int kMaxPart = 1024;
-  NYS_TRY(pc->pn_ws.ensure(2 * vb + kMaxPart * sizeof(double)));
-  char* base = pc->pn_ws.as<char>();
-  T* d = reinterpret_cast<T*>(base);
-  T* w = reinterpret_cast<T*>(base + vb);
-  double* part = reinterpret_cast<double*>(base + 2 * vb);
-  const unsigned nb = std::min<unsigned>(cdiv(N, 256), kMaxPart);
-  hipLaunchKernelGGL((pdiff_kernel<T>), dim3(std::min<unsigned>(cdiv(N, 256), 4096)), dim3(256), 0,
-                     st, a, b, d, N);
-  NYS_TRY(launch_check("pdiff_kernel"));
-  NYS_TRY(pc_apply<T>(pc, inverse, d, w, 1, st));
-  hipLaunchKernelGGL((pdot_partial_kernel<T>), dim3(nb), dim3(256), 0, st, d, w, N, part);
-  NYS_TRY(launch_check("pdot_partial_kernel"));
   hipLaunchKernelGGL(pdot_final_kernel, dim3(1), dim3(256), 0, st, part, static_cast<int>(nb), out);
   return launch_check("pdot_final_kernel");
 }
 
+extern "C" nys_status nys_pnorm2_workspace_size(nys_pc pc, int64_t n, nys_dtype dt, size_t* bytes) {
+  NYS_REQUIRE(bytes && n > 0 && (dt == NYS_F64 || dt == NYS_F32),
+              "nys_pnorm2_workspace_size: bad argument");
+  *bytes = pnorm2_ws_bytes(pc, n, dtype_size(dt));
+  return NYS_OK;
+}
+
 extern "C" nys_status nys_pnorm2(nys_pc pc, int64_t n, int32_t inverse, nys_dtype dt,
-                                 const void* a, const void* b, double* out, void* stream) {
+                                 const void* a, const void* b, double* out, void* ws,
+                                 size_t ws_bytes, void* stream) {
   NYS_REQUIRE(a && out && n > 0, "nys_pnorm2: bad argument");
   NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "nys_pnorm2: dtype must be F64 or F32");
   if (pc) {
@@ -1079,11 +1144,13 @@ extern "C" nys_status nys_pnorm2(nys_pc pc, int64_t n, int32_t inverse, nys_dtyp
     NYS_REQUIRE(static_cast<int32_t>(dt) == pc->u_dtype,
                 "nys_pnorm2: dtype must equal the pc's u_dtype");
   }
+  NYS_TRY(check_workspace(ws, ws_bytes, pnorm2_ws_bytes(pc, n, dtype_size(dt)), "nys_pnorm2"));
+  WsBind bind(ws, ws_bytes, nullptr, pc);
   hipStream_t st = as_stream(stream);
   if (dt == NYS_F64)
-    return pnorm2_impl<double>(pc, n, inverse != 0, static_cast<const double*>(a),
+    return pnorm2_impl<double>(pc, &bind.s, n, inverse != 0, static_cast<const double*>(a),
                                static_cast<const double*>(b), out, st);
-  return pnorm2_impl<float>(pc, n, inverse != 0, static_cast<const float*>(a),
+  return pnorm2_impl<float>(pc, &bind.s, n, inverse != 0, static_cast<const float*>(a),
                             static_cast<const float*>(b), out, st);
 }
 

@@ -5,7 +5,13 @@
 
 namespace nys {
 
-// y = A x / x = A^T y with the optional wavelet composition (ops.hip).
+// Workspace bytes of op_fwd / op_adj on ncols columns of es-byte values, and
+// of the sketch on ell columns stored in dt (ops.hip).
+size_t op_ws_bytes(nys_op op, size_t es, int64_t ncols);
+size_t sketch_ws_bytes(nys_op op, nys_dtype dt, int64_t ell);
+
+// y = A x / x = A^T y with the optional wavelet composition (ops.hip).  The
+// scratch comes from the workspace bound to op (op->scr).
 template <class T> nys_status op_fwd(nys_op op, const T* x, T* y, int64_t ncols, hipStream_t st);
 template <class T> nys_status op_adj(nys_op op, const T* y, T* x, int64_t ncols, hipStream_t st);
 // out = psi(A x - yobs) in one kernel (psi of the loss: identity for least
@@ -26,11 +32,14 @@ nys_status sketch_sr_chain_bf16(nys_op op, const uint16_t* omega, uint16_t* Y, i
 nys_status sketch_sr_chain_f32(nys_op op, const float* omega, float* Y, int64_t ell,
                                hipStream_t st);
 
-// Preconditioner application on T-typed vectors (factor.hip).
+// Preconditioner application on T-typed vectors (pinv.hip); the scratch
+// comes from the workspace bound to pc (pc->scr), pc_ws_bytes(pc, ncols) of
+// it for pc_apply.
 // out = v + U (coef . (U^T v)) with coef = d (P^{-1}) or e (P).
+size_t pc_ws_bytes(nys_pc pc, int64_t ncols);
 template <class T>
 nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, hipStream_t st);
-// cd[col][k] = coef_k (U^T v_col)_k in FP64 (coef = d or e); uses pc->work.
+// cd[col][k] = coef_k (U^T v_col)_k in FP64 (coef = d or e).
 template <class T>
 nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double* cd,
                      hipStream_t st);
@@ -42,8 +51,8 @@ template <class T>
 nys_status pc_coeffs_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, bool inverse, const T* v,
                         int64_t ncols, double* cd, hipStream_t st);
 // Its two stages: block partials of B^T v (FP64, nblk x ell_pad per column,
-// in pc->work until the next use of that buffer), then their sums times the
-// coefficients.
+// taken from the bound workspace and left there for the caller), then their
+// sums times the coefficients.
 struct CoefPartials {
   const double* part = nullptr;
   int nblk = 0, ncols = 0;
@@ -89,6 +98,9 @@ inline nys_status check_box(const nys_reg_desc& r) {
   NYS_REQUIRE(r.lo <= r.hi, "box constraint: lo must be <= hi");
   return NYS_OK;
 }
+// Bytes of the preconditioner's semismooth Newton buffer (state, partials,
+// stored factors) for N pixels, L columns and es-byte values.
+size_t ssn_ws_bytes(int64_t N, int L, size_t es);
 template <class T>
 nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
                     double* gamma_state, hipStream_t st, int* trials_out = nullptr,
@@ -114,15 +126,28 @@ struct PcMeta {
   static constexpr int kTotal = kScalars + 16;
 };
 
+// p[0:n] = 0 by a fill kernel on the stream (prox.hip).
+template <class T> nys_status fill_zero(T* p, size_t n, hipStream_t st);
+
+// Scratch bytes of Alg. 1 steps 3-8 for N pixels and L columns (factor.hip).
+size_t factor_ws_bytes(int64_t N, int L);
+
+// A preconditioner handle with its buffers (U zeroed on st), before any
+// factorisation (factor.hip).
+nys_status pc_create(int64_t N, int64_t ell, const nys_factor_opts& o, nys_pc* out,
+                     hipStream_t st);
+
 // Alg. 1 steps 3-8 on an existing handle of the same N, ell and dtype
-// (factor.hip).
+// (factor.hip); its scratch comes from the workspace bound to pc.
 nys_status factor_refresh(nys_pc pc, const void* omega, const void* Y, nys_dtype in_dt,
                           const nys_factor_opts& o, hipStream_t st);
 
-// Weighted prox (prox.hip).  state as in prox_weighted.
+// Weighted prox (prox.hip).  state as in prox_weighted; work: prox_ws_bytes
+// of device memory (the dual iteration's buffers); a preconditioner's
+// applications take their scratch from the workspace bound to pc.
 template <class T>
 nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    void* state, hipStream_t st, void* work = nullptr);
+                    void* state, hipStream_t st, void* work);
 template <class T> size_t prox_ws_bytes(const nys_reg_desc& reg);
 
 }  // namespace nys

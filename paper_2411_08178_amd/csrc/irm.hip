@@ -164,7 +164,7 @@ struct Irm {
   int n1, n2;
   T *wf, *wg, *meas, *g, *b, *r, *z, *d, *q, *xprev;
   double *part, *dots;
-  DevBuf buf, cols;     // vectors; multi-column temporaries of the sketch
+  Scratch* scr = nullptr;   // the caller's workspace (vectors, sketch temporaries)
 
   Irm(const nys_problem& pr, hipStream_t s) : p(pr), st(s) {
     N = p.op->N;
@@ -173,11 +173,15 @@ struct Irm {
     n2 = p.op->d.n2;
   }
 
+  static size_t vec_bytes(int64_t N, int64_t M) {
+    return ws_round(sizeof(T) * (2 * static_cast<size_t>(M) + 10 * N)) +
+           ws_round(sizeof(double) * (2 * kIrmRed + 8));
+  }
   nys_status alloc() {
     // meas, wf (M each); g, wg (2N each); b, r, z, d, q, xprev (N each)
     const size_t vecs = 2 * static_cast<size_t>(M) + 4 * N + 6 * N;
-    NYS_TRY(buf.ensure(sizeof(T) * vecs + sizeof(double) * (2 * kIrmRed + 8) + 512));
-    T* base = buf.as<T>();
+    T* base = nullptr;
+    NYS_TAKE(scr, T, base, vecs);
     meas = base;
     wf = meas + M;
     g = wf + M;
@@ -188,8 +192,7 @@ struct Irm {
     d = z + N;
     q = d + N;
     xprev = q + N;
-    part = reinterpret_cast<double*>(
-        (reinterpret_cast<uintptr_t>(xprev + N) + 255) & ~static_cast<uintptr_t>(255));
+    NYS_TAKE(scr, double, part, 2 * kIrmRed + 8);
     dots = part + 2 * kIrmRed;
     return NYS_OK;
   }
@@ -230,16 +233,35 @@ struct Irm {
   }
 };
 
+// Workspace of irm_impl: the vectors, the multi-column temporaries of the
+// sketch of Phi_k, the operator's scratch on as many columns and, with a
+// preconditioner, the scratch of Alg. 1 and of its applications.
+template <class T>
+size_t irm_ws_bytes(const nys_problem& p, int64_t ell) {
+  const int64_t N = p.op->N, M = p.op->M;
+  const int64_t ncs = ell > 0 ? ell : 1;
+  size_t b = Irm<T>::vec_bytes(N, M) +
+             ws_round(sizeof(T) * (static_cast<size_t>(M) + 2 * N + (ell > 0 ? N : 0)) * ncs) +
+             op_ws_bytes(p.op, sizeof(T), ncs);
+  if (ell > 0) {
+    const int64_t Lp = (ell + 15) / 16 * 16;
+    b += factor_ws_bytes(N, static_cast<int>(ell)) + ws_round(sizeof(double) * ell) +
+         ws_round(sizeof(double) * 256 * Lp);
+  }
+  return b;
+}
+
 template <class T>
 nys_status irm_impl(const nys_problem& p, const nys_irm_opts& o, const T* omega, int64_t ell,
                     const T* x0, T* x, int32_t* cg_iters, int32_t* outer_done, double* info,
-                    hipStream_t st) {
+                    Scratch* scr, hipStream_t st) {
   Irm<T> w(p, st);
+  w.scr = scr;
   NYS_TRY(w.alloc());
   const int64_t N = w.N, M = w.M;
   const int64_t ncs = ell > 0 ? ell : 1;
-  NYS_TRY(w.cols.ensure(sizeof(T) * (static_cast<size_t>(M) + 2 * N + (ell > 0 ? N : 0)) * ncs));
-  T* scrM = w.cols.template as<T>();
+  T* scrM = nullptr;
+  NYS_TAKE(scr, T, scrM, (static_cast<size_t>(M) + 2 * N + (ell > 0 ? N : 0)) * ncs);
   T* scrG = scrM + M * ncs;
   T* Y = scrG + 2 * N * ncs;
   if (x0 && x0 != x) NYS_CHECK_HIP(hipMemcpyAsync(x, x0, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
@@ -271,12 +293,14 @@ nys_status irm_impl(const nys_problem& p, const nys_irm_opts& o, const T* omega,
     if (ell > 0) {
       NYS_TRY(w.phi(omega, Y, ell, scrM, scrG));
       if (!pc) {
-        status = nys_factor(omega, Y, dt, N, ell, &fo, &pc, st);
+        // the preconditioner handle of this call (its buffers), bound to the
+        // caller's workspace for Alg. 1 and the applications
+        status = pc_create(N, ell, fo, &pc, st);
         if (status != NYS_OK) return status;
-      } else {
-        status = factor_refresh(pc, omega, Y, dt, fo, st);
-        if (status != NYS_OK) { nys_pc_destroy(pc); return status; }
+        pc->scr = scr;
       }
+      status = factor_refresh(pc, omega, Y, dt, fo, st);
+      if (status != NYS_OK) { nys_pc_destroy(pc); return status; }
       if (info) {
         double nu = 0;
         int32_t keff = 0, fst = 0;
@@ -339,10 +363,19 @@ nys_status irm_impl(const nys_problem& p, const nys_irm_opts& o, const T* omega,
 
 using namespace nys;
 
+extern "C" nys_status irm_workspace_size(const nys_problem* prob, nys_dtype dt, int64_t ell,
+                                         size_t* bytes) {
+  NYS_REQUIRE(prob && prob->op && bytes && ell >= 0 && ell <= PcMeta::kMaxEll,
+              "irm_workspace_size: bad argument");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "irm_workspace_size: dtype must be F64 or F32");
+  *bytes = dt == NYS_F64 ? irm_ws_bytes<double>(*prob, ell) : irm_ws_bytes<float>(*prob, ell);
+  return NYS_OK;
+}
+
 extern "C" nys_status irm_solve(const nys_problem* prob, nys_dtype dt, const nys_irm_opts* opts,
                                 const void* omega, int64_t ell, const void* x0, void* x,
-                                int32_t* cg_iters, int32_t* outer_done, double* info,
-                                void* stream) {
+                                int32_t* cg_iters, int32_t* outer_done, double* info, void* ws,
+                                size_t ws_bytes, void* stream) {
   NYS_REQUIRE(prob && prob->op && prob->y && opts && x, "irm_solve: bad argument");
   NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "irm_solve: dtype must be F64 or F32");
   const nys_irm_opts& o = *opts;
@@ -356,12 +389,16 @@ extern "C" nys_status irm_solve(const nys_problem* prob, nys_dtype dt, const nys
               "irm_solve: ell must be 0 (plain CG) or in [1, %d] with omega", PcMeta::kMaxEll);
   NYS_REQUIRE(o.tail == 0 || o.tail == 1, "irm_solve: tail must be 0 or 1");
   NYS_REQUIRE(o.nu_mode == 0 || o.nu_mode == 1, "irm_solve: nu_mode must be 0 or 1");
+  size_t need = 0;
+  NYS_TRY(irm_workspace_size(prob, dt, ell, &need));
+  NYS_TRY(check_workspace(ws, ws_bytes, need, "irm_solve"));
+  WsBind bind(ws, ws_bytes, prob->op, nullptr);
   hipStream_t st = as_stream(stream);
   if (dt == NYS_F64)
     return irm_impl<double>(*prob, o, static_cast<const double*>(omega), ell,
                             static_cast<const double*>(x0), static_cast<double*>(x), cg_iters,
-                            outer_done, info, st);
+                            outer_done, info, &bind.s, st);
   return irm_impl<float>(*prob, o, static_cast<const float*>(omega), ell,
                          static_cast<const float*>(x0), static_cast<float*>(x), cg_iters,
-                         outer_done, info, st);
+                         outer_done, info, &bind.s, st);
 }

@@ -705,9 +705,13 @@ static nys_status launch_wavelet(nys_op_s* op, const SI* in, SO* out, int64_t nc
   if (d.wavelet != NYS_WAVELET_DB4)
     return launch_haar<kAnalysis, SI, SO, C>(d.wavelet_levels, in, out, d.n1, d.n2, ncols, st);
   const size_t n = static_cast<size_t>(d.n1) * d.n2 * ncols;
-  NYS_TRY(op->tmp2.ensure(sizeof(C) * 2 * n));
-  return launch_db4<kAnalysis, SI, SO, C>(op, d.wavelet_levels, in, out, op->tmp2.as<C>(),
-                                          op->tmp2.as<C>() + n, d.n1, d.n2, ncols, st);
+  Scratch::Mark mark(op->scr);
+  C* scratch = nullptr;
+  C* work = nullptr;
+  NYS_TAKE(op->scr, C, scratch, n);
+  if (!std::is_same<SO, C>::value) NYS_TAKE(op->scr, C, work, n);
+  return launch_db4<kAnalysis, SI, SO, C>(op, d.wavelet_levels, in, out, scratch, work, d.n1,
+                                          d.n2, ncols, st);
 }
 
 // Filters of the Daubechies-4 wavelet by spectral factorisation (host, FP64):
@@ -762,8 +766,9 @@ template <class SI, class SO, class C>
 static nys_status launch_joseph_fwd(const nys_op_s* op, const SI* x, SO* p, int64_t ncols,
                                     hipStream_t st) {
   const int n = op->d.n1, V = op->d.n_views, B = op->d.n_bins;
-  NYS_TRY(op->xT.ensure(sizeof(SI) * static_cast<size_t>(n) * n * ncols));
-  SI* xT = op->xT.as<SI>();
+  Scratch::Mark mark(op->scr);
+  SI* xT = nullptr;
+  NYS_TAKE(op->scr, SI, xT, static_cast<size_t>(n) * n * ncols);
   hipLaunchKernelGGL((transpose_kernel<SI>), dim3(cdiv(n, 32), cdiv(n, 32), static_cast<unsigned>(ncols)),
                      dim3(256), 0, st, x, xT, n);
   NYS_TRY(launch_check("transpose_kernel"));
@@ -1042,8 +1047,7 @@ static nys_status launch_fan_adj(nys_op_s* op, const SI* p, SO* x, int64_t ncols
   if constexpr (std::is_same<SO, C>::value) {
     acc = x;
   } else {
-    NYS_TRY(op->tmp2.ensure(sizeof(C) * n));
-    acc = op->tmp2.as<C>();
+    NYS_TAKE(op->scr, C, acc, n);
   }
   NYS_TRY(fill_zero<C>(acc, n, st));
   dim3 grid(cdiv(d.n_bins, 256), d.n_views, static_cast<unsigned>(ncols));
@@ -1108,9 +1112,10 @@ template <class T>
 nys_status op_fwd(nys_op op, const T* x, T* y, int64_t ncols, hipStream_t st) {
   const auto& d = op->d;
   const T* src = x;
+  Scratch::Mark mark(op->scr);
   if (d.wavelet_levels > 0) {
-    NYS_TRY(op->tmp0.ensure(sizeof(T) * op->N * ncols));
-    T* t = op->tmp0.as<T>();
+    T* t = nullptr;
+    if (d.kind != NYS_OP_IDENTITY) NYS_TAKE(op->scr, T, t, static_cast<size_t>(op->N) * ncols);
     NYS_TRY((launch_wavelet<false, T, T, T>(op, x, d.kind == NYS_OP_IDENTITY ? y : t, ncols, st)));
     if (d.kind == NYS_OP_IDENTITY) return NYS_OK;
     src = t;
@@ -1129,8 +1134,9 @@ nys_status op_adj(nys_op op, const T* y, T* x, int64_t ncols, hipStream_t st) {
     return copy_cols(y, x, static_cast<size_t>(op->N) * ncols, st);
   }
   if (d.wavelet_levels > 0) {
-    NYS_TRY(op->tmp0.ensure(sizeof(T) * op->N * ncols));
-    T* t = op->tmp0.as<T>();
+    Scratch::Mark mark(op->scr);
+    T* t = nullptr;
+    NYS_TAKE(op->scr, T, t, static_cast<size_t>(op->N) * ncols);
     NYS_TRY((apply_At_plain<T, T, T>(op, y, t, ncols, st)));
     return launch_wavelet<true, T, T, T>(op, t, x, ncols, st);
   }
@@ -1150,21 +1156,22 @@ static nys_status sketch_chain(nys_op op, const S* omega, S* Y, int64_t ell, hip
   const auto& d = op->d;
   const int64_t N = op->N, M = op->M;
   const bool wav = d.wavelet_levels > 0;
+  Scratch::Mark mark(op->scr);
   if (d.kind == NYS_OP_IDENTITY) {
     // Phi = W W^T = I
-    NYS_TRY(op->tmp0.ensure(sizeof(C) * N * ell));
-    C* t = op->tmp0.as<C>();
     if (wav) {
+      C* t = nullptr;
+      NYS_TAKE(op->scr, C, t, static_cast<size_t>(N) * ell);
       NYS_TRY((launch_wavelet<false, S, C, C>(op, omega, t, ell, st)));
       return launch_wavelet<true, C, S, C>(op, t, Y, ell, st);
     }
     NYS_CHECK_HIP(hipMemcpyAsync(Y, omega, sizeof(S) * N * ell, hipMemcpyDeviceToDevice, st));
     return NYS_OK;
   }
-  NYS_TRY(op->tmp0.ensure(sizeof(C) * (wav ? N : 0) * ell + 64));
-  NYS_TRY(op->tmp1.ensure(sizeof(C) * std::max(M, wav ? N : 0) * ell));
-  C* img = op->tmp0.as<C>();
-  C* meas = op->tmp1.as<C>();
+  C* img = nullptr;
+  C* meas = nullptr;
+  if (wav) NYS_TAKE(op->scr, C, img, static_cast<size_t>(N) * ell);
+  NYS_TAKE(op->scr, C, meas, static_cast<size_t>(std::max(M, wav ? N : 0)) * ell);
   if (wav) {
     NYS_TRY((launch_wavelet<false, S, C, C>(op, omega, img, ell, st)));
     NYS_TRY((apply_A_plain<C, C, C>(op, img, meas, ell, st)));
@@ -1372,10 +1379,6 @@ extern "C" void nys_op_destroy(nys_op op) {
   if (!op) return;
   op->psf_dev.release();
   op->trig.release();
-  op->xT.release();
-  op->tmp0.release();
-  op->tmp1.release();
-  op->tmp2.release();
   op->rays.release();
   delete op;
 }
@@ -1387,38 +1390,90 @@ extern "C" nys_status nys_op_shape(nys_op op, int64_t* n_unknowns, int64_t* n_me
   return NYS_OK;
 }
 
+namespace nys {
+// Workspace of op_fwd / op_adj on ncols columns of es-byte values: the
+// larger of the two directions (the synthesis / analysis intermediate of a
+// wavelet composition, then the Daubechies-4 pass scratch or the transposed
+// images of the parallel-beam forward).
+size_t op_ws_bytes(nys_op op, size_t es, int64_t ncols) {
+  const auto& d = op->d;
+  const size_t img = ws_round(es * static_cast<size_t>(op->N) * ncols);
+  const bool wav = d.wavelet_levels > 0;
+  size_t inner = 0;
+  if (wav && d.wavelet == NYS_WAVELET_DB4) inner = img;
+  if (d.kind == NYS_OP_PARALLEL_BEAM) inner = img;
+  return (wav && d.kind != NYS_OP_IDENTITY ? img : 0) + inner;
+}
+
+// Workspace of the sketch on ell columns stored in dt: the image and
+// measurement stacks of the chain (compute type), then the pass scratch.
+size_t sketch_ws_bytes(nys_op op, nys_dtype dt, int64_t ell) {
+  const auto& d = op->d;
+  const size_t cs = dt == NYS_F64 ? 8 : 4, ss = dtype_size(dt);
+  const size_t nimg = static_cast<size_t>(op->N) * ell;
+  const bool wav = d.wavelet_levels > 0;
+  const bool db4 = wav && d.wavelet == NYS_WAVELET_DB4;
+  const size_t db4_b = db4 ? ws_round(cs * nimg) * (ss == cs ? 1 : 2) : 0;
+  if (d.kind == NYS_OP_IDENTITY) return wav ? ws_round(cs * nimg) + db4_b : 0;
+  size_t inner = db4_b;
+  if (d.kind == NYS_OP_PARALLEL_BEAM) inner = std::max(inner, ws_round(std::max(ss, cs) * nimg));
+  if (d.kind == NYS_OP_FAN_BEAM && ss != cs) inner = std::max(inner, ws_round(cs * nimg));
+  return (wav ? ws_round(cs * nimg) : 0) +
+         ws_round(cs * static_cast<size_t>(std::max(op->M, wav ? op->N : 0)) * ell) + inner;
+}
+}  // namespace nys
+
+extern "C" nys_status nys_op_workspace_size(nys_op op, nys_dtype dt, int64_t ncols,
+                                            size_t* bytes) {
+  NYS_REQUIRE(op && bytes && ncols > 0, "nys_op_workspace_size: bad argument");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "nys_op_workspace_size: dtype must be F64 or F32");
+  *bytes = op_ws_bytes(op, dtype_size(dt), ncols);
+  return NYS_OK;
+}
+
+extern "C" nys_status nys_sketch_workspace_size(nys_op op, nys_dtype dt, int64_t ell,
+                                                size_t* bytes) {
+  NYS_REQUIRE(op && bytes && ell > 0, "nys_sketch_workspace_size: bad argument");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32 || dt == NYS_BF16, "nys_sketch_workspace_size: bad dtype");
+  *bytes = sketch_ws_bytes(op, dt, ell);
+  return NYS_OK;
+}
+
 extern "C" nys_status op_forward(nys_op op, nys_dtype dt, const void* x, void* y, int64_t ncols,
-                                 void* stream) {
+                                 void* ws, size_t ws_bytes, void* stream) {
   NYS_REQUIRE(op && x && y && ncols > 0, "op_forward: bad argument");
   NYS_REQUIRE(ncols <= 65535, "op_forward: ncols > 65535");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "op_forward: dtype must be F64 or F32");
+  NYS_TRY(check_workspace(ws, ws_bytes, op_ws_bytes(op, dtype_size(dt), ncols), "op_forward"));
+  WsBind bind(ws, ws_bytes, op, nullptr);
   if (dt == NYS_F64)
     return op_fwd<double>(op, static_cast<const double*>(x), static_cast<double*>(y), ncols,
                           as_stream(stream));
-  if (dt == NYS_F32)
-    return op_fwd<float>(op, static_cast<const float*>(x), static_cast<float*>(y), ncols,
-                         as_stream(stream));
-  set_error("op_forward: dtype must be F64 or F32");
-  return NYS_EINVAL;
+  return op_fwd<float>(op, static_cast<const float*>(x), static_cast<float*>(y), ncols,
+                       as_stream(stream));
 }
 
 extern "C" nys_status op_adjoint(nys_op op, nys_dtype dt, const void* y, void* x, int64_t ncols,
-                                 void* stream) {
+                                 void* ws, size_t ws_bytes, void* stream) {
   NYS_REQUIRE(op && x && y && ncols > 0, "op_adjoint: bad argument");
   NYS_REQUIRE(ncols <= 65535, "op_adjoint: ncols > 65535");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32, "op_adjoint: dtype must be F64 or F32");
+  NYS_TRY(check_workspace(ws, ws_bytes, op_ws_bytes(op, dtype_size(dt), ncols), "op_adjoint"));
+  WsBind bind(ws, ws_bytes, op, nullptr);
   if (dt == NYS_F64)
     return op_adj<double>(op, static_cast<const double*>(y), static_cast<double*>(x), ncols,
                           as_stream(stream));
-  if (dt == NYS_F32)
-    return op_adj<float>(op, static_cast<const float*>(y), static_cast<float*>(x), ncols,
-                         as_stream(stream));
-  set_error("op_adjoint: dtype must be F64 or F32");
-  return NYS_EINVAL;
+  return op_adj<float>(op, static_cast<const float*>(y), static_cast<float*>(x), ncols,
+                       as_stream(stream));
 }
 
 extern "C" nys_status nys_sketch(nys_op op, nys_dtype dt, const void* omega, void* Y, int64_t ell,
-                                 void* stream) {
+                                 void* ws, size_t ws_bytes, void* stream) {
   NYS_REQUIRE(op && omega && Y && ell > 0, "nys_sketch: bad argument");
   NYS_REQUIRE(ell <= 65535, "nys_sketch: ell > 65535");
   NYS_REQUIRE(omega != Y, "nys_sketch: omega and Y must not alias");
+  NYS_REQUIRE(dt == NYS_F64 || dt == NYS_F32 || dt == NYS_BF16, "nys_sketch: bad dtype");
+  NYS_TRY(check_workspace(ws, ws_bytes, sketch_ws_bytes(op, dt, ell), "nys_sketch"));
+  WsBind bind(ws, ws_bytes, op, nullptr);
   return sketch_dispatch(op, dt, omega, Y, ell, as_stream(stream));
 }

@@ -399,8 +399,10 @@ nys_status pc_partials_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, const
   int nblk;
   int64_t chunk;
   red_geometry(len, nblk, chunk);
-  NYS_TRY(pc->work.ensure(sizeof(double) * static_cast<size_t>(ncols) * nblk * Lp));
-  double* part = pc->work.as<double>();
+  // from the bound workspace, left in place for the caller's tail (its scope
+  // releases it)
+  double* part = nullptr;
+  NYS_TAKE(pc->scr, double, part, static_cast<size_t>(ncols) * nblk * Lp);
   out->part = part;
   out->nblk = nblk;
   out->ncols = static_cast<int>(ncols);
@@ -427,6 +429,7 @@ nys_status pc_tail(nys_pc pc, bool inverse, const CoefPartials& cp, double* cd, 
 template <class T>
 nys_status pc_coeffs_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, bool inverse, const T* v,
                         int64_t ncols, double* cd, hipStream_t st) {
+  Scratch::Mark mark(pc->scr);   // the partials live until the tail has read them
   CoefPartials cp;
   NYS_TRY(pc_partials_on<T>(pc, B, ldb, len, v, ncols, &cp, st));
   return pc_tail(pc, inverse, cp, cd, st);
@@ -438,12 +441,20 @@ nys_status pc_coeffs(nys_pc pc, bool inverse, const T* v, int64_t ncols, double*
   return pc_coeffs_on<T>(pc, pc->U.as<T>(), pc->ldu, pc->N, inverse, v, ncols, cd, st);
 }
 
+// Workspace of pc_apply on ncols columns: the coefficients and the block
+// partials (at most 256 blocks a column).
+size_t pc_ws_bytes(nys_pc pc, int64_t ncols) {
+  return ws_round(sizeof(double) * static_cast<size_t>(ncols) * pc->ell) +
+         ws_round(sizeof(double) * static_cast<size_t>(ncols) * 256 * pc->ell_pad);
+}
+
 template <class T>
 nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, hipStream_t st) {
   const int64_t N = pc->N;
   const int L = static_cast<int>(pc->ell);
-  NYS_TRY(pc->work2.ensure(sizeof(double) * static_cast<size_t>(ncols) * L));
-  double* cd = pc->work2.as<double>();
+  Scratch::Mark mark(pc->scr);
+  double* cd = nullptr;
+  NYS_TAKE(pc->scr, double, cd, static_cast<size_t>(ncols) * L);
   NYS_TRY(pc_coeffs<T>(pc, inverse, v, ncols, cd, st));
   hipLaunchKernelGGL((u_update_kernel<T>), dim3(cdiv(N, 256), ncols), dim3(256), 0, st,
                      pc->U.as<T>(), pc->ldu, v, cd, N, L, out);
@@ -454,8 +465,9 @@ nys_status pc_apply(nys_pc pc, bool inverse, const T* v, T* out, int64_t ncols, 
 // s = u - alpha (g + U cd).
 template <class T>
 nys_status pc_step(nys_pc pc, const T* u, const T* g, double alpha, T* s, hipStream_t st) {
-  NYS_TRY(pc->work2.ensure(sizeof(double) * pc->ell));
-  double* cd = pc->work2.as<double>();
+  Scratch::Mark mark(pc->scr);
+  double* cd = nullptr;
+  NYS_TAKE(pc->scr, double, cd, pc->ell);
   NYS_TRY(pc_coeffs<T>(pc, true, g, 1, cd, st));
   return pc_x_from_pinv<T>(pc, u, g, cd, alpha, s, st);
 }
@@ -503,7 +515,8 @@ struct SsnState {
   static constexpr int kS = 4 * PcMeta::kMaxEll;         // scalars
   static constexpr int kNF = kS + 0, kT = kS + 1, kDone = kS + 2, kHalv = kS + 3,
                        kHave = kS + 4, kNeedGram = kS + 5, kTrials = kS + 6, kSteps = kS + 7,
-                       kLuOk = kS + 8;   // FP32: inverse of the last Newton Jacobian stored
+                       kLuOk = kS + 8,   // FP32: inverse of the last Newton Jacobian stored
+                       kBad = kS + 9;    // a trial point gave a non-finite ||F||
   static constexpr int kTotal = kS + 16;
 };
 
@@ -631,7 +644,7 @@ __global__ __launch_bounds__(512) void ssn_eval_step_kernel(
       if (threadIdx.x == 0) {
         state[SsnState::kNF] = 0; state[SsnState::kT] = 1; state[SsnState::kDone] = 0;
         state[SsnState::kHalv] = 0; state[SsnState::kHave] = 0; state[SsnState::kNeedGram] = 0;
-        state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0;
+        state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0; state[SsnState::kBad] = 0;
         if (!keep_lu) state[SsnState::kLuOk] = 0;
       }
     }
@@ -672,14 +685,16 @@ __global__ __launch_bounds__(512) void ssn_eval_step_kernel(
 }
 
 // The host learns the outcome from one 64-bit word in pinned host memory,
-// hflag = 8 seq + 4 done + 2 need_gram + lu_ok, written by a single
-// system-scope store (no fence: the host reads nothing else the kernel
-// wrote), also when an earlier decision had finished.
+// hflag = 16 seq + 8 non-finite + 4 done + 2 need_gram + lu_ok, written by a
+// single system-scope store (no fence: the host reads nothing else the
+// kernel wrote), also when an earlier decision had finished.
 __device__ __forceinline__ void ssn_publish(unsigned long long* hflag, unsigned long long seq,
-                                            double done, double need_gram, double lu_ok) {
+                                            double done, double need_gram, double lu_ok,
+                                            double bad) {
   if (hflag == nullptr || threadIdx.x != 0) return;
-  const unsigned long long w = (seq << 3) | (done != 0.0 ? 4ull : 0ull) |
-                               (need_gram != 0.0 ? 2ull : 0ull) | (lu_ok != 0.0 ? 1ull : 0ull);
+  const unsigned long long w = (seq << 4) | (bad != 0.0 ? 8ull : 0ull) |
+                               (done != 0.0 ? 4ull : 0ull) | (need_gram != 0.0 ? 2ull : 0ull) |
+                               (lu_ok != 0.0 ? 1ull : 0ull);
   __hip_atomic_store(hflag, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
@@ -734,8 +749,9 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
     gk = state[SsnState::kGamma + tid];
     dk = state[SsnState::kDelta + tid];
   }
-  double have = 0, nF = 0, t = 0, halv = 0, trials = 0, luok = 0, steps = 0;
+  double have = 0, nF = 0, t = 0, halv = 0, trials = 0, luok = 0, steps = 0, bad0 = 0;
   if (tid == 0) {
+    bad0 = state[SsnState::kBad];
     have = state[SsnState::kHave];
     nF = state[SsnState::kNF];
     t = state[SsnState::kT];
@@ -752,7 +768,7 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
     }
   }
   if (done0 != 0.0) {
-    ssn_publish(hflag, seq, 1.0, 0.0, luok);
+    ssn_publish(hflag, seq, 1.0, 0.0, luok, bad0);
     return;
   }
   if (sl < S) red[sl * L + k] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
@@ -781,13 +797,20 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
   if (tid == 0) {
     const double nFt = sqrt(wsum[0][0] + wsum[1][0]), gn = sqrt(wsum[0][1] + wsum[1][1]);
     state[SsnState::kTrials] = trials + 1.0;
-    const bool accept = have == 0.0 || nFt <= (1.0 - 1e-4 * t) * nF || halv >= max_halvings ||
-                        !isfinite(nFt);
+    // a non-finite ||F|| ends the iteration without accepting the point (the
+    // warm start keeps its value) and is reported to the host
+    const bool bad = !isfinite(nFt) || !isfinite(gn);
+    const bool accept = !bad && (have == 0.0 || nFt <= (1.0 - 1e-4 * t) * nF ||
+                                 halv >= max_halvings);
     double done = 0.0, need = 0.0;
-    if (accept) {
+    if (bad) {
+      done = 1.0;
+      state[SsnState::kDone] = 1.0;
+      state[SsnState::kBad] = 1.0;
+    } else if (accept) {
       state[SsnState::kHave] = 1.0;
       state[SsnState::kNF] = nFt;
-      if (nFt <= tol * (1.0 + gn) || !isfinite(nFt)) done = 1.0;
+      if (nFt <= tol * (1.0 + gn)) done = 1.0;
       else need = 1.0;
       state[SsnState::kDone] = done;
     } else {
@@ -804,7 +827,7 @@ __device__ __forceinline__ void ssn_decide_body(const double* __restrict__ part,
       state[SsnState::kHalv] = 0.0;
       state[SsnState::kSteps] = steps + 1.0;
     }
-    ssn_publish(hflag, seq, done, need, luok);
+    ssn_publish(hflag, seq, done, need, luok, bad ? 1.0 : 0.0);
   }
   __syncthreads();
   if (tid < L) {
@@ -1511,7 +1534,7 @@ __global__ void ssn_init_kernel(double* __restrict__ state, const double* __rest
   if (threadIdx.x == 0) {
     state[SsnState::kNF] = 0; state[SsnState::kT] = 1; state[SsnState::kDone] = 0;
     state[SsnState::kHalv] = 0; state[SsnState::kHave] = 0; state[SsnState::kNeedGram] = 0;
-    state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0;
+    state[SsnState::kTrials] = 0; state[SsnState::kSteps] = 0; state[SsnState::kBad] = 0;
     if (!keep_lu) state[SsnState::kLuOk] = 0;
   }
 }
@@ -1637,16 +1660,16 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
 // outcome (sequence number pc->flag_seq).  Spins on the pinned word for up to
 // 2 s, then falls back to a stream synchronisation.
 static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool& need_gram,
-                                    bool& lu_ok) {
+                                    bool& lu_ok, bool& bad) {
   volatile unsigned long long* f = pc->hflag;
   const unsigned long long want = pc->flag_seq;
   const auto t0 = std::chrono::steady_clock::now();
   unsigned long long w = *f;
-  while ((w >> 3) != want) {
+  while ((w >> 4) != want) {
     if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
       NYS_CHECK_HIP(hipStreamSynchronize(st));
       w = *f;
-      if ((w >> 3) != want) {
+      if ((w >> 4) != want) {
         set_error("semismooth Newton decision %llu not published", want);
         return NYS_EHIP;
       }
@@ -1654,11 +1677,46 @@ static nys_status ssn_wait_decision(nys_pc pc, hipStream_t st, bool& done, bool&
     }
     w = *f;
   }
+  bad = (w & 8) != 0;
   done = (w & 4) != 0;
   need_gram = (w & 2) != 0;
   lu_ok = (w & 1) != 0;
   return NYS_OK;
 }
+
+// Geometry and buffer layout of the semismooth Newton iteration for N pixels,
+// L columns and es-byte values: the evaluation blocks, the fused evaluation +
+// Gram blocks, the state, block partials, Gram partials, the FP64 Jacobian,
+// the active-set mask and the stored FP32 Jacobian inverse.  The buffer is
+// allocated with the preconditioner (ssn_ws_bytes).
+struct SsnLayout {
+  int nblk, ngb, nrg;
+  int64_t chunk, gchunk;
+  size_t gpart_d, need, mask_b, lu_b;
+  SsnLayout(int64_t N, int L, size_t es) {
+    red_geometry(N, nblk, chunk);
+    // fused pass: one block per CU at most, at least two 64-pixel stages per
+    // wave of a block (1024 pixels for 8 waves), chunks a multiple of 64
+    const int nrg0 = (L + 31) / 32;
+    const int64_t per_blk = 64 * 2 * (nrg0 <= 2 ? 8 : 4);
+    const int64_t gblk = std::min<int64_t>(256, std::max<int64_t>(1, (N + per_blk - 1) / per_blk));
+    gchunk = (N + gblk - 1) / gblk;
+    gchunk = (gchunk + 63) / 64 * 64;
+    ngb = static_cast<int>((N + gchunk - 1) / gchunk);
+    nrg = (L + 31) / 32;
+    const size_t LL = static_cast<size_t>(L) * L;
+    const size_t ntri = static_cast<size_t>(nrg) * (nrg + 1) / 2;
+    if (es == 4)   // block partials (FP32), then part2 (kGramSets sets)
+      gpart_d = (static_cast<size_t>(ngb) * ntri * 1024 + 1) / 2 + kGramSets * ntri * 1024 + 1;
+    else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
+    need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
+    mask_b = static_cast<size_t>((N + 255) / 256 * 256);
+    lu_b = sizeof(float) * kLuPitch * kLuPitch;
+  }
+  size_t bytes() const { return sizeof(double) * need + mask_b + lu_b + 256; }
+};
+
+size_t ssn_ws_bytes(int64_t N, int L, size_t es) { return SsnLayout(N, L, es).bytes(); }
 
 template <class T>
 nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
@@ -1670,43 +1728,18 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   pc->ssn_hi = box ? box->hi : 0.0;
   const int64_t N = pc->N;
   const int L = static_cast<int>(pc->ell);
-  int nblk;
-  int64_t chunk;
-  red_geometry(N, nblk, chunk);
-  // fused pass: one block per CU at most, at least two 64-pixel stages per
-  // wave of a block (1024 pixels for 8 waves), chunks a multiple of 64
-  const int nrg0 = (L + 31) / 32;
-  const int64_t per_blk = 64 * 2 * (nrg0 <= 2 ? 8 : 4);
-  const int64_t gblk = std::min<int64_t>(256, std::max<int64_t>(1, (N + per_blk - 1) / per_blk));
-  int64_t gchunk = (N + gblk - 1) / gblk;
-  gchunk = (gchunk + 63) / 64 * 64;
-  const int ngb = static_cast<int>((N + gchunk - 1) / gchunk);
-  const int nrg = (L + 31) / 32;
+  const SsnLayout ly(N, L, sizeof(T));
+  const int nblk = ly.nblk, ngb = ly.ngb, nrg = ly.nrg;
+  const int64_t chunk = ly.chunk, gchunk = ly.gchunk;
   const size_t LL = static_cast<size_t>(L) * L;
-  size_t gpart_d;
-  const size_t ntri = static_cast<size_t>(nrg) * (nrg + 1) / 2;
-  if (sizeof(T) == 4)   // block partials (FP32), then part2 (kGramSets sets)
-    gpart_d = (static_cast<size_t>(ngb) * ntri * 1024 + 1) / 2 + kGramSets * ntri * 1024 + 1;
-  else gpart_d = static_cast<size_t>(cdiv(N, 4096)) * LL;
-  const size_t need = SsnState::kTotal + static_cast<size_t>(std::max(nblk, ngb)) * L + gpart_d + LL;
-  const size_t mask_b = static_cast<size_t>((N + 255) / 256 * 256);
-  const size_t lu_b = sizeof(float) * kLuPitch * kLuPitch;
-  const void* ws_before = pc->ssn_ws.p;
-  NYS_TRY(pc->ssn_ws.ensure(sizeof(double) * need + mask_b + lu_b + 256));
-  if (pc->ssn_ws.p != ws_before) pc->ssn_lu_valid = false;   // a new buffer holds no factors
+  NYS_REQUIRE(pc->ssn_ws.bytes >= ly.bytes(), "ssn_prox: semismooth Newton buffer too small");
+  NYS_REQUIRE(pc->hflag, "ssn_prox: no decision word");
   double* state = pc->ssn_ws.as<double>();
   double* part = state + SsnState::kTotal;
   double* gpart = part + static_cast<size_t>(std::max(nblk, ngb)) * L;
-  double* Mj = gpart + gpart_d;
+  double* Mj = gpart + ly.gpart_d;
   uint8_t* mask = reinterpret_cast<uint8_t*>(Mj + LL);
-  float* lu = reinterpret_cast<float*>(mask + mask_b);
-  if (!pc->hflag) {
-    void* h = nullptr;
-    NYS_CHECK_HIP(hipHostMalloc(&h, sizeof(unsigned long long), hipHostMallocCoherent));
-    pc->hflag = static_cast<unsigned long long*>(h);
-    *pc->hflag = 0;
-    pc->flag_seq = 0;
-  }
+  float* lu = reinterpret_cast<float*>(mask + ly.mask_b);
   const T lam = static_cast<T>(lam_bar);
   const double tol = reg.newton_tol > 0 ? reg.newton_tol : (sizeof(T) == 8 ? 1e-12 : 1e-6);
   const int max_trials = reg.max_newton > 0 ? reg.max_newton : 60;
@@ -1729,7 +1762,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   }
   pc->ssn_gout = gamma_state;   // the deciding kernel stores the root
   int trial = 0;
-  bool done = false, need_gram = false, lu_ok = false;
+  bool done = false, need_gram = false, lu_ok = false, bad = false;
   // FP32: without stored factors the first trial point (nearly always
   // followed by a Newton step) runs the fused evaluation + Gram pass; with
   // them, and at every later trial point, the evaluation runs alone.  A new
@@ -1798,7 +1831,7 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     }
     // the decision of this trial, read from pinned host memory while the
     // device goes on; the next trial is enqueued only if it is needed
-    NYS_TRY(ssn_wait_decision(pc, st, done, need_gram, lu_ok));
+    NYS_TRY(ssn_wait_decision(pc, st, done, need_gram, lu_ok, bad));
     if (fp32_lu) pc->ssn_lu_hint = lu_ok;
     if (done) break;
     if constexpr (sizeof(T) == 4) {
@@ -1817,8 +1850,8 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
       }
     }
   }
-  if (fp32_lu) pc->ssn_lu_valid = true;
-  if (trials_out) *trials_out = trial + 1;
+  if (fp32_lu && !bad) pc->ssn_lu_valid = true;
+  if (trials_out) *trials_out = done ? trial + 1 : trial;
   // the FP32 pass has written soft(s - U g) of its trial point g to x: when
   // the iteration stopped there (accepted and converged), x is the prox
   if (!(sizeof(T) == 4 && done && xf != nullptr)) {
@@ -1831,6 +1864,14 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   if (gamma_state && !done) {   // the trials ran out: the last accepted point
     hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
     NYS_TRY(launch_check("ssn_store_gamma_kernel"));
+  }
+  if (bad) {
+    set_error("semismooth Newton: non-finite ||F|| (NaN or infinity in the prox centre or U)");
+    return NYS_ENOTFINITE;
+  }
+  if (!done) {
+    set_error("semismooth Newton: no convergence within %d trial points", max_trials);
+    return NYS_ENOCONV;
   }
   return NYS_OK;
 }

@@ -96,6 +96,7 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
   if (reg.box && pc) NYS_TRY(fill_zero<double>(gbox, PcMeta::kMaxEll, st));
   const int L = pc ? static_cast<int>(pc->ell) : 0;
   double tau = 1.0;
+  nys_status conv = NYS_OK;   // a box projection that ran out of Newton trials
   for (int it = 0; it <= reg.n_inner; ++it) {
     const bool last = it == reg.n_inner;
     const T* src = last ? Q : R;                 // the output uses Q, not R
@@ -111,7 +112,11 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
       NYS_TRY(pc_x_from_pinv<T>(pc, s, tbuf, cd, lam_bar, x, st));
     }
     // x(Q) = prox^P_{delta_C}(s - lam_bar P^{-1} L^T Q) for a box C
-    if (reg.box) NYS_TRY(project_box<T>(reg, pc, x, gbox, st));
+    if (reg.box) {
+      const nys_status bs = project_box<T>(reg, pc, x, gbox, st);
+      if (bs == NYS_ENOCONV) conv = bs;
+      else NYS_TRY(bs);
+    }
     if (last) break;
     double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
     double beta = (tau - 1.0) / tau_n;
@@ -120,7 +125,9 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
     NYS_TRY(launch_check("dual_update_kernel"));
     tau = tau_n;
   }
-  return NYS_OK;
+  if (conv != NYS_OK)
+    set_error("prox: a P-weighted box projection ran out of semismooth Newton trial points");
+  return conv;
 }
 
 template <class T>
@@ -152,14 +159,10 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     return ssn_prox<T>(reg, lam_bar, pc, s, x, static_cast<double*>(state), st);
   }
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
-  // work: [cd, gbox: kMaxEll doubles each | R | Q (when no state) | t]; the
-  // caller's buffer of prox_ws_bytes, else a per-thread one
-  static thread_local DevBuf fallback;
+  // work: [cd, gbox: kMaxEll doubles each | R | Q (when no state) | t], the
+  // caller's buffer of prox_ws_bytes
+  NYS_REQUIRE(work, "prox: no work buffer");
   char* base = static_cast<char*>(work);
-  if (!base) {
-    NYS_TRY(fallback.ensure(prox_ws_bytes<T>(reg)));
-    base = static_cast<char*>(fallback.p);
-  }
   double* cd = reinterpret_cast<double*>(base);
   double* gbox = cd + PcMeta::kMaxEll;
   T* R = reinterpret_cast<T*>(gbox + PcMeta::kMaxEll);
@@ -206,16 +209,41 @@ extern "C" nys_status nys_prox_state_bytes(const nys_reg_desc* reg, nys_pc pc, n
   return NYS_OK;
 }
 
+// Workspace of prox_weighted: the dual iteration's buffers and, with a
+// preconditioner, the scratch of its applications.
+template <class T>
+static size_t prox_call_ws_bytes(const nys_reg_desc& reg, nys_pc pc) {
+  return ws_round(prox_ws_bytes<T>(reg)) + (pc ? pc_ws_bytes(pc, 1) : 0);
+}
+
+extern "C" nys_status nys_prox_workspace_size(const nys_reg_desc* reg, nys_pc pc, nys_dtype dt,
+                                              size_t* bytes) {
+  NYS_TRY(check_reg(reg, pc, dt));
+  NYS_REQUIRE(bytes, "null bytes");
+  *bytes = dt == NYS_F64 ? prox_call_ws_bytes<double>(*reg, pc) : prox_call_ws_bytes<float>(*reg, pc);
+  return NYS_OK;
+}
+
+template <class T>
+static nys_status prox_call(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
+                            void* state, void* ws, size_t ws_bytes, hipStream_t st) {
+  NYS_TRY(check_workspace(ws, ws_bytes, prox_call_ws_bytes<T>(reg, pc), "prox_weighted"));
+  WsBind bind(ws, ws_bytes, nullptr, pc);
+  char* work = nullptr;
+  NYS_TAKE(&bind.s, char, work, prox_ws_bytes<T>(reg));
+  return prox_run<T>(reg, lam_bar, pc, s, x, state, st, work);
+}
+
 extern "C" nys_status prox_weighted(const nys_reg_desc* reg, double lambda_bar, nys_pc pc,
-                                    nys_dtype dt, const void* s, void* x, void* state,
-                                    void* stream) {
+                                    nys_dtype dt, const void* s, void* x, void* state, void* ws,
+                                    size_t ws_bytes, void* stream) {
   NYS_TRY(check_reg(reg, pc, dt));
   NYS_REQUIRE(s && x && s != x, "prox_weighted: bad s / x");
   NYS_REQUIRE(lambda_bar > 0 && std::isfinite(lambda_bar), "prox_weighted: lambda_bar must be > 0");
   hipStream_t st = as_stream(stream);
   if (dt == NYS_F64)
-    return prox_run<double>(*reg, lambda_bar, pc, static_cast<const double*>(s), static_cast<double*>(x),
-                            state, st);
-  return prox_run<float>(*reg, lambda_bar, pc, static_cast<const float*>(s), static_cast<float*>(x),
-                         state, st);
+    return prox_call<double>(*reg, lambda_bar, pc, static_cast<const double*>(s),
+                             static_cast<double*>(x), state, ws, ws_bytes, st);
+  return prox_call<float>(*reg, lambda_bar, pc, static_cast<const float*>(s), static_cast<float*>(x),
+                          state, ws, ws_bytes, st);
 }

@@ -44,6 +44,22 @@ __global__ void momentum_kernel(const T* __restrict__ xn, T* __restrict__ x, T* 
   x[n] = a;
 }
 
+// status = NYS_ENOTFINITE when any of v[0:n] is NaN or infinite (the word
+// was cleared at the start of the call)
+template <class T>
+__global__ __launch_bounds__(256) void finite_check_kernel(const T* __restrict__ v, int64_t n,
+                                                           int32_t* __restrict__ status) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    bad |= !isfinite(v[i]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0) status[0] = NYS_ENOTFINITE;
+}
+
+__global__ void status_clear_kernel(int32_t* status) {
+  if (threadIdx.x < 2) status[threadIdx.x] = 0;
+}
+
 // ---------------------------------------------------------------- reductions
 template <class T>
 __global__ __launch_bounds__(256) void term_sum_kernel(const T* __restrict__ a, const T* __restrict__ b,
@@ -256,7 +272,9 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
   }
   const bool fwd_fused = op_fwd_fused_ok<T>(op);
   double t_prev = 1.0;
+  nys_status conv = NYS_OK;   // a prox that ran out of Newton trials (the solve goes on)
   for (int k = 0; k < max_iter; ++k) {
+    Scratch::Mark mark(op->scr);   // this iteration's coefficient partials
     // s = u - alpha P^{-1} grad f(u), grad f(u) = A^T psi(A u - y)
     if (fwd_fused) {
       NYS_TRY(op_fwd_psi<T>(op, w.u, static_cast<const T*>(p.y), p.loss, p.delta, w.meas, 1, st));
@@ -276,8 +294,11 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
       // the step s = u - alpha (grad + U cd) is formed inside the prox (by
       // its first evaluation pass over U where possible)
       const SsnStep sp{w.u, w.g, alpha, cp, w.part};
-      NYS_TRY(ssn_prox<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? static_cast<double*>(w.state) : nullptr,
-                          st, nullptr, &sp));
+      const nys_status ps = ssn_prox<T>(p.reg, lam_bar, pc, w.s, w.xn,
+                                        warm_start ? static_cast<double*>(w.state) : nullptr, st,
+                                        nullptr, &sp);
+      if (ps == NYS_ENOCONV) conv = ps;
+      else if (ps != NYS_OK) return ps;
     } else if (pc) {
       NYS_TRY(pc_tail(pc, true, cp, w.part, st));
       NYS_TRY(pc_x_from_pinv<T>(pc, w.u, w.g, w.part, alpha, w.s, st));
@@ -287,8 +308,12 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
       NYS_TRY(launch_check("step_kernel"));
     }
     // x+ = prox^P_{alpha lambda g}(s)
-    if (!(pc && p.reg.kind == NYS_REG_L1))
-      NYS_TRY(prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn, warm_start ? w.state : nullptr, st, w.prox));
+    if (!(pc && p.reg.kind == NYS_REG_L1)) {
+      const nys_status ps = prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn,
+                                        warm_start ? w.state : nullptr, st, w.prox);
+      if (ps == NYS_ENOCONV) conv = ps;
+      else if (ps != NYS_OK) return ps;
+    }
     // momentum
     const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
     const double beta = (t_prev - 1.0) / t;
@@ -298,7 +323,7 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
     t_prev = t;
     if (costs) NYS_TRY(cost_impl<T>(p, x, costs + k, w.meas, w.part, st));
   }
-  return NYS_OK;
+  return conv;
 }
 
 template nys_status power_enqueue<float>(const nys_problem&, nys_pc, const float*, int, void*, hipStream_t);
@@ -306,40 +331,73 @@ template nys_status power_enqueue<double>(const nys_problem&, nys_pc, const doub
 template nys_status wapg_enqueue<float>(const nys_problem&, nys_pc, double, int, int, float*, double*, void*, hipStream_t);
 template nys_status wapg_enqueue<double>(const nys_problem&, nys_pc, double, int, int, double*, double*, void*, hipStream_t);
 
+
+// Workspace of solve: the status word, the iteration's buffers (SolveWs),
+// and the scratch of the operator (on one column, or on ell_pad columns when
+// A U is formed) and of the preconditioner's applications.
 template <class T>
-size_t solve_ws_bytes(const nys_problem& p, nys_pc pc) { return SolveWs<T>::bytes(p, pc); }
-template size_t solve_ws_bytes<float>(const nys_problem&, nys_pc);
-template size_t solve_ws_bytes<double>(const nys_problem&, nys_pc);
+size_t solve_call_ws_bytes(const nys_problem& p, nys_pc pc) {
+  const int64_t cols = SolveWs<T>::use_au(p, pc) ? pc->ell_pad : 1;
+  // the gradient step's coefficient partials are held while the prox takes
+  // its own: two columns' worth of the preconditioner's scratch
+  return 256 + ws_round(SolveWs<T>::bytes(p, pc)) + op_ws_bytes(p.op, sizeof(T), cols) +
+         (pc ? pc_ws_bytes(pc, 2) : 0);
+}
 
 template <class T>
 static nys_status solve_impl(const nys_problem& p, nys_pc pc, const nys_solve_opts& o, T* x,
-                             double* costs, double* info, hipStream_t st) {
-  static thread_local DevBuf ws;
-  NYS_TRY(ws.ensure(SolveWs<T>::bytes(p, pc)));
-  SolveWs<T> w(p, pc, ws.p);
+                             double* costs, double* info, void* ws, size_t ws_bytes,
+                             hipStream_t st) {
+  NYS_TRY(check_workspace(ws, ws_bytes, solve_call_ws_bytes<T>(p, pc), "solve"));
+  WsBind bind(ws, ws_bytes, p.op, pc);
+  int32_t* status = nullptr;
+  char* wsb = nullptr;
+  NYS_TAKE(&bind.s, int32_t, status, 64);
+  NYS_TAKE(&bind.s, char, wsb, SolveWs<T>::bytes(p, pc));
+  SolveWs<T> w(p, pc, wsb);
+  hipLaunchKernelGGL(status_clear_kernel, dim3(1), dim3(64), 0, st, status);
+  NYS_TRY(launch_check("status_clear_kernel"));
   const double curv = p.loss == NYS_LOSS_HUBER ? 1.0 / p.delta : 1.0;
   double alpha = o.alpha;
   double Lest = 0.0;
   if (!(alpha > 0)) {
     NYS_REQUIRE(o.power_v0 && o.power_iters > 0, "solve: power_v0 / power_iters needed when alpha <= 0");
-    NYS_TRY(power_enqueue<T>(p, pc, static_cast<const T*>(o.power_v0), o.power_iters, ws.p, st));
+    NYS_TRY(power_enqueue<T>(p, pc, static_cast<const T*>(o.power_v0), o.power_iters, wsb, st));
     double lam = 0;
     NYS_CHECK_HIP(hipMemcpyAsync(&lam, w.norms, sizeof(double), hipMemcpyDeviceToHost, st));
     NYS_CHECK_HIP(hipStreamSynchronize(st));
     Lest = curv * lam;
     const double safety = o.safety > 0 ? o.safety : 1.01;
-    NYS_REQUIRE(Lest > 0 && std::isfinite(Lest), "solve: power method gave L = %g", Lest);
+    if (!(Lest > 0 && std::isfinite(Lest))) {
+      set_error("solve: the power method gave L = %g (non-finite or non-positive inputs)", Lest);
+      return std::isfinite(Lest) ? NYS_EINVAL : NYS_ENOTFINITE;
+    }
     alpha = 1.0 / (safety * Lest);
   }
-  NYS_TRY(wapg_enqueue<T>(p, pc, alpha, o.max_iter, o.warm_start, x, costs, ws.p, st));
+  const nys_status ws_status =
+      wapg_enqueue<T>(p, pc, alpha, o.max_iter, o.warm_start, x, costs, wsb, st);
+  if (ws_status != NYS_OK && ws_status != NYS_ENOCONV) return ws_status;
+  hipLaunchKernelGGL((finite_check_kernel<T>),
+                     dim3(std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(p.op->N, 256)))),
+                     dim3(256), 0, st, x, p.op->N, status);
+  NYS_TRY(launch_check("finite_check_kernel"));
+  nys_status result = ws_status;
   if (info) {
+    int32_t dev_status = 0;
+    NYS_CHECK_HIP(hipMemcpyAsync(&dev_status, status, sizeof dev_status, hipMemcpyDeviceToHost, st));
     NYS_CHECK_HIP(hipStreamSynchronize(st));
+    if (dev_status != NYS_OK) {
+      set_error("solve: the iterate holds non-finite values");
+      result = static_cast<nys_status>(dev_status);
+    }
     info[0] = alpha;
     info[1] = Lest;
-    info[2] = NYS_OK;
+    info[2] = result;
     info[3] = 0;
   }
-  return NYS_OK;
+  if (result == NYS_ENOCONV)
+    set_error("solve: a semismooth Newton prox ran out of trial points (the iteration went on)");
+  return result;
 }
 
 }  // namespace nys
@@ -358,9 +416,19 @@ static nys_status check_problem(const nys_problem* p, nys_dtype dt) {
   return NYS_OK;
 }
 
+extern "C" nys_status nys_workspace_size(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                                         size_t* bytes) {
+  NYS_TRY(check_problem(prob, dt));
+  NYS_REQUIRE(bytes, "nys_workspace_size: null bytes");
+  if (pc) NYS_REQUIRE(pc->N == prob->op->N, "nys_workspace_size: pc size != number of unknowns");
+  *bytes = dt == NYS_F64 ? solve_call_ws_bytes<double>(*prob, pc)
+                         : solve_call_ws_bytes<float>(*prob, pc);
+  return NYS_OK;
+}
+
 extern "C" nys_status solve(const nys_problem* prob, nys_pc pc, nys_dtype dt,
                             const nys_solve_opts* opts, void* x_out, double* costs, double* info,
-                            void* stream) {
+                            void* ws, size_t ws_bytes, void* stream) {
   NYS_TRY(check_problem(prob, dt));
   NYS_REQUIRE(opts && x_out && opts->max_iter >= 0, "solve: bad options or x_out");
   NYS_REQUIRE(prob->lambda > 0, "solve: lambda must be > 0");
@@ -370,24 +438,36 @@ extern "C" nys_status solve(const nys_problem* prob, nys_pc pc, nys_dtype dt,
   }
   hipStream_t st = as_stream(stream);
   if (dt == NYS_F64)
-    return solve_impl<double>(*prob, pc, *opts, static_cast<double*>(x_out), costs, info, st);
-  return solve_impl<float>(*prob, pc, *opts, static_cast<float*>(x_out), costs, info, st);
+    return solve_impl<double>(*prob, pc, *opts, static_cast<double*>(x_out), costs, info, ws,
+                              ws_bytes, st);
+  return solve_impl<float>(*prob, pc, *opts, static_cast<float*>(x_out), costs, info, ws, ws_bytes,
+                           st);
+}
+
+extern "C" nys_status nys_cost_workspace_size(const nys_problem* prob, nys_dtype dt, size_t* bytes) {
+  NYS_TRY(check_problem(prob, dt));
+  NYS_REQUIRE(bytes, "nys_cost_workspace_size: null bytes");
+  *bytes = ws_round(sizeof(double) * 2 * kRedBlocks) + ws_round(dtype_size(dt) * prob->op->M) +
+           op_ws_bytes(prob->op, dtype_size(dt), 1);
+  return NYS_OK;
 }
 
 extern "C" nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void* x, double* cost,
-                               void* stream) {
+                               void* ws, size_t ws_bytes, void* stream) {
   NYS_TRY(check_problem(prob, dt));
   NYS_REQUIRE(x && cost, "nys_cost: null x / cost");
-  static thread_local DevBuf ws;
-  const int64_t M = prob->op->M;
-  NYS_TRY(ws.ensure(dtype_size(dt) * M + sizeof(double) * 2 * kRedBlocks + 64));
+  size_t need = 0;
+  NYS_TRY(nys_cost_workspace_size(prob, dt, &need));
+  NYS_TRY(check_workspace(ws, ws_bytes, need, "nys_cost"));
+  WsBind bind(ws, ws_bytes, prob->op, nullptr);
   hipStream_t st = as_stream(stream);
-  char* base = static_cast<char*>(ws.p);
-  double* part = reinterpret_cast<double*>(base);
-  void* meas = base + sizeof(double) * 2 * kRedBlocks;
+  double* part = nullptr;
+  char* meas = nullptr;
+  NYS_TAKE(&bind.s, double, part, 2 * kRedBlocks);
+  NYS_TAKE(&bind.s, char, meas, dtype_size(dt) * prob->op->M);
   if (dt == NYS_F64)
-    return cost_impl<double>(*prob, static_cast<const double*>(x), cost, static_cast<double*>(meas),
-                             part, st);
-  return cost_impl<float>(*prob, static_cast<const float*>(x), cost, static_cast<float*>(meas), part,
-                          st);
+    return cost_impl<double>(*prob, static_cast<const double*>(x), cost,
+                             reinterpret_cast<double*>(meas), part, st);
+  return cost_impl<float>(*prob, static_cast<const float*>(x), cost, reinterpret_cast<float*>(meas),
+                          part, st);
 }

@@ -432,11 +432,20 @@ static nys_status unroll_backward(const nys_problem& p, nys_pc pc, const nys_unr
   return NYS_OK;
 }
 
+// Workspace: the checkpoints and iteration buffers (kept from the forward to
+// the backward call), then the scratch of the operator and the
+// preconditioner's applications (one column).
 template <class T>
-static size_t unroll_ws_bytes(int64_t N, int64_t M, int K, int nin, int batch) {
-  return sizeof(T) * (static_cast<size_t>(batch) * Unroll<T>::ckpt_elems(N, K) +
-                      Unroll<T>::scratch_elems(N, M, nin)) +
-         sizeof(double) * (kDotBlocks + 8) + 512;
+static size_t unroll_state_bytes(int64_t N, int64_t M, int K, int nin, int batch) {
+  return ws_round(sizeof(T) * (static_cast<size_t>(batch) * Unroll<T>::ckpt_elems(N, K) +
+                               Unroll<T>::scratch_elems(N, M, nin)) +
+                  sizeof(double) * (kDotBlocks + 8) + 512);
+}
+
+template <class T>
+static size_t unroll_ws_bytes(nys_op op, nys_pc pc, int K, int nin, int batch) {
+  return unroll_state_bytes<T>(op->N, op->M, K, nin, batch) + op_ws_bytes(op, sizeof(T), 1) +
+         (pc ? pc_ws_bytes(pc, 1) : 0);
 }
 
 }  // namespace nys
@@ -467,9 +476,8 @@ extern "C" nys_status nys_unrolled_workspace(const nys_problem* prob, nys_pc pc,
                                              size_t* bytes) {
   NYS_TRY(check_unroll(prob, pc, dt, opts, batch));
   NYS_REQUIRE(bytes, "nys_unrolled_workspace: null bytes");
-  const int64_t N = prob->op->N, M = prob->op->M;
-  *bytes = dt == NYS_F64 ? unroll_ws_bytes<double>(N, M, opts->n_outer, opts->n_inner, batch)
-                         : unroll_ws_bytes<float>(N, M, opts->n_outer, opts->n_inner, batch);
+  *bytes = dt == NYS_F64 ? unroll_ws_bytes<double>(prob->op, pc, opts->n_outer, opts->n_inner, batch)
+                         : unroll_ws_bytes<float>(prob->op, pc, opts->n_outer, opts->n_inner, batch);
   return NYS_OK;
 }
 
@@ -481,8 +489,12 @@ extern "C" nys_status unrolled_forward(const nys_problem* prob, nys_pc pc, nys_d
   NYS_REQUIRE(y && lambda && x && ws, "unrolled_forward: null argument");
   size_t need = 0;
   NYS_TRY(nys_unrolled_workspace(prob, pc, dt, opts, batch, &need));
-  NYS_REQUIRE(ws_bytes >= need, "unrolled_forward: workspace of %zu bytes < %zu", ws_bytes, need);
+  NYS_TRY(check_workspace(ws, ws_bytes, need, "unrolled_forward"));
   for (int b = 0; b < batch; ++b) NYS_REQUIRE(lambda[b] > 0, "unrolled_forward: lambda must be > 0");
+  const size_t keep = dt == NYS_F64
+      ? unroll_state_bytes<double>(prob->op->N, prob->op->M, opts->n_outer, opts->n_inner, batch)
+      : unroll_state_bytes<float>(prob->op->N, prob->op->M, opts->n_outer, opts->n_inner, batch);
+  WsBind bind(static_cast<char*>(ws) + keep, ws_bytes - keep, prob->op, pc);
   hipStream_t st = as_stream(stream);
   if (dt == NYS_F64)
     return unroll_forward<double>(*prob, pc, *opts, batch, static_cast<const double*>(y), lambda,
@@ -500,8 +512,12 @@ extern "C" nys_status unrolled_backward(const nys_problem* prob, nys_pc pc, nys_
   NYS_REQUIRE(y && lambda && bar_x && bar_y && bar_lambda && ws, "unrolled_backward: null argument");
   size_t need = 0;
   NYS_TRY(nys_unrolled_workspace(prob, pc, dt, opts, batch, &need));
-  NYS_REQUIRE(ws_bytes >= need, "unrolled_backward: workspace of %zu bytes < %zu", ws_bytes, need);
+  NYS_TRY(check_workspace(ws, ws_bytes, need, "unrolled_backward"));
   for (int b = 0; b < batch; ++b) NYS_REQUIRE(lambda[b] > 0, "unrolled_backward: lambda must be > 0");
+  const size_t keep = dt == NYS_F64
+      ? unroll_state_bytes<double>(prob->op->N, prob->op->M, opts->n_outer, opts->n_inner, batch)
+      : unroll_state_bytes<float>(prob->op->N, prob->op->M, opts->n_outer, opts->n_inner, batch);
+  WsBind bind(static_cast<char*>(ws) + keep, ws_bytes - keep, prob->op, pc);
   hipStream_t st = as_stream(stream);
   if (dt == NYS_F64)
     return unroll_backward<double>(*prob, pc, *opts, batch, static_cast<const double*>(y), lambda,

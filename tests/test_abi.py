@@ -26,3 +26,24 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
     assert P.version().startswith("nys-mi355x")
+
+
+def test_host_side_argument_errors_without_a_device():
+    """Argument checks and size queries run on the host: they answer without a
+    GPU and never enqueue anything."""
+    import paper_2411_08178_amd as P
+    lib = ctypes.CDLL(P.library_path)
+    lib.nys_last_error.restype = ctypes.c_char_p
+    nb = ctypes.c_size_t()
+    # Alg. 1 scratch: Gram partials, the 2 ell x 2 ell Gram, 5 ell^2 + ell matrices
+    assert lib.nys_factor_workspace_size(ctypes.c_int64(16384), ctypes.c_int64(32),
+                                         ctypes.byref(nb)) == 0
+    assert nb.value >= 8 * (64 * 64 + 5 * 32 * 32 + 32)
+    assert lib.nys_factor_workspace_size(ctypes.c_int64(16384), ctypes.c_int64(129),
+                                         ctypes.byref(nb)) == 1           # ell > 128
+    assert b"bad argument" in lib.nys_last_error()
+    # a null operator handle is refused before any device work
+    assert lib.op_forward(None, 1, None, None, ctypes.c_int64(1), None, ctypes.c_size_t(0),
+                          None) == 1
+    assert lib.nys_sketch(None, 1, None, None, ctypes.c_int64(1), None, ctypes.c_size_t(0),
+                          None) == 1

@@ -547,3 +547,30 @@ def test_rate_constant_matches_oracle_across_sketch_sizes(ell):
     assert abs(got["L"] - ref["L"]) <= 1e-9 * ref["L"]
     assert abs(got["pdist2"] - ref["pdist2"]) <= 1e-10 * ref["pdist2"]
     assert abs(got["value"] - ref["value"]) <= 1e-9 * ref["value"]
+
+
+def test_solve_tv_at_size_with_a_preconditioner():
+    """WAPG with the P-weighted TV prox at 384^2, ell = 64, FP32 (the
+    gradient step's coefficient partials stay held while the prox applies
+    P^{-1} in each of its 20 dual iterations), 3 outer iterations against the
+    oracle on the same rounded inputs; P from a steep synthetic sketch."""
+    P = need_gpu()
+    banner("solve TV 384^2 ell=64 f32 with P")
+    n, ell, iters = 384, 64, 3
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=5, n=n)
+    op = P.Operator(P.OP_BLUR, n, n, psf=prob.h)
+    yd = dev(prob.y, "f32")
+    prob.y = host(yd)
+    om, Y = _steep_psd_sketch(n, ell, seed=70)
+    omd, Yd = dev(om.reshape(ell, n, n), "f32"), dev(Y.reshape(ell, n, n), "f32")
+    ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+    pc = P.nys_factor(omd, Yd, ell, u_dtype=torch.float32)
+    alpha = 0.3
+    rd = P.reg_desc("tv", n, n, n_inner=20)
+    x, costs, info = P.solve(op, yd, rd, prob.lam, pc, iters, alpha=alpha)
+    assert info["status"] == 0
+    xr, cr = sv.wapg(prob, opc, alpha, iters, inner=20)
+    check(host(x), xr, TOL["f32"], what="x after 3 iterations")
+    check(host(costs), cr, TOL["f32"], what="costs")
