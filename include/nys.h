@@ -201,6 +201,17 @@ nys_status nys_apply_workspace_size(nys_pc pc, int64_t ncols, size_t* bytes);
 nys_status nys_apply(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
                      void* out, int64_t ncols, void* ws, size_t ws_bytes, void* stream);
 
+/* nys_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and results, with the coefficients and the block partials of
+ * U^T v in a file-scope device array of 2 MiB per GPU (held by each GPU the
+ * library runs on until the process ends) instead of a workspace.  ncols <= 8
+ * (EINVAL beyond); no allocation of any kind.  Every call on one GPU shares
+ * that GPU's array: calls whose work may overlap (several streams or host
+ * threads) race. */
+nys_status nys_apply_static(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
+                            void* out, int64_t ncols, void* stream);
+
 /* Squared P-norm of a difference, the metric of the WAPG rate bound
  * 2 L_f^P ||x^1 - x^*||_P^2 / (k + 1)^2 stated after eq. (20) (Sec. III-B):
  * *out (one device double, written on `stream`) = (a - b)^T P (a - b), or

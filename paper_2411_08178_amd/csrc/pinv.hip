@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <type_traits>
@@ -1882,3 +1883,69 @@ template nys_status ssn_prox<float>(const nys_reg_desc&, double, nys_pc, const f
                                     double*, hipStream_t, int*, const SsnStep*, const SsnBox*);
 
 }  // namespace nys
+
+// ================================================================ no-allocation P^{-1}
+// nys_apply for callers that cannot allocate: the coefficients and the block
+// partials of U^T v live in one file-scope device array instead of a caller
+// workspace.  Each device holds its own copy; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device (the array's
+// name is a host-side stand-in there).
+namespace {
+
+constexpr int kStaticApplyCols = 8;
+// per column: ell coefficients and at most 256 blocks x 128 rows of partials,
+// each part rounded to 256 bytes as the workspace stack hands them out
+constexpr size_t kStaticApplyBytes =
+    kStaticApplyCols * (((sizeof(double) * nys::PcMeta::kMaxEll + 255) / 256 * 256) +
+                        ((sizeof(double) * 256 * nys::PcMeta::kMaxEll + 255) / 256 * 256));
+
+__device__ __align__(256) char scratch[kStaticApplyBytes];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::once_flag g_scratch_once[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// The device address of this device's array (looked up once per device, with
+// the device current).
+nys_status static_scratch(void** out) {
+  int dev = 0;
+  NYS_CHECK_HIP(hipGetDevice(&dev));
+  NYS_REQUIRE(dev >= 0 && dev < kMaxDevices, "nys_apply_static: device %d out of range", dev);
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g_scratch_err[dev] == hipSuccess) g_scratch_ptr[dev] = p;
+  });
+  if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev]) {
+    nys::set_error("nys_apply_static: hipGetSymbolAddress failed: %s",
+                   hipGetErrorString(g_scratch_err[dev]));
+    return NYS_EHIP;
+  }
+  *out = g_scratch_ptr[dev];
+  return NYS_OK;
+}
+
+}  // namespace
+
+extern "C" nys_status nys_apply_static(nys_pc pc, int32_t inverse, nys_dtype dt, const void* v,
+                                       void* out, int64_t ncols, void* stream) {
+  using namespace nys;
+  NYS_REQUIRE(pc && v && out && ncols > 0, "nys_apply_static: bad argument");
+  NYS_REQUIRE(ncols <= kStaticApplyCols, "nys_apply_static: ncols = %lld exceeds the maximum %d",
+              static_cast<long long>(ncols), kStaticApplyCols);
+  NYS_REQUIRE(static_cast<int32_t>(dt) == pc->u_dtype,
+              "nys_apply_static: dtype must equal the pc's u_dtype");
+  const size_t need = pc_ws_bytes(pc, ncols);
+  NYS_REQUIRE(need <= kStaticApplyBytes, "nys_apply_static: needs %zu bytes of scratch > %zu", need,
+              kStaticApplyBytes);
+  void* ptr = nullptr;
+  NYS_TRY(static_scratch(&ptr));
+  WsBind bind(ptr, kStaticApplyBytes, nullptr, pc);
+  hipStream_t st = as_stream(stream);
+  if (dt == NYS_F64)
+    return pc_apply<double>(pc, inverse != 0, static_cast<const double*>(v),
+                            static_cast<double*>(out), ncols, st);
+  return pc_apply<float>(pc, inverse != 0, static_cast<const float*>(v), static_cast<float*>(out),
+                         ncols, st);
+}
