@@ -519,7 +519,7 @@ def main_batch(args, P, torch, wl):
     achieved = B.sketch_bytes / (sk_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": batch_sketch_traffic(wl, args.seed),
-            "kernel": "bstencil_kernel: batched sketch A^T A Omega, all instances, one launch",
+            "kernel": "bstream_kernel: batched sketch A^T A Omega, all instances, one launch",
             "bytes_per_launch": B.sketch_bytes, "avg_launch_us": round(sk_ms * 1e3, 2)}
     roof["measured_copy_peak"] = copy_peak(torch)
     roof["frac_of_copy_peak"] = round(achieved / roof["measured_copy_peak"], 4)

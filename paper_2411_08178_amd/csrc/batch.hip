@@ -52,7 +52,8 @@ struct StTask {
   int32_t n1, n2;
   int32_t lo_r, nt_r, lo_c, nt_c;
   int32_t taps;     // offset of nt_r row taps, then nt_c column taps
-  int32_t ty;       // tile rows
+  int32_t ty;       // tile rows (tile kernel) or run length (streaming kernel)
+  int32_t ss;       // 1: streaming kernel (see ss_eligible)
 };
 
 struct StItem {
@@ -292,6 +293,179 @@ __global__ __launch_bounds__(256) void bstencil_kernel(const StTask* __restrict_
   }
 }
 
+// ---------------------------------------------------------------- streaming
+// One wave per item: a strip of 128 output columns (two per lane) and a run
+// of up to T.ty output rows, for NT row taps = NT column taps (odd, <= 29,
+// palindromic: the autocorrelation of a PSF always is).  The wave walks down
+// the periodic input window one row at a time:
+//   * row m is staged in LDS (128 + NT - 1 values: a float2 per lane plus one
+//     halo value on NT - 1 lanes), from registers that were loaded NT rows
+//     earlier, so NT rows of global loads stay in flight;
+//   * horizontal pass: each lane reads its NT + 1 window values as float2
+//     runs and forms its two columns' sums;
+//   * vertical pass: the row's two results are added, with each row tap, to
+//     a ring of NT partial outputs per column held in registers; after row m
+//     the ring slot of output row m - NT + 1 is complete, stored and cleared.
+// Per output pixel that is 2 NT (1 + (NT - 1) / rows) FMAs and 8 bytes of
+// HBM traffic (plus the halo re-reads of neighbouring strips and runs).
+// Only this wave touches its LDS row, and LDS operations of a wave complete
+// in order, so a compiler-only memory barrier (no instruction) is the only
+// synchronisation.  Global pointers are cast to the global address space so
+// that loads are global (not flat) loads, which leave the LDS counter alone.
+constexpr int kSsW = 128;
+constexpr int kSsMaxNT = 29;
+constexpr int kSsBuf = kSsW + 64;           // a float2 per lane, then one value per lane
+
+typedef float v2f32 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const float gcf32;
+typedef __attribute__((address_space(1))) const v2f32 gcf32x2;
+typedef __attribute__((address_space(1))) float gf32;
+typedef __attribute__((address_space(1))) v2f32 gf32x2;
+
+// taps of a task palindromic (t[a] == t[nt - 1 - a] on both axes)
+inline bool taps_palindromic(const std::vector<double>& t, int off, int nr, int nc) {
+  for (int a = 0; a < nr; ++a)
+    if (t[off + a] != t[off + nr - 1 - a]) return false;
+  for (int a = 0; a < nc; ++a)
+    if (t[off + nr + a] != t[off + nr + nc - 1 - a]) return false;
+  return true;
+}
+
+// The streaming kernel takes equal odd row and column tap counts up to 29,
+// palindromic taps, an even row length and an even first column offset (so
+// that every lane's column pair is one aligned float2 that never straddles
+// the periodic wrap).
+inline bool ss_eligible(int nt_r, int nt_c, int lo_c, int n2, bool palindromic) {
+  return nt_r == nt_c && (nt_r & 1) && nt_r <= kSsMaxNT && n2 % 2 == 0 && lo_c % 2 == 0 &&
+         palindromic;
+}
+
+__device__ __forceinline__ void wave_fence() { asm volatile("" ::: "memory"); }
+
+template <int NT, bool SUB>
+__device__ __forceinline__ void ss_item(const StTask& T, const StItem& I,
+                                        const float* __restrict__ taps, float* buf) {
+  constexpr int NH = (NT + 1) / 2;        // distinct taps per axis (palindromic)
+  constexpr int RG = (NT + 7) / 8 * 8;    // ring slots: >= NT, a multiple of the prefetch depth
+  constexpr int PD = 8;                   // rows of global loads in flight
+  const int lane = threadIdx.x;
+  const int n1 = T.n1, n2 = T.n2;
+  const int rows = min(T.ty, n1 - I.y0);
+  const int M = rows + NT - 1;                       // input rows of the run
+  gcf32* src = (gcf32*)(T.in + static_cast<int64_t>(I.col) * T.cstride);
+  gf32* dst = (gf32*)(T.out + static_cast<int64_t>(I.col) * T.cstride);
+  const int cb = I.x0 + T.lo_c;                     // even (see ss_eligible)
+  const int c0 = wrap_idx(cb + 2 * lane, n2);
+  const bool hal = lane < NT - 1;
+  const int chl = wrap_idx(cb + kSsW + (hal ? lane : 0), n2);
+  const int j = I.x0 + 2 * lane;
+  const bool inb = j < n2;                           // n2 even: j + 1 < n2 as well
+  const int jc = inb ? j : 0;
+  float tr[NH], tc[NH];
+#pragma unroll
+  for (int a = 0; a < NH; ++a) {
+    tr[a] = taps[T.taps + a];
+    tc[a] = taps[T.taps + NT + a];
+  }
+  float px[PD], py[PD], ph[PD];
+  float a0[RG], a1[RG];
+#pragma unroll
+  for (int s = 0; s < RG; ++s) {
+    a0[s] = 0.f;
+    a1[s] = 0.f;
+  }
+  // Loads and stores are issued on every step without uniform branches (the
+  // loads past the run wrap to valid rows and go unused; a step before the
+  // first complete output row stores into row y0, which the first complete
+  // row overwrites later), so the compiler's wait counts keep PD rows of
+  // loads in flight.
+  int rl = wrap_idx(I.y0 + T.lo_r, n1);              // next input row to load
+  auto load_row = [&](const int q) __attribute__((always_inline)) {
+    gcf32* row = src + static_cast<int64_t>(rl) * n2;
+    const v2f32 v = *(gcf32x2*)(row + c0);
+    px[q] = v.x;
+    py[q] = v.y;
+    ph[q] = row[chl];
+    rl = rl + 1 == n1 ? 0 : rl + 1;
+  };
+#pragma unroll
+  for (int q = 0; q < PD; ++q) load_row(q);
+  // one input row: s is the (compile-time) step within a block of RG rows
+  auto step = [&](const int s, const int m) __attribute__((always_inline)) {
+    const int q = s % PD;
+    wave_fence();
+    *reinterpret_cast<float2*>(buf + 2 * lane) = make_float2(px[q], py[q]);
+    buf[kSsW + lane] = ph[q];                        // lanes >= NT - 1 write unread slots
+    load_row(q);
+    const int o = m - (NT - 1);
+    const int orow = I.y0 + (o > 0 ? o : 0);
+    v2f32 sb = {0.f, 0.f};
+    if (SUB) sb = *(gcf32x2*)((gcf32*)T.sub + static_cast<int64_t>(orow) * n2 + jc);
+    wave_fence();
+    float h0 = 0.f, h1 = 0.f;
+#pragma unroll
+    for (int e = 0; e < NH; ++e) {
+      const float2 w = *reinterpret_cast<const float2*>(buf + 2 * lane + 2 * e);
+      // window value b feeds column 0 with tap b and column 1 with tap b - 1
+      const int b0 = 2 * e, b1 = 2 * e + 1;
+      h0 = fmaf(tc[b0 < NH ? b0 : NT - 1 - b0], w.x, h0);
+      if (b1 < NT) h0 = fmaf(tc[b1 < NH ? b1 : NT - 1 - b1], w.y, h0);
+      if (b0 >= 1) h1 = fmaf(tc[b0 - 1 < NH ? b0 - 1 : NT - b0], w.x, h1);
+      h1 = fmaf(tc[b0 < NH ? b0 : NT - 1 - b0], w.y, h1);
+    }
+    // input row m feeds output row m - a with row tap a
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const int sl = (s - a + RG) % RG;
+      const float t = tr[a < NH ? a : NT - 1 - a];
+      a0[sl] = fmaf(t, h0, a0[sl]);
+      a1[sl] = fmaf(t, h1, a1[sl]);
+    }
+    // output row o = m - NT + 1 is complete (o < 0: a placeholder store)
+    const int so = (s - (NT - 1) + RG) % RG;
+    if (inb)
+      *(gf32x2*)(dst + static_cast<int64_t>(orow) * n2 + j) = v2f32{a0[so] - sb.x, a1[so] - sb.y};
+    a0[so] = 0.f;
+    a1[so] = 0.f;
+  };
+  int m0 = 0;
+  for (; m0 + RG <= M; m0 += RG) {
+#pragma unroll
+    for (int s = 0; s < RG; ++s) step(s, m0 + s);
+  }
+#pragma unroll
+  for (int s = 0; s < RG; ++s)
+    if (m0 + s < M) step(s, m0 + s);
+}
+
+// One workgroup (one wave) per item; items are sorted by tap count, largest
+// first, so the longest items start first.
+template <bool SUB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+void bstream_kernel(const StTask* __restrict__ tasks, const StItem* __restrict__ items,
+                    const float* __restrict__ taps) {
+  __shared__ float buf[kSsBuf];
+  const StItem I = items[blockIdx.x];
+  const StTask T = tasks[I.task];
+  switch (T.nt_r) {
+    case 1: ss_item<1, SUB>(T, I, taps, buf); break;
+    case 3: ss_item<3, SUB>(T, I, taps, buf); break;
+    case 5: ss_item<5, SUB>(T, I, taps, buf); break;
+    case 7: ss_item<7, SUB>(T, I, taps, buf); break;
+    case 9: ss_item<9, SUB>(T, I, taps, buf); break;
+    case 11: ss_item<11, SUB>(T, I, taps, buf); break;
+    case 13: ss_item<13, SUB>(T, I, taps, buf); break;
+    case 15: ss_item<15, SUB>(T, I, taps, buf); break;
+    case 17: ss_item<17, SUB>(T, I, taps, buf); break;
+    case 19: ss_item<19, SUB>(T, I, taps, buf); break;
+    case 21: ss_item<21, SUB>(T, I, taps, buf); break;
+    case 23: ss_item<23, SUB>(T, I, taps, buf); break;
+    case 25: ss_item<25, SUB>(T, I, taps, buf); break;
+    case 27: ss_item<27, SUB>(T, I, taps, buf); break;
+    default: ss_item<29, SUB>(T, I, taps, buf); break;
+  }
+}
+
 // ================================================================ pixel kernels
 // All over 1024-pixel blocks (256 threads x 4) of a segment table.
 #define BSEG_PROLOGUE                                              \
@@ -458,6 +632,9 @@ static std::mutex g_tune_mu;
 static std::map<std::pair<int, int>, int> g_tile_table;
 constexpr int kTyCandidates[] = {8, 16, 32, 64};
 constexpr int kTyDefault = 32;
+// run lengths (output rows per item) of the streaming kernel
+constexpr int kRunCandidates[] = {32, 64, 128, 256};
+constexpr int kRunDefault = 64;
 
 }  // namespace nys
 
@@ -483,10 +660,13 @@ struct nys_batch_s {
   // stencil launches: tasks, items, queue bases, LDS bytes
   struct St {
     const StTask* tasks = nullptr;
-    const StItem* items = nullptr;
+    const StItem* items = nullptr;       // tile kernel items (queued)
     const int* qbase = nullptr;
     int64_t nitems = 0;
     size_t lds = 0;
+    const StItem* sitems = nullptr;      // streaming kernel items
+    int64_t nsitems = 0;
+    bool sub = false;                    // tasks subtract an image
   } st_sketch, st_phi_v, st_grad, st_aty, st_hx;
   const float* taps = nullptr;
   std::vector<std::pair<int, int>> tiles;    // (taps class packed, ty) used
@@ -529,15 +709,16 @@ nys_status rank1_psf(const double* psf, int k, std::vector<double>& u, std::vect
   return NYS_OK;
 }
 
-// r[d + k - 1] = sum_a w[a] w[a + d], d = -(k-1) .. k-1
+// r[d + k - 1] = sum_a w[a] w[a + d], d = -(k-1) .. k-1; r[-d] = r[d] is
+// stored bit for bit (the sum is formed once per |d|)
 std::vector<double> autocorr(const std::vector<double>& w) {
   const int k = static_cast<int>(w.size());
   std::vector<double> r(2 * k - 1, 0.0);
-  for (int dd = -(k - 1); dd <= k - 1; ++dd) {
+  for (int dd = 0; dd <= k - 1; ++dd) {
     double s = 0;
-    for (int a = 0; a < k; ++a)
-      if (a + dd >= 0 && a + dd < k) s += w[a] * w[a + dd];
-    r[dd + k - 1] = s;
+    for (int a = 0; a + dd < k; ++a) s += w[a] * w[a + dd];
+    r[k - 1 + dd] = s;
+    r[k - 1 - dd] = s;
   }
   return r;
 }
@@ -547,16 +728,26 @@ struct TaskSpec {
   int ncols;
 };
 
-// Items of a list of tasks, split into kQueues contiguous queues.
+// Items of a list of tasks.  Tasks with equal odd row and column tap counts
+// up to 29 go to the streaming kernel (strips of 128 columns, runs of ty
+// rows), sorted by tap count, largest first (stable: neighbouring runs of a
+// strip stay adjacent); the others to the tile kernel, split into kQueues
+// contiguous queues.
 void build_items(const std::vector<TaskSpec>& ts, std::vector<StItem>& items,
-                 std::vector<int>& qbase) {
+                 std::vector<int>& qbase, std::vector<StItem>& sitems) {
   items.clear();
+  sitems.clear();
   for (size_t i = 0; i < ts.size(); ++i) {
     const StTask& t = ts[i].t;
+    const bool ss = t.ss != 0;
     for (int c = 0; c < ts[i].ncols; ++c)
       for (int y0 = 0; y0 < t.n1; y0 += t.ty)
-        for (int x0 = 0; x0 < t.n2; x0 += kStW) items.push_back({static_cast<int32_t>(i), c, y0, x0});
+        for (int x0 = 0; x0 < t.n2; x0 += ss ? kSsW : kStW)
+          (ss ? sitems : items).push_back({static_cast<int32_t>(i), c, y0, x0});
   }
+  std::stable_sort(sitems.begin(), sitems.end(), [&](const StItem& a, const StItem& b) {
+    return ts[a.task].t.nt_r > ts[b.task].t.nt_r;
+  });
   qbase.assign(kQueues + 1, 0);
   const int64_t n = static_cast<int64_t>(items.size());
   for (int q = 0; q <= kQueues; ++q) qbase[q] = static_cast<int>(n * q / kQueues);
@@ -564,7 +755,9 @@ void build_items(const std::vector<TaskSpec>& ts, std::vector<StItem>& items,
 
 size_t tasks_lds(const std::vector<TaskSpec>& ts) {
   size_t m = 0;
-  for (const auto& s : ts) m = std::max<size_t>(m, sizeof(float) * st_lds_floats(s.t.ty, s.t.nt_r, s.t.nt_c));
+  for (const auto& s : ts)
+    if (!s.t.ss)
+      m = std::max<size_t>(m, sizeof(float) * st_lds_floats(s.t.ty, s.t.nt_r, s.t.nt_c));
   return m;
 }
 
@@ -579,6 +772,15 @@ int stencil_grid(size_t lds) {
 }
 
 nys_status stencil_launch(const nys_batch_s::St& s, const float* taps, int* ctr, hipStream_t st) {
+  if (s.nsitems > 0) {
+    if (s.sub)
+      hipLaunchKernelGGL(bstream_kernel<true>, dim3(static_cast<unsigned>(s.nsitems)), dim3(64), 0, st,
+                         s.tasks, s.sitems, taps);
+    else
+      hipLaunchKernelGGL(bstream_kernel<false>, dim3(static_cast<unsigned>(s.nsitems)), dim3(64), 0, st,
+                         s.tasks, s.sitems, taps);
+    NYS_TRY(launch_check("bstream_kernel"));
+  }
   if (s.nitems == 0) return NYS_OK;
   hipLaunchKernelGGL(bstencil_kernel, dim3(stencil_grid(s.lds)), dim3(256), s.lds, st, s.tasks,
                      s.items, s.qbase, taps, ctr);
@@ -882,10 +1084,13 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   auto grms = segs(all, [&](int i) { return gram_nblk[i]; }, [&](int i) { return gram_chunk[i]; });
 
   // ---- stencil tasks (tile heights from the autotuner table)
-  auto ty_for = [&](int nt_r, int nt_c) {
+  // tuner classes: (row taps, column taps + 65536 for the streaming kernel)
+  auto tkey = [](const StTask& t) { return std::make_pair(t.nt_r, t.nt_c + (t.ss ? 65536 : 0)); };
+  auto ty_for = [&](const StTask& t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto itr = g_tile_table.find({nt_r, nt_c});
-    return itr == g_tile_table.end() ? kTyDefault : itr->second;
+    auto itr = g_tile_table.find(tkey(t));
+    if (itr != g_tile_table.end()) return itr->second;
+    return t.ss ? kRunDefault : kTyDefault;
   };
   auto mk = [&](int i, const float* in, float* outp, const float* sub, int64_t cstride, int ncols,
                 int which) {
@@ -905,7 +1110,9 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
       s.t.lo_r = -c; s.t.nt_r = k; s.t.lo_c = -c; s.t.nt_c = k;
       s.t.taps = which == 1 ? taps_h[i] : taps_hf[i];
     }
-    s.t.ty = ty_for(s.t.nt_r, s.t.nt_c);
+    s.t.ss = ss_eligible(s.t.nt_r, s.t.nt_c, s.t.lo_c, s.t.n2,
+                         taps_palindromic(tap_host, s.t.taps, s.t.nt_r, s.t.nt_c));
+    s.t.ty = ty_for(s.t);
     s.ncols = ncols;
     return s;
   };
@@ -933,21 +1140,24 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     const size_t o_fac = tb.add(facs.first);
     const size_t o_gram = tb.add(grms.first);
     const size_t o_ctr = tb.add(std::vector<int>(kQueues + 1 + 63, 0));
-    struct StOff { size_t tasks, items, qbase; int64_t n; size_t lds; };
+    struct StOff { size_t tasks, items, qbase, sitems; int64_t n, ns; size_t lds; bool sub; };
     std::vector<TaskSpec>* lists[5] = {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx};
     StOff so[5] = {};
     if (with_stencils) {
       for (int l = 0; l < 5; ++l) {
         std::vector<StTask> tv;
         for (auto& s : *lists[l]) tv.push_back(s.t);
-        std::vector<StItem> iv;
+        std::vector<StItem> iv, sv;
         std::vector<int> qb;
-        build_items(*lists[l], iv, qb);
+        build_items(*lists[l], iv, qb, sv);
         so[l].tasks = tb.add(tv);
         so[l].items = tb.add(iv);
         so[l].qbase = tb.add(qb);
+        so[l].sitems = tb.add(sv);
         so[l].n = static_cast<int64_t>(iv.size());
+        so[l].ns = static_cast<int64_t>(sv.size());
         so[l].lds = tasks_lds(*lists[l]);
+        so[l].sub = !tv.empty() && tv[0].sub != nullptr;
       }
     }
     NYS_TRY(b->tables.ensure(tb.bytes.size() + 256));
@@ -972,6 +1182,9 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
       sts[l]->qbase = reinterpret_cast<const int*>(T + so[l].qbase);
       sts[l]->nitems = with_stencils ? so[l].n : 0;
       sts[l]->lds = so[l].lds;
+      sts[l]->sitems = reinterpret_cast<const StItem*>(T + so[l].sitems);
+      sts[l]->nsitems = with_stencils ? so[l].ns : 0;
+      sts[l]->sub = so[l].sub;
     }
     return NYS_OK;
   };
@@ -992,7 +1205,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   if (o.tune && pc) {
     std::map<std::pair<int, int>, std::vector<int>> classes;
     for (size_t i = 0; i < t_sketch.size(); ++i)
-      classes[{t_sketch[i].t.nt_r, t_sketch[i].t.nt_c}].push_back(static_cast<int>(i));
+      classes[tkey(t_sketch[i].t)].push_back(static_cast<int>(i));
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
       set_error("batch_solve_create: hipEventCreate failed");
@@ -1004,9 +1217,13 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
         std::lock_guard<std::mutex> lk(g_tune_mu);
         if (g_tile_table.count(cl.first)) continue;
       }
+      const bool ss = cl.first.second >= 65536;
       double best_t = 1e300;
-      int best_ty = kTyDefault;
-      for (int ty : kTyCandidates) {
+      int best_ty = ss ? kRunDefault : kTyDefault;
+      std::vector<int> cands;
+      if (ss) cands.assign(std::begin(kRunCandidates), std::end(kRunCandidates));
+      else cands.assign(std::begin(kTyCandidates), std::end(kTyCandidates));
+      for (int ty : cands) {
         std::vector<TaskSpec> ts;
         for (int i : cl.second) {
           TaskSpec s = t_sketch[i];
@@ -1015,11 +1232,11 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
         }
         std::vector<StTask> tv;
         for (auto& s : ts) tv.push_back(s.t);
-        std::vector<StItem> iv;
+        std::vector<StItem> iv, sv;
         std::vector<int> qb;
-        build_items(ts, iv, qb);
+        build_items(ts, iv, qb, sv);
         TableBuilder tbb;
-        const size_t ot = tbb.add(tv), oi = tbb.add(iv), oq = tbb.add(qb);
+        const size_t ot = tbb.add(tv), oi = tbb.add(iv), oq = tbb.add(qb), os = tbb.add(sv);
         if (tb.ensure(tbb.bytes.size() + 256) != NYS_OK ||
             hipMemcpyAsync(tb.p, tbb.bytes.data(), tbb.bytes.size(), hipMemcpyHostToDevice, ust) != hipSuccess) {
           (void)hipEventDestroy(e0);
@@ -1034,6 +1251,8 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
         s.qbase = reinterpret_cast<const int*>(tb.as<char>() + oq);
         s.nitems = static_cast<int64_t>(iv.size());
         s.lds = tasks_lds(ts);
+        s.sitems = reinterpret_cast<const StItem*>(tb.as<char>() + os);
+        s.nsitems = static_cast<int64_t>(sv.size());
         float ms = 0;
         nys_status st2 = stencil_launch(s, b->taps, b->ctr, ust);        // warm-up
         if (st2 == NYS_OK && hipEventRecord(e0, ust) == hipSuccess) {
@@ -1060,7 +1279,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     tb.release();
     // re-derive tile heights from the table
     for (auto* l : {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx})
-      for (auto& s : *l) s.t.ty = ty_for(s.t.nt_r, s.t.nt_c);
+      for (auto& s : *l) s.t.ty = ty_for(s.t);
   }
   for (auto* l : {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx})
     for (auto& s : *l) {

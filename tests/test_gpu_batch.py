@@ -55,25 +55,55 @@ def _oracle_pc(Y, om, ell):
     return sv.Precond(r["U"], r["shat"], r["nu"], "sqrt"), r
 
 
+def _sketch_f32_accumulated(om, h):
+    """Y = A^T A Omega evaluated in FP32 by the oracle side itself: the PSF's
+    separable autocorrelation stencil (rows, then columns), one FP32 rounding
+    per tap, as an FP32-accumulating sketch computes it."""
+    k = h.shape[0]
+    c = k // 2
+    u = h[:, c] / np.sqrt(h[c, c])
+    v = h[c, :] / np.sqrt(h[c, c])
+
+    def autocorr(w):
+        r = np.zeros(2 * k - 1)
+        for d in range(k):
+            r[k - 1 + d] = r[k - 1 - d] = np.dot(w[:k - d], w[d:])
+        return r
+
+    tr = autocorr(u).astype(np.float32)
+    tc = autocorr(v).astype(np.float32)
+    lo = -(k - 1)
+    x = np.asarray(om, np.float32)
+    acc = np.zeros_like(x)
+    for a in range(2 * k - 1):
+        acc = (np.float64(tr[a]) * np.roll(x, -(lo + a), -2) + acc).astype(np.float32)
+    out = np.zeros_like(x)
+    for b in range(2 * k - 1):
+        out = (np.float64(tc[b]) * np.roll(acc, -(lo + b), -1) + out).astype(np.float32)
+    return out.astype(np.float64)
+
+
 class Floor:
-    """The batched plan factorises its own FP32 sketch, so results downstream
-    of it carry the FP32 error of Y through the factorisation.  The oracle
-    measures that effect on itself: it factorises its FP64 sketch and the same
-    sketch rounded to FP32 and compares.  The GPU's sketch carries FP32
-    accumulation error on top of its rounding (measured 1.2e-7 relative, about
-    twice the rounding alone), so a tolerance is the stated FP32 one, or ten
-    times that self-sensitivity where the factorisation's conditioning makes
-    it larger (a 32^2 instance with a 11 x 11, sigma 2.5 PSF and ell = 64:
-    Nystrom eigenvalues over many decades)."""
+    """The batched plan factorises its own FP32 sketch, whose sums accumulate
+    in FP32 (the precision the sketch applies are specified to use), so
+    results downstream of it carry that sketch error through the
+    factorisation.  The oracle measures the effect on itself: it factorises
+    its FP64 sketch and its own FP32-accumulated evaluation of the same
+    stencil and compares.  A tolerance is the stated FP32 one, or three times
+    that self-sensitivity where the factorisation's conditioning makes it
+    larger (a 32^2 instance with a 11 x 11, sigma 2.5 PSF and ell = 64:
+    Nystrom eigenvalues over many decades, where an FP32-accumulated sketch
+    moves P^-1 by ~3e-5); two FP32 summation orders differ by a factor of
+    about two in this error."""
 
     def __init__(self, prob, om, Yref, ell):
         self.pc64, self.ref = _oracle_pc(Yref, om, ell)
-        self.pc32, _ = _oracle_pc(W.round_dtype(Yref, "f32"), om, ell)
+        self.pc32, _ = _oracle_pc(_sketch_f32_accumulated(om, prob.h), om, ell)
         self.prob = prob
 
     @staticmethod
     def tol(a64, a32):
-        return max(TOL["f32"], 10.0 * rel(a32, a64))
+        return max(TOL["f32"], 3.0 * rel(a32, a64))
 
     def pinv(self, z):
         a = self.pc64.pinv(z)
@@ -175,7 +205,7 @@ def test_batch_tile_table_and_errors():
     inst = _instances(700, specs=SPECS[:2])
     plan = P.BatchSolver(inst, max_iter=1, n_inner=1, power_iters=2, tune=True)
     tiles = plan.tiles()
-    assert tiles and all(t[2] in (8, 16, 32, 64) for t in tiles)
+    assert tiles and all(t[2] in (8, 16, 32, 64, 128, 256) for t in tiles)
     # the A^T A class of a k-tap PSF has 2k - 1 taps per axis
     assert {(2 * k - 1) for (_, k, _, _, _) in SPECS[:2]} <= {t[0] for t in tiles}
     bad = dict(inst[0])
