@@ -30,6 +30,7 @@
 
 #include "batch.hpp"
 #include "common.hpp"
+#include "fused.hpp"
 #include "internal.hpp"
 #include "stencil.hpp"
 
@@ -623,6 +624,68 @@ __global__ __launch_bounds__(256) void bcopy_out_kernel(const BDesc* __restrict_
   }
 }
 
+// One fused inner iteration of every instance's P-weighted prox (fused.hpp):
+// block b -> tile g of the launch (XCD-contiguous runs) -> instance and tile.
+template <int TW>
+__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void bfused_kernel(const BDesc* __restrict__ d, const BSeg* __restrict__ seg, int nseg,
+                   int ntiles, int reg, int fqi, int fri, int fqo, int fro, float beta, int last) {
+  __shared__ FusedLds<TW> L;
+  const int g = fused_tile_of(blockIdx.x, ntiles);
+  if (g >= ntiles) return;
+  const BSeg& sg = seg[seg_find(seg, nseg, g)];
+  const BDesc& D = d[sg.inst];
+  FusedArgs A;
+  A.n1 = D.n1;
+  A.n2 = D.n2;
+  A.reg = reg;
+  A.ell = D.ell;
+  A.ell_pad = D.ell_pad;
+  A.ldu = D.ldu;
+  A.U = D.U;
+  A.cd = D.cd;
+  A.s = D.f[kFldS];
+  A.Qi = D.f[fqi];
+  A.Ri = D.f[fri];
+  A.Qo = D.f[fqo];
+  A.Ro = D.f[fro];
+  A.lam_bar = static_cast<float>(D.scal[BScal::kLamBar]);
+  A.step = static_cast<float>(D.scal[BScal::kDualStep]);
+  A.beta = beta;
+  A.last = last;
+  A.part = D.fpart;
+  const int tile = static_cast<int>(g - sg.first);
+  const int ntx = (D.n2 + TW - 1) / TW;
+  switch (D.ell_pad) {
+    case 16: fused_tile<16, TW>(A, tile, ntx, L); break;
+    case 32: fused_tile<32, TW>(A, tile, ntx, L); break;
+    default: fused_tile<64, TW>(A, tile, ntx, L); break;
+  }
+}
+
+// D.cd[k] = d_k sum_b D.fpart[b][k] for 16 coefficients a block: block
+// (segment, group of 16); 64 groups of 16 lanes read 128-byte runs of the
+// tile partials, then an LDS tree sums the groups (fixed order).
+__global__ __launch_bounds__(1024) void bftail_kernel(const BDesc* __restrict__ d,
+                                                      const BSeg* __restrict__ seg) {
+  __shared__ double red[64][17];
+  const BSeg& sg = seg[blockIdx.x];
+  const BDesc& D = d[sg.inst];
+  const int kk = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int k = blockIdx.y * 16 + kk;
+  if (blockIdx.y * 16 >= D.ell) return;
+  double s = 0.0;
+  if (k < D.ell)
+    for (int64_t b = grp; b < sg.nblk; b += 64) s += D.fpart[b * D.ell_pad + k];
+  red[grp][kk] = s;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (grp < w) red[grp][kk] += red[grp + w][kk];
+    __syncthreads();
+  }
+  if (grp == 0 && k < D.ell) D.cd[k] = D.meta[PcMeta::kD + k] * red[0][kk];
+}
+
 #undef BSEG_PROLOGUE
 
 // ================================================================ autotuner
@@ -652,7 +715,7 @@ struct nys_batch_s {
   std::vector<int64_t> pix_off;              // packed offsets of the images
   int64_t P = 0;                             // packed image length
   BDesc* dd = nullptr;                       // device descriptors
-  BLaunch pix, cmb, red, upix, fac, gram;
+  BLaunch pix, cmb, red, upix, fac, gram, ftl;
   int kgroups = 0;
   int max_ell = 0;
   int64_t lds_doubles = 0;
@@ -721,6 +784,12 @@ std::vector<double> autocorr(const std::vector<double>& w) {
     r[k - 1 - dd] = s;
   }
   return r;
+}
+
+// tiles of the fused inner iteration in an n1 x n2 image
+int64_t batch_tiles(int n1, int n2, int reg) {
+  const int tw = fused_tw(reg_hessian(reg));
+  return static_cast<int64_t>(cdiv(n1, kFThreads / tw)) * static_cast<int64_t>(cdiv(n2, tw));
 }
 
 struct TaskSpec {
@@ -863,23 +932,64 @@ nys_status enqueue_all(nys_batch_s* b) {
     NYS_TRY(batch_combine(d, b->cmb.seg, b->cmb.nseg, b->cmb.nblk, kFldU, kFldG, kFldS, BScal::kAlpha, st));
     // x+ = prox^P_{lam_bar g}(s): accelerated projected gradient on the dual
     if (!o.warm_start) NYS_TRY(fill_zero<float>(d0.f[kFldQ], static_cast<size_t>(b->nch) * b->P, st));
-    NYS_CHECK_HIP(hipMemcpyAsync(d0.f[kFldR], d0.f[kFldQ], sizeof(float) * b->nch * b->P,
-                                 hipMemcpyDeviceToDevice, st));
-    double tau = 1.0;
-    for (int it = 0; it <= o.n_inner; ++it) {
-      const bool last = it == o.n_inner;
-      hipLaunchKernelGGL(blt_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg,
-                         int(last ? kFldQ : kFldR), int(kFldT));
+    if (pc) {
+      // with P^{-1} inside: the warm start's coefficients, then one fused
+      // launch and the coefficient tail per dual iteration (R = Q at the
+      // start; the duals alternate between Q, R and Q2, R2)
+      hipLaunchKernelGGL(blt_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg, int(kFldQ),
+                         int(kFldT));
       NYS_TRY(launch_check("blt_kernel"));
-      if (pc) NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldT, st));
+      NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldT, st));
+      int qi = kFldQ, ri = kFldQ;
+      double tau = 1.0;
+      const int ntiles = static_cast<int>(b->ftl.nblk);
+      const dim3 fg(static_cast<unsigned>((ntiles + 7) / 8 * 8));
+      const dim3 tg(static_cast<unsigned>(b->ftl.nseg), static_cast<unsigned>(cdiv(b->max_ell, 16)));
+      for (int it = 0; it < o.n_inner; ++it) {
+        const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
+        const double beta = (tau - 1.0) / tau_n;
+        const int qo = (it & 1) ? kFldQ : kFldQ2;
+        const int ro = (it & 1) ? kFldR2 : kFldR;
+        if (reg_hessian(reg))
+          hipLaunchKernelGGL(bfused_kernel<fused_tw(true)>, fg, dim3(kFThreads), 0, st, d, b->ftl.seg,
+                             b->ftl.nseg, ntiles, reg, qi, ri, qo, ro, static_cast<float>(beta),
+                             int(it == o.n_inner - 1));
+        else
+          hipLaunchKernelGGL(bfused_kernel<fused_tw(false)>, fg, dim3(kFThreads), 0, st, d, b->ftl.seg,
+                             b->ftl.nseg, ntiles, reg, qi, ri, qo, ro, static_cast<float>(beta),
+                             int(it == o.n_inner - 1));
+        NYS_TRY(launch_check("bfused_kernel"));
+        hipLaunchKernelGGL(bftail_kernel, tg, dim3(1024), 0, st, d, b->ftl.seg);
+        NYS_TRY(launch_check("bftail_kernel"));
+        qi = qo;
+        ri = ro;
+        tau = tau_n;
+      }
+      if (qi != kFldQ)
+        NYS_CHECK_HIP(hipMemcpyAsync(d0.f[kFldQ], d0.f[qi], sizeof(float) * b->nch * b->P,
+                                     hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(blt_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg, int(kFldQ),
+                         int(kFldT));
+      NYS_TRY(launch_check("blt_kernel"));
       NYS_TRY(batch_combine(d, b->cmb.seg, b->cmb.nseg, b->cmb.nblk, kFldS, kFldT, kFldXN, BScal::kLamBar, st));
-      if (last) break;
-      const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
-      const double beta = (tau - 1.0) / tau_n;
-      hipLaunchKernelGGL(bdual_update_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg,
-                         static_cast<float>(beta));
-      NYS_TRY(launch_check("bdual_update_kernel"));
-      tau = tau_n;
+    } else {
+      NYS_CHECK_HIP(hipMemcpyAsync(d0.f[kFldR], d0.f[kFldQ], sizeof(float) * b->nch * b->P,
+                                   hipMemcpyDeviceToDevice, st));
+      double tau = 1.0;
+      for (int it = 0; it <= o.n_inner; ++it) {
+        const bool last = it == o.n_inner;
+        hipLaunchKernelGGL(blt_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg,
+                           int(last ? kFldQ : kFldR), int(kFldT));
+        NYS_TRY(launch_check("blt_kernel"));
+        NYS_TRY(batch_combine(d, b->cmb.seg, b->cmb.nseg, b->cmb.nblk, kFldS, kFldT, kFldXN, BScal::kLamBar, st));
+        if (last) break;
+        const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
+        const double beta = (tau - 1.0) / tau_n;
+        hipLaunchKernelGGL(bdual_update_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg,
+                           static_cast<float>(beta));
+        NYS_TRY(launch_check("bdual_update_kernel"));
+        tau = tau_n;
+      }
     }
     const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
     const double beta = (t_prev - 1.0) / t;
@@ -972,7 +1082,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   b->P = P;
 
   // ---- arena layout
-  struct Off { size_t Y, U, meta, G, gpart, fwork, part, cd, scal; };
+  struct Off { size_t Y, U, meta, G, gpart, fwork, part, fpart, cd, scal; };
   std::vector<Off> off(count);
   size_t cur = 0;
   auto take = [&](size_t bytes) { size_t o0 = cur; cur += (bytes + 255) / 256 * 256; return o0; };
@@ -980,7 +1090,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   cur += 0;
   size_t field_off[kNumFields];
   for (int f = 0; f < kNumFields; ++f) {
-    const int ch = (f == kFldQ || f == kFldR) ? b->nch : 1;
+    const int ch = field_is_dual(f) ? b->nch : 1;
     field_off[f] = take(sizeof(float) * ch * P);
   }
   (void)fields_off;
@@ -1014,6 +1124,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     q.gpart = take(sizeof(double) * gram_nblk[i] * ntri * 4096);
     q.fwork = take(sizeof(double) * (5 * ell * ell + ell + 1));
     q.part = take(sizeof(double) * std::max<int64_t>(red_nblk[i] * std::max(ell_pad, 16), pblk));
+    q.fpart = take(ell > 0 ? sizeof(double) * batch_tiles(it.n1, it.n2, o.reg) * ell_pad : 0);
     q.cd = take(sizeof(double) * std::max(ell_pad, 16));
     q.scal = take(sizeof(double) * BScal::kTotal);
     BDesc D{};
@@ -1049,12 +1160,13 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     D.gpart = reinterpret_cast<double*>(A + q.gpart);
     D.fwork = reinterpret_cast<double*>(A + q.fwork);
     D.part = reinterpret_cast<double*>(A + q.part);
+    D.fpart = reinterpret_cast<double*>(A + q.fpart);
     D.cd = reinterpret_cast<double*>(A + q.cd);
     D.scal = reinterpret_cast<double*>(A + q.scal);
     D.costs = it.costs;
     D.x_out = it.x;
     for (int f = 0; f < kNumFields; ++f) {
-      const int ch = (f == kFldQ || f == kFldR) ? b->nch : 1;
+      const int ch = field_is_dual(f) ? b->nch : 1;
       D.f[f] = reinterpret_cast<float*>(A + field_off[f]) + ch * b->pix_off[i];
     }
   }
@@ -1082,6 +1194,8 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   auto upxs = segs(all, [&](int i) { return (b->hd[i].N + 255) / 256; }, [](int) { return int64_t(256); });
   auto facs = segs(all, [](int) { return int64_t(1); }, [](int) { return int64_t(0); });
   auto grms = segs(all, [&](int i) { return gram_nblk[i]; }, [&](int i) { return gram_chunk[i]; });
+  auto ftls = segs(all, [&](int i) { return batch_tiles(b->hd[i].n1, b->hd[i].n2, o.reg); },
+                   [](int) { return int64_t(kFThreads); });
 
   // ---- stencil tasks (tile heights from the autotuner table)
   // tuner classes: (row taps, column taps + 65536 for the streaming kernel)
@@ -1139,6 +1253,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     const size_t o_upx = tb.add(upxs.first);
     const size_t o_fac = tb.add(facs.first);
     const size_t o_gram = tb.add(grms.first);
+    const size_t o_ftl = tb.add(ftls.first);
     const size_t o_ctr = tb.add(std::vector<int>(kQueues + 1 + 63, 0));
     struct StOff { size_t tasks, items, qbase, sitems; int64_t n, ns; size_t lds; bool sub; };
     std::vector<TaskSpec>* lists[5] = {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx};
@@ -1174,6 +1289,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     b->fac = {reinterpret_cast<const BSeg*>(T + o_fac), pc ? static_cast<int>(facs.first.size()) : 0, facs.second};
     b->gram = {reinterpret_cast<const BSeg*>(T + o_gram), static_cast<int>(grms.first.size()),
                grms.second};
+    b->ftl = {reinterpret_cast<const BSeg*>(T + o_ftl), static_cast<int>(ftls.first.size()), ftls.second};
     b->ctr = reinterpret_cast<int*>(T + o_ctr);
     nys_batch_s::St* sts[5] = {&b->st_sketch, &b->st_phi_v, &b->st_grad, &b->st_aty, &b->st_hx};
     for (int l = 0; l < 5; ++l) {

@@ -14,7 +14,14 @@
 namespace nys {
 
 // Image fields of a batched instance (all N floats, Q and R nch * N).
-enum BField { kFldX = 0, kFldU, kFldG, kFldS, kFldXN, kFldT, kFldB, kFldV, kFldW, kFldQ, kFldR, kNumFields };
+// Q2 / R2: the second dual buffers of the fused inner iteration.
+enum BField {
+  kFldX = 0, kFldU, kFldG, kFldS, kFldXN, kFldT, kFldB, kFldV, kFldW, kFldQ, kFldR, kFldQ2, kFldR2,
+  kNumFields
+};
+__host__ __device__ inline bool field_is_dual(int f) {
+  return f == kFldQ || f == kFldR || f == kFldQ2 || f == kFldR2;
+}
 
 // Per-instance FP64 scalars produced on the device.
 struct BScal {
@@ -43,6 +50,7 @@ struct BDesc {
   double* fwork;             // factor scratch (5 ell^2 + ell)
   float* f[kNumFields];      // image fields
   double* part;              // per-block reduction partials
+  double* fpart;             // per-tile partials of the fused inner iteration
   double* cd;                // ell coefficients d . U^T v
   double* scal;              // BScal::kTotal scalars
   double* costs;             // optional cost per outer iteration

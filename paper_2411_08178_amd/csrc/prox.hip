@@ -7,8 +7,10 @@
 // decisions (accept / backtrack / converge) are taken on the device.
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
+#include "fused.hpp"
 #include "internal.hpp"
 #include "stencil.hpp"
 
@@ -35,6 +37,63 @@ __global__ __launch_bounds__(256) void dual_update_kernel(const T* __restrict__ 
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= n1 || j >= n2) return;
   dual_update_at(x, Q, R, reg, i, j, n1, n2, step, beta);
+}
+
+// One fused inner iteration over the tiles of one image (see fused.hpp).
+template <int KR, int TW>
+__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void dual_fused_kernel(FusedArgs A, int ntx, int ntiles) {
+  __shared__ FusedLds<TW> L;
+  const int tile = fused_tile_of(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
+  fused_tile<KR, TW>(A, tile, ntx, L);
+}
+
+// x = s - lam_bar (L^T Q + U c): the prox output from the final dual
+template <class T>
+__global__ __launch_bounds__(256) void x_from_dual_kernel(const T* __restrict__ s,
+                                                          const T* __restrict__ Q, int reg, int n1,
+                                                          int n2, const T* __restrict__ U,
+                                                          int64_t ldu, const double* __restrict__ cd,
+                                                          int L, T lam, T* __restrict__ x) {
+  __shared__ T cs[PcMeta::kMaxEll];
+  for (int k = threadIdx.x; k < L; k += blockDim.x) cs[k] = static_cast<T>(cd[k]);
+  __syncthreads();
+  const int64_t N = static_cast<int64_t>(n1) * n2;
+  const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (n >= N) return;
+  const int i = static_cast<int>(n / n2), j = static_cast<int>(n - static_cast<int64_t>(i) * n2);
+  T acc = 0;
+  for (int k = 0; k < L; ++k) acc += U[static_cast<size_t>(k) * ldu + n] * cs[k];
+  x[n] = s[n] - lam * (lt_at(Q, reg, i, j, n1, n2) + acc);
+}
+
+static int fused_keep(int ell_pad) { return ell_pad < kFKeep ? ell_pad : kFKeep; }
+
+template <int TW>
+static nys_status fused_launch_tw(const FusedArgs& A, hipStream_t st) {
+  const int ntx = cdiv(A.n2, TW), nty = cdiv(A.n1, kFThreads / TW);
+  const int ntiles = ntx * nty;
+  const dim3 grid(static_cast<unsigned>((ntiles + 7) / 8 * 8));
+  switch (fused_keep(A.ell_pad)) {
+    case 16: hipLaunchKernelGGL((dual_fused_kernel<16, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
+    case 32: hipLaunchKernelGGL((dual_fused_kernel<32, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
+    case 48: hipLaunchKernelGGL((dual_fused_kernel<48, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
+    case 64: hipLaunchKernelGGL((dual_fused_kernel<64, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
+    default: hipLaunchKernelGGL((dual_fused_kernel<80, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
+  }
+  return launch_check("dual_fused_kernel");
+}
+
+static nys_status fused_launch(const FusedArgs& A, hipStream_t st) {
+  return reg_hessian(A.reg) ? fused_launch_tw<fused_tw(true)>(A, st)
+                            : fused_launch_tw<fused_tw(false)>(A, st);
+}
+
+// tiles of the fused iteration for an image and regulariser kind
+static size_t fused_tiles(int n1, int n2, int kind) {
+  const int tw = fused_tw(reg_hessian(kind));
+  return static_cast<size_t>(cdiv(n1, kFThreads / tw)) * static_cast<size_t>(cdiv(n2, tw));
 }
 
 template <class T>
@@ -130,6 +189,73 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
   return conv;
 }
 
+// The dual iteration of dual_prox with P^{-1} applied inside one fused pass
+// per inner iteration (FP32 U, C = R^N).  The duals alternate between the
+// caller's Q / the workspace R and the second buffers Q2 / R2; the first
+// iteration reads R = Q (the warm start), the last writes the partials of
+// L^T Q+ (the output uses Q, not R).  The final Q is left in the caller's Q.
+static nys_status dual_prox_fused(const nys_reg_desc& reg, double lam_bar, nys_pc pc,
+                                  const float* s, float* x, float* Q, float* R, float* Q2,
+                                  float* R2, float* tbuf, double* cd, double* fpart,
+                                  hipStream_t st) {
+  const int n1 = reg.n1, n2 = reg.n2;
+  const int64_t N = static_cast<int64_t>(n1) * n2;
+  const int nch = reg_hessian(reg.kind) ? 3 : 2;
+  const double lnorm2 = reg.lnorm2 > 0 ? reg.lnorm2 : (reg_hessian(reg.kind) ? 34.0 : 8.0);
+  if (pc->pinv_norm_cache < 0) {
+    double hm[PcMeta::kTotal];
+    NYS_CHECK_HIP(hipMemcpyAsync(hm, pc->meta.p, sizeof hm, hipMemcpyDeviceToHost, st));
+    NYS_CHECK_HIP(hipStreamSynchronize(st));
+    pc->pinv_norm_cache = hm[PcMeta::kPinvNorm];
+  }
+  const double step = 1.0 / (lam_bar * lnorm2 * pc->pinv_norm_cache);
+  const dim3 g2(cdiv(n2, 64), cdiv(n1, 4));
+  // c of the warm start: d . U^T L^T Q
+  hipLaunchKernelGGL((lt_kernel<float>), g2, dim3(256), 0, st, Q, reg.kind, n1, n2,
+                     static_cast<const float*>(nullptr), 0.f, tbuf);
+  NYS_TRY(launch_check("lt_kernel"));
+  NYS_TRY(pc_coeffs<float>(pc, true, tbuf, 1, cd, st));
+  FusedArgs A{};
+  A.n1 = n1;
+  A.n2 = n2;
+  A.reg = reg.kind;
+  A.ell = static_cast<int>(pc->ell);
+  A.ell_pad = static_cast<int>(pc->ell_pad);
+  A.ldu = pc->ldu;
+  A.U = pc->U.as<float>();
+  A.cd = cd;
+  A.s = s;
+  A.lam_bar = static_cast<float>(lam_bar);
+  A.step = static_cast<float>(step);
+  A.part = fpart;
+  const CoefPartials cp{fpart, static_cast<int>(fused_tiles(n1, n2, reg.kind)), 1};
+  float* qbuf[2] = {Q, Q2};
+  float* rbuf[2] = {R, R2};
+  const float* qcur = Q;
+  const float* rcur = Q;             // R = Q at the start
+  double tau = 1.0;
+  for (int it = 0; it < reg.n_inner; ++it) {
+    const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
+    A.beta = static_cast<float>((tau - 1.0) / tau_n);
+    A.Qi = qcur;
+    A.Ri = rcur;
+    A.Qo = qbuf[(it + 1) & 1];
+    A.Ro = rbuf[it & 1];
+    A.last = it == reg.n_inner - 1;
+    NYS_TRY(fused_launch(A, st));
+    NYS_TRY(pc_tail(pc, true, cp, cd, st));
+    qcur = A.Qo;
+    rcur = A.Ro;
+    tau = tau_n;
+  }
+  if (qcur != Q)
+    NYS_CHECK_HIP(hipMemcpyAsync(Q, qcur, sizeof(float) * nch * N, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL((x_from_dual_kernel<float>), dim3(cdiv(N, 256)), dim3(256), 0, st, s, Q,
+                     reg.kind, n1, n2, pc->U.as<float>(), pc->ldu, cd, static_cast<int>(pc->ell),
+                     static_cast<float>(lam_bar), x);
+  return launch_check("x_from_dual_kernel");
+}
+
 template <class T>
 __global__ void soft_kernel(const T* __restrict__ s, T lam, int64_t N, T* __restrict__ x) {
   const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -139,11 +265,17 @@ __global__ void soft_kernel(const T* __restrict__ s, T lam, int64_t N, T* __rest
   x[n] = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
 }
 
+// [cd, gbox: kMaxEll doubles each | R | Q (when no state) | t | FP32 only:
+//  Q', R' (the fused iteration's second buffers) | block partials]
 template <class T>
 size_t prox_ws_bytes(const nys_reg_desc& reg) {
   const size_t N = static_cast<size_t>(reg.n1) * reg.n2;
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
-  return sizeof(double) * 2 * PcMeta::kMaxEll + sizeof(T) * (static_cast<size_t>(nch) * N * 2 + N) + 256;
+  size_t b = sizeof(double) * 2 * PcMeta::kMaxEll + sizeof(T) * (static_cast<size_t>(nch) * N * 2 + N);
+  if (std::is_same<T, float>::value)
+    b += ws_round(sizeof(T) * static_cast<size_t>(nch) * N * 2) +
+         ws_round(sizeof(double) * fused_tiles(reg.n1, reg.n2, reg.kind) * PcMeta::kMaxEll);
+  return b + 512;
 }
 
 template <class T>
@@ -159,8 +291,7 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     return ssn_prox<T>(reg, lam_bar, pc, s, x, static_cast<double*>(state), st);
   }
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
-  // work: [cd, gbox: kMaxEll doubles each | R | Q (when no state) | t], the
-  // caller's buffer of prox_ws_bytes
+  // work: the caller's buffer of prox_ws_bytes
   NYS_REQUIRE(work, "prox: no work buffer");
   char* base = static_cast<char*>(work);
   double* cd = reinterpret_cast<double*>(base);
@@ -169,6 +300,17 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   T* Q = state ? static_cast<T*>(state) : R + static_cast<size_t>(nch) * N;
   T* tbuf = R + static_cast<size_t>(nch) * N * 2;
   if (!state) NYS_TRY(fill_zero<T>(Q, static_cast<size_t>(nch) * N, st));
+  if constexpr (std::is_same<T, float>::value) {
+    if (pc && !reg.box && pc->u_dtype == NYS_F32 && pc->ell >= 1 && pc->ell_pad <= PcMeta::kMaxEll) {
+      char* f = reinterpret_cast<char*>(tbuf + N);
+      f = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(f) + 255) / 256 * 256);
+      T* Q2 = reinterpret_cast<T*>(f);
+      T* R2 = Q2 + static_cast<size_t>(nch) * N;
+      double* fpart = reinterpret_cast<double*>(
+          f + ws_round(sizeof(T) * static_cast<size_t>(nch) * N * 2));
+      return dual_prox_fused(reg, lam_bar, pc, s, x, Q, R, Q2, R2, tbuf, cd, fpart, st);
+    }
+  }
   return dual_prox<T>(reg, lam_bar, pc, s, x, Q, R, tbuf, cd, gbox, st);
 }
 

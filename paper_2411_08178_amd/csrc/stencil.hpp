@@ -22,44 +22,79 @@ __device__ __forceinline__ T ldc(const T* x, int i, int j, int n1, int n2) {
   return x[static_cast<size_t>(i) * n2 + j];
 }
 
-// Sum of q over {(i, j) : clip(i + di) = ip, clip(j + dj) = jp}.
-template <class T>
-__device__ __forceinline__ T rep_adj(const T* q, int ip, int jp, int di, int dj, int n1, int n2) {
-  int is[2], js[2], ni = 0, nj = 0;
-  if (di == 0) { is[ni++] = ip; }
-  else if (di < 0) { if (ip + 1 < n1) is[ni++] = ip + 1; if (ip == 0) is[ni++] = 0; }
-  else { if (ip >= 1) is[ni++] = ip - 1; if (ip == n1 - 1) is[ni++] = n1 - 1; }
-  if (dj == 0) { js[nj++] = jp; }
-  else if (dj < 0) { if (jp + 1 < n2) js[nj++] = jp + 1; if (jp == 0) js[nj++] = 0; }
-  else { if (jp >= 1) js[nj++] = jp - 1; if (jp == n2 - 1) js[nj++] = n2 - 1; }
+// The stencils read their operands through accessors a(c, i, j) (channel c
+// at in-image pixel (i, j)), so that the same arithmetic serves arrays in
+// global memory and tiles staged in LDS.
+
+// Sum of q(c, ., .) over {(i, j) : clip(i + di) = ip, clip(j + dj) = jp}:
+// along each axis at most two indices, the neighbour p - d (inside the
+// image) and, at the border the clip maps onto, p itself; summed in the
+// order (a0, b0), (a0, b1), (a1, b0), (a1, b1).
+template <class T, class Acc>
+__device__ __forceinline__ T rep_adj_with(const Acc& q, int c, int ip, int jp, int di, int dj,
+                                          int n1, int n2) {
+  const int a0 = ip - di, a1 = di < 0 ? 0 : n1 - 1;
+  const bool va0 = di == 0 || (di < 0 ? ip + 1 < n1 : ip >= 1);
+  const bool va1 = di != 0 && (di < 0 ? ip == 0 : ip == n1 - 1);
+  const int b0 = jp - dj, b1 = dj < 0 ? 0 : n2 - 1;
+  const bool vb0 = dj == 0 || (dj < 0 ? jp + 1 < n2 : jp >= 1);
+  const bool vb1 = dj != 0 && (dj < 0 ? jp == 0 : jp == n2 - 1);
   T s = 0;
-  for (int a = 0; a < ni; ++a)
-    for (int b = 0; b < nj; ++b) s += q[static_cast<size_t>(is[a]) * n2 + js[b]];
+  if (va0 && vb0) s += q(c, a0, b0);
+  if (va0 && vb1) s += q(c, a0, b1);
+  if (va1 && vb0) s += q(c, a1, b0);
+  if (va1 && vb1) s += q(c, a1, b1);
   return s;
+}
+
+// (L^T q) at (i, j)
+template <class T, class Acc>
+__device__ __forceinline__ T lt_with(const Acc& q, int reg, int i, int j, int n1, int n2) {
+  if (!reg_hessian(reg)) {
+    T v = 0;
+    if (i >= 1) v += q(0, i, j);
+    if (i + 1 < n1) v -= q(0, i + 1, j);
+    if (j >= 1) v += q(1, i, j);
+    if (j + 1 < n2) v -= q(1, i, j + 1);
+    return v;
+  }
+  T v = rep_adj_with<T>(q, 0, i, j, -1, 0, n1, n2) - T(2) * q(0, i, j) +
+        rep_adj_with<T>(q, 0, i, j, 1, 0, n1, n2);
+  v += rep_adj_with<T>(q, 1, i, j, 0, -1, n1, n2) - T(2) * q(1, i, j) +
+       rep_adj_with<T>(q, 1, i, j, 0, 1, n1, n2);
+  v += T(0.5) * (rep_adj_with<T>(q, 2, i, j, 1, 1, n1, n2) - rep_adj_with<T>(q, 2, i, j, 1, -1, n1, n2) -
+                 rep_adj_with<T>(q, 2, i, j, -1, 1, n1, n2) + rep_adj_with<T>(q, 2, i, j, -1, -1, n1, n2));
+  return v;
+}
+
+// (L x) at (i, j) into l0, l1 (and l2 for the Hessian kinds); returns the
+// channel count.  x(i, j) reads pixel (i, j).
+template <class T, class Acc>
+__device__ __forceinline__ int lx_with(const Acc& x, int reg, int i, int j, int n1, int n2, T& l0,
+                                       T& l1, T& l2) {
+  auto cl = [&](int ii, int jj) {
+    ii = ii < 0 ? 0 : (ii >= n1 ? n1 - 1 : ii);
+    jj = jj < 0 ? 0 : (jj >= n2 ? n2 - 1 : jj);
+    return x(ii, jj);
+  };
+  const T xc = x(i, j);
+  if (!reg_hessian(reg)) {
+    l0 = i >= 1 ? xc - x(i - 1, j) : T(0);
+    l1 = j >= 1 ? xc - x(i, j - 1) : T(0);
+    l2 = T(0);
+    return 2;
+  }
+  l0 = cl(i - 1, j) - T(2) * xc + cl(i + 1, j);
+  l1 = cl(i, j - 1) - T(2) * xc + cl(i, j + 1);
+  l2 = T(0.25) * (cl(i + 1, j + 1) - cl(i + 1, j - 1) - cl(i - 1, j + 1) + cl(i - 1, j - 1));
+  return 3;
 }
 
 template <class T>
 __device__ __forceinline__ T lt_at(const T* q, int reg, int i, int j, int n1, int n2) {
   const size_t N = static_cast<size_t>(n1) * n2;
-  const size_t o = static_cast<size_t>(i) * n2 + j;
-  if (!reg_hessian(reg)) {
-    const T* q1 = q;
-    const T* q2 = q + N;
-    T v = 0;
-    if (i >= 1) v += q1[o];
-    if (i + 1 < n1) v -= q1[o + n2];
-    if (j >= 1) v += q2[o];
-    if (j + 1 < n2) v -= q2[o + 1];
-    return v;
-  }
-  const T* q11 = q;
-  const T* q22 = q + N;
-  const T* q12 = q + 2 * N;
-  T v = rep_adj(q11, i, j, -1, 0, n1, n2) - T(2) * q11[o] + rep_adj(q11, i, j, 1, 0, n1, n2);
-  v += rep_adj(q22, i, j, 0, -1, n1, n2) - T(2) * q22[o] + rep_adj(q22, i, j, 0, 1, n1, n2);
-  v += T(0.5) * (rep_adj(q12, i, j, 1, 1, n1, n2) - rep_adj(q12, i, j, 1, -1, n1, n2) -
-                 rep_adj(q12, i, j, -1, 1, n1, n2) + rep_adj(q12, i, j, -1, -1, n1, n2));
-  return v;
+  auto acc = [&](int c, int ii, int jj) { return q[c * N + static_cast<size_t>(ii) * n2 + jj]; };
+  return lt_with<T>(acc, reg, i, j, n1, n2);
 }
 
 template <class T>
@@ -116,21 +151,9 @@ __device__ __forceinline__ void dual_update_at(const T* __restrict__ x, T* __res
                                                int n2, T step, T beta) {
   const size_t N = static_cast<size_t>(n1) * n2;
   const size_t o = static_cast<size_t>(i) * n2 + j;
+  auto xa = [&](int ii, int jj) { return x[static_cast<size_t>(ii) * n2 + jj]; };
   T lx[3];
-  int nch;
-  if (!reg_hessian(reg)) {
-    T xc = x[o];
-    lx[0] = i >= 1 ? xc - x[o - n2] : T(0);
-    lx[1] = j >= 1 ? xc - x[o - 1] : T(0);
-    nch = 2;
-  } else {
-    T xc = x[o];
-    lx[0] = ldc(x, i - 1, j, n1, n2) - T(2) * xc + ldc(x, i + 1, j, n1, n2);
-    lx[1] = ldc(x, i, j - 1, n1, n2) - T(2) * xc + ldc(x, i, j + 1, n1, n2);
-    lx[2] = T(0.25) * (ldc(x, i + 1, j + 1, n1, n2) - ldc(x, i + 1, j - 1, n1, n2) -
-                       ldc(x, i - 1, j + 1, n1, n2) + ldc(x, i - 1, j - 1, n1, n2));
-    nch = 3;
-  }
+  const int nch = lx_with<T>(xa, reg, i, j, n1, n2, lx[0], lx[1], lx[2]);
   T v[3], qo[3];
   for (int c = 0; c < nch; ++c) {
     qo[c] = Q[c * N + o];
