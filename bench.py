@@ -571,7 +571,7 @@ def batch_sketch_traffic(wl, seed):
     counter summary, or None when the stencil source changed since it was
     taken or the workload differs."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "bstencil_batch64_hbm.json")
+    path = os.path.join(ROOT, "profiles", "bstream_batch64_hbm.json")
     src = os.path.join(ROOT, "paper_2411_08178_amd", "csrc", "batch.hip")
     if not os.path.exists(path):
         return None
@@ -756,6 +756,32 @@ def main_rate_sweep(args, P, torch, wl):
                       "power_iters": args.power_iters, "rows": rows}), flush=True)
 
 
+def sketch_burst(args, P, torch, wl):
+    """Inputs of the workload, then args.sketch_burst back-to-back sketch
+    launches bracketed by events (a profiler run's subject)."""
+    stream = torch.cuda.current_stream()
+    if wl.count > 1:
+        B = BatchSetup(P, torch, wl, args.seed)
+        plan = batch_plan(P, B, wl, True, 1, 1, False)
+        run, nbytes = plan.sketch_only, B.sketch_bytes
+    else:
+        S = Setup(P, torch, wl, args.seed)
+        run = lambda: P.nys_sketch(S.op, S.omega, out=S.Y)  # noqa: E731
+        nbytes = 2 * wl.ell * S.op.N * S.omega.element_size()
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.sketch_burst):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.sketch_burst
+    print(json.dumps({"workload": wl.name, "sketch_launches": args.sketch_burst + 1,
+                      "avg_sketch_us": round(ms * 1e3, 2), "bytes_per_launch": nbytes,
+                      "GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -783,6 +809,9 @@ def main():
                     help="a:b -- instances of the F* table to compute (--make-fstar)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--sketch-burst", type=int, default=0,
+                    help="only build the workload's inputs and run its sketch this many times "
+                         "(kernel traces and counters of the sketch kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -808,6 +837,8 @@ def main():
         return
 
     wl = W.workload(WORKLOAD_KEYS[args.workload])
+    if args.sketch_burst > 0:
+        return sketch_burst(args, P, torch, wl)
     if wl.count > 1:
         if args.make_fstar:
             return make_fstar(args, P, torch, wl)

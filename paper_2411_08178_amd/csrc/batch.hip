@@ -439,14 +439,32 @@ __device__ __forceinline__ void ss_item(const StTask& T, const StItem& I,
     if (m0 + s < M) step(s, m0 + s);
 }
 
+// Workgroups go to the eight XCDs in turn (block b to XCD b mod 8); chunks
+// of kSsChunk consecutive items are dealt to the XCDs in turn, so that each
+// XCD runs whole chunks -- neighbouring runs of a strip, whose windows
+// overlap -- back to back and serves the overlap from its own L2.
+constexpr int kSsChunk = 16;
+
+__device__ __forceinline__ int ss_item_of(int b) {
+  const int x = b & 7, j = b >> 3;
+  return ((j / kSsChunk) * 8 + x) * kSsChunk + j % kSsChunk;
+}
+
+inline int64_t ss_grid(int64_t nitems) {
+  const int64_t per = 8 * kSsChunk;
+  return (nitems + per - 1) / per * per;
+}
+
 // One workgroup (one wave) per item; items are sorted by tap count, largest
 // first, so the longest items start first.
 template <bool SUB>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
 void bstream_kernel(const StTask* __restrict__ tasks, const StItem* __restrict__ items,
-                    const float* __restrict__ taps) {
+                    const float* __restrict__ taps, int nitems) {
   __shared__ float buf[kSsBuf];
-  const StItem I = items[blockIdx.x];
+  const int it = ss_item_of(blockIdx.x);
+  if (it >= nitems) return;
+  const StItem I = items[it];
   const StTask T = tasks[I.task];
   switch (T.nt_r) {
     case 1: ss_item<1, SUB>(T, I, taps, buf); break;
@@ -808,11 +826,17 @@ void build_items(const std::vector<TaskSpec>& ts, std::vector<StItem>& items,
   sitems.clear();
   for (size_t i = 0; i < ts.size(); ++i) {
     const StTask& t = ts[i].t;
-    const bool ss = t.ss != 0;
-    for (int c = 0; c < ts[i].ncols; ++c)
-      for (int y0 = 0; y0 < t.n1; y0 += t.ty)
-        for (int x0 = 0; x0 < t.n2; x0 += ss ? kSsW : kStW)
-          (ss ? sitems : items).push_back({static_cast<int32_t>(i), c, y0, x0});
+    if (t.ss) {
+      // runs of a strip consecutive: a run's window overlaps the previous
+      // run's by NT - 1 rows
+      for (int c = 0; c < ts[i].ncols; ++c)
+        for (int x0 = 0; x0 < t.n2; x0 += kSsW)
+          for (int y0 = 0; y0 < t.n1; y0 += t.ty) sitems.push_back({static_cast<int32_t>(i), c, y0, x0});
+    } else {
+      for (int c = 0; c < ts[i].ncols; ++c)
+        for (int y0 = 0; y0 < t.n1; y0 += t.ty)
+          for (int x0 = 0; x0 < t.n2; x0 += kStW) items.push_back({static_cast<int32_t>(i), c, y0, x0});
+    }
   }
   std::stable_sort(sitems.begin(), sitems.end(), [&](const StItem& a, const StItem& b) {
     return ts[a.task].t.nt_r > ts[b.task].t.nt_r;
@@ -842,12 +866,13 @@ int stencil_grid(size_t lds) {
 
 nys_status stencil_launch(const nys_batch_s::St& s, const float* taps, int* ctr, hipStream_t st) {
   if (s.nsitems > 0) {
+    const dim3 grid(static_cast<unsigned>(ss_grid(s.nsitems)));
     if (s.sub)
-      hipLaunchKernelGGL(bstream_kernel<true>, dim3(static_cast<unsigned>(s.nsitems)), dim3(64), 0, st,
-                         s.tasks, s.sitems, taps);
+      hipLaunchKernelGGL(bstream_kernel<true>, grid, dim3(64), 0, st, s.tasks, s.sitems, taps,
+                         static_cast<int>(s.nsitems));
     else
-      hipLaunchKernelGGL(bstream_kernel<false>, dim3(static_cast<unsigned>(s.nsitems)), dim3(64), 0, st,
-                         s.tasks, s.sitems, taps);
+      hipLaunchKernelGGL(bstream_kernel<false>, grid, dim3(64), 0, st, s.tasks, s.sitems, taps,
+                         static_cast<int>(s.nsitems));
     NYS_TRY(launch_check("bstream_kernel"));
   }
   if (s.nitems == 0) return NYS_OK;
