@@ -343,51 +343,76 @@ def load_fstar(wl, seed, specs):
     return out if len(out) == len(specs) else None
 
 
+def cpu_model():
+    """The host CPU's model name and the CPUs this process may use."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
 def cpu_baseline_batch(wl, B, k_pc, power_iters, seed=0):
     """The FP64 oracle on a bounded sample of the batch (two instances of
-    different sizes), extrapolated per pixel to all instances (seconds)."""
-    from threadpoolctl import threadpool_info
+    different sizes), extrapolated per pixel to all instances (seconds); once
+    with every BLAS thread and once on one core."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import nystrom as onys
     from oracle import solver as sv
     sample = [s for s in B.specs if s.n == 256][:1] + [s for s in B.specs if s.n == 512][:1]
-    per_px = dict(sketch_col=[], factor_col=[], power=[], wapg=[])
-    for s in sample:
-        n = s.n
-        h = W.gaussian_psf(s.psf_k, s.psf_sigma)
-        prob = sv.Problem("blur", n, None, s.lam, "tv", h=h)
-        prob.y = prob.A(W.phantom_blocks(n, s.seed)) + wl.noise_sigma * W.gaussian((n, n), s.seed)
-        om = W.round_dtype(W.omega(s.ell, n, n, s.seed), "f32")
-        ncols = 8
-        t0 = time.perf_counter()
-        Y = np.stack([prob.phi(om[k]) for k in range(ncols)])
-        per_px["sketch_col"].append((time.perf_counter() - t0) / ncols / (n * n))
-        d = 0.01 + 0.24 * np.abs(W.gaussian((n * n,), seed, stream=8))
-        Yfull = d[None, :] * om.reshape(s.ell, -1)
-        t0 = time.perf_counter()
-        r = onys.nystrom(Yfull, om.reshape(s.ell, -1))
-        per_px["factor_col"].append((time.perf_counter() - t0) / (n * n * s.ell))
-        pc = sv.Precond(r["U"], r["shat"], r["nu"], "sqrt")
-        t0 = time.perf_counter()
-        sv.lipschitz(prob, pc, W.gaussian((n, n), s.seed, stream=7), 10)
-        per_px["power"].append((time.perf_counter() - t0) / 10 / (n * n))
-        it = 4
-        t0 = time.perf_counter()
-        sv.wapg(prob, pc, 0.5, it, inner=wl.inner, record_cost=False)
-        per_px["wapg"].append((time.perf_counter() - t0) / it / (n * n))
-        del Y
-    m = {k: float(np.mean(v)) for k, v in per_px.items()}
-    total = 0.0
-    for s in B.specs:
-        N = s.n * s.n
-        total += (m["sketch_col"] * N * s.ell + m["factor_col"] * N * s.ell +
-                  m["power"] * N * power_iters + m["wapg"] * N * k_pc)
+
+    def measure():
+        per_px = dict(sketch_col=[], factor_col=[], power=[], wapg=[])
+        for s in sample:
+            n = s.n
+            h = W.gaussian_psf(s.psf_k, s.psf_sigma)
+            prob = sv.Problem("blur", n, None, s.lam, "tv", h=h)
+            prob.y = prob.A(W.phantom_blocks(n, s.seed)) + wl.noise_sigma * W.gaussian((n, n), s.seed)
+            om = W.round_dtype(W.omega(s.ell, n, n, s.seed), "f32")
+            ncols = 8
+            t0 = time.perf_counter()
+            Y = np.stack([prob.phi(om[k]) for k in range(ncols)])
+            per_px["sketch_col"].append((time.perf_counter() - t0) / ncols / (n * n))
+            d = 0.01 + 0.24 * np.abs(W.gaussian((n * n,), seed, stream=8))
+            Yfull = d[None, :] * om.reshape(s.ell, -1)
+            t0 = time.perf_counter()
+            r = onys.nystrom(Yfull, om.reshape(s.ell, -1))
+            per_px["factor_col"].append((time.perf_counter() - t0) / (n * n * s.ell))
+            pc = sv.Precond(r["U"], r["shat"], r["nu"], "sqrt")
+            t0 = time.perf_counter()
+            sv.lipschitz(prob, pc, W.gaussian((n, n), s.seed, stream=7), 10)
+            per_px["power"].append((time.perf_counter() - t0) / 10 / (n * n))
+            it = 4
+            t0 = time.perf_counter()
+            sv.wapg(prob, pc, 0.5, it, inner=wl.inner, record_cost=False)
+            per_px["wapg"].append((time.perf_counter() - t0) / it / (n * n))
+            del Y
+        m = {k: float(np.mean(v)) for k, v in per_px.items()}
+        total = 0.0
+        for s in B.specs:
+            N = s.n * s.n
+            total += (m["sketch_col"] * N * s.ell + m["factor_col"] * N * s.ell +
+                      m["power"] * N * power_iters + m["wapg"] * N * k_pc)
+        return total, m
+
+    total, m = measure()
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    with threadpool_limits(limits=1):
+        total1, m1 = measure()
+    model, ncpu = cpu_model()
     desc = (f"oracle on instances n={[s.n for s in sample]}: 8 sketch columns, full Alg. 1 "
             f"factor, 10 power steps, 4 WAPG iterations each; per-pixel costs extrapolated to "
             f"all {len(B.specs)} instances ({k_pc} iterations); numpy/scipy FP64, "
             f"BLAS threads {threads}")
     return dict(value=total, unit="s", cores=threads, kind="oracle", sample=desc,
+                cpu_model=model, host_cpus=ncpu,
+                one_core={"value": total1, "cores": 1,
+                          "parts": {k + "_per_px_s": v for k, v in m1.items()}},
                 parts={k + "_per_px_s": v for k, v in m.items()})
 
 
@@ -756,6 +781,63 @@ def main_rate_sweep(args, P, torch, wl):
                       "power_iters": args.power_iters, "rows": rows}), flush=True)
 
 
+def main_ell_sweep(args, P, torch, wl):
+    """Time to the 1e-4 gap against the sketch size K (one JSON line): for
+    plain APG and each K, an untimed reference run of args.ref_iters
+    iterations, F* = the smallest cost of all of them, then a timed run of
+    exactly the iterations that reach the gap (sketch + factorisation + power
+    method + WAPG, as the headline metric times them)."""
+    S = Setup(P, torch, wl, args.seed)
+    S.tail = args.tail
+    n = wl.n
+    Ks = [0] + [int(k) for k in args.ell_sweep.split(",") if k]
+
+    def one(K, iters, record):
+        if K == 0:
+            return P.solve(S.op, S.y, S.rd, wl.lam, None, iters, power_v0=S.v0,
+                           power_iters=args.power_iters, loss=S.loss, delta=S.delta,
+                           record_cost=record)
+        om = torch.from_numpy(W.round_dtype(W.omega(K, n, n, args.seed), wl.sketch_dtype)) \
+            .to(S.sdt).cuda().contiguous()
+        Y = P.nys_sketch(S.op, om)
+        pc = P.nys_factor(om, Y, K, u_dtype=S.tdt, tail=args.tail)
+        return P.solve(S.op, S.y, S.rd, wl.lam, pc, iters, power_v0=S.v0,
+                       power_iters=args.power_iters, loss=S.loss, delta=S.delta,
+                       record_cost=record)
+
+    costs, Ls = {}, {}
+    for K in Ks:
+        t0 = time.perf_counter()
+        _, c, info = one(K, args.ref_iters, True)
+        torch.cuda.synchronize()
+        costs[K] = c.cpu().numpy()
+        Ls[K] = info["L"]
+        log(f"K={K}: reference {args.ref_iters} its in {time.perf_counter() - t0:.1f}s, "
+            f"end cost {costs[K][-1]:.10g}, L={Ls[K]:.6g}")
+    fstar = float(min(c.min() for c in costs.values()))
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for K in Ks:
+        k = first_below(costs[K], fstar, GAP)
+        row = {"K": K, "iters_to_gap": k, "L": Ls[K]}
+        if k is not None:
+            one(K, k, False)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            one(K, k, False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            row["time_to_gap_s"] = round(e0.elapsed_time(e1) / 1e3, 6)
+        else:
+            row["gap_after_reference"] = float((costs[K][-1] - fstar) / fstar)
+        rows.append(row)
+        log(f"K={K}: {row}")
+    print(json.dumps({"metric": "time to 1e-4 rel. cost gap vs sketch size (K = 0: plain APG)",
+                      "workload": wl.name, "tail": args.tail, "reference_iters": args.ref_iters,
+                      "fstar": fstar, "power_iters": args.power_iters, "rows": rows}), flush=True)
+
+
 def sketch_burst(args, P, torch, wl):
     """Inputs of the workload, then args.sketch_burst back-to-back sketch
     launches bracketed by events (a profiler run's subject)."""
@@ -792,6 +874,8 @@ def main():
     ap.add_argument("--power-iters", type=int, default=100)
     ap.add_argument("--rate-sweep", default="",
                     help="comma-separated sketch sizes: print the rate constant per size")
+    ap.add_argument("--ell-sweep", default="",
+                    help="comma-separated sketch sizes: print the time to the gap per size")
     ap.add_argument("--ref-iters", type=int, default=20000,
                     help="iterations of the untimed F* runs of both methods")
     ap.add_argument("--tail", default="sqrt", choices=["sqrt", "plain"],
@@ -849,6 +933,8 @@ def main():
         return main_irm(args, P, torch, wl)
     if args.rate_sweep:
         return main_rate_sweep(args, P, torch, wl)
+    if args.ell_sweep:
+        return main_ell_sweep(args, P, torch, wl)
     log(f"workload {wl.name}: n={wl.n} ell={wl.ell} sketch={wl.sketch_dtype} solver={wl.dtype}")
     S = Setup(P, torch, wl, args.seed)
     torch.cuda.synchronize()
