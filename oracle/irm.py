@@ -4,7 +4,7 @@ with the Nystrom preconditioner of Phi_k rebuilt at every outer iteration.
 
 Test infrastructure only.
 
-Problem (Sec. IV-A, component-wise form):
+Problem (Sec. III-A, component-wise form):
     min_x 1/p sum_m |(A x - y)_m|^p + lambda/q sum_l |(L x)_l|^q
 with L the first differences of the TV regulariser, every component its own
 group (the anisotropic l_1 norm for q = 1).  The half-quadratic identity
@@ -88,7 +88,7 @@ class IrmResult:
 def irm(A, At, y, lam, p, q, eps, x0, max_outer, outer_tol, cg_tol, cg_maxit,
         omega: Optional[np.ndarray] = None, tail: str = "plain", mu=None):
     """Alg. 2.  With `omega` (ell x n1 x n2) the x-update is PCG with the
-    Nystrom preconditioner of Phi_k (Alg. 1 on Y = Phi_k Omega, eq. (6)),
+    Nystrom preconditioner of Phi_k (Alg. 1 on Y = Phi_k Omega, eq. (11)),
     rebuilt at every outer iteration; without it, plain CG.  Every x-update
     starts from the previous iterate."""
     x = np.array(x0, np.float64, copy=True)

@@ -73,7 +73,7 @@ def tail_value(shat: np.ndarray, tail: str = "sqrt") -> float:
 
 def pinv_apply(v: np.ndarray, U: np.ndarray, shat: np.ndarray, mu: float,
                tail: str = "sqrt") -> np.ndarray:
-    """P^{-1} v = (s_K + mu) U (S + mu I)^{-1} U^T v + (I - U U^T) v, eq. (6).
+    """P^{-1} v = (s_K + mu) U (S + mu I)^{-1} U^T v + (I - U U^T) v, eq. (11).
 
     v may be a stack (..., N); U is (K, N) with orthonormal rows.
     """
@@ -84,7 +84,7 @@ def pinv_apply(v: np.ndarray, U: np.ndarray, shat: np.ndarray, mu: float,
 
 def p_apply(v: np.ndarray, U: np.ndarray, shat: np.ndarray, mu: float,
             tail: str = "sqrt") -> np.ndarray:
-    """P v = U (S + mu I) U^T v / (s_K + mu) + (I - U U^T) v, eq. (6)."""
+    """P v = U (S + mu I) U^T v / (s_K + mu) + (I - U U^T) v, eq. (11)."""
     sK = tail_value(shat, tail)
     c = v @ U.T
     return ((c * (shat + mu)) @ U) / (sK + mu) + v - c @ U

@@ -4,16 +4,16 @@ Test infrastructure only (see the package docstring).  Every operator acts on
 the last two axes, so a stack of images (..., n1, n2) is processed at once.
 
 Operators
-- periodic blur H and its adjoint (Sec. V-A; the PSF enters the definition as
+- periodic blur H and its adjoint (Sec. IV-A; the PSF enters the definition as
   a k x k array, centre (k-1)/2):
       (H x)[i, j]  = sum_{a,b} h[a, b] x[(i + c - a) mod n1, (j + c - b) mod n2]
       (H^T y)[i, j] = sum_{a,b} h[a, b] y[(i - c + a) mod n1, (j - c + b) mod n2]
-- blur + decimation A = S H, S keeps the samples (f i, f j) (Sec. V-A).
+- blur + decimation A = S H, S keeps the samples (f i, f j) (Sec. IV-A).
 - orthonormal Haar pyramid W (analysis) and W^T (synthesis), 'in place'
   coefficient layout: each level replaces the 2 x 2 groups of the current
   low-pass grid by (LL, HL; LH, HH) at the same positions; level l acts on the
   grid of stride 2^l.  The wavelet regulariser of Sec. III-B uses x = W^T xbar.
-- parallel-beam ray-driven (Joseph) projector and its transpose (Sec. V-B):
+- parallel-beam ray-driven (Joseph) projector and its transpose (Sec. IV-B):
   unit pixels centred at the origin, pixel (i, j) at (x, y) = (j - c, i - c)
   with c = (n - 1) / 2; bin b at s = b - (B - 1) / 2; view v at
   theta = v pi / V; the ray is {p : p . (cos t, sin t) = s}.  If

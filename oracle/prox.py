@@ -3,7 +3,7 @@
 Test infrastructure only.
 
 - `prox_mixed_dual`: the P-weighted prox of lambda_bar ||L x||_{1,phi} with
-  C = R^N, solved through its dual (eqs. (17)-(22)): accelerated projected
+  C = R^N, solved through its dual (eqs. (21)-(29)): accelerated projected
   gradient on the dual variable Q, x(Q) = s - lambda_bar P^{-1} L^T Q, dual
   gradient -2 lambda_bar L x(Q), step 1 / (2 lambda_bar^2 ||L||^2 ||P^{-1}||)
   (reading of the garbled Lipschitz constant: 2 lambda_bar^2 ||L P^{-1} L^T||
@@ -87,7 +87,7 @@ def project_l1_ball(w):
 
 
 def project_dual_ball(q, reg):
-    """Projection onto B_{inf,psi} (eq. (18)), 1/phi + 1/psi = 1.
+    """Projection onto B_{inf,psi} (eq. (23)), 1/phi + 1/psi = 1.
 
     'tv'      : each (q1, q2) onto the unit l2 ball
     'tv_aniso': each entry clipped to [-1, 1]
@@ -132,11 +132,11 @@ def prox_mixed_dual(s, lam_bar, reg, pinv, pinv_norm, n_inner, q0=None,
     pinv: callable v -> P^{-1} v (identity for the plain method).
     proj_c: None for C = R^N, else the P-weighted projection onto C
     (prox^P_{delta_C}, a callable z -> x): then x(Q) = proj_c(s - lam_bar
-    P^{-1} L^T Q) (eq. (21)), the dual gradient -2 lam_bar L x(Q) and the same
+    P^{-1} L^T Q) (eq. (26)), the dual gradient -2 lam_bar L x(Q) (eq. (28)) and the same
     step (prox^P_{delta_C} is nonexpansive in the P-norm, so the Lipschitz
     bound of the unconstrained case holds).
     Returns (x, Q).  The returned x is built from the last projected Q, not
-    from the extrapolated point (eq. (22)).
+    from the extrapolated point (eq. (29)).
     """
     xq = (lambda z: z) if proj_c is None else proj_c
     if lnorm2 is None:
@@ -178,7 +178,7 @@ def soft(z, t):
 
 def constrained_gap(x_of_q, Q, lam_bar, reg):
     """Primal minus dual value of the constrained WPM at Q, with x(Q) the
-    minimiser of the Lagrangian over C (eq. (20)): lam_bar (||L x||_{1,phi}
+    minimiser of the Lagrangian over C (eq. (26)): lam_bar (||L x||_{1,phi}
     - <Q, L x>), nonnegative for Q in the dual ball."""
     return lam_bar * (reg_value(x_of_q, reg) - ops.pair(Q, reg_L(x_of_q, reg), reg))
 

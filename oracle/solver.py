@@ -8,7 +8,7 @@ with the Huber reading h_delta(r) = r^2 / (2 delta) for |r| <= delta and
 |r| - delta / 2 otherwise (the super-resolution workload names a Huber data
 term; the paper's own super-resolution uses l_p data terms).  For the wavelet
 regulariser the unknown is xbar = W x, the operator is A W^T and
-g = ||xbar||_1 (all coefficients, as in eq. (23)).
+g = ||xbar||_1 (all coefficients, as in eq. (30)).
 """
 from __future__ import annotations
 
@@ -107,7 +107,7 @@ def sketch(problem: Problem, Omega: np.ndarray) -> np.ndarray:
 
 @dataclasses.dataclass
 class Precond:
-    """P from eq. (6) with s_K <- sqrt(s_K) optionally (Sec. III-B)."""
+    """P from eq. (11) with s_K <- sqrt(s_K) optionally (Sec. III-B)."""
     U: np.ndarray        # (K, N)
     shat: np.ndarray     # (K,)
     mu: float
@@ -135,7 +135,7 @@ class Precond:
 
 
 def build_precond(problem, Omega, nu_mode="spectral", tail="sqrt", mu=None):
-    """Sketch + Alg. 1 + eq. (6).  mu defaults to the shift nu (reading)."""
+    """Sketch + Alg. 1 + eq. (11).  mu defaults to the shift nu (reading)."""
     Y = sketch(problem, Omega).reshape(Omega.shape[0], -1)
     r = nys.nystrom(Y, Omega.reshape(Omega.shape[0], -1), nu_mode)
     mu = r["nu"] if mu is None else mu
@@ -143,7 +143,7 @@ def build_precond(problem, Omega, nu_mode="spectral", tail="sqrt", mu=None):
 
 
 def lipschitz(problem, pc: Optional[Precond], v0, iters):
-    """L_f^P = lambda_max(P^{-1} grad^2 f) bound by the power method (eq. (15))."""
+    """L_f^P = lambda_max(P^{-1} grad^2 f) bound by the power method (eq. (20))."""
     shp = v0.shape
     if pc is None:
         M = lambda v: problem.phi(v.reshape(shp)).reshape(-1)
@@ -154,7 +154,7 @@ def lipschitz(problem, pc: Optional[Precond], v0, iters):
 
 def rate_constant(problem, pc: Optional[Precond], x_star, v0, iters, x1=None):
     """L_f^P ||x^1 - x*||_P^2, the constant of the O(1/k^2) bound on WAPG's cost
-    gap (twice it over (k + 1)^2, stated after eq. (15), Sec. IV-B), whose
+    gap (twice it over (k + 1)^2, stated after eq. (20), Sec. III-B), whose
     dependence on the sketch size the CT experiments study.  x^1 is the start
     of Alg. 3 (zero unless given); L_f^P by the power method of `lipschitz`;
     P = I without a preconditioner."""

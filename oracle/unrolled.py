@@ -1,7 +1,7 @@
 """FP64 oracle of the unrolled WAPG map x_K(y, lambda) and its gradient.
 
 Test infrastructure only.  The forward is Alg. 3 with the P-weighted TV prox
-solved by dual accelerated projected gradient (eqs. (17)-(22)) for fixed
+solved by dual accelerated projected gradient (eqs. (21)-(29)) for fixed
 iteration counts, written with torch CPU tensors so that torch's reverse-mode
 chain rule supplies the reference gradient.  The linear pieces call the
 oracle's own operators (A, A^T from `operators`, P^{-1} from `nystrom`, L and

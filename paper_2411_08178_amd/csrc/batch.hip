@@ -1,10 +1,10 @@
 // Many periodic-blur reconstructions of different sizes solved together.
 //
 // Each instance solves eq. (4) with f = 1/2 ||h * x - y||^2 and a TV / HS1
-// prior by WAPG (Alg. 3) preconditioned with P of eq. (6), which is built
+// prior by WAPG (Alg. 3) preconditioned with P of eq. (11), which is built
 // from the sketch Y = A^T A Omega (Alg. 1, step 2) and the shifted Nystrom
 // factorisation (Alg. 1, steps 3-7); the step follows the power-method bound
-// of L_f^P (the constant of eq. (15)).  Every launch covers all instances:
+// of L_f^P (the constant of eq. (20)).  Every launch covers all instances:
 //   * A^T A of a periodic blur is the periodic correlation with the
 //     autocorrelation of the PSF, separable for a separable PSF.  One
 //     persistent kernel applies it (and H, H^T) to every (instance, column,

@@ -1,5 +1,5 @@
 // Shifted Nystrom factorisation (Alg. 1 steps 3-8) and the preconditioner of
-// eq. (6): Gram of [Omega Y], ell x ell FP64 algebra on one workgroup,
+// eq. (11): Gram of [Omega Y], ell x ell FP64 algebra on one workgroup,
 // U = Y_nu R in one pass, and P^{-1} / P applications.
 
 #include <algorithm>

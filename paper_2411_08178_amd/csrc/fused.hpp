@@ -1,5 +1,5 @@
 // One inner iteration of the P-weighted TV / Hessian-Schatten prox (the
-// accelerated dual gradient method of eqs. (24)-(29) with C = R^N) fused
+// accelerated dual gradient method of eqs. (21)-(29) with C = R^N) fused
 // into one pass over U.
 //
 // With P^{-1} = I + U diag(d) U^T (eq. (11)), the iteration on the dual pair

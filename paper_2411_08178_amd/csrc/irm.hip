@@ -5,7 +5,7 @@
 //   Phi_k x = A^T W_f y,   Phi_k = A^T W_f A + lambda L^T W_g L,
 // with W_f = diag(|A x - y|^{p-2}) and W_g = diag(|L x|^{q-2}) (|r| smoothed to
 // sqrt(r^2 + eps)), solved by conjugate gradients, or by PCG with the Nystrom
-// preconditioner of eq. (6) rebuilt from a sketch of Phi_k at every outer
+// preconditioner of eq. (11) rebuilt from a sketch of Phi_k at every outer
 // iteration (Alg. 1 on Y = Phi_k Omega).  Every x-update starts from the
 // previous iterate.
 //

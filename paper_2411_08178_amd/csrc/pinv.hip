@@ -1,4 +1,4 @@
-// Applications of the Nystrom preconditioner (eq. (6)) and the P-weighted l1
+// Applications of the Nystrom preconditioner (eq. (11)) and the P-weighted l1
 // prox of Thm. 1, the two places where the tall U (N x ell) is streamed.
 //
 // U is stored column by column with a padded pitch (pc->ldu >= N elements),
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void but_partial_kernel(const BDesc* __restric
   }
 }
 
-// One block per segment: D.cd[k] = d_k * sum_b D.part[b][k]  (d of eq. (6)).
+// One block per segment: D.cd[k] = d_k * sum_b D.part[b][k]  (d of eq. (11)).
 __global__ __launch_bounds__(1024) void but_tail_kernel(const BDesc* __restrict__ d,
                                                         const BSeg* __restrict__ seg) {
   __shared__ double red[1024];
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(1024) void but_tail_kernel(const BDesc* __restrict_
 
 // out = s + c (t + U cd) over the pixel chunk of a block, c = -scal[sidx]
 // (sidx >= 0) or 1; s = 0 when fs < 0; no U term without a preconditioner
-// (ell = 0).  P^{-1} t = t + U (d . U^T t) (eq. (6)).  N % 4 == 0.
+// (ell = 0).  P^{-1} t = t + U (d . U^T t) (eq. (11)).  N % 4 == 0.
 __global__ __launch_bounds__(256) void bcombine_kernel(const BDesc* __restrict__ d,
                                                        const BSeg* __restrict__ seg, int nseg,
                                                        int fs, int ft, int fout, int sidx) {
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(512) void ssn_eval_kernel(const T* __restrict__ U, 
 }
 
 // The first trial of a call whose prox centre is the preconditioned gradient
-// step s = u - alpha (g + U cd), cd = d . U^T g (eq. (6); FP32, ROWS <= 64),
+// step s = u - alpha (g + U cd), cd = d . U^T g (eq. (11); FP32, ROWS <= 64),
 // in one kernel: every block sums the ncb partials of U^T g (pitch ROWS, in a
 // fixed order) into alpha cd itself and takes the trial point from the warm
 // start gamma0 (zero if null); block 0 initialises the Newton state as

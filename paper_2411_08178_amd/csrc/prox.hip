@@ -1,7 +1,7 @@
 // P-weighted proximal maps (definition in Sec. I-D; C = R^N or a box).
 //
 // TV / TV_ANISO / Hessian Schatten kinds: accelerated projected gradient on the dual variable Q
-// (eqs. (17)-(22)): each inner iteration computes t = L^T R, applies P^{-1},
+// (eqs. (21)-(29)): each inner iteration computes t = L^T R, applies P^{-1},
 // forms x = s - lam_bar (P^{-1} t), and updates Q, R with the ball
 // projection and momentum.  L1: Thm. 1 with a semismooth Newton method whose
 // decisions (accept / backtrack / converge) are taken on the device.
@@ -117,7 +117,7 @@ __global__ void clip_kernel(T* __restrict__ x, T lo, T hi, int64_t N) {
   x[n] = fmin(hi, fmax(lo, x[n]));
 }
 
-// x <- prox^P_{delta_C}(x) for the box of reg (eq. (21)): the clip for P = I,
+// x <- prox^P_{delta_C}(x) for the box of reg (eq. (26)): the clip for P = I,
 // else Thm. 1's semismooth Newton with the clip, warm-started from gbox
 template <class T>
 static nys_status project_box(const nys_reg_desc& reg, nys_pc pc, T* x, double* gbox,

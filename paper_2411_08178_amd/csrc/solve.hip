@@ -1,4 +1,4 @@
-// WAPG (Alg. 3), its step size by the power method (eq. (15) constant), and
+// WAPG (Alg. 3), its step size by the power method (eq. (20) constant), and
 // the cost F = f + lambda g with FP64 accumulation.
 
 #include <cmath>
@@ -284,7 +284,7 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
                          static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
       NYS_TRY(launch_check("residual_kernel"));
     }
-    // cd = d . U^T grad (eq. (6)): partials of (A U)^T psi where A U is held,
+    // cd = d . U^T grad (eq. (11)): partials of (A U)^T psi where A U is held,
     // else of U^T grad
     CoefPartials cp;
     if (w.au) NYS_TRY(pc_partials_on<T>(pc, w.au, w.ldau, M, w.meas, 1, &cp, st));

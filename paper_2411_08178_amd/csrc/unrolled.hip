@@ -1,5 +1,5 @@
 // Unrolled WAPG (Alg. 3) with the P-weighted TV prox (dual FISTA, eqs.
-// (17)-(22)) for a fixed number of outer and inner iterations, and its exact
+// (21)-(29)) for a fixed number of outer and inner iterations, and its exact
 // reverse pass (vector-Jacobian products) with respect to the measurements y
 // and the regularisation weight lambda.
 //

@@ -29,7 +29,7 @@ def test_exact_recovery_of_low_rank_psd():
 
 
 def test_matches_nystrom_formula_on_well_conditioned_case():
-    # eq. (5): Phi<Omega> = (Phi Omega)(Omega^T Phi Omega)^+ (Phi Omega)^T
+    # eq. (9): Phi<Omega> = (Phi Omega)(Omega^T Phi Omega)^+ (Phi Omega)^T
     N, K = 50, 10
     ev = np.linspace(1.0, 2.0, N)
     Q, _ = np.linalg.qr(W.gaussian((N, N), 3))

@@ -1,5 +1,5 @@
 """Pins of the WAPG rate constant L_f^P ||x^1 - x*||_P^2 (`rate_constant`):
-its metric from eq. (6)'s P on the sketched subspace and off it, L_f^P of a
+its metric from eq. (11)'s P on the sketched subspace and off it, L_f^P of a
 periodic blur without a preconditioner (the top of |DFT(h)|^2) and with a
 full sketch (the closed spectrum of P^{-1} A^T A)."""
 import numpy as np
@@ -62,7 +62,7 @@ def test_metric_is_eq6_p_on_and_off_the_sketched_subspace():
 
 def test_full_sketch_constant_is_the_closed_spectrum():
     """K = N: the Nystrom approximation is A^T A itself, so P^{-1} A^T A has the
-    eigenvalues (s_min + mu) s_i / (s_i + mu) (eq. (6), plain tail) and L_f^P
+    eigenvalues (s_min + mu) s_i / (s_i + mu) (eq. (11), plain tail) and L_f^P
     is their largest."""
     n = 8
     prob, h = _blur(n, 3, 0.6)

@@ -7,7 +7,7 @@ storage precisions.  Measurements y = A x + noise are formed by whichever side
 consumes these inputs, with its own operator.
 
 The synthetic workloads stand in for the paper's natural test images, the AAPM
-CT slices and the walnut data (Sec. V), none of which is available; they keep
+CT slices and the walnut data (Sec. IV), none of which is available; they keep
 the shapes, value ranges and noise models the five benchmark workloads name.
 """
 from __future__ import annotations
@@ -32,7 +32,7 @@ def rng(seed: int, stream: int = 0) -> np.random.Generator:
 def gaussian_psf(k: int, sigma: float) -> np.ndarray:
     """k x k Gaussian point-spread function, centred at (k-1)/2, sum 1.
 
-    Sampled at integer offsets and truncated to the k x k support (Sec. V-A
+    Sampled at integer offsets and truncated to the k x k support (Sec. IV-A
     names only the size and the standard deviation).
     """
     if k < 1 or k % 2 == 0:
@@ -107,7 +107,7 @@ def gaussian(shape, seed: int, stream: int = 4) -> np.ndarray:
 
 def salt_pepper_masks(shape, seed: int, frac: float = 0.05):
     """Two disjoint index masks: `frac` of the entries set to 1, then another
-    `frac` of the remaining ones set to 0 (Sec. V-A footnote)."""
+    `frac` of the remaining ones set to 0 (Sec. IV-A footnote)."""
     g = rng(seed, 5)
     m = int(np.prod(shape))
     perm = g.permutation(m)
