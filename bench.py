@@ -591,18 +591,30 @@ def main_batch(args, P, torch, wl):
     print(json.dumps(out), flush=True)
 
 
+def code_digest(path):
+    """sha1 of a C++ source without its // comments and blank lines: changes
+    to the code (not to its comments) change it."""
+    import hashlib
+    import re
+    lines = []
+    for line in open(path, encoding="utf-8"):
+        code = re.sub(r"//.*$", "", line).rstrip()
+        if code:
+            lines.append(code)
+    return hashlib.sha1("\n".join(lines).encode()).hexdigest()
+
+
 def batch_sketch_traffic(wl, seed):
     """HBM bytes of one batched sketch launch from the committed rocprofv3
-    counter summary, or None when the stencil source changed since it was
-    taken or the workload differs."""
-    import hashlib
+    counter summary, or None when the stencil source's code changed since it
+    was taken or the workload differs."""
     path = os.path.join(ROOT, "profiles", "bstream_batch64_hbm.json")
     src = os.path.join(ROOT, "paper_2411_08178_amd", "csrc", "batch.hip")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("workload") != wl.name or d.get("seed") != seed or \
-            hashlib.sha1(open(src, "rb").read()).hexdigest() != d["source_sha1"]:
+            code_digest(src) != d.get("source_code_sha1"):
         return None
     return d["traffic_bytes_per_launch"]
 
