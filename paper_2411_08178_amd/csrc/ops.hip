@@ -392,6 +392,340 @@ __global__ __launch_bounds__(256) void joseph_adj_lds_kernel(
     Io<SO>::st(x, static_cast<size_t>(blockIdx.z) * n * n + static_cast<size_t>(i) * n + j, acc);
 }
 
+// ---------------------------------------------------------------- FP32 pair
+// Compute type FP32 with FP32 images.  Coordinates reach a few hundred, where
+// an FP32 value carries absolute rounding errors near 1e-5; here every
+// coordinate is instead split into an integer and a fraction.  The terms a
+// coordinate is built from -- one per ray and one per step in the forward,
+// one per view and pixel row in the adjoint -- are split in FP64, and only
+// fractions (or exactly representable multiples of 2^-12) are added in FP32,
+// so an interpolation weight is off by a few 1e-7 at any coordinate.
+// Staging is double-buffered with one barrier per stage: the 16-byte loads of
+// the next stage are issued before the current stage's samples are taken and
+// are stored to the other LDS buffer after them.  The per-row (per-view)
+// terms, window bases included, are built two stages ahead into a three-deep
+// table, so that the loads of the next stage read their bases from LDS.  A
+// 16-byte group of a row lies wholly inside or wholly outside the image
+// (window starts aligned to 4, row lengths multiples of 4), so it is loaded
+// or zero-filled whole.  The windows are sized so that every sample, its
+// coordinate rounded either way across an integer, lies inside: no index is
+// clamped.  The forward samples only the bins in the image's shadow, and on
+// few columns halves its steps between two workgroups.
+constexpr int kJfRows = 8;                                         // steps per stage
+constexpr int kJfSlots = (kJfRows * (kJosWin / 4) + 255) / 256;    // loads per thread per stage
+struct JosStep {
+  float frac;   // fraction of (t - c) g - base, in [0, 1)
+  int whole;    // its integer part plus the LDS offset of the step's window row
+  int base;     // first pixel of the window (multiple of 4)
+  int pad;
+};
+
+// Leftmost pixel any ray of the block may read on step t, less one pixel of
+// margin for a coordinate rounded down across an integer, aligned down to 4.
+__device__ __forceinline__ int jos_fwd_base(double lo0, double g, double c, int t) {
+  return (static_cast<int>(floor(lo0 + (t - c) * g)) - 1) & ~3;
+}
+__device__ __forceinline__ int jos_next3(int i) { return i == 2 ? 0 : i + 1; }
+// the largest float below 1: fractions rounded to FP32 stay below 1, so that
+// the sum of two stays below 2
+constexpr float kJosBelowOne = 0x1.fffffep-1f;
+
+template <class SO>
+__global__ __launch_bounds__(256) void joseph_fwd_f32_kernel(
+    const float* __restrict__ x, const float* __restrict__ xT, SO* __restrict__ p,
+    float* __restrict__ part, int n, int V, int B, const double* __restrict__ trig) {
+  __shared__ __align__(16) float win[2 * kJfRows * kJosWin];
+  __shared__ JosStep tab[3][kJfRows];
+  const int tid = threadIdx.x;
+  const int v = blockIdx.y;
+  const int bfirst = blockIdx.x * 256, blast = min(B - 1, bfirst + 255);
+  const int b = bfirst + tid;
+  const double ct = trig[2 * v], st = trig[2 * v + 1];
+  const bool rows = fabs(ct) >= fabs(st);
+  const double a = rows ? ct : st, bb = rows ? st : ct;
+  // blockIdx.z: column, or column and half of the steps on a split forward
+  const int split = part ? 2 : 1;
+  const int col = blockIdx.z / split, h = blockIdx.z - col * split;
+  const float* img = (rows ? x : xT) + static_cast<size_t>(col) * n * n;
+  const size_t orow = (static_cast<size_t>(col) * V + v) * B;
+  const double c = 0.5 * (n - 1), half = 0.5 * (B - 1);
+  const double ia = 1.0 / a;
+  const double g = -bb * ia;
+  // the bins of the block in the image's shadow (one bin of margin): a
+  // sample at centred position (f - c, t - c) with |f - c| < c + 1 and
+  // |t - c| <= c lies on rays with |s| < (c + 1)(|cos| + |sin|), so every
+  // other bin is exactly zero
+  const double shadow = (c + 1.0) * (fabs(ct) + fabs(st)) + 1.0;
+  const int bs0 = max(bfirst, static_cast<int>(floor(half - shadow)));
+  const int bs1 = min(blast, static_cast<int>(ceil(half + shadow)));
+  if (bs0 > bs1) {   // the block's bins all miss the image
+    if (b < B) {
+      if (part) part[static_cast<size_t>(h) * (gridDim.z / split) * V * B + orow + b] = 0.f;
+      else Io<SO>::st(p, orow + b, 0.f);
+    }
+    return;
+  }
+  // a wave samples only if some of its bins are in the shadow
+  const bool live = bfirst + (tid & ~63) <= bs1 && bfirst + (tid | 63) >= bs0;
+  const double fa0 = (bs0 - half) * ia + c, fb0 = (bs1 - half) * ia + c;
+  const double lo0 = fmin(fa0, fb0), hi0 = fmax(fa0, fb0);
+  int T0 = 0, T1 = n - 1;
+  if (g != 0.0) {
+    double ta = g > 0.0 ? (-1.0 - hi0) / g + c : (n - lo0) / g + c;
+    double tb = g > 0.0 ? (n - lo0) / g + c : (-1.0 - hi0) / g + c;
+    ta = fmin(fmax(ta, -2.0), n + 1.0);
+    tb = fmin(fmax(tb, -2.0), n + 1.0);
+    T0 = max(0, static_cast<int>(floor(ta)) - 1);
+    T1 = min(n - 1, static_cast<int>(ceil(tb)) + 1);
+  } else if (!(lo0 < n && hi0 >= -1.0)) {
+    T1 = -1;
+  }
+  if (part) {   // this block's half of the stages
+    const int nst = T0 <= T1 ? (T1 - T0 + kJfRows) / kJfRows : 0;
+    const int mid = T0 + (nst + 1) / 2 * kJfRows;
+    if (h == 0) T1 = min(T1, mid - 1);
+    else T0 = mid;
+  }
+  // window: pixels [floor(lo) - 1, floor(hi) + 2] of a step and up to 3 of
+  // alignment, floor(hi0 - lo0) + 8 at most (<= kJosWin for |a| >= 1/sqrt 2)
+  const int w4 = min(kJosWin / 4, (static_cast<int>(hi0 - lo0) + 11) / 4);
+  // the slots: (row, column) of each 16-byte load; (e + 1/2) / w4 is at least
+  // 1 / (2 w4) away from an integer, far beyond the FP32 product's error
+  const float inv_w4 = 1.0f / static_cast<float>(w4);
+  int sr[kJfSlots], sk[kJfSlots];
+#pragma unroll
+  for (int m = 0; m < kJfSlots; ++m) {
+    const int e = tid + 256 * m;
+    const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_w4);
+    sr[m] = r;
+    sk[m] = 4 * (e - r * w4);
+  }
+  // steps T .. T + kJfRows - 1 into table tb, window buffer wb
+  auto params = [&](int T, int tb, int wb) {
+    if (tid < kJfRows) {
+      const int t = T + tid;
+      const int base = jos_fwd_base(lo0, g, c, t);
+      const double d = (t - c) * g - base;
+      const double dw = floor(d);
+      tab[tb][tid] = JosStep{fminf(static_cast<float>(d - dw), kJosBelowOne),
+                             static_cast<int>(dw) + (wb * kJfRows + tid) * kJosWin, base, 0};
+    }
+  };
+  float4 q[kJfSlots];
+  auto load = [&](int T, int tb) {
+#pragma unroll
+    for (int m = 0; m < kJfSlots; ++m) {
+      const int t = T + sr[m];
+      q[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (sr[m] < kJfRows && t < n) {
+        const int col = tab[tb][sr[m]].base + sk[m];
+        if (col >= 0 && col < n)
+          q[m] = *reinterpret_cast<const float4*>(img + static_cast<size_t>(t) * n + col);
+      }
+    }
+  };
+  auto store = [&](int wb) {
+#pragma unroll
+    for (int m = 0; m < kJfSlots; ++m)
+      if (sr[m] < kJfRows)
+        *reinterpret_cast<float4*>(&win[(wb * kJfRows + sr[m]) * kJosWin + sk[m]]) = q[m];
+  };
+  // the ray's own offset f0 = (b - (B - 1) / 2) / a + c, split (lanes off
+  // the shadow take its nearest ray, which stays inside the windows)
+  const double f0 = (min(max(b, bs0), bs1) - half) * ia + c;
+  const double f0w = floor(f0);
+  const int F0 = static_cast<int>(f0w);
+  const float phi0 = fminf(static_cast<float>(f0 - f0w), kJosBelowOne);
+  float acc = 0.f;
+  if (T0 <= T1) {
+    params(T0, 0, 0);
+    params(T0 + kJfRows, 1, 1);
+    __syncthreads();
+    load(T0, 0);
+    store(0);
+    __syncthreads();
+    for (int T = T0, wb = 0, tb = 0;; T += kJfRows, wb ^= 1, tb = jos_next3(tb)) {
+      const int tn = jos_next3(tb);
+      const bool more = T + kJfRows <= T1;
+      if (more) load(T + kJfRows, tn);
+      if (live) {
+#pragma unroll
+      for (int r = 0; r < kJfRows; ++r) {
+        const JosStep e = tab[tb][r];
+        const float w = phi0 + e.frac;                     // in [0, 2)
+        const int k = F0 + e.whole + (w >= 1.f ? 1 : 0);   // LDS index of the left pixel
+        const float wf = __builtin_amdgcn_fractf(w);
+        const float a0 = win[k], a1 = win[k + 1];
+        acc += fmaf(wf, a1 - a0, a0);
+      }
+      }
+      if (more) {
+        store(wb ^ 1);
+        params(T + 2 * kJfRows, jos_next3(tn), wb);
+      }
+      __syncthreads();
+      if (!more) break;
+    }
+  }
+  if (b < B) {
+    const float val = b >= bs0 && b <= bs1 ? acc * static_cast<float>(1.0 / fabs(a)) : 0.f;
+    if (part) part[static_cast<size_t>(h) * (gridDim.z / split) * V * B + orow + b] = val;
+    else Io<SO>::st(p, orow + b, val);
+  }
+}
+
+// p = part[0] + part[1], the two halves of a split forward.
+template <class SO>
+__global__ __launch_bounds__(256) void joseph_fwd_join_kernel(const float* __restrict__ part,
+                                                              SO* __restrict__ p, size_t count) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < count) Io<SO>::st(p, i, part[i] + part[i + count]);
+}
+
+// A forward on few columns leaves the last round of workgroups mostly
+// idle; below this many workgroups its steps are split in two halves that
+// write FP32 partial sums, joined by a second pass.
+constexpr int64_t kJfSplitBelow = 3072;
+inline int64_t jos_fwd_blocks(int V, int B, int64_t ncols) {
+  return static_cast<int64_t>((B + 255) / 256) * V * ncols;
+}
+inline bool jos_fwd_split(int V, int B, int64_t ncols) {
+  return jos_fwd_blocks(V, B, ncols) < kJfSplitBelow;
+}
+// The most columns, up to ncols, of a split forward: a workspace sized for
+// ncols columns serves every call on fewer.
+inline int64_t jos_fwd_split_cols(int V, int B, int64_t ncols) {
+  return std::min<int64_t>(ncols, (kJfSplitBelow - 1) / jos_fwd_blocks(V, B, 1));
+}
+
+// Adjoint: a workgroup takes a 64 x 4 pixel tile (one wave per pixel row),
+// kJaViews views per stage.  Pixel (i, j) has bin coordinate
+// bc = (j - c) cos + (i - c) sin + (B - 1) / 2 on every view (either branch),
+// and with bc = K + phi (K integer, 0 <= phi < 1) only bins K and K + 1 lie
+// within |a| <= 1 of it, weighted (1 - phi / |a|) / |a| and
+// (1 - (1 - phi) / |a|) / |a| (clamped at 0).  Per view and pixel row the
+// FP64 coordinate of the row's first pixel relative to the window, plus the
+// LDS offset of the window row, is split as hi + lo with hi a multiple of
+// 2^-12 below 2^12, and cos as hi' + lo' likewise; then hi + dj hi' is exact
+// in FP32 (under 2^24 units of 2^-12), its integer part is the LDS index of
+// bin K, and its fraction plus lo + dj lo' (below 2^-7) is phi to a few 1e-7.
+constexpr int kJaViews = 24;                                        // views per stage
+constexpr int kJaSlots = (kJaViews * (kJosBins / 4) + 255) / 256;   // loads per thread per stage
+static_assert(2 * kJaViews * kJosBins + 128 < 4096, "LDS offsets must stay below 2^12");
+struct JosView {
+  float4 w;     // 1/|a|, 1/a^2, 1/|a| - 1/a^2, 0 (all zero on a padding view)
+  int base;     // first bin of the window (multiple of 4)
+};
+
+template <class SO>
+__global__ __launch_bounds__(256) void joseph_adj_f32_kernel(
+    const float* __restrict__ p, SO* __restrict__ x, int n, int V, int B,
+    const double* __restrict__ trig) {
+  __shared__ __align__(16) float win[2 * kJaViews * kJosBins];
+  __shared__ float4 tabs[3][kJaViews][4];   // per pixel row: hi, lo, cos hi', cos lo'
+  __shared__ JosView tabv[3][kJaViews];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.y * 4, j0 = blockIdx.x * 64;
+  const int dj = tid & 63, di = tid >> 6;
+  const int j = j0 + dj, i = i0 + di;
+  const float* sino = p + static_cast<size_t>(blockIdx.z) * V * B;
+  const double c = 0.5 * (n - 1), half = 0.5 * (B - 1);
+  const int nstage = (V + kJaViews - 1) / kJaViews;
+  // per-view terms of stage s (window buffer s & 1), by threads tid < kJaViews
+  auto params = [&](int s, int tb) {
+    if (tid < kJaViews) {
+      const int v = s * kJaViews + tid;
+      const int off = ((s & 1) * kJaViews + tid) * kJosBins;
+      if (v < V) {
+        const double ct = trig[2 * v], st = trig[2 * v + 1];
+        const double aa = fmax(fabs(ct), fabs(st)), ia = 1.0 / aa;
+        // lowest bin coordinate of the tile: at a corner
+        const double bcmin = fmin((j0 - c) * ct, (j0 + 63 - c) * ct) +
+                             fmin((i0 - c) * st, (i0 + 3 - c) * st) + half;
+        const int base = (static_cast<int>(floor(bcmin)) - 1) & ~3;
+        const double chi = nearbyint(ct * 4096.0) / 4096.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double s0 = (j0 - c) * ct + (i0 + r - c) * st + half - base + off;
+          const double shi = nearbyint(s0 * 4096.0) / 4096.0;
+          tabs[tb][tid][r] = make_float4(static_cast<float>(shi), static_cast<float>(s0 - shi),
+                                         static_cast<float>(chi), static_cast<float>(ct - chi));
+        }
+        tabv[tb][tid] = JosView{make_float4(static_cast<float>(ia), static_cast<float>(ia * ia),
+                                            static_cast<float>(ia - ia * ia), 0.f),
+                                base};
+      } else {
+        // a padding view reads the start of its own (zero) window row
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          tabs[tb][tid][r] = make_float4(static_cast<float>(off), 0.f, 0.f, 0.f);
+        tabv[tb][tid] = JosView{make_float4(0.f, 0.f, 0.f, 0.f), 0};
+      }
+    }
+  };
+  int sr[kJaSlots], sk[kJaSlots];
+#pragma unroll
+  for (int m = 0; m < kJaSlots; ++m) {
+    const int e = tid + 256 * m;
+    sr[m] = e / (kJosBins / 4);
+    sk[m] = 4 * (e - sr[m] * (kJosBins / 4));
+  }
+  float4 q[kJaSlots];
+  auto load = [&](int s, int tb) {
+#pragma unroll
+    for (int m = 0; m < kJaSlots; ++m) {
+      const int v = s * kJaViews + sr[m];
+      q[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (sr[m] < kJaViews && v < V) {
+        const int col = tabv[tb][sr[m]].base + sk[m];
+        if (col >= 0 && col < B)
+          q[m] = *reinterpret_cast<const float4*>(sino + static_cast<size_t>(v) * B + col);
+      }
+    }
+  };
+  auto store = [&](int wb) {
+#pragma unroll
+    for (int m = 0; m < kJaSlots; ++m)
+      if (sr[m] < kJaViews)
+        *reinterpret_cast<float4*>(&win[(wb * kJaViews + sr[m]) * kJosBins + sk[m]]) = q[m];
+  };
+  const float djf = static_cast<float>(dj);
+  float acc = 0.f;
+  params(0, 0);
+  params(1, 1);
+  __syncthreads();
+  load(0, 0);
+  store(0);
+  __syncthreads();
+  for (int s = 0, wb = 0, tb = 0;; ++s, wb ^= 1, tb = jos_next3(tb)) {
+    const int tn = jos_next3(tb);
+    const bool more = s + 1 < nstage;
+    if (more) load(s + 1, tn);
+#pragma unroll 8
+    for (int r = 0; r < kJaViews; ++r) {
+      const float4 sv = tabs[tb][r][di];
+      const float4 w = tabv[tb][r].w;
+      const float S = fmaf(djf, sv.z, sv.x);   // exact
+      const float fl = floorf(S);
+      float ph = (S - fl) + fmaf(djf, sv.w, sv.y);
+      const float f2 = floorf(ph);
+      ph -= f2;
+      const int k = static_cast<int>(fl + f2);   // LDS index of bin K
+      const float x0 = win[k], x1 = win[k + 1];
+      acc = fmaf(fmaxf(fmaf(-ph, w.y, w.x), 0.f), x0, acc);
+      acc = fmaf(fmaxf(fmaf(ph, w.y, w.z), 0.f), x1, acc);
+    }
+    if (more) {
+      store(wb ^ 1);
+      params(s + 2, jos_next3(tn));   // zeros past the last view
+    }
+    __syncthreads();
+    if (!more) break;
+  }
+  if (i < n && j < n)
+    Io<SO>::st(x, static_cast<size_t>(blockIdx.z) * n * n + static_cast<size_t>(i) * n + j, acc);
+}
+
 // ================================================================ launchers
 template <class C> const C* psf_ptr(const nys_op_s* op, bool flipped);
 template <> const double* psf_ptr<double>(const nys_op_s* op, bool flipped) {
@@ -777,9 +1111,28 @@ static nys_status launch_joseph_fwd(const nys_op_s* op, const SI* x, SO* p, int6
     // 16-byte row loads need 16-byte aligned rows of both images
     if (n % 4 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(xT) % 16 == 0) {
-      hipLaunchKernelGGL((joseph_fwd_lds_kernel<SI, SO, C, true>), grid, dim3(256), 0, st, x, xT,
-                         p, n, V, B, trig_ptr<double>(op));
-      return launch_check("joseph_fwd_lds_kernel");
+      if constexpr (std::is_same<C, float>::value) {
+        float* part = nullptr;
+        if (jos_fwd_split(V, B, ncols)) {
+          NYS_TAKE(op->scr, float, part, 2 * ncols * V * B);
+          grid.z *= 2;
+        }
+        hipLaunchKernelGGL((joseph_fwd_f32_kernel<SO>), grid, dim3(256), 0, st, x, xT, p, part, n,
+                           V, B, trig_ptr<double>(op));
+        NYS_TRY(launch_check("joseph_fwd_f32_kernel"));
+        if (part) {
+          const size_t count = static_cast<size_t>(ncols) * V * B;
+          hipLaunchKernelGGL((joseph_fwd_join_kernel<SO>),
+                             dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, st,
+                             part, p, count);
+          NYS_TRY(launch_check("joseph_fwd_join_kernel"));
+        }
+        return NYS_OK;
+      } else {
+        hipLaunchKernelGGL((joseph_fwd_lds_kernel<SI, SO, C, true>), grid, dim3(256), 0, st, x, xT,
+                           p, n, V, B, trig_ptr<double>(op));
+        return launch_check("joseph_fwd_lds_kernel");
+      }
     }
   }
   hipLaunchKernelGGL((joseph_fwd_lds_kernel<SI, SO, C, false>), grid, dim3(256), 0, st, x, xT, p,
@@ -794,9 +1147,15 @@ static nys_status launch_joseph_adj(const nys_op_s* op, const SI* p, SO* x, int6
   dim3 grid(cdiv(n, 64), cdiv(n, 4), static_cast<unsigned>(ncols));
   if constexpr (std::is_same<SI, float>::value) {
     if (B % 4 == 0 && reinterpret_cast<uintptr_t>(p) % 16 == 0) {
-      hipLaunchKernelGGL((joseph_adj_lds_kernel<SI, SO, C, true>), grid, dim3(256), 0, st, p, x, n,
-                         V, B, trig_ptr<double>(op), inva_ptr<double>(op));
-      return launch_check("joseph_adj_lds_kernel");
+      if constexpr (std::is_same<C, float>::value) {
+        hipLaunchKernelGGL((joseph_adj_f32_kernel<SO>), grid, dim3(256), 0, st, p, x, n, V, B,
+                           trig_ptr<double>(op));
+        return launch_check("joseph_adj_f32_kernel");
+      } else {
+        hipLaunchKernelGGL((joseph_adj_lds_kernel<SI, SO, C, true>), grid, dim3(256), 0, st, p, x, n,
+                           V, B, trig_ptr<double>(op), inva_ptr<double>(op));
+        return launch_check("joseph_adj_lds_kernel");
+      }
     }
   }
   hipLaunchKernelGGL((joseph_adj_lds_kernel<SI, SO, C, false>), grid, dim3(256), 0, st, p, x, n, V,
@@ -1401,7 +1760,13 @@ size_t op_ws_bytes(nys_op op, size_t es, int64_t ncols) {
   const bool wav = d.wavelet_levels > 0;
   size_t inner = 0;
   if (wav && d.wavelet == NYS_WAVELET_DB4) inner = img;
-  if (d.kind == NYS_OP_PARALLEL_BEAM) inner = img;
+  if (d.kind == NYS_OP_PARALLEL_BEAM) {
+    inner = img;
+    // FP32 partial sums of a split whole-view forward
+    if (es == 4)
+      inner += ws_round(2 * sizeof(float) * static_cast<size_t>(op->M) *
+                        jos_fwd_split_cols(d.n_views, d.n_bins, ncols));
+  }
   return (wav && d.kind != NYS_OP_IDENTITY ? img : 0) + inner;
 }
 
@@ -1416,7 +1781,13 @@ size_t sketch_ws_bytes(nys_op op, nys_dtype dt, int64_t ell) {
   const size_t db4_b = db4 ? ws_round(cs * nimg) * (ss == cs ? 1 : 2) : 0;
   if (d.kind == NYS_OP_IDENTITY) return wav ? ws_round(cs * nimg) + db4_b : 0;
   size_t inner = db4_b;
-  if (d.kind == NYS_OP_PARALLEL_BEAM) inner = std::max(inner, ws_round(std::max(ss, cs) * nimg));
+  if (d.kind == NYS_OP_PARALLEL_BEAM) {
+    inner = std::max(inner, ws_round(std::max(ss, cs) * nimg));
+    // FP32 partial sums of a split whole-view forward
+    if (cs == 4)
+      inner += ws_round(2 * sizeof(float) * static_cast<size_t>(op->M) *
+                        jos_fwd_split_cols(d.n_views, d.n_bins, ell));
+  }
   if (d.kind == NYS_OP_FAN_BEAM && ss != cs) inner = std::max(inner, ws_round(cs * nimg));
   return (wav ? ws_round(cs * nimg) : 0) +
          ws_round(cs * static_cast<size_t>(std::max(op->M, wav ? op->N : 0)) * ell) + inner;

@@ -164,6 +164,18 @@ def test_joseph_full_size_ct_f32():
     check(host(P.op_adjoint(op, q)), ops.joseph_adjoint(host(q), n), TOL["f32"])
 
 
+@pytest.mark.parametrize("n,V,B,cols", [(64, 90, 92, 36), (8, 10, 300, 1), (1004, 6, 1424, 1)])
+def test_joseph_forward_launch_forms_f32(n, V, B, cols):
+    """The FP32 forward without the split of its steps (enough workgroups to
+    fill the chip), with workgroups whose bins all miss the image (the
+    image's shadow is narrower than the detector), and on a large image."""
+    P = need_gpu()
+    banner(f"joseph forward forms f32 n={n} V={V} B={B} cols={cols}")
+    op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=V, bins=B)
+    xd = dev(W.gaussian((cols, n, n), 13), "f32")
+    check(host(P.op_forward(op, xd)), ops.joseph(host(xd), V, B), TOL["f32"])
+
+
 def test_sketch_ct_f32():
     P = need_gpu()
     banner("sketch CT f32")
