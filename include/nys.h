@@ -317,6 +317,42 @@ nys_status solve(const nys_problem* prob, nys_pc pc, nys_dtype dt,
                  double* info, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The same fixed-count solve (Alg. 3, opts->max_iter iterations) captured
+ * once as HIP graphs and replayed with no host work inside the loop: the
+ * start, a chunk of 16 iterations launched max_iter / 16 times, the remaining
+ * iterations and the final finite check, all enqueued by nys_solve_plan_run
+ * on the caller's stream.  Each iteration finds its momentum weight and cost
+ * slot through a device counter; the results are those of solve with the
+ * same arguments (the same kernels and step) for the TV / Hessian priors and
+ * for every prior without a preconditioner.  The P-weighted l1 prox (Thm. 1,
+ * FP32 with ell <= 64) runs a fixed sequence of semismooth Newton trials
+ * whose kernels skip themselves once the device state has converged: the
+ * first two trials of solve, then 2 rounds of a Newton step and a trial; a
+ * call that has not converged by then goes on from its last accepted point
+ * and sets the second int32 of ws to NYS_ENOCONV (solve allows max_newton
+ * trials instead).  The P-weighted box projection decides on the host and is
+ * EINVAL here.
+ * create: alpha <= 0 runs the power method on `stream` and synchronises; the
+ * plan keeps prob->y, x_out, costs (device, max_iter values, or NULL), ws
+ * (nys_workspace_size bytes) and pc by address: they must stay allocated and
+ * unmoved while the plan lives.  info (host, 8 doubles, may be NULL): [0]
+ * alpha, [1] L estimate.  The first int32 of ws is the status word of each
+ * run (NYS_ENOTFINITE when x_out holds a NaN or infinity at its end, or a
+ * Newton trial met one), the second NYS_ENOCONV as above.  With the l1 prior
+ * and a preconditioner whose Newton factors are not stored yet, create runs
+ * one iteration on `stream` first and synchronises.
+ * destroy: only once the runs have completed (synchronise their streams).
+ * Allocates the plan, its graphs and max_iter + 1 doubles of device memory.
+ * ------------------------------------------------------------------------- */
+typedef struct nys_solve_plan_s* nys_solve_plan;
+nys_status nys_solve_plan_create(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                                 const nys_solve_opts* opts, void* x_out, double* costs,
+                                 void* ws, size_t ws_bytes, void* stream, double* info,
+                                 nys_solve_plan* out);
+nys_status nys_solve_plan_run(nys_solve_plan plan, void* stream);
+void nys_solve_plan_destroy(nys_solve_plan plan);
+
+/* ---------------------------------------------------------------------------
  * Unrolled, differentiable WAPG (Alg. 3) with the P-weighted TV prox (dual
  * FISTA of eqs. (21)-(29), warm-started across outer iterations): a fixed
  * number n_outer of outer and n_inner of inner iterations, a fixed step

@@ -125,6 +125,9 @@ def lib():
             "solve": [C.POINTER(Problem), vp, i32, C.POINTER(SolveOpts), vp, vp,
                       C.POINTER(dbl), vp, C.c_size_t, vp],
             "nys_cost": [C.POINTER(Problem), i32, vp, vp, vp, C.c_size_t, vp],
+            "nys_solve_plan_create": [C.POINTER(Problem), vp, i32, C.POINTER(SolveOpts), vp, vp,
+                                      vp, C.c_size_t, vp, C.POINTER(dbl), C.POINTER(vp)],
+            "nys_solve_plan_run": [vp, vp],
             "nys_unrolled_workspace": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32,
                                        C.POINTER(C.c_size_t)],
             "unrolled_forward": [C.POINTER(Problem), vp, i32, C.POINTER(UnrollOpts), i32, vp,
@@ -154,6 +157,8 @@ def lib():
         L.nys_pc_destroy.restype = None
         L.batch_solve_destroy.argtypes = [vp]
         L.batch_solve_destroy.restype = None
+        L.nys_solve_plan_destroy.argtypes = [vp]
+        L.nys_solve_plan_destroy.restype = None
         L.nys_last_error.restype = C.c_char_p
         L.nys_version.restype = C.c_char_p
         _lib = L
@@ -424,6 +429,58 @@ def solve(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, pc: Optional[
     _check(lib().solve(C.byref(p), h, _dt(y), C.byref(o), _ptr(x), _ptr(costs), info, wp, wb,
                        _stream()))
     return x, costs, dict(alpha=info[0], L=info[1], status=int(info[2]))
+
+
+class SolvePlan:
+    """`solve` captured once as HIP graphs (nys_solve_plan_*): run() replays
+    the whole fixed-count iteration on the current stream with no host work
+    inside the loop, into the tensors x and costs it owns (like its inputs,
+    they keep their addresses while the plan lives)."""
+
+    def __init__(self, op: Operator, y: torch.Tensor, reg: RegDesc, lam: float,
+                 pc: Optional[Preconditioner], max_iter: int, alpha: float = -1.0,
+                 power_v0: Optional[torch.Tensor] = None, power_iters: int = 100,
+                 safety: float = 1.01, loss: int = LOSS_LS, delta: float = 0.0,
+                 warm_start: bool = True, record_cost: bool = True):
+        self.handle = None
+        self._keep = (op, y, pc, power_v0)
+        self._p = _problem(op, y, reg, lam, loss, delta)
+        o = SolveOpts(max_iter, alpha, safety, power_iters,
+                      power_v0.data_ptr() if power_v0 is not None else None,
+                      1 if warm_start else 0)
+        self.x = torch.empty((op.n1, op.n2), dtype=y.dtype, device=y.device)
+        self.costs = (torch.empty(max(max_iter, 1), dtype=torch.float64, device=y.device)
+                      if record_cost else None)
+        h = pc.handle if pc else None
+        self._ws, wp, wb = _workspace(lib().nys_workspace_size, C.byref(self._p), h, _dt(y))
+        self._ws_ptr = wp.value if wp is not None else 0
+        info = (C.c_double * 8)()
+        out = C.c_void_p()
+        _check(lib().nys_solve_plan_create(C.byref(self._p), h, _dt(y), C.byref(o), _ptr(self.x),
+                                           _ptr(self.costs), wp, wb, _stream(), info,
+                                           C.byref(out)))
+        self.handle = out.value
+        self.info = dict(alpha=info[0], L=info[1])
+
+    def run(self):
+        _check(lib().nys_solve_plan_run(self.handle, _stream()))
+        return self.x, self.costs
+
+    def status(self) -> int:
+        """The status of the last run (synchronises): the first device status
+        word (NYS_ENOTFINITE), else the second (NYS_ENOCONV: an l1 prox that
+        did not converge within its captured trials)."""
+        if self._ws is None:
+            return 0
+        off = self._ws_ptr - self._ws.data_ptr()
+        w = self._ws[off:off + 8].view(torch.int32).tolist()
+        return int(w[0] or w[1])
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize()
+            lib().nys_solve_plan_destroy(self.handle)
+            self.handle = None
 
 
 def nys_cost(op: Operator, y: torch.Tensor, reg: RegDesc, lam: float, x: torch.Tensor,

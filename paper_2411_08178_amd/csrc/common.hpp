@@ -223,6 +223,13 @@ struct nys_pc_s {
   // workspace is reallocated)
   bool ssn_lu_valid = false;
   bool ssn_lu_hint = false;   // the last decision read reported stored factors
+  // calls being captured into a graph: a fixed sequence of trials whose
+  // kernels skip themselves on the device state (no host decision), with
+  // ssn_slots Newton-and-trial rounds after the first two trials; the
+  // outcome goes to ssn_status[0] (NYS_ENOTFINITE) or [1] (NYS_ENOCONV)
+  bool ssn_device = false;
+  int ssn_slots = 2;
+  int32_t* ssn_status = nullptr;
 };
 
 namespace nys {

@@ -912,7 +912,8 @@ template <int NRG>
 __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
     const float* __restrict__ U, int64_t ldu, const float* __restrict__ s, int64_t N, int L,
     int64_t chunk, float lam, const double* __restrict__ state, double* __restrict__ part,
-    float* __restrict__ gpart, float* __restrict__ xo, int gsrc, int box, float lo, float hi) {
+    float* __restrict__ gpart, float* __restrict__ xo, int gsrc, int box, float lo, float hi,
+    int need_only) {
   constexpr int W = evg_waves<NRG>();
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   constexpr int ROWS = 32 * NRG;
@@ -923,7 +924,9 @@ __global__ __launch_bounds__(64 * evg_waves<NRG>()) void ssn_evalgram_kernel(
   __shared__ __align__(16) float dw[W][64];
   __shared__ __align__(16) float mw[W][64];
   __shared__ double udw[W][ROWS];
-  if (state[SsnState::kDone] != 0.0) return;
+  // skipped once the iteration has converged, and (need_only) unless the
+  // last decision asked for a Newton direction
+  if (state[SsnState::kDone] != 0.0 || (need_only && state[SsnState::kNeedGram] == 0.0)) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 31, lh = lane >> 5;
   for (int k = tid; k < ROWS; k += 64 * W) gs[k] = k < L ? static_cast<float>(state[gsrc + k]) : 0.f;
@@ -1059,13 +1062,18 @@ __global__ __launch_bounds__(1024) void ssn_decide_gram_kernel(
     const double* __restrict__ part, int nblk, int L, const double* __restrict__ meta,
     double* __restrict__ state, double tol, int max_halvings, unsigned long long* hflag,
     unsigned long long seq, double* gout,
-    const float* __restrict__ gpart, double* __restrict__ part2, int with_decide) {
+    const float* __restrict__ gpart, double* __restrict__ part2, int with_decide,
+    int need_only) {
   static_assert(kGramSets == 4, "four sets on the thread quarters of 1024");
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   if (with_decide && blockIdx.x == gridDim.x - 1) {
     ssn_decide_body(part, nblk, L, meta, state, tol, max_halvings, hflag, seq, gout);
     return;
   }
+  // a Newton step at the accepted point only: skipped as its Gram pass was
+  if (!with_decide && (state[SsnState::kDone] != 0.0 ||
+                       (need_only && state[SsnState::kNeedGram] == 0.0)))
+    return;
   const int e = blockIdx.x * 256 + (threadIdx.x & 255), q = threadIdx.x >> 8;
   if (e >= NTRI * 1024) return;
   const size_t stride = static_cast<size_t>(NTRI) * 1024;
@@ -1509,8 +1517,10 @@ __global__ __launch_bounds__(256) void ssn_final_kernel(const T* __restrict__ U,
                                                         const T* __restrict__ s,
                                                         const double* __restrict__ state,
                                                         int64_t N, int L, T lam, T* __restrict__ x,
-                                                        int box, T lo, T hi) {
+                                                        int box, T lo, T hi, int unfinished_only) {
   __shared__ T g[PcMeta::kMaxEll];
+  // (unfinished_only) the converged trial has written x already
+  if (unfinished_only && state[SsnState::kDone] != 0.0 && state[SsnState::kBad] == 0.0) return;
   for (int k = threadIdx.x; k < L; k += blockDim.x) g[k] = static_cast<T>(state[SsnState::kGamma + k]);
   __syncthreads();
   const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -1540,8 +1550,18 @@ __global__ void ssn_init_kernel(double* __restrict__ state, const double* __rest
   }
 }
 
-__global__ void ssn_store_gamma_kernel(const double* __restrict__ state, double* __restrict__ gamma, int L) {
+__global__ void ssn_store_gamma_kernel(const double* __restrict__ state, double* __restrict__ gamma, int L,
+                                       int unfinished_only) {
+  if (unfinished_only && state[SsnState::kDone] != 0.0) return;
   for (int k = threadIdx.x; k < L; k += blockDim.x) gamma[k] = state[SsnState::kGamma + k];
+}
+
+// The outcome of a device-decided call: a non-finite ||F|| (status[0] =
+// NYS_ENOTFINITE) or no convergence within its trials (status[1] = NYS_ENOCONV).
+__global__ void ssn_status_kernel(const double* __restrict__ state, int32_t* __restrict__ status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (state[SsnState::kBad] != 0.0) status[0] = NYS_ENOTFINITE;
+  else if (state[SsnState::kDone] == 0.0) status[1] = NYS_ENOCONV;
 }
 
 template <class T, int ROWS>
@@ -1628,7 +1648,8 @@ static nys_status launch_eval_step(nys_pc pc, const SsnStep& sp, const double* g
 template <int NRG>
 static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double* state,
                                    double* fpart, float* part, int nblk, int64_t chunk, double tol,
-                                   float* x, float* lu, hipStream_t st, bool newton_at_gamma = false) {
+                                   float* x, float* lu, hipStream_t st, bool newton_at_gamma = false,
+                                   bool need_only = false) {
   constexpr int NTRI = NRG * (NRG + 1) / 2;
   const int L = static_cast<int>(pc->ell);
   constexpr size_t elds = evg_lds_bytes<NRG>();
@@ -1638,22 +1659,23 @@ static nys_status launch_ssn_trial(nys_pc pc, const float* s, float lam, double*
   hipLaunchKernelGGL((ssn_evalgram_kernel<NRG>), dim3(nblk), dim3(64 * evg_waves<NRG>()), elds, st,
                      pc->U.as<float>(), pc->ldu, s, pc->N, L, chunk, lam, state, fpart, part, x,
                      static_cast<int>(newton_at_gamma ? SsnState::kGamma : SsnState::kTry),
-                     pc->ssn_box, static_cast<float>(pc->ssn_lo), static_cast<float>(pc->ssn_hi));
+                     pc->ssn_box, static_cast<float>(pc->ssn_lo), static_cast<float>(pc->ssn_hi),
+                     need_only ? 1 : 0);
   NYS_TRY(launch_check("ssn_evalgram_kernel"));
   double* part2 = reinterpret_cast<double*>(part + static_cast<size_t>(nblk) * NTRI * 1024);
   const int with_decide = newton_at_gamma ? 0 : 1;
   if (with_decide) ++pc->flag_seq;
   hipLaunchKernelGGL((ssn_decide_gram_kernel<NRG>), dim3(NTRI * 4 + with_decide), dim3(1024), 0, st,
                      fpart, nblk, L, pc->meta.as<double>(), state, tol, 30, pc->hflag, pc->flag_seq,
-                     pc->ssn_gout, part, part2, with_decide);
+                     pc->ssn_gout, part, part2, with_decide, need_only ? 1 : 0);
   NYS_TRY(launch_check("ssn_decide_gram_kernel"));
   const size_t lds = sizeof(double) * pc->ell * (pc->ell + 1);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&ssn_solve_kernel<NRG>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   hipLaunchKernelGGL((ssn_solve_kernel<NRG>), dim3(1), dim3(1024), lds, st, part2,
-                     static_cast<int>(pc->ell), pc->meta.as<double>(), state, newton_at_gamma ? 1 : 0,
-                     lu);
+                     static_cast<int>(pc->ell), pc->meta.as<double>(), state,
+                     newton_at_gamma && !need_only ? 1 : 0, lu);
   return launch_check("ssn_solve_kernel");
 }
 
@@ -1720,6 +1742,11 @@ struct SsnLayout {
 size_t ssn_ws_bytes(int64_t N, int L, size_t es) { return SsnLayout(N, L, es).bytes(); }
 
 template <class T>
+static bool xf_ok(const T* x, const T* s) {
+  return x != nullptr && static_cast<const void*>(x) != static_cast<const void*>(s);
+}
+
+template <class T>
 nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
                     double* gamma_state, hipStream_t st, int* trials_out, const SsnStep* step,
                     const SsnBox* box) {
@@ -1754,6 +1781,51 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   // With `step` there, the first trial also initialises the state and forms
   // the gradient step from the partials of U^T g; otherwise the step is
   // formed into s first.
+  if (pc->ssn_device) {
+    // A call being captured: the first two trials as below (the gradient
+    // step fused into the first, the chord step after its decision), then
+    // ssn_slots rounds of a Newton step at the accepted point and a trial
+    // there, every kernel skipping itself on the device state once the
+    // iteration has converged (the Newton step of a later round also unless
+    // the last decision asked for a direction).  The prox output is the
+    // converged trial's, else soft(s - U gamma) at the last accepted point.
+    NYS_REQUIRE(sizeof(T) == 4 && fp32_lu && have_lu && step != nullptr && xf_ok(x, s) && !box,
+                "ssn_prox: a captured call needs FP32 U with ell <= 64, stored factors, the "
+                "gradient step and x apart from s");
+    if constexpr (sizeof(T) == 4) {
+      pc->ssn_gout = gamma_state;
+      float* sw = reinterpret_cast<float*>(const_cast<T*>(s));
+      float* xw = reinterpret_cast<float*>(x);
+      const float lf = static_cast<float>(lam);
+      NYS_TRY(launch_eval_step(pc, *step, gamma_state, 1, sw, lf, state, part, nblk, chunk, tol,
+                               xw, lu, st));
+      NYS_TRY(launch_eval<float>(pc, sw, lf, state, nullptr, part, nblk, chunk, tol, st, xw));
+      for (int r = 0; r < pc->ssn_slots; ++r) {
+        float* gp = reinterpret_cast<float*>(gpart);
+        nys_status ts;
+        switch (nrg) {
+          case 1: ts = launch_ssn_trial<1>(pc, sw, lf, state, part, gp, ngb, gchunk, tol, nullptr, lu, st, true, r > 0); break;
+          default: ts = launch_ssn_trial<2>(pc, sw, lf, state, part, gp, ngb, gchunk, tol, nullptr, lu, st, true, r > 0); break;
+        }
+        NYS_TRY(ts);
+        NYS_TRY(launch_eval<float>(pc, sw, lf, state, nullptr, part, nblk, chunk, tol, st, xw));
+      }
+      hipLaunchKernelGGL((ssn_final_kernel<float>), dim3(cdiv(N, 256)), dim3(256), 0, st,
+                         pc->U.as<float>(), pc->ldu, sw, state, N, L, lf, xw, 0, 0.f, 0.f, 1);
+      NYS_TRY(launch_check("ssn_final_kernel"));
+      if (gamma_state) {
+        hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state,
+                           L, 1);
+        NYS_TRY(launch_check("ssn_store_gamma_kernel"));
+      }
+      if (pc->ssn_status) {
+        hipLaunchKernelGGL(ssn_status_kernel, dim3(1), dim3(64), 0, st, state, pc->ssn_status);
+        NYS_TRY(launch_check("ssn_status_kernel"));
+      }
+      pc->ssn_gout = nullptr;
+      return NYS_OK;
+    }
+  }
   const bool prelude = have_lu && pc->ssn_lu_hint && max_trials >= 2;
   const bool step_fused = sizeof(T) == 4 && prelude && step != nullptr;
   if (!step_fused) {
@@ -1858,12 +1930,12 @@ nys_status ssn_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   if (!(sizeof(T) == 4 && done && xf != nullptr)) {
     hipLaunchKernelGGL((ssn_final_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, pc->U.as<T>(),
                        pc->ldu, s, state, N, L, lam, x, pc->ssn_box, static_cast<T>(pc->ssn_lo),
-                       static_cast<T>(pc->ssn_hi));
+                       static_cast<T>(pc->ssn_hi), 0);
     NYS_TRY(launch_check("ssn_final_kernel"));
   }
   pc->ssn_gout = nullptr;
   if (gamma_state && !done) {   // the trials ran out: the last accepted point
-    hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L);
+    hipLaunchKernelGGL(ssn_store_gamma_kernel, dim3(1), dim3(128), 0, st, state, gamma_state, L, 0);
     NYS_TRY(launch_check("ssn_store_gamma_kernel"));
   }
   if (bad) {

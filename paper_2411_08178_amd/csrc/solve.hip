@@ -33,15 +33,23 @@ __global__ void step_kernel(const T* __restrict__ u, const T* __restrict__ g, T 
   s[n] = u[n] - alpha * g[n];
 }
 
-// u = x+ + beta (x+ - x);  x = x+
+// u = x+ + beta (x+ - x);  x = x+.  With betas given, beta is
+// betas[*ctr + j] (a graph replayed over the iterations).
 template <class T>
 __global__ void momentum_kernel(const T* __restrict__ xn, T* __restrict__ x, T* __restrict__ u,
-                                T beta, int64_t N) {
+                                T beta, int64_t N, const double* __restrict__ betas,
+                                const int32_t* __restrict__ ctr, int j) {
   const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (n >= N) return;
+  if (betas != nullptr) beta = static_cast<T>(betas[*ctr + j]);
   T a = xn[n];
   u[n] = a + beta * (a - x[n]);
   x[n] = a;
+}
+
+// *ctr = 0, or *ctr += step
+__global__ void counter_kernel(int32_t* ctr, int step, int reset) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *ctr = reset ? 0 : *ctr + step;
 }
 
 // status = NYS_ENOTFINITE when any of v[0:n] is NaN or infinite (the word
@@ -79,15 +87,23 @@ __global__ __launch_bounds__(256) void term_sum_kernel(const T* __restrict__ a, 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// out = w0 * sum(part0[0:n0]) + w1 * sum(part1[0:n1])
-__global__ void combine_kernel(const double* __restrict__ p0, int n0, double w0,
-                               const double* __restrict__ p1, int n1, double w1,
-                               double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out[0] = w0 * sum(part0[0:n0]) + w1 * sum(part1[0:n1]) on one wave (lane
+// sums over a fixed stride, then a fixed butterfly: the same order on every
+// call); with ctr given, out[*ctr + j] (a graph replayed over the iterations)
+__global__ __launch_bounds__(64) void combine_kernel(const double* __restrict__ p0, int n0,
+                                                     double w0, const double* __restrict__ p1,
+                                                     int n1, double w1, double* __restrict__ out,
+                                                     const int32_t* __restrict__ ctr, int j) {
+  const int l = threadIdx.x;
   double a = 0, b = 0;
-  for (int i = 0; i < n0; ++i) a += p0[i];
-  for (int i = 0; i < n1; ++i) b += p1[i];
-  *out = w0 * a + w1 * b;
+  for (int i = l; i < n0; i += 64) a += p0[i];
+  for (int i = l; i < n1; i += 64) b += p1[i];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  if (l == 0) out[ctr != nullptr ? *ctr + j : 0] = w0 * a + w1 * b;
 }
 
 // v = w / ||w||, norm[it] = ||w|| (power method, FP64 norm)
@@ -198,7 +214,7 @@ static int reg_term(const nys_reg_desc& r) {
 
 template <class T>
 static nys_status cost_impl(const nys_problem& p, const T* x, double* cost, T* meas, double* part,
-                            hipStream_t st) {
+                            hipStream_t st, const int32_t* ctr = nullptr, int j = 0) {
   nys_op op = p.op;
   NYS_TRY(op_fwd<T>(op, x, meas, 1, st));
   const int which = p.loss == NYS_LOSS_HUBER ? kHuber : kSq;
@@ -210,7 +226,7 @@ static nys_status cost_impl(const nys_problem& p, const T* x, double* cost, T* m
                      static_cast<T>(0), p.reg.n1, p.reg.n2, part + kRedBlocks);
   NYS_TRY(launch_check("term_sum_kernel"));
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, part, kRedBlocks, 1.0,
-                     part + kRedBlocks, kRedBlocks, p.lambda, cost);
+                     part + kRedBlocks, kRedBlocks, p.lambda, cost, ctr, j);
   return launch_check("combine_kernel");
 }
 
@@ -248,16 +264,14 @@ nys_status power_enqueue(const nys_problem& p, nys_pc pc, const T* v0, int iters
   return NYS_OK;
 }
 
-// WAPG outer iterations with a known step (no host synchronisation for the
-// TV / HS priors once pc->pinv_norm_cache is set).
+// WAPG start: x = u = 0, the prox state cleared, and A U formed when it is
+// held (the operator's rows of U, for the coefficients (A U)^T psi).
 template <class T>
-nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_iter,
-                        int warm_start, T* x, double* costs, void* wsb, hipStream_t st) {
-  SolveWs<T> w(p, pc, wsb);
+static nys_status wapg_setup(const nys_problem& p, nys_pc pc, T* x, const SolveWs<T>& w,
+                             hipStream_t st) {
   nys_op op = p.op;
   const int64_t N = op->N, M = op->M;
   const int nch = SolveWs<T>::nch(p.reg);
-  const double lam_bar = alpha * p.lambda;
   NYS_TRY(fill_zero<T>(x, N, st));
   NYS_TRY(fill_zero<T>(w.u, N, st));
   if (nch) NYS_TRY(fill_zero<T>(static_cast<T*>(w.state), static_cast<size_t>(nch) * N, st));
@@ -270,58 +284,103 @@ nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_i
     NYS_CHECK_HIP(hipMemcpy2DAsync(w.au, sizeof(T) * w.ldau, w.aucont, sizeof(T) * M, sizeof(T) * M,
                                    pc->ell_pad, hipMemcpyDeviceToDevice, st));
   }
-  const bool fwd_fused = op_fwd_fused_ok<T>(op);
+  return NYS_OK;
+}
+
+// Where a replayed iteration finds its momentum weight and cost slot:
+// betas[*ctr + j] and costs[*ctr + j] (null: beta and costs + k from the host).
+struct WapgIdx {
+  const double* betas = nullptr;
+  const int32_t* ctr = nullptr;
+  int j = 0;
+};
+
+// One WAPG iteration (Alg. 3): s = u - alpha P^{-1} grad f(u), x+ = prox^P(s),
+// the momentum step with weight beta, and F(x+) into cost when given.
+// Returns NYS_ENOCONV (and goes on) when a semismooth Newton prox ran out of
+// trial points.
+template <class T>
+static nys_status wapg_iter(const nys_problem& p, nys_pc pc, double alpha, int warm_start, T* x,
+                            const SolveWs<T>& w, double beta, double* cost, const WapgIdx& ix,
+                            hipStream_t st) {
+  nys_op op = p.op;
+  const int64_t N = op->N, M = op->M;
+  const double lam_bar = alpha * p.lambda;
+  Scratch::Mark mark(op->scr);   // this iteration's coefficient partials
+  nys_status conv = NYS_OK;
+  // s = u - alpha P^{-1} grad f(u), grad f(u) = A^T psi(A u - y)
+  if (op_fwd_fused_ok<T>(op)) {
+    NYS_TRY(op_fwd_psi<T>(op, w.u, static_cast<const T*>(p.y), p.loss, p.delta, w.meas, 1, st));
+  } else {
+    NYS_TRY(op_fwd<T>(op, w.u, w.meas, 1, st));
+    hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, w.meas,
+                       static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
+    NYS_TRY(launch_check("residual_kernel"));
+  }
+  // cd = d . U^T grad (eq. (11)): partials of (A U)^T psi where A U is held,
+  // else of U^T grad
+  CoefPartials cp;
+  if (w.au) NYS_TRY(pc_partials_on<T>(pc, w.au, w.ldau, M, w.meas, 1, &cp, st));
+  NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
+  if (pc && !w.au) NYS_TRY(pc_partials_on<T>(pc, pc->U.as<T>(), pc->ldu, N, w.g, 1, &cp, st));
+  if (pc && p.reg.kind == NYS_REG_L1) {
+    // the step s = u - alpha (grad + U cd) is formed inside the prox (by
+    // its first evaluation pass over U where possible)
+    const SsnStep sp{w.u, w.g, alpha, cp, w.part};
+    const nys_status ps = ssn_prox<T>(p.reg, lam_bar, pc, w.s, w.xn,
+                                      warm_start ? static_cast<double*>(w.state) : nullptr, st,
+                                      nullptr, &sp);
+    if (ps == NYS_ENOCONV) conv = ps;
+    else if (ps != NYS_OK) return ps;
+  } else if (pc) {
+    NYS_TRY(pc_tail(pc, true, cp, w.part, st));
+    NYS_TRY(pc_x_from_pinv<T>(pc, w.u, w.g, w.part, alpha, w.s, st));
+  } else {
+    hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
+                       static_cast<T>(alpha), N, w.s);
+    NYS_TRY(launch_check("step_kernel"));
+  }
+  // x+ = prox^P_{alpha lambda g}(s)
+  if (!(pc && p.reg.kind == NYS_REG_L1)) {
+    const nys_status ps = prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn,
+                                      warm_start ? w.state : nullptr, st, w.prox);
+    if (ps == NYS_ENOCONV) conv = ps;
+    else if (ps != NYS_OK) return ps;
+  }
+  hipLaunchKernelGGL((momentum_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.xn, x, w.u,
+                     static_cast<T>(beta), N, ix.betas, ix.ctr, ix.j);
+  NYS_TRY(launch_check("momentum_kernel"));
+  if (cost) NYS_TRY(cost_impl<T>(p, x, cost, w.meas, w.part, st, ix.ctr, ix.j));
+  return conv;
+}
+
+// The momentum weights of Alg. 3: t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2,
+// beta_k = (t_k - 1) / t_{k+1}.
+static std::vector<double> wapg_betas(int n) {
+  std::vector<double> b(std::max(n, 0));
   double t_prev = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
+    b[k] = (t_prev - 1.0) / t;
+    t_prev = t;
+  }
+  return b;
+}
+
+// WAPG outer iterations with a known step (no host synchronisation for the
+// TV / HS priors once pc->pinv_norm_cache is set).
+template <class T>
+nys_status wapg_enqueue(const nys_problem& p, nys_pc pc, double alpha, int max_iter,
+                        int warm_start, T* x, double* costs, void* wsb, hipStream_t st) {
+  SolveWs<T> w(p, pc, wsb);
+  NYS_TRY(wapg_setup<T>(p, pc, x, w, st));
+  const std::vector<double> betas = wapg_betas(max_iter);
   nys_status conv = NYS_OK;   // a prox that ran out of Newton trials (the solve goes on)
   for (int k = 0; k < max_iter; ++k) {
-    Scratch::Mark mark(op->scr);   // this iteration's coefficient partials
-    // s = u - alpha P^{-1} grad f(u), grad f(u) = A^T psi(A u - y)
-    if (fwd_fused) {
-      NYS_TRY(op_fwd_psi<T>(op, w.u, static_cast<const T*>(p.y), p.loss, p.delta, w.meas, 1, st));
-    } else {
-      NYS_TRY(op_fwd<T>(op, w.u, w.meas, 1, st));
-      hipLaunchKernelGGL((residual_kernel<T>), dim3(cdiv(M, 256)), dim3(256), 0, st, w.meas,
-                         static_cast<const T*>(p.y), M, p.loss, static_cast<T>(p.delta));
-      NYS_TRY(launch_check("residual_kernel"));
-    }
-    // cd = d . U^T grad (eq. (11)): partials of (A U)^T psi where A U is held,
-    // else of U^T grad
-    CoefPartials cp;
-    if (w.au) NYS_TRY(pc_partials_on<T>(pc, w.au, w.ldau, M, w.meas, 1, &cp, st));
-    NYS_TRY(op_adj<T>(op, w.meas, w.g, 1, st));
-    if (pc && !w.au) NYS_TRY(pc_partials_on<T>(pc, pc->U.as<T>(), pc->ldu, N, w.g, 1, &cp, st));
-    if (pc && p.reg.kind == NYS_REG_L1) {
-      // the step s = u - alpha (grad + U cd) is formed inside the prox (by
-      // its first evaluation pass over U where possible)
-      const SsnStep sp{w.u, w.g, alpha, cp, w.part};
-      const nys_status ps = ssn_prox<T>(p.reg, lam_bar, pc, w.s, w.xn,
-                                        warm_start ? static_cast<double*>(w.state) : nullptr, st,
-                                        nullptr, &sp);
-      if (ps == NYS_ENOCONV) conv = ps;
-      else if (ps != NYS_OK) return ps;
-    } else if (pc) {
-      NYS_TRY(pc_tail(pc, true, cp, w.part, st));
-      NYS_TRY(pc_x_from_pinv<T>(pc, w.u, w.g, w.part, alpha, w.s, st));
-    } else {
-      hipLaunchKernelGGL((step_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.u, w.g,
-                         static_cast<T>(alpha), N, w.s);
-      NYS_TRY(launch_check("step_kernel"));
-    }
-    // x+ = prox^P_{alpha lambda g}(s)
-    if (!(pc && p.reg.kind == NYS_REG_L1)) {
-      const nys_status ps = prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn,
-                                        warm_start ? w.state : nullptr, st, w.prox);
-      if (ps == NYS_ENOCONV) conv = ps;
-      else if (ps != NYS_OK) return ps;
-    }
-    // momentum
-    const double t = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t_prev * t_prev));
-    const double beta = (t_prev - 1.0) / t;
-    hipLaunchKernelGGL((momentum_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, w.xn, x, w.u,
-                       static_cast<T>(beta), N);
-    NYS_TRY(launch_check("momentum_kernel"));
-    t_prev = t;
-    if (costs) NYS_TRY(cost_impl<T>(p, x, costs + k, w.meas, w.part, st));
+    const nys_status s = wapg_iter<T>(p, pc, alpha, warm_start, x, w, betas[k],
+                                      costs ? costs + k : nullptr, WapgIdx{}, st);
+    if (s == NYS_ENOCONV) conv = s;
+    else if (s != NYS_OK) return s;
   }
   return conv;
 }
@@ -471,3 +530,199 @@ extern "C" nys_status nys_cost(const nys_problem* prob, nys_dtype dt, const void
   return cost_impl<float>(*prob, static_cast<const float*>(x), cost, reinterpret_cast<float*>(meas),
                           part, st);
 }
+
+// ================================================================ captured solve
+// A fixed-count WAPG solve as HIP graphs captured once: the start (status
+// word, x = u = 0, prox state, A U), a chunk of G iterations replayed
+// max_iter / G times, the remaining iterations, and the final finite check.
+// The replays find their momentum weight and cost slot through a device
+// counter that the chunk advances; the host only enqueues graph launches.
+struct nys_solve_plan_s {
+  hipStream_t cs = nullptr;             // the capturing stream (never run on)
+  hipGraph_t g[4] = {};                 // start, chunk, remainder, end
+  hipGraphExec_t e[4] = {};
+  int nchunk = 0;
+  double* dev = nullptr;                // betas (max_iter), then the counter
+  double alpha = 0, L = 0;
+  ~nys_solve_plan_s() {
+    for (int i = 0; i < 4; ++i) {
+      if (e[i]) (void)hipGraphExecDestroy(e[i]);
+      if (g[i]) (void)hipGraphDestroy(g[i]);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (dev) (void)hipFree(dev);
+  }
+};
+
+namespace nys {
+
+constexpr int kPlanChunk = 16;
+
+// Runs `body` under capture on plan->cs into graph slot i.
+template <class F>
+static nys_status plan_capture(nys_solve_plan_s* plan, int i, F&& body) {
+  NYS_CHECK_HIP(hipStreamBeginCapture(plan->cs, hipStreamCaptureModeThreadLocal));
+  const nys_status s = body(plan->cs);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(plan->cs, &g);
+  if (s != NYS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (ee != hipSuccess || !g) {
+    set_error("nys_solve_plan_create: capture failed: %s", hipGetErrorString(ee));
+    return NYS_EHIP;
+  }
+  plan->g[i] = g;
+  if (hipGraphInstantiate(&plan->e[i], g, nullptr, nullptr, 0) != hipSuccess) {
+    set_error("nys_solve_plan_create: hipGraphInstantiate failed");
+    return NYS_EHIP;
+  }
+  return NYS_OK;
+}
+
+template <class T>
+static nys_status plan_create_impl(const nys_problem& p, nys_pc pc, const nys_solve_opts& o,
+                                   T* x, double* costs, void* ws, size_t ws_bytes, hipStream_t st,
+                                   nys_solve_plan_s* plan) {
+  NYS_TRY(check_workspace(ws, ws_bytes, solve_call_ws_bytes<T>(p, pc), "nys_solve_plan_create"));
+  WsBind bind(ws, ws_bytes, p.op, pc);
+  int32_t* status = nullptr;
+  char* wsb = nullptr;
+  NYS_TAKE(&bind.s, int32_t, status, 64);
+  NYS_TAKE(&bind.s, char, wsb, SolveWs<T>::bytes(p, pc));
+  SolveWs<T> w(p, pc, wsb);
+  // the step, by the power method on the caller's stream when not given
+  double alpha = o.alpha;
+  if (!(alpha > 0)) {
+    NYS_REQUIRE(o.power_v0 && o.power_iters > 0,
+                "nys_solve_plan_create: power_v0 / power_iters needed when alpha <= 0");
+    NYS_TRY(power_enqueue<T>(p, pc, static_cast<const T*>(o.power_v0), o.power_iters, wsb, st));
+    double lam = 0;
+    NYS_CHECK_HIP(hipMemcpyAsync(&lam, w.norms, sizeof(double), hipMemcpyDeviceToHost, st));
+    NYS_CHECK_HIP(hipStreamSynchronize(st));
+    const double curv = p.loss == NYS_LOSS_HUBER ? 1.0 / p.delta : 1.0;
+    plan->L = curv * lam;
+    if (!(plan->L > 0 && std::isfinite(plan->L))) {
+      set_error("nys_solve_plan_create: the power method gave L = %g", plan->L);
+      return std::isfinite(plan->L) ? NYS_EINVAL : NYS_ENOTFINITE;
+    }
+    alpha = 1.0 / ((o.safety > 0 ? o.safety : 1.01) * plan->L);
+  }
+  plan->alpha = alpha;
+  // ||P^{-1}||, which the P-weighted dual prox reads on the host, once
+  if (pc && pc->pinv_norm_cache < 0) {
+    double hm[PcMeta::kTotal];
+    NYS_CHECK_HIP(hipMemcpyAsync(hm, pc->meta.p, sizeof hm, hipMemcpyDeviceToHost, st));
+    NYS_CHECK_HIP(hipStreamSynchronize(st));
+    pc->pinv_norm_cache = hm[PcMeta::kPinvNorm];
+  }
+  // the P-weighted l1 prox: its captured trials need stored Jacobian factors
+  // of this preconditioner, which one host-driven iteration leaves behind
+  const bool l1pc = pc && p.reg.kind == NYS_REG_L1;
+  if (l1pc && !pc->ssn_lu_valid) {
+    NYS_TRY(wapg_setup<T>(p, pc, x, w, st));
+    const nys_status s0 = wapg_iter<T>(p, pc, alpha, o.warm_start, x, w, 0.0, nullptr, WapgIdx{}, st);
+    if (s0 != NYS_OK && s0 != NYS_ENOCONV) return s0;
+    NYS_CHECK_HIP(hipStreamSynchronize(st));
+    NYS_REQUIRE(pc->ssn_lu_valid, "nys_solve_plan_create: no stored Newton factors");
+  }
+  struct SsnDeviceMode {   // the semismooth Newton calls of the capture decide on the device
+    nys_pc pc;
+    SsnDeviceMode(nys_pc q, int32_t* status) : pc(q) {
+      if (pc) { pc->ssn_device = true; pc->ssn_status = status; }
+    }
+    ~SsnDeviceMode() {
+      if (pc) { pc->ssn_device = false; pc->ssn_status = nullptr; }
+    }
+  } ssn_mode(l1pc ? pc : nullptr, status);
+  const int K = o.max_iter;
+  const std::vector<double> betas = wapg_betas(K);
+  NYS_CHECK_HIP(hipMalloc(&plan->dev, sizeof(double) * (K + 1)));
+  if (K > 0)
+    NYS_CHECK_HIP(hipMemcpy(plan->dev, betas.data(), sizeof(double) * K, hipMemcpyHostToDevice));
+  int32_t* ctr = reinterpret_cast<int32_t*>(plan->dev + K);
+  NYS_CHECK_HIP(hipStreamCreateWithFlags(&plan->cs, hipStreamNonBlocking));
+  const int G = std::min(kPlanChunk, std::max(K, 1));
+  plan->nchunk = K / G;
+  const int rem = K - plan->nchunk * G;
+  NYS_TRY(plan_capture(plan, 0, [&](hipStream_t cs) -> nys_status {
+    hipLaunchKernelGGL(status_clear_kernel, dim3(1), dim3(64), 0, cs, status);
+    NYS_TRY(launch_check("status_clear_kernel"));
+    NYS_TRY(wapg_setup<T>(p, pc, x, w, cs));
+    hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, cs, ctr, 0, 1);
+    return launch_check("counter_kernel");
+  }));
+  auto iters = [&](int count) {
+    return [&, count](hipStream_t cs) -> nys_status {
+      for (int j = 0; j < count; ++j)
+        NYS_TRY(wapg_iter<T>(p, pc, alpha, o.warm_start, x, w, 0.0, costs,
+                             WapgIdx{plan->dev, ctr, j}, cs));
+      hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, cs, ctr, count, 0);
+      return launch_check("counter_kernel");
+    };
+  };
+  if (plan->nchunk > 0) NYS_TRY(plan_capture(plan, 1, iters(G)));
+  if (rem > 0) NYS_TRY(plan_capture(plan, 2, iters(rem)));
+  NYS_TRY(plan_capture(plan, 3, [&](hipStream_t cs) -> nys_status {
+    hipLaunchKernelGGL((finite_check_kernel<T>),
+                       dim3(std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(p.op->N, 256)))),
+                       dim3(256), 0, cs, x, p.op->N, status);
+    return launch_check("finite_check_kernel");
+  }));
+  return NYS_OK;
+}
+
+}  // namespace nys
+
+extern "C" nys_status nys_solve_plan_create(const nys_problem* prob, nys_pc pc, nys_dtype dt,
+                                            const nys_solve_opts* opts, void* x_out,
+                                            double* costs, void* ws, size_t ws_bytes,
+                                            void* stream, double* info, nys_solve_plan* out) {
+  NYS_TRY(check_problem(prob, dt));
+  NYS_REQUIRE(opts && x_out && out && opts->max_iter >= 0, "nys_solve_plan_create: bad argument");
+  NYS_REQUIRE(prob->lambda > 0, "nys_solve_plan_create: lambda must be > 0");
+  if (pc) {
+    NYS_REQUIRE(pc->N == prob->op->N, "nys_solve_plan_create: pc size != number of unknowns");
+    NYS_REQUIRE(pc->u_dtype == static_cast<int32_t>(dt),
+                "nys_solve_plan_create: pc u_dtype != solver dtype");
+    NYS_REQUIRE(!prob->reg.box, "nys_solve_plan_create: the P-weighted box projection decides "
+                "on the host (semismooth Newton); use solve");
+    NYS_REQUIRE(prob->reg.kind != NYS_REG_L1 || (dt == NYS_F32 && pc->ell <= 64),
+                "nys_solve_plan_create: the P-weighted l1 prox is captured in FP32 with ell <= 64 "
+                "only; use solve");
+  }
+  *out = nullptr;
+  auto* plan = new nys_solve_plan_s;
+  const hipStream_t st = as_stream(stream);
+  const nys_status s =
+      dt == NYS_F64
+          ? plan_create_impl<double>(*prob, pc, *opts, static_cast<double*>(x_out), costs, ws,
+                                     ws_bytes, st, plan)
+          : plan_create_impl<float>(*prob, pc, *opts, static_cast<float*>(x_out), costs, ws,
+                                    ws_bytes, st, plan);
+  if (s != NYS_OK) {
+    delete plan;
+    return s;
+  }
+  if (info) {
+    info[0] = plan->alpha;
+    info[1] = plan->L;
+    info[2] = NYS_OK;
+    info[3] = 0;
+  }
+  *out = plan;
+  return NYS_OK;
+}
+
+extern "C" nys_status nys_solve_plan_run(nys_solve_plan plan, void* stream) {
+  NYS_REQUIRE(plan && plan->e[0] && plan->e[3], "nys_solve_plan_run: bad plan");
+  const hipStream_t st = as_stream(stream);
+  NYS_CHECK_HIP(hipGraphLaunch(plan->e[0], st));
+  for (int c = 0; c < plan->nchunk; ++c) NYS_CHECK_HIP(hipGraphLaunch(plan->e[1], st));
+  if (plan->e[2]) NYS_CHECK_HIP(hipGraphLaunch(plan->e[2], st));
+  NYS_CHECK_HIP(hipGraphLaunch(plan->e[3], st));
+  return NYS_OK;
+}
+
+extern "C" void nys_solve_plan_destroy(nys_solve_plan plan) { delete plan; }

@@ -1,0 +1,153 @@
+"""The captured fixed-count solve (nys_solve_plan_*): its replays give the
+results of `solve` with the same arguments bit for bit (the same kernels in
+the same order, the momentum weights and cost slots read through a device
+counter), and those results match the FP64 oracle of WAPG (Alg. 3)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import nystrom as onys
+from oracle import solver as sv
+from gpu_util import TOL, banner, check, dev, host, need_gpu, rel
+
+pytestmark = pytest.mark.gpu
+EINVAL = 1
+
+
+def _pc_for(P, prob, n, ell, dt, seed):
+    om = W.omega(ell, n, n, seed)
+    omd = dev(om, dt)
+    Yd = dev(sv.sketch(prob, host(omd)), dt)
+    ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+    pc = P.nys_factor(omd, Yd, ell, u_dtype=torch.float64 if dt == "f64" else torch.float32)
+    return opc, pc
+
+
+def _replays_match_solve(P, op, yd, rd, lam, pc, iters, alpha):
+    """Two plan runs with an eager solve between them, each against solve."""
+    plan = P.SolvePlan(op, yd, rd, lam, pc, iters, alpha=alpha)
+    x0, c0, info = P.solve(op, yd, rd, lam, pc, iters, alpha=alpha)
+    assert info["status"] == 0
+    for rep in range(2):
+        x, c = plan.run()
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        assert torch.equal(x, x0), f"replay {rep}: x differs from solve"
+        assert torch.equal(c, c0), f"replay {rep}: costs differ from solve"
+        if rep == 0:   # eager work on the same stream between the replays
+            P.solve(op, yd, rd, lam, pc, 3, alpha=alpha)
+    return host(x0), host(c0)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_plan_tv_deblur_with_preconditioner(dt):
+    """40^2 deblurring, TV, ell = 10, 37 iterations: two 16-iteration chunks
+    and a remainder of 5."""
+    P = need_gpu()
+    banner(f"solve plan TV deblur {dt}")
+    n, ell, iters = 40, 10, 37
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=2, n=n)
+    op = P.Operator(P.OP_BLUR, n, n, psf=prob.h)
+    yd = dev(prob.y, dt)
+    prob.y = host(yd)
+    opc, pc = _pc_for(P, prob, n, ell, dt, 20)
+    alpha = 0.9 / sv.lipschitz(prob, opc, W.gaussian((n, n), 21), 200)
+    rd = P.reg_desc("tv", n, n, n_inner=10)
+    x, c = _replays_match_solve(P, op, yd, rd, prob.lam, pc, iters, alpha)
+    xr, cr = sv.wapg(prob, opc, alpha, iters, inner=10)
+    check(x, xr, TOL[dt], what="x")
+    check(c, cr, TOL[dt], what="costs")
+
+
+def test_plan_ct_hs1_f32():
+    """32^2 parallel-beam CT (36 views, 48 bins), HS1, ell = 10, 20 iterations."""
+    P = need_gpu()
+    banner("solve plan CT HS1 f32")
+    wl = W.workload("ct512_hs1_f32")
+    prob, _ = sv.problem_from_workload(wl, seed=4, n=32, views=36, bins=48)
+    n, ell, iters = 32, 10, 20
+    op = P.Operator(P.OP_PARALLEL_BEAM, n, n, views=36, bins=48)
+    yd = dev(prob.y, "f32")
+    prob.y = host(yd)
+    opc, pc = _pc_for(P, prob, n, ell, "f32", 20)
+    alpha = 0.9 / sv.lipschitz(prob, opc, W.gaussian((n, n), 21), 200)
+    rd = P.reg_desc("hs1", n, n, n_inner=10)
+    x, c = _replays_match_solve(P, op, yd, rd, prob.lam, pc, iters, alpha)
+    xr, cr = sv.wapg(prob, opc, alpha, iters, inner=10)
+    check(x, xr, TOL["f32"], what="x")
+    check(c, cr, TOL["f32"], what="costs")
+
+
+def test_plan_plain_with_power_method():
+    """No preconditioner, the step from the power method at creation, 5
+    iterations (one chunk shorter than 16)."""
+    P = need_gpu()
+    banner("solve plan plain APG, power method")
+    n = 32
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=3, n=n)
+    op = P.Operator(P.OP_BLUR, n, n, psf=prob.h)
+    yd = dev(prob.y, "f32")
+    v0 = dev(W.gaussian((n, n), 9), "f32")
+    rd = P.reg_desc("tv", n, n, n_inner=8)
+    plan = P.SolvePlan(op, yd, rd, prob.lam, None, 5, power_v0=v0, power_iters=50)
+    x0, c0, info = P.solve(op, yd, rd, prob.lam, None, 5, power_v0=v0, power_iters=50)
+    assert plan.info["alpha"] == info["alpha"]
+    x, c = plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(x, x0) and torch.equal(c, c0)
+
+
+@pytest.mark.parametrize("n,ell,iters", [(64, 8, 20), (512, 64, 6)])
+def test_plan_l1_super_resolution_f32(n, ell, iters):
+    """The super-resolution problem (blur + 2x decimation, Haar-3, Huber, FP32)
+    with the P-weighted l1 prox: the captured semismooth Newton trials decide
+    on the device.  The plan's iterates against the oracle's FP64 ones; at
+    512^2, ell = 64 the launch configuration of the workload."""
+    P = need_gpu()
+    banner(f"solve plan l1 SR n={n} ell={ell} f32")
+    wl = W.workload("sr512_haar_bf16")
+    prob, _ = sv.problem_from_workload(wl, seed=3, n=n if n != 512 else None)
+    assert prob.n == n
+    op = P.Operator(P.OP_BLURDOWN, n, n, psf=prob.h, factor=2, wavelet_levels=3)
+    yd = dev(prob.y, "f32")
+    prob.y = host(yd)
+    om = W.omega(ell, n, n, 20)
+    Yref = sv.sketch(prob, om)
+    ref = onys.nystrom(Yref.reshape(ell, -1), om.reshape(ell, -1))
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+    pc = P.nys_factor(dev(om, "f32"), dev(Yref, "f32"), ell, u_dtype=torch.float32)
+    alpha = 0.9 / sv.lipschitz(prob, opc, W.gaussian((n, n), 21), 60)
+    rd = P.reg_desc("l1", n, n)
+    plan = P.SolvePlan(op, yd, rd, prob.lam, pc, iters, alpha=alpha, loss=P.LOSS_HUBER,
+                       delta=prob.delta)
+    xr, cr = sv.wapg(prob, opc, alpha, iters, ssn_tol=1e-10)
+    for rep in range(2):
+        x, c = plan.run()
+        torch.cuda.synchronize()
+        assert plan.status() == 0
+        ex, ec = rel(host(x), xr), np.max(np.abs(host(c) - cr) / np.abs(cr))
+        banner(f"plan l1 replay {rep}: x rel err {ex:.2e}, cost rel err {ec:.2e}")
+        assert ex < 2e-6 and ec < 1e-7    # the bounds of the host-driven solve's test
+        if rep == 0:
+            P.solve(op, yd, rd, prob.lam, pc, 2, alpha=alpha, loss=P.LOSS_HUBER, delta=prob.delta)
+
+
+def test_plan_refuses_the_weighted_box_projection():
+    """The P-weighted projection onto a box takes its semismooth Newton
+    decisions on the host: no plan for it."""
+    P = need_gpu()
+    banner("solve plan: box with P is EINVAL")
+    n, ell = 32, 6
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=2, n=n)
+    op = P.Operator(P.OP_BLUR, n, n, psf=prob.h)
+    yd = dev(prob.y, "f32")
+    _, pc = _pc_for(P, prob, n, ell, "f32", 5)
+    rd = P.reg_desc("tv", n, n, box=(0.0, 1.0))
+    with pytest.raises(P.NysError) as e:
+        P.SolvePlan(op, yd, rd, prob.lam, pc, 4, alpha=0.5)
+    assert e.value.status == EINVAL
