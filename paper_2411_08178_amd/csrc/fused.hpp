@@ -166,17 +166,19 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   __syncthreads();
   auto ra = [&](int c, int ii, int jj) { return L.r[c][(ii - ry0) * rw + (jj - rx0)]; };
   // (U c)_o: the first KR rows with every load issued before the sum, the
-  // rest in runs of 16
+  // rest in runs of 16.  Rows from ell on are U's zero padding: they are not
+  // loaded (a zero in their place gives the same sums).
+  const int ell = A.ell;
   auto uc = [&](int64_t o, float* v) {
 #pragma unroll
-    for (int k = 0; k < KR; ++k) v[k] = U[k * ldu + o];
+    for (int k = 0; k < KR; ++k) v[k] = k < ell ? U[k * ldu + o] : 0.f;
     float y = 0.f;
 #pragma unroll
     for (int k = 0; k < KR; ++k) y = fmaf(v[k], L.c[k], y);
     for (int k0 = KR; k0 < Lp; k0 += 16) {
       float w[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) w[j] = U[(k0 + j) * ldu + o];
+      for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + o] : 0.f;
 #pragma unroll
       for (int j = 0; j < 16; ++j) y = fmaf(w[j], L.c[k0 + j], y);
     }
@@ -261,7 +263,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   for (int k0 = KR; k0 < Lp; k0 += 16) {
     float w[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) w[j] = U[(k0 + j) * ldu + po] * tp;
+    for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + po] * tp : 0.f;
     int b2 = 0;
     using B2 = Bfly<16, 32>;
     B2::run(w, lane, b2);
