@@ -417,8 +417,9 @@ struct JosStep {
   float frac;   // fraction of (t - c) g - base, in [0, 1)
   int whole;    // its integer part plus the LDS offset of the step's window row
   int base;     // first pixel of the window (multiple of 4)
-  int pad;
+  int lbase;    // base for the loads: kJosNoRow past the image's last row
 };
+constexpr int kJosNoRow = -(1 << 29);   // makes every column of the row test as outside
 
 // Leftmost pixel any ray of the block may read on step t, less one pixel of
 // margin for a coordinate rounded down across an integer, aligned down to 4.
@@ -492,13 +493,17 @@ __global__ __launch_bounds__(256) void joseph_fwd_f32_kernel(
   // the slots: (row, column) of each 16-byte load; (e + 1/2) / w4 is at least
   // 1 / (2 w4) away from an integer, far beyond the FP32 product's error
   const float inv_w4 = 1.0f / static_cast<float>(w4);
-  int sr[kJfSlots], sk[kJfSlots];
+  // per slot: its row (kJfRows: idle), its column in the window, its row's
+  // offset in the image and its place in an LDS buffer
+  int sr[kJfSlots], sk[kJfSlots], srn[kJfSlots], sld[kJfSlots];
 #pragma unroll
   for (int m = 0; m < kJfSlots; ++m) {
     const int e = tid + 256 * m;
     const int r = static_cast<int>((static_cast<float>(e) + 0.5f) * inv_w4);
-    sr[m] = r;
+    sr[m] = min(r, kJfRows);
     sk[m] = 4 * (e - r * w4);
+    srn[m] = sr[m] * n;
+    sld[m] = sr[m] * kJosWin + sk[m];
   }
   // steps T .. T + kJfRows - 1 into table tb, window buffer wb
   auto params = [&](int T, int tb, int wb) {
@@ -508,27 +513,28 @@ __global__ __launch_bounds__(256) void joseph_fwd_f32_kernel(
       const double d = (t - c) * g - base;
       const double dw = floor(d);
       tab[tb][tid] = JosStep{fminf(static_cast<float>(d - dw), kJosBelowOne),
-                             static_cast<int>(dw) + (wb * kJfRows + tid) * kJosWin, base, 0};
+                             static_cast<int>(dw) + (wb * kJfRows + tid) * kJosWin, base,
+                             t < n ? base : kJosNoRow};
     }
   };
   float4 q[kJfSlots];
+  // one unsigned test per 16-byte group: a column outside [0, n) or a row
+  // past the image (its load base is kJosNoRow) reads zeros
   auto load = [&](int T, int tb) {
+    const int Tn = T * n;
 #pragma unroll
     for (int m = 0; m < kJfSlots; ++m) {
-      const int t = T + sr[m];
+      const int col = tab[tb][min(sr[m], kJfRows - 1)].lbase + sk[m];
       q[m] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (sr[m] < kJfRows && t < n) {
-        const int col = tab[tb][sr[m]].base + sk[m];
-        if (col >= 0 && col < n)
-          q[m] = *reinterpret_cast<const float4*>(img + static_cast<size_t>(t) * n + col);
-      }
+      if (sr[m] < kJfRows && static_cast<unsigned>(col) < static_cast<unsigned>(n))
+        q[m] = *reinterpret_cast<const float4*>(img + static_cast<unsigned>(Tn + srn[m] + col));
     }
   };
   auto store = [&](int wb) {
+    float* wbuf = win + wb * kJfRows * kJosWin;
 #pragma unroll
     for (int m = 0; m < kJfSlots; ++m)
-      if (sr[m] < kJfRows)
-        *reinterpret_cast<float4*>(&win[(wb * kJfRows + sr[m]) * kJosWin + sk[m]]) = q[m];
+      if (sr[m] < kJfRows) *reinterpret_cast<float4*>(wbuf + sld[m]) = q[m];
   };
   // the ray's own offset f0 = (b - (B - 1) / 2) / a + c, split (lanes off
   // the shadow take its nearest ray, which stays inside the windows)
