@@ -213,7 +213,9 @@ __device__ __forceinline__ void ut_rows_any(const float* __restrict__ U, int64_t
   if (k0 + 16 <= Lp) ut_rows_body<16>(U + k0 * ldu, ldu, v, n0, n1, red, bsum, dst + k0);
 }
 
-// Single preconditioner, FP32 U, N % 4 == 0: block (chunk, column).
+// Single preconditioner, FP32 U, N % 4 == 0: block (chunk, column), all
+// rows; or, with gridDim.z > 1 (short vectors, too few chunks to fill the
+// chip), block (chunk, column, group of 16 rows).
 __global__ __launch_bounds__(256) void ut_rows_kernel(const float* __restrict__ U, int64_t ldu,
                                                       const float* __restrict__ v, int64_t N,
                                                       int Lp, int64_t chunk,
@@ -223,8 +225,14 @@ __global__ __launch_bounds__(256) void ut_rows_kernel(const float* __restrict__ 
   const int nblk = gridDim.x, col = blockIdx.y;
   const int64_t n0 = static_cast<int64_t>(blockIdx.x) * chunk;
   const int64_t n1 = (n0 + chunk < N) ? n0 + chunk : N;
-  ut_rows_any(U, ldu, v + static_cast<size_t>(col) * N, Lp, n0, n1, red, bsum,
-              part + (static_cast<size_t>(col) * nblk + blockIdx.x) * Lp);
+  double* dst = part + (static_cast<size_t>(col) * nblk + blockIdx.x) * Lp;
+  if (gridDim.z > 1) {
+    const int k0 = 16 * blockIdx.z;
+    ut_rows_body<16>(U + k0 * ldu, ldu, v + static_cast<size_t>(col) * N, n0, n1, red, bsum,
+                     dst + k0);
+    return;
+  }
+  ut_rows_any(U, ldu, v + static_cast<size_t>(col) * N, Lp, n0, n1, red, bsum, dst);
 }
 
 // Block (256 threads) -> (instance, chunk): D.part[b][k] = sum U[k][n] v[n].
@@ -409,8 +417,10 @@ nys_status pc_partials_on(nys_pc pc, const T* B, int64_t ldb, int64_t len, const
   out->ncols = static_cast<int>(ncols);
   if constexpr (std::is_same<T, float>::value) {
     if ((len & 3) == 0 && (ldb & 3) == 0) {
-      hipLaunchKernelGGL(ut_rows_kernel, dim3(nblk, static_cast<unsigned>(ncols)), dim3(256), 0, st,
-                         B, ldb, v, len, Lp, chunk, part);
+      // fewer chunks than compute units: a block per group of 16 rows too
+      const unsigned groups = nblk * ncols < 256 ? static_cast<unsigned>(Lp / 16) : 1u;
+      hipLaunchKernelGGL(ut_rows_kernel, dim3(nblk, static_cast<unsigned>(ncols), groups),
+                         dim3(256), 0, st, B, ldb, v, len, Lp, chunk, part);
       return launch_check("ut_rows_kernel");
     }
   }
