@@ -151,3 +151,53 @@ def test_plan_refuses_the_weighted_box_projection():
     with pytest.raises(P.NysError) as e:
         P.SolvePlan(op, yd, rd, prob.lam, pc, 4, alpha=0.5)
     assert e.value.status == EINVAL
+
+
+def _sr_small(P, n=32, ell=8):
+    wl = W.workload("sr512_haar_bf16")
+    prob, _ = sv.problem_from_workload(wl, seed=3, n=n)
+    op = P.Operator(P.OP_BLURDOWN, n, n, psf=prob.h, factor=2, wavelet_levels=3)
+    om = dev(W.omega(ell, n, n, 20), "f32")
+    pc = P.nys_factor(om, P.nys_sketch(op, om), ell, u_dtype=torch.float32)
+    return prob, op, pc
+
+
+def test_plan_l1_reports_unconverged_newton_on_the_device():
+    """A Newton tolerance no trial can meet: every captured prox call runs out
+    of its trials, goes on from its last accepted point, and the run's second
+    status word says NYS_ENOCONV; the iterate stays finite."""
+    P = need_gpu()
+    banner("solve plan: l1 prox out of trials -> ENOCONV")
+    prob, op, pc = _sr_small(P)
+    rd = P.reg_desc("l1", prob.n, prob.n, newton_tol=1e-30)
+    plan = P.SolvePlan(op, dev(prob.y, "f32"), rd, prob.lam, pc, 3, alpha=0.01,
+                       loss=P.LOSS_LS)
+    x, _ = plan.run()
+    torch.cuda.synchronize()
+    assert plan.status() == 5          # NYS_ENOCONV
+    assert torch.isfinite(x).all()
+
+
+def test_plan_reports_non_finite_iterates():
+    """NaN in the measurements: the run's final check sets NYS_ENOTFINITE in
+    the first status word (the captured Newton trials meet a non-finite ||F||
+    and keep the warm start).  The clean plan is made first, so that the
+    preconditioner's Newton factors are stored before the NaN plan is
+    captured (its creation then runs no iteration on the host)."""
+    P = need_gpu()
+    banner("solve plan: NaN in y -> ENOTFINITE")
+    prob, op, pc = _sr_small(P)
+    rd = P.reg_desc("l1", prob.n, prob.n)
+    good = P.SolvePlan(op, dev(prob.y, "f32"), rd, prob.lam, pc, 3, alpha=0.01, loss=P.LOSS_LS)
+    x, _ = good.run()
+    torch.cuda.synchronize()
+    assert good.status() == 0 and torch.isfinite(x).all()
+    yd = dev(prob.y, "f32")
+    yd[2, 2] = float("nan")
+    bad = P.SolvePlan(op, yd, rd, prob.lam, pc, 3, alpha=0.01, loss=P.LOSS_LS)
+    bad.run()
+    torch.cuda.synchronize()
+    assert bad.status() == 4           # NYS_ENOTFINITE
+    x, _ = good.run()                  # the preconditioner is still usable
+    torch.cuda.synchronize()
+    assert good.status() == 0 and torch.isfinite(x).all()
