@@ -35,35 +35,41 @@ constexpr int kFKeep = 80;              // rows of U a thread keeps in registers
 // 41 % instead of 59 %).
 __host__ __device__ constexpr int fused_tw(bool hess) { return hess ? 32 : 64; }
 
-// One tile's operands (a single reconstruction or one instance of a batch).
-struct FusedArgs {
+// One tile's operands (a single reconstruction or one instance of a batch),
+// in the compute type T of U and the images (float or double).
+template <class T>
+struct FusedArgsT {
   int n1, n2, reg;
   int ell, ell_pad;
   int64_t ldu;
-  const float* U;                  // column-major, ell_pad rows, zero padded
+  const T* U;                      // column-major, ell_pad rows, zero padded
   const double* cd;                // c = d . U^T L^T R (ell values)
-  const float* s;                  // prox centre
-  const float* Qi;                 // duals read (nch channels, N apart)
-  const float* Ri;
-  float* Qo;                       // duals written (tile pixels only)
-  float* Ro;
-  float lam_bar, step, beta;
+  const T* s;                      // prox centre
+  const T* Qi;                     // duals read (nch channels, N apart)
+  const T* Ri;
+  T* Qo;                           // duals written (tile pixels only)
+  T* Ro;
+  T lam_bar, step, beta;
   int last;                        // partials of L^T Q+ instead of L^T R+
   double* part;                    // [tiles][ell_pad] block partials
 };
+using FusedArgs = FusedArgsT<float>;
 
 // LDS of a tile TW wide (regions for a ring of up to 2): R (ring 3), Q and
 // R+ (ring 1), x (ring 2)
-template <int TW>
+template <int TW, class T = float>
 struct FusedLds {
   static constexpr int TH = kFThreads / TW;
-  float r[3][(TH + 6) * (TW + 6)];
-  float q[3][(TH + 2) * (TW + 2)];
-  float x[(TH + 4) * (TW + 4)];
-  float p[3][(TH + 2) * (TW + 2)];
-  float c[PcMeta::kMaxEll];
+  T r[3][(TH + 6) * (TW + 6)];
+  T q[3][(TH + 2) * (TW + 2)];
+  T x[(TH + 4) * (TW + 4)];
+  T p[3][(TH + 2) * (TW + 2)];
+  T c[PcMeta::kMaxEll];
   double red[kFWaves][PcMeta::kMaxEll];
 };
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return fma(a, b, c); }
 
 // Butterfly reduce-scatter of CNT values over the lanes of a wave: at each
 // offset OFF (32, 16, ...) a lane keeps one half of its values, sends the
@@ -77,13 +83,14 @@ struct Bfly {
   static constexpr int kLeft = kHalve ? Bfly<CNT / 2, OFF / 2>::kLeft : CNT;
   // lanes below this mask hold duplicates of one another's sums
   static constexpr int kDupMask = kHalve ? Bfly<CNT / 2, OFF / 2>::kDupMask : (OFF * 2 - 1);
-  __device__ __forceinline__ static void run(float* v, int lane, int& base) {
+  template <class T>
+  __device__ __forceinline__ static void run(T* v, int lane, int& base) {
     if constexpr (kHalve) {
       const bool up = (lane & OFF) != 0;
 #pragma unroll
       for (int i = 0; i < CNT / 2; ++i) {
-        const float keep = up ? v[i + CNT / 2] : v[i];
-        const float send = up ? v[i] : v[i + CNT / 2];
+        const T keep = up ? v[i + CNT / 2] : v[i];
+        const T send = up ? v[i] : v[i + CNT / 2];
         v[i] = keep + __shfl_xor(send, OFF);
       }
       if (up) base += CNT / 2;
@@ -101,7 +108,8 @@ template <int CNT>
 struct Bfly<CNT, 0> {
   static constexpr int kLeft = CNT;
   static constexpr int kDupMask = 0;
-  __device__ __forceinline__ static void run(float*, int, int&) {}
+  template <class T>
+  __device__ __forceinline__ static void run(T*, int, int&) {}
 };
 
 // Pixel h (0 <= h < 2 hr (TW + 2 hr) + 2 hr TH) of the ring of hr pixels
@@ -124,8 +132,9 @@ __device__ __forceinline__ void fused_ring(int h, int hr, int& ey, int& ex) {
 
 // KR (a multiple of 16, <= min(ell_pad, kFKeep)) rows of U stay in registers;
 // rows KR .. ell_pad - 1 are read a second time for the partials.
-template <int KR, int TW>
-__device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx, FusedLds<TW>& L) {
+template <int KR, int TW, class T>
+__device__ __forceinline__ void fused_tile(const FusedArgsT<T>& A, int tile, int ntx,
+                                           FusedLds<TW, T>& L) {
   constexpr int kFW = TW, kFH = kFThreads / TW;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int n1 = A.n1, n2 = A.n2, reg = A.reg;
@@ -136,7 +145,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   const int ty0 = (tile / ntx) * kFH, tx0 = (tile % ntx) * kFW;
   const int Lp = A.ell_pad;
   const int64_t ldu = A.ldu;
-  const float* __restrict__ U = A.U;
+  const T* __restrict__ U = A.U;
   // region geometry: R (ring hr + 1), x (ring hr), duals (ring 1)
   const int rw = kFW + 2 * hr + 2, rh = kFH + 2 * hr + 2;
   const int ry0 = ty0 - hr - 1, rx0 = tx0 - hr - 1;
@@ -146,7 +155,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   const int dy0 = ty0 - 1, dx0 = tx0 - 1;
 
   // ---- c, R and Q into LDS
-  for (int k = t; k < Lp; k += kFThreads) L.c[k] = k < A.ell ? static_cast<float>(A.cd[k]) : 0.f;
+  for (int k = t; k < Lp; k += kFThreads) L.c[k] = k < A.ell ? static_cast<T>(A.cd[k]) : T(0);
   for (int r = t; r < rw * rh; r += kFThreads) {
     const int yy = r / rw, xx = r - yy * rw;
     const int gi = ry0 + yy, gj = rx0 + xx;
@@ -169,18 +178,18 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   // rest in runs of 16.  Rows from ell on are U's zero padding: they are not
   // loaded (a zero in their place gives the same sums).
   const int ell = A.ell;
-  auto uc = [&](int64_t o, float* v) {
+  auto uc = [&](int64_t o, T* v) {
 #pragma unroll
-    for (int k = 0; k < KR; ++k) v[k] = k < ell ? U[k * ldu + o] : 0.f;
-    float y = 0.f;
+    for (int k = 0; k < KR; ++k) v[k] = k < ell ? U[k * ldu + o] : T(0);
+    T y = 0;
 #pragma unroll
-    for (int k = 0; k < KR; ++k) y = fmaf(v[k], L.c[k], y);
+    for (int k = 0; k < KR; ++k) y = fma_t(v[k], L.c[k], y);
     for (int k0 = KR; k0 < Lp; k0 += 16) {
-      float w[16];
+      T w[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + o] : 0.f;
+      for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + o] : T(0);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) y = fmaf(w[j], L.c[k0 + j], y);
+      for (int j = 0; j < 16; ++j) y = fma_t(w[j], L.c[k0 + j], y);
     }
     return y;
   };
@@ -188,7 +197,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   // ---- x = s - lam_bar (L^T R + U c) on the ring of hr (first, so that
   // its loads do not hold registers next to the tile's kept rows) and the
   // tile
-  float u[KR];
+  T u[KR];
   const int nring = 2 * hr * xw + 2 * hr * kFH;
   for (int h = t; h < nring; h += kFThreads) {
     int ey, ex;
@@ -196,8 +205,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
     const int gi = xy0 + ey, gj = xx0 + ex;
     if (gi >= 0 && gi < n1 && gj >= 0 && gj < n2) {
       const int64_t o = static_cast<int64_t>(gi) * n2 + gj;
-      const float y = uc(o, u);
-      const float tr = lt_with<float>(ra, reg, gi, gj, n1, n2);
+      const T y = uc(o, u);
+      const T tr = lt_with<T>(ra, reg, gi, gj, n1, n2);
       L.x[ey * xw + ex] = A.s[o] - A.lam_bar * (tr + y);
     }
   }
@@ -206,9 +215,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   const bool pin = pi < n1 && pj < n2;
   const int64_t po = pin ? static_cast<int64_t>(pi) * n2 + pj : 0;
   {
-    const float y = uc(po, u);
+    const T y = uc(po, u);
     if (pin) {
-      const float tr = lt_with<float>(ra, reg, pi, pj, n1, n2);
+      const T tr = lt_with<T>(ra, reg, pi, pj, n1, n2);
       L.x[(iy + hr) * xw + ix + hr] = A.s[po] - A.lam_bar * (tr + y);
     }
   }
@@ -224,17 +233,17 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
     if (!hess && (yy == 0 || xx == 0)) continue;
     const int64_t o = static_cast<int64_t>(gi) * n2 + gj;
     const int rl = (gi - ry0) * rw + (gj - rx0);
-    float l0, l1, l2, v[3];
-    lx_with<float>(xa, reg, gi, gj, n1, n2, l0, l1, l2);
+    T l0, l1, l2, v[3];
+    lx_with<T>(xa, reg, gi, gj, n1, n2, l0, l1, l2);
     v[0] = L.r[0][rl] + A.step * l0;
     v[1] = L.r[1][rl] + A.step * l1;
-    v[2] = hess ? L.r[2][rl] + A.step * l2 : 0.f;
+    v[2] = hess ? L.r[2][rl] + A.step * l2 : T(0);
     project_group(reg, v);
     const bool own = yy >= 1 && yy <= kFH && xx >= 1 && xx <= kFW;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (c < nch) {
-        const float rn = v[c] + A.beta * (v[c] - L.q[c][r]);
+        const T rn = v[c] + A.beta * (v[c] - L.q[c][r]);
         L.p[c][r] = A.last ? v[c] : rn;
         if (own) {
           A.Qo[c * N + o] = v[c];
@@ -246,10 +255,10 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
   __syncthreads();
 
   // ---- (L^T R+)_p and the tile's partial of U^T L^T R+
-  float tp = 0.f;
+  T tp = 0;
   if (pin) {
     auto pa = [&](int c, int ii, int jj) { return L.p[c][(ii - dy0) * dw + (jj - dx0)]; };
-    tp = lt_with<float>(pa, reg, pi, pj, n1, n2);
+    tp = lt_with<T>(pa, reg, pi, pj, n1, n2);
   }
 #pragma unroll
   for (int k = 0; k < KR; ++k) u[k] *= tp;
@@ -261,9 +270,9 @@ __device__ __forceinline__ void fused_tile(const FusedArgs& A, int tile, int ntx
     for (int i = 0; i < B::kLeft; ++i) L.red[wave][base + i] = static_cast<double>(u[i]);
   }
   for (int k0 = KR; k0 < Lp; k0 += 16) {
-    float w[16];
+    T w[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + po] * tp : 0.f;
+    for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + po] * tp : T(0);
     int b2 = 0;
     using B2 = Bfly<16, 32>;
     B2::run(w, lane, b2);

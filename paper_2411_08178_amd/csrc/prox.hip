@@ -40,10 +40,20 @@ __global__ __launch_bounds__(256) void dual_update_kernel(const T* __restrict__ 
 }
 
 // One fused inner iteration over the tiles of one image (see fused.hpp).
+// FP32: static LDS; FP64: the same regions in dynamic LDS (over 64 KiB).
 template <int KR, int TW>
 __global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void dual_fused_kernel(FusedArgs A, int ntx, int ntiles) {
   __shared__ FusedLds<TW> L;
+  const int tile = fused_tile_of(blockIdx.x, ntiles);
+  if (tile >= ntiles) return;
+  fused_tile<KR, TW>(A, tile, ntx, L);
+}
+template <int KR, int TW>
+__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void dual_fused_f64_kernel(FusedArgsT<double> A, int ntx, int ntiles) {
+  extern __shared__ __align__(16) char fused_lds[];
+  auto& L = *reinterpret_cast<FusedLds<TW, double>*>(fused_lds);
   const int tile = fused_tile_of(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
   fused_tile<KR, TW>(A, tile, ntx, L);
@@ -69,6 +79,9 @@ __global__ __launch_bounds__(256) void x_from_dual_kernel(const T* __restrict__ 
 }
 
 static int fused_keep(int ell_pad) { return ell_pad < kFKeep ? ell_pad : kFKeep; }
+// FP64 values take two registers: 32 rows are kept on the Hessian tiles, 16
+// on the wider TV tiles (32 would spill there)
+template <int TW> constexpr int fused_keep64() { return TW == fused_tw(true) ? 32 : 16; }
 
 template <int TW>
 static nys_status fused_launch_tw(const FusedArgs& A, hipStream_t st) {
@@ -85,7 +98,30 @@ static nys_status fused_launch_tw(const FusedArgs& A, hipStream_t st) {
   return launch_check("dual_fused_kernel");
 }
 
-static nys_status fused_launch(const FusedArgs& A, hipStream_t st) {
+template <int TW, int KR>
+static nys_status fused_launch_f64_kr(const FusedArgsT<double>& A, dim3 grid, int ntx, int ntiles,
+                                      hipStream_t st) {
+  constexpr size_t lds = sizeof(FusedLds<TW, double>);
+  // the device allows up to 160 KiB per workgroup (a launch without the
+  // attribute fails and is reported by launch_check)
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dual_fused_f64_kernel<KR, TW>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  hipLaunchKernelGGL((dual_fused_f64_kernel<KR, TW>), grid, dim3(kFThreads), lds, st, A, ntx,
+                     ntiles);
+  return launch_check("dual_fused_f64_kernel");
+}
+
+template <int TW>
+static nys_status fused_launch_tw(const FusedArgsT<double>& A, hipStream_t st) {
+  const int ntx = cdiv(A.n2, TW), nty = cdiv(A.n1, kFThreads / TW);
+  const int ntiles = ntx * nty;
+  const dim3 grid(static_cast<unsigned>((ntiles + 7) / 8 * 8));
+  return A.ell_pad <= 16 ? fused_launch_f64_kr<TW, 16>(A, grid, ntx, ntiles, st)
+                         : fused_launch_f64_kr<TW, fused_keep64<TW>()>(A, grid, ntx, ntiles, st);
+}
+
+template <class T>
+static nys_status fused_launch(const FusedArgsT<T>& A, hipStream_t st) {
   return reg_hessian(A.reg) ? fused_launch_tw<fused_tw(true)>(A, st)
                             : fused_launch_tw<fused_tw(false)>(A, st);
 }
@@ -194,10 +230,10 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
 // caller's Q / the workspace R and the second buffers Q2 / R2; the first
 // iteration reads R = Q (the warm start), the last writes the partials of
 // L^T Q+ (the output uses Q, not R).  The final Q is left in the caller's Q.
+template <class T>
 static nys_status dual_prox_fused(const nys_reg_desc& reg, double lam_bar, nys_pc pc,
-                                  const float* s, float* x, float* Q, float* R, float* Q2,
-                                  float* R2, float* tbuf, double* cd, double* fpart,
-                                  hipStream_t st) {
+                                  const T* s, T* x, T* Q, T* R, T* Q2, T* R2, T* tbuf,
+                                  double* cd, double* fpart, hipStream_t st) {
   const int n1 = reg.n1, n2 = reg.n2;
   const int64_t N = static_cast<int64_t>(n1) * n2;
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
@@ -211,48 +247,48 @@ static nys_status dual_prox_fused(const nys_reg_desc& reg, double lam_bar, nys_p
   const double step = 1.0 / (lam_bar * lnorm2 * pc->pinv_norm_cache);
   const dim3 g2(cdiv(n2, 64), cdiv(n1, 4));
   // c of the warm start: d . U^T L^T Q
-  hipLaunchKernelGGL((lt_kernel<float>), g2, dim3(256), 0, st, Q, reg.kind, n1, n2,
-                     static_cast<const float*>(nullptr), 0.f, tbuf);
+  hipLaunchKernelGGL((lt_kernel<T>), g2, dim3(256), 0, st, Q, reg.kind, n1, n2,
+                     static_cast<const T*>(nullptr), T(0), tbuf);
   NYS_TRY(launch_check("lt_kernel"));
-  NYS_TRY(pc_coeffs<float>(pc, true, tbuf, 1, cd, st));
-  FusedArgs A{};
+  NYS_TRY(pc_coeffs<T>(pc, true, tbuf, 1, cd, st));
+  FusedArgsT<T> A{};
   A.n1 = n1;
   A.n2 = n2;
   A.reg = reg.kind;
   A.ell = static_cast<int>(pc->ell);
   A.ell_pad = static_cast<int>(pc->ell_pad);
   A.ldu = pc->ldu;
-  A.U = pc->U.as<float>();
+  A.U = pc->U.as<T>();
   A.cd = cd;
   A.s = s;
-  A.lam_bar = static_cast<float>(lam_bar);
-  A.step = static_cast<float>(step);
+  A.lam_bar = static_cast<T>(lam_bar);
+  A.step = static_cast<T>(step);
   A.part = fpart;
   const CoefPartials cp{fpart, static_cast<int>(fused_tiles(n1, n2, reg.kind)), 1};
-  float* qbuf[2] = {Q, Q2};
-  float* rbuf[2] = {R, R2};
-  const float* qcur = Q;
-  const float* rcur = Q;             // R = Q at the start
+  T* qbuf[2] = {Q, Q2};
+  T* rbuf[2] = {R, R2};
+  const T* qcur = Q;
+  const T* rcur = Q;                 // R = Q at the start
   double tau = 1.0;
   for (int it = 0; it < reg.n_inner; ++it) {
     const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
-    A.beta = static_cast<float>((tau - 1.0) / tau_n);
+    A.beta = static_cast<T>((tau - 1.0) / tau_n);
     A.Qi = qcur;
     A.Ri = rcur;
     A.Qo = qbuf[(it + 1) & 1];
     A.Ro = rbuf[it & 1];
     A.last = it == reg.n_inner - 1;
-    NYS_TRY(fused_launch(A, st));
+    NYS_TRY(fused_launch<T>(A, st));
     NYS_TRY(pc_tail(pc, true, cp, cd, st));
     qcur = A.Qo;
     rcur = A.Ro;
     tau = tau_n;
   }
   if (qcur != Q)
-    NYS_CHECK_HIP(hipMemcpyAsync(Q, qcur, sizeof(float) * nch * N, hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL((x_from_dual_kernel<float>), dim3(cdiv(N, 256)), dim3(256), 0, st, s, Q,
-                     reg.kind, n1, n2, pc->U.as<float>(), pc->ldu, cd, static_cast<int>(pc->ell),
-                     static_cast<float>(lam_bar), x);
+    NYS_CHECK_HIP(hipMemcpyAsync(Q, qcur, sizeof(T) * nch * N, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL((x_from_dual_kernel<T>), dim3(cdiv(N, 256)), dim3(256), 0, st, s, Q,
+                     reg.kind, n1, n2, pc->U.as<T>(), pc->ldu, cd, static_cast<int>(pc->ell),
+                     static_cast<T>(lam_bar), x);
   return launch_check("x_from_dual_kernel");
 }
 
@@ -265,16 +301,15 @@ __global__ void soft_kernel(const T* __restrict__ s, T lam, int64_t N, T* __rest
   x[n] = ar > lam ? (r > 0 ? r - lam : r + lam) : T(0);
 }
 
-// [cd, gbox: kMaxEll doubles each | R | Q (when no state) | t | FP32 only:
-//  Q', R' (the fused iteration's second buffers) | block partials]
+// [cd, gbox: kMaxEll doubles each | R | Q (when no state) | t | Q', R' (the
+//  fused iteration's second buffers) | block partials]
 template <class T>
 size_t prox_ws_bytes(const nys_reg_desc& reg) {
   const size_t N = static_cast<size_t>(reg.n1) * reg.n2;
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
   size_t b = sizeof(double) * 2 * PcMeta::kMaxEll + sizeof(T) * (static_cast<size_t>(nch) * N * 2 + N);
-  if (std::is_same<T, float>::value)
-    b += ws_round(sizeof(T) * static_cast<size_t>(nch) * N * 2) +
-         ws_round(sizeof(double) * fused_tiles(reg.n1, reg.n2, reg.kind) * PcMeta::kMaxEll);
+  b += ws_round(sizeof(T) * static_cast<size_t>(nch) * N * 2) +
+       ws_round(sizeof(double) * fused_tiles(reg.n1, reg.n2, reg.kind) * PcMeta::kMaxEll);
   return b + 512;
 }
 
@@ -300,16 +335,15 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
   T* Q = state ? static_cast<T*>(state) : R + static_cast<size_t>(nch) * N;
   T* tbuf = R + static_cast<size_t>(nch) * N * 2;
   if (!state) NYS_TRY(fill_zero<T>(Q, static_cast<size_t>(nch) * N, st));
-  if constexpr (std::is_same<T, float>::value) {
-    if (pc && !reg.box && pc->u_dtype == NYS_F32 && pc->ell >= 1 && pc->ell_pad <= PcMeta::kMaxEll) {
-      char* f = reinterpret_cast<char*>(tbuf + N);
-      f = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(f) + 255) / 256 * 256);
-      T* Q2 = reinterpret_cast<T*>(f);
-      T* R2 = Q2 + static_cast<size_t>(nch) * N;
-      double* fpart = reinterpret_cast<double*>(
-          f + ws_round(sizeof(T) * static_cast<size_t>(nch) * N * 2));
-      return dual_prox_fused(reg, lam_bar, pc, s, x, Q, R, Q2, R2, tbuf, cd, fpart, st);
-    }
+  const int udt = std::is_same<T, float>::value ? NYS_F32 : NYS_F64;
+  if (pc && !reg.box && pc->u_dtype == udt && pc->ell >= 1 && pc->ell_pad <= PcMeta::kMaxEll) {
+    char* f = reinterpret_cast<char*>(tbuf + N);
+    f = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(f) + 255) / 256 * 256);
+    T* Q2 = reinterpret_cast<T*>(f);
+    T* R2 = Q2 + static_cast<size_t>(nch) * N;
+    double* fpart = reinterpret_cast<double*>(
+        f + ws_round(sizeof(T) * static_cast<size_t>(nch) * N * 2));
+    return dual_prox_fused<T>(reg, lam_bar, pc, s, x, Q, R, Q2, R2, tbuf, cd, fpart, st);
   }
   return dual_prox<T>(reg, lam_bar, pc, s, x, Q, R, tbuf, cd, gbox, st);
 }
