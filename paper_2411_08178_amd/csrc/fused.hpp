@@ -131,10 +131,12 @@ __device__ __forceinline__ void fused_ring(int h, int hr, int& ey, int& ex) {
 }
 
 // KR (a multiple of 16, <= min(ell_pad, kFKeep)) rows of U stay in registers;
-// rows KR .. ell_pad - 1 are read a second time for the partials.
+// the next ntl rows (at most ell - KR) stay in LDS (Lt, one column per
+// thread, written and read back by the same thread), and rows from KR + ntl
+// on are read a second time for the partials.
 template <int KR, int TW, class T>
 __device__ __forceinline__ void fused_tile(const FusedArgsT<T>& A, int tile, int ntx,
-                                           FusedLds<TW, T>& L) {
+                                           FusedLds<TW, T>& L, T* Lt = nullptr, int ntl = 0) {
   constexpr int kFW = TW, kFH = kFThreads / TW;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int n1 = A.n1, n2 = A.n2, reg = A.reg;
@@ -178,7 +180,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgsT<T>& A, int tile, int
   // rest in runs of 16.  Rows from ell on are U's zero padding: they are not
   // loaded (a zero in their place gives the same sums).
   const int ell = A.ell;
-  auto uc = [&](int64_t o, T* v) {
+  auto uc = [&](int64_t o, T* v, int keep) {
 #pragma unroll
     for (int k = 0; k < KR; ++k) v[k] = k < ell ? U[k * ldu + o] : T(0);
     T y = 0;
@@ -189,7 +191,10 @@ __device__ __forceinline__ void fused_tile(const FusedArgsT<T>& A, int tile, int
 #pragma unroll
       for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + o] : T(0);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) y = fma_t(w[j], L.c[k0 + j], y);
+      for (int j = 0; j < 16; ++j) {
+        y = fma_t(w[j], L.c[k0 + j], y);
+        if (k0 + j - KR < keep) Lt[(k0 + j - KR) * kFThreads + t] = w[j];
+      }
     }
     return y;
   };
@@ -205,7 +210,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgsT<T>& A, int tile, int
     const int gi = xy0 + ey, gj = xx0 + ex;
     if (gi >= 0 && gi < n1 && gj >= 0 && gj < n2) {
       const int64_t o = static_cast<int64_t>(gi) * n2 + gj;
-      const T y = uc(o, u);
+      const T y = uc(o, u, 0);
       const T tr = lt_with<T>(ra, reg, gi, gj, n1, n2);
       L.x[ey * xw + ex] = A.s[o] - A.lam_bar * (tr + y);
     }
@@ -215,7 +220,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgsT<T>& A, int tile, int
   const bool pin = pi < n1 && pj < n2;
   const int64_t po = pin ? static_cast<int64_t>(pi) * n2 + pj : 0;
   {
-    const T y = uc(po, u);
+    const T y = uc(po, u, ntl);
     if (pin) {
       const T tr = lt_with<T>(ra, reg, pi, pj, n1, n2);
       L.x[(iy + hr) * xw + ix + hr] = A.s[po] - A.lam_bar * (tr + y);
@@ -272,7 +277,10 @@ __device__ __forceinline__ void fused_tile(const FusedArgsT<T>& A, int tile, int
   for (int k0 = KR; k0 < Lp; k0 += 16) {
     T w[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) w[j] = k0 + j < ell ? U[(k0 + j) * ldu + po] * tp : T(0);
+    for (int j = 0; j < 16; ++j) {
+      const int k = k0 + j;
+      w[j] = k < ell ? (k - KR < ntl ? Lt[(k - KR) * kFThreads + t] : U[k * ldu + po]) * tp : T(0);
+    }
     int b2 = 0;
     using B2 = Bfly<16, 32>;
     B2::run(w, lane, b2);

@@ -43,11 +43,12 @@ __global__ __launch_bounds__(256) void dual_update_kernel(const T* __restrict__ 
 // FP32: static LDS; FP64: the same regions in dynamic LDS (over 64 KiB).
 template <int KR, int TW>
 __global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void dual_fused_kernel(FusedArgs A, int ntx, int ntiles) {
+void dual_fused_kernel(FusedArgs A, int ntx, int ntiles, int ntl) {
   __shared__ FusedLds<TW> L;
+  extern __shared__ float fused_tail[];  // ntl rows of the tile past the kept ones
   const int tile = fused_tile_of(blockIdx.x, ntiles);
   if (tile >= ntiles) return;
-  fused_tile<KR, TW>(A, tile, ntx, L);
+  fused_tile<KR, TW>(A, tile, ntx, L, fused_tail, ntl);
 }
 template <int KR, int TW>
 __global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
@@ -89,11 +90,26 @@ static nys_status fused_launch_tw(const FusedArgs& A, hipStream_t st) {
   const int ntiles = ntx * nty;
   const dim3 grid(static_cast<unsigned>((ntiles + 7) / 8 * 8));
   switch (fused_keep(A.ell_pad)) {
-    case 16: hipLaunchKernelGGL((dual_fused_kernel<16, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
-    case 32: hipLaunchKernelGGL((dual_fused_kernel<32, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
-    case 48: hipLaunchKernelGGL((dual_fused_kernel<48, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
-    case 64: hipLaunchKernelGGL((dual_fused_kernel<64, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
-    default: hipLaunchKernelGGL((dual_fused_kernel<80, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles); break;
+    case 16: hipLaunchKernelGGL((dual_fused_kernel<16, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles, 0); break;
+    case 32: hipLaunchKernelGGL((dual_fused_kernel<32, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles, 0); break;
+    case 48: hipLaunchKernelGGL((dual_fused_kernel<48, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles, 0); break;
+    case 64: hipLaunchKernelGGL((dual_fused_kernel<64, TW>), grid, dim3(kFThreads), 0, st, A, ntx, ntiles, 0); break;
+    default: {
+      // rows past the 80 kept ones: as many as fit in LDS next to the
+      // tile's regions with two workgroups per CU (160 KiB per CU) stay
+      // there, the rest are read again
+      constexpr int kPerCu = 160 * 1024, kSlack = 1024;
+      constexpr int kRowBytes = kFThreads * static_cast<int>(sizeof(float));
+      constexpr int cap = (kPerCu / 2 - static_cast<int>(sizeof(FusedLds<TW>)) - kSlack) / kRowBytes;
+      const int ntl = std::max(0, std::min(A.ell - kFKeep, cap));
+      const size_t dyn = static_cast<size_t>(ntl) * kRowBytes;
+      if (dyn > 0)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dual_fused_kernel<kFKeep, TW>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(dyn));
+      hipLaunchKernelGGL((dual_fused_kernel<kFKeep, TW>), grid, dim3(kFThreads), dyn, st, A, ntx,
+                         ntiles, ntl);
+      break;
+    }
   }
   return launch_check("dual_fused_kernel");
 }
