@@ -693,8 +693,18 @@ __global__ __launch_bounds__(1024) void bftail_kernel(const BDesc* __restrict__ 
   const int k = blockIdx.y * 16 + kk;
   if (blockIdx.y * 16 >= D.ell) return;
   double s = 0.0;
-  if (k < D.ell)
-    for (int64_t b = grp; b < sg.nblk; b += 64) s += D.fpart[b * D.ell_pad + k];
+  if (k < D.ell) {
+    // eight loads in flight, added in tile order
+    int64_t b = grp;
+    for (; b + 7 * 64 < sg.nblk; b += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = D.fpart[(b + 64 * i) * D.ell_pad + k];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s += v[i];
+    }
+    for (; b < sg.nblk; b += 64) s += D.fpart[b * D.ell_pad + k];
+  }
   red[grp][kk] = s;
   __syncthreads();
   for (int w = 32; w > 0; w >>= 1) {

@@ -347,8 +347,18 @@ __global__ __launch_bounds__(1024) void ut_tail_cols_kernel(const double* __rest
   const int k = blockIdx.x * 16 + kk;
   const double* pc = part + static_cast<size_t>(blockIdx.y) * nblk * Lp;
   double s = 0.0;
-  if (k < L)
-    for (int b = grp; b < nblk; b += 64) s += pc[static_cast<size_t>(b) * Lp + k];
+  if (k < L) {
+    // eight loads in flight, added in block order
+    int b = grp;
+    for (; b + 7 * 64 < nblk; b += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = pc[static_cast<size_t>(b + 64 * i) * Lp + k];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) s += v[i];
+    }
+    for (; b < nblk; b += 64) s += pc[static_cast<size_t>(b) * Lp + k];
+  }
   red[grp][kk] = s;
   __syncthreads();
   for (int w = 32; w > 0; w >>= 1) {
