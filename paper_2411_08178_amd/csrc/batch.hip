@@ -642,10 +642,16 @@ __global__ __launch_bounds__(256) void bcopy_out_kernel(const BDesc* __restrict_
   }
 }
 
-// One fused inner iteration of every instance's P-weighted prox (fused.hpp):
-// block b -> tile g of the launch (XCD-contiguous runs) -> instance and tile.
-template <int TW>
-__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(4)))
+// One fused inner iteration of the P-weighted prox (fused.hpp) of the
+// instances whose U has KR rows: block b -> tile g of the launch
+// (XCD-contiguous runs) -> instance and tile.  One launch per row count, so
+// that the register budget (and with it the workgroups resident per CU:
+// four at 16 rows, three at 32, two at 64) follows the rows each launch
+// keeps; the tiles' phases are latency-bound, so residency is what hides
+// them.
+template <int KR> constexpr int bfused_waves() { return KR <= 16 ? 8 : KR <= 32 ? 6 : 4; }
+template <int TW, int KR>
+__global__ __launch_bounds__(kFThreads) __attribute__((amdgpu_waves_per_eu(bfused_waves<KR>())))
 void bfused_kernel(const BDesc* __restrict__ d, const BSeg* __restrict__ seg, int nseg,
                    int ntiles, int reg, int fqi, int fri, int fqo, int fro, float beta, int last) {
   __shared__ FusedLds<TW> L;
@@ -674,11 +680,7 @@ void bfused_kernel(const BDesc* __restrict__ d, const BSeg* __restrict__ seg, in
   A.part = D.fpart;
   const int tile = static_cast<int>(g - sg.first);
   const int ntx = (D.n2 + TW - 1) / TW;
-  switch (D.ell_pad) {
-    case 16: fused_tile<16, TW>(A, tile, ntx, L); break;
-    case 32: fused_tile<32, TW>(A, tile, ntx, L); break;
-    default: fused_tile<64, TW>(A, tile, ntx, L); break;
-  }
+  fused_tile<KR, TW>(A, tile, ntx, L);
 }
 
 // D.cd[k] = d_k sum_b D.fpart[b][k] for 16 coefficients a block: block
@@ -744,6 +746,7 @@ struct nys_batch_s {
   int64_t P = 0;                             // packed image length
   BDesc* dd = nullptr;                       // device descriptors
   BLaunch pix, cmb, red, upix, fac, gram, ftl;
+  BLaunch ftlk[3];                           // the tiles of the instances with 16, 32, 64 rows of U
   int kgroups = 0;
   int max_ell = 0;
   int64_t lds_doubles = 0;
@@ -771,6 +774,32 @@ namespace nys {
 namespace {
 
 // Host builder of one device table region: appends POD arrays, 256-byte aligned.
+// One fused dual iteration of every instance: a launch per row count of U
+// (instances without tiles of that count are skipped).
+template <int TW>
+static nys_status bfused_launch_tw(const nys_batch_s* b, int reg, int qi, int ri, int qo, int ro,
+                                   float beta, int last, hipStream_t st) {
+  for (int c = 0; c < 3; ++c) {
+    const BLaunch& l = b->ftlk[c];
+    if (l.nblk == 0) continue;
+    const int ntiles = static_cast<int>(l.nblk);
+    const dim3 fg(static_cast<unsigned>((ntiles + 7) / 8 * 8));
+    switch (c) {
+      case 0: hipLaunchKernelGGL((bfused_kernel<TW, 16>), fg, dim3(kFThreads), 0, st, b->dd, l.seg, l.nseg, ntiles, reg, qi, ri, qo, ro, beta, last); break;
+      case 1: hipLaunchKernelGGL((bfused_kernel<TW, 32>), fg, dim3(kFThreads), 0, st, b->dd, l.seg, l.nseg, ntiles, reg, qi, ri, qo, ro, beta, last); break;
+      default: hipLaunchKernelGGL((bfused_kernel<TW, 64>), fg, dim3(kFThreads), 0, st, b->dd, l.seg, l.nseg, ntiles, reg, qi, ri, qo, ro, beta, last); break;
+    }
+    NYS_TRY(launch_check("bfused_kernel"));
+  }
+  return NYS_OK;
+}
+
+static nys_status bfused_launch(const nys_batch_s* b, int reg, int qi, int ri, int qo, int ro,
+                                float beta, int last, hipStream_t st) {
+  return reg_hessian(reg) ? bfused_launch_tw<fused_tw(true)>(b, reg, qi, ri, qo, ro, beta, last, st)
+                          : bfused_launch_tw<fused_tw(false)>(b, reg, qi, ri, qo, ro, beta, last, st);
+}
+
 struct TableBuilder {
   std::vector<unsigned char> bytes;
   template <class T>
@@ -977,23 +1006,14 @@ nys_status enqueue_all(nys_batch_s* b) {
       NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldT, st));
       int qi = kFldQ, ri = kFldQ;
       double tau = 1.0;
-      const int ntiles = static_cast<int>(b->ftl.nblk);
-      const dim3 fg(static_cast<unsigned>((ntiles + 7) / 8 * 8));
       const dim3 tg(static_cast<unsigned>(b->ftl.nseg), static_cast<unsigned>(cdiv(b->max_ell, 16)));
       for (int it = 0; it < o.n_inner; ++it) {
         const double tau_n = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));
         const double beta = (tau - 1.0) / tau_n;
         const int qo = (it & 1) ? kFldQ : kFldQ2;
         const int ro = (it & 1) ? kFldR2 : kFldR;
-        if (reg_hessian(reg))
-          hipLaunchKernelGGL(bfused_kernel<fused_tw(true)>, fg, dim3(kFThreads), 0, st, d, b->ftl.seg,
-                             b->ftl.nseg, ntiles, reg, qi, ri, qo, ro, static_cast<float>(beta),
-                             int(it == o.n_inner - 1));
-        else
-          hipLaunchKernelGGL(bfused_kernel<fused_tw(false)>, fg, dim3(kFThreads), 0, st, d, b->ftl.seg,
-                             b->ftl.nseg, ntiles, reg, qi, ri, qo, ro, static_cast<float>(beta),
-                             int(it == o.n_inner - 1));
-        NYS_TRY(launch_check("bfused_kernel"));
+        NYS_TRY(bfused_launch(b, reg, qi, ri, qo, ro, static_cast<float>(beta),
+                              int(it == o.n_inner - 1), st));
         hipLaunchKernelGGL(bftail_kernel, tg, dim3(1024), 0, st, d, b->ftl.seg);
         NYS_TRY(launch_check("bftail_kernel"));
         qi = qo;
@@ -1231,6 +1251,14 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   auto grms = segs(all, [&](int i) { return gram_nblk[i]; }, [&](int i) { return gram_chunk[i]; });
   auto ftls = segs(all, [&](int i) { return batch_tiles(b->hd[i].n1, b->hd[i].n2, o.reg); },
                    [](int) { return int64_t(kFThreads); });
+  std::pair<std::vector<BSeg>, int64_t> ftlks[3];
+  for (int c = 0; c < 3; ++c) {
+    std::vector<int> inst;
+    for (int i = 0; i < count; ++i)
+      if (b->hd[i].ell_pad == (16 << c)) inst.push_back(i);
+    ftlks[c] = segs(inst, [&](int i) { return batch_tiles(b->hd[i].n1, b->hd[i].n2, o.reg); },
+                    [](int) { return int64_t(kFThreads); });
+  }
 
   // ---- stencil tasks (tile heights from the autotuner table)
   // tuner classes: (row taps, column taps + 65536 for the streaming kernel)
@@ -1289,6 +1317,8 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     const size_t o_fac = tb.add(facs.first);
     const size_t o_gram = tb.add(grms.first);
     const size_t o_ftl = tb.add(ftls.first);
+    size_t o_ftlk[3];
+    for (int c = 0; c < 3; ++c) o_ftlk[c] = tb.add(ftlks[c].first);
     const size_t o_ctr = tb.add(std::vector<int>(kQueues + 1 + 63, 0));
     struct StOff { size_t tasks, items, qbase, sitems; int64_t n, ns; size_t lds; bool sub; };
     std::vector<TaskSpec>* lists[5] = {&t_sketch, &t_phi, &t_grad, &t_aty, &t_hx};
@@ -1325,6 +1355,9 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     b->gram = {reinterpret_cast<const BSeg*>(T + o_gram), static_cast<int>(grms.first.size()),
                grms.second};
     b->ftl = {reinterpret_cast<const BSeg*>(T + o_ftl), static_cast<int>(ftls.first.size()), ftls.second};
+    for (int c = 0; c < 3; ++c)
+      b->ftlk[c] = {reinterpret_cast<const BSeg*>(T + o_ftlk[c]), static_cast<int>(ftlks[c].first.size()),
+                    ftlks[c].second};
     b->ctr = reinterpret_cast<int*>(T + o_ctr);
     nys_batch_s::St* sts[5] = {&b->st_sketch, &b->st_phi_v, &b->st_grad, &b->st_aty, &b->st_hx};
     for (int l = 0; l < 5; ++l) {
