@@ -522,6 +522,24 @@ __global__ __launch_bounds__(256) void bsumsq_kernel(const BDesc* __restrict__ d
   if (threadIdx.x == 0) D.part[lb] = s;
 }
 
+// The warm start's coefficients c = d . U^T L^T Q of every instance
+// (block = instance).  The last fused dual iteration of a prox forms them for
+// its final Q (the partials of L^T Q+), and the next prox starts from that
+// same Q, so they are kept instead of formed again with a pass over U:
+// mode 0 clears the kept ones (Q = 0 at the start of a solve), 1 restores
+// them into cd, 2 keeps cd, 3 clears cd (a cold start, Q = 0).
+__global__ __launch_bounds__(64) void bcq_kernel(const BDesc* __restrict__ d, int mode) {
+  const BDesc& D = d[blockIdx.x];
+  for (int k = threadIdx.x; k < D.ell; k += blockDim.x) {
+    switch (mode) {
+      case 0: D.cq[k] = 0.0; break;
+      case 1: D.cd[k] = D.cq[k]; break;
+      case 2: D.cq[k] = D.cd[k]; break;
+      default: D.cd[k] = 0.0; break;
+    }
+  }
+}
+
 // Sum of an instance's block partials, fixed order (blockIdx.x = segment):
 // which = 0: scal[kNorm] = sqrt(sum); which = 1: costs[k] = sum.
 __global__ __launch_bounds__(256) void bpart_tail_kernel(const BDesc* __restrict__ d,
@@ -987,6 +1005,11 @@ nys_status enqueue_all(nys_batch_s* b) {
   NYS_TRY(fill_zero<float>(d0.f[kFldX], b->P, st));
   NYS_TRY(fill_zero<float>(d0.f[kFldU], b->P, st));
   NYS_TRY(fill_zero<float>(d0.f[kFldQ], static_cast<size_t>(b->nch) * b->P, st));
+  const dim3 ig(static_cast<unsigned>(b->hd.size()));
+  if (pc) {
+    hipLaunchKernelGGL(bcq_kernel, ig, dim3(64), 0, st, d, 0);
+    NYS_TRY(launch_check("bcq_kernel"));
+  }
   const int term = reg_term_of(reg);
   double t_prev = 1.0;
   for (int k = 0; k < o.max_iter; ++k) {
@@ -997,13 +1020,12 @@ nys_status enqueue_all(nys_batch_s* b) {
     // x+ = prox^P_{lam_bar g}(s): accelerated projected gradient on the dual
     if (!o.warm_start) NYS_TRY(fill_zero<float>(d0.f[kFldQ], static_cast<size_t>(b->nch) * b->P, st));
     if (pc) {
-      // with P^{-1} inside: the warm start's coefficients, then one fused
-      // launch and the coefficient tail per dual iteration (R = Q at the
-      // start; the duals alternate between Q, R and Q2, R2)
-      hipLaunchKernelGGL(blt_kernel, pg, dim3(256), 0, st, d, b->pix.seg, nseg, reg, int(kFldQ),
-                         int(kFldT));
-      NYS_TRY(launch_check("blt_kernel"));
-      NYS_TRY(batch_pinv_coeffs(d, b->red.seg, b->red.nseg, b->red.nblk, kFldT, st));
+      // with P^{-1} inside: the warm start's coefficients (kept from the
+      // last prox, whose final Q this one starts from), then one fused
+      // launch per row count and the coefficient tail per dual iteration
+      // (R = Q at the start; the duals alternate between Q, R and Q2, R2)
+      hipLaunchKernelGGL(bcq_kernel, ig, dim3(64), 0, st, d, o.warm_start ? 1 : 3);
+      NYS_TRY(launch_check("bcq_kernel"));
       int qi = kFldQ, ri = kFldQ;
       double tau = 1.0;
       const dim3 tg(static_cast<unsigned>(b->ftl.nseg), static_cast<unsigned>(cdiv(b->max_ell, 16)));
@@ -1020,6 +1042,8 @@ nys_status enqueue_all(nys_batch_s* b) {
         ri = ro;
         tau = tau_n;
       }
+      hipLaunchKernelGGL(bcq_kernel, ig, dim3(64), 0, st, d, 2);
+      NYS_TRY(launch_check("bcq_kernel"));
       if (qi != kFldQ)
         NYS_CHECK_HIP(hipMemcpyAsync(d0.f[kFldQ], d0.f[qi], sizeof(float) * b->nch * b->P,
                                      hipMemcpyDeviceToDevice, st));
@@ -1137,7 +1161,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
   b->P = P;
 
   // ---- arena layout
-  struct Off { size_t Y, U, meta, G, gpart, fwork, part, fpart, cd, scal; };
+  struct Off { size_t Y, U, meta, G, gpart, fwork, part, fpart, cd, cq, scal; };
   std::vector<Off> off(count);
   size_t cur = 0;
   auto take = [&](size_t bytes) { size_t o0 = cur; cur += (bytes + 255) / 256 * 256; return o0; };
@@ -1181,6 +1205,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     q.part = take(sizeof(double) * std::max<int64_t>(red_nblk[i] * std::max(ell_pad, 16), pblk));
     q.fpart = take(ell > 0 ? sizeof(double) * batch_tiles(it.n1, it.n2, o.reg) * ell_pad : 0);
     q.cd = take(sizeof(double) * std::max(ell_pad, 16));
+    q.cq = take(sizeof(double) * std::max(ell_pad, 16));
     q.scal = take(sizeof(double) * BScal::kTotal);
     BDesc D{};
     D.n1 = it.n1;
@@ -1217,6 +1242,7 @@ extern "C" nys_status batch_solve_create(const nys_batch_item* items, int32_t co
     D.part = reinterpret_cast<double*>(A + q.part);
     D.fpart = reinterpret_cast<double*>(A + q.fpart);
     D.cd = reinterpret_cast<double*>(A + q.cd);
+    D.cq = reinterpret_cast<double*>(A + q.cq);
     D.scal = reinterpret_cast<double*>(A + q.scal);
     D.costs = it.costs;
     D.x_out = it.x;

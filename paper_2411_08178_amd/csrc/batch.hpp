@@ -52,6 +52,7 @@ struct BDesc {
   double* part;              // per-block reduction partials
   double* fpart;             // per-tile partials of the fused inner iteration
   double* cd;                // ell coefficients d . U^T v
+  double* cq;                // d . U^T L^T Q of the last prox's final dual (the next prox's warm start)
   double* scal;              // BScal::kTotal scalars
   double* costs;             // optional cost per outer iteration
   float* x_out;              // caller's output image
