@@ -145,9 +145,13 @@ nys_status factor_refresh(nys_pc pc, const void* omega, const void* Y, nys_dtype
 // Weighted prox (prox.hip).  state as in prox_weighted; work: prox_ws_bytes
 // of device memory (the dual iteration's buffers); a preconditioner's
 // applications take their scratch from the workspace bound to pc.
+// c_kept: the work buffer's leading coefficients already hold d . U^T L^T Q
+// for the state's Q with this pc (the previous call on the same state and
+// work left them there, or they were cleared with Q = 0); the fused path
+// then starts from them instead of a pass over U.
 template <class T>
 nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    void* state, hipStream_t st, void* work);
+                    void* state, hipStream_t st, void* work, bool c_kept = false);
 template <class T> size_t prox_ws_bytes(const nys_reg_desc& reg);
 
 }  // namespace nys

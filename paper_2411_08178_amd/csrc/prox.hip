@@ -249,7 +249,7 @@ static nys_status dual_prox(const nys_reg_desc& reg, double lam_bar, nys_pc pc, 
 template <class T>
 static nys_status dual_prox_fused(const nys_reg_desc& reg, double lam_bar, nys_pc pc,
                                   const T* s, T* x, T* Q, T* R, T* Q2, T* R2, T* tbuf,
-                                  double* cd, double* fpart, hipStream_t st) {
+                                  double* cd, double* fpart, bool c_kept, hipStream_t st) {
   const int n1 = reg.n1, n2 = reg.n2;
   const int64_t N = static_cast<int64_t>(n1) * n2;
   const int nch = reg_hessian(reg.kind) ? 3 : 2;
@@ -262,11 +262,14 @@ static nys_status dual_prox_fused(const nys_reg_desc& reg, double lam_bar, nys_p
   }
   const double step = 1.0 / (lam_bar * lnorm2 * pc->pinv_norm_cache);
   const dim3 g2(cdiv(n2, 64), cdiv(n1, 4));
-  // c of the warm start: d . U^T L^T Q
-  hipLaunchKernelGGL((lt_kernel<T>), g2, dim3(256), 0, st, Q, reg.kind, n1, n2,
-                     static_cast<const T*>(nullptr), T(0), tbuf);
-  NYS_TRY(launch_check("lt_kernel"));
-  NYS_TRY(pc_coeffs<T>(pc, true, tbuf, 1, cd, st));
+  // c of the warm start: d . U^T L^T Q (kept in cd by the previous call on
+  // the same state: its last iteration forms them for its final Q)
+  if (!c_kept) {
+    hipLaunchKernelGGL((lt_kernel<T>), g2, dim3(256), 0, st, Q, reg.kind, n1, n2,
+                       static_cast<const T*>(nullptr), T(0), tbuf);
+    NYS_TRY(launch_check("lt_kernel"));
+    NYS_TRY(pc_coeffs<T>(pc, true, tbuf, 1, cd, st));
+  }
   FusedArgsT<T> A{};
   A.n1 = n1;
   A.n2 = n2;
@@ -331,7 +334,7 @@ size_t prox_ws_bytes(const nys_reg_desc& reg) {
 
 template <class T>
 nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T* s, T* x,
-                    void* state, hipStream_t st, void* work) {
+                    void* state, hipStream_t st, void* work, bool c_kept) {
   const int64_t N = static_cast<int64_t>(reg.n1) * reg.n2;
   if (reg.kind == NYS_REG_L1) {
     if (!pc) {
@@ -359,15 +362,16 @@ nys_status prox_run(const nys_reg_desc& reg, double lam_bar, nys_pc pc, const T*
     T* R2 = Q2 + static_cast<size_t>(nch) * N;
     double* fpart = reinterpret_cast<double*>(
         f + ws_round(sizeof(T) * static_cast<size_t>(nch) * N * 2));
-    return dual_prox_fused<T>(reg, lam_bar, pc, s, x, Q, R, Q2, R2, tbuf, cd, fpart, st);
+    return dual_prox_fused<T>(reg, lam_bar, pc, s, x, Q, R, Q2, R2, tbuf, cd, fpart,
+                              c_kept && state != nullptr, st);
   }
   return dual_prox<T>(reg, lam_bar, pc, s, x, Q, R, tbuf, cd, gbox, st);
 }
 
 template nys_status prox_run<double>(const nys_reg_desc&, double, nys_pc, const double*, double*,
-                                     void*, hipStream_t, void*);
+                                     void*, hipStream_t, void*, bool);
 template nys_status prox_run<float>(const nys_reg_desc&, double, nys_pc, const float*, float*,
-                                    void*, hipStream_t, void*);
+                                    void*, hipStream_t, void*, bool);
 template size_t prox_ws_bytes<double>(const nys_reg_desc&);
 template size_t prox_ws_bytes<float>(const nys_reg_desc&);
 template nys_status fill_zero<double>(double*, size_t, hipStream_t);

@@ -276,6 +276,8 @@ static nys_status wapg_setup(const nys_problem& p, nys_pc pc, T* x, const SolveW
   NYS_TRY(fill_zero<T>(w.u, N, st));
   if (nch) NYS_TRY(fill_zero<T>(static_cast<T*>(w.state), static_cast<size_t>(nch) * N, st));
   else if (w.state) NYS_TRY(fill_zero<double>(static_cast<double*>(w.state), pc->ell, st));
+  // the prox's kept warm-start coefficients: those of Q = 0
+  if (nch && pc) NYS_TRY(fill_zero<double>(static_cast<double*>(w.prox), PcMeta::kMaxEll, st));
   if (w.au) {
     // A U: U's rows (zero past ell) packed, then the operator on all of them
     NYS_CHECK_HIP(hipMemcpy2DAsync(w.ucopy, sizeof(T) * N, pc->U.p, sizeof(T) * pc->ldu,
@@ -343,7 +345,7 @@ static nys_status wapg_iter(const nys_problem& p, nys_pc pc, double alpha, int w
   // x+ = prox^P_{alpha lambda g}(s)
   if (!(pc && p.reg.kind == NYS_REG_L1)) {
     const nys_status ps = prox_run<T>(p.reg, lam_bar, pc, w.s, w.xn,
-                                      warm_start ? w.state : nullptr, st, w.prox);
+                                      warm_start ? w.state : nullptr, st, w.prox, warm_start);
     if (ps == NYS_ENOCONV) conv = ps;
     else if (ps != NYS_OK) return ps;
   }
