@@ -151,6 +151,29 @@ def test_batch_preconditioned_matches_oracle(reg):
         check(host(plan.costs[i]), cr, tol_c, what="costs")
 
 
+def test_batch_preconditioned_cold_start_matches_oracle():
+    """warm_start off: every prox starts from Q = 0 (and c = 0), against the
+    oracle's WAPG with the same start."""
+    P = need_gpu()
+    banner("batch preconditioned tv cold start")
+    inst = _instances(350, specs=SPECS[:3])
+    iters, inner, piters = 6, 8, 60
+    plan = P.BatchSolver(inst, max_iter=iters, n_inner=inner, power_iters=piters,
+                         warm_start=False, record_costs=True, tune=False)
+    plan.run()
+    torch.cuda.synchronize()
+    for i, it in enumerate(inst):
+        prob, ell, n = it["prob"], it["ell"], it["prob"].n
+        banner(f"batch cold-start instance {i} n={n} ell={ell}")
+        om = host(it["omega"])
+        fl = Floor(prob, om, sv.sketch(prob, om), ell)
+        info = plan.info(i)
+        assert info["status"] == 0
+        xr, cr, tol_x, tol_c = fl.wapg(info["alpha"], iters, inner, warm_start=False)
+        check(host(plan.x[i]), xr, tol_x, what="x after 6 iterations")
+        check(host(plan.costs[i]), cr, tol_c, what="costs")
+
+
 def test_batch_plain_apg_matches_oracle():
     P = need_gpu()
     banner("batch plain APG tv_aniso")

@@ -62,6 +62,35 @@ def test_plan_tv_deblur_with_preconditioner(dt):
     check(c, cr, TOL[dt], what="costs")
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("warm", [True, False])
+def test_solve_prox_warm_and_cold_start(dt, warm):
+    """The solver keeps the warm start's coefficients d . U^T L^T Q from the
+    previous prox (and clears them with Q at the start); with warm_start off
+    every prox starts from Q = 0.  Both against the oracle's WAPG with the
+    same start, and the plan's replays against solve."""
+    P = need_gpu()
+    banner(f"solve TV deblur warm={warm} {dt}")
+    n, ell, iters = 40, 10, 21
+    wl = W.workload("deblur128_tv_f64")
+    prob, _ = sv.problem_from_workload(wl, seed=3, n=n)
+    op = P.Operator(P.OP_BLUR, n, n, psf=prob.h)
+    yd = dev(prob.y, dt)
+    prob.y = host(yd)
+    opc, pc = _pc_for(P, prob, n, ell, dt, 22)
+    alpha = 0.9 / sv.lipschitz(prob, opc, W.gaussian((n, n), 23), 200)
+    rd = P.reg_desc("tv", n, n, n_inner=6)
+    x0, c0, info = P.solve(op, yd, rd, prob.lam, pc, iters, alpha=alpha, warm_start=warm)
+    assert info["status"] == 0
+    plan = P.SolvePlan(op, yd, rd, prob.lam, pc, iters, alpha=alpha, warm_start=warm)
+    x, c = plan.run()
+    torch.cuda.synchronize()
+    assert torch.equal(x, x0) and torch.equal(c, c0)
+    xr, cr = sv.wapg(prob, opc, alpha, iters, inner=6, warm_start=warm)
+    check(host(x0), xr, TOL[dt], what="x")
+    check(host(c0), cr, TOL[dt], what="costs")
+
+
 def test_plan_ct_hs1_f32():
     """32^2 parallel-beam CT (36 views, 48 bins), HS1, ell = 10, 20 iterations."""
     P = need_gpu()
