@@ -160,6 +160,35 @@ def test_ct_configuration_pinv_and_hs1_prox():
     check(host(x), xr, TOL["f32"], what="HS1 prox")
 
 
+@pytest.mark.parametrize("reg,ell", [("hs1", 100), ("hs1", 128), ("tv", 128)])
+def test_fused_prox_rows_in_lds_and_read_again(reg, ell):
+    """The fused dual iteration keeps 80 rows of U in registers, the next
+    ones (about 20, as LDS allows at two workgroups per CU) in LDS, and reads
+    any further ones again for the partials: ell = 100 takes registers and
+    LDS, ell = 128 all three.  FP32 on ragged 48^2 tiles, the warm-started
+    second call included, against the oracle."""
+    P = need_gpu()
+    banner(f"fused prox {reg} ell={ell}: rows in registers, LDS and read again")
+    n = 48
+    om, Y = _steep_psd_sketch(n, ell, r=ell + 40, seed=70)
+    omd, Yd = dev(om.reshape(ell, n, n), "f32"), dev(Y.reshape(ell, n, n), "f32")
+    ref = onys.nystrom(host(Yd).reshape(ell, -1), host(omd).reshape(ell, -1))
+    pc = P.nys_factor(omd, Yd, ell, u_dtype=torch.float32)
+    assert pc.info()["status"] == 0
+    opc = sv.Precond(ref["U"], ref["shat"], ref["nu"], "sqrt")
+    s = W.phantom_ellipses(n, 72) + 0.002 * W.gaussian((n, n), 73)
+    sd = dev(s, "f32")
+    lam_bar = 1e-3
+    rd = P.reg_desc(reg, n, n, n_inner=12)
+    state = P.prox_state(rd, pc, sd.dtype)
+    x = P.prox_weighted(rd, lam_bar, pc, sd, state)
+    xr, Q = opx.prox_mixed_dual(host(sd), lam_bar, reg, opc.pinv, opc.pinv_norm, 12)
+    check(host(x), xr, TOL["f32"], what=f"{reg} prox")
+    x2 = P.prox_weighted(rd, lam_bar, pc, sd, state)
+    xr2, _ = opx.prox_mixed_dual(host(sd), lam_bar, reg, opc.pinv, opc.pinv_norm, 12, q0=Q)
+    check(host(x2), xr2, TOL["f32"], what=f"{reg} prox, warm start")
+
+
 def test_factor_exact_recovery_low_rank():
     """Phi = G G^T of rank 5 < ell = 8: U S U^T reproduces Phi."""
     P = need_gpu()
