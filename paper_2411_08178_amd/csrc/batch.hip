@@ -725,13 +725,17 @@ __global__ __launch_bounds__(1024) void bftail_kernel(const BDesc* __restrict__ 
     }
     for (; b < sg.nblk; b += 64) s += D.fpart[b * D.ell_pad + k];
   }
-  red[grp][kk] = s;
+  // the four groups of a wave by lane exchange, then the 16 waves in order
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) < 16) red[wave][kk] = s;
   __syncthreads();
-  for (int w = 32; w > 0; w >>= 1) {
-    if (grp < w) red[grp][kk] += red[grp + w][kk];
-    __syncthreads();
+  if (threadIdx.x < 16 && k < D.ell) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w][kk];
+    D.cd[k] = D.meta[PcMeta::kD + k] * t;
   }
-  if (grp == 0 && k < D.ell) D.cd[k] = D.meta[PcMeta::kD + k] * red[0][kk];
 }
 
 #undef BSEG_PROLOGUE

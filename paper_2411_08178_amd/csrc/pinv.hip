@@ -359,13 +359,17 @@ __global__ __launch_bounds__(1024) void ut_tail_cols_kernel(const double* __rest
     }
     for (; b < nblk; b += 64) s += pc[static_cast<size_t>(b) * Lp + k];
   }
-  red[grp][kk] = s;
+  // the four groups of a wave by lane exchange, then the 16 waves in order
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) < 16) red[wave][kk] = s;
   __syncthreads();
-  for (int w = 32; w > 0; w >>= 1) {
-    if (grp < w) red[grp][kk] += red[grp + w][kk];
-    __syncthreads();
+  if (threadIdx.x < 16 && k < L) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w][kk];
+    cd[static_cast<size_t>(blockIdx.y) * L + k] = coef[k] * t;
   }
-  if (grp == 0 && k < L) cd[static_cast<size_t>(blockIdx.y) * L + k] = coef[k] * red[0][kk];
 }
 
 // out = v + U cd   (one column of cd per image)
